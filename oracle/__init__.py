@@ -1,0 +1,11 @@
+"""FP64 CPU oracle for the flux-limited-diffusion radiation-energy step.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything here; the
+product path (the HIP library and its binding) never does, and shares no code
+with it.  See ``oracle.fld`` for what each function follows in the paper
+(Moens et al. 2022, "Radiation-hydrodynamics with MPI-AMRVAC: flux-limited
+diffusion").
+"""
+from .fld import *  # noqa: F401,F403
+from .fld import __all__  # noqa: F401

@@ -1,0 +1,417 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+limits, invariants, a spectral (DCT) solution, brute force on tiny grids, and
+the paper's two hot-path experiments (heating/cooling, optically thin front).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle as O
+import workloads as W
+
+
+# ----------------------------------------------------------------------------- limiter
+def test_limiter_limits_and_monotonicity():
+    """Sec. 2.2: lambda -> 1/3 as R -> 0 and lambda -> 1/R as R -> inf; causality R*lambda < 1."""
+    assert O.flux_limiter(np.array([0.0]))[0] == pytest.approx(1.0 / 3.0, rel=0, abs=1e-16)
+    big = np.array([1e4, 1e6, 1e8])
+    assert np.allclose(big * O.flux_limiter(big), 1.0, rtol=3e-4)
+    assert abs(1e8 * O.flux_limiter(np.array([1e8]))[0] - 1.0) < 1e-7
+    R = np.concatenate([[0.0], np.logspace(-8, 8, 4001)])
+    lam = O.flux_limiter(R)
+    assert np.all(np.diff(lam) <= 4 * 5.6e-17), "lambda must not increase with R (up to a few ulps)"
+    Rs = np.logspace(-3, 8, 2001)
+    assert np.all(np.diff(O.flux_limiter(Rs)) < 0), "lambda must decrease strictly with R"
+    assert np.all(R * lam < 1.0), "flux |F| = D|grad E| must stay below cE"
+    assert np.all(O.flux_limiter(R, "diffusion") == 1.0 / 3.0)
+    # the bridging law lies between the two limits: 1/3 >= lambda and lambda >= 1/(3+R)
+    assert np.all(lam <= 1.0 / 3.0 + 1e-16) and np.all(lam >= 1.0 / (3.0 + R) - 1e-16)
+
+
+def test_free_streaming_flux_magnitude():
+    """Sec. 2.2 (eq. fld_F): in the thin limit |F| = D |grad E| -> c E (never above)."""
+    n = 64
+    x = W.cell_centres(n)
+    E = np.exp(-40.0 * x)[None, :].repeat(4, axis=0)          # steep exponential: |grad E|/E = 40
+    for kr in (1e-6, 1e-3):
+        krho = np.full_like(E, kr)
+        D = O.diffusion_coefficient(E, krho, (1.0 / n, 1.0 / 4), c=1.0)
+        g = O.gradient4(E, (1.0 / n, 1.0 / 4))
+        F = D * np.sqrt(g[0] ** 2 + g[1] ** 2)
+        ratio = (F / E)[:, 4:-4]                              # interior, away from mirrored ends
+        assert np.all(ratio < 1.0)
+        assert np.all(ratio > 0.99)
+
+
+# ----------------------------------------------------------------------------- gradient
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_gradient_exact_for_quartics(ndim):
+    """Sec. 3.2 (eq. ileyk_flux): the 5-point 4th-order stencil is exact for degree <= 4."""
+    shape = {1: (23,), 2: (11, 13), 3: (7, 9, 8)}[ndim]
+    h = [0.1, 0.07, 0.13][:ndim]
+    coords = np.meshgrid(*[np.arange(shape[ndim - 1 - d]) * h[d] + 0.3 for d in range(ndim)][::-1],
+                         indexing="ij")[::-1]             # coords[d] varies along dimension d
+    rng = np.random.default_rng(1)
+    c = rng.standard_normal((ndim, 5))
+    E = sum(sum(c[d, p] * coords[d] ** p for p in range(5)) for d in range(ndim)) + 50.0
+    exact = [sum(p * c[d, p] * coords[d] ** (p - 1) for p in range(1, 5)) for d in range(ndim)]
+    g = O.gradient4(E, h)
+    interior = tuple(slice(2, s - 2) for s in shape)
+    for d in range(ndim):
+        err = np.abs(g[d][interior] - exact[d][interior]).max()
+        assert err < 1e-9 * np.abs(exact[d]).max(), (d, err)
+
+
+def test_constant_energy_gives_thick_limit():
+    """E = const gives R = 0 and D = c/(3 kappa rho) exactly (Sec. 2.2 diffusion limit)."""
+    E = np.full((9, 12), 3.7)
+    kr = np.random.default_rng(2).uniform(0.5, 2.0, size=E.shape)
+    R = O.radiation_parameter(E, kr, (0.1, 0.2))
+    assert np.all(R < 1e-14)            # zero up to the rounding of the 1/12, 2/3 weights
+    D = O.diffusion_coefficient(E, kr, (0.1, 0.2), c=2.0)
+    assert np.allclose(D, 2.0 / (3.0 * kr), rtol=1e-14, atol=0)
+
+
+def test_mirror_ghosts_are_even_reflection():
+    """Zero-flux BC reading: E_{-1} = E_0, E_{-2} = E_1 on every face."""
+    E = np.arange(20.0).reshape(4, 5)
+    P = O.pad_mirror(E, 2)
+    assert np.all(P[2:-2, 1] == E[:, 0]) and np.all(P[2:-2, 0] == E[:, 1])
+    assert np.all(P[2:-2, -2] == E[:, -1]) and np.all(P[2:-2, -1] == E[:, -2])
+    assert np.all(P[1, 2:-2] == E[0]) and np.all(P[0, 2:-2] == E[1])
+
+
+# ----------------------------------------------------------------------------- faces
+def test_harmonic_face_is_series_conductance():
+    """Sec. 3.4: the face value between two cells is the series combination of two half cells.
+
+    The steady flux through half a cell of D_1 then half a cell of D_2 with end
+    values E_1, E_2 is (E_1 - E_2) / (h/(2 D_1) + h/(2 D_2)).
+    """
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        D1, D2 = 10.0 ** rng.uniform(-4, 4, size=2)
+        h, dt = rng.uniform(0.01, 1.0), rng.uniform(1e-3, 1.0)
+        D = np.array([[D1, D2]])
+        w = O.face_weights(D, dt, (h, 1.0))
+        E1, E2 = 2.0, 0.5
+        flux_series = (E1 - E2) / (h / (2 * D1) + h / (2 * D2))
+        # dt * flux / h  is the change of cell-2 content per unit area in one step
+        assert w[0][0, 1] * (E1 - E2) == pytest.approx(dt * flux_series / h, rel=1e-13)
+        assert w[0][0, 0] == 0.0 and np.all(w[1] == 0.0)
+
+
+# ----------------------------------------------------------------------------- operator + solve
+def _dct_solve(E, D, dt, h):
+    """Closed form for constant D under zero flux: the cell-centred Neumann Laplacian is
+    diagonalised by the orthonormal DCT-II with eigenvalues (4/h^2) sin^2(pi k / (2 n))."""
+    nd = E.ndim
+    Ehat = scipy.fft.dctn(E, type=2, norm="ortho")
+    lam = np.zeros_like(E)
+    for d in range(nd):
+        n = E.shape[nd - 1 - d]
+        k = np.arange(n)
+        ev = 4.0 / h[d] ** 2 * np.sin(np.pi * k / (2 * n)) ** 2
+        sh = [1] * nd
+        sh[nd - 1 - d] = n
+        lam = lam + ev.reshape(sh)
+    return scipy.fft.idctn(Ehat / (1.0 + dt * D * lam), type=2, norm="ortho")
+
+
+@pytest.mark.parametrize("shape,h", [((12, 7), (0.03, 0.05)), ((33, 20), (1 / 20, 1 / 33)),
+                                     ((6, 5, 4), (0.2, 0.25, 0.1)), ((64, 64), (1 / 64, 1 / 64))])
+def test_dct_closed_form_constant_coefficients(shape, h):
+    """Constant kappa rho with the diffusion limiter: oracle LU / CG == the spectral solution."""
+    rng = np.random.default_rng(4)
+    E = 1.0 + rng.random(shape)
+    kr = np.full(shape, 0.7)
+    dt, c = 2e-3, 1.3
+    D = c / (3 * 0.7)
+    ref = _dct_solve(E, D, dt, h)
+    for method in ("lu", "cg"):
+        x, info = O.diffusion_step(E, kr, dt, h, c=c, limiter="diffusion", method=method)
+        assert np.abs(x - ref).max() / np.abs(ref).max() < 1e-12, (method, info)
+
+
+def test_dct_closed_form_large_2d_and_3d():
+    """The same spectral pin at sizes the GPU runs: 1024^2 and 64^3 (CG)."""
+    for shape in ((1024, 1024), (64, 64, 64)):
+        n = shape[0]
+        h = tuple(1.0 / s for s in reversed(shape))
+        E = W.random_grid(shape, 99000, 1e-3).E
+        kr = np.full(shape, 10.0)
+        ref = _dct_solve(E, 1.0 / 30.0, 1e-3, h)
+        x, info = O.diffusion_step(E, kr, 1e-3, h, limiter="diffusion", method="cg")
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-12, info
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (3, 5), (16, 16), (4, 4, 4), (8, 5, 6)])
+def test_brute_force_solvers_agree(shape):
+    """Variable coefficients on tiny grids: dense LU == sparse LU == CG == Gauss-Seidel."""
+    g = W.random_grid(shape, 7000 + shape[0], dt=1e-2)
+    D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h)
+    w = O.face_weights(D, g.dt, g.h)
+    A = O.assemble_operator(w)
+    xs = {m: O.solve(A, g.E, method=m, w=w)[0] for m in ("lu", "direct", "cg", "gs")}
+    ref = xs["lu"]
+    for m, x in xs.items():
+        assert np.abs(x - ref).max() / np.abs(ref).max() < 1e-12, m
+    # brute force: A assembled from its definition agrees with the matrix-free stencil
+    v = np.random.default_rng(5).random(shape)
+    scale = abs(A) @ v.ravel()                       # row magnitudes bound the rounding
+    assert np.all(np.abs(A @ v.ravel() - O.apply_operator(w, v).ravel()) <= 1e-15 * scale)
+
+
+def test_operator_is_symmetric_m_matrix():
+    g = W.random_grid((9, 11), 7100, dt=5e-3)
+    w = O.face_weights(O.diffusion_coefficient(g.E, g.kappa_rho, g.h), g.dt, g.h)
+    A = O.assemble_operator(w).toarray()
+    assert np.array_equal(A, A.T)
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0)
+    assert np.allclose(A.sum(axis=0), 1.0, rtol=0, atol=1e-12)        # 1^T A = 1^T (zero flux)
+    assert np.linalg.eigvalsh(A).min() >= 1.0 - 1e-12
+
+
+def test_conservation_and_residual_certificate():
+    """Zero flux conserves sum(E); ||x - x*|| <= ||b - A x|| because lambda_min(A) >= 1."""
+    g = W.random_grid((40, 40), 7200, dt=1e-2)
+    x, info, A, w = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, method="direct",
+                                     return_operator=True)
+    assert abs(x.sum() - g.E.sum()) / g.E.sum() < 1e-13
+    xl, _ = O.solve(A, g.E, method="cg", tol=1e-5, w=w)              # deliberately loose
+    r = np.linalg.norm(g.E.ravel() - A @ xl.ravel())
+    err = np.linalg.norm((xl - x).ravel())
+    assert err <= r * (1 + 1e-12)
+    # and the q_b bound on the relative error
+    assert err / np.linalg.norm(x) <= O.q_b(g.E) * r / np.linalg.norm(g.E) * (1 + 1e-12)
+
+
+def test_config1_symmetry():
+    """The config-1 pulse sits on a cell corner: inputs are D4-symmetric, so D and E^{n+1} are."""
+    g = W.pulse_2d()
+    D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h, g.c)
+    for T in (D.T, D[::-1, :], D[:, ::-1], D[::-1, ::-1].T):
+        assert np.abs(T - D).max() <= 1e-15 * D.max()      # a few ulps
+    x, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c)
+    for T in (x.T, x[::-1, :], x[:, ::-1]):
+        assert np.abs(T - x).max() <= 1e-12 * x.max()
+    assert info.rel_residual < 1e-13
+    # the configuration's known range: R peaks near 5.5, D in [0.014, 1/30]
+    R = O.radiation_parameter(g.E, g.kappa_rho, g.h)
+    assert 5.0 < R.max() < 6.0 and D.max() == pytest.approx(1 / 30, rel=1e-12) and D.min() > 0.0135
+
+
+def test_thick_pulse_variance_grows_exactly():
+    """Backward Euler with constant D: the pulse variance grows by exactly 2 D dt per step and axis.
+
+    For the cell-centred stencil, sum_i (x_i - x0)^2 (L u)_i = -2 D sum u along each axis
+    (the discrete Laplacian of a quadratic is exact); boundary terms vanish for a pulse far
+    from the walls.  This pins dt, the 1/h^2 scaling, D = c/(3 kappa rho) and the axis order.
+    """
+    nx, ny = 96, 64
+    h = (1.0 / nx, 1.5 / ny)                       # anisotropic cells: x and y cannot be swapped
+    xc = (np.arange(nx) + 0.5) * h[0]
+    yc = (np.arange(ny) + 0.5) * h[1]
+    X, Y = np.meshgrid(xc, yc, indexing="xy")
+    u0 = 1e3 * np.exp(-((X - 0.5) ** 2 + (Y - 0.75) ** 2) / (2 * 0.05 ** 2))
+    E = 1.0 + u0
+    kr, c, dt = 5.0, 2.0, 2e-4
+    D = c / (3 * kr)
+    x = E.copy()
+    mx = [((X - 0.5) ** 2 * u0).sum()]
+    my = [((Y - 0.75) ** 2 * u0).sum()]
+    for _ in range(3):
+        x, info = O.diffusion_step(x, np.full_like(E, kr), dt, h, c=c, limiter="diffusion",
+                                   method="direct")
+        u = x - 1.0
+        mx.append(((X - 0.5) ** 2 * u).sum())
+        my.append(((Y - 0.75) ** 2 * u).sum())
+    M0 = u0.sum()
+    for k in range(3):
+        assert (mx[k + 1] - mx[k]) == pytest.approx(2 * D * dt * M0, rel=1e-9)
+        assert (my[k + 1] - my[k]) == pytest.approx(2 * D * dt * M0, rel=1e-9)
+
+
+def test_thick_pulse_converges_to_continuum():
+    """Gaussian pulse in the diffusion limit: error against the continuum solution
+    E = 1 + A (s^2/(s^2 + 2Dt))^{d/2} exp(-r^2/(2(s^2+2Dt))) falls as O(dt) and O(h^2)."""
+    A, s, kr, T = 1e3, 0.05, 10.0, 4e-3
+    D = 1.0 / (3 * kr)
+
+    def run(n, steps):
+        g = W.pulse_2d(n=n, kappa_rho=kr, dt=T / steps, limiter="diffusion")
+        x = g.E
+        for _ in range(steps):
+            x, _ = O.diffusion_step(x, g.kappa_rho, g.dt, g.h, limiter="diffusion", method="cg")
+        xc = W.cell_centres(n)
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        st2 = s * s + 2 * D * T
+        ex = 1.0 + A * (s * s / st2) * np.exp(-((X - .5) ** 2 + (Y - .5) ** 2) / (2 * st2))
+        return np.sqrt(np.mean((x - ex) ** 2)) / A
+
+    e_t = [run(128, k) for k in (2, 4, 8)]
+    r1, r2 = e_t[0] / e_t[1], e_t[1] / e_t[2]
+    assert 1.6 < r1 < 2.2 and 1.5 < r2 < 2.2, e_t                 # first order in time
+    e_h = [run(n, 32) for n in (32, 64)]
+    assert e_h[1] < e_h[0] / 2.5, e_h                              # second order in space (dt error small)
+
+
+def test_free_streaming_front_speed(golden_dir):
+    """Sec. 4.4: with the limiter the front moves no faster than c; without it, far faster."""
+    p = json.load(open(os.path.join(golden_dir, "e4_optically_thin.json")))
+    c = W.CGS["c"]
+    n = p["n_cells"]
+    h = (p["x_hi_cm"] - p["x_lo_cm"]) / n
+    xc = p["x_lo_cm"] + (np.arange(n) + 0.5) * h
+    from scipy.special import erf
+    E0 = p["E0_erg_cm3"] + 0.5 * (1.0 - erf(xc / p["d_cm"])) * p["E1_erg_cm3"]
+    kr = np.full(n, p["rho_g_cm3"] * p["kappa_cm2_g"])
+    # the stated total optical depth (0.002) is 10x below kappa*rho*L = 0.02 for the stated
+    # rho, kappa and slab; both are optically thin, and the stated rho and kappa are used
+    tau = kr[0] * (p["x_hi_cm"] - p["x_lo_cm"])
+    assert tau == pytest.approx(10 * p["optical_depth_total"]) and tau < 0.05
+    steps = 60
+
+    def run(limiter):
+        x = E0.copy()
+        for _ in range(steps):
+            x, info = O.diffusion_step(x, kr, p["dt_s"], (h,), c=c, limiter=limiter, method="direct")
+        return x
+
+    t = steps * p["dt_s"]
+    half = 0.5 * p["E1_erg_cm3"]
+    x_lp = run("lp")
+    f_lp = xc[np.nonzero(x_lp < half)[0][0]]
+    assert f_lp <= c * t + 3 * h                 # the half-maximum front is causal
+    assert f_lp >= 0.5 * c * t                   # and it does stream
+    ahead = xc > c * t + 8 * h
+    frac = lambda x: (x[ahead] - p["E0_erg_cm3"]).sum() / (x - p["E0_erg_cm3"]).sum()
+    assert frac(x_lp) < 1e-2                     # almost no energy beyond the light front
+    assert frac(run("diffusion")) > 0.2          # the unlimited diffusion front is acausal
+
+
+# ----------------------------------------------------------------------------- exchange
+def _ferrari_root(beta):
+    """Positive root of beta y^4 + y - 1 = 0 via Ferrari's resolvent cubic (closed form).
+
+    With p = 1/beta: y^4 + p y - p = 0.  Adding 2 m y^2 + m^2 to both sides makes the
+    right side the square 2m (y - p/(4m))^2 when 8 m^3 + 8 p m - p^2 = 0 (one real root,
+    Cardano).  Then y^2 + s y + m - p/(2s) = 0 with s = sqrt(2m) holds the roots of
+    opposite sign, i.e. the positive one.
+    """
+    p = 1.0 / beta
+    P, Q = p, -p * p / 8.0                    # m^3 + P m + Q = 0
+    disc = np.sqrt((Q / 2) ** 2 + (P / 3) ** 3)
+    m = np.cbrt(-Q / 2 + disc) + np.cbrt(-Q / 2 - disc)
+    s = np.sqrt(2 * m)
+    cq = m - p / (2 * s)
+    return (-s + np.sqrt(s * s - 4 * cq)) / 2
+
+
+def test_exchange_root_closed_form_and_roots():
+    rng = np.random.default_rng(6)
+    n = 200
+    E = 10.0 ** rng.uniform(-2, 2, n)
+    eps = 10.0 ** rng.uniform(-2, 2, n)
+    rho = 10.0 ** rng.uniform(-1, 1, n)
+    kap = 10.0 ** rng.uniform(-2, 2, n)
+    dt = 10.0 ** rng.uniform(-3, 0, n)
+    E2, eps2 = O.exchange(E, eps, rho, kap, dt, c=1.0, a_r=1.0, c_v=1.0)
+    a1 = kap * dt / rho ** 3
+    a2 = kap * rho * dt
+    for i in range(n):
+        rts = np.roots([a1[i], 0, 0, 1 + a2[i], -((1 + a2[i]) * eps[i] + a2[i] * E[i])])
+        pos = [r.real for r in rts if abs(r.imag) < 1e-9 * abs(r) and r.real > 0]
+        assert len(pos) == 1                                       # unique positive root
+        assert eps2[i] == pytest.approx(pos[0], rel=1e-9)
+        assert 0 < eps2[i] < eps[i] + E[i]
+    C = (1 + a2) * eps + a2 * E
+    beta = a1 * C ** 3 / (1 + a2) ** 4
+    ok = (beta > 1e-2) & (beta < 1e2)
+    y1 = _ferrari_root(beta[ok])
+    yor = (eps2 * (1 + a2) / C)[ok]
+    assert ok.sum() > 20 and np.all(abs(y1 - yor) < 1e-11)
+
+
+def test_exchange_conserves_and_satisfies_implicit_pair():
+    """eps' + E' = eps + E, and both point-implicit equations of Sec. 3.3 hold at the root."""
+    g = W.c2_inputs(64)
+    E2, eps2 = O.exchange(g.E, g.eps, g.rho, g.kappa, g.dt, 1.0, 1.0, 1.0)
+    tot = g.E + g.eps
+    assert np.abs(E2 + eps2 - tot).max() / tot.max() < 1e-14
+    # eps' = eps + dt [c k rho E' - 4 k rho sigma T'^4] with 4 sigma = c a_r, T' = eps'/(rho c_v)
+    T2 = eps2 / (g.rho * 1.0)
+    lhs = eps2 - g.eps
+    rhs = g.dt * (g.kappa * g.rho * E2 - g.kappa * g.rho * T2 ** 4)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * tot.max()
+
+
+def test_exchange_limits():
+    g = W.c2_inputs(32)
+    E2, eps2 = O.exchange(g.E, g.eps, g.rho, g.kappa, 1e-300, 1.0, 1.0, 1.0)
+    assert np.allclose(E2, g.E, rtol=1e-15) and np.allclose(eps2, g.eps, rtol=1e-15)
+    E3, eps3 = O.exchange(g.E, g.eps, g.rho, g.kappa, 1e12, 1.0, 1.0, 1.0)
+    T3 = eps3 / g.rho
+    assert np.allclose(E3, T3 ** 4, rtol=1e-9)                     # equilibrium E = a_r T^4
+    assert np.allclose(E3 + eps3, g.E + g.eps, rtol=1e-14)
+
+
+def test_heating_cooling_relaxation(golden_dir):
+    """Sec. 4.1 with the paper's parameters: the gas relaxes monotonically to e_equil on a
+    time scale that does not depend on the step, and E stays essentially constant."""
+    p = json.load(open(os.path.join(golden_dir, "e1_heating_cooling.json")))
+    cg = W.CGS
+    rho, kap, E0 = p["rho_g_cm3"], p["kappa_cm2_g"], p["E_erg_cm3"]
+    c_v = cg["k_b"] / ((p["gamma"] - 1) * p["mu"] * cg["m_p"])
+    a_r, c = cg["a_r"], cg["c"]
+    one = lambda v: np.array([v])
+    for fac in p["e_over_e_equil_initial"]:
+        # e_equil: the total is conserved and a_r T(e)^4 = E at equilibrium, with e0 = fac e_equil
+        lo, hi = 0.0, E0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            g = a_r * (mid / (rho * c_v)) ** 4 + mid - (fac * mid + E0)
+            lo, hi = (mid, hi) if g < 0 else (lo, mid)
+        e_eq = 0.5 * (lo + hi)
+        E_eq = fac * e_eq + E0 - e_eq
+        # equilibrium is a fixed point of the implicit update for any step
+        for dt in (1e-12, 1e-6, 1.0):
+            E1, e1 = O.exchange(one(E_eq), one(e_eq), one(rho), one(kap), dt, c, a_r, c_v)
+            assert e1[0] == pytest.approx(e_eq, rel=1e-9) and E1[0] == pytest.approx(E_eq, rel=1e-14)
+        # a very large step lands on the equilibrium at once
+        E1, e1 = O.exchange(one(E0), one(fac * e_eq), one(rho), one(kap), 1e6, c, a_r, c_v)
+        assert e1[0] == pytest.approx(e_eq, rel=1e-9)
+        t_end = 5e-9
+        traj = {}
+        for dt in p["dt_s"]:
+            E, e = one(E0), one(fac * e_eq)
+            hist = [e[0]]
+            for _ in range(int(round(t_end / dt))):
+                E, e = O.exchange(E, e, one(rho), one(kap), dt, c, a_r, c_v)
+                hist.append(e[0])
+            hist = np.array(hist)
+            d = np.diff(hist)
+            if fac < 1:
+                assert np.all(d >= 0) and hist[-1] < e_eq * (1 + 1e-9)       # heats, from below
+            else:
+                assert np.all(d <= 0) and hist[-1] > e_eq * (1 - 1e-9)       # cools, from above
+            # E changes by at most the gas energy moved: below 1 % of E here
+            assert abs(E[0] - E0) <= abs(fac * e_eq - e_eq) * (1 + 1e-9) and abs(E[0] - E0) / E0 < 1e-2
+            assert E[0] + e[0] == pytest.approx(E0 + fac * e_eq, rel=1e-11)   # rounding over 1e4 steps
+            traj[dt] = (hist[-1], E[0])
+            # continue with a coarser step to t = 1e-6 s: the state settles on the equilibrium
+            for _ in range(1000):
+                E, e = O.exchange(E, e, one(rho), one(kap), 1e-9, c, a_r, c_v)
+            assert e[0] == pytest.approx(e_eq, rel=1e-6) and E[0] == pytest.approx(E_eq, rel=1e-9)
+        a, b = traj[p["dt_s"][0]][0], traj[p["dt_s"][1]][0]
+        if fac < 1:
+            assert 0.02 * e_eq < a < e_eq and abs(a - b) / a < 0.05          # same time scale
+        else:
+            assert e_eq < a < 2 * e_eq and abs(a - b) / a < 0.05
