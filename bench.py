@@ -1,0 +1,189 @@
+"""Throughput benchmark of the FLD radiation-energy step on one MI355X.
+
+Default workload: the 2D 1024 x 1024 FP64 configuration with gas -- every step
+is one implicit diffusion solve to a 1e-10 relative residual followed by the
+implicit gas-radiation energy exchange, on seeded synthetic fields that stay
+resident in HBM.  ``--steps K`` steps are timed after ``--warmup W`` untimed
+ones (the trajectory continues through both).
+
+One JSON line is printed: cell-updates/s (cells x steps / wall time), per-step
+latency percentiles, the roofline of the dominant kernel (the level-0 red-black
+half sweep, timed with HIP events right after the timed region) and the FP64
+CPU oracle timed on one step of the same grid on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-reps", type=int, default=200)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def smooth_bytes_per_cell(ndim: int, word: int) -> int:
+    """Algorithmic bytes of one red-black half sweep per cell of the level:
+    read x of every cell (neighbours), b of the updated half, every face weight
+    (each face touches one cell of each colour), write x of the updated half."""
+    return word * (1 + ndim) + word  # x + w*d + (b/2 + x_write/2)
+
+
+def cpu_baseline(g, steps_gas: bool):
+    import oracle as O
+    t0 = time.perf_counter()
+    x, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c)
+    if steps_gas:
+        O.exchange(x, g.eps, g.rho, g.kappa, g.dt, g.c, g.a_r, g.c_v)
+    t = time.perf_counter() - t0
+    return t, info
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("bench.py: only single-GPU runs are supported (the workload is one GPU's share)")
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2104_03968_amd as fld
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = args.config
+    prec = args.precision or ("mixed" if cfg == "c3" else "fp64")
+    precision = fld.FLD_PREC_MIXED if prec == "mixed" else fld.FLD_PREC_FP64
+    log(f"bench: building inputs for {cfg} ({prec})")
+
+    has_gas = False
+    if cfg == "c1":
+        grids = [W.pulse_2d()]
+        workload = "2D 64x64 Gaussian pulse, kappa*rho=10, one backward-Euler FLD step"
+    elif cfg == "c2":
+        grids = [W.c2_inputs(1024)]
+        has_gas = True
+        workload = ("2D 1024x1024 FP64 FLD step + implicit gas-radiation exchange, log10(kappa*rho) "
+                    "in [-2,2] (32 Fourier modes), log-normal E (sigma=1), dt=1e-3, rtol=1e-10")
+    elif cfg == "c3":
+        grids = [W.c3_inputs(256)]
+        workload = ("3D 256^3 FLD step, config-2 field recipe in 3D, dt=1e-3, rtol=1e-10, "
+                    f"{prec} (FP32 V-cycles in FP64 defect correction)" )
+    else:
+        lay = W.c4_layout()
+        grids = [W.c4_grid(j, n, dt) for j, (n, dt) in enumerate(lay)]
+        workload = "512 independent 2D grids, sides U{64..512 step 32}, dt U[1e-4,1e-2], one launch per phase"
+    ncells = sum(g.E.size for g in grids)
+    shapes = [g.E.shape for g in grids]
+    plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    E = [to(g.E) for g in grids]
+    K = [to(g.kappa_rho) for g in grids]
+    dts = [g.dt for g in grids]
+    if has_gas:
+        eps = [to(g.eps) for g in grids]
+        rho = [to(g.rho) for g in grids]
+        kap = [to(g.kappa) for g in grids]
+        gas = fld.fld_gas_default(c=grids[0].c, a_rad=grids[0].a_r, c_v=grids[0].c_v)
+    stream = torch.cuda.current_stream()
+
+    cycles = []
+
+    def one_step():
+        rc, st = plan.step(E, K, E, dts, stream=stream, check=False)
+        if rc != 0:
+            raise RuntimeError(f"fld_step failed: {fld.fld_strerror(rc)} {st[:2]}")
+        if has_gas:
+            plan.exchange(E, eps, rho, kap, dts, gas, stream=stream)
+        cycles.append(max(s["cycles"] for s in st))
+        return st
+
+    log(f"bench: {len(grids)} grid(s), {ncells} cells; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    cycles.clear()
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st = one_step()
+        if has_gas:
+            stream.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = ncells * args.steps / elapsed
+    log(f"bench: {args.steps} steps in {elapsed:.4f} s -> {value:.4e} cell-updates/s, cycles {cycles}")
+    if has_gas:
+        rc, nbis = plan.exchange_status(stream)
+        assert rc == 0, "exchange rejected cells"
+
+    # dominant kernel: level-0 red-black half sweep, timed on the same stream
+    ms, cells = plan.profile(fld.FLD_KERNEL_SMOOTH, 0, args.profile_reps, stream)
+    ndim = len(shapes[0])
+    word = 4 if precision == fld.FLD_PREC_MIXED else 8
+    bpc = smooth_bytes_per_cell(ndim, word)
+    achieved = bpc * cells / (ms * 1e-3) / 1e9
+    log(f"bench: level-0 half sweep {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")
+
+    out = {
+        "metric": "cell-updates/s of implicit FLD step at 1e-10 residual; p50/p99 solve latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == fld.FLD_PREC_FP64 else "f32-in-f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
+                   "rtol": 1e-10},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_smooth level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"},
+    }
+    if not args.no_cpu_baseline:
+        g0 = grids[0] if cfg != "c4" else grids[0]
+        log("bench: timing the FP64 CPU oracle on one step of the first grid")
+        t, info = cpu_baseline(g0, has_gas)
+        out["cpu_baseline"] = {"value": g0.E.size / t, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": (f"one FLD step of a {'x'.join(map(str, g0.E.shape))} grid "
+                                          f"({info.method}, {info.iterations} iterations, {t:.1f} s; "
+                                          "scipy sparse + numpy, single-threaded)"),
+                               "host_cpus": os.cpu_count()}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * fld.h -- C ABI of the MI355X flux-limited-diffusion (FLD) radiation-energy step.
+ *
+ * The method is the one of Moens et al., "Radiation-hydrodynamics with
+ * MPI-AMRVAC: flux-limited diffusion" (A&A 2022):
+ *
+ *   diffusion (Sec. 3.4):  E^{n+1}/dt - div(D^n grad E^{n+1}) = E^n/dt,
+ *     D = c lambda(R) / (kappa rho)                (Sec. 2.2, eq. fld_F)
+ *     R = |grad E| / (kappa rho E)                 (Sec. 2.2)
+ *     lambda = (2+R)/(6+3R+R^2)                    (Sec. 2.2, eq. fld_lambda)
+ *     grad E by the 4th-order central stencil      (Sec. 3.2, eq. ileyk_flux)
+ *     face D by the harmonic mean of cell values   (Sec. 3.4)
+ *     5-point (2D) / 7-point (3D) finite volumes   (Sec. 3.4, eq. discdiff)
+ *   exchange (Sec. 3.3): the point-implicit gas/radiation energy exchange, a
+ *     quartic for the new gas energy solved by Halley's method with a
+ *     bisection fallback, then E^{n+1} = (a1 eps'^4 + E^n)/(1 + a2).
+ *
+ * Conventions shared by every call:
+ *   - Grids are uniform Cartesian, 2D or 3D, every axis >= 2 cells.  A field
+ *     is one contiguous FP64 array, x fastest: idx = i + nx*(j + ny*k).
+ *   - Boundaries are zero flux (Neumann with zero gradient, Sec. 3.4): ghost
+ *     values mirror the interior (E_{-1} = E_0, E_{-2} = E_1).
+ *   - "device" pointers are HIP device memory on the device that was current
+ *     when the plan was created; "host" pointers are ordinary host memory.
+ *     The caller owns every buffer it passes; the library never frees or
+ *     retains caller memory beyond the call, except the workspace bound to a
+ *     plan (kept until fld_plan_destroy or the next bind) and the server arena.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued on it; calls documented as synchronous also wait for it.
+ *   - Every call returns FLD_OK (0), a positive status (FLD_PENDING) or a
+ *     negative error code; fld_strerror() names it.  No C++ exception crosses
+ *     the boundary.  A plan must not be used from two threads at once; a
+ *     server may be.
+ */
+#ifndef FLD_H
+#define FLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define FLD_OK                   0
+#define FLD_PENDING              1   /* fld_poll: the request is not finished  */
+#define FLD_ERR_INVALID_ARG     -1   /* bad argument (null, size, option)      */
+#define FLD_ERR_BAD_INPUT       -2   /* device-detected E <= 0, kappa*rho <= 0,
+                                        rho <= 0, kappa < 0 or a non-finite value */
+#define FLD_ERR_NOT_CONVERGED   -3   /* rtol not met within max_cycles (or the
+                                        residual stagnated); the output holds the
+                                        best iterate and the stats are filled   */
+#define FLD_ERR_TOO_LARGE       -4   /* request larger than the server arena   */
+#define FLD_ERR_UNKNOWN_TICKET  -5
+#define FLD_ERR_HIP             -6   /* a HIP runtime call failed              */
+#define FLD_ERR_NO_WORKSPACE    -7   /* plan has no (or too small) workspace   */
+#define FLD_ERR_UNSUPPORTED     -8   /* option not built (e.g. a BC other than zero flux) */
+#define FLD_ERR_SHUTDOWN        -9   /* server is shutting down               */
+
+/* ---- options ------------------------------------------------------------ */
+#define FLD_LIMITER_LP          0    /* lambda = (2+R)/(6+3R+R^2)   (Sec. 2.2, eq. fld_lambda) */
+#define FLD_LIMITER_DIFFUSION   1    /* lambda = 1/3, the optically thick limit (Sec. 2.2)   */
+
+#define FLD_BC_ZERO_FLUX        0    /* Neumann, zero gradient (Sec. 3.4)      */
+
+#define FLD_PREC_FP64           0    /* every step in FP64                     */
+#define FLD_PREC_MIXED          1    /* FP32 V-cycles inside FP64 defect correction:
+                                        residual, update and stop test in FP64 */
+
+/* One grid: ndim in {2,3}; n[d] cells and h[d] cell width along x, y, z
+   (n[2], h[2] ignored in 2D). */
+typedef struct fld_grid {
+    int32_t ndim;
+    int32_t n[3];
+    double  h[3];
+} fld_grid;
+
+/* Solver options (fld_opts_default fills the defaults given in brackets). */
+typedef struct fld_opts {
+    double  c;            /* speed of light in the caller's units [1]               */
+    int32_t limiter;      /* FLD_LIMITER_* [LP]                                      */
+    int32_t bc[6];        /* per face x-,x+,y-,y+,z-,z+: FLD_BC_* [ZERO_FLUX]        */
+    int32_t precision;    /* FLD_PREC_* [FP64]                                       */
+    double  rtol;         /* stop when ||E^n - A E||_2 <= rtol ||E^n||_2 [1e-10]     */
+    int32_t max_cycles;   /* V-cycles (outer iterations in mixed mode) per step [50] */
+    int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after the coarse
+                             correction [2, 2]                                      */
+    int32_t use_graph;    /* replay V-cycles from a captured hipGraph [1]           */
+    int32_t autotune;     /* time the candidate launch shapes at bind time [0]      */
+} fld_opts;
+
+/* Per-grid result of fld_step. */
+typedef struct fld_stats {
+    int32_t cycles;        /* V-cycles (outer iterations) performed                 */
+    int32_t status;        /* FLD_OK, FLD_ERR_NOT_CONVERGED or FLD_ERR_BAD_INPUT    */
+    double  rel_residual;  /* final ||b - A x||_2 / ||b||_2, FP64                   */
+    double  q_b;           /* ||b||_2 / (sqrt(N) |mean b|): relative error of the
+                              result <= q_b * rel_residual (A is SPD, lambda_min>=1,
+                              and zero flux conserves the mean)                     */
+    double  b_norm;        /* ||E^n||_2                                             */
+    double  b_sum;         /* sum of E^n (conserved by the exact solution)          */
+} fld_stats;
+
+/* Gas/radiation exchange constants (Sec. 3.3).  c_v = k_b / ((gamma-1) mu m_p)
+   so that T_g = eps / (rho c_v); a_rad = 4 sigma / c. */
+typedef struct fld_gas {
+    double  c;
+    double  a_rad;
+    double  c_v;
+    int32_t max_halley;   /* Halley iterations before bisection [100] (0 forces bisection) */
+    double  root_rtol;    /* Halley stop: |step| <= root_rtol * root [4 * 2^-52]   */
+} fld_gas;
+
+typedef struct fld_plan_s* fld_plan_t;
+
+/* Device pointers into a bound workspace for one level of one grid's
+   multigrid hierarchy (level 0 = the grid itself).  w[d] holds the lower-face
+   weights dt * D_face / h_d^2 along d (entry 0 along d is the domain face: 0).
+   Pointers that the plan's precision does not use are NULL. */
+typedef struct fld_level_view {
+    int32_t ndim;
+    int32_t n[3];
+    double* x;            /* FP64 solution / correction                             */
+    double* b;            /* FP64 right-hand side                                   */
+    double* w[3];         /* FP64 face weights                                      */
+    float*  x32;
+    float*  b32;
+    float*  w32[3];
+} fld_level_view;
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t fld_version(void);
+/* Static string naming a status code; never NULL. */
+const char* fld_strerror(int32_t code);
+/* Text of the last HIP failure seen on the calling thread (empty if none);
+   valid until the next failing call on that thread. */
+const char* fld_last_error(void);
+/* Fill *o with the defaults listed in fld_opts. */
+void fld_opts_default(fld_opts* o);
+void fld_gas_default(fld_gas* g);
+
+/* Build a plan for ngrids independent grids solved together: the multigrid
+   hierarchy of each grid (halve every axis while all are even and >= 4), the
+   workspace layout and the launch work-lists.  Host only: no device memory
+   is allocated.  Errors: INVALID_ARG (null, ngrids < 1, ndim not 2/3, an axis
+   < 2, h <= 0, bad option), UNSUPPORTED (a BC other than zero flux). */
+int32_t fld_plan_create(const fld_grid* grids, int32_t ngrids, const fld_opts* opts,
+                        fld_plan_t* out);
+int32_t fld_plan_destroy(fld_plan_t plan);
+
+/* Bytes of device workspace the plan needs (256-byte aligned). */
+int32_t fld_plan_workspace_bytes(fld_plan_t plan, size_t* bytes);
+/* Bind caller-owned device memory of >= the size above (256-byte aligned).  The
+   library keeps the pointer (never frees it) and writes its level tables there.
+   Synchronous.  Errors: INVALID_ARG, NO_WORKSPACE (too small), HIP. */
+int32_t fld_plan_bind_workspace(fld_plan_t plan, void* dev, size_t bytes);
+
+/* Number of multigrid levels of grid g, and a view of one level (see above). */
+int32_t fld_plan_levels(fld_plan_t plan, int32_t g, int32_t* nlevels);
+int32_t fld_plan_level_view(fld_plan_t plan, int32_t g, int32_t level, fld_level_view* out);
+
+/* Coefficients only (the first stage of fld_step), for every grid g:
+   D from E_in[g] and kappa_rho[g] (device, N_g doubles each) with dt[g] (host
+   array of ngrids), written as face weights into the workspace of every level
+   (level 0 per Sec. 3.4; coarser levels average the sub-faces and scale by
+   1/4 per halving).  Asynchronous on stream.  Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
+int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in,
+                         const double* const* kappa_rho, const double* dt, void* stream);
+
+/* One implicit FLD diffusion step for every grid g of the plan:
+     E_out[g] = (I + dt[g] L(D(E_in[g])))^{-1} E_in[g]
+   with D lagged at E_in (Sec. 3.4).  E_in, kappa_rho, E_out: host arrays of
+   ngrids device pointers to N_g doubles (caller-owned; E_out[g] may equal
+   E_in[g]).  dt: host array of ngrids.  Solved by multigrid V-cycles to
+   opts.rtol relative residual (FP64 residual in both precisions).
+   Synchronous: returns after the stream has finished the step.  stats: host
+   array of ngrids (may be NULL).  Returns FLD_OK, or the first non-OK grid
+   status (NOT_CONVERGED, BAD_INPUT) -- every grid's output is still written --
+   or INVALID_ARG / NO_WORKSPACE / HIP. */
+int32_t fld_step(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho,
+                 double* const* E_out, const double* dt, void* stream, fld_stats* stats);
+
+/* Point-implicit gas-radiation energy exchange (Sec. 3.3), in place, per cell
+   of every grid g: with a1 = c a_rad kappa dt / (rho^3 c_v^4) and
+   a2 = c kappa rho dt, eps' is the unique root in ]0, eps + E[ of
+   a1 x^4 + (1+a2) x - ((1+a2) eps + a2 E) = 0 and E' = (a1 eps'^4 + E)/(1+a2).
+   E, eps (read/write), rho, kappa (read): host arrays of ngrids device
+   pointers to N_g doubles.  dt: host array of ngrids.  Asynchronous on stream.
+   Cells with rho <= 0, kappa < 0, E < 0, eps < 0 or non-finite values are left
+   unchanged and reported by the next fld_exchange_status().
+   Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
+int32_t fld_exchange(fld_plan_t plan, double* const* E, double* const* eps,
+                     const double* const* rho, const double* const* kappa,
+                     const double* dt, const fld_gas* gas, void* stream);
+/* Synchronous: waits for stream, returns FLD_OK or FLD_ERR_BAD_INPUT if any
+   cell of any earlier fld_exchange on this plan was rejected (and clears the flag);
+   *bisected (may be NULL) receives the number of cells that needed the
+   bisection fallback since the last call. */
+int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
+
+/* ---- measurement -------------------------------------------------------- */
+#define FLD_KERNEL_SMOOTH    0   /* one red-black half sweep over every grid's level `level` */
+#define FLD_KERNEL_RESIDUAL  1   /* level-0 FP64 residual and its per-tile norms           */
+#define FLD_KERNEL_RESTRICT  2   /* residual + restriction from level `level` to level+1   */
+#define FLD_KERNEL_PROLONG   3   /* prolongation + correction from level+1 to `level`      */
+#define FLD_KERNEL_COEFF     4   /* coefficients, on the inputs of the last fld_step        */
+#define FLD_KERNEL_VCYCLE    5   /* one whole V-cycle with its residual test               */
+#define FLD_KERNEL_EXCHANGE  6   /* exchange, on the arrays of the last fld_exchange (alters them) */
+
+/* Time `reps` back-to-back launches of one kernel of the plan (launch shape
+   as fld_step uses it) between two HIP events on `stream`; *avg_ms receives
+   the mean time per launch (it includes the dispatch gap between launches)
+   and *cells the cells one launch processes (the level's cells summed over
+   the grids).  Every grid is made active for the measurement and inactive
+   afterwards, so call it between steps only.  The level arrays are modified
+   (smoothing further an already converged iterate); fld_step outputs are not.
+   Synchronous.  Errors: INVALID_ARG (kernel, level or reps), NO_WORKSPACE, HIP. */
+int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps,
+                           void* stream, double* avg_ms, int64_t* cells);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLD_H */

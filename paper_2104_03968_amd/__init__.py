@@ -1,0 +1,332 @@
+"""Python binding of the MI355X FLD radiation-energy step library (``libfld.so``).
+
+Argument marshalling only: every computation runs in the HIP kernels behind
+the C ABI of ``include/fld.h``.  PyTorch provides device memory (the plan
+workspace and the fields are torch tensors) and streams.  The module-level
+functions carry the C names; :class:`Plan` is a small convenience wrapper.
+
+Importing this module loads the in-tree ``libfld.so`` and raises if it is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfld.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_2104_03968_amd/build.py` "
+        "(hipcc, gfx950). There is no CPU fallback.")
+_lib = C.CDLL(LIB_PATH)
+
+# ---- constants (include/fld.h) ---------------------------------------------------------
+FLD_OK = 0
+FLD_PENDING = 1
+FLD_ERR_INVALID_ARG = -1
+FLD_ERR_BAD_INPUT = -2
+FLD_ERR_NOT_CONVERGED = -3
+FLD_ERR_TOO_LARGE = -4
+FLD_ERR_UNKNOWN_TICKET = -5
+FLD_ERR_HIP = -6
+FLD_ERR_NO_WORKSPACE = -7
+FLD_ERR_UNSUPPORTED = -8
+FLD_ERR_SHUTDOWN = -9
+FLD_LIMITER_LP = 0
+FLD_LIMITER_DIFFUSION = 1
+FLD_BC_ZERO_FLUX = 0
+FLD_PREC_FP64 = 0
+FLD_PREC_MIXED = 1
+FLD_KERNEL_SMOOTH = 0
+FLD_KERNEL_RESIDUAL = 1
+FLD_KERNEL_RESTRICT = 2
+FLD_KERNEL_PROLONG = 3
+FLD_KERNEL_COEFF = 4
+FLD_KERNEL_VCYCLE = 5
+FLD_KERNEL_EXCHANGE = 6
+
+
+class fld_grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3)]
+
+
+class fld_opts(C.Structure):
+    _fields_ = [("c", C.c_double), ("limiter", C.c_int32), ("bc", C.c_int32 * 6),
+                ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
+                ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
+                ("autotune", C.c_int32)]
+
+
+class fld_stats(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("status", C.c_int32), ("rel_residual", C.c_double),
+                ("q_b", C.c_double), ("b_norm", C.c_double), ("b_sum", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fld_gas(C.Structure):
+    _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("c_v", C.c_double),
+                ("max_halley", C.c_int32), ("root_rtol", C.c_double)]
+
+
+class fld_level_view(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("x", C.c_void_p), ("b", C.c_void_p),
+                ("w", C.c_void_p * 3), ("x32", C.c_void_p), ("b32", C.c_void_p),
+                ("w32", C.c_void_p * 3)]
+
+
+_P = C.c_void_p
+_PP = C.POINTER(C.c_void_p)
+_sig = {
+    "fld_version": (C.c_int32, []),
+    "fld_strerror": (C.c_char_p, [C.c_int32]),
+    "fld_last_error": (C.c_char_p, []),
+    "fld_opts_default": (None, [C.POINTER(fld_opts)]),
+    "fld_gas_default": (None, [C.POINTER(fld_gas)]),
+    "fld_plan_create": (C.c_int32, [C.POINTER(fld_grid), C.c_int32, C.POINTER(fld_opts), _PP]),
+    "fld_plan_destroy": (C.c_int32, [_P]),
+    "fld_plan_workspace_bytes": (C.c_int32, [_P, C.POINTER(C.c_size_t)]),
+    "fld_plan_bind_workspace": (C.c_int32, [_P, _P, C.c_size_t]),
+    "fld_plan_levels": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int32)]),
+    "fld_plan_level_view": (C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(fld_level_view)]),
+    "fld_coefficients": (C.c_int32, [_P, _PP, _PP, C.POINTER(C.c_double), _P]),
+    "fld_step": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
+    "fld_exchange": (C.c_int32, [_P, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas), _P]),
+    "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
+    "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class FLDError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.fld_strerror(code).decode()
+        extra = _lib.fld_last_error().decode() if code == FLD_ERR_HIP else ""
+        super().__init__(f"{where}: {msg} ({code}){' ' + extra if extra else ''}")
+        self.code = code
+
+
+def _check(code: int, where: str, ok=(FLD_OK,)) -> int:
+    if code not in ok:
+        raise FLDError(code, where)
+    return code
+
+
+def _ptrs(tensors) -> C.Array:
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t if isinstance(t, int) else t.data_ptr()
+    return arr
+
+
+def _dts(dt, n) -> C.Array:
+    if not isinstance(dt, (list, tuple)):
+        dt = [float(dt)] * n
+    return (C.c_double * n)(*[float(x) for x in dt])
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---- C-named functions ----------------------------------------------------------------
+def fld_version() -> int:
+    return _lib.fld_version()
+
+
+def fld_strerror(code: int) -> str:
+    return _lib.fld_strerror(code).decode()
+
+
+def fld_opts_default(**kw) -> fld_opts:
+    o = fld_opts()
+    _lib.fld_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "bc":
+            for i, x in enumerate(v):
+                o.bc[i] = x
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def fld_gas_default(**kw) -> fld_gas:
+    g = fld_gas()
+    _lib.fld_gas_default(C.byref(g))
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def make_grid(n: Sequence[int], h: Optional[Sequence[float]] = None) -> fld_grid:
+    """fld_grid from cell counts in x, y[, z] order (h defaults to the unit square/cube)."""
+    g = fld_grid()
+    g.ndim = len(n)
+    for d in range(3):
+        g.n[d] = int(n[d]) if d < len(n) else 1
+        g.h[d] = float(h[d]) if h is not None and d < len(n) else (1.0 / max(1, n[d]) if d < len(n) else 1.0)
+    return g
+
+
+def fld_plan_create(grids: Sequence[fld_grid], opts: fld_opts) -> int:
+    arr = (fld_grid * len(grids))(*grids)
+    out = C.c_void_p()
+    _check(_lib.fld_plan_create(arr, len(grids), C.byref(opts), C.byref(out)), "fld_plan_create")
+    return out.value
+
+
+def fld_plan_destroy(plan: int) -> None:
+    _check(_lib.fld_plan_destroy(plan), "fld_plan_destroy")
+
+
+def fld_plan_workspace_bytes(plan: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.fld_plan_workspace_bytes(plan, C.byref(b)), "fld_plan_workspace_bytes")
+    return b.value
+
+
+def fld_plan_bind_workspace(plan: int, ptr: int, nbytes: int) -> None:
+    _check(_lib.fld_plan_bind_workspace(plan, ptr, nbytes), "fld_plan_bind_workspace")
+
+
+def fld_plan_levels(plan: int, g: int) -> int:
+    n = C.c_int32()
+    _check(_lib.fld_plan_levels(plan, g, C.byref(n)), "fld_plan_levels")
+    return n.value
+
+
+def fld_plan_level_view(plan: int, g: int, level: int) -> fld_level_view:
+    v = fld_level_view()
+    _check(_lib.fld_plan_level_view(plan, g, level, C.byref(v)), "fld_plan_level_view")
+    return v
+
+
+def fld_coefficients(plan: int, E_in, kappa_rho, dt, stream=None) -> None:
+    n = len(E_in)
+    _check(_lib.fld_coefficients(plan, _ptrs(E_in), _ptrs(kappa_rho), _dts(dt, n), _stream(stream)),
+           "fld_coefficients")
+
+
+def fld_step(plan: int, E_in, kappa_rho, E_out, dt, stream=None, check: bool = True):
+    """Returns (status, [stats dict per grid])."""
+    n = len(E_in)
+    stats = (fld_stats * n)()
+    rc = _lib.fld_step(plan, _ptrs(E_in), _ptrs(kappa_rho), _ptrs(E_out), _dts(dt, n),
+                       _stream(stream), stats)
+    if check:
+        _check(rc, "fld_step")
+    return rc, [s.as_dict() for s in stats]
+
+
+def fld_exchange(plan: int, E, eps, rho, kappa, dt, gas: fld_gas, stream=None) -> None:
+    n = len(E)
+    _check(_lib.fld_exchange(plan, _ptrs(E), _ptrs(eps), _ptrs(rho), _ptrs(kappa), _dts(dt, n),
+                             C.byref(gas), _stream(stream)), "fld_exchange")
+
+
+def fld_exchange_status(plan: int, stream=None):
+    b = C.c_int64()
+    rc = _lib.fld_exchange_status(plan, _stream(stream), C.byref(b))
+    return rc, b.value
+
+
+def fld_profile_kernel(plan: int, kernel: int, level: int = 0, reps: int = 100, stream=None):
+    """Returns (mean ms per launch, cells per launch)."""
+    ms = C.c_double()
+    cells = C.c_int64()
+    _check(_lib.fld_profile_kernel(plan, kernel, level, reps, _stream(stream), C.byref(ms), C.byref(cells)),
+           "fld_profile_kernel")
+    return ms.value, cells.value
+
+
+# ---- convenience wrapper -----------------------------------------------------------
+class Plan:
+    """A plan plus its torch-owned workspace.
+
+    ``shapes`` are array shapes ((ny, nx) or (nz, ny, nx)); ``h`` per grid in x, y[, z]
+    order (default: unit square / cube).
+    """
+
+    def __init__(self, shapes, h=None, device=None, **opts):
+        import torch
+        self.shapes = [tuple(int(s) for s in sh) for sh in shapes]
+        grids = []
+        for i, sh in enumerate(self.shapes):
+            n = tuple(reversed(sh))
+            grids.append(make_grid(n, None if h is None else h[i]))
+        self.opts = fld_opts_default(**opts)
+        self.device = torch.device(device if device is not None else "cuda")
+        with torch.cuda.device(self.device):
+            self.handle = fld_plan_create(grids, self.opts)
+            nbytes = fld_plan_workspace_bytes(self.handle)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            fld_plan_bind_workspace(self.handle, self.workspace.data_ptr(), nbytes)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                fld_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def ngrids(self) -> int:
+        return len(self.shapes)
+
+    def levels(self, g: int) -> int:
+        return fld_plan_levels(self.handle, g)
+
+    def level_tensors(self, g: int, level: int):
+        """Views of one level's workspace arrays as torch tensors (shape (nz, ny, nx) / (ny, nx))."""
+        import torch
+        v = fld_plan_level_view(self.handle, g, level)
+        shape = tuple(reversed([v.n[d] for d in range(v.ndim)]))
+        n = 1
+        for s in shape:
+            n *= s
+        base = self.workspace.data_ptr()
+
+        def view(ptr, dtype, size):
+            if not ptr:
+                return None
+            off = ptr - base
+            return self.workspace[off: off + n * size].view(dtype).view(shape)
+
+        out = {"x": view(v.x, torch.float64, 8), "b": view(v.b, torch.float64, 8),
+               "x32": view(v.x32, torch.float32, 4), "b32": view(v.b32, torch.float32, 4)}
+        out["w"] = [view(v.w[d], torch.float64, 8) for d in range(v.ndim)]
+        out["w32"] = [view(v.w32[d], torch.float32, 4) for d in range(v.ndim)]
+        return out
+
+    def coefficients(self, E_in, kappa_rho, dt, stream=None):
+        fld_coefficients(self.handle, E_in, kappa_rho, dt, stream)
+
+    def step(self, E_in, kappa_rho, E_out, dt, stream=None, check: bool = True):
+        return fld_step(self.handle, E_in, kappa_rho, E_out, dt, stream, check)
+
+    def exchange(self, E, eps, rho, kappa, dt, gas: Optional[fld_gas] = None, stream=None):
+        fld_exchange(self.handle, E, eps, rho, kappa, dt, gas or fld_gas_default(), stream)
+
+    def exchange_status(self, stream=None):
+        return fld_exchange_status(self.handle, stream)
+
+    def profile(self, kernel: int, level: int = 0, reps: int = 100, stream=None):
+        return fld_profile_kernel(self.handle, kernel, level, reps, stream)

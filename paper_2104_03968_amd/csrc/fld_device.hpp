@@ -1,0 +1,128 @@
+// Device-side data structures shared by the HIP kernels and the host runtime.
+//
+// Every multigrid phase is one launch over a work-list of (level, tile) items
+// drawn from any number of grids, so a single grid and a batch of uneven grids
+// run through the same kernels.  A level descriptor (LevelDesc) names the
+// arrays of one level of one grid inside the caller's workspace; a JobList
+// names which levels a launch covers and where each level's tiles start.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fld {
+
+// Cell-parallel kernels: one thread per cell, 64 x 4 (x 1) cell tiles.
+constexpr int kTX = 64;
+constexpr int kTY = 4;
+constexpr int kBlock = 256;
+// Red-black smoother: one thread per cell of one colour, 128 x 4 (x 1) cell tiles.
+constexpr int kSX = 128;
+// Coarsest-level solve: one workgroup per grid, up to kCoarseCPT cells per thread.
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseCPT = 4;
+constexpr int kCoarseMaxLDS = kCoarseThreads * kCoarseCPT;   // 4096 cells
+
+// Tile counts of one level for the two tilings (host and device agree on these).
+__host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
+    return ((n[0] + kTX - 1) / kTX) * ((n[1] + kTY - 1) / kTY) * n[2];
+}
+__host__ __device__ inline int32_t smooth_tiles(const int32_t n[3]) {
+    return ((n[0] + kSX - 1) / kSX) * ((n[1] + kTY - 1) / kTY) * n[2];
+}
+
+struct LevelDesc {
+    int32_t n[3];        // nx, ny, nz (nz = 1 in 2D)
+    int32_t ndim;
+    int32_t grid;        // owning grid
+    int32_t level;       // 0 = finest
+    int32_t coarse;      // index of the next coarser level, -1 at the coarsest
+    int32_t fine;        // index of the next finer level, -1 at level 0
+    double  hinv[3];     // 1/h per axis (level 0 values are the grid's)
+    double* x;           // FP64 solution (level 0) / correction (coarser)
+    double* b;           // FP64 right-hand side
+    double* w[3];        // FP64 lower-face weights dt*D_face/h^2
+    float*  x32;
+    float*  b32;
+    float*  w32[3];
+    double* part;        // per-tile partial sums (level 0 only)
+    double* scratch;     // coarse-solve vectors for levels too large for LDS
+};
+
+// Per-grid solver state, updated on the device between V-cycles.
+struct GridState {
+    double  bnorm2;      // ||b||^2
+    double  bsum;        // sum b
+    double  rnorm2;      // last ||b - A x||^2
+    double  rprev2;      // previous cycle's ||r||^2 (stagnation test)
+    double  tol2;        // rtol^2 ||b||^2
+    int32_t active;      // 1 while V-cycles are still needed
+    int32_t cycles;      // V-cycles done
+    int32_t status;      // FLD_* status
+    int32_t stall;       // consecutive cycles with little progress
+    int32_t bad;         // input-validation bits (atomicOr)
+    int32_t ntiles0;     // cell-tiles of level 0 (number of partial sums)
+};
+
+// Which levels a launch covers.  Level j of the list is LevelDesc levels[j];
+// its tiles occupy [prefix[j], prefix[j+1]) of the launch's tile range.
+struct JobList {
+    const int32_t* levels;
+    const int32_t* prefix;
+    int32_t njobs;
+    int32_t total;       // prefix[njobs]
+};
+
+// Per-call pointers of fld_step (one entry per grid).
+struct StepIO {
+    const double* E_in;
+    const double* kr;
+    double*       E_out;
+    double        dt;
+};
+
+// Per-call pointers of fld_exchange (one entry per grid).
+struct ExchangeIO {
+    double*       E;
+    double*       eps;
+    const double* rho;
+    const double* kappa;
+    double        dt;
+    int64_t       n;
+};
+
+struct Control {
+    int32_t nactive;     // grids still iterating after the last count
+    int32_t bad_exchange;
+    int64_t bisected;    // exchange cells that used the bisection fallback
+};
+
+// ---- launch wrappers (kernels.hip) ------------------------------------------
+// All launches are asynchronous on `s`.  `nblk` caps the persistent grid size.
+void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+                  const StepIO* io, double c, int limiter, int nblk, hipStream_t s);
+void launch_finalize_b(const LevelDesc* L, GridState* S, JobList jl, double rtol, hipStream_t s);
+void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s);
+void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                   int color, int nblk, hipStream_t s);
+void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                     int nblk, hipStream_t s);
+void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                    int nblk, hipStream_t s);
+void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                         hipStream_t s);
+void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
+                     int nblk, hipStream_t s);
+void launch_finalize_r(const LevelDesc* L, GridState* S, JobList jl, int max_cycles, int count_cycle,
+                       hipStream_t s);
+void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                    hipStream_t s);
+void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
+                   hipStream_t s);
+void launch_count(const GridState* S, int ngrids, Control* ctrl, hipStream_t s);
+void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s);
+void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,
+                     double c_v, int max_halley, double root_rtol, Control* ctrl, int nblk,
+                     hipStream_t s);
+
+}  // namespace fld

@@ -1,0 +1,859 @@
+// HIP kernels of the FLD radiation-energy step for gfx950 (wave64, no MFMA:
+// every kernel here is a stencil, a reduction or a pointwise update, bound by
+// memory bandwidth, not a dense contraction).
+//
+// Method (Moens et al., "Radiation-hydrodynamics with MPI-AMRVAC:
+// flux-limited diffusion"):
+//   coefficients  Sec. 3.2 (4th-order gradient), Sec. 2.2 (R, lambda, D),
+//                 Sec. 3.4 (harmonic face mean, eq. discdiff)
+//   solve         Sec. 3.4 (backward Euler with lagged D, multigrid with a
+//                 Gauss-Seidel smoother); the red-black ordering, the
+//                 transfer operators and the coarsest-level CG are this
+//                 library's own multigrid design
+//   exchange      Sec. 3.3 (point-implicit heating/cooling quartic, Halley's
+//                 method with a bisection fallback, back-substitution for E)
+//
+// Every kernel walks a JobList of (level, tile) items with a grid-stride
+// loop, so one launch serves one grid or a batch of uneven grids.  Per-grid
+// convergence flags (GridState::active) make kernels skip finished grids.
+// Reductions are deterministic: fixed per-tile partial sums, fixed-order
+// wave butterflies and fixed-order cross-wave sums; no floating-point atomics.
+#include "fld_device.hpp"
+#include "fld.h"
+
+#include <math.h>
+
+namespace fld {
+
+namespace {
+
+__device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int njobs, int t) {
+    int lo = 0, hi = njobs;            // prefix[lo] <= t < prefix[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int mirror(int i, int n) {
+    // even reflection across a zero-flux face: -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2
+    return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of two values; every thread receives the totals.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();                       // sh may still be read from a previous call
+    if (lane == 0) { sh[2 * wid] = a; sh[2 * wid + 1] = b; }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
+    a = sa;
+    b = sb;
+}
+
+template <int DIM>
+__device__ __forceinline__ void cell_of_tile(const int32_t n[3], int lt, int tid, int& i, int& j, int& k) {
+    const int tx_n = (n[0] + kTX - 1) / kTX;
+    const int ty_n = (n[1] + kTY - 1) / kTY;
+    const int tx = lt % tx_n;
+    const int rest = lt / tx_n;
+    const int ty = rest % ty_n;
+    k = (DIM == 3) ? rest / ty_n : 0;
+    i = tx * kTX + (tid & (kTX - 1));
+    j = ty * kTY + (tid / kTX);
+}
+
+// ---------------------------------------------------------------------------
+// K1: coefficients.  R = |grad E|/(kappa rho E) with the 4th-order central
+// gradient (mirrored ghosts), lambda(R), D = c lambda/(kappa rho), and the
+// lower-face weights dt * 2 D_L D_R/(D_L + D_R) / h^2.  The D of a lower
+// neighbour is recomputed from its own stencil (same arithmetic as that
+// neighbour's thread), so each face is written once with no second pass.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ double cell_D(const double* __restrict__ E, const double* __restrict__ kr,
+                                         int i, int j, int k, const int32_t n[3], const double c12[3],
+                                         double c, int limiter) {
+    const long sy = n[0], sz = (long)n[0] * n[1];
+    const long row = (long)j * sy + (long)k * sz;
+    const double e = E[i + row];
+    const double kk = kr[i + row];
+    const double gx = ((E[mirror(i - 2, n[0]) + row] - E[mirror(i + 2, n[0]) + row]) +
+                       8.0 * (E[mirror(i + 1, n[0]) + row] - E[mirror(i - 1, n[0]) + row])) * c12[0];
+    const long col = i + (long)k * sz;
+    const double gy = ((E[col + mirror(j - 2, n[1]) * sy] - E[col + mirror(j + 2, n[1]) * sy]) +
+                       8.0 * (E[col + mirror(j + 1, n[1]) * sy] - E[col + mirror(j - 1, n[1]) * sy])) * c12[1];
+    double g2 = gx * gx + gy * gy;
+    if (DIM == 3) {
+        const long pil = i + (long)j * sy;
+        const double gz = ((E[pil + mirror(k - 2, n[2]) * sz] - E[pil + mirror(k + 2, n[2]) * sz]) +
+                           8.0 * (E[pil + mirror(k + 1, n[2]) * sz] - E[pil + mirror(k - 1, n[2]) * sz])) * c12[2];
+        g2 += gz * gz;
+    }
+    const double R = sqrt(g2) / (kk * e);
+    double lam;
+    if (limiter == FLD_LIMITER_DIFFUSION) {
+        lam = 1.0 / 3.0;
+    } else if (R < 1e100) {
+        lam = (2.0 + R) / (6.0 + R * (3.0 + R));
+    } else {
+        lam = 1.0 / R;                      // free-streaming limit, avoids inf/inf
+    }
+    return c * lam / kk;
+}
+
+__device__ __forceinline__ double face_w(double DL, double DR, double dt, double hinv) {
+    return dt * (2.0 * DL * DR / (DL + DR)) * (hinv * hinv);
+}
+
+template <int DIM, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
+        const StepIO* __restrict__ io, double c, int limiter) {
+    __shared__ double sh[2 * kBlock / 64];
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        const int lt = t - jl.prefix[jb];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
+        const StepIO& p = io[d.grid];
+        const double dt = p.dt;
+        double s2 = 0.0, s1 = 0.0;
+        if (i < d.n[0] && j < d.n[1]) {
+            const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            const double e = p.E_in[idx];
+            const double kk = p.kr[idx];
+            const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
+            if (!ok) atomicOr(&S[d.grid].bad, 1);
+            const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter);
+            double wx = 0.0, wy = 0.0, wz = 0.0;
+            if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter), Dc, dt, d.hinv[0]);
+            if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter), Dc, dt, d.hinv[1]);
+            if (DIM == 3 && k > 0)
+                wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter), Dc, dt, d.hinv[2]);
+            d.w[0][idx] = wx;
+            d.w[1][idx] = wy;
+            if (DIM == 3) d.w[2][idx] = wz;
+            if (MIXED) {
+                d.w32[0][idx] = (float)wx;
+                d.w32[1][idx] = (float)wy;
+                if (DIM == 3) d.w32[2][idx] = (float)wz;
+            }
+            d.b[idx] = e;
+            d.x[idx] = e;
+            s2 = e * e;
+            s1 = e;
+        }
+        block_sum2<kBlock>(s2, s1, sh);
+        if (threadIdx.x == 0) {
+            d.part[2 * lt] = s2;
+            d.part[2 * lt + 1] = s1;
+        }
+    }
+}
+
+// Sum the level-0 per-tile partials of one grid in a fixed order.
+__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int ntiles, int stride,
+                                          double& a, double& b, double* sh) {
+    a = 0.0;
+    b = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
+        a += part[stride * i];
+        if (stride == 2) b += part[stride * i + 1];
+    }
+    block_sum2<kBlock>(a, b, sh);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_finalize_b(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol) {
+    __shared__ double sh[2 * kBlock / 64];
+    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    GridState& g = S[d.grid];
+    double s2, s1;
+    sum_parts(d.part, g.ntiles0, 2, s2, s1, sh);
+    if (threadIdx.x == 0) {
+        g.bnorm2 = s2;
+        g.bsum = s1;
+        g.tol2 = rtol * rtol * s2;
+        g.cycles = 0;
+        g.stall = 0;
+        g.rnorm2 = s2;
+        g.rprev2 = INFINITY;
+        if (g.bad) {
+            g.status = FLD_ERR_BAD_INPUT;
+            g.active = 0;
+        } else {
+            g.status = FLD_OK;
+            g.active = 1;
+        }
+        g.bad = 0;                       // read once per step; cleared for the next one
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level face weights: average the fine weights of the sub-faces that
+// make up a coarse face, and scale by 1/4 for the doubled cell width.
+// ---------------------------------------------------------------------------
+template <int DIM, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& cL = L[f.coarse];
+        int I, J, K;
+        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        if (I >= cL.n[0] || J >= cL.n[1]) continue;
+        const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
+        const long fsy = f.n[0], fsz = (long)f.n[0] * f.n[1];
+        const long f0 = 2 * I + 2 * J * fsy + (DIM == 3 ? 2 * K * fsz : 0);
+        const double sc = (DIM == 3) ? 0.0625 : 0.125;    // 1/2^(DIM-1) * 1/4
+        double wc[3] = {0.0, 0.0, 0.0};
+        // x faces: sub-faces at fine x = 2I over (j, j+1) [and (k, k+1)]
+        if (I > 0) {
+            double s = f.w[0][f0] + f.w[0][f0 + fsy];
+            if (DIM == 3) s += f.w[0][f0 + fsz] + f.w[0][f0 + fsy + fsz];
+            wc[0] = s * sc;
+        }
+        if (J > 0) {
+            double s = f.w[1][f0] + f.w[1][f0 + 1];
+            if (DIM == 3) s += f.w[1][f0 + fsz] + f.w[1][f0 + 1 + fsz];
+            wc[1] = s * sc;
+        }
+        if (DIM == 3 && K > 0) {
+            wc[2] = (f.w[2][f0] + f.w[2][f0 + 1] + f.w[2][f0 + fsy] + f.w[2][f0 + 1 + fsy]) * sc;
+        }
+        for (int a = 0; a < DIM; ++a) {
+            cL.w[a][cidx] = wc[a];
+            if (MIXED) cL.w32[a][cidx] = (float)wc[a];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stencil helpers over one level, in precision T.  The operator is
+// (A x)_i = x_i + sum_faces w_f (x_i - x_nb); the residual is formed as
+// b - x - sum w (x - x_nb), so nearly equal neighbours cancel before scaling.
+// ---------------------------------------------------------------------------
+template <typename T> struct Arr;
+template <> struct Arr<double> {
+    __device__ static double* x(const LevelDesc& d) { return d.x; }
+    __device__ static double* b(const LevelDesc& d) { return d.b; }
+    __device__ static double* w(const LevelDesc& d, int a) { return d.w[a]; }
+};
+template <> struct Arr<float> {
+    __device__ static float* x(const LevelDesc& d) { return d.x32; }
+    __device__ static float* b(const LevelDesc& d) { return d.b32; }
+    __device__ static float* w(const LevelDesc& d, int a) { return d.w32[a]; }
+};
+
+template <int DIM, typename T>
+__device__ __forceinline__ T residual_at(const T* __restrict__ x, const T* __restrict__ b,
+                                         const T* __restrict__ w0, const T* __restrict__ w1,
+                                         const T* __restrict__ w2, const int32_t n[3],
+                                         int i, int j, int k) {
+    const long sy = n[0], sz = (long)n[0] * n[1];
+    const long idx = i + j * sy + k * sz;
+    const T xc = x[idx];
+    T r = b[idx] - xc;
+    if (i > 0) r -= w0[idx] * (xc - x[idx - 1]);
+    if (i + 1 < n[0]) r -= w0[idx + 1] * (xc - x[idx + 1]);
+    if (j > 0) r -= w1[idx] * (xc - x[idx - sy]);
+    if (j + 1 < n[1]) r -= w1[idx + sy] * (xc - x[idx + sy]);
+    if (DIM == 3) {
+        if (k > 0) r -= w2[idx] * (xc - x[idx - sz]);
+        if (k + 1 < n[2]) r -= w2[idx + sz] * (xc - x[idx + sz]);
+    }
+    return r;
+}
+
+// Red-black Gauss-Seidel half sweep: update the cells with (i+j+k) % 2 == color
+// to x_i = (b_i + sum w_f x_nb) / (1 + sum w_f).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int color) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        const int lt = t - jl.prefix[jb];
+        const int tx_n = (d.n[0] + kSX - 1) / kSX;
+        const int ty_n = (d.n[1] + kTY - 1) / kTY;
+        const int tx = lt % tx_n;
+        const int rest = lt / tx_n;
+        const int j = (rest % ty_n) * kTY + (threadIdx.x >> 6);
+        const int k = (DIM == 3) ? rest / ty_n : 0;
+        const int i = tx * kSX + 2 * (threadIdx.x & 63) + ((j + k + color) & 1);
+        if (i >= d.n[0] || j >= d.n[1]) continue;
+        T* __restrict__ x = Arr<T>::x(d);
+        const T* __restrict__ b = Arr<T>::b(d);
+        const T* __restrict__ w0 = Arr<T>::w(d, 0);
+        const T* __restrict__ w1 = Arr<T>::w(d, 1);
+        const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+        const long idx = i + j * sy + k * sz;
+        T s = b[idx], dg = T(1);
+        if (i > 0) { const T w = w0[idx]; s += w * x[idx - 1]; dg += w; }
+        if (i + 1 < d.n[0]) { const T w = w0[idx + 1]; s += w * x[idx + 1]; dg += w; }
+        if (j > 0) { const T w = w1[idx]; s += w * x[idx - sy]; dg += w; }
+        if (j + 1 < d.n[1]) { const T w = w1[idx + sy]; s += w * x[idx + sy]; dg += w; }
+        if (DIM == 3) {
+            const T* __restrict__ w2 = Arr<T>::w(d, 2);
+            if (k > 0) { const T w = w2[idx]; s += w * x[idx - sz]; dg += w; }
+            if (k + 1 < d.n[2]) { const T w = w2[idx + sz]; s += w * x[idx + sz]; dg += w; }
+        }
+        x[idx] = s / dg;
+    }
+}
+
+// Residual of the 2^DIM children, averaged into the coarse right-hand side;
+// the coarse correction starts from zero.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& f = L[jl.levels[jb]];
+        if (!S[f.grid].active) continue;
+        const LevelDesc& cL = L[f.coarse];
+        int I, J, K;
+        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        if (I >= cL.n[0] || J >= cL.n[1]) continue;
+        const T* x = Arr<T>::x(f);
+        const T* b = Arr<T>::b(f);
+        const T* w0 = Arr<T>::w(f, 0);
+        const T* w1 = Arr<T>::w(f, 1);
+        const T* w2 = (DIM == 3) ? Arr<T>::w(f, 2) : nullptr;
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c) {
+            s += residual_at<DIM, T>(x, b, w0, w1, w2, f.n, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1),
+                                     DIM == 3 ? 2 * K + (c >> 2) : 0);
+        }
+        const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
+        Arr<T>::b(cL)[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
+        Arr<T>::x(cL)[cidx] = T(0);
+    }
+}
+
+// Piecewise-constant prolongation of the coarse correction, added to the fine level.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& f = L[jl.levels[jb]];
+        if (!S[f.grid].active) continue;
+        const LevelDesc& cL = L[f.coarse];
+        int i, j, k;
+        cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        if (i >= f.n[0] || j >= f.n[1]) continue;
+        const long idx = i + (long)f.n[0] * (j + (long)f.n[1] * k);
+        const long cidx = (i >> 1) + (long)cL.n[0] * ((j >> 1) + (long)cL.n[1] * (k >> 1));
+        Arr<T>::x(f)[idx] += Arr<T>::x(cL)[cidx];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: Jacobi-preconditioned conjugate gradients in one workgroup
+// per grid, from a zero start, to a 1e-6 relative residual (or n iterations).
+// Up to kCoarseMaxLDS cells the search direction lives in LDS and every other
+// vector in registers; larger coarsest levels use workspace scratch vectors.
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+__device__ __forceinline__ void cell_coords(const int32_t n[3], int c, int& i, int& j, int& k) {
+    i = c % n[0];
+    const int r = c / n[0];
+    j = r % n[1];
+    k = (DIM == 3) ? r / n[1] : 0;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restrict__ w0,
+                                      const T* __restrict__ w1, const T* __restrict__ w2,
+                                      const int32_t n[3], int c, T& dg) {
+    int i, j, k;
+    cell_coords<DIM, T>(n, c, i, j, k);
+    const int sy = n[0], sz = n[0] * n[1];
+    const T pc = p[c];
+    T q = pc;
+    dg = T(1);
+    if (i > 0) { const T w = w0[c]; q += w * (pc - p[c - 1]); dg += w; }
+    if (i + 1 < n[0]) { const T w = w0[c + 1]; q += w * (pc - p[c + 1]); dg += w; }
+    if (j > 0) { const T w = w1[c]; q += w * (pc - p[c - sy]); dg += w; }
+    if (j + 1 < n[1]) { const T w = w1[c + sy]; q += w * (pc - p[c + sy]); dg += w; }
+    if (DIM == 3) {
+        if (k > 0) { const T w = w2[c]; q += w * (pc - p[c - sz]); dg += w; }
+        if (k + 1 < n[2]) { const T w = w2[c + sz]; q += w * (pc - p[c + sz]); dg += w; }
+    }
+    return q;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restrict__ w1,
+                                     const T* __restrict__ w2, const int32_t n[3], int c) {
+    int i, j, k;
+    cell_coords<DIM, T>(n, c, i, j, k);
+    const int sy = n[0], sz = n[0] * n[1];
+    T dg = T(1);
+    if (i > 0) dg += w0[c];
+    if (i + 1 < n[0]) dg += w0[c + 1];
+    if (j > 0) dg += w1[c];
+    if (j + 1 < n[1]) dg += w1[c + sy];
+    if (DIM == 3) {
+        if (k > 0) dg += w2[c];
+        if (k + 1 < n[2]) dg += w2[c + sz];
+    }
+    return dg;
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kCoarseThreads)
+k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    __shared__ T p_sh[kCoarseMaxLDS];
+    __shared__ double red[2 * kCoarseThreads / 64];
+    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    if (!S[d.grid].active) return;
+    const int ncell = d.n[0] * d.n[1] * d.n[2];
+    const T* w0 = Arr<T>::w(d, 0);
+    const T* w1 = Arr<T>::w(d, 1);
+    const T* w2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
+    T* xg = Arr<T>::x(d);
+    const T* bg = Arr<T>::b(d);
+    const int maxit = ncell < 2000 ? ncell + 4 : 2000;
+    const double tol2 = 1e-12;                 // (1e-6)^2 relative
+    if (ncell <= kCoarseMaxLDS) {
+        T x[kCoarseCPT], r[kCoarseCPT], dinv[kCoarseCPT];
+        double rz = 0.0, rr0 = 0.0;
+#pragma unroll
+        for (int m = 0; m < kCoarseCPT; ++m) {
+            const int c = threadIdx.x + m * kCoarseThreads;
+            x[m] = T(0);
+            r[m] = T(0);
+            dinv[m] = T(0);
+            if (c < ncell) {
+                r[m] = bg[c];
+                dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, d.n, c);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kCoarseCPT; ++m) {
+            const int c = threadIdx.x + m * kCoarseThreads;
+            if (c < ncell) {
+                const T z = r[m] * dinv[m];
+                p_sh[c] = z;
+                rz += (double)r[m] * (double)z;
+                rr0 += (double)r[m] * (double)r[m];
+            }
+        }
+        block_sum2<kCoarseThreads>(rz, rr0, red);     // also orders the p_sh writes
+        if (rr0 > 0.0) {
+            for (int it = 0; it < maxit; ++it) {
+                T q[kCoarseCPT];
+                double pq = 0.0, unused = 0.0;
+#pragma unroll
+                for (int m = 0; m < kCoarseCPT; ++m) {
+                    const int c = threadIdx.x + m * kCoarseThreads;
+                    q[m] = T(0);
+                    if (c < ncell) {
+                        T dg;
+                        q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, d.n, c, dg);
+                        pq += (double)p_sh[c] * (double)q[m];
+                    }
+                }
+                block_sum2<kCoarseThreads>(pq, unused, red);
+                const T alpha = (T)(rz / pq);
+                double rz_new = 0.0, rr = 0.0;
+#pragma unroll
+                for (int m = 0; m < kCoarseCPT; ++m) {
+                    const int c = threadIdx.x + m * kCoarseThreads;
+                    if (c < ncell) {
+                        x[m] += alpha * p_sh[c];
+                        r[m] -= alpha * q[m];
+                        const T z = r[m] * dinv[m];
+                        rz_new += (double)r[m] * (double)z;
+                        rr += (double)r[m] * (double)r[m];
+                    }
+                }
+                block_sum2<kCoarseThreads>(rz_new, rr, red);   // every thread is done reading p_sh
+                if (rr <= tol2 * rr0) break;
+                const T beta = (T)(rz_new / rz);
+                rz = rz_new;
+#pragma unroll
+                for (int m = 0; m < kCoarseCPT; ++m) {
+                    const int c = threadIdx.x + m * kCoarseThreads;
+                    if (c < ncell) p_sh[c] = r[m] * dinv[m] + beta * p_sh[c];
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kCoarseCPT; ++m) {
+            const int c = threadIdx.x + m * kCoarseThreads;
+            if (c < ncell) xg[c] = x[m];
+        }
+        return;
+    }
+    // Large coarsest level: vectors in workspace scratch (x lives in the level itself).
+    T* r = reinterpret_cast<T*>(d.scratch);
+    T* p = r + ncell;
+    T* q = p + ncell;
+    T* dv = q + ncell;
+    double rz = 0.0, rr0 = 0.0;
+    for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
+        const T dg = diag_at<DIM, T>(w0, w1, w2, d.n, c);
+        const T rc = bg[c];
+        const T z = rc / dg;
+        xg[c] = T(0);
+        r[c] = rc;
+        dv[c] = T(1) / dg;
+        p[c] = z;
+        rz += (double)rc * (double)z;
+        rr0 += (double)rc * (double)rc;
+    }
+    block_sum2<kCoarseThreads>(rz, rr0, red);
+    if (rr0 <= 0.0) return;
+    for (int it = 0; it < maxit; ++it) {
+        double pq = 0.0, unused = 0.0;
+        for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
+            T dg;
+            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg);
+            q[c] = qc;
+            pq += (double)p[c] * (double)qc;
+        }
+        block_sum2<kCoarseThreads>(pq, unused, red);
+        const T alpha = (T)(rz / pq);
+        double rz_new = 0.0, rr = 0.0;
+        for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
+            xg[c] += alpha * p[c];
+            const T rc = r[c] - alpha * q[c];
+            r[c] = rc;
+            rz_new += (double)rc * (double)(rc * dv[c]);
+            rr += (double)rc * (double)rc;
+        }
+        block_sum2<kCoarseThreads>(rz_new, rr, red);
+        if (rr <= tol2 * rr0) break;
+        const T beta = (T)(rz_new / rz);
+        rz = rz_new;
+        for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) p[c] = r[c] * dv[c] + beta * p[c];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 FP64 residual r = b - A x and its per-tile partial ||r||^2.  In mixed
+// precision the residual also becomes the FP32 right-hand side of the next
+// correction V-cycle, whose correction starts from zero.
+// ---------------------------------------------------------------------------
+template <int DIM, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    __shared__ double sh[2 * kBlock / 64];
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;          // uniform per tile: no barrier divergence
+        const int lt = t - jl.prefix[jb];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
+        double r2 = 0.0, unused = 0.0;
+        if (i < d.n[0] && j < d.n[1]) {
+            const double r = residual_at<DIM, double>(d.x, d.b, d.w[0], d.w[1], d.w[2], d.n, i, j, k);
+            r2 = r * r;
+            if (MIXED) {
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                d.b32[idx] = (float)r;
+                d.x32[idx] = 0.0f;
+            }
+        }
+        block_sum2<kBlock>(r2, unused, sh);
+        if (threadIdx.x == 0) d.part[lt] = r2;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_finalize_r(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int max_cycles,
+             int count_cycle) {
+    __shared__ double sh[2 * kBlock / 64];
+    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    GridState& g = S[d.grid];
+    if (!g.active) return;
+    double s2, unused;
+    sum_parts(d.part, g.ntiles0, 1, s2, unused, sh);
+    if (threadIdx.x == 0) {
+        g.rnorm2 = s2;
+        if (count_cycle) g.cycles += 1;
+        if (!(s2 == s2) || isinf(s2)) {
+            g.active = 0;
+            g.status = FLD_ERR_NOT_CONVERGED;
+        } else if (s2 <= g.tol2) {
+            g.active = 0;
+            g.status = FLD_OK;
+        } else if (g.cycles >= max_cycles) {
+            g.active = 0;
+            g.status = FLD_ERR_NOT_CONVERGED;
+        } else {
+            // stagnation: the residual norm shrinks by less than 10 % for 3 cycles in a row
+            g.stall = (s2 > 0.81 * g.rprev2) ? g.stall + 1 : 0;
+            if (g.stall >= 3) {
+                g.active = 0;
+                g.status = FLD_ERR_NOT_CONVERGED;
+            }
+        }
+        g.rprev2 = s2;
+    }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        if (i >= d.n[0] || j >= d.n[1]) continue;
+        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+        d.x[idx] += (double)d.x32[idx];
+    }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__ io) {
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        if (i >= d.n[0] || j >= d.n[1]) continue;
+        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+        io[d.grid].E_out[idx] = d.x[idx];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_count(const GridState* __restrict__ S, int ngrids, Control* ctrl) {
+    __shared__ double sh[2 * kBlock / 64];
+    double a = 0.0, b = 0.0;
+    for (int g = threadIdx.x; g < ngrids; g += kBlock) a += S[g].active;
+    block_sum2<kBlock>(a, b, sh);
+    if (threadIdx.x == 0) ctrl->nactive = (int32_t)a;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_set_active(GridState* __restrict__ S, int ngrids, int value) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngrids; g += gridDim.x * blockDim.x)
+        S[g].active = value;
+}
+
+// ---------------------------------------------------------------------------
+// Exchange.  With x = C y / (1+a2), C = (1+a2) eps + a2 E, the quartic
+// a1 x^4 + (1+a2) x - C = 0 becomes g(y) = beta y^4 + y - 1 = 0 with
+// beta = a1 C^3 / (1+a2)^4 >= 0: g is increasing and convex on y > 0,
+// g(0) = -1 < 0 <= g(1), so the root is unique in (0, 1].  Halley's method
+// starts from the upper bound min(1, beta^(-1/4)) inside a bracket that every
+// iterate tightens; an iterate that leaves the bracket, or running out of
+// Halley iterations, hands over to bisection of the bracket.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double quartic_root(double beta, int max_halley, double rtol, bool& bisected) {
+    bisected = false;
+    if (!(beta > 0.0)) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    double y = fmin(1.0, 1.0 / sqrt(sqrt(beta)));
+    for (int it = 0; it < max_halley; ++it) {
+        const double y2 = y * y;
+        const double g = beta * y2 * y2 + y - 1.0;
+        if (g > 0.0) hi = y; else if (g < 0.0) lo = y; else return y;
+        const double g1 = 4.0 * beta * y2 * y + 1.0;
+        const double g2 = 12.0 * beta * y2;
+        const double den = 2.0 * g1 * g1 - g * g2;
+        const double step = 2.0 * g * g1 / den;
+        const double yn = y - step;
+        if (!(den > 0.0) || !(yn > lo) || !(yn < hi)) {
+            // outside the bracket: bisect this once and go on with Halley
+            y = 0.5 * (lo + hi);
+            continue;
+        }
+        if (fabs(step) <= rtol * yn) return yn;
+        y = yn;
+    }
+    bisected = true;
+    for (int it = 0; it < 1100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        const double m2 = mid * mid;
+        if (beta * m2 * m2 + mid - 1.0 > 0.0) hi = mid; else lo = mid;
+    }
+    const double glo = fabs(beta * lo * lo * lo * lo + lo - 1.0);
+    const double ghi = fabs(beta * hi * hi * hi * hi + hi - 1.0);
+    return glo <= ghi ? lo : hi;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_exchange(const ExchangeIO* __restrict__ io, double c, double a_rad, double c_v, int max_halley,
+           double root_rtol, Control* ctrl) {
+    const ExchangeIO p = io[blockIdx.y];
+    int bad = 0;
+    long nbis = 0;
+    const double cv2 = c_v * c_v;
+    const double cv4 = cv2 * cv2;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.n;
+         idx += (long)gridDim.x * blockDim.x) {
+        const double E = p.E[idx], eps = p.eps[idx], rho = p.rho[idx], kap = p.kappa[idx];
+        const bool ok = isfinite(E) && isfinite(eps) && isfinite(rho) && isfinite(kap) && rho > 0.0 &&
+                        kap >= 0.0 && E >= 0.0 && eps >= 0.0;
+        if (!ok) { bad = 1; continue; }
+        const double a2 = c * kap * rho * p.dt;
+        const double a1 = c * a_rad * kap * p.dt / (rho * rho * rho * cv4);
+        const double opa = 1.0 + a2;
+        const double C = opa * eps + a2 * E;
+        if (!(C > 0.0)) continue;                       // no energy in gas or radiation
+        const double s = C / opa;
+        const double beta = a1 * s * s * s / opa;       // a1 C^3 / (1+a2)^4
+        bool bis;
+        const double y = quartic_root(beta, max_halley, root_rtol, bis);
+        nbis += bis;
+        const double eps_new = s * y;
+        const double e2 = eps_new * eps_new;
+        p.eps[idx] = eps_new;
+        p.E[idx] = (a1 * e2 * e2 + E) / opa;
+    }
+    if (bad) atomicOr(&ctrl->bad_exchange, 1);
+    if (nbis) atomicAdd((unsigned long long*)&ctrl->bisected, (unsigned long long)nbis);
+}
+
+inline int blocks_for(int total, int nblk) { return total < nblk ? (total > 0 ? total : 1) : nblk; }
+
+}  // namespace
+
+// ---- launch wrappers ---------------------------------------------------------
+#define FLD_DISPATCH_DIM(dim, ...) \
+    do { if ((dim) == 3) { constexpr int D = 3; __VA_ARGS__; } else { constexpr int D = 2; __VA_ARGS__; } } while (0)
+
+void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+                  const StepIO* io, double c, int limiter, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter);
+        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter);
+    });
+}
+
+void launch_finalize_b(const LevelDesc* L, GridState* S, JobList jl, double rtol, hipStream_t s) {
+    if (jl.njobs <= 0) return;
+    hipLaunchKernelGGL(k_finalize_b, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, rtol);
+}
+
+void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (mixed) hipLaunchKernelGGL((k_coarsen<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl);
+        else hipLaunchKernelGGL((k_coarsen<D, false>), dim3(g), dim3(kBlock), 0, s, L, jl);
+    });
+}
+
+void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                   int color, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_smooth<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl, color);
+        else hipLaunchKernelGGL((k_smooth<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl, color);
+    });
+}
+
+void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                     int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_restrict<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_restrict<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                    int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                         hipStream_t s) {
+    if (jl.njobs <= 0) return;
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_coarse_solve<D, float>), dim3(jl.njobs), dim3(kCoarseThreads), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_coarse_solve<D, double>), dim3(jl.njobs), dim3(kCoarseThreads), 0, s, L, S, jl);
+    });
+}
+
+void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
+                     int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+void launch_finalize_r(const LevelDesc* L, GridState* S, JobList jl, int max_cycles, int count_cycle,
+                       hipStream_t s) {
+    if (jl.njobs <= 0) return;
+    hipLaunchKernelGGL(k_finalize_r, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, max_cycles, count_cycle);
+}
+
+void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                    hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_correct<D>), dim3(g), dim3(kBlock), 0, s, L, S, jl); });
+}
+
+void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
+                   hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_output<D>), dim3(g), dim3(kBlock), 0, s, L, jl, io); });
+}
+
+void launch_count(const GridState* S, int ngrids, Control* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, s, S, ngrids, ctrl);
+}
+
+void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_active, dim3((ngrids + kBlock - 1) / kBlock), dim3(kBlock), 0, s, S, ngrids, value);
+}
+
+void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,
+                     double c_v, int max_halley, double root_rtol, Control* ctrl, int nblk,
+                     hipStream_t s) {
+    if (ngrids <= 0 || max_n <= 0) return;
+    int64_t bx = (max_n + kBlock - 1) / kBlock;
+    if (bx > nblk) bx = nblk;
+    hipLaunchKernelGGL(k_exchange, dim3((unsigned)bx, (unsigned)ngrids), dim3(kBlock), 0, s, io, c,
+                       a_rad, c_v, max_halley, root_rtol, ctrl);
+}
+
+}  // namespace fld

@@ -1,0 +1,822 @@
+// Host runtime of the FLD step: plans (multigrid hierarchies of one or many
+// grids), the workspace layout inside caller-owned device memory, the launch
+// work-lists, the V-cycle / defect-correction drivers with optional hipGraph
+// replay, and the C ABI declared in include/fld.h.
+//
+// Nothing here allocates device memory: every device buffer lives in the
+// workspace the caller binds (a torch tensor in the Python binding).  Host
+// allocations are plain C++ containers plus a few pinned staging buffers.
+#include "fld_device.hpp"
+#include "fld.h"
+
+#include <algorithm>
+#include <cstddef>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace fld {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* where, hipError_t e) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s", where, hipGetErrorString(e));
+    g_last_error = buf;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Device-side work-list storage: levels[] and prefix[] of one JobList.
+struct HostList {
+    std::vector<int32_t> levels;
+    std::vector<int32_t> prefix;   // size levels.size() + 1
+    size_t off_levels = 0, off_prefix = 0;
+    JobList dev{};                 // filled at bind
+
+    bool empty() const { return levels.empty(); }
+};
+
+}  // namespace
+
+// One dimension's worth of work-lists (2D and 3D grids run in separate launches).
+struct DimLists {
+    int dim = 0;
+    HostList l0_cell;                          // level 0, cell tiles
+    std::vector<HostList> smooth;              // per depth, smoother tiles
+    std::vector<HostList> restrict_;           // per depth, cell tiles of the coarse level
+    std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
+    HostList coarsest;                         // one block per grid
+    int maxdepth = 0;
+};
+
+struct Plan {
+    int device = 0;
+    fld_opts opts{};
+    std::vector<fld_grid> grids;
+    std::vector<LevelDesc> levels;             // host copy (device pointers after bind)
+    std::vector<int32_t> level0;               // LevelDesc index of each grid's level 0
+    std::vector<int32_t> nlev;                 // levels per grid
+    std::vector<int64_t> ncell;                // cells per grid
+    DimLists dl[2];                            // [0] = 2D, [1] = 3D
+    bool mixed = false;
+
+    // workspace layout (byte offsets)
+    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_ctrl = 0;
+    size_t ws_bytes = 0;
+    static constexpr int kExSlots = 4;
+    struct FieldOff {
+        size_t x = 0, b = 0, w[3] = {0, 0, 0}, x32 = 0, b32 = 0, w32[3] = {0, 0, 0}, part = 0, scratch = 0;
+        bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
+    };
+    std::vector<FieldOff> foff;                // per level
+
+    // bound state
+    char* ws = nullptr;
+    LevelDesc* dL = nullptr;
+    GridState* dS = nullptr;
+    StepIO* dIO = nullptr;
+    ExchangeIO* dEx = nullptr;
+    Control* dCtrl = nullptr;
+    StepIO* hIO = nullptr;                     // pinned staging
+    ExchangeIO* hEx = nullptr;                 // pinned staging, kExSlots * ngrids
+    Control* hCtrl = nullptr;                  // pinned
+    GridState* hS = nullptr;                   // pinned
+    hipEvent_t ex_done[kExSlots] = {};
+    int ex_slot = 0;
+    int ex_last = -1;                          // slot of the last fld_exchange (profiling)
+    int64_t max_n = 0;
+    int nblk = 2048;
+    int last_cycles = 0;                       // cycles of the previous step (replay sizing)
+
+    fld_gas last_gas{};                        // constants of the last fld_exchange (profiling)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    ~Plan();
+    int ngrids() const { return (int)grids.size(); }
+};
+
+Plan::~Plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& e : ex_done)
+        if (e) (void)hipEventDestroy(e);
+    if (hIO) (void)hipHostFree(hIO);
+    if (hEx) (void)hipHostFree(hEx);
+    if (hCtrl) (void)hipHostFree(hCtrl);
+    if (hS) (void)hipHostFree(hS);
+}
+
+#define FLD_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) {                         \
+            ::fld::set_error(#call, e_);                \
+            return FLD_ERR_HIP;                         \
+        }                                               \
+    } while (0)
+
+namespace {
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int validate_opts(const fld_opts& o) {
+    if (!(o.c > 0.0) || !std::isfinite(o.c)) return FLD_ERR_INVALID_ARG;
+    if (o.limiter != FLD_LIMITER_LP && o.limiter != FLD_LIMITER_DIFFUSION) return FLD_ERR_INVALID_ARG;
+    for (int f = 0; f < 6; ++f)
+        if (o.bc[f] != FLD_BC_ZERO_FLUX) return FLD_ERR_UNSUPPORTED;
+    if (o.precision != FLD_PREC_FP64 && o.precision != FLD_PREC_MIXED) return FLD_ERR_INVALID_ARG;
+    if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return FLD_ERR_INVALID_ARG;
+    if (o.max_cycles < 1 || o.max_cycles > 100000) return FLD_ERR_INVALID_ARG;
+    if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 16 || o.nu2 > 16) return FLD_ERR_INVALID_ARG;
+    return FLD_OK;
+}
+
+int validate_grid(const fld_grid& g) {
+    if (g.ndim != 2 && g.ndim != 3) return FLD_ERR_INVALID_ARG;
+    int64_t n = 1;
+    for (int d = 0; d < g.ndim; ++d) {
+        if (g.n[d] < 2 || g.n[d] > (1 << 20)) return FLD_ERR_INVALID_ARG;
+        if (!(g.h[d] > 0.0) || !std::isfinite(g.h[d])) return FLD_ERR_INVALID_ARG;
+        n *= g.n[d];
+    }
+    if (n > (int64_t(1) << 31) - 1) return FLD_ERR_INVALID_ARG;   // 32-bit tile/cell indices
+    return FLD_OK;
+}
+
+void finish_list(HostList& l, const std::vector<LevelDesc>& L, int (*tiles)(const LevelDesc&)) {
+    l.prefix.assign(1, 0);
+    for (int32_t li : l.levels) l.prefix.push_back(l.prefix.back() + tiles(L[li]));
+}
+
+int tiles_cell(const LevelDesc& d) { return cell_tiles(d.n); }
+int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
+int tiles_one(const LevelDesc&) { return 1; }
+
+}  // namespace
+
+// Coarsening rule: halve every axis while all are even and >= 4.
+static void build_levels(Plan& p) {
+    p.levels.clear();
+    p.level0.clear();
+    p.nlev.clear();
+    p.ncell.clear();
+    for (int g = 0; g < p.ngrids(); ++g) {
+        const fld_grid& gr = p.grids[g];
+        int32_t n[3] = {gr.n[0], gr.n[1], gr.ndim == 3 ? gr.n[2] : 1};
+        double hinv[3] = {1.0 / gr.h[0], 1.0 / gr.h[1], gr.ndim == 3 ? 1.0 / gr.h[2] : 0.0};
+        p.level0.push_back((int32_t)p.levels.size());
+        p.ncell.push_back((int64_t)n[0] * n[1] * n[2]);
+        int lev = 0;
+        while (true) {
+            LevelDesc d{};
+            for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = hinv[a]; }
+            d.ndim = gr.ndim;
+            d.grid = g;
+            d.level = lev;
+            d.coarse = -1;
+            d.fine = lev == 0 ? -1 : (int32_t)p.levels.size() - 1;
+            if (lev > 0) p.levels.back().coarse = (int32_t)p.levels.size();
+            p.levels.push_back(d);
+            bool can = true;
+            for (int a = 0; a < gr.ndim; ++a) can = can && (n[a] % 2 == 0) && (n[a] >= 4);
+            if (!can) break;
+            for (int a = 0; a < gr.ndim; ++a) { n[a] /= 2; hinv[a] *= 0.5; }
+            ++lev;
+        }
+        p.nlev.push_back(lev + 1);
+    }
+}
+
+static void build_lists(Plan& p) {
+    for (int di = 0; di < 2; ++di) {
+        DimLists& D = p.dl[di];
+        D = DimLists{};
+        D.dim = di + 2;
+        int maxdepth = 0;
+        for (int g = 0; g < p.ngrids(); ++g)
+            if (p.grids[g].ndim == D.dim) maxdepth = std::max(maxdepth, p.nlev[g] - 1);
+        D.maxdepth = maxdepth;
+        D.smooth.resize(maxdepth);
+        D.restrict_.resize(maxdepth);
+        D.prolong.resize(maxdepth);
+        for (int g = 0; g < p.ngrids(); ++g) {
+            if (p.grids[g].ndim != D.dim) continue;
+            const int l0 = p.level0[g];
+            D.l0_cell.levels.push_back(l0);
+            for (int dpt = 0; dpt < p.nlev[g] - 1; ++dpt) {
+                D.smooth[dpt].levels.push_back(l0 + dpt);
+                D.restrict_[dpt].levels.push_back(l0 + dpt);
+                D.prolong[dpt].levels.push_back(l0 + dpt);
+            }
+            D.coarsest.levels.push_back(l0 + p.nlev[g] - 1);
+        }
+        finish_list(D.l0_cell, p.levels, tiles_cell);
+        finish_list(D.coarsest, p.levels, tiles_one);
+        for (int dpt = 0; dpt < maxdepth; ++dpt) {
+            finish_list(D.smooth[dpt], p.levels, tiles_smooth);
+            finish_list(D.prolong[dpt], p.levels, tiles_cell);
+            // restriction / coarsening tiles cover the coarse level
+            HostList& r = D.restrict_[dpt];
+            r.prefix.assign(1, 0);
+            for (int32_t li : r.levels) r.prefix.push_back(r.prefix.back() + cell_tiles(p.levels[p.levels[li].coarse].n));
+        }
+    }
+}
+
+static void layout(Plan& p) {
+    const int G = p.ngrids();
+    const size_t NL = p.levels.size();
+    size_t off = 0;
+    p.off_levels = off; off = align_up(off + NL * sizeof(LevelDesc));
+    p.off_state = off;  off = align_up(off + G * sizeof(GridState));
+    p.off_stepio = off; off = align_up(off + G * sizeof(StepIO));
+    p.off_exio = off;   off = align_up(off + Plan::kExSlots * G * sizeof(ExchangeIO));
+    p.off_ctrl = off;   off = align_up(off + sizeof(Control));
+    auto place_list = [&](HostList& l) {
+        l.off_levels = off; off = align_up(off + std::max<size_t>(1, l.levels.size()) * sizeof(int32_t));
+        l.off_prefix = off; off = align_up(off + l.prefix.size() * sizeof(int32_t));
+    };
+    for (auto& D : p.dl) {
+        place_list(D.l0_cell);
+        place_list(D.coarsest);
+        for (auto& l : D.smooth) place_list(l);
+        for (auto& l : D.restrict_) place_list(l);
+        for (auto& l : D.prolong) place_list(l);
+    }
+    p.foff.assign(NL, Plan::FieldOff{});
+    for (size_t li = 0; li < NL; ++li) {
+        const LevelDesc& d = p.levels[li];
+        Plan::FieldOff& f = p.foff[li];
+        const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
+        const bool lev0 = d.level == 0;
+        // FP64: weights at every level (coarse weights derive from them); x and b at
+        // level 0 always, and at every level in FP64 mode.
+        for (int a = 0; a < d.ndim; ++a) { f.w[a] = off; off = align_up(off + n * 8); }
+        if (lev0 || !p.mixed) {
+            f.has_x = f.has_b = true;
+            f.x = off; off = align_up(off + n * 8);
+            f.b = off; off = align_up(off + n * 8);
+        }
+        if (p.mixed) {
+            f.has_x32 = true;
+            f.x32 = off; off = align_up(off + n * 4);
+            f.b32 = off; off = align_up(off + n * 4);
+            for (int a = 0; a < d.ndim; ++a) { f.w32[a] = off; off = align_up(off + n * 4); }
+        }
+        if (lev0) {
+            f.has_part = true;
+            f.part = off; off = align_up(off + 2 * (size_t)cell_tiles(d.n) * 8);
+        }
+        if (d.coarse < 0 && n > (size_t)kCoarseMaxLDS) {
+            f.has_scratch = true;
+            f.scratch = off; off = align_up(off + 4 * n * 8);
+        }
+    }
+    p.ws_bytes = off;
+}
+
+// Enqueue one V-cycle (FP64 mode: on the solution; mixed: the FP32 correction
+// solve of the current residual) followed by the FP64 residual and stop test.
+static void enqueue_cycle(Plan& p, hipStream_t s) {
+    const bool f32 = p.mixed;
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        const int dim = D.dim;
+        for (int d = 0; d < D.maxdepth; ++d) {
+            for (int it = 0; it < p.opts.nu1; ++it) {
+                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
+                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
+            }
+            launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
+        }
+        launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
+        for (int d = D.maxdepth - 1; d >= 0; --d) {
+            launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
+            for (int it = 0; it < p.opts.nu2; ++it) {
+                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
+                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
+            }
+        }
+        if (p.mixed) launch_correct(dim, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
+        launch_residual(dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
+        launch_finalize_r(p.dL, p.dS, D.l0_cell.dev, p.opts.max_cycles, 1, s);
+    }
+}
+
+static int capture_graph(Plan& p) {
+    if (p.graph_exec) { (void)hipGraphExecDestroy(p.graph_exec); p.graph_exec = nullptr; }
+    if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
+    if (!p.cap_stream) FLD_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+    FLD_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_cycle(p, p.cap_stream);
+    hipGraph_t g = nullptr;
+    FLD_HIP(hipStreamEndCapture(p.cap_stream, &g));
+    p.graph = g;
+    FLD_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+    return FLD_OK;
+}
+
+static int bind(Plan& p, void* dev, size_t bytes) {
+    if (!dev) return FLD_ERR_INVALID_ARG;
+    if (bytes < p.ws_bytes) return FLD_ERR_NO_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(dev) % kAlign) != 0) return FLD_ERR_INVALID_ARG;
+    p.ws = static_cast<char*>(dev);
+    char* ws = p.ws;
+    p.dL = reinterpret_cast<LevelDesc*>(ws + p.off_levels);
+    p.dS = reinterpret_cast<GridState*>(ws + p.off_state);
+    p.dIO = reinterpret_cast<StepIO*>(ws + p.off_stepio);
+    p.dEx = reinterpret_cast<ExchangeIO*>(ws + p.off_exio);
+    p.dCtrl = reinterpret_cast<Control*>(ws + p.off_ctrl);
+    for (size_t li = 0; li < p.levels.size(); ++li) {
+        LevelDesc& d = p.levels[li];
+        const Plan::FieldOff& f = p.foff[li];
+        for (int a = 0; a < 3; ++a) {
+            d.w[a] = a < d.ndim ? reinterpret_cast<double*>(ws + f.w[a]) : nullptr;
+            d.w32[a] = (p.mixed && a < d.ndim) ? reinterpret_cast<float*>(ws + f.w32[a]) : nullptr;
+        }
+        d.x = f.has_x ? reinterpret_cast<double*>(ws + f.x) : nullptr;
+        d.b = f.has_b ? reinterpret_cast<double*>(ws + f.b) : nullptr;
+        d.x32 = f.has_x32 ? reinterpret_cast<float*>(ws + f.x32) : nullptr;
+        d.b32 = f.has_x32 ? reinterpret_cast<float*>(ws + f.b32) : nullptr;
+        d.part = f.has_part ? reinterpret_cast<double*>(ws + f.part) : nullptr;
+        d.scratch = f.has_scratch ? reinterpret_cast<double*>(ws + f.scratch) : nullptr;
+    }
+    FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
+    std::vector<GridState> st(p.ngrids());
+    for (int g = 0; g < p.ngrids(); ++g) {
+        st[g] = GridState{};
+        st[g].ntiles0 = cell_tiles(p.levels[p.level0[g]].n);
+    }
+    FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
+    Control c0{};
+    FLD_HIP(hipMemcpy(p.dCtrl, &c0, sizeof(Control), hipMemcpyHostToDevice));
+    auto upload = [&](HostList& l) -> int {
+        int32_t* lv = reinterpret_cast<int32_t*>(ws + l.off_levels);
+        int32_t* pf = reinterpret_cast<int32_t*>(ws + l.off_prefix);
+        if (!l.levels.empty())
+            FLD_HIP(hipMemcpy(lv, l.levels.data(), l.levels.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back()};
+        return FLD_OK;
+    };
+    for (auto& D : p.dl) {
+        int rc;
+        if ((rc = upload(D.l0_cell)) != FLD_OK) return rc;
+        if ((rc = upload(D.coarsest)) != FLD_OK) return rc;
+        for (auto& l : D.smooth) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.restrict_) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.prolong) if ((rc = upload(l)) != FLD_OK) return rc;
+    }
+    if (!p.hIO) FLD_HIP(hipHostMalloc((void**)&p.hIO, p.ngrids() * sizeof(StepIO), hipHostMallocDefault));
+    if (!p.hEx)
+        FLD_HIP(hipHostMalloc((void**)&p.hEx, Plan::kExSlots * p.ngrids() * sizeof(ExchangeIO), hipHostMallocDefault));
+    if (!p.hCtrl) FLD_HIP(hipHostMalloc((void**)&p.hCtrl, sizeof(Control), hipHostMallocDefault));
+    if (!p.hS) FLD_HIP(hipHostMalloc((void**)&p.hS, p.ngrids() * sizeof(GridState), hipHostMallocDefault));
+    for (auto& e : p.ex_done)
+        if (!e) FLD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p.max_n = 0;
+    for (auto n : p.ncell) p.max_n = std::max<int64_t>(p.max_n, n);
+    if (p.opts.use_graph) {
+        int rc = capture_graph(p);
+        if (rc != FLD_OK) return rc;
+    }
+    return FLD_OK;
+}
+
+static int step(Plan& p, const double* const* E_in, const double* const* kr, double* const* E_out,
+                const double* dt, hipStream_t s, fld_stats* stats) {
+    const int G = p.ngrids();
+    for (int g = 0; g < G; ++g) {
+        if (!E_in[g] || !kr[g] || !E_out[g]) return FLD_ERR_INVALID_ARG;
+        if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+        p.hIO[g].E_in = E_in[g];
+        p.hIO[g].kr = kr[g];
+        p.hIO[g].E_out = E_out[g];
+        p.hIO[g].dt = dt[g];
+    }
+    FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(StepIO), hipMemcpyHostToDevice, s));
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+        launch_finalize_b(p.dL, p.dS, D.l0_cell.dev, p.opts.rtol, s);
+        for (int d = 0; d < D.maxdepth; ++d) launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
+        launch_finalize_r(p.dL, p.dS, D.l0_cell.dev, p.opts.max_cycles, 0, s);
+    }
+    FLD_HIP(hipGetLastError());
+    // V-cycles in rounds: each round replays `burst` cycles, then reads back how
+    // many grids are still active.  The first burst is sized from the previous
+    // step's cycle count so a typical step needs one or two host round trips.
+    int done = 0;
+    int burst = std::max(1, std::min(p.last_cycles > 0 ? p.last_cycles : 4, p.opts.max_cycles));
+    int used = 0;
+    while (done < p.opts.max_cycles) {
+        const int nrun = std::min(burst, p.opts.max_cycles - done);
+        for (int r = 0; r < nrun; ++r) {
+            if (p.graph_exec) FLD_HIP(hipGraphLaunch(p.graph_exec, s));
+            else enqueue_cycle(p, s);
+        }
+        FLD_HIP(hipGetLastError());
+        done += nrun;
+        launch_count(p.dS, G, p.dCtrl, s);
+        FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        FLD_HIP(hipStreamSynchronize(s));
+        if (p.hCtrl->nactive == 0) break;
+        burst = std::max(1, burst / 2);
+    }
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        launch_output(D.dim, p.dL, D.l0_cell.dev, p.dIO, p.nblk, s);
+    }
+    FLD_HIP(hipMemcpyAsync(p.hS, p.dS, G * sizeof(GridState), hipMemcpyDeviceToHost, s));
+    FLD_HIP(hipStreamSynchronize(s));
+    int rc = FLD_OK;
+    int maxc = 0;
+    for (int g = 0; g < G; ++g) {
+        const GridState& st = p.hS[g];
+        // a grid still active after max_cycles did not converge
+        const int status = st.active ? FLD_ERR_NOT_CONVERGED : st.status;
+        maxc = std::max(maxc, (int)st.cycles);
+        if (stats) {
+            fld_stats& o = stats[g];
+            o.cycles = st.cycles;
+            o.status = status;
+            o.rel_residual = st.bnorm2 > 0 ? std::sqrt(st.rnorm2 / st.bnorm2) : 0.0;
+            o.b_norm = std::sqrt(st.bnorm2);
+            o.b_sum = st.bsum;
+            const double N = (double)p.ncell[g];
+            o.q_b = (st.bsum != 0.0) ? std::sqrt(st.bnorm2) / (std::sqrt(N) * std::fabs(st.bsum / N)) : INFINITY;
+        }
+        if (rc == FLD_OK && status != FLD_OK) rc = status;
+    }
+    (void)used;
+    p.last_cycles = maxc;
+    return rc;
+}
+
+static int exchange(Plan& p, double* const* E, double* const* eps, const double* const* rho,
+                    const double* const* kappa, const double* dt, const fld_gas& gas, hipStream_t s) {
+    const int G = p.ngrids();
+    p.last_gas = gas;
+    const int slot = p.ex_slot;
+    p.ex_slot = (p.ex_slot + 1) % Plan::kExSlots;
+    FLD_HIP(hipEventSynchronize(p.ex_done[slot]));     // staging slot free again
+    ExchangeIO* h = p.hEx + (size_t)slot * G;
+    for (int g = 0; g < G; ++g) {
+        if (!E[g] || !eps[g] || !rho[g] || !kappa[g]) return FLD_ERR_INVALID_ARG;
+        if (!(dt[g] >= 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+        h[g] = ExchangeIO{E[g], eps[g], rho[g], kappa[g], dt[g], p.ncell[g]};
+    }
+    ExchangeIO* d = p.dEx + (size_t)slot * G;
+    FLD_HIP(hipMemcpyAsync(d, h, G * sizeof(ExchangeIO), hipMemcpyHostToDevice, s));
+    launch_exchange(d, G, p.max_n, gas.c, gas.a_rad, gas.c_v, gas.max_halley, gas.root_rtol, p.dCtrl,
+                    p.nblk, s);
+    FLD_HIP(hipGetLastError());
+    FLD_HIP(hipEventRecord(p.ex_done[slot], s));
+    p.ex_last = slot;
+    return FLD_OK;
+}
+
+static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t s, double* avg_ms,
+                          int64_t* cells) {
+    const int G = p.ngrids();
+    int64_t nc = 0;
+    // collect the lists the kernel runs over (2D and 3D grids launch separately)
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        const bool has_level = level >= 0 && level < D.maxdepth;
+        const HostList* l = nullptr;
+        switch (kernel) {
+            case FLD_KERNEL_SMOOTH: if (has_level) l = &D.smooth[level]; break;
+            case FLD_KERNEL_RESTRICT: if (has_level) l = &D.restrict_[level]; break;
+            case FLD_KERNEL_PROLONG: if (has_level) l = &D.prolong[level]; break;
+            default: l = &D.l0_cell; break;
+        }
+        if (!l) continue;
+        for (int32_t li : l->levels) nc += (int64_t)p.levels[li].n[0] * p.levels[li].n[1] * p.levels[li].n[2];
+    }
+    if (kernel == FLD_KERNEL_EXCHANGE) {
+        if (p.ex_last < 0) return FLD_ERR_INVALID_ARG;
+        nc = 0;
+        for (auto n : p.ncell) nc += n;
+    }
+    if (nc == 0) return FLD_ERR_INVALID_ARG;
+    hipEvent_t e0, e1;
+    FLD_HIP(hipEventCreate(&e0));
+    FLD_HIP(hipEventCreate(&e1));
+    launch_set_active(p.dS, G, 1, s);
+    auto once = [&]() {
+        for (auto& D : p.dl) {
+            if (D.l0_cell.empty()) continue;
+            const bool has_level = level >= 0 && level < D.maxdepth;
+            switch (kernel) {
+                case FLD_KERNEL_SMOOTH:
+                    if (has_level) launch_smooth(D.dim, p.mixed, p.dL, p.dS, D.smooth[level].dev, 0, p.nblk, s);
+                    break;
+                case FLD_KERNEL_RESIDUAL:
+                    launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
+                    break;
+                case FLD_KERNEL_RESTRICT:
+                    if (has_level) launch_restrict(D.dim, p.mixed, p.dL, p.dS, D.restrict_[level].dev, p.nblk, s);
+                    break;
+                case FLD_KERNEL_PROLONG:
+                    if (has_level) launch_prolong(D.dim, p.mixed, p.dL, p.dS, D.prolong[level].dev, p.nblk, s);
+                    break;
+                case FLD_KERNEL_COEFF:
+                    launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+                    break;
+                default: break;
+            }
+        }
+        if (kernel == FLD_KERNEL_VCYCLE) {
+            if (p.graph_exec) (void)hipGraphLaunch(p.graph_exec, s);
+            else enqueue_cycle(p, s);
+            launch_set_active(p.dS, G, 1, s);
+        }
+        if (kernel == FLD_KERNEL_EXCHANGE) {
+            const fld_gas* g = &p.last_gas;
+            launch_exchange(p.dEx + (size_t)p.ex_last * G, G, p.max_n, g->c, g->a_rad, g->c_v, g->max_halley,
+                            g->root_rtol, p.dCtrl, p.nblk, s);
+        }
+    };
+    once();                                    // warm-up
+    FLD_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) once();
+    FLD_HIP(hipEventRecord(e1, s));
+    FLD_HIP(hipGetLastError());
+    FLD_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FLD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    launch_set_active(p.dS, G, 0, s);
+    FLD_HIP(hipStreamSynchronize(s));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    *cells = nc;
+    return FLD_OK;
+}
+
+}  // namespace fld
+
+// ============================================================================
+// C ABI
+// ============================================================================
+using fld::Plan;
+
+struct fld_plan_s {
+    Plan p;
+};
+
+extern "C" {
+
+int32_t fld_version(void) { return 100; }
+
+const char* fld_strerror(int32_t code) {
+    switch (code) {
+        case FLD_OK: return "ok";
+        case FLD_PENDING: return "pending";
+        case FLD_ERR_INVALID_ARG: return "invalid argument";
+        case FLD_ERR_BAD_INPUT: return "bad input (non-positive or non-finite field value)";
+        case FLD_ERR_NOT_CONVERGED: return "not converged";
+        case FLD_ERR_TOO_LARGE: return "request larger than the arena";
+        case FLD_ERR_UNKNOWN_TICKET: return "unknown ticket";
+        case FLD_ERR_HIP: return "HIP runtime error";
+        case FLD_ERR_NO_WORKSPACE: return "no or too small workspace bound";
+        case FLD_ERR_UNSUPPORTED: return "unsupported option";
+        case FLD_ERR_SHUTDOWN: return "server shutting down";
+        default: return "unknown status";
+    }
+}
+
+const char* fld_last_error(void) { return fld::g_last_error.c_str(); }
+
+void fld_opts_default(fld_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->c = 1.0;
+    o->limiter = FLD_LIMITER_LP;
+    for (int f = 0; f < 6; ++f) o->bc[f] = FLD_BC_ZERO_FLUX;
+    o->precision = FLD_PREC_FP64;
+    o->rtol = 1e-10;
+    o->max_cycles = 50;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->use_graph = 1;
+    o->autotune = 0;
+}
+
+void fld_gas_default(fld_gas* g) {
+    if (!g) return;
+    g->c = 1.0;
+    g->a_rad = 1.0;
+    g->c_v = 1.0;
+    g->max_halley = 100;
+    g->root_rtol = 4.0 * 2.220446049250313e-16;
+}
+
+int32_t fld_plan_create(const fld_grid* grids, int32_t ngrids, const fld_opts* opts, fld_plan_t* out) {
+    try {
+        if (!grids || ngrids < 1 || !opts || !out) return FLD_ERR_INVALID_ARG;
+        *out = nullptr;
+        int rc = fld::validate_opts(*opts);
+        if (rc != FLD_OK) return rc;
+        for (int g = 0; g < ngrids; ++g)
+            if ((rc = fld::validate_grid(grids[g])) != FLD_OK) return rc;
+        auto* h = new fld_plan_s();
+        Plan& p = h->p;
+        if (hipGetDevice(&p.device) != hipSuccess) p.device = 0;
+        p.opts = *opts;
+        p.mixed = opts->precision == FLD_PREC_MIXED;
+        p.grids.assign(grids, grids + ngrids);
+        for (auto& g : p.grids)
+            if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
+        fld::build_levels(p);
+        fld::build_lists(p);
+        fld::layout(p);
+        *out = h;
+        return FLD_OK;
+    } catch (const std::bad_alloc&) {
+        return FLD_ERR_INVALID_ARG;
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_plan_destroy(fld_plan_t plan) {
+    if (!plan) return FLD_ERR_INVALID_ARG;
+    fld::DeviceGuard dg(plan->p.device);
+    delete plan;
+    return FLD_OK;
+}
+
+int32_t fld_plan_workspace_bytes(fld_plan_t plan, size_t* bytes) {
+    if (!plan || !bytes) return FLD_ERR_INVALID_ARG;
+    *bytes = plan->p.ws_bytes;
+    return FLD_OK;
+}
+
+int32_t fld_plan_bind_workspace(fld_plan_t plan, void* dev, size_t bytes) {
+    if (!plan || !dev) return FLD_ERR_INVALID_ARG;
+    if (bytes < plan->p.ws_bytes) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(plan->p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        int rc = fld::bind(plan->p, dev, bytes);
+        if (rc != FLD_OK) plan->p.ws = nullptr;
+        return rc;
+    } catch (...) {
+        plan->p.ws = nullptr;
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_plan_levels(fld_plan_t plan, int32_t g, int32_t* nlevels) {
+    if (!plan || !nlevels || g < 0 || g >= plan->p.ngrids()) return FLD_ERR_INVALID_ARG;
+    *nlevels = plan->p.nlev[g];
+    return FLD_OK;
+}
+
+int32_t fld_plan_level_view(fld_plan_t plan, int32_t g, int32_t level, fld_level_view* out) {
+    if (!plan || !out || g < 0 || g >= plan->p.ngrids()) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (level < 0 || level >= p.nlev[g]) return FLD_ERR_INVALID_ARG;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    const fld::LevelDesc& d = p.levels[p.level0[g] + level];
+    out->ndim = d.ndim;
+    for (int a = 0; a < 3; ++a) {
+        out->n[a] = d.n[a];
+        out->w[a] = d.w[a];
+        out->w32[a] = d.w32[a];
+    }
+    out->x = d.x;
+    out->b = d.b;
+    out->x32 = d.x32;
+    out->b32 = d.b32;
+    return FLD_OK;
+}
+
+int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho,
+                         const double* dt, void* stream) {
+    if (!plan || !E_in || !kappa_rho || !dt) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int G = p.ngrids();
+        FLD_HIP(hipStreamSynchronize(s));            // the staging buffer is reused below
+        for (int g = 0; g < G; ++g) {
+            if (!E_in[g] || !kappa_rho[g]) return FLD_ERR_INVALID_ARG;
+            if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+            p.hIO[g] = fld::StepIO{E_in[g], kappa_rho[g], nullptr, dt[g]};
+        }
+        FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(fld::StepIO), hipMemcpyHostToDevice, s));
+        for (auto& D : p.dl) {
+            if (D.l0_cell.empty()) continue;
+            fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+            fld::launch_finalize_b(p.dL, p.dS, D.l0_cell.dev, p.opts.rtol, s);
+            for (int d = 0; d < D.maxdepth; ++d)
+                fld::launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
+        }
+        FLD_HIP(hipGetLastError());
+        FLD_HIP(hipStreamSynchronize(s));            // staging buffer free on return
+        return FLD_OK;
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_step(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho,
+                 double* const* E_out, const double* dt, void* stream, fld_stats* stats) {
+    if (!plan || !E_in || !kappa_rho || !E_out || !dt) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        FLD_HIP(hipStreamSynchronize(s));            // earlier work may still read the staging buffer
+        return fld::step(p, E_in, kappa_rho, E_out, dt, s, stats);
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_exchange(fld_plan_t plan, double* const* E, double* const* eps, const double* const* rho,
+                     const double* const* kappa, const double* dt, const fld_gas* gas, void* stream) {
+    if (!plan || !E || !eps || !rho || !kappa || !dt || !gas) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    if (!(gas->c > 0.0) || !(gas->a_rad >= 0.0) || !(gas->c_v > 0.0) || gas->max_halley < 0 ||
+        !(gas->root_rtol > 0.0))
+        return FLD_ERR_INVALID_ARG;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        return fld::exchange(p, E, eps, rho, kappa, dt, *gas, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected) {
+    if (!plan) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    fld::DeviceGuard dg(p.device);
+    if (!dg.ok) return FLD_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(fld::Control), hipMemcpyDeviceToHost, s));
+    FLD_HIP(hipStreamSynchronize(s));
+    const int bad = p.hCtrl->bad_exchange;
+    if (bisected) *bisected = p.hCtrl->bisected;
+    // clear bad_exchange (offset 4) and bisected (offset 8): 12 contiguous bytes
+    static_assert(offsetof(fld::Control, bisected) == offsetof(fld::Control, bad_exchange) + 4,
+                  "Control layout");
+    p.hCtrl->bad_exchange = 0;
+    p.hCtrl->bisected = 0;
+    FLD_HIP(hipMemcpyAsync(&p.dCtrl->bad_exchange, &p.hCtrl->bad_exchange, sizeof(int32_t) + sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    FLD_HIP(hipStreamSynchronize(s));
+    return bad ? FLD_ERR_BAD_INPUT : FLD_OK;
+}
+
+int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps, void* stream,
+                           double* avg_ms, int64_t* cells) {
+    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_EXCHANGE)
+        return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        return fld::profile_kernel(p, kernel, level, reps, static_cast<hipStream_t>(stream), avg_ms, cells);
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: face weights <= 1e-14 relative per face; one diffusion step <= 1e-10
+relative L2 (the run stops at rtol = 1e-10 / q_b, so ||x - x*|| / ||x*|| <= 1e-10 is
+guaranteed by the residual bound; the oracle itself is within 1e-13 q_b of x*);
+exchange <= 1e-12 (eps + E) per cell.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as O                     # noqa: E402
+import workloads as W                  # noqa: E402
+import paper_2104_03968_amd as fld     # noqa: E402
+from tests.gpu_common import dev, rel_l2, run_step   # noqa: E402
+
+
+def _rtol_for(g):
+    return 1e-10 / O.q_b(g.E)
+
+
+# ------------------------------------------------------------------ K1 coefficients
+@pytest.mark.parametrize("shape,limiter", [((64, 64), "lp"), ((37, 100), "lp"), ((64, 64), "diffusion"),
+                                           ((9, 13, 20), "lp"), ((2, 2), "lp"), ((3, 2, 5), "lp")])
+def test_face_weights_match_oracle(shape, limiter):
+    g = W.pulse_2d() if shape == (64, 64) else W.random_grid(shape, 123000 + sum(shape), dt=3e-3)
+    g.limiter = limiter
+    plan = fld.Plan([g.E.shape], h=[g.h], limiter=0 if limiter == "lp" else 1, c=g.c)
+    plan.coefficients([dev(g.E)], [dev(g.kappa_rho)], [g.dt])
+    torch.cuda.synchronize()
+    lv = plan.level_tensors(0, 0)
+    D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h, g.c, limiter)
+    w_or = O.face_weights(D, g.dt, g.h)
+    for d in range(g.E.ndim):
+        wg = lv["w"][d].cpu().numpy()
+        wo = w_or[d]
+        assert np.all((wg == 0) == (wo == 0))
+        err = np.abs(wg - wo) / np.where(wo == 0, 1.0, np.abs(wo))
+        assert err.max() <= 1e-14, (d, err.max())
+    # the right-hand side copy and initial guess are E^n, bitwise
+    assert np.array_equal(lv["b"].cpu().numpy(), g.E)
+    plan.close()
+
+
+def test_face_weights_full_size_config2():
+    g = W.c2_inputs(1024)
+    plan = fld.Plan([g.E.shape], h=[g.h])
+    plan.coefficients([dev(g.E)], [dev(g.kappa_rho)], [g.dt])
+    torch.cuda.synchronize()
+    lv = plan.level_tensors(0, 0)
+    w_or = O.face_weights(O.diffusion_coefficient(g.E, g.kappa_rho, g.h), g.dt, g.h)
+    for d in range(2):
+        wg = lv["w"][d].cpu().numpy()
+        err = np.abs(wg - w_or[d]) / np.where(w_or[d] == 0, 1.0, np.abs(w_or[d]))
+        assert err.max() <= 1e-14
+    plan.close()
+
+
+# ------------------------------------------------------------------ one diffusion step
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_step_matches_lu(precision):
+    g = W.pulse_2d()
+    x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="lu")
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g))
+    assert rc == 0 and st["status"] == 0, st
+    assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st)
+    assert st["q_b"] == pytest.approx(O.q_b(g.E), rel=1e-12)
+    assert abs(x.sum() - g.E.sum()) / g.E.sum() < 1e-12
+
+
+@pytest.mark.parametrize("shape,dt", [((37, 100), 5e-3), ((96, 96), 1e-2), ((3, 5), 1e-2), ((2, 2), 1e-1),
+                                      ((130, 66), 2e-3), ((20, 12, 8), 5e-3), ((24, 24, 24), 1e-2),
+                                      ((9, 7, 5), 1e-2)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ragged_and_odd_grids_match_oracle(shape, dt, precision):
+    g = W.random_grid(shape, 555000 + 7 * sum(shape), dt=dt)
+    x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, method="auto")
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g))
+    assert rc == 0 and st["status"] == 0, st
+    assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st, info)
+
+
+def test_diffusion_limiter_matches_dct():
+    """Constant coefficients, lambda = 1/3: the GPU step equals the spectral solution."""
+    import scipy.fft
+    n = 256
+    E = W.random_grid((n, n), 99100, 1e-3).E
+    kr = np.full_like(E, 10.0)
+    g = W.GridInput(E=E, kappa_rho=kr, dt=1e-2, h=(1 / n, 1 / n), limiter="diffusion")
+    k = np.arange(n)
+    ev = 4 * n * n * np.sin(np.pi * k / (2 * n)) ** 2
+    lam = ev[None, :] + ev[:, None]
+    ref = scipy.fft.idctn(scipy.fft.dctn(E, type=2, norm="ortho") / (1 + g.dt / 30.0 * lam),
+                          type=2, norm="ortho")
+    (x,), (st,), rc = run_step([g], limiter="diffusion", rtol=_rtol_for(g))
+    assert rc == 0 and rel_l2(x, ref) <= 1e-10
+
+
+def test_in_place_output():
+    g = W.random_grid((64, 80), 321000, dt=5e-3)
+    x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h)
+    (x,), (st,), rc = run_step([g], rtol=_rtol_for(g), in_place=True)
+    assert rc == 0 and rel_l2(x, x_or) <= 1e-10
+
+
+def test_graph_and_direct_launches_agree_bitwise():
+    g = W.random_grid((128, 96), 77000, dt=5e-3)
+    (xa,), (sa,), _ = run_step([g], use_graph=1)
+    (xb,), (sb,), _ = run_step([g], use_graph=0)
+    assert np.array_equal(xa, xb) and sa["cycles"] == sb["cycles"]
+
+
+def test_reported_residual_is_the_oracle_residual():
+    g = W.random_grid((200, 120), 88000, dt=1e-2)
+    (x,), (st,), rc = run_step([g])
+    D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h)
+    A = O.assemble_operator(O.face_weights(D, g.dt, g.h))
+    rr = O.relative_residual(A, x, g.E)
+    assert rr <= 1e-10 * 1.01
+    assert st["rel_residual"] == pytest.approx(rr, rel=1e-3, abs=1e-16)
+    assert 1 <= st["cycles"] <= 20
+
+
+# ------------------------------------------------------------------ batching
+def test_batched_equals_alone_bitwise():
+    shapes = [(64, 64), (96, 96), (37, 100), (160, 160), (24, 24, 24)]
+    grids = [W.random_grid(s, 600000 + 13 * i, dt=2e-3 * (i + 1)) for i, s in enumerate(shapes)]
+    xb, sb, rc = run_step(grids)
+    assert rc == 0
+    for i, g in enumerate(grids):
+        (xa,), (sa,), _ = run_step([g])
+        assert np.array_equal(xa, xb[i]), i
+        assert sa["cycles"] == sb[i]["cycles"]
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h)
+        assert rel_l2(xb[i], x_or) <= 1e-10 * O.q_b(g.E) * 1.01
+
+
+# ------------------------------------------------------------------ failure paths
+def test_bad_input_reported():
+    g = W.random_grid((32, 32), 1000, dt=1e-3)
+    g.E[5, 5] = -1.0
+    (x,), (st,), rc = run_step([g])
+    assert rc == fld.FLD_ERR_BAD_INPUT and st["status"] == fld.FLD_ERR_BAD_INPUT
+    g2 = W.random_grid((32, 32), 1001, dt=1e-3)
+    g2.kappa_rho[0, 0] = np.nan
+    _, (st2,), rc2 = run_step([g2])
+    assert rc2 == fld.FLD_ERR_BAD_INPUT
+    # a good grid in the same batch is still solved
+    g3 = W.random_grid((32, 32), 1002, dt=1e-3)
+    xs, sts, rc3 = run_step([g, g3])
+    assert rc3 == fld.FLD_ERR_BAD_INPUT and sts[1]["status"] == 0
+    x_or, _ = O.diffusion_step(g3.E, g3.kappa_rho, g3.dt, g3.h)
+    assert rel_l2(xs[1], x_or) <= 1e-10 * O.q_b(g3.E)
+
+
+def test_not_converged_reported_with_stats():
+    g = W.random_grid((128, 128), 1003, dt=1e-2)
+    (x,), (st,), rc = run_step([g], rtol=1e-15, max_cycles=2)
+    assert rc == fld.FLD_ERR_NOT_CONVERGED and st["status"] == fld.FLD_ERR_NOT_CONVERGED
+    assert st["cycles"] == 2 and 0 < st["rel_residual"] < 1e-1
+    assert np.all(np.isfinite(x))
+
+
+# ------------------------------------------------------------------ exchange
+def _exchange_gpu(g, max_halley=100):
+    plan = fld.Plan([g.E.shape], h=[g.h])
+    E, eps, rho, kap = dev(g.E), dev(g.eps), dev(g.rho), dev(g.kappa)
+    plan.exchange([E], [eps], [rho], [kap], [g.dt], fld.fld_gas_default(max_halley=max_halley))
+    rc, nbis = plan.exchange_status()
+    out = E.cpu().numpy(), eps.cpu().numpy(), rc, nbis
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [64, 1024])
+def test_exchange_matches_oracle(n):
+    g = W.c2_inputs(n)
+    E2, eps2, rc, nbis = _exchange_gpu(g)
+    Eo, epso = O.exchange(g.E, g.eps, g.rho, g.kappa, g.dt)
+    tot = g.E + g.eps
+    assert rc == 0 and nbis == 0
+    assert np.all(np.abs(eps2 - epso) <= 1e-12 * tot)
+    assert np.all(np.abs(E2 - Eo) <= 1e-12 * tot)
+    assert np.all(np.abs(E2 + eps2 - tot) <= 1e-14 * tot)
+
+
+def test_exchange_bisection_fallback_gives_same_root():
+    g = W.c2_inputs(64)
+    E_h, eps_h, _, nb_h = _exchange_gpu(g, 100)
+    E_b, eps_b, rc, nb_b = _exchange_gpu(g, 0)
+    assert rc == 0 and nb_h == 0 and nb_b == g.E.size
+    tot = g.E + g.eps
+    assert np.all(np.abs(eps_b - eps_h) <= 4e-16 * tot)
+
+
+def test_exchange_wide_dynamic_range():
+    """Roots across many decades of beta (cgs-like and stiff cases)."""
+    rng = np.random.default_rng(9)
+    n = 50000
+    shape = (250, 200)
+    g = W.GridInput(E=10.0 ** rng.uniform(-3, 3, n).reshape(shape), kappa_rho=np.ones(shape), dt=1.0,
+                    h=(1 / 200, 1 / 250))
+    g.eps = 10.0 ** rng.uniform(-3, 3, n).reshape(shape)
+    g.rho = 10.0 ** rng.uniform(-2, 2, n).reshape(shape)
+    g.kappa = 10.0 ** rng.uniform(-3, 3, n).reshape(shape)
+    g.dt = 0.37
+    E2, eps2, rc, _ = _exchange_gpu(g)
+    Eo, epso = O.exchange(g.E, g.eps, g.rho, g.kappa, g.dt)
+    tot = g.E + g.eps
+    assert rc == 0
+    assert np.all(np.abs(eps2 - epso) <= 1e-12 * tot)
+
+
+def test_exchange_rejects_bad_cells():
+    g = W.c2_inputs(32)
+    g.rho[3, 3] = -1.0
+    E2, eps2, rc, _ = _exchange_gpu(g)
+    assert rc == fld.FLD_ERR_BAD_INPUT
+    assert E2[3, 3] == g.E[3, 3] and eps2[3, 3] == g.eps[3, 3]
