@@ -435,6 +435,9 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     const T* bg = Arr<T>::b(d);
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
     const double tol2 = 1e-12;                 // (1e-6)^2 relative
+    // The finest level of a single-level FP64 grid holds the solution itself: iterate
+    // from it.  Every other coarsest level solves for a correction from zero.
+    const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
         T x[kCoarseCPT], r[kCoarseCPT], dinv[kCoarseCPT];
         double rz = 0.0, rr0 = 0.0;
@@ -447,7 +450,23 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
             if (c < ncell) {
                 r[m] = bg[c];
                 dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, d.n, c);
+                if (warm) {
+                    x[m] = xg[c];
+                    p_sh[c] = x[m];
+                }
             }
+        }
+        if (warm) {                                  // r = b - A x from the current iterate
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < kCoarseCPT; ++m) {
+                const int c = threadIdx.x + m * kCoarseThreads;
+                if (c < ncell) {
+                    T dg;
+                    r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, d.n, c, dg);
+                }
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int m = 0; m < kCoarseCPT; ++m) {
@@ -513,11 +532,14 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     T* q = p + ncell;
     T* dv = q + ncell;
     double rz = 0.0, rr0 = 0.0;
+    if (!warm)
+        for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) xg[c] = T(0);
+    __syncthreads();
     for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
-        const T dg = diag_at<DIM, T>(w0, w1, w2, d.n, c);
-        const T rc = bg[c];
+        T dg;
+        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg);
+        const T rc = bg[c] - ax;
         const T z = rc / dg;
-        xg[c] = T(0);
         r[c] = rc;
         dv[c] = T(1) / dg;
         p[c] = z;

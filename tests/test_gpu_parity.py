@@ -1,6 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances: face weights <= 1e-14 relative per face; one diffusion step <= 1e-10
+Tolerances: face weights <= 1e-14 relative per face plus the rounding bound of the
+4th-order gradient where its terms cancel (see face_tolerance); one diffusion step <= 1e-10
 relative L2 (the run stops at rtol = 1e-10 / q_b, so ||x - x*|| / ||x*|| <= 1e-10 is
 guaranteed by the residual bound; the oracle itself is within 1e-13 q_b of x*);
 exchange <= 1e-12 (eps + E) per cell.
@@ -22,6 +23,54 @@ def _rtol_for(g):
     return 1e-10 / O.q_b(g.E)
 
 
+EPS = np.finfo(np.float64).eps
+
+
+def face_tolerance(g, limiter="lp"):
+    """Per-face relative tolerance from the conditioning of the 4th-order gradient.
+
+    The computed g_d carries an absolute rounding error of a few eps times
+    S_d = (|E_-2| + 8|E_-1| + 8|E_+1| + |E_+2|) / (12 h_d) whatever the order of the
+    sum, so |grad E| is uncertain by ~4 eps sum_d |g_d| S_d / |grad E|.  D depends on R
+    with relative sensitivity s(R) = |d ln lambda / d ln R| <= 1 (0 for lambda = 1/3),
+    and a harmonic face mean passes on at most the sum of its two cells' relative errors.
+    """
+    nd = g.E.ndim
+    P = O.pad_mirror(g.E, 2)
+    core = tuple(slice(2, 2 + s) for s in g.E.shape)
+    grads = O.gradient4(g.E, g.h)
+    gn = np.sqrt(sum(x * x for x in grads))
+    acc = np.zeros_like(g.E)
+    for d in range(nd):
+        a = nd - 1 - d
+
+        def sh(k):
+            sl = list(core)
+            sl[a] = slice(2 + k, 2 + k + g.E.shape[a])
+            return np.abs(P[tuple(sl)])
+        S = (sh(-2) + 8 * sh(-1) + 8 * sh(1) + sh(2)) / (12 * g.h[d])
+        acc += np.abs(grads[d]) * S
+    R = gn / (g.kappa_rho * g.E)
+    if limiter == "lp":
+        sens = R * np.abs(1 / (2 + R) - (3 + 2 * R) / (6 + 3 * R + R * R))
+    else:
+        sens = np.zeros_like(R)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel_R = np.where(gn > 0, 4 * EPS * acc / (gn * gn), 0.0)
+    cell = 8 * EPS + sens * rel_R
+    tol = []
+    for d in range(nd):
+        a = nd - 1 - d
+        lo = [slice(None)] * nd
+        hi = [slice(None)] * nd
+        lo[a] = slice(0, g.E.shape[a] - 1)
+        hi[a] = slice(1, g.E.shape[a])
+        t = np.full_like(g.E, 1e-14)
+        t[tuple(hi)] = 1e-14 + cell[tuple(lo)] + cell[tuple(hi)]
+        tol.append(t)
+    return tol
+
+
 # ------------------------------------------------------------------ K1 coefficients
 @pytest.mark.parametrize("shape,limiter", [((64, 64), "lp"), ((37, 100), "lp"), ((64, 64), "diffusion"),
                                            ((9, 13, 20), "lp"), ((2, 2), "lp"), ((3, 2, 5), "lp")])
@@ -34,12 +83,13 @@ def test_face_weights_match_oracle(shape, limiter):
     lv = plan.level_tensors(0, 0)
     D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h, g.c, limiter)
     w_or = O.face_weights(D, g.dt, g.h)
+    tol = face_tolerance(g, limiter)
     for d in range(g.E.ndim):
         wg = lv["w"][d].cpu().numpy()
         wo = w_or[d]
         assert np.all((wg == 0) == (wo == 0))
         err = np.abs(wg - wo) / np.where(wo == 0, 1.0, np.abs(wo))
-        assert err.max() <= 1e-14, (d, err.max())
+        assert np.all(err <= tol[d]), (d, err.max(), (err / tol[d]).max())
     # the right-hand side copy and initial guess are E^n, bitwise
     assert np.array_equal(lv["b"].cpu().numpy(), g.E)
     plan.close()
@@ -52,10 +102,13 @@ def test_face_weights_full_size_config2():
     torch.cuda.synchronize()
     lv = plan.level_tensors(0, 0)
     w_or = O.face_weights(O.diffusion_coefficient(g.E, g.kappa_rho, g.h), g.dt, g.h)
+    tol = face_tolerance(g)
     for d in range(2):
         wg = lv["w"][d].cpu().numpy()
         err = np.abs(wg - w_or[d]) / np.where(w_or[d] == 0, 1.0, np.abs(w_or[d]))
-        assert err.max() <= 1e-14
+        assert np.all(err <= tol[d]), (err.max(), (err / tol[d]).max())
+        # most faces are well conditioned: the flat 1e-14 bound holds for > 99 % of them
+        assert np.mean(err <= 1e-14) > 0.99
     plan.close()
 
 
