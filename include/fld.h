@@ -83,11 +83,15 @@ typedef struct fld_opts {
     int32_t bc[6];        /* per face x-,x+,y-,y+,z-,z+: FLD_BC_* [ZERO_FLUX]        */
     int32_t precision;    /* FLD_PREC_* [FP64]                                       */
     double  rtol;         /* stop when ||E^n - A E||_2 <= rtol ||E^n||_2 [1e-10]     */
-    int32_t max_cycles;   /* V-cycles (outer iterations in mixed mode) per step [50] */
+    int32_t max_cycles;   /* V-cycles (= outer iterations) per step [50]            */
     int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after the coarse
                              correction [2, 2]                                      */
     int32_t use_graph;    /* replay V-cycles from a captured hipGraph [1]           */
     int32_t autotune;     /* time the candidate launch shapes at bind time [0]      */
+    int32_t krylov;       /* 1: conjugate gradients preconditioned by one V-cycle per
+                             iteration, stopped on the recursive residual and
+                             confirmed on the true FP64 residual; 0: plain V-cycle
+                             iteration (defect correction in mixed precision) [1]   */
 } fld_opts;
 
 /* Per-grid result of fld_step. */

@@ -47,21 +47,44 @@ struct LevelDesc {
     float*  w32[3];
     double* part;        // per-tile partial sums (level 0 only)
     double* scratch;     // coarse-solve vectors for levels too large for LDS
+    // level 0 only: the outer FP64 iteration (x and b above are the arrays the
+    // V-cycle works on: X/B0 for plain V-cycle iteration, Z/R for CG)
+    double* X;           // iterate, E^{n+1}
+    double* B0;          // right-hand side E^n
+    double* R;           // FP64 residual B0 - A X
+    double* P[2];        // CG search directions (ping-pong by iteration parity)
+    double* Q;           // A p
 };
 
 // Per-grid solver state, updated on the device between V-cycles.
 struct GridState {
     double  bnorm2;      // ||b||^2
     double  bsum;        // sum b
-    double  rnorm2;      // last ||b - A x||^2
-    double  rprev2;      // previous cycle's ||r||^2 (stagnation test)
+    double  rnorm2;      // last ||b - A x||^2 (recursive in CG, true after a check)
+    double  rprev2;      // best ||r||^2 so far (stagnation test)
     double  tol2;        // rtol^2 ||b||^2
-    int32_t active;      // 1 while V-cycles are still needed
-    int32_t cycles;      // V-cycles done
+    double  rho;         // CG: r . z
+    double  alpha;       // CG step length
+    double  beta;        // CG direction update
+    int32_t active;      // 1 while iterations are still needed
+    int32_t cycles;      // V-cycles done (one per CG iteration)
     int32_t status;      // FLD_* status
-    int32_t stall;       // consecutive cycles with little progress
+    int32_t stall;       // consecutive iterations without 10 % progress
     int32_t bad;         // input-validation bits (atomicOr)
     int32_t ntiles0;     // cell-tiles of level 0 (number of partial sums)
+    int32_t iter;        // CG iterations since the last (re)start
+    int32_t pad_;
+};
+
+// Finalization modes of k_finalize (one block per grid, fixed-order sums).
+enum FinMode : int32_t {
+    FIN_B = 0,           // ||b||^2, sum b from the coefficient pass; (re)start the step
+    FIN_R_INIT = 1,      // initial true residual
+    FIN_R_CYCLE = 2,     // true residual after a plain V-cycle
+    FIN_R_VERIFY = 3,    // true residual after CG reported convergence
+    FIN_RZ = 4,          // CG: rho = r . z, beta
+    FIN_PQ = 5,          // CG: alpha = rho / p . q
+    FIN_CG = 6,          // CG: recursive ||r||^2, stop test
 };
 
 // Which levels a launch covers.  Level j of the list is LevelDesc levels[j];
@@ -101,7 +124,8 @@ struct Control {
 // All launches are asynchronous on `s`.  `nblk` caps the persistent grid size.
 void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
                   const StepIO* io, double c, int limiter, int nblk, hipStream_t s);
-void launch_finalize_b(const LevelDesc* L, GridState* S, JobList jl, double rtol, hipStream_t s);
+void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
+                     int max_cycles, hipStream_t s);
 void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s);
 void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                    int color, int nblk, hipStream_t s);
@@ -111,10 +135,17 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
                     int nblk, hipStream_t s);
 void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          hipStream_t s);
+// select: 0 = active grids, 1 = grids whose status is FLD_OK (convergence check).
+// zero_x: also clear the level-0 V-cycle iterate (FP64 or FP32 by `mixed`); mixed also
+// writes the FP32 right-hand side.
 void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
-                     int nblk, hipStream_t s);
-void launch_finalize_r(const LevelDesc* L, GridState* S, JobList jl, int max_cycles, int count_cycle,
-                       hipStream_t s);
+                     int select, int zero_x, int nblk, hipStream_t s);
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                  hipStream_t s);
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                  hipStream_t s);
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                      hipStream_t s);
 void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,

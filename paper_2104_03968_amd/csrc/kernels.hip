@@ -153,8 +153,8 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 d.w32[1][idx] = (float)wy;
                 if (DIM == 3) d.w32[2][idx] = (float)wz;
             }
-            d.b[idx] = e;
-            d.x[idx] = e;
+            d.B0[idx] = e;
+            d.X[idx] = e;
             s2 = e * e;
             s1 = e;
         }
@@ -178,29 +178,79 @@ __device__ __forceinline__ void sum_parts(const double* __restrict__ part, int n
     block_sum2<kBlock>(a, b, sh);
 }
 
+// One block per grid: sum the grid's level-0 tile partials in a fixed order and
+// apply the stop test / CG scalar update of the given mode.
 __global__ void __launch_bounds__(kBlock)
-k_finalize_b(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol) {
+k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int mode, double rtol,
+           int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     const LevelDesc& d = L[jl.levels[blockIdx.x]];
     GridState& g = S[d.grid];
+    const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
+    if (!run) return;                                // uniform per block
     double s2, s1;
-    sum_parts(d.part, g.ntiles0, 2, s2, s1, sh);
-    if (threadIdx.x == 0) {
-        g.bnorm2 = s2;
-        g.bsum = s1;
-        g.tol2 = rtol * rtol * s2;
-        g.cycles = 0;
-        g.stall = 0;
-        g.rnorm2 = s2;
-        g.rprev2 = INFINITY;
-        if (g.bad) {
-            g.status = FLD_ERR_BAD_INPUT;
-            g.active = 0;
-        } else {
-            g.status = FLD_OK;
-            g.active = 1;
+    sum_parts(d.part, g.ntiles0, mode == FIN_B ? 2 : 1, s2, s1, sh);
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+        case FIN_B:
+            g.bnorm2 = s2;
+            g.bsum = s1;
+            g.tol2 = rtol * rtol * s2;
+            g.cycles = 0;
+            g.iter = 0;
+            g.stall = 0;
+            g.rnorm2 = s2;
+            g.rprev2 = INFINITY;
+            g.status = g.bad ? FLD_ERR_BAD_INPUT : FLD_OK;
+            g.active = g.bad ? 0 : 1;
+            g.bad = 0;                               // read once per step; cleared for the next one
+            break;
+        case FIN_R_INIT:
+        case FIN_R_VERIFY:
+            g.rnorm2 = s2;
+            g.iter = 0;                              // (re)start CG from this residual
+            g.stall = 0;
+            if (!(s2 == s2) || isinf(s2)) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
+            else g.active = (s2 > g.tol2 && g.cycles < max_cycles) ? 1 : 0;
+            if (g.active == 0 && s2 > g.tol2 && g.status == FLD_OK) g.status = FLD_ERR_NOT_CONVERGED;
+            g.rprev2 = s2;
+            break;
+        case FIN_R_CYCLE:
+        case FIN_CG: {
+            g.rnorm2 = s2;
+            g.cycles += 1;
+            if (mode == FIN_CG) g.iter += 1;
+            if (!(s2 == s2) || isinf(s2)) {
+                g.active = 0;
+                g.status = FLD_ERR_NOT_CONVERGED;
+            } else if (s2 <= g.tol2) {
+                g.active = 0;
+                g.status = FLD_OK;
+            } else if (g.cycles >= max_cycles) {
+                g.active = 0;
+                g.status = FLD_ERR_NOT_CONVERGED;
+            } else {
+                // stagnation: no 10 % gain in ||r|| over the best so far for 5 iterations
+                if (s2 < 0.81 * g.rprev2) { g.rprev2 = s2; g.stall = 0; }
+                else if (++g.stall >= 5) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
+            }
+            break;
         }
-        g.bad = 0;                       // read once per step; cleared for the next one
+        case FIN_RZ:
+            g.beta = (g.iter > 0 && g.rho != 0.0) ? s2 / g.rho : 0.0;
+            g.rho = s2;
+            break;
+        case FIN_PQ:
+            if (s2 > 0.0 && isfinite(s2)) {
+                g.alpha = g.rho / s2;
+            } else {                                 // breakdown: no descent direction left
+                g.alpha = 0.0;
+                g.active = 0;
+                g.status = (g.rnorm2 <= g.tol2) ? FLD_OK : FLD_ERR_NOT_CONVERGED;
+            }
+            break;
+        default:
+            break;
     }
 }
 
@@ -582,23 +632,28 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
 // ---------------------------------------------------------------------------
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int select,
+           int zero_x) {
     __shared__ double sh[2 * kBlock / 64];
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;          // uniform per tile: no barrier divergence
+        const GridState& g = S[d.grid];
+        if (select == 0 ? !g.active : g.status != FLD_OK) continue;   // uniform per tile
         const int lt = t - jl.prefix[jb];
         int i, j, k;
         cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         double r2 = 0.0, unused = 0.0;
         if (i < d.n[0] && j < d.n[1]) {
-            const double r = residual_at<DIM, double>(d.x, d.b, d.w[0], d.w[1], d.w[2], d.n, i, j, k);
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            const double r = residual_at<DIM, double>(d.X, d.B0, d.w[0], d.w[1], d.w[2], d.n, i, j, k);
             r2 = r * r;
+            d.R[idx] = r;
             if (MIXED) {
-                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
                 d.b32[idx] = (float)r;
-                d.x32[idx] = 0.0f;
+                if (zero_x) d.x32[idx] = 0.0f;
+            } else if (zero_x) {
+                d.x[idx] = 0.0;
             }
         }
         block_sum2<kBlock>(r2, unused, sh);
@@ -606,36 +661,111 @@ k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
     }
 }
 
+// ---------------------------------------------------------------------------
+// Conjugate gradients on A with the V-cycle as preconditioner (FP64 scalars and
+// vectors; in mixed precision the V-cycle itself is FP32).  One iteration:
+//   z = V(r); rho = r.z; beta = rho/rho_old; p = z + beta p; q = A p;
+//   alpha = rho/p.q; x += alpha p; r -= alpha q.
+// The search direction is double-buffered by iteration parity so that q = A p
+// can read neighbours' new p without a second pass.
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+__device__ __forceinline__ double z_at(const LevelDesc& d, long idx) {
+    return MIXED ? (double)d.x32[idx] : d.x[idx];
+}
+
+template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_finalize_r(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int max_cycles,
-             int count_cycle) {
+k_cg_rz(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
     __shared__ double sh[2 * kBlock / 64];
-    const LevelDesc& d = L[jl.levels[blockIdx.x]];
-    GridState& g = S[d.grid];
-    if (!g.active) return;
-    double s2, unused;
-    sum_parts(d.part, g.ntiles0, 1, s2, unused, sh);
-    if (threadIdx.x == 0) {
-        g.rnorm2 = s2;
-        if (count_cycle) g.cycles += 1;
-        if (!(s2 == s2) || isinf(s2)) {
-            g.active = 0;
-            g.status = FLD_ERR_NOT_CONVERGED;
-        } else if (s2 <= g.tol2) {
-            g.active = 0;
-            g.status = FLD_OK;
-        } else if (g.cycles >= max_cycles) {
-            g.active = 0;
-            g.status = FLD_ERR_NOT_CONVERGED;
-        } else {
-            // stagnation: the residual norm shrinks by less than 10 % for 3 cycles in a row
-            g.stall = (s2 > 0.81 * g.rprev2) ? g.stall + 1 : 0;
-            if (g.stall >= 3) {
-                g.active = 0;
-                g.status = FLD_ERR_NOT_CONVERGED;
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        const int lt = t - jl.prefix[jb];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
+        double a = 0.0, unused = 0.0;
+        if (i < d.n[0] && j < d.n[1]) {
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            a = d.R[idx] * z_at<MIXED>(d, idx);
+        }
+        block_sum2<kBlock>(a, unused, sh);
+        if (threadIdx.x == 0) d.part[lt] = a;
+    }
+}
+
+template <int DIM, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_cg_pq(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    __shared__ double sh[2 * kBlock / 64];
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        const GridState& g = S[d.grid];
+        if (!g.active) continue;
+        const int lt = t - jl.prefix[jb];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
+        const bool restart = g.iter == 0;            // p = z (the old direction is not read)
+        const double beta = g.beta;
+        const int par = g.iter & 1;
+        double* __restrict__ Pn = d.P[par];
+        const double* __restrict__ Po = d.P[par ^ 1];
+        double pq = 0.0, unused = 0.0;
+        if (i < d.n[0] && j < d.n[1]) {
+            const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+            const long idx = i + j * sy + k * sz;
+            auto p_at = [&](long c) { return restart ? z_at<MIXED>(d, c) : z_at<MIXED>(d, c) + beta * Po[c]; };
+            const double pc = p_at(idx);
+            double q = pc;
+            if (i > 0) q += d.w[0][idx] * (pc - p_at(idx - 1));
+            if (i + 1 < d.n[0]) q += d.w[0][idx + 1] * (pc - p_at(idx + 1));
+            if (j > 0) q += d.w[1][idx] * (pc - p_at(idx - sy));
+            if (j + 1 < d.n[1]) q += d.w[1][idx + sy] * (pc - p_at(idx + sy));
+            if (DIM == 3) {
+                if (k > 0) q += d.w[2][idx] * (pc - p_at(idx - sz));
+                if (k + 1 < d.n[2]) q += d.w[2][idx + sz] * (pc - p_at(idx + sz));
+            }
+            Pn[idx] = pc;
+            d.Q[idx] = q;
+            pq = pc * q;
+        }
+        block_sum2<kBlock>(pq, unused, sh);
+        if (threadIdx.x == 0) d.part[lt] = pq;
+    }
+}
+
+template <int DIM, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_cg_update(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    __shared__ double sh[2 * kBlock / 64];
+    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        const GridState& g = S[d.grid];
+        if (!g.active) continue;
+        const int lt = t - jl.prefix[jb];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
+        const double alpha = g.alpha;
+        const double* __restrict__ P = d.P[g.iter & 1];
+        double r2 = 0.0, unused = 0.0;
+        if (i < d.n[0] && j < d.n[1]) {
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            d.X[idx] += alpha * P[idx];
+            const double r = d.R[idx] - alpha * d.Q[idx];
+            d.R[idx] = r;
+            r2 = r * r;
+            if (MIXED) {
+                d.b32[idx] = (float)r;
+                d.x32[idx] = 0.0f;
+            } else {
+                d.x[idx] = 0.0;
             }
         }
-        g.rprev2 = s2;
+        block_sum2<kBlock>(r2, unused, sh);
+        if (threadIdx.x == 0) d.part[lt] = r2;
     }
 }
 
@@ -650,7 +780,7 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
         if (i >= d.n[0] || j >= d.n[1]) continue;
         const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-        d.x[idx] += (double)d.x32[idx];
+        d.X[idx] += (double)d.x32[idx];
     }
 }
 
@@ -664,7 +794,7 @@ k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__
         cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
         if (i >= d.n[0] || j >= d.n[1]) continue;
         const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-        io[d.grid].E_out[idx] = d.x[idx];
+        io[d.grid].E_out[idx] = d.X[idx];
     }
 }
 
@@ -777,9 +907,10 @@ void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
     });
 }
 
-void launch_finalize_b(const LevelDesc* L, GridState* S, JobList jl, double rtol, hipStream_t s) {
+void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
+                     int max_cycles, hipStream_t s) {
     if (jl.njobs <= 0) return;
-    hipLaunchKernelGGL(k_finalize_b, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, rtol);
+    hipLaunchKernelGGL(k_finalize, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, mode, rtol, max_cycles);
 }
 
 void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s) {
@@ -831,19 +962,36 @@ void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState
 }
 
 void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
-                     int nblk, hipStream_t s) {
+                     int select, int zero_x, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
-        else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x);
+        else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x);
     });
 }
 
-void launch_finalize_r(const LevelDesc* L, GridState* S, JobList jl, int max_cycles, int count_cycle,
-                       hipStream_t s) {
-    if (jl.njobs <= 0) return;
-    hipLaunchKernelGGL(k_finalize_r, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, max_cycles, count_cycle);
+#define FLD_CG_LAUNCH(kern)                                                                          \
+    if (jl.total <= 0) return;                                                                       \
+    const int g = blocks_for(jl.total, nblk);                                                        \
+    FLD_DISPATCH_DIM(dim, {                                                                          \
+        if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);      \
+        else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl);           \
+    })
+
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                  hipStream_t s) {
+    FLD_CG_LAUNCH(k_cg_rz);
+}
+
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                  hipStream_t s) {
+    FLD_CG_LAUNCH(k_cg_pq);
+}
+
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+                      hipStream_t s) {
+    FLD_CG_LAUNCH(k_cg_update);
 }
 
 void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,

@@ -66,6 +66,7 @@ struct Plan {
     std::vector<int64_t> ncell;                // cells per grid
     DimLists dl[2];                            // [0] = 2D, [1] = 3D
     bool mixed = false;
+    bool krylov = true;
 
     // workspace layout (byte offsets)
     size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_ctrl = 0;
@@ -73,7 +74,9 @@ struct Plan {
     static constexpr int kExSlots = 4;
     struct FieldOff {
         size_t x = 0, b = 0, w[3] = {0, 0, 0}, x32 = 0, b32 = 0, w32[3] = {0, 0, 0}, part = 0, scratch = 0;
+        size_t X = 0, B0 = 0, R = 0, P[2] = {0, 0}, Q = 0;
         bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
+        bool lev0 = false, has_cg = false;
     };
     std::vector<FieldOff> foff;                // per level
 
@@ -150,6 +153,8 @@ int validate_opts(const fld_opts& o) {
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return FLD_ERR_INVALID_ARG;
     if (o.max_cycles < 1 || o.max_cycles > 100000) return FLD_ERR_INVALID_ARG;
     if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 16 || o.nu2 > 16) return FLD_ERR_INVALID_ARG;
+    if (o.krylov && o.nu1 != o.nu2) return FLD_ERR_INVALID_ARG;   // CG needs a symmetric V-cycle
+    if (o.krylov != 0 && o.krylov != 1) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
 
@@ -266,32 +271,48 @@ static void layout(Plan& p) {
         for (auto& l : D.prolong) place_list(l);
     }
     p.foff.assign(NL, Plan::FieldOff{});
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     for (size_t li = 0; li < NL; ++li) {
         const LevelDesc& d = p.levels[li];
         Plan::FieldOff& f = p.foff[li];
         const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
         const bool lev0 = d.level == 0;
-        // FP64: weights at every level (coarse weights derive from them); x and b at
-        // level 0 always, and at every level in FP64 mode.
-        for (int a = 0; a < d.ndim; ++a) { f.w[a] = off; off = align_up(off + n * 8); }
-        if (lev0 || !p.mixed) {
-            f.has_x = f.has_b = true;
-            f.x = off; off = align_up(off + n * 8);
-            f.b = off; off = align_up(off + n * 8);
-        }
-        if (p.mixed) {
-            f.has_x32 = true;
-            f.x32 = off; off = align_up(off + n * 4);
-            f.b32 = off; off = align_up(off + n * 4);
-            for (int a = 0; a < d.ndim; ++a) { f.w32[a] = off; off = align_up(off + n * 4); }
-        }
+        // FP64 weights at every level (coarse weights derive from them)
+        for (int a = 0; a < d.ndim; ++a) f.w[a] = take(n * 8);
         if (lev0) {
+            // outer FP64 iteration: iterate, right-hand side, residual (+ CG vectors)
+            f.lev0 = true;
+            f.X = take(n * 8);
+            f.B0 = take(n * 8);
+            f.R = take(n * 8);
+            if (p.krylov) {
+                f.has_cg = true;
+                f.P[0] = take(n * 8);
+                f.P[1] = take(n * 8);
+                f.Q = take(n * 8);
+            }
             f.has_part = true;
-            f.part = off; off = align_up(off + 2 * (size_t)cell_tiles(d.n) * 8);
+            f.part = take(2 * (size_t)cell_tiles(d.n) * 8);
+        }
+        if (!p.mixed) {
+            f.has_x = f.has_b = true;
+            if (lev0) {
+                // the V-cycle runs on (Z, R) under CG and on (X, B0) otherwise
+                f.x = p.krylov ? take(n * 8) : f.X;
+                f.b = p.krylov ? f.R : f.B0;
+            } else {
+                f.x = take(n * 8);
+                f.b = take(n * 8);
+            }
+        } else {
+            f.has_x32 = true;
+            f.x32 = take(n * 4);
+            f.b32 = take(n * 4);
+            for (int a = 0; a < d.ndim; ++a) f.w32[a] = take(n * 4);
         }
         if (d.coarse < 0 && n > (size_t)kCoarseMaxLDS) {
             f.has_scratch = true;
-            f.scratch = off; off = align_up(off + 4 * n * 8);
+            f.scratch = take(4 * n * 8);
         }
     }
     p.ws_bytes = off;
@@ -319,9 +340,19 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
                 launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
             }
         }
-        if (p.mixed) launch_correct(dim, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
-        launch_residual(dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
-        launch_finalize_r(p.dL, p.dS, D.l0_cell.dev, p.opts.max_cycles, 1, s);
+        const JobList& l0 = D.l0_cell.dev;
+        if (p.krylov) {
+            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
+            launch_finalize(p.dL, p.dS, l0, FIN_RZ, p.opts.rtol, p.opts.max_cycles, s);
+            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
+            launch_finalize(p.dL, p.dS, l0, FIN_PQ, p.opts.rtol, p.opts.max_cycles, s);
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
+            launch_finalize(p.dL, p.dS, l0, FIN_CG, p.opts.rtol, p.opts.max_cycles, s);
+        } else {
+            if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, p.nblk, s);
+            launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, p.nblk, s);
+            launch_finalize(p.dL, p.dS, l0, FIN_R_CYCLE, p.opts.rtol, p.opts.max_cycles, s);
+        }
     }
 }
 
@@ -362,6 +393,13 @@ static int bind(Plan& p, void* dev, size_t bytes) {
         d.b32 = f.has_x32 ? reinterpret_cast<float*>(ws + f.b32) : nullptr;
         d.part = f.has_part ? reinterpret_cast<double*>(ws + f.part) : nullptr;
         d.scratch = f.has_scratch ? reinterpret_cast<double*>(ws + f.scratch) : nullptr;
+        auto dp = [&](size_t o, bool has) { return has ? reinterpret_cast<double*>(ws + o) : nullptr; };
+        d.X = dp(f.X, f.lev0);
+        d.B0 = dp(f.B0, f.lev0);
+        d.R = dp(f.R, f.lev0);
+        d.P[0] = dp(f.P[0], f.has_cg);
+        d.P[1] = dp(f.P[1], f.has_cg);
+        d.Q = dp(f.Q, f.has_cg);
     }
     FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
     std::vector<GridState> st(p.ngrids());
@@ -417,13 +455,15 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         p.hIO[g].dt = dt[g];
     }
     FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(StepIO), hipMemcpyHostToDevice, s));
+    const int zero_x = (p.krylov || p.mixed) ? 1 : 0;
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
-        launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
-        launch_finalize_b(p.dL, p.dS, D.l0_cell.dev, p.opts.rtol, s);
+        const JobList& l0 = D.l0_cell.dev;
+        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+        launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
         for (int d = 0; d < D.maxdepth; ++d) launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
-        launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
-        launch_finalize_r(p.dL, p.dS, D.l0_cell.dev, p.opts.max_cycles, 0, s);
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, p.nblk, s);
+        launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
     }
     FLD_HIP(hipGetLastError());
     // V-cycles in rounds: each round replays `burst` cycles, then reads back how
@@ -443,6 +483,18 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         launch_count(p.dS, G, p.dCtrl, s);
         FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         FLD_HIP(hipStreamSynchronize(s));
+        if (p.hCtrl->nactive == 0 && p.krylov) {
+            // CG stopped on its recursive residual: confirm on the true FP64 residual
+            // and restart the grids whose true residual is still above the target
+            for (auto& D : p.dl) {
+                if (D.l0_cell.empty()) continue;
+                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, p.nblk, s);
+                launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
+            }
+            launch_count(p.dS, G, p.dCtrl, s);
+            FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+            FLD_HIP(hipStreamSynchronize(s));
+        }
         if (p.hCtrl->nactive == 0) break;
         burst = std::max(1, burst / 2);
     }
@@ -536,7 +588,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level) launch_smooth(D.dim, p.mixed, p.dL, p.dS, D.smooth[level].dev, 0, p.nblk, s);
                     break;
                 case FLD_KERNEL_RESIDUAL:
-                    launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.nblk, s);
+                    launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 0, 0, p.nblk, s);
                     break;
                 case FLD_KERNEL_RESTRICT:
                     if (has_level) launch_restrict(D.dim, p.mixed, p.dL, p.dS, D.restrict_[level].dev, p.nblk, s);
@@ -625,6 +677,7 @@ void fld_opts_default(fld_opts* o) {
     o->nu2 = 2;
     o->use_graph = 1;
     o->autotune = 0;
+    o->krylov = 1;
 }
 
 void fld_gas_default(fld_gas* g) {
@@ -649,6 +702,7 @@ int32_t fld_plan_create(const fld_grid* grids, int32_t ngrids, const fld_opts* o
         if (hipGetDevice(&p.device) != hipSuccess) p.device = 0;
         p.opts = *opts;
         p.mixed = opts->precision == FLD_PREC_MIXED;
+        p.krylov = opts->krylov != 0;
         p.grids.assign(grids, grids + ngrids);
         for (auto& g : p.grids)
             if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
@@ -737,7 +791,7 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
         for (auto& D : p.dl) {
             if (D.l0_cell.empty()) continue;
             fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
-            fld::launch_finalize_b(p.dL, p.dS, D.l0_cell.dev, p.opts.rtol, s);
+            fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
             for (int d = 0; d < D.maxdepth; ++d)
                 fld::launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
         }

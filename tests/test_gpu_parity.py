@@ -114,10 +114,11 @@ def test_face_weights_full_size_config2():
 
 # ------------------------------------------------------------------ one diffusion step
 @pytest.mark.parametrize("precision", [0, 1])
-def test_config1_step_matches_lu(precision):
+@pytest.mark.parametrize("krylov", [1, 0])
+def test_config1_step_matches_lu(precision, krylov):
     g = W.pulse_2d()
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="lu")
-    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g))
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st)
     assert st["q_b"] == pytest.approx(O.q_b(g.E), rel=1e-12)
@@ -128,10 +129,11 @@ def test_config1_step_matches_lu(precision):
                                       ((130, 66), 2e-3), ((20, 12, 8), 5e-3), ((24, 24, 24), 1e-2),
                                       ((9, 7, 5), 1e-2)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_ragged_and_odd_grids_match_oracle(shape, dt, precision):
+@pytest.mark.parametrize("krylov", [1, 0])
+def test_ragged_and_odd_grids_match_oracle(shape, dt, precision, krylov):
     g = W.random_grid(shape, 555000 + 7 * sum(shape), dt=dt)
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, method="auto")
-    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g))
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st, info)
 
@@ -159,11 +161,31 @@ def test_in_place_output():
     assert rc == 0 and rel_l2(x, x_or) <= 1e-10
 
 
-def test_graph_and_direct_launches_agree_bitwise():
+@pytest.mark.parametrize("krylov", [1, 0])
+def test_graph_and_direct_launches_agree_bitwise(krylov):
     g = W.random_grid((128, 96), 77000, dt=5e-3)
-    (xa,), (sa,), _ = run_step([g], use_graph=1)
-    (xb,), (sb,), _ = run_step([g], use_graph=0)
+    (xa,), (sa,), _ = run_step([g], use_graph=1, krylov=krylov)
+    (xb,), (sb,), _ = run_step([g], use_graph=0, krylov=krylov)
     assert np.array_equal(xa, xb) and sa["cycles"] == sb["cycles"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stiff_trajectory_converges_quickly(precision):
+    """A config-4 grid (288^2, dt = 9.2e-3, coarsest 9^2) whose third step sharpens D
+    enough that plain V-cycles need ~30 iterations; CG with the V-cycle stays <= 16."""
+    n, dt = W.c4_layout()[118]
+    g = W.c4_grid(118, n, dt)
+    E = dev(g.E)
+    K = dev(g.kappa_rho)
+    plan = fld.Plan([g.E.shape], h=[g.h], precision=precision)
+    for step in range(3):
+        E_in = E.cpu().numpy()
+        rc, (st,) = plan.step([E], [K], [E], [g.dt])
+        assert rc == 0 and st["cycles"] <= 16, (step, st)
+    x = E.cpu().numpy()
+    x_or, _ = O.diffusion_step(E_in, g.kappa_rho, g.dt, g.h)
+    assert rel_l2(x, x_or) <= 1e-10 * O.q_b(E_in) * 1.01
+    plan.close()
 
 
 def test_reported_residual_is_the_oracle_residual():
