@@ -125,8 +125,8 @@ typedef struct fld_plan_s* fld_plan_t;
 typedef struct fld_level_view {
     int32_t ndim;
     int32_t n[3];
-    double* x;            /* FP64 solution / correction                             */
-    double* b;            /* FP64 right-hand side                                   */
+    double* x;            /* FP64: level 0 the iterate E^{n+1}, coarser the correction */
+    double* b;            /* FP64: level 0 E^n, coarser the restricted residual      */
     double* w[3];         /* FP64 face weights                                      */
     float*  x32;
     float*  b32;

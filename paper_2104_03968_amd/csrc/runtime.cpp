@@ -764,8 +764,9 @@ int32_t fld_plan_level_view(fld_plan_t plan, int32_t g, int32_t level, fld_level
         out->w[a] = d.w[a];
         out->w32[a] = d.w32[a];
     }
-    out->x = d.x;
-    out->b = d.b;
+    // level 0: the step's iterate and right-hand side; coarser: the V-cycle arrays
+    out->x = level == 0 ? d.X : d.x;
+    out->b = level == 0 ? d.B0 : d.b;
     out->x32 = d.x32;
     out->b32 = d.b32;
     return FLD_OK;

@@ -78,15 +78,20 @@ def test_hierarchy_levels_and_workspace_scaling():
         h = fld.fld_plan_create([fld.make_grid(n)], fld.fld_opts_default())
         assert fld.fld_plan_levels(h, 0) == nl, n
         fld.fld_plan_destroy(h)
-    # workspace: FP64 ~ (2 + d) arrays * 8 B * 4/3 per cell in 2D; mixed adds FP32 copies
-    h64 = fld.fld_plan_create([fld.make_grid((1024, 1024))], fld.fld_opts_default())
-    h32 = fld.fld_plan_create([fld.make_grid((1024, 1024))], fld.fld_opts_default(precision=1))
-    b64, b32 = fld.fld_plan_workspace_bytes(h64), fld.fld_plan_workspace_bytes(h32)
+    # workspace, 2D FP64: level 0 holds w_x, w_y, X, B0, R (+ P0, P1, Q, Z under CG), and
+    # the coarse levels x, b, w_x, w_y on N/3 cells in total
     N = 1024 * 1024
-    assert 4 * 8 * N <= b64 <= 4 * 8 * N * 1.45
-    assert b32 > b64
-    for h in (h64, h32):
+    sizes = {}
+    for kw in (dict(), dict(krylov=0), dict(precision=1), dict(precision=1, krylov=0)):
+        h = fld.fld_plan_create([fld.make_grid((1024, 1024))], fld.fld_opts_default(**kw))
+        sizes[tuple(kw.items())] = fld.fld_plan_workspace_bytes(h) / N
         fld.fld_plan_destroy(h)
+    cg64, mg64 = sizes[()], sizes[(("krylov", 0),)]
+    assert 8 * 9 + 32 / 3 <= cg64 <= 8 * 9 + 32 / 3 + 1
+    assert 8 * 5 + 32 / 3 <= mg64 <= 8 * 5 + 32 / 3 + 1
+    cg32 = sizes[(("precision", 1),)]
+    # FP64 w_x, w_y, X, B0, R, P0, P1, Q at level 0, FP64 coarse weights, FP32 hierarchy
+    assert 8 * 8 + 16 / 3 + 16 * 4 / 3 <= cg32 <= 8 * 8 + 16 / 3 + 16 * 4 / 3 + 1
 
 
 def test_batched_plan_workspace_is_sum_of_parts():
