@@ -135,6 +135,15 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
                     int nblk, hipStream_t s);
 void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          hipStream_t s);
+// Tail: one workgroup per job runs the V-cycle of every level from the job's level down
+// in `smem` bytes of LDS.  prepare_tail raises the kernel's dynamic-LDS limit (call once,
+// outside stream capture).  plain64: level-0 tails iterate from the current x.
+int prepare_tail(int dim, bool fp32, size_t smem);
+void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
+                 int nu1, int nu2, int plain64, hipStream_t s);
+// LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to
+// `levels` levels: x, b and DIM face arrays per level plus one coarsest vector.
+constexpr size_t kTailLdsBudget = 150 * 1024;
 // select: 0 = active grids, 1 = grids whose status is FLD_OK (convergence check).
 // zero_x: also clear the level-0 V-cycle iterate (FP64 or FP32 by `mixed`); mixed also
 // writes the FP32 right-hand side.

@@ -470,6 +470,102 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
     return dg;
 }
 
+// Block-wide Jacobi-preconditioned CG on one level of up to kCoarseMaxLDS cells.
+// Starts from x (read from `x` when warm, else zero), runs until the residual
+// falls by 1e-6 (or maxit iterations) and writes the result back to `x`.  The
+// search direction lives in p_sh (LDS); x, r and the inverse diagonal live in
+// registers of the thread owning the cell.  w, b and x may be global or LDS.
+template <int DIM, typename T>
+__device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
+                         bool warm, T* p_sh, double* red) {
+    const int ncell = n[0] * n[1] * n[2];
+    const int maxit = ncell < 2000 ? ncell + 4 : 2000;
+    const double tol2 = 1e-12;                 // (1e-6)^2 relative
+    T xr[kCoarseCPT], r[kCoarseCPT], dinv[kCoarseCPT];
+#pragma unroll
+    for (int m = 0; m < kCoarseCPT; ++m) {
+        const int c = threadIdx.x + m * kCoarseThreads;
+        xr[m] = T(0);
+        r[m] = T(0);
+        dinv[m] = T(0);
+        if (c < ncell) {
+            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c);
+            xr[m] = warm ? x[c] : T(0);
+            p_sh[c] = xr[m];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kCoarseCPT; ++m) {
+        const int c = threadIdx.x + m * kCoarseThreads;
+        if (c < ncell) {
+            T dg;
+            r[m] = b[c];
+            if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg);
+        }
+    }
+    __syncthreads();
+    double rz = 0.0, rr0 = 0.0;
+#pragma unroll
+    for (int m = 0; m < kCoarseCPT; ++m) {
+        const int c = threadIdx.x + m * kCoarseThreads;
+        if (c < ncell) {
+            const T z = r[m] * dinv[m];
+            p_sh[c] = z;
+            rz += (double)r[m] * (double)z;
+            rr0 += (double)r[m] * (double)r[m];
+        }
+    }
+    block_sum2<kCoarseThreads>(rz, rr0, red);     // also orders the p_sh writes
+    if (rr0 > 0.0) {
+        for (int it = 0; it < maxit; ++it) {
+            T q[kCoarseCPT];
+            double pq = 0.0, unused = 0.0;
+#pragma unroll
+            for (int m = 0; m < kCoarseCPT; ++m) {
+                const int c = threadIdx.x + m * kCoarseThreads;
+                q[m] = T(0);
+                if (c < ncell) {
+                    T dg;
+                    q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg);
+                    pq += (double)p_sh[c] * (double)q[m];
+                }
+            }
+            block_sum2<kCoarseThreads>(pq, unused, red);
+            if (!(pq > 0.0)) break;
+            const T alpha = (T)(rz / pq);
+            double rz_new = 0.0, rr = 0.0;
+#pragma unroll
+            for (int m = 0; m < kCoarseCPT; ++m) {
+                const int c = threadIdx.x + m * kCoarseThreads;
+                if (c < ncell) {
+                    xr[m] += alpha * p_sh[c];
+                    r[m] -= alpha * q[m];
+                    const T z = r[m] * dinv[m];
+                    rz_new += (double)r[m] * (double)z;
+                    rr += (double)r[m] * (double)r[m];
+                }
+            }
+            block_sum2<kCoarseThreads>(rz_new, rr, red);   // every thread is done reading p_sh
+            if (rr <= tol2 * rr0) break;
+            const T beta = (T)(rz_new / rz);
+            rz = rz_new;
+#pragma unroll
+            for (int m = 0; m < kCoarseCPT; ++m) {
+                const int c = threadIdx.x + m * kCoarseThreads;
+                if (c < ncell) p_sh[c] = r[m] * dinv[m] + beta * p_sh[c];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kCoarseCPT; ++m) {
+        const int c = threadIdx.x + m * kCoarseThreads;
+        if (c < ncell) x[c] = xr[m];
+    }
+    __syncthreads();
+}
+
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kCoarseThreads)
 k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
@@ -483,99 +579,15 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     const T* w2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
     T* xg = Arr<T>::x(d);
     const T* bg = Arr<T>::b(d);
-    const int maxit = ncell < 2000 ? ncell + 4 : 2000;
-    const double tol2 = 1e-12;                 // (1e-6)^2 relative
     // The finest level of a single-level FP64 grid holds the solution itself: iterate
     // from it.  Every other coarsest level solves for a correction from zero.
     const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
-        T x[kCoarseCPT], r[kCoarseCPT], dinv[kCoarseCPT];
-        double rz = 0.0, rr0 = 0.0;
-#pragma unroll
-        for (int m = 0; m < kCoarseCPT; ++m) {
-            const int c = threadIdx.x + m * kCoarseThreads;
-            x[m] = T(0);
-            r[m] = T(0);
-            dinv[m] = T(0);
-            if (c < ncell) {
-                r[m] = bg[c];
-                dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, d.n, c);
-                if (warm) {
-                    x[m] = xg[c];
-                    p_sh[c] = x[m];
-                }
-            }
-        }
-        if (warm) {                                  // r = b - A x from the current iterate
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < kCoarseCPT; ++m) {
-                const int c = threadIdx.x + m * kCoarseThreads;
-                if (c < ncell) {
-                    T dg;
-                    r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, d.n, c, dg);
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int m = 0; m < kCoarseCPT; ++m) {
-            const int c = threadIdx.x + m * kCoarseThreads;
-            if (c < ncell) {
-                const T z = r[m] * dinv[m];
-                p_sh[c] = z;
-                rz += (double)r[m] * (double)z;
-                rr0 += (double)r[m] * (double)r[m];
-            }
-        }
-        block_sum2<kCoarseThreads>(rz, rr0, red);     // also orders the p_sh writes
-        if (rr0 > 0.0) {
-            for (int it = 0; it < maxit; ++it) {
-                T q[kCoarseCPT];
-                double pq = 0.0, unused = 0.0;
-#pragma unroll
-                for (int m = 0; m < kCoarseCPT; ++m) {
-                    const int c = threadIdx.x + m * kCoarseThreads;
-                    q[m] = T(0);
-                    if (c < ncell) {
-                        T dg;
-                        q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, d.n, c, dg);
-                        pq += (double)p_sh[c] * (double)q[m];
-                    }
-                }
-                block_sum2<kCoarseThreads>(pq, unused, red);
-                const T alpha = (T)(rz / pq);
-                double rz_new = 0.0, rr = 0.0;
-#pragma unroll
-                for (int m = 0; m < kCoarseCPT; ++m) {
-                    const int c = threadIdx.x + m * kCoarseThreads;
-                    if (c < ncell) {
-                        x[m] += alpha * p_sh[c];
-                        r[m] -= alpha * q[m];
-                        const T z = r[m] * dinv[m];
-                        rz_new += (double)r[m] * (double)z;
-                        rr += (double)r[m] * (double)r[m];
-                    }
-                }
-                block_sum2<kCoarseThreads>(rz_new, rr, red);   // every thread is done reading p_sh
-                if (rr <= tol2 * rr0) break;
-                const T beta = (T)(rz_new / rz);
-                rz = rz_new;
-#pragma unroll
-                for (int m = 0; m < kCoarseCPT; ++m) {
-                    const int c = threadIdx.x + m * kCoarseThreads;
-                    if (c < ncell) p_sh[c] = r[m] * dinv[m] + beta * p_sh[c];
-                }
-                __syncthreads();
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < kCoarseCPT; ++m) {
-            const int c = threadIdx.x + m * kCoarseThreads;
-            if (c < ncell) xg[c] = x[m];
-        }
+        block_cg<DIM, T>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red);
         return;
     }
+    const int maxit = 2000;
+    const double tol2 = 1e-12;
     // Large coarsest level: vectors in workspace scratch (x lives in the level itself).
     T* r = reinterpret_cast<T*>(d.scratch);
     T* p = r + ncell;
@@ -607,6 +619,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
             pq += (double)p[c] * (double)qc;
         }
         block_sum2<kCoarseThreads>(pq, unused, red);
+        if (!(pq > 0.0)) break;
         const T alpha = (T)(rz / pq);
         double rz_new = 0.0, rr = 0.0;
         for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
@@ -622,6 +635,143 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
         rz = rz_new;
         for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) p[c] = r[c] * dv[c] + beta * p[c];
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tail: one workgroup per grid runs the whole V-cycle below a level T out of
+// LDS -- every tail level's x, b and face weights, plus the coarsest CG's
+// search direction -- so the coarse levels cost one launch instead of a few
+// per level.  The restriction from level T-1 left b_T in global memory and the
+// prolongation to level T-1 reads the correction x_T back from global memory.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TailLevel {
+    int32_t n[3];
+    int32_t ncell;
+    T* x;
+    T* b;
+    T* w[3];
+};
+constexpr int kMaxTail = 16;
+
+template <int DIM, typename T>
+__device__ __forceinline__ void tl_half_sweep(const TailLevel<T>& lv, int color) {
+    const int sy = lv.n[0], sz = lv.n[0] * lv.n[1];
+    for (int c = threadIdx.x; c < lv.ncell; c += kCoarseThreads) {
+        int i, j, k;
+        cell_coords<DIM, T>(lv.n, c, i, j, k);
+        if (((i + j + k) & 1) != color) continue;
+        T s = lv.b[c], dg = T(1);
+        if (i > 0) { const T w = lv.w[0][c]; s += w * lv.x[c - 1]; dg += w; }
+        if (i + 1 < lv.n[0]) { const T w = lv.w[0][c + 1]; s += w * lv.x[c + 1]; dg += w; }
+        if (j > 0) { const T w = lv.w[1][c]; s += w * lv.x[c - sy]; dg += w; }
+        if (j + 1 < lv.n[1]) { const T w = lv.w[1][c + sy]; s += w * lv.x[c + sy]; dg += w; }
+        if (DIM == 3) {
+            if (k > 0) { const T w = lv.w[2][c]; s += w * lv.x[c - sz]; dg += w; }
+            if (k + 1 < lv.n[2]) { const T w = lv.w[2][c + sz]; s += w * lv.x[c + sz]; dg += w; }
+        }
+        lv.x[c] = s / dg;
+    }
+    __syncthreads();
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kCoarseThreads)
+k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int nu1, int nu2,
+       int plain64) {
+    extern __shared__ __align__(16) unsigned char tail_smem[];
+    __shared__ TailLevel<T> tl[kMaxTail];
+    __shared__ double red[2 * kCoarseThreads / 64];
+    __shared__ int ntl;
+    const int first = jl.levels[blockIdx.x];
+    if (!S[L[first].grid].active) return;
+    if (threadIdx.x == 0) {
+        T* base = reinterpret_cast<T*>(tail_smem);
+        int m = 0;
+        for (int li = first; li >= 0 && m < kMaxTail; li = L[li].coarse, ++m) {
+            const LevelDesc& d = L[li];
+            TailLevel<T>& t = tl[m];
+            t.n[0] = d.n[0]; t.n[1] = d.n[1]; t.n[2] = d.n[2];
+            t.ncell = d.n[0] * d.n[1] * d.n[2];
+            t.x = base; base += t.ncell;
+            t.b = base; base += t.ncell;
+            for (int a = 0; a < 3; ++a) {
+                t.w[a] = (a < DIM) ? base : nullptr;
+                if (a < DIM) base += t.ncell;
+            }
+        }
+        ntl = m;
+    }
+    __syncthreads();
+    const int nl = ntl;
+    T* p_sh = tl[nl - 1].w[DIM - 1] + tl[nl - 1].ncell;   // the coarsest CG's search direction
+    // load weights of every tail level, b and (warm) x of the first
+    {
+        int li = first;
+        for (int m = 0; m < nl; ++m, li = L[li].coarse) {
+            const LevelDesc& d = L[li];
+            const TailLevel<T>& t = tl[m];
+            for (int a = 0; a < DIM; ++a) {
+                const T* src = Arr<T>::w(d, a);
+                for (int c = threadIdx.x; c < t.ncell; c += kCoarseThreads) t.w[a][c] = src[c];
+            }
+            if (m == 0) {
+                const T* bsrc = Arr<T>::b(d);
+                const T* xsrc = Arr<T>::x(d);
+                const bool warm = plain64 && d.level == 0;
+                for (int c = threadIdx.x; c < t.ncell; c += kCoarseThreads) {
+                    t.b[c] = bsrc[c];
+                    t.x[c] = warm ? xsrc[c] : T(0);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // descend
+    for (int m = 0; m + 1 < nl; ++m) {
+        const TailLevel<T>& f = tl[m];
+        const TailLevel<T>& cT = tl[m + 1];
+        for (int it = 0; it < nu1; ++it) {
+            tl_half_sweep<DIM, T>(f, 0);
+            tl_half_sweep<DIM, T>(f, 1);
+        }
+        for (int c = threadIdx.x; c < cT.ncell; c += kCoarseThreads) {
+            int I, J, K;
+            cell_coords<DIM, T>(cT.n, c, I, J, K);
+            T sum = T(0);
+#pragma unroll
+            for (int q = 0; q < (1 << DIM); ++q)
+                sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
+                                           2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0);
+            cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
+            cT.x[c] = T(0);
+        }
+        __syncthreads();
+    }
+    // coarsest: CG from the current x (zero unless the grid has a single level)
+    {
+        const TailLevel<T>& cT = tl[nl - 1];
+        block_cg<DIM, T>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
+    }
+    // ascend
+    for (int m = nl - 2; m >= 0; --m) {
+        const TailLevel<T>& f = tl[m];
+        const TailLevel<T>& cT = tl[m + 1];
+        for (int c = threadIdx.x; c < f.ncell; c += kCoarseThreads) {
+            int i, j, k;
+            cell_coords<DIM, T>(f.n, c, i, j, k);
+            f.x[c] += cT.x[(i >> 1) + cT.n[0] * ((j >> 1) + cT.n[1] * (k >> 1))];
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) {
+            tl_half_sweep<DIM, T>(f, 1);
+            tl_half_sweep<DIM, T>(f, 0);
+        }
+    }
+    {
+        T* xdst = Arr<T>::x(L[first]);
+        for (int c = threadIdx.x; c < tl[0].ncell; c += kCoarseThreads) xdst[c] = tl[0].x[c];
     }
 }
 
@@ -949,6 +1099,24 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+int prepare_tail(int dim, bool fp32, size_t smem) {
+    hipError_t e;
+    if (dim == 3) e = fp32 ? hipFuncSetAttribute((const void*)k_tail<3, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)
+                           : hipFuncSetAttribute((const void*)k_tail<3, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    else e = fp32 ? hipFuncSetAttribute((const void*)k_tail<2, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)
+                  : hipFuncSetAttribute((const void*)k_tail<2, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    return e == hipSuccess ? 0 : -1;
+}
+
+void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
+                 int nu1, int nu2, int plain64, hipStream_t s) {
+    if (jl.njobs <= 0) return;
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_tail<D, float>), dim3(jl.njobs), dim3(kCoarseThreads), smem, s, L, S, jl, nu1, nu2, plain64);
+        else hipLaunchKernelGGL((k_tail<D, double>), dim3(jl.njobs), dim3(kCoarseThreads), smem, s, L, S, jl, nu1, nu2, plain64);
     });
 }
 

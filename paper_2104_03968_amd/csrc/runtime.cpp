@@ -52,7 +52,10 @@ struct DimLists {
     std::vector<HostList> smooth;              // per depth, smoother tiles
     std::vector<HostList> restrict_;           // per depth, cell tiles of the coarse level
     std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
-    HostList coarsest;                         // one block per grid
+    std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
+    HostList coarsest;                         // coarsest level of grids without a tail
+    HostList tail;                             // first tail level of grids with a tail
+    size_t tail_smem = 0;                      // LDS bytes of the largest tail
     int maxdepth = 0;
 };
 
@@ -64,6 +67,7 @@ struct Plan {
     std::vector<int32_t> level0;               // LevelDesc index of each grid's level 0
     std::vector<int32_t> nlev;                 // levels per grid
     std::vector<int64_t> ncell;                // cells per grid
+    std::vector<int32_t> tail_lev;             // first tail level of each grid (-1: no tail)
     DimLists dl[2];                            // [0] = 2D, [1] = 3D
     bool mixed = false;
     bool krylov = true;
@@ -214,14 +218,46 @@ static void build_levels(Plan& p) {
     }
 }
 
+// First level of each grid's LDS tail: the finest level from which every coarser
+// level (x, b, d face arrays) plus the coarsest CG's search direction fits the
+// LDS budget, with a coarsest level small enough for the block CG.
+static size_t tail_bytes(const Plan& p, int g, int t) {
+    const int l0 = p.level0[g], L = p.nlev[g];
+    const int dim = p.grids[g].ndim;
+    const size_t word = p.mixed ? 4 : 8;
+    size_t cells = 0;
+    for (int l = t; l < L; ++l) {
+        const LevelDesc& d = p.levels[l0 + l];
+        cells += (size_t)(2 + dim) * d.n[0] * d.n[1] * d.n[2];
+    }
+    const LevelDesc& c = p.levels[l0 + L - 1];
+    cells += (size_t)c.n[0] * c.n[1] * c.n[2];
+    return cells * word;
+}
+
+static void choose_tails(Plan& p) {
+    p.tail_lev.assign(p.ngrids(), -1);
+    for (int g = 0; g < p.ngrids(); ++g) {
+        const int L = p.nlev[g];
+        const LevelDesc& c = p.levels[p.level0[g] + L - 1];
+        if ((int64_t)c.n[0] * c.n[1] * c.n[2] > kCoarseMaxLDS) continue;
+        for (int t = 0; t < L; ++t) {
+            if (tail_bytes(p, g, t) <= kTailLdsBudget) { p.tail_lev[g] = t; break; }
+        }
+    }
+}
+
 static void build_lists(Plan& p) {
+    choose_tails(p);
     for (int di = 0; di < 2; ++di) {
         DimLists& D = p.dl[di];
         D = DimLists{};
         D.dim = di + 2;
+        // wide (grid-parallel) depths of grid g: levels below its tail, or all but the coarsest
+        auto wide = [&](int g) { return p.tail_lev[g] >= 0 ? p.tail_lev[g] : p.nlev[g] - 1; };
         int maxdepth = 0;
         for (int g = 0; g < p.ngrids(); ++g)
-            if (p.grids[g].ndim == D.dim) maxdepth = std::max(maxdepth, p.nlev[g] - 1);
+            if (p.grids[g].ndim == D.dim) maxdepth = std::max(maxdepth, wide(g));
         D.maxdepth = maxdepth;
         D.smooth.resize(maxdepth);
         D.restrict_.resize(maxdepth);
@@ -230,15 +266,21 @@ static void build_lists(Plan& p) {
             if (p.grids[g].ndim != D.dim) continue;
             const int l0 = p.level0[g];
             D.l0_cell.levels.push_back(l0);
-            for (int dpt = 0; dpt < p.nlev[g] - 1; ++dpt) {
+            for (int dpt = 0; dpt < wide(g); ++dpt) {
                 D.smooth[dpt].levels.push_back(l0 + dpt);
                 D.restrict_[dpt].levels.push_back(l0 + dpt);
                 D.prolong[dpt].levels.push_back(l0 + dpt);
             }
-            D.coarsest.levels.push_back(l0 + p.nlev[g] - 1);
+            if (p.tail_lev[g] >= 0) {
+                D.tail.levels.push_back(l0 + p.tail_lev[g]);
+                D.tail_smem = std::max(D.tail_smem, tail_bytes(p, g, p.tail_lev[g]));
+            } else {
+                D.coarsest.levels.push_back(l0 + p.nlev[g] - 1);
+            }
         }
         finish_list(D.l0_cell, p.levels, tiles_cell);
         finish_list(D.coarsest, p.levels, tiles_one);
+        finish_list(D.tail, p.levels, tiles_one);
         for (int dpt = 0; dpt < maxdepth; ++dpt) {
             finish_list(D.smooth[dpt], p.levels, tiles_smooth);
             finish_list(D.prolong[dpt], p.levels, tiles_cell);
@@ -246,6 +288,20 @@ static void build_lists(Plan& p) {
             HostList& r = D.restrict_[dpt];
             r.prefix.assign(1, 0);
             for (int32_t li : r.levels) r.prefix.push_back(r.prefix.back() + cell_tiles(p.levels[p.levels[li].coarse].n));
+        }
+        // coarse face weights are needed on every level, tails included
+        D.coarsen.resize(0);
+        int depth_all = 0;
+        for (int g = 0; g < p.ngrids(); ++g)
+            if (p.grids[g].ndim == D.dim) depth_all = std::max(depth_all, p.nlev[g] - 1);
+        D.coarsen.resize(depth_all);
+        for (int g = 0; g < p.ngrids(); ++g) {
+            if (p.grids[g].ndim != D.dim) continue;
+            for (int dpt = 0; dpt < p.nlev[g] - 1; ++dpt) D.coarsen[dpt].levels.push_back(p.level0[g] + dpt);
+        }
+        for (auto& c : D.coarsen) {
+            c.prefix.assign(1, 0);
+            for (int32_t li : c.levels) c.prefix.push_back(c.prefix.back() + cell_tiles(p.levels[p.levels[li].coarse].n));
         }
     }
 }
@@ -266,6 +322,8 @@ static void layout(Plan& p) {
     for (auto& D : p.dl) {
         place_list(D.l0_cell);
         place_list(D.coarsest);
+        place_list(D.tail);
+        for (auto& l : D.coarsen) place_list(l);
         for (auto& l : D.smooth) place_list(l);
         for (auto& l : D.restrict_) place_list(l);
         for (auto& l : D.prolong) place_list(l);
@@ -332,6 +390,8 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             }
             launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
         }
+        launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2,
+                    (!p.krylov && !p.mixed) ? 1 : 0, s);
         launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
         for (int d = D.maxdepth - 1; d >= 0; --d) {
             launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
@@ -423,6 +483,12 @@ static int bind(Plan& p, void* dev, size_t bytes) {
         int rc;
         if ((rc = upload(D.l0_cell)) != FLD_OK) return rc;
         if ((rc = upload(D.coarsest)) != FLD_OK) return rc;
+        if ((rc = upload(D.tail)) != FLD_OK) return rc;
+        for (auto& l : D.coarsen) if ((rc = upload(l)) != FLD_OK) return rc;
+        if (!D.tail.empty() && prepare_tail(D.dim, p.mixed, D.tail_smem) != 0) {
+            g_last_error = "hipFuncSetAttribute(max dynamic LDS) failed for the tail kernel";
+            return FLD_ERR_HIP;
+        }
         for (auto& l : D.smooth) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.restrict_) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.prolong) if ((rc = upload(l)) != FLD_OK) return rc;
@@ -461,7 +527,7 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         const JobList& l0 = D.l0_cell.dev;
         launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
         launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
-        for (int d = 0; d < D.maxdepth; ++d) launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
+        for (auto& c : D.coarsen) launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
         launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, p.nblk, s);
         launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
     }
@@ -793,8 +859,7 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
             if (D.l0_cell.empty()) continue;
             fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
             fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
-            for (int d = 0; d < D.maxdepth; ++d)
-                fld::launch_coarsen(D.dim, p.mixed, p.dL, D.restrict_[d].dev, p.nblk, s);
+            for (auto& c : D.coarsen) fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
         }
         FLD_HIP(hipGetLastError());
         FLD_HIP(hipStreamSynchronize(s));            // staging buffer free on return
