@@ -92,6 +92,10 @@ typedef struct fld_opts {
                              iteration, stopped on the recursive residual and
                              confirmed on the true FP64 residual; 0: plain V-cycle
                              iteration (defect correction in mixed precision) [1]   */
+    int32_t fused;        /* 2D: run each multigrid level as two fused LDS-tiled
+                             kernels (sweeps + restriction, prolongation + sweeps)
+                             when nu1, nu2 are in 1..3; 0: one kernel per colour
+                             sweep and per transfer [1]                             */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -211,6 +215,9 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
 #define FLD_KERNEL_COEFF     4   /* coefficients, on the inputs of the last fld_step        */
 #define FLD_KERNEL_VCYCLE    5   /* one whole V-cycle with its residual test               */
 #define FLD_KERNEL_EXCHANGE  6   /* exchange, on the arrays of the last fld_exchange (alters them) */
+#define FLD_KERNEL_DOWN      7   /* fused 2D: nu1 sweeps + residual + restriction at `level` */
+#define FLD_KERNEL_UP        8   /* fused 2D: prolongation + nu2 sweeps at `level`           */
+#define FLD_KERNEL_TAIL      9   /* the LDS tail of every grid                             */
 
 /* Time `reps` back-to-back launches of one kernel of the plan (launch shape
    as fld_step uses it) between two HIP events on `stream`; *avg_ms receives

@@ -47,6 +47,9 @@ FLD_KERNEL_PROLONG = 3
 FLD_KERNEL_COEFF = 4
 FLD_KERNEL_VCYCLE = 5
 FLD_KERNEL_EXCHANGE = 6
+FLD_KERNEL_DOWN = 7
+FLD_KERNEL_UP = 8
+FLD_KERNEL_TAIL = 9
 
 
 class fld_grid(C.Structure):
@@ -57,7 +60,7 @@ class fld_opts(C.Structure):
     _fields_ = [("c", C.c_double), ("limiter", C.c_int32), ("bc", C.c_int32 * 6),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
-                ("autotune", C.c_int32), ("krylov", C.c_int32)]
+                ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32)]
 
 
 class fld_stats(C.Structure):

@@ -30,6 +30,12 @@ __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
 __host__ __device__ inline int32_t smooth_tiles(const int32_t n[3]) {
     return ((n[0] + kSX - 1) / kSX) * ((n[1] + kTY - 1) / kTY) * n[2];
 }
+// Fused 2D smoother tiles: 64 x 16 interior cells staged in LDS with a halo.
+constexpr int kFX = 64;
+constexpr int kFY = 16;
+__host__ __device__ inline int32_t fused_tiles(const int32_t n[3]) {
+    return ((n[0] + kFX - 1) / kFX) * ((n[1] + kFY - 1) / kFY) * n[2];
+}
 
 struct LevelDesc {
     int32_t n[3];        // nx, ny, nz (nz = 1 in 2D)
@@ -139,6 +145,14 @@ void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState
 // in `smem` bytes of LDS.  prepare_tail raises the kernel's dynamic-LDS limit (call once,
 // outside stream capture).  plain64: level-0 tails iterate from the current x.
 int prepare_tail(int dim, bool fp32, size_t smem);
+// Fused 2D level kernels (nu in 1..3).  down: nu red-black sweeps from a zero (or, with
+// load_x, the stored) iterate, then the residual restricted to the coarse right-hand
+// side; up: add the prolonged coarse correction, then nu black-red sweeps.
+bool fused2_supported(int nu);
+void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
+                  int nblk, hipStream_t s);
+void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int nblk,
+                hipStream_t s);
 void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s);
 // LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to

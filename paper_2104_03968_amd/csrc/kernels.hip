@@ -639,6 +639,151 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
 }
 
 // ---------------------------------------------------------------------------
+// Fused 2D level kernels.  A 64 x 16 tile is staged in LDS with a halo of
+// width HALO and every half sweep is computed on a region that shrinks by one
+// ring, so the tile's cells come out exactly as a global red-black sweep would
+// leave them (the halo recomputes what neighbouring tiles compute).  Cells
+// outside the domain hold x = b = 0 and zero face weights, so updating them
+// keeps them 0 and no boundary test is needed inside the sweep.
+// ---------------------------------------------------------------------------
+template <typename T, int HALO>
+struct Tile2 {
+    static constexpr int W = kFX + 2 * HALO;
+    static constexpr int H = kFY + 2 * HALO;
+    T x[H][W];
+    T b[H][W];
+    T w0[H][W];
+    T w1[H][W];
+};
+
+template <typename T, int HALO>
+__device__ __forceinline__ void tile2_half_sweep(Tile2<T, HALO>& t, int gx0, int gy0, int color, int m) {
+    // update the cells of `color` with local coordinates in [m, W-m) x [m, H-m)
+    const int lane = threadIdx.x & 63;
+    for (int lj = m + (threadIdx.x >> 6); lj < Tile2<T, HALO>::H - m; lj += kBlock / 64) {
+        const int li = m + (((gx0 + m + gy0 + lj) ^ color) & 1) + 2 * lane;
+        if (li >= Tile2<T, HALO>::W - m) continue;
+        const T wl = t.w0[lj][li], wr = t.w0[lj][li + 1], wd = t.w1[lj][li], wu = t.w1[lj + 1][li];
+        const T s = t.b[lj][li] + wl * t.x[lj][li - 1] + wr * t.x[lj][li + 1] + wd * t.x[lj - 1][li] +
+                    wu * t.x[lj + 1][li];
+        t.x[lj][li] = s / (T(1) + wl + wr + wd + wu);
+    }
+    __syncthreads();
+}
+
+template <typename T, int HALO>
+__device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d, int gx0, int gy0,
+                                           bool load_x) {
+    const T* __restrict__ xs = Arr<T>::x(d);
+    const T* __restrict__ bs = Arr<T>::b(d);
+    const T* __restrict__ w0 = Arr<T>::w(d, 0);
+    const T* __restrict__ w1 = Arr<T>::w(d, 1);
+    constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;
+    for (int e = threadIdx.x; e < W * H; e += kBlock) {
+        const int lj = e / W, li = e - lj * W;
+        const int gi = gx0 + li, gj = gy0 + lj;
+        T vx = T(0), vb = T(0), v0 = T(0), v1 = T(0);
+        if (gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1]) {
+            const long idx = gi + (long)d.n[0] * gj;
+            vb = bs[idx];
+            v0 = w0[idx];
+            v1 = w1[idx];
+            if (load_x) vx = xs[idx];
+        }
+        t.x[lj][li] = vx;
+        t.b[lj][li] = vb;
+        t.w0[lj][li] = v0;
+        t.w1[lj][li] = v1;
+    }
+    __syncthreads();
+}
+
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBlock)
+k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int load_x) {
+    constexpr int HALO = 2 * NU + 1;
+    __shared__ Tile2<T, HALO> t;
+    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        const LevelDesc& cL = L[d.coarse];
+        const int lt = tt - jl.prefix[jb];
+        const int tx_n = (d.n[0] + kFX - 1) / kFX;
+        const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
+        tile2_load<T, HALO>(t, d, gx0, gy0, load_x != 0);
+        for (int it = 0; it < NU; ++it) {
+            tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 1);
+            tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 2);
+        }
+        // smoothed iterate of the interior, and the residual averaged onto the coarse cells
+        T* __restrict__ xo = Arr<T>::x(d);
+        for (int e = threadIdx.x; e < kFX * kFY; e += kBlock) {
+            const int lj = e / kFX, li = e - lj * kFX;
+            const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
+            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
+        }
+        T* __restrict__ cb = Arr<T>::b(cL);
+        {
+            const int e = threadIdx.x;                 // one coarse cell per thread: 32 x 8
+            const int cj = e / (kFX / 2), ci = e - cj * (kFX / 2);
+            const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj;
+            if (CI < cL.n[0] && CJ < cL.n[1]) {
+                T sum = T(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int li = HALO + 2 * ci + (q & 1), lj = HALO + 2 * cj + (q >> 1);
+                    const T xc = t.x[lj][li];
+                    sum += t.b[lj][li] - xc - t.w0[lj][li] * (xc - t.x[lj][li - 1]) -
+                           t.w0[lj][li + 1] * (xc - t.x[lj][li + 1]) - t.w1[lj][li] * (xc - t.x[lj - 1][li]) -
+                           t.w1[lj + 1][li] * (xc - t.x[lj + 1][li]);
+                }
+                cb[CI + (long)cL.n[0] * CJ] = sum * T(0.25);
+            }
+        }
+        __syncthreads();                               // t is reloaded by the next tile
+    }
+}
+
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBlock)
+k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    constexpr int HALO = 2 * NU;
+    __shared__ Tile2<T, HALO> t;
+    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        const LevelDesc& cL = L[d.coarse];
+        const int lt = tt - jl.prefix[jb];
+        const int tx_n = (d.n[0] + kFX - 1) / kFX;
+        const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
+        tile2_load<T, HALO>(t, d, gx0, gy0, true);
+        // add the piecewise-constant prolongation of the coarse correction
+        const T* __restrict__ cx = Arr<T>::x(cL);
+        constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;
+        for (int e = threadIdx.x; e < W * H; e += kBlock) {
+            const int lj = e / W, li = e - lj * W;
+            const int gi = gx0 + li, gj = gy0 + lj;
+            if (gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1])
+                t.x[lj][li] += cx[(gi >> 1) + (long)cL.n[0] * (gj >> 1)];
+        }
+        __syncthreads();
+        for (int it = 0; it < NU; ++it) {
+            tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 1);
+            tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 2);
+        }
+        T* __restrict__ xo = Arr<T>::x(d);
+        for (int e = threadIdx.x; e < kFX * kFY; e += kBlock) {
+            const int lj = e / kFX, li = e - lj * kFX;
+            const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
+            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Tail: one workgroup per grid runs the whole V-cycle below a level T out of
 // LDS -- every tail level's x, b and face weights, plus the coarsest CG's
 // search direction -- so the coarse levels cost one launch instead of a few
@@ -1099,6 +1244,35 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+bool fused2_supported(int nu) { return nu >= 1 && nu <= 3; }
+
+#define FLD_NU_DISPATCH(nu, ...)                                          \
+    do {                                                                  \
+        if ((nu) == 1) { constexpr int NU = 1; __VA_ARGS__; }             \
+        else if ((nu) == 2) { constexpr int NU = 2; __VA_ARGS__; }        \
+        else { constexpr int NU = 3; __VA_ARGS__; }                       \
+    } while (0)
+
+void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
+                  int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_NU_DISPATCH(nu, {
+        if (fp32) hipLaunchKernelGGL((k_down2<float, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
+        else hipLaunchKernelGGL((k_down2<double, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
+    });
+}
+
+void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int nblk,
+                hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+    FLD_NU_DISPATCH(nu, {
+        if (fp32) hipLaunchKernelGGL((k_up2<float, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_up2<double, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
     });
 }
 

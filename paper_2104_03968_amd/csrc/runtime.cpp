@@ -53,6 +53,8 @@ struct DimLists {
     std::vector<HostList> restrict_;           // per depth, cell tiles of the coarse level
     std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
     std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
+    std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
+    bool fused = false;
     HostList coarsest;                         // coarsest level of grids without a tail
     HostList tail;                             // first tail level of grids with a tail
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
@@ -159,6 +161,7 @@ int validate_opts(const fld_opts& o) {
     if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 16 || o.nu2 > 16) return FLD_ERR_INVALID_ARG;
     if (o.krylov && o.nu1 != o.nu2) return FLD_ERR_INVALID_ARG;   // CG needs a symmetric V-cycle
     if (o.krylov != 0 && o.krylov != 1) return FLD_ERR_INVALID_ARG;
+    if (o.fused != 0 && o.fused != 1) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
 
@@ -182,6 +185,7 @@ void finish_list(HostList& l, const std::vector<LevelDesc>& L, int (*tiles)(cons
 int tiles_cell(const LevelDesc& d) { return cell_tiles(d.n); }
 int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
+int tiles_fused(const LevelDesc& d) { return fused_tiles(d.n); }
 
 }  // namespace
 
@@ -281,6 +285,15 @@ static void build_lists(Plan& p) {
         finish_list(D.l0_cell, p.levels, tiles_cell);
         finish_list(D.coarsest, p.levels, tiles_one);
         finish_list(D.tail, p.levels, tiles_one);
+        D.fused = D.dim == 2 && p.opts.fused && fused2_supported(p.opts.nu1) && fused2_supported(p.opts.nu2);
+        D.down2.resize(D.fused ? maxdepth : 0);
+        D.up2.resize(D.fused ? maxdepth : 0);
+        for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
+            D.down2[dpt].levels = D.smooth[dpt].levels;
+            D.up2[dpt].levels = D.smooth[dpt].levels;
+            finish_list(D.down2[dpt], p.levels, tiles_fused);
+            finish_list(D.up2[dpt], p.levels, tiles_fused);
+        }
         for (int dpt = 0; dpt < maxdepth; ++dpt) {
             finish_list(D.smooth[dpt], p.levels, tiles_smooth);
             finish_list(D.prolong[dpt], p.levels, tiles_cell);
@@ -324,6 +337,8 @@ static void layout(Plan& p) {
         place_list(D.coarsest);
         place_list(D.tail);
         for (auto& l : D.coarsen) place_list(l);
+        for (auto& l : D.down2) place_list(l);
+        for (auto& l : D.up2) place_list(l);
         for (auto& l : D.smooth) place_list(l);
         for (auto& l : D.restrict_) place_list(l);
         for (auto& l : D.prolong) place_list(l);
@@ -380,20 +395,28 @@ static void layout(Plan& p) {
 // solve of the current residual) followed by the FP64 residual and stop test.
 static void enqueue_cycle(Plan& p, hipStream_t s) {
     const bool f32 = p.mixed;
+    const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;   // level-0 V-cycle starts from the iterate
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const int dim = D.dim;
         for (int d = 0; d < D.maxdepth; ++d) {
+            if (D.fused) {
+                launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.nblk, s);
+                continue;
+            }
             for (int it = 0; it < p.opts.nu1; ++it) {
                 launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
                 launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
             }
             launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
         }
-        launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2,
-                    (!p.krylov && !p.mixed) ? 1 : 0, s);
+        launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
         launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
         for (int d = D.maxdepth - 1; d >= 0; --d) {
+            if (D.fused) {
+                launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.nblk, s);
+                continue;
+            }
             launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
             for (int it = 0; it < p.opts.nu2; ++it) {
                 launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
@@ -485,6 +508,8 @@ static int bind(Plan& p, void* dev, size_t bytes) {
         if ((rc = upload(D.coarsest)) != FLD_OK) return rc;
         if ((rc = upload(D.tail)) != FLD_OK) return rc;
         for (auto& l : D.coarsen) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.down2) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.up2) if ((rc = upload(l)) != FLD_OK) return rc;
         if (!D.tail.empty() && prepare_tail(D.dim, p.mixed, D.tail_smem) != 0) {
             g_last_error = "hipFuncSetAttribute(max dynamic LDS) failed for the tail kernel";
             return FLD_ERR_HIP;
@@ -630,6 +655,9 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
             case FLD_KERNEL_SMOOTH: if (has_level) l = &D.smooth[level]; break;
             case FLD_KERNEL_RESTRICT: if (has_level) l = &D.restrict_[level]; break;
             case FLD_KERNEL_PROLONG: if (has_level) l = &D.prolong[level]; break;
+            case FLD_KERNEL_DOWN: if (has_level && D.fused) l = &D.down2[level]; break;
+            case FLD_KERNEL_UP: if (has_level && D.fused) l = &D.up2[level]; break;
+            case FLD_KERNEL_TAIL: l = D.tail.empty() ? nullptr : &D.tail; break;
             default: l = &D.l0_cell; break;
         }
         if (!l) continue;
@@ -664,6 +692,15 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_COEFF:
                     launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+                    break;
+                case FLD_KERNEL_DOWN:
+                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0, p.nblk, s);
+                    break;
+                case FLD_KERNEL_UP:
+                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2, p.nblk, s);
+                    break;
+                case FLD_KERNEL_TAIL:
+                    launch_tail(D.dim, p.mixed, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
                     break;
                 default: break;
             }
@@ -744,6 +781,7 @@ void fld_opts_default(fld_opts* o) {
     o->use_graph = 1;
     o->autotune = 0;
     o->krylov = 1;
+    o->fused = 1;
 }
 
 void fld_gas_default(fld_gas* g) {
@@ -926,7 +964,7 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected) {
 
 int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps, void* stream,
                            double* avg_ms, int64_t* cells) {
-    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_EXCHANGE)
+    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_TAIL)
         return FLD_ERR_INVALID_ARG;
     Plan& p = plan->p;
     if (!p.ws) return FLD_ERR_NO_WORKSPACE;

@@ -115,10 +115,11 @@ def test_face_weights_full_size_config2():
 # ------------------------------------------------------------------ one diffusion step
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("krylov", [1, 0])
-def test_config1_step_matches_lu(precision, krylov):
+@pytest.mark.parametrize("nu", [1, 2, 3, 4])
+def test_config1_step_matches_lu(precision, krylov, nu):
     g = W.pulse_2d()
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="lu")
-    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov)
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, nu1=nu, nu2=nu)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st)
     assert st["q_b"] == pytest.approx(O.q_b(g.E), rel=1e-12)
@@ -130,10 +131,11 @@ def test_config1_step_matches_lu(precision, krylov):
                                       ((9, 7, 5), 1e-2)])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("krylov", [1, 0])
-def test_ragged_and_odd_grids_match_oracle(shape, dt, precision, krylov):
+@pytest.mark.parametrize("fused", [1, 0])
+def test_ragged_and_odd_grids_match_oracle(shape, dt, precision, krylov, fused):
     g = W.random_grid(shape, 555000 + 7 * sum(shape), dt=dt)
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, method="auto")
-    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov)
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, fused=fused)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st, info)
 
