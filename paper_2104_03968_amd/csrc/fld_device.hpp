@@ -51,6 +51,8 @@ struct LevelDesc {
     float*  x32;
     float*  b32;
     float*  w32[3];
+    double* xs;          // fused 2D levels: smoothed iterate left by the down pass, read by
+    float*  xs32;        //   the up pass (which writes x), so no pass reads what it writes
     double* part;        // per-tile partial sums (level 0 only)
     double* scratch;     // coarse-solve vectors for levels too large for LDS
     // level 0 only: the outer FP64 iteration (x and b above are the arrays the

@@ -302,11 +302,13 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
 template <typename T> struct Arr;
 template <> struct Arr<double> {
     __device__ static double* x(const LevelDesc& d) { return d.x; }
+    __device__ static double* xs(const LevelDesc& d) { return d.xs; }
     __device__ static double* b(const LevelDesc& d) { return d.b; }
     __device__ static double* w(const LevelDesc& d, int a) { return d.w[a]; }
 };
 template <> struct Arr<float> {
     __device__ static float* x(const LevelDesc& d) { return d.x32; }
+    __device__ static float* xs(const LevelDesc& d) { return d.xs32; }
     __device__ static float* b(const LevelDesc& d) { return d.b32; }
     __device__ static float* w(const LevelDesc& d, int a) { return d.w32[a]; }
 };
@@ -644,7 +646,9 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
 // ring, so the tile's cells come out exactly as a global red-black sweep would
 // leave them (the halo recomputes what neighbouring tiles compute).  Cells
 // outside the domain hold x = b = 0 and zero face weights, so updating them
-// keeps them 0 and no boundary test is needed inside the sweep.
+// keeps them 0 and no boundary test is needed inside the sweep.  A pass never
+// reads the array it writes (tiles overlap through their halos): down reads x
+// (when it starts from a stored iterate) and writes xs; up reads xs and writes x.
 // ---------------------------------------------------------------------------
 template <typename T, int HALO>
 struct Tile2 {
@@ -672,9 +676,8 @@ __device__ __forceinline__ void tile2_half_sweep(Tile2<T, HALO>& t, int gx0, int
 }
 
 template <typename T, int HALO>
-__device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d, int gx0, int gy0,
-                                           bool load_x) {
-    const T* __restrict__ xs = Arr<T>::x(d);
+__device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d, const T* __restrict__ xs,
+                                           int gx0, int gy0, bool load_x) {
     const T* __restrict__ bs = Arr<T>::b(d);
     const T* __restrict__ w0 = Arr<T>::w(d, 0);
     const T* __restrict__ w1 = Arr<T>::w(d, 1);
@@ -711,13 +714,14 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + kFX - 1) / kFX;
         const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
-        tile2_load<T, HALO>(t, d, gx0, gy0, load_x != 0);
+        tile2_load<T, HALO>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0);
         for (int it = 0; it < NU; ++it) {
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 1);
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 2);
         }
-        // smoothed iterate of the interior, and the residual averaged onto the coarse cells
-        T* __restrict__ xo = Arr<T>::x(d);
+        // smoothed iterate of the interior (to xs: other tiles may still read x), and the
+        // residual averaged onto the coarse cells
+        T* __restrict__ xo = Arr<T>::xs(d);
         for (int e = threadIdx.x; e < kFX * kFY; e += kBlock) {
             const int lj = e / kFX, li = e - lj * kFX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
@@ -758,7 +762,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + kFX - 1) / kFX;
         const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
-        tile2_load<T, HALO>(t, d, gx0, gy0, true);
+        tile2_load<T, HALO>(t, d, Arr<T>::xs(d), gx0, gy0, true);
         // add the piecewise-constant prolongation of the coarse correction
         const T* __restrict__ cx = Arr<T>::x(cL);
         constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;

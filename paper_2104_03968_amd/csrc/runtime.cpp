@@ -80,8 +80,9 @@ struct Plan {
     static constexpr int kExSlots = 4;
     struct FieldOff {
         size_t x = 0, b = 0, w[3] = {0, 0, 0}, x32 = 0, b32 = 0, w32[3] = {0, 0, 0}, part = 0, scratch = 0;
-        size_t X = 0, B0 = 0, R = 0, P[2] = {0, 0}, Q = 0;
+        size_t X = 0, B0 = 0, R = 0, P[2] = {0, 0}, Q = 0, xs = 0;
         bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
+        bool has_xs = false;
         bool lev0 = false, has_cg = false;
     };
     std::vector<FieldOff> foff;                // per level
@@ -387,6 +388,11 @@ static void layout(Plan& p) {
             f.has_scratch = true;
             f.scratch = take(4 * n * 8);
         }
+        // fused 2D levels (every level with a coarser one) keep the down pass's output apart
+        if (d.ndim == 2 && d.coarse >= 0 && p.dl[0].fused) {
+            f.has_xs = true;
+            f.xs = take(n * (p.mixed ? 4 : 8));
+        }
     }
     p.ws_bytes = off;
 }
@@ -483,6 +489,8 @@ static int bind(Plan& p, void* dev, size_t bytes) {
         d.P[0] = dp(f.P[0], f.has_cg);
         d.P[1] = dp(f.P[1], f.has_cg);
         d.Q = dp(f.Q, f.has_cg);
+        d.xs = (f.has_xs && !p.mixed) ? reinterpret_cast<double*>(ws + f.xs) : nullptr;
+        d.xs32 = (f.has_xs && p.mixed) ? reinterpret_cast<float*>(ws + f.xs) : nullptr;
     }
     FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
     std::vector<GridState> st(p.ngrids());

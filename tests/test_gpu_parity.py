@@ -172,6 +172,18 @@ def test_graph_and_direct_launches_agree_bitwise(krylov):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_fused_and_per_colour_kernels_agree(precision):
+    """The fused LDS level kernels run the same red-black V-cycle as the one-kernel-per-
+    colour path: same iteration count, results equal to rounding."""
+    g = W.random_grid((512, 384), 4242, dt=5e-3)
+    (xa,), (sa,), ra = run_step([g], precision=precision, fused=1)
+    (xb,), (sb,), rb = run_step([g], precision=precision, fused=0)
+    assert ra == 0 and rb == 0
+    assert sa["cycles"] == sb["cycles"], (sa, sb)
+    assert rel_l2(xa, xb) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_stiff_trajectory_converges_quickly(precision):
     """A config-4 grid (288^2, dt = 9.2e-3, coarsest 9^2) whose third step sharpens D
     enough that plain V-cycles need ~30 iterations; CG with the V-cycle stays <= 16."""
