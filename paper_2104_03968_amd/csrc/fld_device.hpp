@@ -22,6 +22,10 @@ constexpr int kSX = 128;
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseCPT = 4;
 constexpr int kCoarseMaxLDS = kCoarseThreads * kCoarseCPT;   // 4096 cells
+// LDS tail: one 256-thread workgroup per grid; its coarsest CG holds up to 8 cells a thread.
+constexpr int kTailThreads = 256;
+constexpr int kTailCPT = 8;
+constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 
 // Tile counts of one level for the two tilings (host and device agree on these).
 __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
@@ -81,7 +85,7 @@ struct GridState {
     int32_t bad;         // input-validation bits (atomicOr)
     int32_t ntiles0;     // cell-tiles of level 0 (number of partial sums)
     int32_t iter;        // CG iterations since the last (re)start
-    int32_t pad_;
+    int32_t done;        // tiles of the running reduction finished so far (last block resets)
 };
 
 // Finalization modes of k_finalize (one block per grid, fixed-order sums).
@@ -130,8 +134,11 @@ struct Control {
 
 // ---- launch wrappers (kernels.hip) ------------------------------------------
 // All launches are asynchronous on `s`.  `nblk` caps the persistent grid size.
+// Reductions finish on the device: the block that completes a grid's last tile sums
+// the grid's tile partials in a fixed order and applies the FinMode update.
 void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
-                  const StepIO* io, double c, int limiter, int nblk, hipStream_t s);
+                  const StepIO* io, double c, int limiter, double rtol, int max_cycles, int nblk,
+                  hipStream_t s);
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
                      int max_cycles, hipStream_t s);
 void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s);
@@ -163,14 +170,15 @@ constexpr size_t kTailLdsBudget = 150 * 1024;
 // select: 0 = active grids, 1 = grids whose status is FLD_OK (convergence check).
 // zero_x: also clear the level-0 V-cycle iterate (FP64 or FP32 by `mixed`); mixed also
 // writes the FP32 right-hand side.
-void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
-                     int select, int zero_x, int nblk, hipStream_t s);
-void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
-                  hipStream_t s);
-void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
-                  hipStream_t s);
-void launch_cg_update(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
-                      hipStream_t s);
+// fin: FinMode applied by the last block (-1: none, for timing).
+void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+                     int select, int zero_x, int fin, double rtol, int max_cycles, int nblk, hipStream_t s);
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
+                  int max_cycles, int nblk, hipStream_t s);
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
+                  int max_cycles, int nblk, hipStream_t s);
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
+                      int max_cycles, int nblk, hipStream_t s);
 void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,

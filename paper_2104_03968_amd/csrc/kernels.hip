@@ -75,6 +75,143 @@ __device__ __forceinline__ void cell_of_tile(const int32_t n[3], int lt, int tid
     j = ty * kTY + (tid / kTX);
 }
 
+// Sum the level-0 per-tile partials of one grid in a fixed order.
+__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int ntiles, int stride,
+                                          double& a, double& b, double* sh) {
+    a = 0.0;
+    b = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
+        a += part[stride * i];
+        if (stride == 2) b += part[stride * i + 1];
+    }
+    block_sum2<kBlock>(a, b, sh);
+}
+
+// Stop test / CG scalar update of one grid from the summed partials (thread 0).
+__device__ void finalize_grid(GridState& g, double s2, double s1, int mode, double rtol, int max_cycles) {
+    switch (mode) {
+        case FIN_B:
+            g.bnorm2 = s2;
+            g.bsum = s1;
+            g.tol2 = rtol * rtol * s2;
+            g.cycles = 0;
+            g.iter = 0;
+            g.stall = 0;
+            g.rnorm2 = s2;
+            g.rprev2 = INFINITY;
+            g.status = g.bad ? FLD_ERR_BAD_INPUT : FLD_OK;
+            g.active = g.bad ? 0 : 1;
+            g.bad = 0;                               // read once per step; cleared for the next one
+            break;
+        case FIN_R_INIT:
+        case FIN_R_VERIFY:
+            g.rnorm2 = s2;
+            g.iter = 0;                              // (re)start CG from this residual
+            g.stall = 0;
+            if (!(s2 == s2) || isinf(s2)) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
+            else g.active = (s2 > g.tol2 && g.cycles < max_cycles) ? 1 : 0;
+            if (g.active == 0 && s2 > g.tol2 && g.status == FLD_OK) g.status = FLD_ERR_NOT_CONVERGED;
+            g.rprev2 = s2;
+            break;
+        case FIN_R_CYCLE:
+        case FIN_CG:
+            g.rnorm2 = s2;
+            g.cycles += 1;
+            if (mode == FIN_CG) g.iter += 1;
+            if (!(s2 == s2) || isinf(s2)) {
+                g.active = 0;
+                g.status = FLD_ERR_NOT_CONVERGED;
+            } else if (s2 <= g.tol2) {
+                g.active = 0;
+                g.status = FLD_OK;
+            } else if (g.cycles >= max_cycles) {
+                g.active = 0;
+                g.status = FLD_ERR_NOT_CONVERGED;
+            } else {
+                // stagnation: no 10 % gain in ||r|| over the best so far for 5 iterations
+                if (s2 < 0.81 * g.rprev2) { g.rprev2 = s2; g.stall = 0; }
+                else if (++g.stall >= 5) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
+            }
+            break;
+        case FIN_RZ:
+            g.beta = (g.iter > 0 && g.rho != 0.0) ? s2 / g.rho : 0.0;
+            g.rho = s2;
+            break;
+        case FIN_PQ:
+            if (s2 > 0.0 && isfinite(s2)) {
+                g.alpha = g.rho / s2;
+            } else {                                 // breakdown: no descent direction left
+                g.alpha = 0.0;
+                g.active = 0;
+                g.status = (g.rnorm2 <= g.tol2) ? FLD_OK : FLD_ERR_NOT_CONVERGED;
+            }
+            break;
+        default:
+            break;
+    }
+}
+
+// Called by every block after thread 0 stored its tile partial: count the tile
+// and report whether it was the grid's last.  The counter is an integer atomic;
+// the partials themselves are summed in a fixed order by the last block.
+__device__ __forceinline__ bool grid_tile_done(GridState& g, int ntiles, int* flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                             // publish this tile's partial
+        const int prev = atomicAdd(&g.done, 1);
+        const int last = (prev == ntiles - 1);
+        if (last) g.done = 0;                        // every tile has counted: reset for the next
+        *flag = last;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Fixed-order sum of a grid's tile partials, read past the (non-coherent) L1.
+__device__ __forceinline__ void sum_parts_coherent(const double* part, int ntiles, int stride, double& a,
+                                                   double& b, double* sh) {
+    __threadfence();
+    a = 0.0;
+    b = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
+        a += __hip_atomic_load(part + stride * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (stride == 2) b += __hip_atomic_load(part + stride * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum2<kBlock>(a, b, sh);
+}
+
+// End of a reducing kernel's tile: store the partial(s) and, if this was the
+// grid's last tile, finish the reduction (fin < 0: store only).
+__device__ __forceinline__ void tile_reduce_finish(const LevelDesc& d, GridState& g, int lt, int ntiles,
+                                                   double a, double b, int stride, int fin, double rtol,
+                                                   int max_cycles, double* sh, int* flag) {
+    block_sum2<kBlock>(a, b, sh);
+    if (threadIdx.x == 0) {
+        d.part[stride * lt] = a;
+        if (stride == 2) d.part[stride * lt + 1] = b;
+    }
+    if (fin < 0) return;
+    if (!grid_tile_done(g, ntiles, flag)) return;
+    double s2, s1;
+    sum_parts_coherent(d.part, ntiles, stride, s2, s1, sh);
+    if (threadIdx.x == 0) finalize_grid(g, s2, s1, fin, rtol, max_cycles);
+}
+
+// One block per grid: the same finalization as a separate launch (kept for the
+// plain V-cycle path's callers that reduce without finishing).
+__global__ void __launch_bounds__(kBlock)
+k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int mode, double rtol,
+           int max_cycles) {
+    __shared__ double sh[2 * kBlock / 64];
+    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    GridState& g = S[d.grid];
+    const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
+    if (!run) return;                                // uniform per block
+    double s2, s1;
+    sum_parts(d.part, g.ntiles0, mode == FIN_B ? 2 : 1, s2, s1, sh);
+    if (threadIdx.x == 0) finalize_grid(g, s2, s1, mode, rtol, max_cycles);
+}
+
 // ---------------------------------------------------------------------------
 // K1: coefficients.  R = |grad E|/(kappa rho E) with the 4th-order central
 // gradient (mirrored ghosts), lambda(R), D = c lambda/(kappa rho), and the
@@ -121,8 +258,9 @@ __device__ __forceinline__ double face_w(double DL, double DR, double dt, double
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
-        const StepIO* __restrict__ io, double c, int limiter) {
+        const StepIO* __restrict__ io, double c, int limiter, double rtol, int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
+    __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
@@ -158,99 +296,8 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
             s2 = e * e;
             s1 = e;
         }
-        block_sum2<kBlock>(s2, s1, sh);
-        if (threadIdx.x == 0) {
-            d.part[2 * lt] = s2;
-            d.part[2 * lt + 1] = s1;
-        }
-    }
-}
-
-// Sum the level-0 per-tile partials of one grid in a fixed order.
-__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int ntiles, int stride,
-                                          double& a, double& b, double* sh) {
-    a = 0.0;
-    b = 0.0;
-    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
-        a += part[stride * i];
-        if (stride == 2) b += part[stride * i + 1];
-    }
-    block_sum2<kBlock>(a, b, sh);
-}
-
-// One block per grid: sum the grid's level-0 tile partials in a fixed order and
-// apply the stop test / CG scalar update of the given mode.
-__global__ void __launch_bounds__(kBlock)
-k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int mode, double rtol,
-           int max_cycles) {
-    __shared__ double sh[2 * kBlock / 64];
-    const LevelDesc& d = L[jl.levels[blockIdx.x]];
-    GridState& g = S[d.grid];
-    const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
-    if (!run) return;                                // uniform per block
-    double s2, s1;
-    sum_parts(d.part, g.ntiles0, mode == FIN_B ? 2 : 1, s2, s1, sh);
-    if (threadIdx.x != 0) return;
-    switch (mode) {
-        case FIN_B:
-            g.bnorm2 = s2;
-            g.bsum = s1;
-            g.tol2 = rtol * rtol * s2;
-            g.cycles = 0;
-            g.iter = 0;
-            g.stall = 0;
-            g.rnorm2 = s2;
-            g.rprev2 = INFINITY;
-            g.status = g.bad ? FLD_ERR_BAD_INPUT : FLD_OK;
-            g.active = g.bad ? 0 : 1;
-            g.bad = 0;                               // read once per step; cleared for the next one
-            break;
-        case FIN_R_INIT:
-        case FIN_R_VERIFY:
-            g.rnorm2 = s2;
-            g.iter = 0;                              // (re)start CG from this residual
-            g.stall = 0;
-            if (!(s2 == s2) || isinf(s2)) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
-            else g.active = (s2 > g.tol2 && g.cycles < max_cycles) ? 1 : 0;
-            if (g.active == 0 && s2 > g.tol2 && g.status == FLD_OK) g.status = FLD_ERR_NOT_CONVERGED;
-            g.rprev2 = s2;
-            break;
-        case FIN_R_CYCLE:
-        case FIN_CG: {
-            g.rnorm2 = s2;
-            g.cycles += 1;
-            if (mode == FIN_CG) g.iter += 1;
-            if (!(s2 == s2) || isinf(s2)) {
-                g.active = 0;
-                g.status = FLD_ERR_NOT_CONVERGED;
-            } else if (s2 <= g.tol2) {
-                g.active = 0;
-                g.status = FLD_OK;
-            } else if (g.cycles >= max_cycles) {
-                g.active = 0;
-                g.status = FLD_ERR_NOT_CONVERGED;
-            } else {
-                // stagnation: no 10 % gain in ||r|| over the best so far for 5 iterations
-                if (s2 < 0.81 * g.rprev2) { g.rprev2 = s2; g.stall = 0; }
-                else if (++g.stall >= 5) { g.active = 0; g.status = FLD_ERR_NOT_CONVERGED; }
-            }
-            break;
-        }
-        case FIN_RZ:
-            g.beta = (g.iter > 0 && g.rho != 0.0) ? s2 / g.rho : 0.0;
-            g.rho = s2;
-            break;
-        case FIN_PQ:
-            if (s2 > 0.0 && isfinite(s2)) {
-                g.alpha = g.rho / s2;
-            } else {                                 // breakdown: no descent direction left
-                g.alpha = 0.0;
-                g.active = 0;
-                g.status = (g.rnorm2 <= g.tol2) ? FLD_OK : FLD_ERR_NOT_CONVERGED;
-            }
-            break;
-        default:
-            break;
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, FIN_B, rtol,
+                           max_cycles, sh, &flag);
     }
 }
 
@@ -472,21 +519,21 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
     return dg;
 }
 
-// Block-wide Jacobi-preconditioned CG on one level of up to kCoarseMaxLDS cells.
+// Block-wide Jacobi-preconditioned CG on one level of up to NT * CPT cells.
 // Starts from x (read from `x` when warm, else zero), runs until the residual
 // falls by 1e-6 (or maxit iterations) and writes the result back to `x`.  The
 // search direction lives in p_sh (LDS); x, r and the inverse diagonal live in
 // registers of the thread owning the cell.  w, b and x may be global or LDS.
-template <int DIM, typename T>
+template <int DIM, typename T, int NT, int CPT>
 __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
                          bool warm, T* p_sh, double* red) {
     const int ncell = n[0] * n[1] * n[2];
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
     const double tol2 = 1e-12;                 // (1e-6)^2 relative
-    T xr[kCoarseCPT], r[kCoarseCPT], dinv[kCoarseCPT];
+    T xr[CPT], r[CPT], dinv[CPT];
 #pragma unroll
-    for (int m = 0; m < kCoarseCPT; ++m) {
-        const int c = threadIdx.x + m * kCoarseThreads;
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
         xr[m] = T(0);
         r[m] = T(0);
         dinv[m] = T(0);
@@ -498,8 +545,8 @@ __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* 
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < kCoarseCPT; ++m) {
-        const int c = threadIdx.x + m * kCoarseThreads;
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
         if (c < ncell) {
             T dg;
             r[m] = b[c];
@@ -509,8 +556,8 @@ __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* 
     __syncthreads();
     double rz = 0.0, rr0 = 0.0;
 #pragma unroll
-    for (int m = 0; m < kCoarseCPT; ++m) {
-        const int c = threadIdx.x + m * kCoarseThreads;
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
         if (c < ncell) {
             const T z = r[m] * dinv[m];
             p_sh[c] = z;
@@ -518,14 +565,14 @@ __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* 
             rr0 += (double)r[m] * (double)r[m];
         }
     }
-    block_sum2<kCoarseThreads>(rz, rr0, red);     // also orders the p_sh writes
+    block_sum2<NT>(rz, rr0, red);     // also orders the p_sh writes
     if (rr0 > 0.0) {
         for (int it = 0; it < maxit; ++it) {
-            T q[kCoarseCPT];
+            T q[CPT];
             double pq = 0.0, unused = 0.0;
 #pragma unroll
-            for (int m = 0; m < kCoarseCPT; ++m) {
-                const int c = threadIdx.x + m * kCoarseThreads;
+            for (int m = 0; m < CPT; ++m) {
+                const int c = threadIdx.x + m * NT;
                 q[m] = T(0);
                 if (c < ncell) {
                     T dg;
@@ -533,13 +580,13 @@ __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* 
                     pq += (double)p_sh[c] * (double)q[m];
                 }
             }
-            block_sum2<kCoarseThreads>(pq, unused, red);
+            block_sum2<NT>(pq, unused, red);
             if (!(pq > 0.0)) break;
             const T alpha = (T)(rz / pq);
             double rz_new = 0.0, rr = 0.0;
 #pragma unroll
-            for (int m = 0; m < kCoarseCPT; ++m) {
-                const int c = threadIdx.x + m * kCoarseThreads;
+            for (int m = 0; m < CPT; ++m) {
+                const int c = threadIdx.x + m * NT;
                 if (c < ncell) {
                     xr[m] += alpha * p_sh[c];
                     r[m] -= alpha * q[m];
@@ -548,21 +595,21 @@ __device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* 
                     rr += (double)r[m] * (double)r[m];
                 }
             }
-            block_sum2<kCoarseThreads>(rz_new, rr, red);   // every thread is done reading p_sh
+            block_sum2<NT>(rz_new, rr, red);   // every thread is done reading p_sh
             if (rr <= tol2 * rr0) break;
             const T beta = (T)(rz_new / rz);
             rz = rz_new;
 #pragma unroll
-            for (int m = 0; m < kCoarseCPT; ++m) {
-                const int c = threadIdx.x + m * kCoarseThreads;
+            for (int m = 0; m < CPT; ++m) {
+                const int c = threadIdx.x + m * NT;
                 if (c < ncell) p_sh[c] = r[m] * dinv[m] + beta * p_sh[c];
             }
             __syncthreads();
         }
     }
 #pragma unroll
-    for (int m = 0; m < kCoarseCPT; ++m) {
-        const int c = threadIdx.x + m * kCoarseThreads;
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
         if (c < ncell) x[c] = xr[m];
     }
     __syncthreads();
@@ -585,7 +632,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     // from it.  Every other coarsest level solves for a correction from zero.
     const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
-        block_cg<DIM, T>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red);
+        block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red);
         return;
     }
     const int maxit = 2000;
@@ -675,28 +722,47 @@ __device__ __forceinline__ void tile2_half_sweep(Tile2<T, HALO>& t, int gx0, int
     __syncthreads();
 }
 
+// Stage the tile and its halo in LDS.  All global loads of a thread are issued
+// before any LDS store so their latencies overlap.  With `cx`, the piecewise-
+// constant prolongation of the coarse correction is added to x on the way in.
 template <typename T, int HALO>
 __device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d, const T* __restrict__ xs,
-                                           int gx0, int gy0, bool load_x) {
+                                           int gx0, int gy0, bool load_x, const T* __restrict__ cx,
+                                           int ncx) {
     const T* __restrict__ bs = Arr<T>::b(d);
     const T* __restrict__ w0 = Arr<T>::w(d, 0);
     const T* __restrict__ w1 = Arr<T>::w(d, 1);
     constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;
-    for (int e = threadIdx.x; e < W * H; e += kBlock) {
+    constexpr int NE = (W * H + kBlock - 1) / kBlock;
+    T vx[NE], vb[NE], v0[NE], v1[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const int e = threadIdx.x + r * kBlock;
+        vx[r] = T(0);
+        vb[r] = T(0);
+        v0[r] = T(0);
+        v1[r] = T(0);
         const int lj = e / W, li = e - lj * W;
         const int gi = gx0 + li, gj = gy0 + lj;
-        T vx = T(0), vb = T(0), v0 = T(0), v1 = T(0);
-        if (gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1]) {
+        if (e < W * H && gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1]) {
             const long idx = gi + (long)d.n[0] * gj;
-            vb = bs[idx];
-            v0 = w0[idx];
-            v1 = w1[idx];
-            if (load_x) vx = xs[idx];
+            vb[r] = bs[idx];
+            v0[r] = w0[idx];
+            v1[r] = w1[idx];
+            if (load_x) vx[r] = xs[idx];
+            if (cx) vx[r] += cx[(gi >> 1) + (long)ncx * (gj >> 1)];
         }
-        t.x[lj][li] = vx;
-        t.b[lj][li] = vb;
-        t.w0[lj][li] = v0;
-        t.w1[lj][li] = v1;
+    }
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const int e = threadIdx.x + r * kBlock;
+        if (e < W * H) {
+            const int lj = e / W, li = e - lj * W;
+            t.x[lj][li] = vx[r];
+            t.b[lj][li] = vb[r];
+            t.w0[lj][li] = v0[r];
+            t.w1[lj][li] = v1[r];
+        }
     }
     __syncthreads();
 }
@@ -714,7 +780,7 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + kFX - 1) / kFX;
         const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
-        tile2_load<T, HALO>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0);
+        tile2_load<T, HALO>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0, nullptr, 0);
         for (int it = 0; it < NU; ++it) {
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 1);
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 2);
@@ -762,17 +828,8 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + kFX - 1) / kFX;
         const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
-        tile2_load<T, HALO>(t, d, Arr<T>::xs(d), gx0, gy0, true);
-        // add the piecewise-constant prolongation of the coarse correction
-        const T* __restrict__ cx = Arr<T>::x(cL);
-        constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;
-        for (int e = threadIdx.x; e < W * H; e += kBlock) {
-            const int lj = e / W, li = e - lj * W;
-            const int gi = gx0 + li, gj = gy0 + lj;
-            if (gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1])
-                t.x[lj][li] += cx[(gi >> 1) + (long)cL.n[0] * (gj >> 1)];
-        }
-        __syncthreads();
+        // the down pass's iterate plus the prolonged coarse correction
+        tile2_load<T, HALO>(t, d, Arr<T>::xs(d), gx0, gy0, true, Arr<T>::x(cL), cL.n[0]);
         for (int it = 0; it < NU; ++it) {
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 1);
             tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 2);
@@ -798,19 +855,47 @@ template <typename T>
 struct TailLevel {
     int32_t n[3];
     int32_t ncell;
+    int32_t hx;          // colour cells per row: ceil(nx / 2)
+    float rhx;           // 1 / hx
+    float rny;           // 1 / ny
+    float rnx;           // 1 / nx
     T* x;
     T* b;
     T* w[3];
 };
 constexpr int kMaxTail = 16;
 
+// q / d for 0 <= q < 2^20 and d <= 2^10 through a float reciprocal: (q + 1/2)/d
+// lies at least 1/(2d) from an integer, far beyond the float rounding error.
+__device__ __forceinline__ int fdiv(int q, float rd) { return (int)(((float)q + 0.5f) * rd); }
+
+template <int DIM, typename T>
+__device__ __forceinline__ void tl_coords(const TailLevel<T>& lv, int c, int& i, int& j, int& k) {
+    const int r = fdiv(c, lv.rnx);
+    i = c - r * lv.n[0];
+    if (DIM == 3) {
+        k = fdiv(r, lv.rny);
+        j = r - k * lv.n[1];
+    } else {
+        j = r;
+        k = 0;
+    }
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ void tl_half_sweep(const TailLevel<T>& lv, int color) {
     const int sy = lv.n[0], sz = lv.n[0] * lv.n[1];
-    for (int c = threadIdx.x; c < lv.ncell; c += kCoarseThreads) {
-        int i, j, k;
-        cell_coords<DIM, T>(lv.n, c, i, j, k);
-        if (((i + j + k) & 1) != color) continue;
+    const int rows = lv.n[1] * lv.n[2];
+    for (int m = threadIdx.x; m < rows * lv.hx; m += kTailThreads) {
+        const int r = fdiv(m, lv.rhx);
+        int j = r, k = 0;
+        if (DIM == 3) {
+            k = fdiv(r, lv.rny);
+            j = r - k * lv.n[1];
+        }
+        const int i = 2 * (m - r * lv.hx) + ((j + k + color) & 1);
+        if (i >= lv.n[0]) continue;
+        const int c = i + j * sy + k * sz;
         T s = lv.b[c], dg = T(1);
         if (i > 0) { const T w = lv.w[0][c]; s += w * lv.x[c - 1]; dg += w; }
         if (i + 1 < lv.n[0]) { const T w = lv.w[0][c + 1]; s += w * lv.x[c + 1]; dg += w; }
@@ -826,12 +911,12 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T>& lv, int color)
 }
 
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kCoarseThreads)
+__global__ void __launch_bounds__(kTailThreads)
 k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int nu1, int nu2,
        int plain64) {
     extern __shared__ __align__(16) unsigned char tail_smem[];
     __shared__ TailLevel<T> tl[kMaxTail];
-    __shared__ double red[2 * kCoarseThreads / 64];
+    __shared__ double red[2 * kTailThreads / 64];
     __shared__ int ntl;
     const int first = jl.levels[blockIdx.x];
     if (!S[L[first].grid].active) return;
@@ -843,6 +928,10 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
             TailLevel<T>& t = tl[m];
             t.n[0] = d.n[0]; t.n[1] = d.n[1]; t.n[2] = d.n[2];
             t.ncell = d.n[0] * d.n[1] * d.n[2];
+            t.hx = (d.n[0] + 1) / 2;
+            t.rhx = 1.0f / (float)t.hx;
+            t.rnx = 1.0f / (float)d.n[0];
+            t.rny = 1.0f / (float)d.n[1];
             t.x = base; base += t.ncell;
             t.b = base; base += t.ncell;
             for (int a = 0; a < 3; ++a) {
@@ -855,23 +944,31 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     __syncthreads();
     const int nl = ntl;
     T* p_sh = tl[nl - 1].w[DIM - 1] + tl[nl - 1].ncell;   // the coarsest CG's search direction
-    // load weights of every tail level, b and (warm) x of the first
+    // load every tail level's weights, and b and (warm) x of the first; loads of a
+    // level are issued together, then stored
     {
         int li = first;
         for (int m = 0; m < nl; ++m, li = L[li].coarse) {
             const LevelDesc& d = L[li];
             const TailLevel<T>& t = tl[m];
-            for (int a = 0; a < DIM; ++a) {
-                const T* src = Arr<T>::w(d, a);
-                for (int c = threadIdx.x; c < t.ncell; c += kCoarseThreads) t.w[a][c] = src[c];
-            }
-            if (m == 0) {
-                const T* bsrc = Arr<T>::b(d);
-                const T* xsrc = Arr<T>::x(d);
-                const bool warm = plain64 && d.level == 0;
-                for (int c = threadIdx.x; c < t.ncell; c += kCoarseThreads) {
-                    t.b[c] = bsrc[c];
-                    t.x[c] = warm ? xsrc[c] : T(0);
+            const T* s0 = Arr<T>::w(d, 0);
+            const T* s1 = Arr<T>::w(d, 1);
+            const T* s2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
+            const bool lead = (m == 0);
+            const bool warm = lead && plain64 && d.level == 0;
+            const T* bsrc = Arr<T>::b(d);
+            const T* xsrc = Arr<T>::x(d);
+            for (int c = threadIdx.x; c < t.ncell; c += kTailThreads) {
+                const T a0 = s0[c], a1 = s1[c];
+                const T a2 = (DIM == 3) ? s2[c] : T(0);
+                const T bb = lead ? bsrc[c] : T(0);
+                const T xx = warm ? xsrc[c] : T(0);
+                t.w[0][c] = a0;
+                t.w[1][c] = a1;
+                if (DIM == 3) t.w[2][c] = a2;
+                if (lead) {
+                    t.b[c] = bb;
+                    t.x[c] = xx;
                 }
             }
         }
@@ -885,9 +982,9 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
             tl_half_sweep<DIM, T>(f, 0);
             tl_half_sweep<DIM, T>(f, 1);
         }
-        for (int c = threadIdx.x; c < cT.ncell; c += kCoarseThreads) {
+        for (int c = threadIdx.x; c < cT.ncell; c += kTailThreads) {
             int I, J, K;
-            cell_coords<DIM, T>(cT.n, c, I, J, K);
+            tl_coords<DIM, T>(cT, c, I, J, K);
             T sum = T(0);
 #pragma unroll
             for (int q = 0; q < (1 << DIM); ++q)
@@ -901,15 +998,15 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     // coarsest: CG from the current x (zero unless the grid has a single level)
     {
         const TailLevel<T>& cT = tl[nl - 1];
-        block_cg<DIM, T>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
+        block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
         const TailLevel<T>& f = tl[m];
         const TailLevel<T>& cT = tl[m + 1];
-        for (int c = threadIdx.x; c < f.ncell; c += kCoarseThreads) {
+        for (int c = threadIdx.x; c < f.ncell; c += kTailThreads) {
             int i, j, k;
-            cell_coords<DIM, T>(f.n, c, i, j, k);
+            tl_coords<DIM, T>(f, c, i, j, k);
             f.x[c] += cT.x[(i >> 1) + cT.n[0] * ((j >> 1) + cT.n[1] * (k >> 1))];
         }
         __syncthreads();
@@ -920,7 +1017,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     }
     {
         T* xdst = Arr<T>::x(L[first]);
-        for (int c = threadIdx.x; c < tl[0].ncell; c += kCoarseThreads) xdst[c] = tl[0].x[c];
+        for (int c = threadIdx.x; c < tl[0].ncell; c += kTailThreads) xdst[c] = tl[0].x[c];
     }
 }
 
@@ -931,9 +1028,10 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
 // ---------------------------------------------------------------------------
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int select,
-           int zero_x) {
+k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int select,
+           int zero_x, int fin, double rtol, int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
+    __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
@@ -955,8 +1053,8 @@ k_residual(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
                 d.x[idx] = 0.0;
             }
         }
-        block_sum2<kBlock>(r2, unused, sh);
-        if (threadIdx.x == 0) d.part[lt] = r2;
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
+                           max_cycles, sh, &flag);
     }
 }
 
@@ -975,8 +1073,10 @@ __device__ __forceinline__ double z_at(const LevelDesc& d, long idx) {
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_rz(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+        int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
+    __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
@@ -989,19 +1089,21 @@ k_cg_rz(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             a = d.R[idx] * z_at<MIXED>(d, idx);
         }
-        block_sum2<kBlock>(a, unused, sh);
-        if (threadIdx.x == 0) d.part[lt] = a;
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, FIN_RZ, rtol,
+                           max_cycles, sh, &flag);
     }
 }
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_pq(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+        int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
+    __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        const GridState& g = S[d.grid];
+        GridState& g = S[d.grid];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
         int i, j, k;
@@ -1030,19 +1132,21 @@ k_cg_pq(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
             d.Q[idx] = q;
             pq = pc * q;
         }
-        block_sum2<kBlock>(pq, unused, sh);
-        if (threadIdx.x == 0) d.part[lt] = pq;
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, FIN_PQ, rtol,
+                           max_cycles, sh, &flag);
     }
 }
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_update(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+        int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
+    __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        const GridState& g = S[d.grid];
+        GridState& g = S[d.grid];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
         int i, j, k;
@@ -1063,8 +1167,8 @@ k_cg_update(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Jo
                 d.x[idx] = 0.0;
             }
         }
-        block_sum2<kBlock>(r2, unused, sh);
-        if (threadIdx.x == 0) d.part[lt] = r2;
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, FIN_CG, rtol,
+                           max_cycles, sh, &flag);
     }
 }
 
@@ -1197,12 +1301,13 @@ inline int blocks_for(int total, int nblk) { return total < nblk ? (total > 0 ? 
     do { if ((dim) == 3) { constexpr int D = 3; __VA_ARGS__; } else { constexpr int D = 2; __VA_ARGS__; } } while (0)
 
 void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
-                  const StepIO* io, double c, int limiter, int nblk, hipStream_t s) {
+                  const StepIO* io, double c, int limiter, double rtol, int max_cycles, int nblk,
+                  hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter);
-        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter);
+        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, rtol, max_cycles);
+        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, rtol, max_cycles);
     });
 }
 
@@ -1293,8 +1398,8 @@ void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, Job
                  int nu1, int nu2, int plain64, hipStream_t s) {
     if (jl.njobs <= 0) return;
     FLD_DISPATCH_DIM(dim, {
-        if (fp32) hipLaunchKernelGGL((k_tail<D, float>), dim3(jl.njobs), dim3(kCoarseThreads), smem, s, L, S, jl, nu1, nu2, plain64);
-        else hipLaunchKernelGGL((k_tail<D, double>), dim3(jl.njobs), dim3(kCoarseThreads), smem, s, L, S, jl, nu1, nu2, plain64);
+        if (fp32) hipLaunchKernelGGL((k_tail<D, float>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64);
+        else hipLaunchKernelGGL((k_tail<D, double>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64);
     });
 }
 
@@ -1307,13 +1412,13 @@ void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState
     });
 }
 
-void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl,
-                     int select, int zero_x, int nblk, hipStream_t s) {
+void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+                     int select, int zero_x, int fin, double rtol, int max_cycles, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x);
-        else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x);
+        if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x, fin, rtol, max_cycles);
+        else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x, fin, rtol, max_cycles);
     });
 }
 
@@ -1321,21 +1426,21 @@ void launch_residual(int dim, bool mixed, const LevelDesc* L, const GridState* S
     if (jl.total <= 0) return;                                                                       \
     const int g = blocks_for(jl.total, nblk);                                                        \
     FLD_DISPATCH_DIM(dim, {                                                                          \
-        if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);      \
-        else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl);           \
+        if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, rtol, max_cycles); \
+        else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, rtol, max_cycles);      \
     })
 
-void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_rz);
 }
 
-void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_pq);
 }
 
-void launch_cg_update(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
                       hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_update);
 }

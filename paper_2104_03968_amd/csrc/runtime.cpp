@@ -245,7 +245,7 @@ static void choose_tails(Plan& p) {
     for (int g = 0; g < p.ngrids(); ++g) {
         const int L = p.nlev[g];
         const LevelDesc& c = p.levels[p.level0[g] + L - 1];
-        if ((int64_t)c.n[0] * c.n[1] * c.n[2] > kCoarseMaxLDS) continue;
+        if ((int64_t)c.n[0] * c.n[1] * c.n[2] > kTailMaxCoarsest) continue;
         for (int t = 0; t < L; ++t) {
             if (tail_bytes(p, g, t) <= kTailLdsBudget) { p.tail_lev[g] = t; break; }
         }
@@ -431,16 +431,13 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
         }
         const JobList& l0 = D.l0_cell.dev;
         if (p.krylov) {
-            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
-            launch_finalize(p.dL, p.dS, l0, FIN_RZ, p.opts.rtol, p.opts.max_cycles, s);
-            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
-            launch_finalize(p.dL, p.dS, l0, FIN_PQ, p.opts.rtol, p.opts.max_cycles, s);
-            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, p.nblk, s);
-            launch_finalize(p.dL, p.dS, l0, FIN_CG, p.opts.rtol, p.opts.max_cycles, s);
+            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
         } else {
             if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, p.nblk, s);
-            launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, p.nblk, s);
-            launch_finalize(p.dL, p.dS, l0, FIN_R_CYCLE, p.opts.rtol, p.opts.max_cycles, s);
+            launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, FIN_R_CYCLE, p.opts.rtol,
+                            p.opts.max_cycles, p.nblk, s);
         }
     }
 }
@@ -558,11 +555,11 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const JobList& l0 = D.l0_cell.dev;
-        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
-        launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
+        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, p.opts.rtol,
+                     p.opts.max_cycles, p.nblk, s);
         for (auto& c : D.coarsen) launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
-        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, p.nblk, s);
-        launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles,
+                        p.nblk, s);
     }
     FLD_HIP(hipGetLastError());
     // V-cycles in rounds: each round replays `burst` cycles, then reads back how
@@ -587,8 +584,8 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
             // and restart the grids whose true residual is still above the target
             for (auto& D : p.dl) {
                 if (D.l0_cell.empty()) continue;
-                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, p.nblk, s);
-                launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
+                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, FIN_R_VERIFY, p.opts.rtol,
+                                p.opts.max_cycles, p.nblk, s);
             }
             launch_count(p.dS, G, p.dCtrl, s);
             FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
@@ -690,7 +687,8 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level) launch_smooth(D.dim, p.mixed, p.dL, p.dS, D.smooth[level].dev, 0, p.nblk, s);
                     break;
                 case FLD_KERNEL_RESIDUAL:
-                    launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 0, 0, p.nblk, s);
+                    launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 0, 0, -1, p.opts.rtol,
+                                    p.opts.max_cycles, p.nblk, s);
                     break;
                 case FLD_KERNEL_RESTRICT:
                     if (has_level) launch_restrict(D.dim, p.mixed, p.dL, p.dS, D.restrict_[level].dev, p.nblk, s);
@@ -699,7 +697,8 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level) launch_prolong(D.dim, p.mixed, p.dL, p.dS, D.prolong[level].dev, p.nblk, s);
                     break;
                 case FLD_KERNEL_COEFF:
-                    launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
+                    launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
+                                 p.opts.rtol, p.opts.max_cycles, p.nblk, s);
                     break;
                 case FLD_KERNEL_DOWN:
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0, p.nblk, s);
@@ -903,8 +902,8 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
         FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(fld::StepIO), hipMemcpyHostToDevice, s));
         for (auto& D : p.dl) {
             if (D.l0_cell.empty()) continue;
-            fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter, p.nblk, s);
-            fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
+            fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
+                              p.opts.rtol, p.opts.max_cycles, p.nblk, s);
             for (auto& c : D.coarsen) fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
         }
         FLD_HIP(hipGetLastError());
