@@ -137,7 +137,7 @@ struct Control {
 // Reductions finish on the device: the block that completes a grid's last tile sums
 // the grid's tile partials in a fixed order and applies the FinMode update.
 void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
-                  const StepIO* io, double c, int limiter, double rtol, int max_cycles, int nblk,
+                  const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s);
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
                      int max_cycles, hipStream_t s);
@@ -170,15 +170,16 @@ constexpr size_t kTailLdsBudget = 150 * 1024;
 // select: 0 = active grids, 1 = grids whose status is FLD_OK (convergence check).
 // zero_x: also clear the level-0 V-cycle iterate (FP64 or FP32 by `mixed`); mixed also
 // writes the FP32 right-hand side.
-// fin: FinMode applied by the last block (-1: none, for timing).
+// fin: FinMode applied by the block that finishes a grid's last tile (-1: none;
+// a separate launch_finalize finishes the reduction).
 void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
                      int select, int zero_x, int fin, double rtol, int max_cycles, int nblk, hipStream_t s);
-void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
                   int max_cycles, int nblk, hipStream_t s);
-void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
                   int max_cycles, int nblk, hipStream_t s);
-void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol,
-                      int max_cycles, int nblk, hipStream_t s);
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
+                  int max_cycles, int nblk, hipStream_t s);
 void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,

@@ -181,7 +181,9 @@ __device__ __forceinline__ void sum_parts_coherent(const double* part, int ntile
 }
 
 // End of a reducing kernel's tile: store the partial(s) and, if this was the
-// grid's last tile, finish the reduction (fin < 0: store only).
+// grid's last tile, finish the reduction (fin < 0: store only, a k_finalize
+// launch finishes).  Counting tiles costs one same-address atomic per tile, so
+// the host uses it for grids of a few tiles only.
 __device__ __forceinline__ void tile_reduce_finish(const LevelDesc& d, GridState& g, int lt, int ntiles,
                                                    double a, double b, int stride, int fin, double rtol,
                                                    int max_cycles, double* sh, int* flag) {
@@ -258,7 +260,7 @@ __device__ __forceinline__ double face_w(double DL, double DR, double dt, double
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
-        const StepIO* __restrict__ io, double c, int limiter, double rtol, int max_cycles) {
+        const StepIO* __restrict__ io, double c, int limiter, int fin, double rtol, int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
     for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
@@ -296,7 +298,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
             s2 = e * e;
             s1 = e;
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, FIN_B, rtol,
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -1073,7 +1075,7 @@ __device__ __forceinline__ double z_at(const LevelDesc& d, long idx) {
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fin, double rtol,
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
@@ -1089,14 +1091,14 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             a = d.R[idx] * z_at<MIXED>(d, idx);
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, FIN_RZ, rtol,
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fin, double rtol,
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
@@ -1132,14 +1134,14 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
             d.Q[idx] = q;
             pq = pc * q;
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, FIN_PQ, rtol,
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, double rtol,
+k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fin, double rtol,
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
@@ -1167,7 +1169,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
                 d.x[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, FIN_CG, rtol,
+        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -1301,13 +1303,13 @@ inline int blocks_for(int total, int nblk) { return total < nblk ? (total > 0 ? 
     do { if ((dim) == 3) { constexpr int D = 3; __VA_ARGS__; } else { constexpr int D = 2; __VA_ARGS__; } } while (0)
 
 void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
-                  const StepIO* io, double c, int limiter, double rtol, int max_cycles, int nblk,
+                  const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, rtol, max_cycles);
-        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, rtol, max_cycles);
+        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
+        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
     });
 }
 
@@ -1426,21 +1428,21 @@ void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobL
     if (jl.total <= 0) return;                                                                       \
     const int g = blocks_for(jl.total, nblk);                                                        \
     FLD_DISPATCH_DIM(dim, {                                                                          \
-        if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, rtol, max_cycles); \
-        else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, rtol, max_cycles);      \
+        if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles); \
+        else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles);      \
     })
 
-void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
+void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_rz);
 }
 
-void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
+void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_pq);
 }
 
-void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, double rtol, int max_cycles, int nblk,
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                       hipStream_t s) {
     FLD_CG_LAUNCH(k_cg_update);
 }

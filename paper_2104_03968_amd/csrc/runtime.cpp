@@ -58,6 +58,7 @@ struct DimLists {
     HostList coarsest;                         // coarsest level of grids without a tail
     HostList tail;                             // first tail level of grids with a tail
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
+    bool fin_fused = false;                    // finish reductions in the last block (small grids)
     int maxdepth = 0;
 };
 
@@ -286,6 +287,11 @@ static void build_lists(Plan& p) {
         finish_list(D.l0_cell, p.levels, tiles_cell);
         finish_list(D.coarsest, p.levels, tiles_one);
         finish_list(D.tail, p.levels, tiles_one);
+        // one same-address atomic per tile is cheaper than a finalize launch only for a few tiles
+        int max_tiles = 0;
+        for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
+            max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
+        D.fin_fused = max_tiles <= 32;
         D.fused = D.dim == 2 && p.opts.fused && fused2_supported(p.opts.nu1) && fused2_supported(p.opts.nu2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
@@ -431,13 +437,20 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
         }
         const JobList& l0 = D.l0_cell.dev;
         if (p.krylov) {
-            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
-            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
-            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+            const double rt = p.opts.rtol;
+            const int mc = p.opts.max_cycles;
+            const bool ff = D.fin_fused;
+            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, p.nblk, s);
+            if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
+            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, p.nblk, s);
+            if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, p.nblk, s);
+            if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_CG, rt, mc, s);
         } else {
             if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, p.nblk, s);
-            launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, FIN_R_CYCLE, p.opts.rtol,
-                            p.opts.max_cycles, p.nblk, s);
+            launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, D.fin_fused ? FIN_R_CYCLE : -1,
+                            p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+            if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_CYCLE, p.opts.rtol, p.opts.max_cycles, s);
         }
     }
 }
@@ -555,11 +568,13 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const JobList& l0 = D.l0_cell.dev;
-        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, p.opts.rtol,
-                     p.opts.max_cycles, p.nblk, s);
+        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, D.fin_fused ? FIN_B : -1,
+                     p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+        if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
         for (auto& c : D.coarsen) launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
-        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles,
-                        p.nblk, s);
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, D.fin_fused ? FIN_R_INIT : -1, p.opts.rtol,
+                        p.opts.max_cycles, p.nblk, s);
+        if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
     }
     FLD_HIP(hipGetLastError());
     // V-cycles in rounds: each round replays `burst` cycles, then reads back how
@@ -584,8 +599,10 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
             // and restart the grids whose true residual is still above the target
             for (auto& D : p.dl) {
                 if (D.l0_cell.empty()) continue;
-                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, FIN_R_VERIFY, p.opts.rtol,
-                                p.opts.max_cycles, p.nblk, s);
+                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, D.fin_fused ? FIN_R_VERIFY : -1,
+                                p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                if (!D.fin_fused)
+                    launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
             }
             launch_count(p.dS, G, p.dCtrl, s);
             FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
@@ -698,7 +715,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_COEFF:
                     launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
-                                 p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                                 -1, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
                     break;
                 case FLD_KERNEL_DOWN:
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0, p.nblk, s);
@@ -903,7 +920,9 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
         for (auto& D : p.dl) {
             if (D.l0_cell.empty()) continue;
             fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
-                              p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                              D.fin_fused ? fld::FIN_B : -1, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+            if (!D.fin_fused)
+                fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
             for (auto& c : D.coarsen) fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
         }
         FLD_HIP(hipGetLastError());

@@ -82,14 +82,17 @@ def test_hierarchy_levels_and_workspace_scaling():
     # the coarse levels x, b, w_x, w_y on N/3 cells in total
     N = 1024 * 1024
     sizes = {}
-    for kw in (dict(), dict(krylov=0), dict(precision=1), dict(precision=1, krylov=0)):
+    for kw in (dict(fused=0), dict(krylov=0, fused=0), dict(precision=1, fused=0), dict()):
         h = fld.fld_plan_create([fld.make_grid((1024, 1024))], fld.fld_opts_default(**kw))
         sizes[tuple(kw.items())] = fld.fld_plan_workspace_bytes(h) / N
         fld.fld_plan_destroy(h)
-    cg64, mg64 = sizes[()], sizes[(("krylov", 0),)]
+    cg64, mg64 = sizes[(("fused", 0),)], sizes[(("krylov", 0), ("fused", 0))]
     assert 8 * 9 + 32 / 3 <= cg64 <= 8 * 9 + 32 / 3 + 1
     assert 8 * 5 + 32 / 3 <= mg64 <= 8 * 5 + 32 / 3 + 1
-    cg32 = sizes[(("precision", 1),)]
+    # fused 2D levels keep the down pass's output apart: one more array on every level
+    # that has a coarser one (~4/3 N cells)
+    assert cg64 + 8 * 4 / 3 - 1 <= sizes[()] <= cg64 + 8 * 4 / 3 + 1
+    cg32 = sizes[(("precision", 1), ("fused", 0))]
     # FP64 w_x, w_y, X, B0, R, P0, P1, Q at level 0, FP64 coarse weights, FP32 hierarchy
     assert 8 * 8 + 16 / 3 + 16 * 4 / 3 <= cg32 <= 8 * 8 + 16 / 3 + 16 * 4 / 3 + 1
 
