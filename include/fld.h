@@ -230,6 +230,79 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
 int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps,
                            void* stream, double* avg_ms, int64_t* cells);
 
+/* ---- request server: continuous batching of independent solves ---------- *
+ * A server owns a worker thread and one HIP stream on the device current at
+ * creation.  Requests (one diffusion step of one 2D or 3D grid each, the
+ * operation of fld_step) are admitted in arrival order when a slot is free and
+ * the caller's arena has room for the request's multigrid workspace, a copy of
+ * its inputs and its result; until then they wait (no request is refused for a
+ * full arena unless it could never fit).  Admitted requests iterate together:
+ * every multigrid phase is one launch over all resident requests, and requests
+ * join and leave at iteration boundaries.  A request's result is the same
+ * whether it runs alone or among others (same kernels, tiles and reduction
+ * orders per grid).  All server calls are thread-safe. */
+typedef struct fld_server_s* fld_server_t;
+
+typedef struct fld_server_opts {
+    int32_t max_slots;        /* requests resident on the device at once [64]          */
+    int32_t precision;        /* FLD_PREC_* for every request [MIXED]                  */
+    double  rtol;             /* relative FP64 residual target [1e-10]                 */
+    int32_t max_cycles;       /* V-cycles per request [50]                             */
+    double  c;                /* speed of light [1]                                    */
+    int32_t limiter;          /* FLD_LIMITER_* [LP]                                    */
+    int32_t cycles_per_round; /* iterations between admission / retirement points [2]  */
+} fld_server_opts;
+
+typedef struct fld_request {
+    fld_grid      grid;
+    double        dt;
+    const double* E_in;       /* N doubles: E^n                                        */
+    const double* kappa_rho;  /* N doubles                                             */
+    int32_t       inputs_on_device;  /* 1: device pointers, read when the request is
+                                        admitted, so they must stay valid and unchanged
+                                        until it is done; 0: host pointers, copied by
+                                        fld_submit before it returns                    */
+} fld_request;
+
+typedef struct fld_result {
+    double*   E_out;          /* device pointer to N doubles inside the arena, valid
+                                 until fld_release                                     */
+    fld_stats stats;
+    double    t_submit;       /* seconds on the library's steady clock                 */
+    double    t_admit;        /* slot and arena space granted                          */
+    double    t_start;        /* first kernels enqueued                                */
+    double    t_done;         /* result written                                        */
+} fld_result;
+
+typedef struct fld_server_info {
+    int64_t submitted, admitted, completed, failed, rounds, cells_done;
+    int32_t pending, resident;
+    size_t  arena_bytes, arena_free;
+    int32_t error;            /* FLD_OK, or the error that stopped the worker          */
+} fld_server_info;
+
+void fld_server_opts_default(fld_server_opts* o);
+/* arena_dev: caller-owned device memory (256-byte aligned) the server carves all
+   its device buffers from; kept until fld_server_destroy.  Errors: INVALID_ARG,
+   TOO_LARGE (arena smaller than the server's tables), HIP. */
+int32_t fld_server_create(const fld_server_opts* opts, void* arena_dev, size_t arena_bytes,
+                          fld_server_t* out);
+/* Stops the worker (requests in flight are abandoned) and frees host state.
+   The arena is not touched afterwards. */
+int32_t fld_server_destroy(fld_server_t server);
+/* Queue one request; *ticket identifies it.  Errors: INVALID_ARG (grid, dt,
+   pointers), TOO_LARGE (can never fit the arena), SHUTDOWN, HIP (worker failed). */
+int32_t fld_submit(fld_server_t server, const fld_request* req, uint64_t* ticket);
+/* FLD_PENDING while queued or running; otherwise the request's final status
+   (FLD_OK, NOT_CONVERGED, BAD_INPUT, HIP) with *out filled.  UNKNOWN_TICKET for
+   tickets never issued or already released. */
+int32_t fld_poll(fld_server_t server, uint64_t ticket, fld_result* out);
+/* As fld_poll, blocking up to timeout_s seconds for the request to finish. */
+int32_t fld_wait(fld_server_t server, uint64_t ticket, double timeout_s, fld_result* out);
+/* Return a finished request's result buffer to the arena (PENDING if not finished). */
+int32_t fld_release(fld_server_t server, uint64_t ticket);
+int32_t fld_server_info_get(fld_server_t server, fld_server_info* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,32 @@ class fld_level_view(C.Structure):
                 ("w32", C.c_void_p * 3)]
 
 
+class fld_server_opts(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("precision", C.c_int32), ("rtol", C.c_double),
+                ("max_cycles", C.c_int32), ("c", C.c_double), ("limiter", C.c_int32),
+                ("cycles_per_round", C.c_int32)]
+
+
+class fld_request(C.Structure):
+    _fields_ = [("grid", fld_grid), ("dt", C.c_double), ("E_in", C.c_void_p), ("kappa_rho", C.c_void_p),
+                ("inputs_on_device", C.c_int32)]
+
+
+class fld_result(C.Structure):
+    _fields_ = [("E_out", C.c_void_p), ("stats", fld_stats), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class fld_server_info(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("rounds", C.c_int64), ("cells_done", C.c_int64),
+                ("pending", C.c_int32), ("resident", C.c_int32), ("arena_bytes", C.c_size_t),
+                ("arena_free", C.c_size_t), ("error", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = C.c_void_p
 _PP = C.POINTER(C.c_void_p)
 _sig = {
@@ -102,6 +128,14 @@ _sig = {
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
     "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
+    "fld_server_opts_default": (None, [C.POINTER(fld_server_opts)]),
+    "fld_server_create": (C.c_int32, [C.POINTER(fld_server_opts), _P, C.c_size_t, _PP]),
+    "fld_server_destroy": (C.c_int32, [_P]),
+    "fld_submit": (C.c_int32, [_P, C.POINTER(fld_request), C.POINTER(C.c_uint64)]),
+    "fld_poll": (C.c_int32, [_P, C.c_uint64, C.POINTER(fld_result)]),
+    "fld_wait": (C.c_int32, [_P, C.c_uint64, C.c_double, C.POINTER(fld_result)]),
+    "fld_release": (C.c_int32, [_P, C.c_uint64]),
+    "fld_server_info_get": (C.c_int32, [_P, C.POINTER(fld_server_info)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -253,6 +287,115 @@ def fld_profile_kernel(plan: int, kernel: int, level: int = 0, reps: int = 100, 
     _check(_lib.fld_profile_kernel(plan, kernel, level, reps, _stream(stream), C.byref(ms), C.byref(cells)),
            "fld_profile_kernel")
     return ms.value, cells.value
+
+
+def fld_server_opts_default(**kw) -> fld_server_opts:
+    o = fld_server_opts()
+    _lib.fld_server_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def fld_server_create(opts: fld_server_opts, arena_ptr: int, arena_bytes: int) -> int:
+    out = C.c_void_p()
+    _check(_lib.fld_server_create(C.byref(opts), arena_ptr, arena_bytes, C.byref(out)), "fld_server_create")
+    return out.value
+
+
+def fld_server_destroy(server: int) -> None:
+    _check(_lib.fld_server_destroy(server), "fld_server_destroy")
+
+
+def fld_submit(server: int, grid: fld_grid, dt: float, E_in, kappa_rho, on_device: bool = True):
+    """Returns (status, ticket)."""
+    req = fld_request()
+    req.grid = grid
+    req.dt = float(dt)
+    req.E_in = E_in if isinstance(E_in, int) else (E_in.data_ptr() if on_device else
+                                                   E_in.ctypes.data)
+    req.kappa_rho = kappa_rho if isinstance(kappa_rho, int) else (kappa_rho.data_ptr() if on_device else
+                                                                  kappa_rho.ctypes.data)
+    req.inputs_on_device = 1 if on_device else 0
+    t = C.c_uint64()
+    rc = _lib.fld_submit(server, C.byref(req), C.byref(t))
+    return rc, t.value
+
+
+def fld_poll(server: int, ticket: int):
+    """Returns (status, fld_result)."""
+    r = fld_result()
+    rc = _lib.fld_poll(server, ticket, C.byref(r))
+    return rc, r
+
+
+def fld_wait(server: int, ticket: int, timeout_s: float = 60.0):
+    r = fld_result()
+    rc = _lib.fld_wait(server, ticket, float(timeout_s), C.byref(r))
+    return rc, r
+
+
+def fld_release(server: int, ticket: int) -> int:
+    return _lib.fld_release(server, ticket)
+
+
+def fld_server_info_get(server: int) -> dict:
+    i = fld_server_info()
+    _check(_lib.fld_server_info_get(server, C.byref(i)), "fld_server_info_get")
+    return i.as_dict()
+
+
+class Server:
+    """A request server over a torch-owned device arena of ``arena_bytes``."""
+
+    def __init__(self, arena_bytes: int, device=None, **opts):
+        import torch
+        self.device = torch.device(device if device is not None else "cuda")
+        self.opts = fld_server_opts_default(**opts)
+        with torch.cuda.device(self.device):
+            self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+            self.handle = fld_server_create(self.opts, self.arena.data_ptr(), int(arena_bytes))
+
+    def submit(self, E_in, kappa_rho, dt: float, h=None, on_device: bool = True):
+        """E_in, kappa_rho: (ny, nx) / (nz, ny, nx) float64 tensors (device) or arrays (host)."""
+        shape = tuple(E_in.shape)
+        grid = make_grid(tuple(reversed(shape)), h)
+        rc, t = fld_submit(self.handle, grid, dt, E_in, kappa_rho, on_device)
+        _check(rc, "fld_submit")
+        return t
+
+    def result_tensor(self, res: fld_result, shape):
+        """A torch view of a finished request's result buffer (inside the arena)."""
+        import torch
+        n = 1
+        for s in shape:
+            n *= s
+        off = res.E_out - self.arena.data_ptr()
+        return self.arena[off: off + 8 * n].view(torch.float64).view(tuple(shape))
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        return fld_wait(self.handle, ticket, timeout_s)
+
+    def poll(self, ticket: int):
+        return fld_poll(self.handle, ticket)
+
+    def release(self, ticket: int):
+        return fld_release(self.handle, ticket)
+
+    def info(self) -> dict:
+        return fld_server_info_get(self.handle)
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h:
+            fld_server_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- convenience wrapper -----------------------------------------------------------

@@ -1,0 +1,144 @@
+// Host-side internals of the FLD runtime shared by the plan C ABI (runtime.cpp)
+// and the request server (server.cpp): plans, work-lists, workspace layout and
+// the step drivers.
+#pragma once
+
+#include "fld_device.hpp"
+#include "fld.h"
+
+#include <string>
+#include <vector>
+
+namespace fld {
+
+extern thread_local std::string g_last_error;
+void set_error(const char* where, hipError_t e);
+
+#define FLD_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) {                         \
+            ::fld::set_error(#call, e_);                \
+            return FLD_ERR_HIP;                         \
+        }                                               \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Device-side work-list storage: levels[] and prefix[] of one JobList.
+struct HostList {
+    std::vector<int32_t> levels;
+    std::vector<int32_t> prefix;   // size levels.size() + 1
+    size_t off_levels = 0, off_prefix = 0;
+    JobList dev{};                 // filled at bind
+
+    bool empty() const { return levels.empty(); }
+};
+
+// One dimension's worth of work-lists (2D and 3D grids run in separate launches).
+struct DimLists {
+    int dim = 0;
+    HostList l0_cell;                          // level 0, cell tiles
+    std::vector<HostList> smooth;              // per depth, smoother tiles
+    std::vector<HostList> restrict_;           // per depth, cell tiles of the coarse level
+    std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
+    std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
+    std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
+    bool fused = false;
+    HostList coarsest;                         // coarsest level of grids without a tail
+    HostList tail;                             // first tail level of grids with a tail
+    size_t tail_smem = 0;                      // LDS bytes of the largest tail
+    bool fin_fused = false;                    // finish reductions in the last block (small grids)
+    int maxdepth = 0;
+};
+
+struct Plan {
+    int device = 0;
+    fld_opts opts{};
+    std::vector<fld_grid> grids;
+    std::vector<LevelDesc> levels;             // host copy (device pointers after bind)
+    std::vector<int32_t> level0;               // LevelDesc index of each grid's level 0
+    std::vector<int32_t> nlev;                 // levels per grid
+    std::vector<int64_t> ncell;                // cells per grid
+    std::vector<int32_t> tail_lev;             // first tail level of each grid (-1: no tail)
+    DimLists dl[2];                            // [0] = 2D, [1] = 3D
+    bool mixed = false;
+    bool krylov = true;
+
+    // workspace layout (byte offsets)
+    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_ctrl = 0;
+    size_t ws_bytes = 0;
+    static constexpr int kExSlots = 4;
+    struct FieldOff {
+        size_t x = 0, b = 0, w[3] = {0, 0, 0}, x32 = 0, b32 = 0, w32[3] = {0, 0, 0}, part = 0, scratch = 0;
+        size_t X = 0, B0 = 0, R = 0, P[2] = {0, 0}, Q = 0, xs = 0;
+        bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
+        bool has_xs = false;
+        bool lev0 = false, has_cg = false;
+    };
+    std::vector<FieldOff> foff;                // per level (relative to the grid's field base)
+    std::vector<size_t> field_off;             // byte offset of each grid's fields in the workspace
+    std::vector<size_t> field_bytes;           // bytes of each grid's fields
+    std::vector<char*> field_base;             // if set: each grid's fields live here instead
+    size_t table_bytes = 0;                    // descriptor / list region at the workspace start
+
+    // bound state
+    char* ws = nullptr;
+    LevelDesc* dL = nullptr;
+    GridState* dS = nullptr;
+    StepIO* dIO = nullptr;
+    ExchangeIO* dEx = nullptr;
+    Control* dCtrl = nullptr;
+    StepIO* hIO = nullptr;                     // pinned staging
+    ExchangeIO* hEx = nullptr;                 // pinned staging, kExSlots * ngrids
+    Control* hCtrl = nullptr;                  // pinned
+    GridState* hS = nullptr;                   // pinned
+    bool own_pinned = true;                    // false: staging buffers belong to a server
+    hipEvent_t ex_done[kExSlots] = {};
+    int ex_slot = 0;
+    int ex_last = -1;                          // slot of the last fld_exchange (profiling)
+    int64_t max_n = 0;
+    int nblk = 2048;
+    int last_cycles = 0;                       // cycles of the previous step (replay sizing)
+
+    fld_gas last_gas{};                        // constants of the last fld_exchange (profiling)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    ~Plan();
+    int ngrids() const { return (int)grids.size(); }
+};
+
+inline Plan::~Plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& e : ex_done)
+        if (e) (void)hipEventDestroy(e);
+    if (own_pinned) {
+        if (hIO) (void)hipHostFree(hIO);
+        if (hEx) (void)hipHostFree(hEx);
+        if (hCtrl) (void)hipHostFree(hCtrl);
+        if (hS) (void)hipHostFree(hS);
+    }
+}
+
+
+// Plan construction: hierarchy, work-lists and workspace layout (host only).
+int validate_opts(const fld_opts& o);
+int validate_grid(const fld_grid& g);
+int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts);
+// Bind device memory: tables at `dev`; fields at `dev` too unless field_base is set.
+// init: initial per-grid solver states (nullptr: fresh).  Synchronous.
+int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init);
+// Per-step phases, asynchronous on s (the StepIO table must be on the device).
+int plan_prologue(Plan& p, hipStream_t s);               // coefficients, norms, initial residual
+void plan_cycle(Plan& p, hipStream_t s);                 // one V-cycle (+ CG update) for active grids
+void plan_verify(Plan& p, hipStream_t s);                // true residual of grids CG reported converged
+void plan_output(Plan& p, hipStream_t s);                // X -> E_out
+void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* out);
+int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s);
+
+}  // namespace fld

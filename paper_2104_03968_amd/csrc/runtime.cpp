@@ -6,8 +6,7 @@
 // Nothing here allocates device memory: every device buffer lives in the
 // workspace the caller binds (a torch tensor in the Python binding).  Host
 // allocations are plain C++ containers plus a few pinned staging buffers.
-#include "fld_device.hpp"
-#include "fld.h"
+#include "fld_internal.hpp"
 
 #include <algorithm>
 #include <cstddef>
@@ -28,113 +27,6 @@ void set_error(const char* where, hipError_t e) {
     g_last_error = buf;
 }
 
-namespace {
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Device-side work-list storage: levels[] and prefix[] of one JobList.
-struct HostList {
-    std::vector<int32_t> levels;
-    std::vector<int32_t> prefix;   // size levels.size() + 1
-    size_t off_levels = 0, off_prefix = 0;
-    JobList dev{};                 // filled at bind
-
-    bool empty() const { return levels.empty(); }
-};
-
-}  // namespace
-
-// One dimension's worth of work-lists (2D and 3D grids run in separate launches).
-struct DimLists {
-    int dim = 0;
-    HostList l0_cell;                          // level 0, cell tiles
-    std::vector<HostList> smooth;              // per depth, smoother tiles
-    std::vector<HostList> restrict_;           // per depth, cell tiles of the coarse level
-    std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
-    std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
-    std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
-    bool fused = false;
-    HostList coarsest;                         // coarsest level of grids without a tail
-    HostList tail;                             // first tail level of grids with a tail
-    size_t tail_smem = 0;                      // LDS bytes of the largest tail
-    bool fin_fused = false;                    // finish reductions in the last block (small grids)
-    int maxdepth = 0;
-};
-
-struct Plan {
-    int device = 0;
-    fld_opts opts{};
-    std::vector<fld_grid> grids;
-    std::vector<LevelDesc> levels;             // host copy (device pointers after bind)
-    std::vector<int32_t> level0;               // LevelDesc index of each grid's level 0
-    std::vector<int32_t> nlev;                 // levels per grid
-    std::vector<int64_t> ncell;                // cells per grid
-    std::vector<int32_t> tail_lev;             // first tail level of each grid (-1: no tail)
-    DimLists dl[2];                            // [0] = 2D, [1] = 3D
-    bool mixed = false;
-    bool krylov = true;
-
-    // workspace layout (byte offsets)
-    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_ctrl = 0;
-    size_t ws_bytes = 0;
-    static constexpr int kExSlots = 4;
-    struct FieldOff {
-        size_t x = 0, b = 0, w[3] = {0, 0, 0}, x32 = 0, b32 = 0, w32[3] = {0, 0, 0}, part = 0, scratch = 0;
-        size_t X = 0, B0 = 0, R = 0, P[2] = {0, 0}, Q = 0, xs = 0;
-        bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
-        bool has_xs = false;
-        bool lev0 = false, has_cg = false;
-    };
-    std::vector<FieldOff> foff;                // per level
-
-    // bound state
-    char* ws = nullptr;
-    LevelDesc* dL = nullptr;
-    GridState* dS = nullptr;
-    StepIO* dIO = nullptr;
-    ExchangeIO* dEx = nullptr;
-    Control* dCtrl = nullptr;
-    StepIO* hIO = nullptr;                     // pinned staging
-    ExchangeIO* hEx = nullptr;                 // pinned staging, kExSlots * ngrids
-    Control* hCtrl = nullptr;                  // pinned
-    GridState* hS = nullptr;                   // pinned
-    hipEvent_t ex_done[kExSlots] = {};
-    int ex_slot = 0;
-    int ex_last = -1;                          // slot of the last fld_exchange (profiling)
-    int64_t max_n = 0;
-    int nblk = 2048;
-    int last_cycles = 0;                       // cycles of the previous step (replay sizing)
-
-    fld_gas last_gas{};                        // constants of the last fld_exchange (profiling)
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-
-    ~Plan();
-    int ngrids() const { return (int)grids.size(); }
-};
-
-Plan::~Plan() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (auto& e : ex_done)
-        if (e) (void)hipEventDestroy(e);
-    if (hIO) (void)hipHostFree(hIO);
-    if (hEx) (void)hipHostFree(hEx);
-    if (hCtrl) (void)hipHostFree(hCtrl);
-    if (hS) (void)hipHostFree(hS);
-}
-
-#define FLD_HIP(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) {                         \
-            ::fld::set_error(#call, e_);                \
-            return FLD_ERR_HIP;                         \
-        }                                               \
-    } while (0)
 
 namespace {
 
@@ -151,6 +43,8 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
+
+}  // namespace
 
 int validate_opts(const fld_opts& o) {
     if (!(o.c > 0.0) || !std::isfinite(o.c)) return FLD_ERR_INVALID_ARG;
@@ -178,6 +72,8 @@ int validate_grid(const fld_grid& g) {
     if (n > (int64_t(1) << 31) - 1) return FLD_ERR_INVALID_ARG;   // 32-bit tile/cell indices
     return FLD_OK;
 }
+
+namespace {
 
 void finish_list(HostList& l, const std::vector<LevelDesc>& L, int (*tiles)(const LevelDesc&)) {
     l.prefix.assign(1, 0);
@@ -326,6 +222,26 @@ static void build_lists(Plan& p) {
     }
 }
 
+static void layout(Plan& p);
+
+int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) {
+    int rc = validate_opts(opts);
+    if (rc != FLD_OK) return rc;
+    for (int g = 0; g < ngrids; ++g)
+        if ((rc = validate_grid(grids[g])) != FLD_OK) return rc;
+    if (hipGetDevice(&p.device) != hipSuccess) p.device = 0;
+    p.opts = opts;
+    p.mixed = opts.precision == FLD_PREC_MIXED;
+    p.krylov = opts.krylov != 0;
+    p.grids.assign(grids, grids + ngrids);
+    for (auto& g : p.grids)
+        if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
+    build_levels(p);
+    build_lists(p);
+    layout(p);
+    return FLD_OK;
+}
+
 static void layout(Plan& p) {
     const int G = p.ngrids();
     const size_t NL = p.levels.size();
@@ -350,9 +266,17 @@ static void layout(Plan& p) {
         for (auto& l : D.restrict_) place_list(l);
         for (auto& l : D.prolong) place_list(l);
     }
+    p.table_bytes = off;
     p.foff.assign(NL, Plan::FieldOff{});
-    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    p.field_off.assign(G, 0);
+    p.field_bytes.assign(G, 0);
+    // each grid's fields are laid out from its own origin (offset 0), so a grid can
+    // live at any address (the server places requests in its arena)
+    size_t goff = 0;
+    auto take = [&](size_t bytes) { size_t o = goff; goff = align_up(goff + bytes); return o; };
     for (size_t li = 0; li < NL; ++li) {
+        if (p.levels[li].level == 0) goff = 0;
+        const int gcur = p.levels[li].grid;
         const LevelDesc& d = p.levels[li];
         Plan::FieldOff& f = p.foff[li];
         const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
@@ -399,6 +323,11 @@ static void layout(Plan& p) {
             f.has_xs = true;
             f.xs = take(n * (p.mixed ? 4 : 8));
         }
+        p.field_bytes[gcur] = goff;
+    }
+    for (int g = 0; g < G; ++g) {
+        p.field_off[g] = off;
+        if (p.field_base.empty()) off = align_up(off + p.field_bytes[g]);
     }
     p.ws_bytes = off;
 }
@@ -468,20 +397,21 @@ static int capture_graph(Plan& p) {
     return FLD_OK;
 }
 
-static int bind(Plan& p, void* dev, size_t bytes) {
+int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     if (!dev) return FLD_ERR_INVALID_ARG;
     if (bytes < p.ws_bytes) return FLD_ERR_NO_WORKSPACE;
     if ((reinterpret_cast<uintptr_t>(dev) % kAlign) != 0) return FLD_ERR_INVALID_ARG;
     p.ws = static_cast<char*>(dev);
-    char* ws = p.ws;
-    p.dL = reinterpret_cast<LevelDesc*>(ws + p.off_levels);
-    p.dS = reinterpret_cast<GridState*>(ws + p.off_state);
-    p.dIO = reinterpret_cast<StepIO*>(ws + p.off_stepio);
-    p.dEx = reinterpret_cast<ExchangeIO*>(ws + p.off_exio);
-    p.dCtrl = reinterpret_cast<Control*>(ws + p.off_ctrl);
+    char* const tab = p.ws;
+    p.dL = reinterpret_cast<LevelDesc*>(tab + p.off_levels);
+    p.dS = reinterpret_cast<GridState*>(tab + p.off_state);
+    p.dIO = reinterpret_cast<StepIO*>(tab + p.off_stepio);
+    p.dEx = reinterpret_cast<ExchangeIO*>(tab + p.off_exio);
+    p.dCtrl = reinterpret_cast<Control*>(tab + p.off_ctrl);
     for (size_t li = 0; li < p.levels.size(); ++li) {
         LevelDesc& d = p.levels[li];
         const Plan::FieldOff& f = p.foff[li];
+        char* const ws = p.field_base.empty() ? p.ws + p.field_off[d.grid] : p.field_base[d.grid];
         for (int a = 0; a < 3; ++a) {
             d.w[a] = a < d.ndim ? reinterpret_cast<double*>(ws + f.w[a]) : nullptr;
             d.w32[a] = (p.mixed && a < d.ndim) ? reinterpret_cast<float*>(ws + f.w32[a]) : nullptr;
@@ -505,15 +435,16 @@ static int bind(Plan& p, void* dev, size_t bytes) {
     FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
     std::vector<GridState> st(p.ngrids());
     for (int g = 0; g < p.ngrids(); ++g) {
-        st[g] = GridState{};
+        st[g] = init ? init[g] : GridState{};
         st[g].ntiles0 = cell_tiles(p.levels[p.level0[g]].n);
+        st[g].done = 0;
     }
     FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
     Control c0{};
     FLD_HIP(hipMemcpy(p.dCtrl, &c0, sizeof(Control), hipMemcpyHostToDevice));
     auto upload = [&](HostList& l) -> int {
-        int32_t* lv = reinterpret_cast<int32_t*>(ws + l.off_levels);
-        int32_t* pf = reinterpret_cast<int32_t*>(ws + l.off_prefix);
+        int32_t* lv = reinterpret_cast<int32_t*>(tab + l.off_levels);
+        int32_t* pf = reinterpret_cast<int32_t*>(tab + l.off_prefix);
         if (!l.levels.empty())
             FLD_HIP(hipMemcpy(lv, l.levels.data(), l.levels.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -537,12 +468,8 @@ static int bind(Plan& p, void* dev, size_t bytes) {
         for (auto& l : D.prolong) if ((rc = upload(l)) != FLD_OK) return rc;
     }
     if (!p.hIO) FLD_HIP(hipHostMalloc((void**)&p.hIO, p.ngrids() * sizeof(StepIO), hipHostMallocDefault));
-    if (!p.hEx)
-        FLD_HIP(hipHostMalloc((void**)&p.hEx, Plan::kExSlots * p.ngrids() * sizeof(ExchangeIO), hipHostMallocDefault));
     if (!p.hCtrl) FLD_HIP(hipHostMalloc((void**)&p.hCtrl, sizeof(Control), hipHostMallocDefault));
     if (!p.hS) FLD_HIP(hipHostMalloc((void**)&p.hS, p.ngrids() * sizeof(GridState), hipHostMallocDefault));
-    for (auto& e : p.ex_done)
-        if (!e) FLD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     p.max_n = 0;
     for (auto n : p.ncell) p.max_n = std::max<int64_t>(p.max_n, n);
     if (p.opts.use_graph) {
@@ -552,18 +479,13 @@ static int bind(Plan& p, void* dev, size_t bytes) {
     return FLD_OK;
 }
 
-static int step(Plan& p, const double* const* E_in, const double* const* kr, double* const* E_out,
-                const double* dt, hipStream_t s, fld_stats* stats) {
-    const int G = p.ngrids();
-    for (int g = 0; g < G; ++g) {
-        if (!E_in[g] || !kr[g] || !E_out[g]) return FLD_ERR_INVALID_ARG;
-        if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
-        p.hIO[g].E_in = E_in[g];
-        p.hIO[g].kr = kr[g];
-        p.hIO[g].E_out = E_out[g];
-        p.hIO[g].dt = dt[g];
-    }
-    FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(StepIO), hipMemcpyHostToDevice, s));
+int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s) {
+    for (int g = 0; g < p.ngrids(); ++g) p.hIO[g] = io[g];
+    FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, p.ngrids() * sizeof(StepIO), hipMemcpyHostToDevice, s));
+    return FLD_OK;
+}
+
+int plan_prologue(Plan& p, hipStream_t s) {
     const int zero_x = (p.krylov || p.mixed) ? 1 : 0;
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
@@ -577,12 +499,58 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
     }
     FLD_HIP(hipGetLastError());
+    return FLD_OK;
+}
+
+void plan_cycle(Plan& p, hipStream_t s) { enqueue_cycle(p, s); }
+
+void plan_verify(Plan& p, hipStream_t s) {
+    // CG stopped on its recursive residual: confirm on the true FP64 residual and
+    // restart the grids whose true residual is still above the target
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, D.fin_fused ? FIN_R_VERIFY : -1,
+                        p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+        if (!D.fin_fused)
+            launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
+    }
+}
+
+void plan_output(Plan& p, hipStream_t s) {
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        launch_output(D.dim, p.dL, D.l0_cell.dev, p.dIO, p.nblk, s);
+    }
+}
+
+void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* o) {
+    // a grid still active after its iteration budget did not converge
+    o->cycles = st.cycles;
+    o->status = st.active ? FLD_ERR_NOT_CONVERGED : st.status;
+    o->rel_residual = st.bnorm2 > 0 ? std::sqrt(st.rnorm2 / st.bnorm2) : 0.0;
+    o->b_norm = std::sqrt(st.bnorm2);
+    o->b_sum = st.bsum;
+    const double N = (double)p.ncell[g];
+    o->q_b = (st.bsum != 0.0) ? std::sqrt(st.bnorm2) / (std::sqrt(N) * std::fabs(st.bsum / N)) : INFINITY;
+}
+
+static int step(Plan& p, const double* const* E_in, const double* const* kr, double* const* E_out,
+                const double* dt, hipStream_t s, fld_stats* stats) {
+    const int G = p.ngrids();
+    std::vector<StepIO> io(G);
+    for (int g = 0; g < G; ++g) {
+        if (!E_in[g] || !kr[g] || !E_out[g]) return FLD_ERR_INVALID_ARG;
+        if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+        io[g] = StepIO{E_in[g], kr[g], E_out[g], dt[g]};
+    }
+    int rc = plan_upload_io(p, io.data(), s);
+    if (rc != FLD_OK) return rc;
+    if ((rc = plan_prologue(p, s)) != FLD_OK) return rc;
     // V-cycles in rounds: each round replays `burst` cycles, then reads back how
     // many grids are still active.  The first burst is sized from the previous
     // step's cycle count so a typical step needs one or two host round trips.
     int done = 0;
     int burst = std::max(1, std::min(p.last_cycles > 0 ? p.last_cycles : 4, p.opts.max_cycles));
-    int used = 0;
     while (done < p.opts.max_cycles) {
         const int nrun = std::min(burst, p.opts.max_cycles - done);
         for (int r = 0; r < nrun; ++r) {
@@ -595,15 +563,7 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         FLD_HIP(hipStreamSynchronize(s));
         if (p.hCtrl->nactive == 0 && p.krylov) {
-            // CG stopped on its recursive residual: confirm on the true FP64 residual
-            // and restart the grids whose true residual is still above the target
-            for (auto& D : p.dl) {
-                if (D.l0_cell.empty()) continue;
-                launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, D.fin_fused ? FIN_R_VERIFY : -1,
-                                p.opts.rtol, p.opts.max_cycles, p.nblk, s);
-                if (!D.fin_fused)
-                    launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
-            }
+            plan_verify(p, s);
             launch_count(p.dS, G, p.dCtrl, s);
             FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
             FLD_HIP(hipStreamSynchronize(s));
@@ -611,32 +571,18 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         if (p.hCtrl->nactive == 0) break;
         burst = std::max(1, burst / 2);
     }
-    for (auto& D : p.dl) {
-        if (D.l0_cell.empty()) continue;
-        launch_output(D.dim, p.dL, D.l0_cell.dev, p.dIO, p.nblk, s);
-    }
+    plan_output(p, s);
     FLD_HIP(hipMemcpyAsync(p.hS, p.dS, G * sizeof(GridState), hipMemcpyDeviceToHost, s));
     FLD_HIP(hipStreamSynchronize(s));
-    int rc = FLD_OK;
+    rc = FLD_OK;
     int maxc = 0;
     for (int g = 0; g < G; ++g) {
-        const GridState& st = p.hS[g];
-        // a grid still active after max_cycles did not converge
-        const int status = st.active ? FLD_ERR_NOT_CONVERGED : st.status;
-        maxc = std::max(maxc, (int)st.cycles);
-        if (stats) {
-            fld_stats& o = stats[g];
-            o.cycles = st.cycles;
-            o.status = status;
-            o.rel_residual = st.bnorm2 > 0 ? std::sqrt(st.rnorm2 / st.bnorm2) : 0.0;
-            o.b_norm = std::sqrt(st.bnorm2);
-            o.b_sum = st.bsum;
-            const double N = (double)p.ncell[g];
-            o.q_b = (st.bsum != 0.0) ? std::sqrt(st.bnorm2) / (std::sqrt(N) * std::fabs(st.bsum / N)) : INFINITY;
-        }
-        if (rc == FLD_OK && status != FLD_OK) rc = status;
+        fld_stats o;
+        plan_stats(p, p.hS[g], g, &o);
+        maxc = std::max(maxc, (int)o.cycles);
+        if (stats) stats[g] = o;
+        if (rc == FLD_OK && o.status != FLD_OK) rc = o.status;
     }
-    (void)used;
     p.last_cycles = maxc;
     return rc;
 }
@@ -644,6 +590,10 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
 static int exchange(Plan& p, double* const* E, double* const* eps, const double* const* rho,
                     const double* const* kappa, const double* dt, const fld_gas& gas, hipStream_t s) {
     const int G = p.ngrids();
+    if (!p.hEx)
+        FLD_HIP(hipHostMalloc((void**)&p.hEx, Plan::kExSlots * G * sizeof(ExchangeIO), hipHostMallocDefault));
+    for (auto& e : p.ex_done)
+        if (!e) FLD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     p.last_gas = gas;
     const int slot = p.ex_slot;
     p.ex_slot = (p.ex_slot + 1) % Plan::kExSlots;
@@ -826,17 +776,11 @@ int32_t fld_plan_create(const fld_grid* grids, int32_t ngrids, const fld_opts* o
         for (int g = 0; g < ngrids; ++g)
             if ((rc = fld::validate_grid(grids[g])) != FLD_OK) return rc;
         auto* h = new fld_plan_s();
-        Plan& p = h->p;
-        if (hipGetDevice(&p.device) != hipSuccess) p.device = 0;
-        p.opts = *opts;
-        p.mixed = opts->precision == FLD_PREC_MIXED;
-        p.krylov = opts->krylov != 0;
-        p.grids.assign(grids, grids + ngrids);
-        for (auto& g : p.grids)
-            if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
-        fld::build_levels(p);
-        fld::build_lists(p);
-        fld::layout(p);
+        rc = fld::plan_init(h->p, grids, ngrids, *opts);
+        if (rc != FLD_OK) {
+            delete h;
+            return rc;
+        }
         *out = h;
         return FLD_OK;
     } catch (const std::bad_alloc&) {
@@ -865,7 +809,7 @@ int32_t fld_plan_bind_workspace(fld_plan_t plan, void* dev, size_t bytes) {
     try {
         fld::DeviceGuard dg(plan->p.device);
         if (!dg.ok) return FLD_ERR_HIP;
-        int rc = fld::bind(plan->p, dev, bytes);
+        int rc = fld::plan_bind(plan->p, dev, bytes, nullptr);
         if (rc != FLD_OK) plan->p.ws = nullptr;
         return rc;
     } catch (...) {

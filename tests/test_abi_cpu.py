@@ -132,3 +132,18 @@ def test_bind_rejects_small_or_null_workspace():
         fld.fld_plan_bind_workspace(h, 4096, nb - 1)
     assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
     fld.fld_plan_destroy(h)
+
+
+def test_server_defaults_and_argument_checks():
+    o = fld.fld_server_opts_default()
+    assert o.max_slots == 64 and o.precision == fld.FLD_PREC_MIXED and o.rtol == 1e-10
+    assert o.cycles_per_round == 2
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_server_create(o, 0, 1 << 20)
+    assert e.value.code == fld.FLD_ERR_INVALID_ARG
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_server_create(o, 4096 + 8, 1 << 20)          # misaligned arena
+    assert e.value.code == fld.FLD_ERR_INVALID_ARG
+    bad = fld.fld_server_opts_default(max_slots=0)
+    with pytest.raises(fld.FLDError):
+        fld.fld_server_create(bad, 4096, 1 << 20)
