@@ -27,8 +27,9 @@ def _run(server, items, on_device=True):
     tickets = []
     for g in items:
         if on_device:
-            tickets.append(server.submit(dev(g.E), dev(g.kappa_rho), g.dt, h=g.h, on_device=True))
-            tickets[-1] = (tickets[-1], None)
+            # device inputs are read at admission: keep them alive until the request is done
+            keep = (dev(g.E), dev(g.kappa_rho))
+            tickets.append((server.submit(keep[0], keep[1], g.dt, h=g.h, on_device=True), keep))
         else:
             E = np.ascontiguousarray(g.E)
             K = np.ascontiguousarray(g.kappa_rho)
@@ -104,7 +105,8 @@ def test_admission_waits_for_arena_space():
 
     th = threading.Thread(target=watch)
     th.start()
-    tickets = [srv.submit(dev(g.E), dev(g.kappa_rho), g.dt, h=g.h) for g in items]
+    keep = [(dev(g.E), dev(g.kappa_rho)) for g in items]
+    tickets = [srv.submit(E, K, g.dt, h=g.h) for (E, K), g in zip(keep, items)]
     results = []
     for t, g in zip(tickets, items):
         rc, res = srv.wait(t, 120.0)
@@ -131,7 +133,8 @@ def test_rejections_and_tickets():
     assert rc == fld.FLD_ERR_UNKNOWN_TICKET
     g = _inputs(5, (64, 64), 1e-3)
     g.E[3, 3] = -1.0                                  # rejected by the device checks
-    t = srv.submit(dev(g.E), dev(g.kappa_rho), g.dt, h=g.h)
+    E, K = dev(g.E), dev(g.kappa_rho)
+    t = srv.submit(E, K, g.dt, h=g.h)
     rc, res = srv.wait(t, 60.0)
     assert rc == fld.FLD_ERR_BAD_INPUT
     assert srv.release(t) == 0 and srv.release(t) == fld.FLD_ERR_UNKNOWN_TICKET
