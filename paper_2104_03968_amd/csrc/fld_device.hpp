@@ -167,7 +167,7 @@ void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, Job
 // LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to
 // `levels` levels: x, b and DIM face arrays per level plus one coarsest vector.
 constexpr size_t kTailLdsBudget = 150 * 1024;
-// select: 0 = active grids, 1 = grids whose status is FLD_OK (convergence check).
+// select: 0 = active grids, 1 = inactive grids whose status is FLD_OK (convergence check).
 // zero_x: also clear the level-0 V-cycle iterate (FP64 or FP32 by `mixed`); mixed also
 // writes the FP32 right-hand side.
 // fin: FinMode applied by the block that finishes a grid's last tile (-1: none;

@@ -1038,7 +1038,9 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const GridState& g = S[d.grid];
-        if (select == 0 ? !g.active : g.status != FLD_OK) continue;   // uniform per tile
+        // select 0: grids still iterating; 1: grids that stopped with FLD_OK (their
+        // recursive residual met the target), whose true residual is checked here
+        if (select == 0 ? !g.active : (g.status != FLD_OK || g.active)) continue;   // uniform per tile
         const int lt = t - jl.prefix[jb];
         int i, j, k;
         cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
