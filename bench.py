@@ -7,9 +7,13 @@ resident in HBM.  ``--steps K`` steps are timed after ``--warmup W`` untimed
 ones (the trajectory continues through both).
 
 One JSON line is printed: cell-updates/s (cells x steps / wall time), per-step
-latency percentiles, the roofline of the dominant kernel (the level-0 red-black
-half sweep, timed with HIP events right after the timed region) and the FP64
-CPU oracle timed on one step of the same grid on this host's cores.
+latency percentiles, the roofline of the dominant kernel (timed with HIP events
+right after the timed region, on the same stream) and the FP64 CPU oracle timed
+on one step of the same grid on this host's cores.
+
+``--config c5`` runs the served stream instead: Poisson arrivals of mixed 2D and
+3D solves submitted to the continuous-batching server on their schedule, with
+throughput, offered load and p50/p99 request latency.
 """
 from __future__ import annotations
 
@@ -33,7 +37,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=384, help="c5: requests in the stream")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5: mean arrival rate (1/s)")
+    ap.add_argument("--arena-gb", type=float, default=32.0, help="c5: server arena")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
@@ -68,8 +75,90 @@ def cpu_baseline(g, steps_gas: bool):
     return t, info
 
 
+def serve_stream(args):
+    """Config 5: the served Poisson stream through the request server."""
+    import threading
+    import torch
+    import workloads as W
+    import paper_2104_03968_amd as fld
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    reqs = W.c5_stream(args.requests, rate=args.rate)
+    log(f"bench c5: generating {len(reqs)} requests on the device")
+    inputs = []
+    for r in reqs:
+        g = r.inputs(backend="torch", device=dev)
+        inputs.append((g.E.contiguous(), g.kappa_rho.contiguous(), g.h))
+    torch.cuda.synchronize()
+    precision = fld.FLD_PREC_FP64 if args.precision == "fp64" else fld.FLD_PREC_MIXED
+    srv = fld.Server(int(args.arena_gb * (1 << 30)), precision=precision, rtol=1e-10)
+    # warm-up: one small request of each dimension (compiles nothing, but pages in the code)
+    for shape in ((128, 128), (32, 32, 32)):
+        g = W.random_grid(shape, 1, 1e-3, backend="torch", device=dev)
+        t = srv.submit(g.E.contiguous(), g.kappa_rho.contiguous(), g.dt, h=g.h)
+        srv.wait(t, 60.0)
+        srv.release(t)
+    tickets = [None] * len(reqs)
+    submit_wall = [0.0] * len(reqs)
+
+    def client():
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            while time.perf_counter() - t0 < r.t_arrival:
+                time.sleep(max(0.0, min(1e-3, r.t_arrival - (time.perf_counter() - t0))))
+            E, K, h = inputs[i]
+            tickets[i] = srv.submit(E, K, r.dt, h=h)
+            submit_wall[i] = time.perf_counter()
+
+    th = threading.Thread(target=client)
+    t_start = time.perf_counter()
+    th.start()
+    lat, done_t, cycles, statuses = [], [], [], []
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(1e-4)
+        rc, res = srv.wait(tickets[i], 600.0)
+        statuses.append(rc)
+        lat.append(res.t_done - res.t_submit)
+        done_t.append(res.t_done)
+        cycles.append(res.stats.cycles)
+        srv.release(tickets[i])
+    th.join()
+    t_end = time.perf_counter()
+    info = srv.info()
+    srv.close()
+    cells = sum(r.cells for r in reqs)
+    makespan = t_end - t_start
+    offered = cells / max(reqs[-1].t_arrival, 1e-9)
+    out = {
+        "metric": "cell-updates/s of implicit FLD step at 1e-10 residual; p50/p99 solve latency",
+        "value": cells / makespan,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 2,
+        "ms_per_step": makespan / len(reqs) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == fld.FLD_PREC_FP64 else "f32-in-f64",
+        "data": "synthetic",
+        "config": {"workload": (f"served stream: {len(reqs)} Poisson arrivals at {args.rate:.0f}/s of 2D "
+                                "128^2..1024^2 and 3D 32^3..192^3 FLD solves, dt U[1e-4,1e-2], rtol 1e-10, "
+                                "continuous batching, arena admission"),
+                   "cells": cells, "arena_gb": args.arena_gb},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "offered_cell_updates_per_s": offered,
+        "makespan_s": makespan,
+        "failed": int(sum(1 for s_ in statuses if s_ != 0)),
+        "vcycles_per_request": float(np.mean(cycles)),
+        "server": {"rounds": info["rounds"], "completed": info["completed"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.config == "c5" and args.gpus == 1:
+        serve_stream(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("bench.py: only single-GPU runs are supported (the workload is one GPU's share)")
