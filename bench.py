@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
+                    help="launch shape: 0 defaults, 1 autotuner (cached), 2 re-time")
     return ap.parse_args()
 
 
@@ -193,7 +195,10 @@ def main():
         workload = "512 independent 2D grids, sides U{64..512 step 32}, dt U[1e-4,1e-2], one launch per phase"
     ncells = sum(g.E.size for g in grids)
     shapes = [g.E.shape for g in grids]
-    plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c)
+    plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c,
+                    autotune=args.autotune)
+    tuning = plan.tuning()
+    log(f"bench: launch shape {tuning}")
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     E = [to(g.E) for g in grids]
     K = [to(g.kappa_rho) for g in grids]
@@ -260,7 +265,8 @@ def main():
         "dtype": "f64" if precision == fld.FLD_PREC_FP64 else "f32-in-f64",
         "data": "synthetic",
         "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
-                   "rtol": 1e-10},
+                   "rtol": 1e-10,
+                   "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "source")}},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

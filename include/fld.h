@@ -87,7 +87,12 @@ typedef struct fld_opts {
     int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after the coarse
                              correction [2, 2]                                      */
     int32_t use_graph;    /* replay V-cycles from a captured hipGraph [1]           */
-    int32_t autotune;     /* time the candidate launch shapes at bind time [0]      */
+    int32_t autotune;     /* launch shape: 0 = from the tile fields below; 1 = from
+                             the autotuner's cache, timed at bind time on a miss;
+                             2 = always timed at bind time [0].  Timing zeroes the
+                             workspace fields and runs V-cycles on them (about 30
+                             V-cycles).  The cache is the file $FLD_AUTOTUNE_CACHE,
+                             else $HOME/.cache/fld_autotune.txt                      */
     int32_t krylov;       /* 1: conjugate gradients preconditioned by one V-cycle per
                              iteration, stopped on the recursive residual and
                              confirmed on the true FP64 residual; 0: plain V-cycle
@@ -96,6 +101,12 @@ typedef struct fld_opts {
                              kernels (sweeps + restriction, prolongation + sweeps)
                              when nu1, nu2 are in 1..3; 0: one kernel per colour
                              sweep and per transfer [1]                             */
+    int32_t tile_rows;    /* fused 2D tile rows: 8, 16 or 32; 0 = 16 [0]            */
+    int32_t tile_wide;    /* fused 2D tile width: 0 = 64 cells, 1 = 128 cells less
+                             the halo (a colour cell per lane of a 64-lane wave) [0].
+                             INVALID_ARG if the tile does not fit the 160 KB LDS   */
+    int32_t max_blocks;   /* cap on workgroups per persistent launch; 0 = 2048 [0].
+                             tile_rows, tile_wide, max_blocks must be 0 with autotune */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -218,6 +229,19 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
 #define FLD_KERNEL_DOWN      7   /* fused 2D: nu1 sweeps + residual + restriction at `level` */
 #define FLD_KERNEL_UP        8   /* fused 2D: prolongation + nu2 sweeps at `level`           */
 #define FLD_KERNEL_TAIL      9   /* the LDS tail of every grid                             */
+
+/* Launch shape of a bound plan, and where it came from. */
+typedef struct fld_tuning {
+    int32_t tile_rows;    /* fused 2D tile rows                                     */
+    int32_t tile_wide;    /* fused 2D tile width class (see fld_opts)               */
+    int32_t max_blocks;   /* workgroup cap of persistent launches                   */
+    int32_t source;       /* 0 = options / defaults, 1 = timed at bind, 2 = cache   */
+    int32_t candidates;   /* shapes timed (source 1)                                */
+    double  vcycle_us;    /* timed multigrid V-cycle of the choice, microseconds
+                             (source 1; 0 otherwise)                                */
+} fld_tuning;
+/* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
+int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);
 
 /* Time `reps` back-to-back launches of one kernel of the plan (launch shape
    as fld_step uses it) between two HIP events on `stream`; *avg_ms receives

@@ -21,6 +21,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python paper_2104_03968_amd/build.py` "
         "(hipcc, gfx950). There is no CPU fallback.")
+# Device memory and streams come from torch, so the library must run on the same HIP
+# runtime as torch.  torch puts its runtime in the process's global symbol scope;
+# importing it before the library is loaded makes every HIP symbol of libfld.so --
+# including the kernel registration done while it loads -- bind to that runtime
+# instead of a second copy.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---- constants (include/fld.h) ---------------------------------------------------------
@@ -60,7 +67,16 @@ class fld_opts(C.Structure):
     _fields_ = [("c", C.c_double), ("limiter", C.c_int32), ("bc", C.c_int32 * 6),
                 ("precision", C.c_int32), ("rtol", C.c_double), ("max_cycles", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
-                ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32)]
+                ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32),
+                ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32)]
+
+
+class fld_tuning(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
+                ("source", C.c_int32), ("candidates", C.c_int32), ("vcycle_us", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class fld_stats(C.Structure):
@@ -126,6 +142,7 @@ _sig = {
     "fld_step": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
     "fld_exchange": (C.c_int32, [_P, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas), _P]),
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
+    "fld_plan_tuning": (C.c_int32, [_P, C.POINTER(fld_tuning)]),
     "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
     "fld_server_opts_default": (None, [C.POINTER(fld_server_opts)]),
@@ -191,7 +208,10 @@ def fld_strerror(code: int) -> str:
 def fld_opts_default(**kw) -> fld_opts:
     o = fld_opts()
     _lib.fld_opts_default(C.byref(o))
+    names = {f for f, _ in fld_opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver option {k!r}")
         if k == "bc":
             for i, x in enumerate(v):
                 o.bc[i] = x
@@ -278,6 +298,14 @@ def fld_exchange_status(plan: int, stream=None):
     b = C.c_int64()
     rc = _lib.fld_exchange_status(plan, _stream(stream), C.byref(b))
     return rc, b.value
+
+
+def fld_plan_tuning(plan: int) -> dict:
+    """Launch shape of a bound plan: tile rows / width class, block cap, and its source
+    (0 options, 1 timed at bind, 2 autotuner cache)."""
+    t = fld_tuning()
+    _check(_lib.fld_plan_tuning(plan, C.byref(t)), "fld_plan_tuning")
+    return t.as_dict()
 
 
 def fld_profile_kernel(plan: int, kernel: int, level: int = 0, reps: int = 100, stream=None):
@@ -476,3 +504,6 @@ class Plan:
 
     def profile(self, kernel: int, level: int = 0, reps: int = 100, stream=None):
         return fld_profile_kernel(self.handle, kernel, level, reps, stream)
+
+    def tuning(self) -> dict:
+        return fld_plan_tuning(self.handle)

@@ -34,12 +34,20 @@ __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
 __host__ __device__ inline int32_t smooth_tiles(const int32_t n[3]) {
     return ((n[0] + kSX - 1) / kSX) * ((n[1] + kTY - 1) / kTY) * n[2];
 }
-// Fused 2D smoother tiles: 64 x 16 interior cells staged in LDS with a halo.
-constexpr int kFX = 64;
-constexpr int kFY = 16;
-__host__ __device__ inline int32_t fused_tiles(const int32_t n[3]) {
-    return ((n[0] + kFX - 1) / kFX) * ((n[1] + kFY - 1) / kFY) * n[2];
+// Fused 2D level tiles: FX x FY interior cells staged in LDS with a halo of HALO
+// cells.  Narrow tiles are 64 cells wide; wide tiles fill a whole 128-cell row
+// (one colour cell per lane of a wave) with the halo included.  FY and the
+// width class are the tunable tile shape.
+__host__ __device__ constexpr int fused_fx(int halo, int wide) { return wide ? 128 - 2 * halo : 64; }
+__host__ __device__ inline int32_t fused_tiles(const int32_t n[3], int fx, int fy) {
+    return ((n[0] + fx - 1) / fx) * ((n[1] + fy - 1) / fy) * n[2];
 }
+// LDS bytes of one fused tile (x, b and the two face arrays).
+__host__ __device__ constexpr size_t fused_lds(int word, int halo, int wide, int fy) {
+    return (size_t)4 * word * (fused_fx(halo, wide) + 2 * halo) * (fy + 2 * halo);
+}
+constexpr size_t kFusedLdsMax = 160 * 1024;
+
 
 struct LevelDesc {
     int32_t n[3];        // nx, ny, nz (nz = 1 in 2D)
@@ -157,11 +165,13 @@ int prepare_tail(int dim, bool fp32, size_t smem);
 // Fused 2D level kernels (nu in 1..3).  down: nu red-black sweeps from a zero (or, with
 // load_x, the stored) iterate, then the residual restricted to the coarse right-hand
 // side; up: add the prolonged coarse correction, then nu black-red sweeps.
+// Tile shapes: wide in {0,1}, fy in {8,16,32}, as long as the tile fits the LDS.
 bool fused2_supported(int nu);
+bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down);
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
-                  int nblk, hipStream_t s);
-void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int nblk,
-                hipStream_t s);
+                  int wide, int fy, int nblk, hipStream_t s);
+void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
+                int nblk, hipStream_t s);
 void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s);
 // LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to

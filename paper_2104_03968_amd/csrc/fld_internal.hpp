@@ -99,7 +99,14 @@ struct Plan {
     int ex_slot = 0;
     int ex_last = -1;                          // slot of the last fld_exchange (profiling)
     int64_t max_n = 0;
+    // launch shape: fused 2D tile (width class, rows) and the persistent-grid cap
+    int tile_wide = 0;
+    int tile_rows = 16;
     int nblk = 2048;
+    int tune_source = 0;                       // 0 defaults / options, 1 timed at bind, 2 cache
+    int tune_candidates = 0;
+    double tune_us = 0.0;                      // timed multigrid part of one V-cycle
+    bool tune_done = false;
     int last_cycles = 0;                       // cycles of the previous step (replay sizing)
 
     fld_gas last_gas{};                        // constants of the last fld_exchange (profiling)
@@ -140,5 +147,11 @@ void plan_verify(Plan& p, hipStream_t s);                // true residual of gri
 void plan_output(Plan& p, hipStream_t s);                // X -> E_out
 void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* out);
 int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s);
+
+// Autotuner (autotune.cpp): pick the launch shape of a bound plan by timing the
+// multigrid part of a V-cycle for each candidate, or take it from the cache.
+int plan_autotune(Plan& p);
+void plan_vcycle_mg(Plan& p, hipStream_t s);             // the timed part: smoothing, transfers, tails
+int plan_set_shape(Plan& p, int wide, int rows, int nblk); // rebuild and upload the fused lists
 
 }  // namespace fld

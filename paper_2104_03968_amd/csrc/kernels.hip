@@ -699,27 +699,27 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
 // reads the array it writes (tiles overlap through their halos): down reads x
 // (when it starts from a stored iterate) and writes xs; up reads xs and writes x.
 // ---------------------------------------------------------------------------
-template <typename T, int HALO>
+template <typename T, int W_, int H_>
 struct Tile2 {
-    static constexpr int W = kFX + 2 * HALO;
-    static constexpr int H = kFY + 2 * HALO;
+    static constexpr int W = W_;
+    static constexpr int H = H_;
     T x[H][W];
     T b[H][W];
     T w0[H][W];
     T w1[H][W];
 };
 
-template <typename T, int HALO>
-__device__ __forceinline__ void tile2_half_sweep(Tile2<T, HALO>& t, int gx0, int gy0, int color, int m) {
+template <typename Tl>
+__device__ __forceinline__ void tile2_half_sweep(Tl& t, int gx0, int gy0, int color, int m) {
     // update the cells of `color` with local coordinates in [m, W-m) x [m, H-m)
     const int lane = threadIdx.x & 63;
-    for (int lj = m + (threadIdx.x >> 6); lj < Tile2<T, HALO>::H - m; lj += kBlock / 64) {
+    for (int lj = m + (threadIdx.x >> 6); lj < Tl::H - m; lj += kBlock / 64) {
         const int li = m + (((gx0 + m + gy0 + lj) ^ color) & 1) + 2 * lane;
-        if (li >= Tile2<T, HALO>::W - m) continue;
-        const T wl = t.w0[lj][li], wr = t.w0[lj][li + 1], wd = t.w1[lj][li], wu = t.w1[lj + 1][li];
-        const T s = t.b[lj][li] + wl * t.x[lj][li - 1] + wr * t.x[lj][li + 1] + wd * t.x[lj - 1][li] +
-                    wu * t.x[lj + 1][li];
-        t.x[lj][li] = s / (T(1) + wl + wr + wd + wu);
+        if (li >= Tl::W - m) continue;
+        const auto wl = t.w0[lj][li], wr = t.w0[lj][li + 1], wd = t.w1[lj][li], wu = t.w1[lj + 1][li];
+        const auto s = t.b[lj][li] + wl * t.x[lj][li - 1] + wr * t.x[lj][li + 1] + wd * t.x[lj - 1][li] +
+                       wu * t.x[lj + 1][li];
+        t.x[lj][li] = s / (decltype(s)(1) + wl + wr + wd + wu);
     }
     __syncthreads();
 }
@@ -727,14 +727,14 @@ __device__ __forceinline__ void tile2_half_sweep(Tile2<T, HALO>& t, int gx0, int
 // Stage the tile and its halo in LDS.  All global loads of a thread are issued
 // before any LDS store so their latencies overlap.  With `cx`, the piecewise-
 // constant prolongation of the coarse correction is added to x on the way in.
-template <typename T, int HALO>
-__device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d, const T* __restrict__ xs,
+template <typename T, typename Tl>
+__device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const T* __restrict__ xs,
                                            int gx0, int gy0, bool load_x, const T* __restrict__ cx,
                                            int ncx) {
     const T* __restrict__ bs = Arr<T>::b(d);
     const T* __restrict__ w0 = Arr<T>::w(d, 0);
     const T* __restrict__ w1 = Arr<T>::w(d, 1);
-    constexpr int W = Tile2<T, HALO>::W, H = Tile2<T, HALO>::H;
+    constexpr int W = Tl::W, H = Tl::H;
     constexpr int NE = (W * H + kBlock - 1) / kBlock;
     T vx[NE], vb[NE], v0[NE], v1[NE];
 #pragma unroll
@@ -769,36 +769,37 @@ __device__ __forceinline__ void tile2_load(Tile2<T, HALO>& t, const LevelDesc& d
     __syncthreads();
 }
 
-template <typename T, int NU>
+template <typename T, int NU, int WIDE, int FY>
 __global__ void __launch_bounds__(kBlock)
 k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int load_x) {
     constexpr int HALO = 2 * NU + 1;
-    __shared__ Tile2<T, HALO> t;
+    constexpr int FX = fused_fx(HALO, WIDE);
+    using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
+    __shared__ Tl t;
     for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
         const LevelDesc& cL = L[d.coarse];
         const int lt = tt - jl.prefix[jb];
-        const int tx_n = (d.n[0] + kFX - 1) / kFX;
-        const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
-        tile2_load<T, HALO>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0, nullptr, 0);
+        const int tx_n = (d.n[0] + FX - 1) / FX;
+        const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
+        tile2_load<T>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0, nullptr, 0);
         for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 1);
-            tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 2);
+            tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 1);
+            tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 2);
         }
         // smoothed iterate of the interior (to xs: other tiles may still read x), and the
         // residual averaged onto the coarse cells
         T* __restrict__ xo = Arr<T>::xs(d);
-        for (int e = threadIdx.x; e < kFX * kFY; e += kBlock) {
-            const int lj = e / kFX, li = e - lj * kFX;
+        for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+            const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
             if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
         }
         T* __restrict__ cb = Arr<T>::b(cL);
-        {
-            const int e = threadIdx.x;                 // one coarse cell per thread: 32 x 8
-            const int cj = e / (kFX / 2), ci = e - cj * (kFX / 2);
+        for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
+            const int cj = e / (FX / 2), ci = e - cj * (FX / 2);
             const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj;
             if (CI < cL.n[0] && CJ < cL.n[1]) {
                 T sum = T(0);
@@ -817,28 +818,30 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
     }
 }
 
-template <typename T, int NU>
+template <typename T, int NU, int WIDE, int FY>
 __global__ void __launch_bounds__(kBlock)
 k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
     constexpr int HALO = 2 * NU;
-    __shared__ Tile2<T, HALO> t;
+    constexpr int FX = fused_fx(HALO, WIDE);
+    using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
+    __shared__ Tl t;
     for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
         const LevelDesc& cL = L[d.coarse];
         const int lt = tt - jl.prefix[jb];
-        const int tx_n = (d.n[0] + kFX - 1) / kFX;
-        const int gx0 = (lt % tx_n) * kFX - HALO, gy0 = (lt / tx_n) * kFY - HALO;
+        const int tx_n = (d.n[0] + FX - 1) / FX;
+        const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
         // the down pass's iterate plus the prolonged coarse correction
-        tile2_load<T, HALO>(t, d, Arr<T>::xs(d), gx0, gy0, true, Arr<T>::x(cL), cL.n[0]);
+        tile2_load<T>(t, d, Arr<T>::xs(d), gx0, gy0, true, Arr<T>::x(cL), cL.n[0]);
         for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep<T, HALO>(t, gx0, gy0, 1, 2 * it + 1);
-            tile2_half_sweep<T, HALO>(t, gx0, gy0, 0, 2 * it + 2);
+            tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 1);
+            tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 2);
         }
         T* __restrict__ xo = Arr<T>::x(d);
-        for (int e = threadIdx.x; e < kFX * kFY; e += kBlock) {
-            const int lj = e / kFX, li = e - lj * kFX;
+        for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+            const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
             if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
         }
@@ -1362,6 +1365,11 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
 
 bool fused2_supported(int nu) { return nu >= 1 && nu <= 3; }
 
+bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down) {
+    if (!fused2_supported(nu) || (wide != 0 && wide != 1) || (fy != 8 && fy != 16 && fy != 32)) return false;
+    return fused_lds(fp32 ? 4 : 8, down ? 2 * nu + 1 : 2 * nu, wide, fy) <= kFusedLdsMax;
+}
+
 #define FLD_NU_DISPATCH(nu, ...)                                          \
     do {                                                                  \
         if ((nu) == 1) { constexpr int NU = 1; __VA_ARGS__; }             \
@@ -1369,24 +1377,54 @@ bool fused2_supported(int nu) { return nu >= 1 && nu <= 3; }
         else { constexpr int NU = 3; __VA_ARGS__; }                       \
     } while (0)
 
+#define FLD_SHAPE_DISPATCH(wide, fy, ...)                                 \
+    do {                                                                  \
+        if (wide) {                                                       \
+            constexpr int WIDE = 1;                                       \
+            if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }         \
+            else if ((fy) == 16) { constexpr int FY = 16; __VA_ARGS__; }  \
+            else { constexpr int FY = 32; __VA_ARGS__; }                  \
+        } else {                                                          \
+            constexpr int WIDE = 0;                                       \
+            if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }         \
+            else if ((fy) == 16) { constexpr int FY = 16; __VA_ARGS__; }  \
+            else { constexpr int FY = 32; __VA_ARGS__; }                  \
+        }                                                                 \
+    } while (0)
+
+namespace {
+// Instantiates a fused kernel only for shapes whose tile fits the LDS; the host
+// never selects the others (fused2_shape_ok).
+template <typename T, int NU, int WIDE, int FY>
+void down2_t(const LevelDesc* L, const GridState* S, JobList jl, int load_x, int g, hipStream_t s) {
+    if constexpr (fused_lds(sizeof(T), 2 * NU + 1, WIDE, FY) <= kFusedLdsMax)
+        hipLaunchKernelGGL((k_down2<T, NU, WIDE, FY>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
+}
+template <typename T, int NU, int WIDE, int FY>
+void up2_t(const LevelDesc* L, const GridState* S, JobList jl, int g, hipStream_t s) {
+    if constexpr (fused_lds(sizeof(T), 2 * NU, WIDE, FY) <= kFusedLdsMax)
+        hipLaunchKernelGGL((k_up2<T, NU, WIDE, FY>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+}
+}  // namespace
+
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
-                  int nblk, hipStream_t s) {
+                  int wide, int fy, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
-    FLD_NU_DISPATCH(nu, {
-        if (fp32) hipLaunchKernelGGL((k_down2<float, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
-        else hipLaunchKernelGGL((k_down2<double, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
-    });
+    FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
+        if (fp32) down2_t<float, NU, WIDE, FY>(L, S, jl, load_x, g, s);
+        else down2_t<double, NU, WIDE, FY>(L, S, jl, load_x, g, s);
+    }));
 }
 
-void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int nblk,
-                hipStream_t s) {
+void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
+                int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for(jl.total, nblk);
-    FLD_NU_DISPATCH(nu, {
-        if (fp32) hipLaunchKernelGGL((k_up2<float, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
-        else hipLaunchKernelGGL((k_up2<double, NU>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
-    });
+    FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
+        if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, g, s);
+        else up2_t<double, NU, WIDE, FY>(L, S, jl, g, s);
+    }));
 }
 
 int prepare_tail(int dim, bool fp32, size_t smem) {

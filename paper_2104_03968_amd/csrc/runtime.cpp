@@ -35,8 +35,9 @@ struct DeviceGuard {
     int prev = -1;
     bool ok = true;
     explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) { set_error("hipGetDevice", e); ok = false; prev = -1; return; }
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) { set_error("hipSetDevice", e); ok = false; }
     }
     ~DeviceGuard() {
         int cur = -1;
@@ -58,6 +59,12 @@ int validate_opts(const fld_opts& o) {
     if (o.krylov && o.nu1 != o.nu2) return FLD_ERR_INVALID_ARG;   // CG needs a symmetric V-cycle
     if (o.krylov != 0 && o.krylov != 1) return FLD_ERR_INVALID_ARG;
     if (o.fused != 0 && o.fused != 1) return FLD_ERR_INVALID_ARG;
+    if (o.autotune < 0 || o.autotune > 2) return FLD_ERR_INVALID_ARG;
+    if (o.tile_rows != 0 && o.tile_rows != 8 && o.tile_rows != 16 && o.tile_rows != 32) return FLD_ERR_INVALID_ARG;
+    if (o.tile_wide != 0 && o.tile_wide != 1) return FLD_ERR_INVALID_ARG;
+    if (o.max_blocks < 0 || o.max_blocks > (1 << 20)) return FLD_ERR_INVALID_ARG;
+    // the tuner picks the launch shape itself
+    if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks)) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
 
@@ -83,7 +90,19 @@ void finish_list(HostList& l, const std::vector<LevelDesc>& L, int (*tiles)(cons
 int tiles_cell(const LevelDesc& d) { return cell_tiles(d.n); }
 int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
-int tiles_fused(const LevelDesc& d) { return fused_tiles(d.n); }
+
+// Fused-tile prefixes of the down / up lists for the plan's tile shape.
+void finish_fused(const Plan& p, DimLists& D) {
+    const int fxd = fused_fx(2 * p.opts.nu1 + 1, p.tile_wide), fxu = fused_fx(2 * p.opts.nu2, p.tile_wide);
+    for (size_t dpt = 0; dpt < D.down2.size(); ++dpt) {
+        HostList& dn = D.down2[dpt];
+        HostList& up = D.up2[dpt];
+        dn.prefix.assign(1, 0);
+        up.prefix.assign(1, 0);
+        for (int32_t li : dn.levels) dn.prefix.push_back(dn.prefix.back() + fused_tiles(p.levels[li].n, fxd, p.tile_rows));
+        for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, p.tile_rows));
+    }
+}
 
 }  // namespace
 
@@ -194,9 +213,8 @@ static void build_lists(Plan& p) {
         for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
             D.down2[dpt].levels = D.smooth[dpt].levels;
             D.up2[dpt].levels = D.smooth[dpt].levels;
-            finish_list(D.down2[dpt], p.levels, tiles_fused);
-            finish_list(D.up2[dpt], p.levels, tiles_fused);
         }
+        finish_fused(p, D);
         for (int dpt = 0; dpt < maxdepth; ++dpt) {
             finish_list(D.smooth[dpt], p.levels, tiles_smooth);
             finish_list(D.prolong[dpt], p.levels, tiles_cell);
@@ -229,6 +247,7 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     if (rc != FLD_OK) return rc;
     for (int g = 0; g < ngrids; ++g)
         if ((rc = validate_grid(grids[g])) != FLD_OK) return rc;
+    // host-only: a plan can be built without a usable device; bind reports HIP failures
     if (hipGetDevice(&p.device) != hipSuccess) p.device = 0;
     p.opts = opts;
     p.mixed = opts.precision == FLD_PREC_MIXED;
@@ -236,6 +255,13 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.grids.assign(grids, grids + ngrids);
     for (auto& g : p.grids)
         if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
+    p.tile_wide = opts.tile_wide;
+    p.tile_rows = opts.tile_rows ? opts.tile_rows : 16;
+    p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
+    if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) &&
+        !(fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows, true) &&
+          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false)))
+        return FLD_ERR_INVALID_ARG;                            // the tile does not fit the LDS
     build_levels(p);
     build_lists(p);
     layout(p);
@@ -332,38 +358,52 @@ static void layout(Plan& p) {
     p.ws_bytes = off;
 }
 
-// Enqueue one V-cycle (FP64 mode: on the solution; mixed: the FP32 correction
-// solve of the current residual) followed by the FP64 residual and stop test.
-static void enqueue_cycle(Plan& p, hipStream_t s) {
+// The multigrid part of one V-cycle of one dimension's grids (FP64 mode: on the
+// solution, or on the CG preconditioner's iterate; mixed: the FP32 correction
+// solve of the current residual).  Reads the solver state, never writes it.
+static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
     const bool f32 = p.mixed;
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;   // level-0 V-cycle starts from the iterate
+    const int dim = D.dim;
+    for (int d = 0; d < D.maxdepth; ++d) {
+        if (D.fused) {
+            launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.tile_wide,
+                         p.tile_rows, p.nblk, s);
+            continue;
+        }
+        for (int it = 0; it < p.opts.nu1; ++it) {
+            launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
+            launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
+        }
+        launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
+    }
+    launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
+    for (int d = D.maxdepth - 1; d >= 0; --d) {
+        if (D.fused) {
+            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, p.tile_rows, p.nblk, s);
+            continue;
+        }
+        launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
+        for (int it = 0; it < p.opts.nu2; ++it) {
+            launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
+            launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
+        }
+    }
+}
+
+void plan_vcycle_mg(Plan& p, hipStream_t s) {
+    for (auto& D : p.dl)
+        if (!D.l0_cell.empty()) enqueue_mg(p, D, s);
+}
+
+// Enqueue one outer iteration: the V-cycle followed by the CG update (or the
+// defect correction) with the FP64 residual and stop test.
+static void enqueue_cycle(Plan& p, hipStream_t s) {
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const int dim = D.dim;
-        for (int d = 0; d < D.maxdepth; ++d) {
-            if (D.fused) {
-                launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.nblk, s);
-                continue;
-            }
-            for (int it = 0; it < p.opts.nu1; ++it) {
-                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
-                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
-            }
-            launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
-        }
-        launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
-        launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
-        for (int d = D.maxdepth - 1; d >= 0; --d) {
-            if (D.fused) {
-                launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.nblk, s);
-                continue;
-            }
-            launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
-            for (int it = 0; it < p.opts.nu2; ++it) {
-                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
-                launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
-            }
-        }
+        enqueue_mg(p, D, s);
         const JobList& l0 = D.l0_cell.dev;
         if (p.krylov) {
             const double rt = p.opts.rtol;
@@ -394,6 +434,35 @@ static int capture_graph(Plan& p) {
     FLD_HIP(hipStreamEndCapture(p.cap_stream, &g));
     p.graph = g;
     FLD_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+    return FLD_OK;
+}
+
+static int upload_list(Plan& p, HostList& l) {
+    int32_t* lv = reinterpret_cast<int32_t*>(p.ws + l.off_levels);
+    int32_t* pf = reinterpret_cast<int32_t*>(p.ws + l.off_prefix);
+    if (!l.levels.empty())
+        FLD_HIP(hipMemcpy(lv, l.levels.data(), l.levels.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back()};
+    return FLD_OK;
+}
+
+int plan_set_shape(Plan& p, int wide, int rows, int nblk) {
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    for (auto& D : p.dl)
+        if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, wide, rows, true) &&
+                         fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false)))
+            return FLD_ERR_INVALID_ARG;
+    if (nblk < 1) return FLD_ERR_INVALID_ARG;
+    p.tile_wide = wide;
+    p.tile_rows = rows;
+    p.nblk = nblk;
+    for (auto& D : p.dl) {
+        finish_fused(p, D);
+        int rc;
+        for (auto& l : D.down2) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
+        for (auto& l : D.up2) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
+    }
     return FLD_OK;
 }
 
@@ -442,15 +511,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
     Control c0{};
     FLD_HIP(hipMemcpy(p.dCtrl, &c0, sizeof(Control), hipMemcpyHostToDevice));
-    auto upload = [&](HostList& l) -> int {
-        int32_t* lv = reinterpret_cast<int32_t*>(tab + l.off_levels);
-        int32_t* pf = reinterpret_cast<int32_t*>(tab + l.off_prefix);
-        if (!l.levels.empty())
-            FLD_HIP(hipMemcpy(lv, l.levels.data(), l.levels.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back()};
-        return FLD_OK;
-    };
+    auto upload = [&](HostList& l) { return upload_list(p, l); };
     for (auto& D : p.dl) {
         int rc;
         if ((rc = upload(D.l0_cell)) != FLD_OK) return rc;
@@ -472,6 +533,12 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     if (!p.hS) FLD_HIP(hipHostMalloc((void**)&p.hS, p.ngrids() * sizeof(GridState), hipHostMallocDefault));
     p.max_n = 0;
     for (auto n : p.ncell) p.max_n = std::max<int64_t>(p.max_n, n);
+    // the tuner runs kernels over the fields: only on a plan that owns its workspace
+    if (p.opts.autotune && !p.tune_done && !init && p.field_base.empty()) {
+        int rc = plan_autotune(p);
+        if (rc != FLD_OK) return rc;
+        FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
+    }
     if (p.opts.use_graph) {
         int rc = capture_graph(p);
         if (rc != FLD_OK) return rc;
@@ -668,10 +735,12 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                                  -1, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
                     break;
                 case FLD_KERNEL_DOWN:
-                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0, p.nblk, s);
+                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0,
+                                                             p.tile_wide, p.tile_rows, p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
-                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2, p.nblk, s);
+                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2,
+                                                         p.tile_wide, p.tile_rows, p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
                     launch_tail(D.dim, p.mixed, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
@@ -930,6 +999,19 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected) {
                            hipMemcpyHostToDevice, s));
     FLD_HIP(hipStreamSynchronize(s));
     return bad ? FLD_ERR_BAD_INPUT : FLD_OK;
+}
+
+int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
+    if (!plan || !out) return FLD_ERR_INVALID_ARG;
+    const Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    out->tile_rows = p.tile_rows;
+    out->tile_wide = p.tile_wide;
+    out->max_blocks = p.nblk;
+    out->source = p.tune_source;
+    out->candidates = p.tune_candidates;
+    out->vcycle_us = p.tune_us;
+    return FLD_OK;
 }
 
 int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps, void* stream,

@@ -66,6 +66,41 @@ def test_plan_create_validates_options(kw, code):
     assert e.value.code == code
 
 
+@pytest.mark.parametrize("kw,ok", [
+    (dict(tile_rows=8), True), (dict(tile_rows=32), True), (dict(tile_rows=12), False),
+    (dict(tile_wide=1), True), (dict(tile_wide=2), False), (dict(max_blocks=512), True),
+    (dict(max_blocks=-1), False), (dict(autotune=1), True), (dict(autotune=2), True),
+    (dict(autotune=3), False), (dict(autotune=1, tile_rows=16), False),
+    (dict(autotune=1, max_blocks=1024), False),
+    # an FP64 128-wide, 32-row tile with the nu = 2 halo needs more than the 160 KB of LDS
+    (dict(tile_wide=1, tile_rows=32), False), (dict(tile_wide=1, tile_rows=32, precision=1), True),
+    (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1), True),
+    (dict(tile_wide=1, tile_rows=32, fused=0), True)])
+def test_launch_shape_options(kw, ok):
+    g = fld.make_grid((256, 256))
+    if ok:
+        fld.fld_plan_destroy(fld.fld_plan_create([g], fld.fld_opts_default(**kw)))
+    else:
+        with pytest.raises(fld.FLDError) as e:
+            fld.fld_plan_create([g], fld.fld_opts_default(**kw))
+        assert e.value.code == fld.FLD_ERR_INVALID_ARG
+
+
+def test_unknown_option_name_is_an_error():
+    with pytest.raises(TypeError):
+        fld.fld_opts_default(tile_row=8)
+
+
+def test_tile_shape_does_not_change_the_workspace():
+    g = [fld.make_grid((300, 196)), fld.make_grid((1024, 1024))]
+    sizes = set()
+    for kw in (dict(), dict(tile_rows=8), dict(tile_wide=1, tile_rows=16), dict(max_blocks=64), dict(autotune=1)):
+        h = fld.fld_plan_create(g, fld.fld_opts_default(**kw))
+        sizes.add(fld.fld_plan_workspace_bytes(h))
+        fld.fld_plan_destroy(h)
+    assert len(sizes) == 1
+
+
 def test_bad_h_rejected():
     g = fld.make_grid((16, 16), (0.1, -0.1))
     with pytest.raises(fld.FLDError):
@@ -119,6 +154,9 @@ def test_calls_before_bind_fail_cleanly():
     assert rc == fld.FLD_ERR_NO_WORKSPACE
     with pytest.raises(fld.FLDError):
         fld.fld_plan_levels(h, 5)
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_plan_tuning(h)
+    assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
     fld.fld_plan_destroy(h)
 
 
@@ -147,3 +185,26 @@ def test_server_defaults_and_argument_checks():
     bad = fld.fld_server_opts_default(max_slots=0)
     with pytest.raises(fld.FLDError):
         fld.fld_server_create(bad, 4096, 1 << 20)
+
+
+def test_library_binds_to_torchs_hip_runtime(tmp_path):
+    """The package imports torch before loading libfld.so, so the library's HIP symbols
+    (the kernel registration at load time included) resolve to torch's runtime rather
+    than a second HIP runtime in the same process, whatever the caller imported first."""
+    import subprocess
+    import sys
+    out = tmp_path / "ld"
+    env = dict(os.environ, LD_DEBUG="bindings", LD_DEBUG_OUTPUT=str(out))
+    code = ("import sys; sys.path.insert(0, %r); import paper_2104_03968_amd as f; "
+            "f.fld_opts_default()" % ROOT)
+    subprocess.run([sys.executable, "-c", code], env=env, check=True, timeout=300)
+    import torch
+    torch_lib = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), "lib"))
+    lines = []
+    for p in tmp_path.iterdir():
+        lines += [ln for ln in p.read_text(errors="replace").splitlines()
+                  if "libfld.so" in ln and "__hipRegisterFatBinary'" in ln]
+    assert lines, "no binding of __hipRegisterFatBinary recorded"
+    for ln in lines:
+        target = ln.split(" to ", 1)[1].split(" [")[0]
+        assert os.path.realpath(target).startswith(torch_lib), ln
