@@ -53,17 +53,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def dominant_kernel(fld, ndim: int, word: int, fused: bool):
+def dominant_kernel(fld, ndim: int, word: int, fused: bool, fused3: bool):
     """The kernel that dominates a step and its algorithmic bytes per cell of level 0.
 
     2D (fused level kernels): the level-0 up pass reads the down pass's iterate,
     b, both face arrays and a quarter-size coarse correction, and writes x:
-    (5 + 1/4) words.  3D: one red-black half sweep reads x of every cell, b of
-    the updated half, every face weight (each face touches one cell of each
-    colour) and writes x of the updated half: (2 + d) words.
+    (5 + 1/4) words.  3D fused sweeps: one whole red-black sweep reads x, b and
+    the three face arrays once and writes x: 6 words.  3D per-colour kernels:
+    one half sweep reads x of every cell, b of the updated half, every face
+    weight (each face touches one cell of each colour) and writes x of the
+    updated half: (2 + d) words.
     """
     if ndim == 2 and fused:
         return fld.FLD_KERNEL_UP, "k_up2", word * 5 + word / 4
+    if ndim == 3 and fused3:
+        return fld.FLD_KERNEL_SWEEP3, "k_sweep3", word * 6
     return fld.FLD_KERNEL_SMOOTH, "k_smooth", word * (2 + ndim)
 
 
@@ -246,7 +250,7 @@ def main():
     # dominant kernel at level 0, timed with HIP events on the same stream
     ndim = len(shapes[0])
     word = 4 if precision == fld.FLD_PREC_MIXED else 8
-    kid, kname, bpc = dominant_kernel(fld, ndim, word, bool(plan.opts.fused))
+    kid, kname, bpc = dominant_kernel(fld, ndim, word, bool(plan.opts.fused), bool(tuning["fused3"]))
     ms, cells = plan.profile(kid, 0, args.profile_reps, stream)
     achieved = bpc * cells / (ms * 1e-3) / 1e9
     log(f"bench: level-0 {kname} {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")
@@ -266,7 +270,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
                    "rtol": 1e-10,
-                   "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "source")}},
+                   "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
+                                                     "fused3_levels", "source")}},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -105,8 +105,14 @@ typedef struct fld_opts {
     int32_t tile_wide;    /* fused 2D tile width: 0 = 64 cells, 1 = 128 cells less
                              the halo (a colour cell per lane of a 64-lane wave) [0].
                              INVALID_ARG if the tile does not fit the 160 KB LDS   */
-    int32_t max_blocks;   /* cap on workgroups per persistent launch; 0 = 2048 [0].
-                             tile_rows, tile_wide, max_blocks must be 0 with autotune */
+    int32_t max_blocks;   /* cap on workgroups per persistent launch; 0 = 2048 [0]   */
+    int32_t tile_depth;   /* fused 3D sweeps: planes per block, 16, 32 or 64; 0 = 32 [0] */
+    int32_t fused3_levels;/* 3D: the first k multigrid levels run fused sweeps, the
+                             coarser ones per-colour kernels; 0 = the levels whose
+                             sweep has at least 256 blocks [0].  3D grids use fused
+                             sweeps when fused = 1, nu1, nu2 >= 1 and nu1 + nu2 is
+                             even.  tile_rows, tile_wide, max_blocks, tile_depth and
+                             fused3_levels must be 0 with autotune                  */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -229,6 +235,7 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
 #define FLD_KERNEL_DOWN      7   /* fused 2D: nu1 sweeps + residual + restriction at `level` */
 #define FLD_KERNEL_UP        8   /* fused 2D: prolongation + nu2 sweeps at `level`           */
 #define FLD_KERNEL_TAIL      9   /* the LDS tail of every grid                             */
+#define FLD_KERNEL_SWEEP3   10   /* fused 3D: one red-black sweep from the stored iterate at `level` */
 
 /* Launch shape of a bound plan, and where it came from. */
 typedef struct fld_tuning {
@@ -239,6 +246,10 @@ typedef struct fld_tuning {
     int32_t candidates;   /* shapes timed (source 1)                                */
     double  vcycle_us;    /* timed multigrid V-cycle of the choice, microseconds
                              (source 1; 0 otherwise)                                */
+    int32_t tile_depth;   /* fused 3D sweep planes per block                        */
+    int32_t fused3;       /* 1 if 3D grids run fused sweeps (the tuner may prefer the
+                             per-colour kernels)                                    */
+    int32_t fused3_levels;/* leading 3D levels with fused sweeps                    */
 } fld_tuning;
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);

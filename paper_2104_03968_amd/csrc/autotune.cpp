@@ -1,9 +1,12 @@
 // Launch-shape autotuner.  A bound plan's multigrid V-cycle (smoothing,
 // transfers, tails; the solver state is only read) is timed for each
-// candidate shape -- the fused 2D tile (64-wide or full-wave-wide, 8/16/32
-// rows) and the cap on persistent workgroups -- and the fastest is kept.
+// candidate launch shape and the fastest is kept.  The candidates are, one
+// dimension after the other: the fused 2D tile (64-wide or full-wave-wide,
+// 8/16/32 rows); for 3D grids the fused sweep's planes per block (16/32/64),
+// then how many leading levels run fused (or none: per-colour kernels); and
+// the cap on persistent workgroups.
 // Choices are cached in a text file, one line per plan class:
-//     <key> TAB <wide> <rows> <max_blocks> <microseconds>
+//     <key> TAB <wide> <rows> <max_blocks> <depth> <sweep3> <levels3> <microseconds>
 // keyed by the device architecture, precision, sweep counts and the size
 // class of the plan's grids, so later plans of the same class skip the timing.
 // The cache file is $FLD_AUTOTUNE_CACHE, else $HOME/.cache/fld_autotune.txt;
@@ -24,9 +27,7 @@ namespace fld {
 
 namespace {
 
-struct Shape {
-    int wide, rows, nblk;
-};
+using Shape = LaunchShape;
 
 std::string cache_path() {
     if (const char* e = std::getenv("FLD_AUTOTUNE_CACHE")) return e;
@@ -51,7 +52,7 @@ std::string plan_key(const Plan& p) {
         cus = prop.multiProcessorCount;
     }
     char buf[512];
-    int n = std::snprintf(buf, sizeof(buf), "v1|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
+    int n = std::snprintf(buf, sizeof(buf), "v3|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
                           p.mixed ? "mixed" : "fp64", p.opts.nu1, p.opts.nu2, p.krylov ? 1 : 0, p.opts.fused);
     for (int dim = 2; dim <= 3; ++dim) {
         int count = 0;
@@ -82,7 +83,8 @@ bool cache_lookup(const std::string& key, Shape& out) {
         if (key != line) continue;
         Shape s{};
         double us = 0;
-        if (std::sscanf(tab + 1, "%d %d %d %lf", &s.wide, &s.rows, &s.nblk, &us) == 4) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %lf", &s.wide, &s.rows, &s.nblk, &s.depth, &s.sweep3,
+                        &s.levels3, &us) == 7) {
             out = s;                                   // the last record of a key wins
             found = true;
         }
@@ -96,7 +98,8 @@ void cache_store(const std::string& key, const Shape& s, double us) {
     if (path.empty()) return;
     FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%d %d %d %.3f\n", key.c_str(), s.wide, s.rows, s.nblk, us);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %.3f\n", key.c_str(), s.wide, s.rows, s.nblk, s.depth, s.sweep3,
+                 s.levels3, us);
     std::fclose(f);
 }
 
@@ -109,6 +112,8 @@ int max_list_tiles(const Plan& p) {
         for (const auto& l : D.prolong) see(l);
         for (const auto& l : D.down2) see(l);
         for (const auto& l : D.up2) see(l);
+        for (const auto& l : D.sw3) see(l);
+        for (const auto& l : D.sr3) see(l);
         see(D.l0_cell);
     }
     return m;
@@ -116,7 +121,7 @@ int max_list_tiles(const Plan& p) {
 
 // Microseconds of one multigrid V-cycle with shape s (median of a few timed runs).
 int time_shape(Plan& p, const Shape& s, hipEvent_t e0, hipEvent_t e1, double& us) {
-    int rc = plan_set_shape(p, s.wide, s.rows, s.nblk);
+    int rc = plan_set_shape(p, s);
     if (rc != FLD_OK) return rc;
     plan_vcycle_mg(p, nullptr);                       // warm-up (instruction cache, lists)
     std::vector<double> t;
@@ -140,14 +145,15 @@ int time_shape(Plan& p, const Shape& s, hipEvent_t e0, hipEvent_t e1, double& us
 int plan_autotune(Plan& p) {
     p.tune_done = true;
     const std::string key = plan_key(p);
-    Shape best{p.tile_wide, p.tile_rows, p.nblk};
+    const Shape start = plan_shape(p);
+    Shape best = start;
     if (p.opts.autotune == 1 && cache_lookup(key, best)) {
-        int rc = plan_set_shape(p, best.wide, best.rows, best.nblk);
-        if (rc == FLD_OK) {
+        if (plan_set_shape(p, best) == FLD_OK) {
             p.tune_source = 2;
             return FLD_OK;
         }
-        best = Shape{p.tile_wide, p.tile_rows, p.nblk};    // stale record: time afresh
+        best = start;                                     // stale record: time afresh
+        (void)plan_set_shape(p, best);
     }
     // the timed kernels read the plan's fields: give them finite values, and let
     // every grid take part
@@ -162,44 +168,82 @@ int plan_autotune(Plan& p) {
         ~EventGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } guard{e0, e1};
 
-    bool any_fused = false;
-    for (const auto& D : p.dl) any_fused = any_fused || (D.fused && !D.down2.empty());
-    // stage 1: tile shapes at the default block cap (the current shape first, so a
-    // tie keeps it); stage 2: block caps for the best shape
-    std::vector<Shape> shapes{best};
-    if (any_fused)
+    bool any2 = false, any3 = false;
+    for (const auto& D : p.dl) {
+        any2 = any2 || (D.fused && !D.down2.empty());
+        any3 = any3 || (D.fused3 && !D.sw3.empty());
+    }
+    double best_us = 0;
+    int timed = 0;
+    // time the candidates of one dimension; the incumbent goes first and a challenger
+    // must beat it by 2 % (timing noise)
+    auto stage = [&](const std::vector<Shape>& cands) -> int {
+        for (const Shape& c : cands) {
+            double us = 0;
+            int rc = time_shape(p, c, e0, e1, us);
+            if (rc != FLD_OK) return rc;
+            if (timed++ == 0 || us < 0.98 * best_us) { best = c; best_us = us; }
+        }
+        return FLD_OK;
+    };
+    int rc = stage({best});
+    if (rc != FLD_OK) return rc;
+    if (any2) {
+        std::vector<Shape> c;
         for (int wide = 0; wide <= 1; ++wide)
             for (int rows : {8, 16, 32}) {
                 if (wide == best.wide && rows == best.rows) continue;
                 if (!fused2_shape_ok(p.mixed, p.opts.nu1, wide, rows, true) ||
                     !fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false))
                     continue;
-                shapes.push_back(Shape{wide, rows, best.nblk});
+                Shape s = best;
+                s.wide = wide;
+                s.rows = rows;
+                c.push_back(s);
             }
-    double best_us = 0;
-    int timed = 0;
-    for (size_t i = 0; i < shapes.size(); ++i) {
-        double us = 0;
-        int rc = time_shape(p, shapes[i], e0, e1, us);
-        if (rc != FLD_OK) return rc;
-        ++timed;
-        // a challenger must win by 2 % to displace the incumbent (timing noise)
-        if (i == 0 || us < 0.98 * best_us) { best = shapes[i]; best_us = us; }
+        if ((rc = stage(c)) != FLD_OK) return rc;
+    }
+    if (any3) {
+        std::vector<Shape> c;
+        for (int depth : {16, 32, 64}) {
+            if (best.sweep3 == 1 && depth == best.depth) continue;
+            Shape s = best;
+            s.sweep3 = 1;
+            s.depth = depth;
+            c.push_back(s);
+        }
+        if ((rc = stage(c)) != FLD_OK) return rc;
+        int depth3 = 0;
+        for (const auto& D : p.dl) depth3 = std::max(depth3, (int)D.sw3.size());
+        c.clear();
+        for (int l = 1; l <= depth3; ++l) {
+            if (l == best.levels3) continue;
+            Shape s = best;
+            s.sweep3 = 1;
+            s.levels3 = l;
+            c.push_back(s);
+        }
+        if (best.sweep3 == 1) {
+            Shape s = best;
+            s.sweep3 = 0;
+            c.push_back(s);
+        }
+        if ((rc = stage(c)) != FLD_OK) return rc;
     }
     // block caps only matter where a launch has more tiles than the smallest cap
-    (void)plan_set_shape(p, best.wide, best.rows, best.nblk);
+    if ((rc = plan_set_shape(p, best)) != FLD_OK) return rc;
     const int tiles = max_list_tiles(p);
-    for (int nblk : {1024, 4096, 8192, 16384}) {
-        if (nblk == best.nblk || (nblk > tiles && best.nblk >= tiles)) continue;
-        Shape s{best.wide, best.rows, nblk};
-        double us = 0;
-        int rc = time_shape(p, s, e0, e1, us);
-        if (rc != FLD_OK) return rc;
-        ++timed;
-        if (us < 0.98 * best_us) { best = s; best_us = us; }
+    {
+        std::vector<Shape> c;
+        for (int nblk : {1024, 4096, 8192, 16384}) {
+            if (nblk == best.nblk || (nblk > tiles && best.nblk >= tiles)) continue;
+            Shape s = best;
+            s.nblk = nblk;
+            c.push_back(s);
+        }
+        if ((rc = stage(c)) != FLD_OK) return rc;
     }
-    int rc = plan_set_shape(p, best.wide, best.rows, best.nblk);
-    if (rc != FLD_OK) return rc;
+    if ((rc = plan_set_shape(p, best)) != FLD_OK) return rc;
     FLD_HIP(hipDeviceSynchronize());
     p.tune_source = 1;
     p.tune_candidates = timed;

@@ -48,6 +48,14 @@ __host__ __device__ constexpr size_t fused_lds(int word, int halo, int wide, int
 }
 constexpr size_t kFusedLdsMax = 160 * 1024;
 
+// Fused 3D sweep blocks: kS3X x FY interior columns and fz planes (fz even, tunable);
+// FY by word size, and one row less where the sweep also restricts (a wider halo).
+constexpr int kS3X = 64;
+__host__ __device__ constexpr int sweep3_fy(int word) { return word == 4 ? 8 : 4; }
+__host__ __device__ constexpr int sweep3_fy_restrict(int word) { return word == 4 ? 6 : 4; }
+__host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], int fy, int fz) {
+    return ((n[0] + kS3X - 1) / kS3X) * ((n[1] + fy - 1) / fy) * ((n[2] + fz - 1) / fz);
+}
 
 struct LevelDesc {
     int32_t n[3];        // nx, ny, nz (nz = 1 in 2D)
@@ -172,6 +180,13 @@ void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                   int wide, int fy, int nblk, hipStream_t s);
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
                 int nblk, hipStream_t s);
+// Fused 3D sweeps (one red-black sweep per launch, colour c0 first), reading x (or xs
+// with from_xs) and writing the other; modes: 0 from the iterate, 1 from zero, 2 / 3 the
+// same plus restriction of the final residual, 4 from the iterate plus the prolonged
+// coarse correction.
+bool fused3_supported(bool fp32);
+void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
+                   int from_xs, int fz, int nblk, hipStream_t s);
 void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s);
 // LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to

@@ -46,6 +46,9 @@ struct DimLists {
     std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
     std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
     bool fused = false;
+    std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
+    bool fused3 = false;                       // fused 3D sweeps available (lists and xs laid out)
+    int levels3 = 0;                           // leading depths that run fused sweeps
     HostList coarsest;                         // coarsest level of grids without a tail
     HostList tail;                             // first tail level of grids with a tail
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
@@ -103,6 +106,9 @@ struct Plan {
     int tile_wide = 0;
     int tile_rows = 16;
     int nblk = 2048;
+    int tile_depth = 32;                       // fused 3D sweep: planes per block
+    int sweep3 = 1;                            // 1: fused 3D sweeps where available; 0: per colour
+    int sweep3_levels = 0;                     // leading 3D depths with fused sweeps (0: by block count)
     int tune_source = 0;                       // 0 defaults / options, 1 timed at bind, 2 cache
     int tune_candidates = 0;
     double tune_us = 0.0;                      // timed multigrid part of one V-cycle
@@ -152,6 +158,10 @@ int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s);
 // multigrid part of a V-cycle for each candidate, or take it from the cache.
 int plan_autotune(Plan& p);
 void plan_vcycle_mg(Plan& p, hipStream_t s);             // the timed part: smoothing, transfers, tails
-int plan_set_shape(Plan& p, int wide, int rows, int nblk); // rebuild and upload the fused lists
+struct LaunchShape {
+    int wide, rows, nblk, depth, sweep3, levels3;
+};
+int plan_set_shape(Plan& p, const LaunchShape& s);         // rebuild and upload the fused lists
+LaunchShape plan_shape(const Plan& p);
 
 }  // namespace fld

@@ -348,6 +348,13 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
 // (A x)_i = x_i + sum_faces w_f (x_i - x_nb); the residual is formed as
 // b - x - sum w (x - x_nb), so nearly equal neighbours cancel before scaling.
 // ---------------------------------------------------------------------------
+// Level arrays live in global memory, but pointers read from a LevelDesc carry no
+// address space, so accesses through them compile to flat loads and stores, which
+// also count against the LDS wait counter: a kernel that keeps global loads in
+// flight while it works on LDS must access them through global pointers.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
+
 template <typename T> struct Arr;
 template <> struct Arr<double> {
     __device__ static double* x(const LevelDesc& d) { return d.x; }
@@ -846,6 +853,241 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
             if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused 3D sweeps.  One launch runs one whole red-black sweep (colour c0, then
+// 1-c0) over FX x FY x fz cell blocks: a block marches along z through its
+// planes, holding a ring of x planes and of b / face-weight planes in LDS.
+// At step zt it stores plane zt (loaded two steps earlier into registers) and
+// issues the loads of plane zt+2, then updates colour c0 on plane zt-1 and
+// colour 1-c0 on plane zt-2 -- the first colour must be final on planes
+// zt-3..zt-1 before the second reads them -- and writes plane zt-2 out.  The xy halo
+// (colour c0 on one ring more than 1-c0) is recomputed exactly as the
+// neighbouring blocks compute it.  Modes add the transfers of the V-cycle:
+//   SW_LOAD      start from the stored iterate
+//   SW_ZERO      start from zero (nothing loaded)
+//   SW_*_RESTR   also compute the residual of the final iterate on plane zt-3
+//                and average it onto the coarse right-hand side (one more halo
+//                ring, one more plane of lag)
+//   SW_PROLONG   add the piecewise-constant prolongation of the coarse
+//                correction to the iterate as it is loaded
+// Each cell update and residual uses the operand order of the per-colour
+// kernels (k_smooth, residual_at, k_restrict), so both paths give bitwise
+// equal results.  A sweep never writes the array it reads.
+// ---------------------------------------------------------------------------
+enum SweepMode : int { SW_LOAD = 0, SW_ZERO = 1, SW_LOAD_RESTR = 2, SW_ZERO_RESTR = 3, SW_PROLONG = 4 };
+
+template <typename T, int W, int H, int RX, int RB>
+struct Sweep3Tile {
+    T x[RX][H][W];
+    T b[RB][H][W];
+    T w0[RB][H][W];
+    T w1[RB][H][W];
+    T w2[RB][H][W];
+};
+
+template <typename T, int MODE>
+struct Sweep3Shape {
+    static constexpr bool RESTR = MODE == SW_LOAD_RESTR || MODE == SW_ZERO_RESTR;
+    static constexpr bool LOADX = MODE == SW_LOAD || MODE == SW_LOAD_RESTR || MODE == SW_PROLONG;
+    static constexpr bool PROL = MODE == SW_PROLONG;
+    static constexpr int HALO = RESTR ? 3 : 2;
+    static constexpr int FX = kS3X;
+    static constexpr int FY = RESTR ? sweep3_fy_restrict(sizeof(T)) : sweep3_fy(sizeof(T));
+    static constexpr int W = FX + 2 * HALO, H = FY + 2 * HALO;
+    static constexpr int RX = HALO + 2;          // x planes zt-RX+1 .. zt
+    static constexpr int RB = HALO + 1;          // b / w planes zt-RB+1 .. zt
+    using Tile = Sweep3Tile<T, W, H, RX, RB>;
+};
+
+// Update colour c on plane p (ring slots s_m, s_0, s_p of planes p-1, p, p+1) over
+// local [m, W-m) x [m, H-m).
+template <typename T, typename Tl, int W, int H>
+__device__ __forceinline__ void sweep3_stage(Tl& t, int gx0, int gy0, int gp, int c, int m, int xs_m,
+                                             int xs_0, int xs_p, int bs_0, int bs_p) {
+    constexpr int PW = W / 2;
+    for (int e = threadIdx.x; e < PW * H; e += kBlock) {
+        const int lj = e / PW, pc = e - lj * PW;
+        if (lj < m || lj >= H - m) continue;
+        const int li = 2 * pc + ((gx0 + gy0 + lj + gp + c) & 1);
+        if (li < m || li >= W - m) continue;
+        T s = t.b[bs_0][lj][li], dg = T(1);
+        T w = t.w0[bs_0][lj][li];
+        s += w * t.x[xs_0][lj][li - 1]; dg += w;
+        w = t.w0[bs_0][lj][li + 1];
+        s += w * t.x[xs_0][lj][li + 1]; dg += w;
+        w = t.w1[bs_0][lj][li];
+        s += w * t.x[xs_0][lj - 1][li]; dg += w;
+        w = t.w1[bs_0][lj + 1][li];
+        s += w * t.x[xs_0][lj + 1][li]; dg += w;
+        w = t.w2[bs_0][lj][li];
+        s += w * t.x[xs_m][lj][li]; dg += w;
+        w = t.w2[bs_p][lj][li];
+        s += w * t.x[xs_p][lj][li]; dg += w;
+        t.x[xs_0][lj][li] = s / dg;
+    }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int c0, int from_xs,
+         int fz) {
+    using Sh = Sweep3Shape<T, MODE>;
+    constexpr int HALO = Sh::HALO, FX = Sh::FX, FY = Sh::FY, W = Sh::W, H = Sh::H, RX = Sh::RX, RB = Sh::RB;
+    constexpr int NE = (W * H + kBlock - 1) / kBlock;
+    static_assert((FX / 2) * (FY / 2) <= kBlock, "one coarse cell per thread");
+    static_assert(FX % 2 == 0 && FY % 2 == 0, "blocks cover whole coarse cells");
+    __shared__ typename Sh::Tile t;
+    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[jl.levels[jb]];
+        if (!S[d.grid].active) continue;
+        const int lt = tt - jl.prefix[jb];
+        const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+        const int tx_n = (n0 + FX - 1) / FX, ty_n = (n1 + FY - 1) / FY;
+        const int tx = lt % tx_n, rest = lt / tx_n;
+        const int gx0 = tx * FX - HALO, gy0 = (rest % ty_n) * FY - HALO;
+        const int z0 = (rest / ty_n) * fz, z1 = min(z0 + fz, n2);
+        const int zs = z0 - HALO, ze = z1 + HALO;          // planes loaded: [zs, ze)
+        const long sy = n0, sz = (long)n0 * n1;
+        const gptr<T> xin = as_global(Sh::LOADX ? (from_xs ? Arr<T>::xs(d) : Arr<T>::x(d)) : Arr<T>::x(d));
+        const gptr<T> xout = as_global(from_xs ? Arr<T>::x(d) : Arr<T>::xs(d));
+        const gptr<T> bg = as_global(Arr<T>::b(d));
+        const gptr<T> w0g = as_global(Arr<T>::w(d, 0));
+        const gptr<T> w1g = as_global(Arr<T>::w(d, 1));
+        const gptr<T> w2g = as_global(Arr<T>::w(d, 2));
+        gptr<T> cx = nullptr;
+        int cn0 = 0, cn1 = 0;
+        if (Sh::PROL || Sh::RESTR) {
+            const LevelDesc& cL = L[d.coarse];
+            cx = as_global(Arr<T>::x(cL));
+            cn0 = cL.n[0];
+            cn1 = cL.n[1];
+        }
+        // Plane loads are branch-free (an address outside the block's domain part is
+        // clamped to element 0 and its value replaced by 0), so every thread issues the
+        // same loads and the wait for a plane loaded two steps ago does not also wait
+        // for the plane loaded one step ago.
+        struct Regs {
+            T x[NE], b[NE], w0[NE], w1[NE], w2[NE];
+        };
+        auto load_plane = [&](Regs& v, int gk) {
+#pragma unroll
+            for (int r = 0; r < NE; ++r) {
+                const int e = threadIdx.x + r * kBlock;
+                const int lj = e / W, li = e - lj * W;
+                const int gi = gx0 + li, gj = gy0 + lj;
+                const bool ok = e < W * H && gk >= 0 && gk < n2 && gi >= 0 && gi < n0 && gj >= 0 && gj < n1;
+                const long idx = ok ? gi + gj * sy + gk * sz : 0;
+                const T bb = bg[idx], a0 = w0g[idx], a1 = w1g[idx], a2 = w2g[idx];
+                T xx = T(0);
+                if (Sh::LOADX) xx = xin[idx];
+                if (Sh::PROL) {
+                    const long cidx = ok ? (gi >> 1) + (long)cn0 * ((gj >> 1) + (long)cn1 * (gk >> 1)) : 0;
+                    xx += cx[cidx];
+                }
+                v.b[r] = ok ? bb : T(0);
+                v.w0[r] = ok ? a0 : T(0);
+                v.w1[r] = ok ? a1 : T(0);
+                v.w2[r] = ok ? a2 : T(0);
+                v.x[r] = ok ? xx : T(0);
+            }
+        };
+        // restriction: thread e < (FX/2)(FY/2) owns one coarse cell of the block and sums
+        // its 8 children over two planes
+        T racc = T(0);
+        gptr<T> cb = nullptr;
+        int cI = 0, cJ = 0, cnx = 0, cny = 0;
+        bool rown = false;
+        if (Sh::RESTR) {
+            const LevelDesc& cL = L[d.coarse];
+            cb = as_global(Arr<T>::b(cL));
+            cnx = cL.n[0];
+            cny = cL.n[1];
+            const int e = threadIdx.x, cj = e / (FX / 2), ci = e - cj * (FX / 2);
+            cI = (gx0 + HALO) / 2 + ci;
+            cJ = (gy0 + HALO) / 2 + cj;
+            rown = e < (FX / 2) * (FY / 2) && cI < cnx && cJ < cny;
+        }
+        // step zt: store plane zt (loaded two steps earlier), load plane zt + 2 into the
+        // same registers, then the two colour stages, the output and the restriction.
+        // ze - zs is even (fz and the halos are), so the steps pair up.
+        auto step = [&](int zt, Regs& v) {
+            const int px = (zt - zs) % RX, pb = (zt - zs) % RB;
+#pragma unroll
+            for (int r = 0; r < NE; ++r) {
+                const int e = threadIdx.x + r * kBlock;
+                if (e < W * H) {
+                    const int lj = e / W, li = e - lj * W;
+                    t.x[px][lj][li] = v.x[r];
+                    t.b[pb][lj][li] = v.b[r];
+                    t.w0[pb][lj][li] = v.w0[r];
+                    t.w1[pb][lj][li] = v.w1[r];
+                    t.w2[pb][lj][li] = v.w2[r];
+                }
+            }
+            load_plane(v, zt + 2);                                // past ze: all clamped, unused
+            __syncthreads();
+            // ring slot of plane p (p >= zs)
+            auto sx = [&](int p) { return (p - zs) % RX; };
+            auto sb = [&](int p) { return (p - zs) % RB; };
+            const int p1 = zt - 1;                                // first colour
+            if (p1 >= z0 - (HALO - 1) && p1 < z1 + (HALO - 1))
+                sweep3_stage<T, typename Sh::Tile, W, H>(t, gx0, gy0, p1, c0, 1, sx(p1 - 1), sx(p1), sx(p1 + 1),
+                                                         sb(p1), sb(p1 + 1));
+            __syncthreads();
+            const int p2 = zt - 2;                                // second colour
+            const bool p2ok = p2 >= z0 - (HALO - 2) && p2 < z1 + (HALO - 2);
+            if (p2ok)
+                sweep3_stage<T, typename Sh::Tile, W, H>(t, gx0, gy0, p2, c0 ^ 1, 2, sx(p2 - 1), sx(p2), sx(p2 + 1),
+                                                         sb(p2), sb(p2 + 1));
+            __syncthreads();
+            if (p2 >= z0 && p2 < z1) {                            // plane p2 is final
+                const int s0 = sx(p2);
+                for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+                    const int lj = e / FX, li = e - lj * FX;
+                    const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
+                    if (gi < n0 && gj < n1) xout[gi + gj * sy + p2 * sz] = t.x[s0][HALO + lj][HALO + li];
+                }
+            }
+            if (Sh::RESTR) {
+                const int p3 = zt - 3;
+                if (p3 >= z0 && p3 < z1 && rown) {
+                    const int m_ = sx(p3 - 1), o_ = sx(p3), q_ = sx(p3 + 1), b0_ = sb(p3), bp_ = sb(p3 + 1);
+                    if (((p3 - z0) & 1) == 0) racc = T(0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int li = HALO + 2 * (cI - (gx0 + HALO) / 2) + (q & 1);
+                        const int lj = HALO + 2 * (cJ - (gy0 + HALO) / 2) + (q >> 1);
+                        const T xc = t.x[o_][lj][li];
+                        T r = t.b[b0_][lj][li] - xc;
+                        r -= t.w0[b0_][lj][li] * (xc - t.x[o_][lj][li - 1]);
+                        r -= t.w0[b0_][lj][li + 1] * (xc - t.x[o_][lj][li + 1]);
+                        r -= t.w1[b0_][lj][li] * (xc - t.x[o_][lj - 1][li]);
+                        r -= t.w1[b0_][lj + 1][li] * (xc - t.x[o_][lj + 1][li]);
+                        r -= t.w2[b0_][lj][li] * (xc - t.x[m_][lj][li]);
+                        r -= t.w2[bp_][lj][li] * (xc - t.x[q_][lj][li]);
+                        racc += r;
+                    }
+                    if ((p3 - z0) & 1) {
+                        // the coarse level's sweeps start from zero (per-colour kernels read it)
+                        const long cidx = cI + (long)cnx * (cJ + (long)cny * (p3 >> 1));
+                        cb[cidx] = racc * T(0.125);
+                        cx[cidx] = T(0);
+                    }
+                }
+            }
+            __syncthreads();                                      // ring slots are rewritten next step
+        };
+        Regs ra, rb;
+        load_plane(ra, zs);
+        load_plane(rb, zs + 1);
+        for (int zt = zs; zt < ze; zt += 2) {
+            step(zt, ra);
+            step(zt + 1, rb);
+        }
     }
 }
 
@@ -1361,6 +1603,32 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
     });
+}
+
+bool fused3_supported(bool fp32) {
+    (void)fp32;
+    return true;
+}
+
+void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
+                   int from_xs, int fz, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for(jl.total, nblk);
+#define FLD_SWEEP3(M)                                                                                   \
+    do {                                                                                               \
+        if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(kBlock), 0, s, L, S, jl, c0,  \
+                                     from_xs, fz);                                                     \
+        else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(kBlock), 0, s, L, S, jl, c0,      \
+                                from_xs, fz);                                                          \
+    } while (0)
+    switch (mode) {
+        case SW_LOAD: FLD_SWEEP3(SW_LOAD); break;
+        case SW_ZERO: FLD_SWEEP3(SW_ZERO); break;
+        case SW_LOAD_RESTR: FLD_SWEEP3(SW_LOAD_RESTR); break;
+        case SW_ZERO_RESTR: FLD_SWEEP3(SW_ZERO_RESTR); break;
+        default: FLD_SWEEP3(SW_PROLONG); break;
+    }
+#undef FLD_SWEEP3
 }
 
 bool fused2_supported(int nu) { return nu >= 1 && nu <= 3; }

@@ -64,7 +64,11 @@ int validate_opts(const fld_opts& o) {
     if (o.tile_wide != 0 && o.tile_wide != 1) return FLD_ERR_INVALID_ARG;
     if (o.max_blocks < 0 || o.max_blocks > (1 << 20)) return FLD_ERR_INVALID_ARG;
     // the tuner picks the launch shape itself
-    if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks)) return FLD_ERR_INVALID_ARG;
+    if (o.tile_depth != 0 && o.tile_depth != 16 && o.tile_depth != 32 && o.tile_depth != 64)
+        return FLD_ERR_INVALID_ARG;
+    if (o.fused3_levels < 0 || o.fused3_levels > 64) return FLD_ERR_INVALID_ARG;
+    if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks || o.tile_depth || o.fused3_levels))
+        return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
 
@@ -91,8 +95,33 @@ int tiles_cell(const LevelDesc& d) { return cell_tiles(d.n); }
 int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
 
-// Fused-tile prefixes of the down / up lists for the plan's tile shape.
+constexpr int kSweep3MinBlocks = 256;
+
+// Fused-tile prefixes of the down / up lists (2D) and the sweep lists (3D) for the
+// plan's launch shape.
 void finish_fused(const Plan& p, DimLists& D) {
+    const int word = p.mixed ? 4 : 8;
+    for (size_t dpt = 0; dpt < D.sw3.size(); ++dpt) {
+        HostList& a = D.sw3[dpt];
+        HostList& r = D.sr3[dpt];
+        a.prefix.assign(1, 0);
+        r.prefix.assign(1, 0);
+        for (int32_t li : a.levels)
+            a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, sweep3_fy(word), p.tile_depth));
+        for (int32_t li : r.levels)
+            r.prefix.push_back(r.prefix.back() +
+                               sweep3_tiles(p.levels[li].n, sweep3_fy_restrict(word), p.tile_depth));
+    }
+    // a fused sweep marches through its planes in sequence, so a level needs many blocks
+    // to fill the chip: by default only the leading depths with at least one block per
+    // compute unit (kSweep3MinBlocks) run fused, the coarser ones per colour
+    const int nd = (int)D.sw3.size();
+    if (p.sweep3_levels > 0) {
+        D.levels3 = std::min(p.sweep3_levels, nd);
+    } else {
+        D.levels3 = 0;
+        while (D.levels3 < nd && D.sw3[D.levels3].prefix.back() >= kSweep3MinBlocks) ++D.levels3;
+    }
     const int fxd = fused_fx(2 * p.opts.nu1 + 1, p.tile_wide), fxu = fused_fx(2 * p.opts.nu2, p.tile_wide);
     for (size_t dpt = 0; dpt < D.down2.size(); ++dpt) {
         HostList& dn = D.down2[dpt];
@@ -214,6 +243,16 @@ static void build_lists(Plan& p) {
             D.down2[dpt].levels = D.smooth[dpt].levels;
             D.up2[dpt].levels = D.smooth[dpt].levels;
         }
+        // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
+        // even for its result to end in x
+        D.fused3 = D.dim == 3 && p.opts.fused && fused3_supported(p.mixed) && p.opts.nu1 >= 1 &&
+                   p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0;
+        D.sw3.resize(D.fused3 ? maxdepth : 0);
+        D.sr3.resize(D.fused3 ? maxdepth : 0);
+        for (int dpt = 0; dpt < (int)D.sw3.size(); ++dpt) {
+            D.sw3[dpt].levels = D.smooth[dpt].levels;
+            D.sr3[dpt].levels = D.smooth[dpt].levels;
+        }
         finish_fused(p, D);
         for (int dpt = 0; dpt < maxdepth; ++dpt) {
             finish_list(D.smooth[dpt], p.levels, tiles_smooth);
@@ -258,6 +297,8 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.tile_wide = opts.tile_wide;
     p.tile_rows = opts.tile_rows ? opts.tile_rows : 16;
     p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
+    p.tile_depth = opts.tile_depth ? opts.tile_depth : 32;
+    p.sweep3_levels = opts.fused3_levels;
     if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) &&
         !(fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows, true) &&
           fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false)))
@@ -288,6 +329,8 @@ static void layout(Plan& p) {
         for (auto& l : D.coarsen) place_list(l);
         for (auto& l : D.down2) place_list(l);
         for (auto& l : D.up2) place_list(l);
+        for (auto& l : D.sw3) place_list(l);
+        for (auto& l : D.sr3) place_list(l);
         for (auto& l : D.smooth) place_list(l);
         for (auto& l : D.restrict_) place_list(l);
         for (auto& l : D.prolong) place_list(l);
@@ -344,8 +387,8 @@ static void layout(Plan& p) {
             f.has_scratch = true;
             f.scratch = take(4 * n * 8);
         }
-        // fused 2D levels (every level with a coarser one) keep the down pass's output apart
-        if (d.ndim == 2 && d.coarse >= 0 && p.dl[0].fused) {
+        // fused levels (every level with a coarser one) keep the down pass's output apart
+        if (d.coarse >= 0 && ((d.ndim == 2 && p.dl[0].fused) || (d.ndim == 3 && p.dl[1].fused3))) {
             f.has_xs = true;
             f.xs = take(n * (p.mixed ? 4 : 8));
         }
@@ -365,7 +408,22 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
     const bool f32 = p.mixed;
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;   // level-0 V-cycle starts from the iterate
     const int dim = D.dim;
+    // fused 3D sweeps on the leading depths: sweep k of a level's V-cycle (1-based)
+    // reads x and writes xs when k is odd, the reverse when k is even; nu1 + nu2 is
+    // even, so the level's result ends in x
+    const int L3 = (D.fused3 && p.sweep3) ? D.levels3 : 0;
+    const int nu1 = p.opts.nu1, nu2 = p.opts.nu2, fz = p.tile_depth;
     for (int d = 0; d < D.maxdepth; ++d) {
+        if (d < L3) {
+            for (int k = 1; k <= nu1; ++k) {
+                const bool load = k > 1 || (d == 0 && plain64);
+                const bool restr = k == nu1;
+                const int mode = restr ? (load ? 2 : 3) : (load ? 0 : 1);
+                launch_sweep3(f32, p.dL, p.dS, restr ? D.sr3[d].dev : D.sw3[d].dev, mode, 0, k % 2 == 0, fz,
+                              p.nblk, s);
+            }
+            continue;
+        }
         if (D.fused) {
             launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.tile_wide,
                          p.tile_rows, p.nblk, s);
@@ -380,6 +438,11 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
     launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
     launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
     for (int d = D.maxdepth - 1; d >= 0; --d) {
+        if (d < L3) {
+            for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
+                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, fz, p.nblk, s);
+            continue;
+        }
         if (D.fused) {
             launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, p.tile_rows, p.nblk, s);
             continue;
@@ -447,21 +510,32 @@ static int upload_list(Plan& p, HostList& l) {
     return FLD_OK;
 }
 
-int plan_set_shape(Plan& p, int wide, int rows, int nblk) {
+LaunchShape plan_shape(const Plan& p) {
+    return LaunchShape{p.tile_wide, p.tile_rows, p.nblk, p.tile_depth, p.sweep3, p.sweep3_levels};
+}
+
+int plan_set_shape(Plan& p, const LaunchShape& sh) {
     if (!p.ws) return FLD_ERR_NO_WORKSPACE;
     for (auto& D : p.dl)
-        if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, wide, rows, true) &&
-                         fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false)))
+        if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows, true) &&
+                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows, false)))
             return FLD_ERR_INVALID_ARG;
-    if (nblk < 1) return FLD_ERR_INVALID_ARG;
-    p.tile_wide = wide;
-    p.tile_rows = rows;
-    p.nblk = nblk;
+    if (sh.nblk < 1 || (sh.depth != 16 && sh.depth != 32 && sh.depth != 64) || (sh.sweep3 != 0 && sh.sweep3 != 1) ||
+        sh.levels3 < 0)
+        return FLD_ERR_INVALID_ARG;
+    p.tile_wide = sh.wide;
+    p.tile_rows = sh.rows;
+    p.nblk = sh.nblk;
+    p.tile_depth = sh.depth;
+    p.sweep3 = sh.sweep3;
+    p.sweep3_levels = sh.levels3;
     for (auto& D : p.dl) {
         finish_fused(p, D);
         int rc;
         for (auto& l : D.down2) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
         for (auto& l : D.up2) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
+        for (auto& l : D.sw3) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
+        for (auto& l : D.sr3) if ((rc = upload_list(p, l)) != FLD_OK) return rc;
     }
     return FLD_OK;
 }
@@ -520,6 +594,8 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
         for (auto& l : D.coarsen) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.down2) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.up2) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.sw3) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.sr3) if ((rc = upload(l)) != FLD_OK) return rc;
         if (!D.tail.empty() && prepare_tail(D.dim, p.mixed, D.tail_smem) != 0) {
             g_last_error = "hipFuncSetAttribute(max dynamic LDS) failed for the tail kernel";
             return FLD_ERR_HIP;
@@ -697,6 +773,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
             case FLD_KERNEL_DOWN: if (has_level && D.fused) l = &D.down2[level]; break;
             case FLD_KERNEL_UP: if (has_level && D.fused) l = &D.up2[level]; break;
             case FLD_KERNEL_TAIL: l = D.tail.empty() ? nullptr : &D.tail; break;
+            case FLD_KERNEL_SWEEP3: if (has_level && D.fused3) l = &D.sw3[level]; break;
             default: l = &D.l0_cell; break;
         }
         if (!l) continue;
@@ -741,6 +818,10 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2,
                                                          p.tile_wide, p.tile_rows, p.nblk, s);
+                    break;
+                case FLD_KERNEL_SWEEP3:
+                    if (has_level && D.fused3)
+                        launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, p.tile_depth, p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
                     launch_tail(D.dim, p.mixed, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
@@ -1011,12 +1092,18 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     out->source = p.tune_source;
     out->candidates = p.tune_candidates;
     out->vcycle_us = p.tune_us;
+    out->tile_depth = p.tile_depth;
+    int l3 = 0;
+    for (const auto& D : p.dl)
+        if (D.fused3 && !D.l0_cell.empty() && p.sweep3) l3 = std::max(l3, D.levels3);
+    out->fused3 = l3 > 0 ? 1 : 0;
+    out->fused3_levels = l3;
     return FLD_OK;
 }
 
 int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps, void* stream,
                            double* avg_ms, int64_t* cells) {
-    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_TAIL)
+    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_SWEEP3)
         return FLD_ERR_INVALID_ARG;
     Plan& p = plan->p;
     if (!p.ws) return FLD_ERR_NO_WORKSPACE;

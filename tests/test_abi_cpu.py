@@ -75,7 +75,9 @@ def test_plan_create_validates_options(kw, code):
     # an FP64 128-wide, 32-row tile with the nu = 2 halo needs more than the 160 KB of LDS
     (dict(tile_wide=1, tile_rows=32), False), (dict(tile_wide=1, tile_rows=32, precision=1), True),
     (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1), True),
-    (dict(tile_wide=1, tile_rows=32, fused=0), True)])
+    (dict(tile_wide=1, tile_rows=32, fused=0), True), (dict(tile_depth=16), True),
+    (dict(tile_depth=64), True), (dict(tile_depth=24), False), (dict(autotune=1, tile_depth=32), False),
+    (dict(fused3_levels=2), True), (dict(fused3_levels=-1), False), (dict(autotune=1, fused3_levels=1), False)])
 def test_launch_shape_options(kw, ok):
     g = fld.make_grid((256, 256))
     if ok:

@@ -103,8 +103,9 @@ def test_autotuned_plan_matches_default_and_caches(precision, tmp_path, monkeypa
     assert len(lines) == 1
     key, rec = lines[0].split("\t")
     assert ("mixed" if precision else "fp64") in key
-    wide, rows, nblk, us = rec.split()
+    wide, rows, nblk, depth, sweep3, levels3, us = rec.split()
     assert (int(wide), int(rows), int(nblk)) == (t["tile_wide"], t["tile_rows"], t["max_blocks"])
+    assert int(depth) == t["tile_depth"]
 
     # same class: taken from the cache, no timing
     again = fld.Plan(shapes, h=hs, precision=precision, autotune=1)
@@ -128,7 +129,7 @@ def test_stale_cache_record_is_retimed(tmp_path, monkeypatch):
     p = fld.Plan([g.E.shape], h=[g.h], autotune=1)
     key = cache.read_text().split("\t")[0]
     p.close()
-    cache.write_text(f"{key}\t1 32 2048 1.0\n")
+    cache.write_text(f"{key}\t1 32 2048 32 1 0 1.0\n")
     q = fld.Plan([g.E.shape], h=[g.h], autotune=1)
     t = q.tuning()
     assert t["source"] == 1 and fits(0, t["tile_wide"], t["tile_rows"])
@@ -143,4 +144,20 @@ def test_untuned_plan_reports_its_options():
     p = fld.Plan([g.E.shape], h=[g.h], tile_rows=8, tile_wide=1, max_blocks=333)
     t = p.tuning()
     assert (t["tile_rows"], t["tile_wide"], t["max_blocks"], t["source"]) == (8, 1, 333, 0)
+    assert t["fused3"] == 0                     # no 3D grid
     p.close()
+
+
+def test_autotuner_times_the_3d_sweep_depths(tmp_path, monkeypatch):
+    monkeypatch.setenv("FLD_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    g = W.random_grid((48, 64, 80), 91400, dt=3e-3)
+    for precision in (0, 1):
+        p = fld.Plan([g.E.shape], h=[g.h], precision=precision, autotune=2)
+        t = p.tuning()
+        # the incumbent, two other depths and the per-colour kernels (+ block caps)
+        assert t["source"] == 1 and t["candidates"] >= 4, t
+        assert t["tile_depth"] in (16, 32, 64) and t["fused3"] in (0, 1)
+        (x,), (st,), rc = _solve(p, [g])
+        (xr,), (sr,), _ = run_step([g], precision=precision)
+        assert rc == 0 and np.array_equal(x, xr) and st["cycles"] == sr["cycles"]
+        p.close()
