@@ -16,6 +16,8 @@ namespace fld {
 constexpr int kTX = 64;
 constexpr int kTY = 4;
 constexpr int kBlock = 256;
+// MI355X: 256 compute units on 8 dies (XCDs), each die with its own L2.
+constexpr int kXcds = 8;
 // Red-black smoother: one thread per cell of one colour, 128 x 4 (x 1) cell tiles.
 constexpr int kSX = 128;
 // Coarsest-level solve: one workgroup per grid, up to kCoarseCPT cells per thread.

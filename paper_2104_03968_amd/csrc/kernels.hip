@@ -36,6 +36,34 @@ __device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int 
     return lo;
 }
 
+// XCD-aware tile order for kernels whose tiles share halo data.  The blocks of
+// a launch are dealt round-robin to the chip's kXcds dies (block b runs on die
+// b % kXcds), each die with its own L2.  With a block count that is a multiple
+// of kXcds, die x walks the contiguous tile range [x C, (x+1) C), C = total / kXcds
+// rounded up, so neighbouring tiles meet in one L2; otherwise the plain grid-stride
+// order is used.  XcdOrder o(total); for (int k = o.first(); o.more(k); k += o.step)
+// visits tile o.tile(k).
+struct XcdOrder {
+    int per, x, chunk, total, start;
+    __device__ explicit XcdOrder(int total_) : total(total_) {
+        const int G = gridDim.x;
+        if (G % kXcds == 0) {
+            per = G / kXcds;
+            x = blockIdx.x % kXcds;
+            start = blockIdx.x / kXcds;
+            chunk = (total + kXcds - 1) / kXcds;
+        } else {
+            per = G;
+            x = 0;
+            start = blockIdx.x;
+            chunk = total;
+        }
+    }
+    __device__ int first() const { return start; }
+    __device__ int tile(int k) const { return x * chunk + k; }
+    __device__ bool more(int k) const { return k < chunk && x * chunk + k < total; }
+};
+
 __device__ __forceinline__ int mirror(int i, int n) {
     // even reflection across a zero-flux face: -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2
     return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
@@ -263,7 +291,9 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         const StepIO* __restrict__ io, double c, int limiter, int fin, double rtol, int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const int lt = t - jl.prefix[jb];
@@ -310,7 +340,9 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
         const LevelDesc& cL = L[f.coarse];
@@ -394,7 +426,9 @@ __device__ __forceinline__ T residual_at(const T* __restrict__ x, const T* __res
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int color) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -432,7 +466,9 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
         if (!S[f.grid].active) continue;
@@ -461,7 +497,9 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
         if (!S[f.grid].active) continue;
@@ -783,7 +821,9 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
     __shared__ Tl t;
-    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k = order.first(); order.more(k); k += order.per) {
+        const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -832,7 +872,9 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
     __shared__ Tl t;
-    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k = order.first(); order.more(k); k += order.per) {
+        const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -940,7 +982,9 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
     static_assert((FX / 2) * (FY / 2) <= kBlock, "one coarse cell per thread");
     static_assert(FX % 2 == 0 && FY % 2 == 0, "blocks cover whole coarse cells");
     __shared__ typename Sh::Tile t;
-    for (int tt = blockIdx.x; tt < jl.total; tt += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k = order.first(); order.more(k); k += order.per) {
+        const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -1279,7 +1323,9 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
            int zero_x, int fin, double rtol, int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const GridState& g = S[d.grid];
@@ -1326,7 +1372,9 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -1349,7 +1397,9 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         GridState& g = S[d.grid];
@@ -1392,7 +1442,9 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         GridState& g = S[d.grid];
@@ -1424,7 +1476,9 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
@@ -1439,7 +1493,9 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__ io) {
-    for (int t = blockIdx.x; t < jl.total; t += gridDim.x) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         int i, j, k;
@@ -1542,6 +1598,11 @@ k_exchange(const ExchangeIO* __restrict__ io, double c, double a_rad, double c_v
 }
 
 inline int blocks_for(int total, int nblk) { return total < nblk ? (total > 0 ? total : 1) : nblk; }
+// block count for the XCD-ordered kernels: a multiple of kXcds
+inline int blocks_for_xcd(int total, int nblk) {
+    const int g = blocks_for(total, nblk);
+    return (g + kXcds - 1) / kXcds * kXcds;
+}
 
 }  // namespace
 
@@ -1553,7 +1614,7 @@ void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
                   const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
         else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
@@ -1568,7 +1629,7 @@ void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, dou
 
 void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_coarsen<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl);
         else hipLaunchKernelGGL((k_coarsen<D, false>), dim3(g), dim3(kBlock), 0, s, L, jl);
@@ -1578,7 +1639,7 @@ void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nbl
 void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                    int color, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_smooth<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl, color);
         else hipLaunchKernelGGL((k_smooth<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl, color);
@@ -1588,7 +1649,7 @@ void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, J
 void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                      int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_restrict<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_restrict<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -1598,7 +1659,7 @@ void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S,
 void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                     int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -1613,7 +1674,7 @@ bool fused3_supported(bool fp32) {
 void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
                    int from_xs, int fz, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_SWEEP3(M)                                                                                   \
     do {                                                                                               \
         if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(kBlock), 0, s, L, S, jl, c0,  \
@@ -1678,7 +1739,7 @@ void up2_t(const LevelDesc* L, const GridState* S, JobList jl, int g, hipStream_
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
                   int wide, int fy, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
         if (fp32) down2_t<float, NU, WIDE, FY>(L, S, jl, load_x, g, s);
         else down2_t<double, NU, WIDE, FY>(L, S, jl, load_x, g, s);
@@ -1688,7 +1749,7 @@ void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
                 int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
         if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, g, s);
         else up2_t<double, NU, WIDE, FY>(L, S, jl, g, s);
@@ -1725,7 +1786,7 @@ void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState
 void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
                      int select, int zero_x, int fin, double rtol, int max_cycles, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x, fin, rtol, max_cycles);
         else hipLaunchKernelGGL((k_residual<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x, fin, rtol, max_cycles);
@@ -1734,7 +1795,7 @@ void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobL
 
 #define FLD_CG_LAUNCH(kern)                                                                          \
     if (jl.total <= 0) return;                                                                       \
-    const int g = blocks_for(jl.total, nblk);                                                        \
+    const int g = blocks_for_xcd(jl.total, nblk);                                                        \
     FLD_DISPATCH_DIM(dim, {                                                                          \
         if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles); \
         else hipLaunchKernelGGL((kern<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles);      \
@@ -1758,14 +1819,14 @@ void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, Job
 void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_correct<D>), dim3(g), dim3(kBlock), 0, s, L, S, jl); });
 }
 
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
                    hipStream_t s) {
     if (jl.total <= 0) return;
-    const int g = blocks_for(jl.total, nblk);
+    const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_output<D>), dim3(g), dim3(kBlock), 0, s, L, jl, io); });
 }
 
