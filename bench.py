@@ -71,6 +71,27 @@ def dominant_kernel(fld, ndim: int, word: int, fused: bool, fused3: bool):
     return fld.FLD_KERNEL_SMOOTH, "k_smooth", word * (2 + ndim)
 
 
+def measured_traffic(cfg: str, kname: str, launch: dict):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record kept under profiles/ (copy-calibrated), or None when there is no record for this
+    workload and launch shape, or kernels.hip has changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2104_03968_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    keys = ("tile_rows", "tile_wide", "max_blocks", "tile_depth", "fused3_levels")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic_record: "):
+                continue
+            rec = json.loads(line[len("traffic_record: "):])
+            if (rec.get("config") == cfg and rec.get("kernel", "").startswith(kname + "<")
+                    and rec.get("kernels_sha256") == sha
+                    and all(rec.get("launch", {}).get(k) == launch.get(k) for k in keys)):
+                return float(rec["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(g, steps_gas: bool):
     import oracle as O
     t0 = time.perf_counter()
@@ -275,7 +296,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(cfg, kname, tuning),
                      "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"},
     }
     if not args.no_cpu_baseline:

@@ -103,16 +103,38 @@ __device__ __forceinline__ void cell_of_tile(const int32_t n[3], int lt, int tid
     j = ty * kTY + (tid / kTX);
 }
 
-// Sum the level-0 per-tile partials of one grid in a fixed order.
-__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int ntiles, int stride,
-                                          double& a, double& b, double* sh) {
+// Sum the level-0 per-tile partials of one grid in a fixed order: thread t adds
+// partials t, t + kBlock, t + 2 kBlock, ... in turn, then a fixed-order block sum.
+// The loads are issued kSumBatch at a time so they overlap; the additions keep
+// their order.  LOAD reads partial i (plain, or past the L1 for the last-block path).
+constexpr int kSumBatch = 16;
+template <typename LOAD>
+__device__ __forceinline__ void sum_parts_with(LOAD load, int ntiles, int stride, double& a, double& b,
+                                               double* sh) {
     a = 0.0;
     b = 0.0;
-    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
-        a += part[stride * i];
-        if (stride == 2) b += part[stride * i + 1];
+    for (int i0 = threadIdx.x; i0 < ntiles; i0 += kSumBatch * kBlock) {
+        double va[kSumBatch], vb[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int i = i0 + u * kBlock;
+            va[u] = i < ntiles ? load(stride * i) : 0.0;
+            vb[u] = (stride == 2 && i < ntiles) ? load(stride * i + 1) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            if (i0 + u * kBlock < ntiles) {
+                a += va[u];
+                if (stride == 2) b += vb[u];
+            }
+        }
     }
     block_sum2<kBlock>(a, b, sh);
+}
+
+__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int ntiles, int stride,
+                                          double& a, double& b, double* sh) {
+    sum_parts_with([&](int i) { return part[i]; }, ntiles, stride, a, b, sh);
 }
 
 // Stop test / CG scalar update of one grid from the summed partials (thread 0).
@@ -199,13 +221,8 @@ __device__ __forceinline__ bool grid_tile_done(GridState& g, int ntiles, int* fl
 __device__ __forceinline__ void sum_parts_coherent(const double* part, int ntiles, int stride, double& a,
                                                    double& b, double* sh) {
     __threadfence();
-    a = 0.0;
-    b = 0.0;
-    for (int i = threadIdx.x; i < ntiles; i += kBlock) {
-        a += __hip_atomic_load(part + stride * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (stride == 2) b += __hip_atomic_load(part + stride * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_sum2<kBlock>(a, b, sh);
+    sum_parts_with([&](int i) { return __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
+                   ntiles, stride, a, b, sh);
 }
 
 // End of a reducing kernel's tile: store the partial(s) and, if this was the
