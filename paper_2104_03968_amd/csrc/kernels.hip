@@ -855,13 +855,13 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         }
         // smoothed iterate of the interior (to xs: other tiles may still read x), and the
         // residual averaged onto the coarse cells
-        T* __restrict__ xo = Arr<T>::xs(d);
+        const gptr<T> xo = as_global(Arr<T>::xs(d));
         for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
             const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
             if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
         }
-        T* __restrict__ cb = Arr<T>::b(cL);
+        const gptr<T> cb = as_global(Arr<T>::b(cL));
         for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
             const int cj = e / (FX / 2), ci = e - cj * (FX / 2);
             const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj;
@@ -905,7 +905,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
             tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 1);
             tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 2);
         }
-        T* __restrict__ xo = Arr<T>::x(d);
+        const gptr<T> xo = as_global(Arr<T>::x(d));
         for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
             const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
@@ -1027,33 +1027,33 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
             cn0 = cL.n[0];
             cn1 = cL.n[1];
         }
-        // Plane loads are branch-free (an address outside the block's domain part is
-        // clamped to element 0 and its value replaced by 0), so every thread issues the
-        // same loads and the wait for a plane loaded two steps ago does not also wait
-        // for the plane loaded one step ago.
+        // Plane loads are branch-free (a cell outside the level loads its nearest
+        // in-level cell; the value is replaced by 0 when it is stored to LDS), so every
+        // thread issues the same loads, nothing uses them before the store two steps
+        // later, and the wait for that plane does not also wait for the next one.
         struct Regs {
-            T x[NE], b[NE], w0[NE], w1[NE], w2[NE];
+            T x[NE], c[NE], b[NE], w0[NE], w1[NE], w2[NE];
+            uint32_t ok;        // bit r: element r lies inside the level
         };
         auto load_plane = [&](Regs& v, int gk) {
+            v.ok = 0;
 #pragma unroll
             for (int r = 0; r < NE; ++r) {
                 const int e = threadIdx.x + r * kBlock;
-                const int lj = e / W, li = e - lj * W;
+                const int ec = min(e, W * H - 1);
+                const int lj = ec / W, li = ec - lj * W;
                 const int gi = gx0 + li, gj = gy0 + lj;
                 const bool ok = e < W * H && gk >= 0 && gk < n2 && gi >= 0 && gi < n0 && gj >= 0 && gj < n1;
-                const long idx = ok ? gi + gj * sy + gk * sz : 0;
-                const T bb = bg[idx], a0 = w0g[idx], a1 = w1g[idx], a2 = w2g[idx];
-                T xx = T(0);
-                if (Sh::LOADX) xx = xin[idx];
-                if (Sh::PROL) {
-                    const long cidx = ok ? (gi >> 1) + (long)cn0 * ((gj >> 1) + (long)cn1 * (gk >> 1)) : 0;
-                    xx += cx[cidx];
-                }
-                v.b[r] = ok ? bb : T(0);
-                v.w0[r] = ok ? a0 : T(0);
-                v.w1[r] = ok ? a1 : T(0);
-                v.w2[r] = ok ? a2 : T(0);
-                v.x[r] = ok ? xx : T(0);
+                // out-of-level cells load their nearest in-level cell (a line read anyway)
+                const int ic = min(max(gi, 0), n0 - 1), jc = min(max(gj, 0), n1 - 1), kc = min(max(gk, 0), n2 - 1);
+                const long idx = ic + jc * sy + kc * sz;
+                v.ok |= (ok ? 1u : 0u) << r;
+                v.b[r] = bg[idx];
+                v.w0[r] = w0g[idx];
+                v.w1[r] = w1g[idx];
+                v.w2[r] = w2g[idx];
+                if (Sh::LOADX) v.x[r] = xin[idx];
+                if (Sh::PROL) v.c[r] = cx[(ic >> 1) + (long)cn0 * ((jc >> 1) + (long)cn1 * (kc >> 1))];
             }
         };
         // restriction: thread e < (FX/2)(FY/2) owns one coarse cell of the block and sums
@@ -1082,11 +1082,14 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 const int e = threadIdx.x + r * kBlock;
                 if (e < W * H) {
                     const int lj = e / W, li = e - lj * W;
-                    t.x[px][lj][li] = v.x[r];
-                    t.b[pb][lj][li] = v.b[r];
-                    t.w0[pb][lj][li] = v.w0[r];
-                    t.w1[pb][lj][li] = v.w1[r];
-                    t.w2[pb][lj][li] = v.w2[r];
+                    const bool ok = (v.ok >> r) & 1u;
+                    T xx = Sh::LOADX ? v.x[r] : T(0);
+                    if (Sh::PROL) xx += v.c[r];
+                    t.x[px][lj][li] = ok ? xx : T(0);
+                    t.b[pb][lj][li] = ok ? v.b[r] : T(0);
+                    t.w0[pb][lj][li] = ok ? v.w0[r] : T(0);
+                    t.w1[pb][lj][li] = ok ? v.w1[r] : T(0);
+                    t.w2[pb][lj][li] = ok ? v.w2[r] : T(0);
                 }
             }
             load_plane(v, zt + 2);                                // past ze: all clamped, unused
