@@ -101,7 +101,7 @@ typedef struct fld_opts {
                              kernels (sweeps + restriction, prolongation + sweeps)
                              when nu1, nu2 are in 1..3; 0: one kernel per colour
                              sweep and per transfer [1]                             */
-    int32_t tile_rows;    /* fused 2D tile rows: 8, 16 or 32; 0 = 16 [0]            */
+    int32_t tile_rows;    /* fused 2D tile rows: 4, 8, 16 or 32; 0 = 16 [0]         */
     int32_t tile_wide;    /* fused 2D tile width: 0 = 64 cells, 1 = 128 cells less
                              the halo (a colour cell per lane of a 64-lane wave) [0].
                              INVALID_ARG if the tile does not fit the 160 KB LDS   */

@@ -2,7 +2,7 @@
 // transfers, tails; the solver state is only read) is timed for each
 // candidate launch shape and the fastest is kept.  The candidates are, one
 // dimension after the other: the fused 2D tile (64-wide or full-wave-wide,
-// 8/16/32 rows); for 3D grids the fused sweep's planes per block (16/32/64),
+// 4/8/16/32 rows); for 3D grids the fused sweep's planes per block (16/32/64),
 // then how many leading levels run fused (or none: per-colour kernels); and
 // the cap on persistent workgroups.
 // Choices are cached in a text file, one line per plan class:
@@ -191,7 +191,7 @@ int plan_autotune(Plan& p) {
     if (any2) {
         std::vector<Shape> c;
         for (int wide = 0; wide <= 1; ++wide)
-            for (int rows : {8, 16, 32}) {
+            for (int rows : {4, 8, 16, 32}) {
                 if (wide == best.wide && rows == best.rows) continue;
                 if (!fused2_shape_ok(p.mixed, p.opts.nu1, wide, rows, true) ||
                     !fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false))

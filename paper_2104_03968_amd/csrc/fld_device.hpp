@@ -66,6 +66,7 @@ struct LevelDesc {
     int32_t level;       // 0 = finest
     int32_t coarse;      // index of the next coarser level, -1 at the coarsest
     int32_t fine;        // index of the next finer level, -1 at level 0
+    int32_t nlev;        // levels of the owning grid (a grid's levels are consecutive entries)
     double  hinv[3];     // 1/h per axis (level 0 values are the grid's)
     double* x;           // FP64 solution (level 0) / correction (coarser)
     double* b;           // FP64 right-hand side
@@ -175,7 +176,7 @@ int prepare_tail(int dim, bool fp32, size_t smem);
 // Fused 2D level kernels (nu in 1..3).  down: nu red-black sweeps from a zero (or, with
 // load_x, the stored) iterate, then the residual restricted to the coarse right-hand
 // side; up: add the prolonged coarse correction, then nu black-red sweeps.
-// Tile shapes: wide in {0,1}, fy in {8,16,32}, as long as the tile fits the LDS.
+// Tile shapes: wide in {0,1}, fy in {4,8,16,32}, as long as the tile fits the LDS.
 bool fused2_supported(int nu);
 bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down);
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,

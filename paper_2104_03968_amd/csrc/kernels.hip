@@ -1193,8 +1193,10 @@ __device__ __forceinline__ void tl_coords(const TailLevel<T>& lv, int c, int& i,
     }
 }
 
+// Levels are passed by value: a copy in registers, since the LDS stores of a phase
+// could otherwise alias the descriptor table in LDS and force its re-reading.
 template <int DIM, typename T>
-__device__ __forceinline__ void tl_half_sweep(const TailLevel<T>& lv, int color) {
+__device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) {
     const int sy = lv.n[0], sz = lv.n[0] * lv.n[1];
     const int rows = lv.n[1] * lv.n[2];
     for (int m = threadIdx.x; m < rows * lv.hx; m += kTailThreads) {
@@ -1227,68 +1229,74 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
        int plain64) {
     extern __shared__ __align__(16) unsigned char tail_smem[];
     __shared__ TailLevel<T> tl[kMaxTail];
+    __shared__ int32_t off[kMaxTail + 1];
     __shared__ double red[2 * kTailThreads / 64];
-    __shared__ int ntl;
     const int first = jl.levels[blockIdx.x];
-    if (!S[L[first].grid].active) return;
-    if (threadIdx.x == 0) {
-        T* base = reinterpret_cast<T*>(tail_smem);
-        int m = 0;
-        for (int li = first; li >= 0 && m < kMaxTail; li = L[li].coarse, ++m) {
-            const LevelDesc& d = L[li];
-            TailLevel<T>& t = tl[m];
-            t.n[0] = d.n[0]; t.n[1] = d.n[1]; t.n[2] = d.n[2];
-            t.ncell = d.n[0] * d.n[1] * d.n[2];
-            t.hx = (d.n[0] + 1) / 2;
-            t.rhx = 1.0f / (float)t.hx;
-            t.rnx = 1.0f / (float)d.n[0];
-            t.rny = 1.0f / (float)d.n[1];
-            t.x = base; base += t.ncell;
-            t.b = base; base += t.ncell;
-            for (int a = 0; a < 3; ++a) {
-                t.w[a] = (a < DIM) ? base : nullptr;
-                if (a < DIM) base += t.ncell;
-            }
+    const LevelDesc& d0 = L[first];
+    if (!S[d0.grid].active) return;
+    // the grid's levels from `first` down are consecutive descriptors: thread m reads
+    // level m's (no chain through the coarse links), then the LDS layout follows
+    const int nl = min(d0.nlev - d0.level, kMaxTail);
+    const int m_own = threadIdx.x;
+    int32_t nown[3] = {0, 0, 0};
+    if (m_own < nl) {
+        const LevelDesc& d = L[first + m_own];
+        nown[0] = d.n[0]; nown[1] = d.n[1]; nown[2] = d.n[2];
+        off[m_own + 1] = (2 + DIM) * d.n[0] * d.n[1] * d.n[2];
+    }
+    if (threadIdx.x == 0) off[0] = 0;
+    __syncthreads();
+    if (m_own < nl) {
+        int o = 0;
+        for (int j = 0; j < m_own; ++j) o += off[j + 1];
+        T* base = reinterpret_cast<T*>(tail_smem) + o;
+        TailLevel<T>& t = tl[m_own];
+        t.n[0] = nown[0]; t.n[1] = nown[1]; t.n[2] = nown[2];
+        t.ncell = nown[0] * nown[1] * nown[2];
+        t.hx = (nown[0] + 1) / 2;
+        t.rhx = 1.0f / (float)t.hx;
+        t.rnx = 1.0f / (float)nown[0];
+        t.rny = 1.0f / (float)nown[1];
+        t.x = base; base += t.ncell;
+        t.b = base; base += t.ncell;
+        for (int a = 0; a < 3; ++a) {
+            t.w[a] = (a < DIM) ? base : nullptr;
+            if (a < DIM) base += t.ncell;
         }
-        ntl = m;
     }
     __syncthreads();
-    const int nl = ntl;
     T* p_sh = tl[nl - 1].w[DIM - 1] + tl[nl - 1].ncell;   // the coarsest CG's search direction
     // load every tail level's weights, and b and (warm) x of the first; loads of a
     // level are issued together, then stored
-    {
-        int li = first;
-        for (int m = 0; m < nl; ++m, li = L[li].coarse) {
-            const LevelDesc& d = L[li];
-            const TailLevel<T>& t = tl[m];
-            const T* s0 = Arr<T>::w(d, 0);
-            const T* s1 = Arr<T>::w(d, 1);
-            const T* s2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
-            const bool lead = (m == 0);
-            const bool warm = lead && plain64 && d.level == 0;
-            const T* bsrc = Arr<T>::b(d);
-            const T* xsrc = Arr<T>::x(d);
-            for (int c = threadIdx.x; c < t.ncell; c += kTailThreads) {
-                const T a0 = s0[c], a1 = s1[c];
-                const T a2 = (DIM == 3) ? s2[c] : T(0);
-                const T bb = lead ? bsrc[c] : T(0);
-                const T xx = warm ? xsrc[c] : T(0);
-                t.w[0][c] = a0;
-                t.w[1][c] = a1;
-                if (DIM == 3) t.w[2][c] = a2;
-                if (lead) {
-                    t.b[c] = bb;
-                    t.x[c] = xx;
-                }
+    for (int m = 0; m < nl; ++m) {
+        const LevelDesc& d = L[first + m];
+        const TailLevel<T> t = tl[m];
+        const T* s0 = Arr<T>::w(d, 0);
+        const T* s1 = Arr<T>::w(d, 1);
+        const T* s2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
+        const bool lead = (m == 0);
+        const bool warm = lead && plain64 && d.level == 0;
+        const T* bsrc = Arr<T>::b(d);
+        const T* xsrc = Arr<T>::x(d);
+        for (int c = threadIdx.x; c < t.ncell; c += kTailThreads) {
+            const T a0 = s0[c], a1 = s1[c];
+            const T a2 = (DIM == 3) ? s2[c] : T(0);
+            const T bb = lead ? bsrc[c] : T(0);
+            const T xx = warm ? xsrc[c] : T(0);
+            t.w[0][c] = a0;
+            t.w[1][c] = a1;
+            if (DIM == 3) t.w[2][c] = a2;
+            if (lead) {
+                t.b[c] = bb;
+                t.x[c] = xx;
             }
         }
     }
     __syncthreads();
     // descend
     for (int m = 0; m + 1 < nl; ++m) {
-        const TailLevel<T>& f = tl[m];
-        const TailLevel<T>& cT = tl[m + 1];
+        const TailLevel<T> f = tl[m];
+        const TailLevel<T> cT = tl[m + 1];
         for (int it = 0; it < nu1; ++it) {
             tl_half_sweep<DIM, T>(f, 0);
             tl_half_sweep<DIM, T>(f, 1);
@@ -1308,13 +1316,13 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     }
     // coarsest: CG from the current x (zero unless the grid has a single level)
     {
-        const TailLevel<T>& cT = tl[nl - 1];
+        const TailLevel<T> cT = tl[nl - 1];
         block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
-        const TailLevel<T>& f = tl[m];
-        const TailLevel<T>& cT = tl[m + 1];
+        const TailLevel<T> f = tl[m];
+        const TailLevel<T> cT = tl[m + 1];
         for (int c = threadIdx.x; c < f.ncell; c += kTailThreads) {
             int i, j, k;
             tl_coords<DIM, T>(f, c, i, j, k);
@@ -1328,7 +1336,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     }
     {
         T* xdst = Arr<T>::x(L[first]);
-        for (int c = threadIdx.x; c < tl[0].ncell; c += kTailThreads) xdst[c] = tl[0].x[c];
+        const TailLevel<T> t0 = tl[0];
+        for (int c = threadIdx.x; c < t0.ncell; c += kTailThreads) xdst[c] = t0.x[c];
     }
 }
 
@@ -1715,7 +1724,7 @@ void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
 bool fused2_supported(int nu) { return nu >= 1 && nu <= 3; }
 
 bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down) {
-    if (!fused2_supported(nu) || (wide != 0 && wide != 1) || (fy != 8 && fy != 16 && fy != 32)) return false;
+    if (!fused2_supported(nu) || (wide != 0 && wide != 1) || (fy != 4 && fy != 8 && fy != 16 && fy != 32)) return false;
     return fused_lds(fp32 ? 4 : 8, down ? 2 * nu + 1 : 2 * nu, wide, fy) <= kFusedLdsMax;
 }
 
@@ -1730,12 +1739,14 @@ bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down) {
     do {                                                                  \
         if (wide) {                                                       \
             constexpr int WIDE = 1;                                       \
-            if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }         \
+            if ((fy) == 4) { constexpr int FY = 4; __VA_ARGS__; }         \
+            else if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }    \
             else if ((fy) == 16) { constexpr int FY = 16; __VA_ARGS__; }  \
             else { constexpr int FY = 32; __VA_ARGS__; }                  \
         } else {                                                          \
             constexpr int WIDE = 0;                                       \
-            if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }         \
+            if ((fy) == 4) { constexpr int FY = 4; __VA_ARGS__; }         \
+            else if ((fy) == 8) { constexpr int FY = 8; __VA_ARGS__; }    \
             else if ((fy) == 16) { constexpr int FY = 16; __VA_ARGS__; }  \
             else { constexpr int FY = 32; __VA_ARGS__; }                  \
         }                                                                 \

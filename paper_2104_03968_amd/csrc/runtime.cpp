@@ -60,7 +60,8 @@ int validate_opts(const fld_opts& o) {
     if (o.krylov != 0 && o.krylov != 1) return FLD_ERR_INVALID_ARG;
     if (o.fused != 0 && o.fused != 1) return FLD_ERR_INVALID_ARG;
     if (o.autotune < 0 || o.autotune > 2) return FLD_ERR_INVALID_ARG;
-    if (o.tile_rows != 0 && o.tile_rows != 8 && o.tile_rows != 16 && o.tile_rows != 32) return FLD_ERR_INVALID_ARG;
+    if (o.tile_rows != 0 && o.tile_rows != 4 && o.tile_rows != 8 && o.tile_rows != 16 && o.tile_rows != 32)
+        return FLD_ERR_INVALID_ARG;
     if (o.tile_wide != 0 && o.tile_wide != 1) return FLD_ERR_INVALID_ARG;
     if (o.max_blocks < 0 || o.max_blocks > (1 << 20)) return FLD_ERR_INVALID_ARG;
     // the tuner picks the launch shape itself
@@ -165,6 +166,7 @@ static void build_levels(Plan& p) {
             ++lev;
         }
         p.nlev.push_back(lev + 1);
+        for (int l = 0; l <= lev; ++l) p.levels[p.level0[g] + l].nlev = lev + 1;
     }
 }
 

@@ -67,7 +67,7 @@ def test_plan_create_validates_options(kw, code):
 
 
 @pytest.mark.parametrize("kw,ok", [
-    (dict(tile_rows=8), True), (dict(tile_rows=32), True), (dict(tile_rows=12), False),
+    (dict(tile_rows=4), True), (dict(tile_rows=8), True), (dict(tile_rows=32), True), (dict(tile_rows=12), False),
     (dict(tile_wide=1), True), (dict(tile_wide=2), False), (dict(max_blocks=512), True),
     (dict(max_blocks=-1), False), (dict(autotune=1), True), (dict(autotune=2), True),
     (dict(autotune=3), False), (dict(autotune=1, tile_rows=16), False),
