@@ -9,3 +9,7 @@ diffusion").
 """
 from .fld import *  # noqa: F401,F403
 from .fld import __all__  # noqa: F401
+from .moments import *  # noqa: F401,F403,E402
+from . import moments as _moments  # noqa: E402
+
+__all__ = list(__all__) + list(_moments.__all__)
