@@ -71,6 +71,39 @@ def dominant_kernel(fld, ndim: int, word: int, fused: bool, fused3: bool):
     return fld.FLD_KERNEL_SMOOTH, "k_smooth", word * (2 + ndim)
 
 
+def time_moments(fld, plan, grids, E, K, stream, reps: int = 20):
+    """Time fld_radiation_moments with every output and a synthetic velocity field (HIP
+    events on the bench stream, after the timed steps).  Algorithmic bytes per cell:
+    E, kappa rho and the d velocity components read; d flux, d force, f, d(d+1)/2
+    pressure components, the tiring work and E_out written (8 B each)."""
+    import torch
+    import workloads as W
+    nd = grids[0].E.ndim
+    v = [[torch.from_numpy(W.smooth_field(g.E.shape, 4242 + 10 * i + a)).to(E[0].device) for a in range(g.E.ndim)]
+         for i, g in enumerate(grids)]
+    outs = []
+    for e in E:
+        d = e.dim()
+        outs.append({"F": [torch.empty_like(e) for _ in range(d)], "f_r": [torch.empty_like(e) for _ in range(d)],
+                     "edd": torch.empty_like(e), "P": [torch.empty_like(e) for _ in range(d * (d + 1) // 2)],
+                     "tiring": torch.empty_like(e), "E_out": torch.empty_like(e)})
+    dts = [g.dt for g in grids]
+    call = lambda: fld.fld_radiation_moments(plan.handle, E, K, outs, v=v, dt=dts, stream=stream)
+    call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    cells = sum(g.E.size for g in grids)
+    bpc = 8 * ((2 + nd) + (nd + nd + 1 + nd * (nd + 1) // 2 + 2))
+    gbs = bpc * cells / (us * 1e-6) / 1e9
+    return {"kernel": "k_moments", "us_per_call": us, "cells": cells, "bytes_per_cell": bpc,
+            "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def measured_traffic(cfg: str, kname: str, launch: dict):
     """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
     record kept under profiles/ (copy-calibrated), or None when there is no record for this
@@ -300,6 +333,7 @@ def main():
                      "traffic": measured_traffic(cfg, kname, tuning),
                      "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"},
     }
+    out["radiation_moments"] = time_moments(fld, plan, grids, E, K, stream)
     if not args.no_cpu_baseline:
         g0 = grids[0] if cfg != "c4" else grids[0]
         log("bench: timing the FP64 CPU oracle on one step of the first grid")

@@ -224,6 +224,38 @@ int32_t fld_exchange(fld_plan_t plan, double* const* E, double* const* eps,
    bisection fallback since the last call. */
 int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected);
 
+/* Radiation moments of E, per cell of every grid g (Sec. 2.2, 2.1 and 3.2), with
+   the 4th-order gradient and the plan's limiter and c (as in the coefficient pass):
+     F   = -c lambda / (kappa rho) grad E                      (eq. fld_F)
+     f_r = rho kappa F / c                                      (eq. rhd_force)
+     f   = lambda + lambda^2 R^2                                (eq. fld_Edd_fac)
+     P   = E (1/2 (1 - f) I + 1/2 (3 f - 1) n n), n = grad E / |grad E|
+           (n = 0 where grad E = 0)                             (eq. fld_Edd)
+   and, given the gas velocity v, the photon-tiring work
+     P : grad v = sum_ij P_ij dv_i/dx_j  (4th-order gradients of v, mirrored ghosts)
+   and the explicit update E_out = E - dt P : grad v (the term's sign in the
+   radiation energy equation, Eq. 0th_cmf).  Each output array holds N_g doubles;
+   NULL outputs are skipped.  P is stored as its upper triangle, row-major:
+   xx, xy, yy (2D); xx, xy, xz, yy, yz, zz (3D). */
+typedef struct fld_moments_out {
+    double* F[3];         /* flux components x, y[, z]                              */
+    double* f_r[3];       /* radiation force density components                     */
+    double* edd;          /* scalar Eddington factor f                              */
+    double* P[6];         /* pressure tensor components (see above)                 */
+    double* tiring;       /* P : grad v (needs v)                                   */
+    double* E_out;        /* E - dt P : grad v (needs v; must differ from E)        */
+} fld_moments_out;
+/* E, kappa_rho: host arrays of ngrids device pointers (N_g doubles each).  v: NULL,
+   or a host array of 3 * ngrids device pointers, v[3 g + d] the d-th component of
+   grid g's velocity (NULL entries: no velocity for that grid; all ndim or none).
+   dt: host array of ngrids (read only where E_out is set; may be NULL otherwise).
+   out: host array of ngrids.  Needs a bound workspace (nothing of a step is read).
+   Asynchronous on stream.  Errors: INVALID_ARG (null inputs, partial velocity,
+   tiring or E_out without velocity, E_out == E, non-finite dt), NO_WORKSPACE, HIP. */
+int32_t fld_radiation_moments(fld_plan_t plan, const double* const* E, const double* const* kappa_rho,
+                              const double* const* v, const double* dt, const fld_moments_out* out,
+                              void* stream);
+
 /* ---- measurement -------------------------------------------------------- */
 #define FLD_KERNEL_SMOOTH    0   /* one red-black half sweep over every grid's level `level` */
 #define FLD_KERNEL_RESIDUAL  1   /* level-0 FP64 residual and its per-tile norms           */

@@ -51,7 +51,7 @@ __all__ = [
     "exchange_coefficients", "fld_step", "residual_floor_tol",
 ]
 
-LIMITERS = ("lp", "diffusion")
+LIMITERS = ("lp", "diffusion", "minerbo", "lp_exact")
 
 
 # --------------------------------------------------------------------------------------
@@ -105,12 +105,30 @@ def flux_limiter(R: np.ndarray, kind: str = "lp") -> np.ndarray:
     """Flux limiter lambda(R) (Sec. 2.2).
 
     ``"lp"``: the rational bridging law ``(2+R)/(6+3R+R^2)`` (eq. fld_lambda);
-    ``"diffusion"``: the optically thick value 1/3.
+    ``"diffusion"``: the optically thick value 1/3;
+    ``"minerbo"``: Minerbo (1978), the alternative Sec. 2.2 names without giving
+    its form: ``2/(3 + sqrt(9 + 12 R^2))`` for R <= 3/2, ``1/(1 + R + sqrt(1 + 2R))``
+    above (the two branches meet with equal value and slope at 3/2);
+    ``"lp_exact"``: Levermore and Pomraning's own form ``(coth R - 1/R)/R``, which
+    the rational law of eq. fld_lambda approximates; below R = 0.1 its series
+    ``1/3 - R^2/45 + 2R^4/945 - R^6/4725 + 2R^8/93555`` (truncation < 1e-16)
+    replaces the cancelling difference.
     """
+    R = np.asarray(R, dtype=np.float64)
     if kind == "lp":
         return (2.0 + R) / (6.0 + 3.0 * R + R * R)
     if kind == "diffusion":
         return np.full_like(R, 1.0 / 3.0)
+    if kind == "minerbo":
+        lo = 2.0 / (3.0 + np.sqrt(9.0 + 12.0 * R * R))
+        hi = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))
+        return np.where(R <= 1.5, lo, hi)
+    if kind == "lp_exact":
+        R2 = R * R
+        series = 1.0 / 3.0 + R2 * (-1.0 / 45.0 + R2 * (2.0 / 945.0 + R2 * (-1.0 / 4725.0 + R2 * 2.0 / 93555.0)))
+        Rs = np.where(R < 0.1, 1.0, R)
+        direct = (1.0 / np.tanh(Rs) - 1.0 / Rs) / Rs
+        return np.where(R < 0.1, series, direct)
     raise ValueError(f"unknown limiter {kind!r}")
 
 

@@ -82,6 +82,11 @@ class fld_tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fld_moments_out(C.Structure):
+    _fields_ = [("F", C.c_void_p * 3), ("f_r", C.c_void_p * 3), ("edd", C.c_void_p), ("P", C.c_void_p * 6),
+                ("tiring", C.c_void_p), ("E_out", C.c_void_p)]
+
+
 class fld_stats(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("status", C.c_int32), ("rel_residual", C.c_double),
                 ("q_b", C.c_double), ("b_norm", C.c_double), ("b_sum", C.c_double)]
@@ -146,6 +151,7 @@ _sig = {
     "fld_exchange": (C.c_int32, [_P, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas), _P]),
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
     "fld_plan_tuning": (C.c_int32, [_P, C.POINTER(fld_tuning)]),
+    "fld_radiation_moments": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_moments_out), _P]),
     "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
     "fld_server_opts_default": (None, [C.POINTER(fld_server_opts)]),
@@ -301,6 +307,34 @@ def fld_exchange_status(plan: int, stream=None):
     b = C.c_int64()
     rc = _lib.fld_exchange_status(plan, _stream(stream), C.byref(b))
     return rc, b.value
+
+
+def fld_radiation_moments(plan: int, E, kappa_rho, outs, v=None, dt=None, stream=None) -> None:
+    """outs: one dict per grid with optional keys F, f_r (lists of ndim tensors), edd,
+    P (list of ndim (ndim+1)/2 tensors), tiring, E_out; v: per grid a list of ndim
+    velocity tensors, or None."""
+    n = len(E)
+    arr = (fld_moments_out * n)()
+    for g, o in enumerate(outs):
+        ptr = lambda t: 0 if t is None else (t if isinstance(t, int) else t.data_ptr())
+        for a, t in enumerate(o.get("F") or []):
+            arr[g].F[a] = ptr(t)
+        for a, t in enumerate(o.get("f_r") or []):
+            arr[g].f_r[a] = ptr(t)
+        for q, t in enumerate(o.get("P") or []):
+            arr[g].P[q] = ptr(t)
+        arr[g].edd = ptr(o.get("edd"))
+        arr[g].tiring = ptr(o.get("tiring"))
+        arr[g].E_out = ptr(o.get("E_out"))
+    vp = None
+    if v is not None:
+        vp = (C.c_void_p * (3 * n))()
+        for g, comps in enumerate(v):
+            for a, t in enumerate(comps or []):
+                vp[3 * g + a] = 0 if t is None else t.data_ptr()
+    dts = _dts(dt, n) if dt is not None else None
+    _check(_lib.fld_radiation_moments(plan, _ptrs(E), _ptrs(kappa_rho), vp, dts, arr, _stream(stream)),
+           "fld_radiation_moments")
 
 
 def fld_plan_tuning(plan: int) -> dict:
@@ -510,3 +544,28 @@ class Plan:
 
     def tuning(self) -> dict:
         return fld_plan_tuning(self.handle)
+
+    def radiation_moments(self, E, kappa_rho, v=None, dt=None, want=("F", "f_r", "edd", "P"), stream=None):
+        """Allocate the requested outputs (torch, on the plan's device) and run
+        fld_radiation_moments; returns one dict of tensors per grid.  With v (per grid a
+        list of velocity tensors) "tiring" and "E_out" may be requested as well."""
+        import torch
+        outs = []
+        for g, e in enumerate(E):
+            nd = e.dim()
+            o = {}
+            if "F" in want:
+                o["F"] = [torch.empty_like(e) for _ in range(nd)]
+            if "f_r" in want:
+                o["f_r"] = [torch.empty_like(e) for _ in range(nd)]
+            if "edd" in want:
+                o["edd"] = torch.empty_like(e)
+            if "P" in want:
+                o["P"] = [torch.empty_like(e) for _ in range(nd * (nd + 1) // 2)]
+            if "tiring" in want:
+                o["tiring"] = torch.empty_like(e)
+            if "E_out" in want:
+                o["E_out"] = torch.empty_like(e)
+            outs.append(o)
+        fld_radiation_moments(self.handle, E, kappa_rho, outs, v=v, dt=dt, stream=stream)
+        return outs

@@ -145,6 +145,21 @@ struct ExchangeIO {
     int64_t       n;
 };
 
+// Per-call pointers of fld_radiation_moments (one entry per grid; NULL outputs are
+// not written; v[0] == NULL: no velocity).
+struct MomentsIO {
+    const double* E;
+    const double* kr;
+    const double* v[3];
+    double*       F[3];
+    double*       fr[3];
+    double*       edd;
+    double*       P[6];
+    double*       tiring;
+    double*       E_out;
+    double        dt;
+};
+
 struct Control {
     int32_t nactive;     // grids still iterating after the last count
     int32_t bad_exchange;
@@ -213,6 +228,9 @@ void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl,
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
                    hipStream_t s);
 void launch_count(const GridState* S, int ngrids, Control* ctrl, hipStream_t s);
+// Radiation moments of every level-0 cell of the listed grids (io indexed by grid).
+void launch_moments(int dim, const LevelDesc* L, JobList jl, const MomentsIO* io, double c, int limiter,
+                    int nblk, hipStream_t s);
 void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s);
 void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,
                      double c_v, int max_halley, double root_rtol, Control* ctrl, int nblk,

@@ -70,7 +70,7 @@ struct Plan {
     bool krylov = true;
 
     // workspace layout (byte offsets)
-    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_ctrl = 0;
+    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_moio = 0, off_ctrl = 0;
     size_t ws_bytes = 0;
     static constexpr int kExSlots = 4;
     struct FieldOff {
@@ -92,14 +92,18 @@ struct Plan {
     GridState* dS = nullptr;
     StepIO* dIO = nullptr;
     ExchangeIO* dEx = nullptr;
+    MomentsIO* dMo = nullptr;
     Control* dCtrl = nullptr;
     StepIO* hIO = nullptr;                     // pinned staging
     ExchangeIO* hEx = nullptr;                 // pinned staging, kExSlots * ngrids
+    MomentsIO* hMo = nullptr;                  // pinned staging, kExSlots * ngrids
     Control* hCtrl = nullptr;                  // pinned
     GridState* hS = nullptr;                   // pinned
     bool own_pinned = true;                    // false: staging buffers belong to a server
     hipEvent_t ex_done[kExSlots] = {};
     int ex_slot = 0;
+    hipEvent_t mo_done[kExSlots] = {};
+    int mo_slot = 0;
     int ex_last = -1;                          // slot of the last fld_exchange (profiling)
     int64_t max_n = 0;
     // launch shape: fused 2D tile (width class, rows) and the persistent-grid cap
@@ -130,9 +134,12 @@ inline Plan::~Plan() {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : ex_done)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : mo_done)
+        if (e) (void)hipEventDestroy(e);
     if (own_pinned) {
         if (hIO) (void)hipHostFree(hIO);
         if (hEx) (void)hipHostFree(hEx);
+        if (hMo) (void)hipHostFree(hMo);
         if (hCtrl) (void)hipHostFree(hCtrl);
         if (hS) (void)hipHostFree(hS);
     }

@@ -266,36 +266,47 @@ k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
 // neighbour is recomputed from its own stencil (same arithmetic as that
 // neighbour's thread), so each face is written once with no second pass.
 // ---------------------------------------------------------------------------
+// 4th-order central gradient of E at cell (i, j, k) with mirrored ghosts (Sec. 3.2,
+// eq. ileyk_flux); c12 = 1 / (12 h) per axis.  g[2] is 0 in 2D.
+template <int DIM>
+__device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, int j, int k, const int32_t n[3],
+                                         const double c12[3], double g[3]) {
+    const long sy = n[0], sz = (long)n[0] * n[1];
+    const long row = (long)j * sy + (long)k * sz;
+    g[0] = ((E[mirror(i - 2, n[0]) + row] - E[mirror(i + 2, n[0]) + row]) +
+            8.0 * (E[mirror(i + 1, n[0]) + row] - E[mirror(i - 1, n[0]) + row])) * c12[0];
+    const long col = i + (long)k * sz;
+    g[1] = ((E[col + mirror(j - 2, n[1]) * sy] - E[col + mirror(j + 2, n[1]) * sy]) +
+            8.0 * (E[col + mirror(j + 1, n[1]) * sy] - E[col + mirror(j - 1, n[1]) * sy])) * c12[1];
+    g[2] = 0.0;
+    if (DIM == 3) {
+        const long pil = i + (long)j * sy;
+        g[2] = ((E[pil + mirror(k - 2, n[2]) * sz] - E[pil + mirror(k + 2, n[2]) * sz]) +
+                8.0 * (E[pil + mirror(k + 1, n[2]) * sz] - E[pil + mirror(k - 1, n[2]) * sz])) * c12[2];
+    }
+}
+
+// Flux limiter lambda(R) (Sec. 2.2): the rational bridging law of eq. fld_lambda,
+// or 1/3.
+__device__ __forceinline__ double limiter_of(double R, int limiter) {
+    if (limiter == FLD_LIMITER_DIFFUSION) return 1.0 / 3.0;
+    if (R < 1e100) return (2.0 + R) / (6.0 + R * (3.0 + R));
+    return 1.0 / R;                         // free-streaming limit, avoids inf/inf
+}
+
 template <int DIM>
 __device__ __forceinline__ double cell_D(const double* __restrict__ E, const double* __restrict__ kr,
                                          int i, int j, int k, const int32_t n[3], const double c12[3],
                                          double c, int limiter) {
-    const long sy = n[0], sz = (long)n[0] * n[1];
-    const long row = (long)j * sy + (long)k * sz;
-    const double e = E[i + row];
-    const double kk = kr[i + row];
-    const double gx = ((E[mirror(i - 2, n[0]) + row] - E[mirror(i + 2, n[0]) + row]) +
-                       8.0 * (E[mirror(i + 1, n[0]) + row] - E[mirror(i - 1, n[0]) + row])) * c12[0];
-    const long col = i + (long)k * sz;
-    const double gy = ((E[col + mirror(j - 2, n[1]) * sy] - E[col + mirror(j + 2, n[1]) * sy]) +
-                       8.0 * (E[col + mirror(j + 1, n[1]) * sy] - E[col + mirror(j - 1, n[1]) * sy])) * c12[1];
-    double g2 = gx * gx + gy * gy;
-    if (DIM == 3) {
-        const long pil = i + (long)j * sy;
-        const double gz = ((E[pil + mirror(k - 2, n[2]) * sz] - E[pil + mirror(k + 2, n[2]) * sz]) +
-                           8.0 * (E[pil + mirror(k + 1, n[2]) * sz] - E[pil + mirror(k - 1, n[2]) * sz])) * c12[2];
-        g2 += gz * gz;
-    }
+    const long idx = i + (long)n[0] * (j + (long)n[1] * k);
+    const double e = E[idx];
+    const double kk = kr[idx];
+    double g[3];
+    grad4_at<DIM>(E, i, j, k, n, c12, g);
+    double g2 = g[0] * g[0] + g[1] * g[1];
+    if (DIM == 3) g2 += g[2] * g[2];
     const double R = sqrt(g2) / (kk * e);
-    double lam;
-    if (limiter == FLD_LIMITER_DIFFUSION) {
-        lam = 1.0 / 3.0;
-    } else if (R < 1e100) {
-        lam = (2.0 + R) / (6.0 + R * (3.0 + R));
-    } else {
-        lam = 1.0 / R;                      // free-streaming limit, avoids inf/inf
-    }
-    return c * lam / kk;
+    return c * limiter_of(R, limiter) / kk;
 }
 
 __device__ __forceinline__ double face_w(double DL, double DR, double dt, double hinv) {
@@ -1342,6 +1353,80 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
 }
 
 // ---------------------------------------------------------------------------
+// Radiation moments of E per cell, after the step (Sec. 2.2 and 3.2): with the
+// gradient and limiter of the coefficient pass, the flux F = -c lambda/(kappa
+// rho) grad E (eq. fld_F), the force density f_r = rho kappa F / c (eq.
+// rhd_force), the Eddington factor f = lambda + lambda^2 R^2 (eq. fld_Edd_fac)
+// and the pressure tensor E (1/2 (1-f) I + 1/2 (3f-1) n n), n = grad E/|grad E|
+// (eq. fld_Edd; n = 0 where the gradient vanishes).  With a velocity field, the
+// photon-tiring work P : grad v = sum_ij P_ij dv_i/dx_j from 4th-order velocity
+// gradients, and E - dt P : grad v (the explicit update of the energy equation,
+// where the term sits on the left-hand side).  Stencil reads of E and v only:
+// every output is written by its own cell.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restrict__ io, double c, int limiter) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        const MomentsIO& m = io[d.grid];
+        int i, j, k;
+        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        if (i >= d.n[0] || j >= d.n[1]) continue;
+        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+        const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
+        const double e = m.E[idx], kk = m.kr[idx];
+        double g[3];
+        grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
+        double g2 = g[0] * g[0] + g[1] * g[1];
+        if (DIM == 3) g2 += g[2] * g[2];
+        const double gn = sqrt(g2);
+        const double R = gn / (kk * e);
+        const double lam = limiter_of(R, limiter);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const double Fa = -c * lam / kk * g[a];
+            if (m.F[a]) m.F[a][idx] = Fa;
+            if (m.fr[a]) m.fr[a][idx] = kk * Fa / c;
+        }
+        const double f = R < 1e100 ? lam + lam * lam * R * R : lam + (lam * R) * (lam * R);
+        if (m.edd) m.edd[idx] = f;
+        double nv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nv[a] = (a < DIM && gn > 0.0) ? g[a] / gn : 0.0;
+        const double iso = 0.5 * (1.0 - f), aniso = 0.5 * (3.0 * f - 1.0);
+        double P[DIM][DIM];
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+            for (int b = a; b < DIM; ++b, ++q) {
+                double tt = aniso * nv[a] * nv[b];
+                if (a == b) tt = tt + iso;
+                P[a][b] = e * tt;
+                P[b][a] = P[a][b];
+                if (m.P[q]) m.P[q][idx] = P[a][b];
+            }
+        }
+        if (m.v[0]) {
+            double tir = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double dv[3];
+                grad4_at<DIM>(m.v[a], i, j, k, d.n, c12, dv);        // dv[b] = d v_a / d x_b
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) tir = tir + P[a][b] * dv[b];
+            }
+            if (m.tiring) m.tiring[idx] = tir;
+            if (m.E_out) m.E_out[idx] = e - m.dt * tir;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Level-0 FP64 residual r = b - A x and its per-tile partial ||r||^2.  In mixed
 // precision the residual also becomes the FP32 right-hand side of the next
 // correction V-cycle, whose correction starts from zero.
@@ -1867,6 +1952,13 @@ void launch_count(const GridState* S, int ngrids, Control* ctrl, hipStream_t s) 
 
 void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s) {
     hipLaunchKernelGGL(k_set_active, dim3((ngrids + kBlock - 1) / kBlock), dim3(kBlock), 0, s, S, ngrids, value);
+}
+
+void launch_moments(int dim, const LevelDesc* L, JobList jl, const MomentsIO* io, double c, int limiter,
+                    int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, hipLaunchKernelGGL((k_moments<D>), dim3(g), dim3(kBlock), 0, s, L, jl, io, c, limiter));
 }
 
 void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,

@@ -319,6 +319,7 @@ static void layout(Plan& p) {
     p.off_state = off;  off = align_up(off + G * sizeof(GridState));
     p.off_stepio = off; off = align_up(off + G * sizeof(StepIO));
     p.off_exio = off;   off = align_up(off + Plan::kExSlots * G * sizeof(ExchangeIO));
+    p.off_moio = off;   off = align_up(off + Plan::kExSlots * G * sizeof(MomentsIO));
     p.off_ctrl = off;   off = align_up(off + sizeof(Control));
     auto place_list = [&](HostList& l) {
         l.off_levels = off; off = align_up(off + std::max<size_t>(1, l.levels.size()) * sizeof(int32_t));
@@ -552,6 +553,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     p.dS = reinterpret_cast<GridState*>(tab + p.off_state);
     p.dIO = reinterpret_cast<StepIO*>(tab + p.off_stepio);
     p.dEx = reinterpret_cast<ExchangeIO*>(tab + p.off_exio);
+    p.dMo = reinterpret_cast<MomentsIO*>(tab + p.off_moio);
     p.dCtrl = reinterpret_cast<Control*>(tab + p.off_ctrl);
     for (size_t li = 0; li < p.levels.size(); ++li) {
         LevelDesc& d = p.levels[li];
@@ -756,6 +758,57 @@ static int exchange(Plan& p, double* const* E, double* const* eps, const double*
     FLD_HIP(hipGetLastError());
     FLD_HIP(hipEventRecord(p.ex_done[slot], s));
     p.ex_last = slot;
+    return FLD_OK;
+}
+
+static int moments(Plan& p, const double* const* E, const double* const* kr, const double* const* v,
+                   const double* dt, const fld_moments_out* out, hipStream_t s) {
+    const int G = p.ngrids();
+    if (!p.hMo)
+        FLD_HIP(hipHostMalloc((void**)&p.hMo, Plan::kExSlots * G * sizeof(MomentsIO), hipHostMallocDefault));
+    for (auto& e : p.mo_done)
+        if (!e) FLD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    std::vector<MomentsIO> io(G);
+    for (int g = 0; g < G; ++g) {
+        const int nd = p.grids[g].ndim;
+        const fld_moments_out& o = out[g];
+        MomentsIO m{};
+        if (!E[g] || !kr[g]) return FLD_ERR_INVALID_ARG;
+        m.E = E[g];
+        m.kr = kr[g];
+        int nv = 0;
+        for (int a = 0; a < nd; ++a) {
+            m.v[a] = v ? v[3 * g + a] : nullptr;
+            nv += m.v[a] != nullptr;
+        }
+        if (nv != 0 && nv != nd) return FLD_ERR_INVALID_ARG;          // all components or none
+        if ((o.tiring || o.E_out) && nv == 0) return FLD_ERR_INVALID_ARG;
+        if (o.E_out) {
+            if (!dt || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+            if (o.E_out == E[g]) return FLD_ERR_INVALID_ARG;            // neighbours still read E
+            m.dt = dt[g];
+        }
+        for (int a = 0; a < nd; ++a) {
+            m.F[a] = o.F[a];
+            m.fr[a] = o.f_r[a];
+        }
+        m.edd = o.edd;
+        for (int q = 0; q < nd * (nd + 1) / 2; ++q) m.P[q] = o.P[q];
+        m.tiring = o.tiring;
+        m.E_out = o.E_out;
+        io[g] = m;
+    }
+    const int slot = p.mo_slot;
+    p.mo_slot = (p.mo_slot + 1) % Plan::kExSlots;
+    FLD_HIP(hipEventSynchronize(p.mo_done[slot]));     // staging slot free again
+    MomentsIO* h = p.hMo + (size_t)slot * G;
+    std::copy(io.begin(), io.end(), h);
+    MomentsIO* d = p.dMo + (size_t)slot * G;
+    FLD_HIP(hipMemcpyAsync(d, h, G * sizeof(MomentsIO), hipMemcpyHostToDevice, s));
+    for (auto& D : p.dl)
+        if (!D.l0_cell.empty()) launch_moments(D.dim, p.dL, D.l0_cell.dev, d, p.opts.c, p.opts.limiter, p.nblk, s);
+    FLD_HIP(hipGetLastError());
+    FLD_HIP(hipEventRecord(p.mo_done[slot], s));
     return FLD_OK;
 }
 
@@ -1082,6 +1135,21 @@ int32_t fld_exchange_status(fld_plan_t plan, void* stream, int64_t* bisected) {
                            hipMemcpyHostToDevice, s));
     FLD_HIP(hipStreamSynchronize(s));
     return bad ? FLD_ERR_BAD_INPUT : FLD_OK;
+}
+
+int32_t fld_radiation_moments(fld_plan_t plan, const double* const* E, const double* const* kappa_rho,
+                              const double* const* v, const double* dt, const fld_moments_out* out,
+                              void* stream) {
+    if (!plan || !E || !kappa_rho || !out) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        return fld::moments(p, E, kappa_rho, v, dt, out, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
 }
 
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {

@@ -210,3 +210,11 @@ def test_library_binds_to_torchs_hip_runtime(tmp_path):
     for ln in lines:
         target = ln.split(" to ", 1)[1].split(" [")[0]
         assert os.path.realpath(target).startswith(torch_lib), ln
+
+
+def test_moments_need_a_bound_workspace():
+    h = fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default())
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_radiation_moments(h, [1], [1], [{}], stream=0)
+    assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
+    fld.fld_plan_destroy(h)

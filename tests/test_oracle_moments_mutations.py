@@ -5,6 +5,8 @@ import pytest
 
 import oracle
 import oracle.moments as M
+import oracle.fld as FLD
+import tests.test_oracle_limiters as PL
 import tests.test_oracle_moments as P
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -41,6 +43,24 @@ def _tiring_diagonal_only(Pt, v, h):
     return out
 
 
+_orig_limiter = FLD.flux_limiter
+
+
+def _minerbo_branches_swapped(R, kind="lp"):
+    if kind != "minerbo":
+        return _orig_limiter(R, kind)
+    R = np.asarray(R, dtype=np.float64)
+    lo = 2.0 / (3.0 + np.sqrt(9.0 + 12.0 * R * R))
+    hi = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))
+    return np.where(R <= 1.5, hi, lo)
+
+
+def _exact_lp_missing_over_r(R, kind="lp"):
+    if kind != "lp_exact":
+        return _orig_limiter(R, kind)
+    return _orig_limiter(R, kind) * np.where(np.asarray(R) > 0, np.asarray(R), 1.0)
+
+
 _orig_moments = M.radiation_moments
 
 
@@ -72,6 +92,20 @@ CASES = [
     ("radiation_moments", _moments_no_c, P.test_free_streaming_limit),
     ("radiation_moments", _moments_force_no_c, P.test_thick_limit_is_fickian_diffusion),
 ]
+
+
+LIMITER_CASES = [
+    (_minerbo_branches_swapped, lambda: PL.test_limits_and_causality("minerbo")),
+    (_exact_lp_missing_over_r, lambda: PL.test_exact_lp_against_high_precision(2.0)),
+]
+
+
+@pytest.mark.parametrize("fn,pin", LIMITER_CASES, ids=[c[0].__name__ for c in LIMITER_CASES])
+def test_limiter_pin_catches_mutation(monkeypatch, fn, pin):
+    monkeypatch.setattr(FLD, "flux_limiter", fn)
+    monkeypatch.setattr(oracle, "flux_limiter", fn)
+    with pytest.raises(AssertionError):
+        pin()
 
 
 @pytest.mark.parametrize("name,fn,pin", CASES, ids=[f"{c[0]}:{c[1].__name__}" for c in CASES])
