@@ -61,6 +61,11 @@ extern "C" {
 /* ---- options ------------------------------------------------------------ */
 #define FLD_LIMITER_LP          0    /* lambda = (2+R)/(6+3R+R^2)   (Sec. 2.2, eq. fld_lambda) */
 #define FLD_LIMITER_DIFFUSION   1    /* lambda = 1/3, the optically thick limit (Sec. 2.2)   */
+#define FLD_LIMITER_MINERBO     2    /* Minerbo (1978), the alternative Sec. 2.2 names:
+                                        2/(3 + sqrt(9 + 12 R^2)) for R <= 3/2,
+                                        1/(1 + R + sqrt(1 + 2R)) above                       */
+#define FLD_LIMITER_LP_EXACT    3    /* Levermore-Pomraning's own (coth R - 1/R)/R, which
+                                        eq. fld_lambda approximates to ~7 %                  */
 
 #define FLD_BC_ZERO_FLUX        0    /* Neumann, zero gradient (Sec. 3.4)      */
 

@@ -44,6 +44,10 @@ FLD_ERR_UNSUPPORTED = -8
 FLD_ERR_SHUTDOWN = -9
 FLD_LIMITER_LP = 0
 FLD_LIMITER_DIFFUSION = 1
+FLD_LIMITER_MINERBO = 2
+FLD_LIMITER_LP_EXACT = 3
+LIMITER_CODES = {"lp": FLD_LIMITER_LP, "diffusion": FLD_LIMITER_DIFFUSION, "minerbo": FLD_LIMITER_MINERBO,
+                 "lp_exact": FLD_LIMITER_LP_EXACT}
 FLD_BC_ZERO_FLUX = 0
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1

@@ -287,9 +287,23 @@ __device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, in
 }
 
 // Flux limiter lambda(R) (Sec. 2.2): the rational bridging law of eq. fld_lambda,
-// or 1/3.
+// 1/3, Minerbo's two branches (meeting with equal value and slope at R = 3/2), or
+// Levermore and Pomraning's (coth R - 1/R)/R, by its series below R = 0.1 where
+// the difference cancels (the series truncation there is below 1e-16).
 __device__ __forceinline__ double limiter_of(double R, int limiter) {
     if (limiter == FLD_LIMITER_DIFFUSION) return 1.0 / 3.0;
+    if (limiter == FLD_LIMITER_MINERBO) {
+        if (R <= 1.5) return 2.0 / (3.0 + sqrt(9.0 + 12.0 * R * R));
+        return 1.0 / (1.0 + R + sqrt(1.0 + 2.0 * R));
+    }
+    if (limiter == FLD_LIMITER_LP_EXACT) {
+        if (R < 0.1) {
+            const double r2 = R * R;
+            return 1.0 / 3.0 +
+                   r2 * (-1.0 / 45.0 + r2 * (2.0 / 945.0 + r2 * (-1.0 / 4725.0 + r2 * (2.0 / 93555.0))));
+        }
+        return (1.0 / tanh(R) - 1.0 / R) / R;
+    }
     if (R < 1e100) return (2.0 + R) / (6.0 + R * (3.0 + R));
     return 1.0 / R;                         // free-streaming limit, avoids inf/inf
 }

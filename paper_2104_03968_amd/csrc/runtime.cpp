@@ -49,7 +49,7 @@ struct DeviceGuard {
 
 int validate_opts(const fld_opts& o) {
     if (!(o.c > 0.0) || !std::isfinite(o.c)) return FLD_ERR_INVALID_ARG;
-    if (o.limiter != FLD_LIMITER_LP && o.limiter != FLD_LIMITER_DIFFUSION) return FLD_ERR_INVALID_ARG;
+    if (o.limiter < FLD_LIMITER_LP || o.limiter > FLD_LIMITER_LP_EXACT) return FLD_ERR_INVALID_ARG;
     for (int f = 0; f < 6; ++f)
         if (o.bc[f] != FLD_BC_ZERO_FLUX) return FLD_ERR_UNSUPPORTED;
     if (o.precision != FLD_PREC_FP64 && o.precision != FLD_PREC_MIXED) return FLD_ERR_INVALID_ARG;

@@ -14,7 +14,7 @@ def run_step(grids, precision=0, rtol=1e-10, limiter="lp", c=1.0, max_cycles=50,
              in_place=False, **kw):
     """One fld_step over a list of GridInput (same limiter and c); returns (xs, stats, rc)."""
     plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids], precision=precision,
-                    rtol=rtol, limiter=0 if limiter == "lp" else 1, c=c, max_cycles=max_cycles,
+                    rtol=rtol, limiter=fld.LIMITER_CODES[limiter], c=c, max_cycles=max_cycles,
                     use_graph=use_graph, **kw)
     E = [dev(g.E) for g in grids]
     K = [dev(g.kappa_rho) for g in grids]

@@ -53,11 +53,16 @@ def face_tolerance(g, limiter="lp"):
     R = gn / (g.kappa_rho * g.E)
     if limiter == "lp":
         sens = R * np.abs(1 / (2 + R) - (3 + 2 * R) / (6 + 3 * R + R * R))
-    else:
+    elif limiter == "diffusion":
         sens = np.zeros_like(R)
+    else:
+        sens = np.ones_like(R)             # lambda falls no faster than 1/R
+    # the exact form's coth R - 1/R loses up to ~300 ulp to cancellation just above
+    # its series threshold, on both sides independently
+    extra = 1000 * EPS if limiter == "lp_exact" else 0.0
     with np.errstate(invalid="ignore", divide="ignore"):
         rel_R = np.where(gn > 0, 4 * EPS * acc / (gn * gn), 0.0)
-    cell = 8 * EPS + sens * rel_R
+    cell = 8 * EPS + sens * rel_R + extra
     tol = []
     for d in range(nd):
         a = nd - 1 - d
@@ -73,11 +78,14 @@ def face_tolerance(g, limiter="lp"):
 
 # ------------------------------------------------------------------ K1 coefficients
 @pytest.mark.parametrize("shape,limiter", [((64, 64), "lp"), ((37, 100), "lp"), ((64, 64), "diffusion"),
-                                           ((9, 13, 20), "lp"), ((2, 2), "lp"), ((3, 2, 5), "lp")])
+                                           ((9, 13, 20), "lp"), ((2, 2), "lp"), ((3, 2, 5), "lp"),
+                                           ((64, 64), "minerbo"), ((33, 47), "minerbo"), ((9, 13, 20), "minerbo"),
+                                           ((64, 64), "lp_exact"), ((33, 47), "lp_exact"),
+                                           ((9, 13, 20), "lp_exact")])
 def test_face_weights_match_oracle(shape, limiter):
     g = W.pulse_2d() if shape == (64, 64) else W.random_grid(shape, 123000 + sum(shape), dt=3e-3)
     g.limiter = limiter
-    plan = fld.Plan([g.E.shape], h=[g.h], limiter=0 if limiter == "lp" else 1, c=g.c)
+    plan = fld.Plan([g.E.shape], h=[g.h], limiter=fld.LIMITER_CODES[limiter], c=g.c)
     plan.coefficients([dev(g.E)], [dev(g.kappa_rho)], [g.dt])
     torch.cuda.synchronize()
     lv = plan.level_tensors(0, 0)
@@ -138,6 +146,17 @@ def test_ragged_and_odd_grids_match_oracle(shape, dt, precision, krylov, fused):
     (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, fused=fused)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st, info)
+
+
+@pytest.mark.parametrize("limiter", ["minerbo", "lp_exact"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_with_limiter_variants(limiter, precision):
+    for shape in ((48, 40), (12, 16, 20)):
+        g = W.random_grid(shape, 124000 + sum(shape), dt=3e-3)
+        g.limiter = limiter
+        (x,), (st,), rc = run_step([g], precision=precision, limiter=limiter, rtol=_rtol_for(g))
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, limiter)
+        assert rc == 0 and rel_l2(x, x_or) <= 1e-10, (shape, st)
 
 
 def test_diffusion_limiter_matches_dct():
