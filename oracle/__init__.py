@@ -13,3 +13,7 @@ from .moments import *  # noqa: F401,F403,E402
 from . import moments as _moments  # noqa: E402
 
 __all__ = list(__all__) + list(_moments.__all__)
+from .imex import *  # noqa: F401,F403,E402
+from . import imex as _imex  # noqa: E402
+
+__all__ = list(__all__) + list(_imex.__all__)
