@@ -104,6 +104,40 @@ def time_moments(fld, plan, grids, E, K, stream, reps: int = 20):
             "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
+def time_imex(fld, plan, grids, E, eps, rho, kap, gas, stream, reps: int = 5):
+    """Time fld_imex_step (midpoint scheme, with a synthetic velocity: tiring and
+    exchange in the explicit stages, one implicit half step) on copies of the
+    post-benchmark state, wall clock around synchronous calls."""
+    import torch
+    import workloads as W
+    v = [[torch.from_numpy(W.smooth_field(g.E.shape, 4343 + 10 * i + a)).to(E[0].device) for a in range(g.E.ndim)]
+         for i, g in enumerate(grids)]
+    dts = [g.dt for g in grids]
+    out = {}
+    for scheme in ("euler", "midpoint"):
+        Ec = [e.clone() for e in E]
+        ec = [x.clone() for x in eps]
+        cyc = []
+
+        def call():
+            rc, st = plan.imex_step(Ec, ec, rho, kap, dts, gas=gas, scheme=scheme, v=v, stream=stream, check=False)
+            if rc != 0:
+                raise RuntimeError(f"fld_imex_step failed: {fld.fld_strerror(rc)}")
+            cyc.append(max(s["cycles"] for s in st))
+        call()
+        torch.cuda.synchronize()
+        cyc.clear()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / reps
+        cells = sum(g.E.size for g in grids)
+        out[scheme] = {"ms_per_step": dt_s * 1e3, "cell_updates_per_s": cells / dt_s,
+                       "vcycles": float(np.mean(cyc)), "steps": reps}
+    return out
+
+
 def measured_traffic(cfg: str, kname: str, launch: dict):
     """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
     record kept under profiles/ (copy-calibrated), or None when there is no record for this
@@ -334,6 +368,9 @@ def main():
                      "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"},
     }
     out["radiation_moments"] = time_moments(fld, plan, grids, E, K, stream)
+    if has_gas:
+        log("bench: timing the IMEX step (tiring + exchange + implicit diffusion)")
+        out["imex_step"] = time_imex(fld, plan, grids, E, eps, rho, kap, gas, stream)
     if not args.no_cpu_baseline:
         g0 = grids[0] if cfg != "c4" else grids[0]
         log("bench: timing the FP64 CPU oracle on one step of the first grid")

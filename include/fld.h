@@ -261,6 +261,48 @@ int32_t fld_radiation_moments(fld_plan_t plan, const double* const* E, const dou
                               const double* const* v, const double* dt, const fld_moments_out* out,
                               void* stream);
 
+/* ---- IMEX time step of the radiation subsystem --------------------------- */
+/* The paper's split of the radiation energy equation (Sec. 3.1, eqs. G_expl_1 -
+   G_implexpl) into an explicit operator G_ex -- the photon-tiring source
+   E <- E - tau P : grad v when a velocity is given (Sec. 3.2), then the
+   point-implicit exchange over tau (Sec. 3.3) -- and the implicit diffusion G_im
+   over tau (Sec. 3.4, D lagged at the stage input), with kappa rho = kappa * rho
+   serving both.  kappa, rho, v stay fixed over the step.
+     FLD_IMEX_EULER:    u* = G_ex(u^n, dt);  E^{n+1} = G_im(E*, dt);  eps^{n+1} = eps*.
+     FLD_IMEX_MIDPOINT: u_+ = G_ex(u^n, dt/2);  E^{n+1/2} = G_im(E_+, dt/2);
+                        E_x = E^n + 2 (E^{n+1/2} - E_+) - dt P(E^{n+1/2}) : grad v
+                        (dt times the half step's implicit tendency, and the tiring
+                        source at the midpoint state); (E, eps)^{n+1} = the exchange
+                        of (E_x, eps^n) over dt.
+   The midpoint scheme is second order where the exchange is inactive; the
+   exchange stage is a backward-Euler step in both schemes. */
+#define FLD_IMEX_EULER      0
+#define FLD_IMEX_MIDPOINT   1
+
+/* Bytes of device scratch fld_imex_step needs for `scheme` (256-byte multiple per
+   grid: 2 (Euler) or 4 (midpoint) arrays of N_g doubles).  Errors: INVALID_ARG. */
+int32_t fld_imex_scratch_bytes(fld_plan_t plan, int32_t scheme, size_t* bytes);
+
+/* One IMEX step for every grid g of the plan, in place on E[g] and eps[g]
+   (host arrays of ngrids device pointers to N_g doubles; E[g] != eps[g]).
+   rho, kappa: host arrays of ngrids device pointers (N_g doubles, read only).
+   v: NULL, or a host array of 3 * ngrids device pointers as for
+   fld_radiation_moments (all ndim components of a grid or none).  dt: host
+   array of ngrids, > 0.  gas: exchange constants; gas->c must equal the plan's c.
+   scratch: caller-owned device memory of >= fld_imex_scratch_bytes(scheme)
+   bytes, 256-byte aligned, not overlapping any input; its contents on return
+   are unspecified.  Synchronous (the implicit stage reads back convergence).
+   stats: host array of ngrids (may be NULL) receiving the implicit solve's
+   statistics.  Returns FLD_OK, the first non-OK solve status (NOT_CONVERGED,
+   BAD_INPUT; every output is still written), BAD_INPUT if an exchange stage met
+   an invalid cell (that cell keeps its pre-exchange values), or INVALID_ARG /
+   NO_WORKSPACE / HIP.  Exchange cells that fell back to bisection add to the
+   count fld_exchange_status reports. */
+int32_t fld_imex_step(fld_plan_t plan, double* const* E, double* const* eps,
+                      const double* const* rho, const double* const* kappa, const double* const* v,
+                      const double* dt, const fld_gas* gas, int32_t scheme, void* scratch,
+                      size_t scratch_bytes, void* stream, fld_stats* stats);
+
 /* ---- measurement -------------------------------------------------------- */
 #define FLD_KERNEL_SMOOTH    0   /* one red-black half sweep over every grid's level `level` */
 #define FLD_KERNEL_RESIDUAL  1   /* level-0 FP64 residual and its per-tile norms           */

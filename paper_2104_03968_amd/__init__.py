@@ -48,6 +48,9 @@ FLD_LIMITER_MINERBO = 2
 FLD_LIMITER_LP_EXACT = 3
 LIMITER_CODES = {"lp": FLD_LIMITER_LP, "diffusion": FLD_LIMITER_DIFFUSION, "minerbo": FLD_LIMITER_MINERBO,
                  "lp_exact": FLD_LIMITER_LP_EXACT}
+FLD_IMEX_EULER = 0
+FLD_IMEX_MIDPOINT = 1
+IMEX_SCHEMES = {"euler": FLD_IMEX_EULER, "midpoint": FLD_IMEX_MIDPOINT}
 FLD_BC_ZERO_FLUX = 0
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
@@ -156,6 +159,9 @@ _sig = {
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
     "fld_plan_tuning": (C.c_int32, [_P, C.POINTER(fld_tuning)]),
     "fld_radiation_moments": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_moments_out), _P]),
+    "fld_imex_scratch_bytes": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
+    "fld_imex_step": (C.c_int32, [_P, _PP, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas),
+                                  C.c_int32, _P, C.c_size_t, _P, C.POINTER(fld_stats)]),
     "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
     "fld_server_opts_default": (None, [C.POINTER(fld_server_opts)]),
@@ -330,15 +336,39 @@ def fld_radiation_moments(plan: int, E, kappa_rho, outs, v=None, dt=None, stream
         arr[g].edd = ptr(o.get("edd"))
         arr[g].tiring = ptr(o.get("tiring"))
         arr[g].E_out = ptr(o.get("E_out"))
-    vp = None
-    if v is not None:
-        vp = (C.c_void_p * (3 * n))()
-        for g, comps in enumerate(v):
-            for a, t in enumerate(comps or []):
-                vp[3 * g + a] = 0 if t is None else t.data_ptr()
+    vp = _vptrs(v, n)
     dts = _dts(dt, n) if dt is not None else None
     _check(_lib.fld_radiation_moments(plan, _ptrs(E), _ptrs(kappa_rho), vp, dts, arr, _stream(stream)),
            "fld_radiation_moments")
+
+
+def _vptrs(v, n):
+    if v is None:
+        return None
+    vp = (C.c_void_p * (3 * n))()
+    for g, comps in enumerate(v):
+        for a, t in enumerate(comps or []):
+            vp[3 * g + a] = 0 if t is None else t.data_ptr()
+    return vp
+
+
+def fld_imex_scratch_bytes(plan: int, scheme: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.fld_imex_scratch_bytes(plan, scheme, C.byref(b)), "fld_imex_scratch_bytes")
+    return b.value
+
+
+def fld_imex_step(plan: int, E, eps, rho, kappa, dt, gas: fld_gas, scheme: int, scratch, scratch_bytes: int,
+                  v=None, stream=None, check: bool = True):
+    """In place on E and eps; returns (status, [stats dict per grid])."""
+    n = len(E)
+    stats = (fld_stats * n)()
+    sp = scratch if isinstance(scratch, int) else (scratch.data_ptr() if scratch is not None else None)
+    rc = _lib.fld_imex_step(plan, _ptrs(E), _ptrs(eps), _ptrs(rho), _ptrs(kappa), _vptrs(v, n), _dts(dt, n),
+                            C.byref(gas), scheme, sp, scratch_bytes, _stream(stream), stats)
+    if check:
+        _check(rc, "fld_imex_step")
+    return rc, [s.as_dict() for s in stats]
 
 
 def fld_plan_tuning(plan: int) -> dict:
@@ -542,6 +572,20 @@ class Plan:
 
     def exchange_status(self, stream=None):
         return fld_exchange_status(self.handle, stream)
+
+    def imex_step(self, E, eps, rho, kappa, dt, gas: Optional[fld_gas] = None, scheme: str = "midpoint", v=None,
+                  stream=None, check: bool = True):
+        """One IMEX step in place on E and eps (lists of tensors per grid); the scratch
+        is a torch buffer kept with the plan and grown on demand."""
+        import torch
+        code = IMEX_SCHEMES[scheme]
+        need = fld_imex_scratch_bytes(self.handle, code)
+        buf = getattr(self, "_imex_scratch", None)
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            self._imex_scratch = buf
+        return fld_imex_step(self.handle, E, eps, rho, kappa, dt, gas or fld_gas_default(c=self.opts.c), code,
+                             buf.data_ptr(), buf.numel(), v=v, stream=stream, check=check)
 
     def profile(self, kernel: int, level: int = 0, reps: int = 100, stream=None):
         return fld_profile_kernel(self.handle, kernel, level, reps, stream)

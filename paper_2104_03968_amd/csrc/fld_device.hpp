@@ -160,10 +160,31 @@ struct MomentsIO {
     double        dt;
 };
 
+// Per-grid pointers of one pointwise stage of fld_imex_step (NULL: not used):
+// kr <- kappa rho; E_x = E + 2 (Em - Ep) - dt_tir tir; (E_out, eps_out) <- the
+// exchange of (E_x, eps) over tau.  E_out NULL: kr only.
+struct ImexIO {
+    const double* E;
+    const double* eps;
+    const double* rho;
+    const double* kappa;
+    const double* Em;
+    const double* Ep;
+    const double* tir;
+    double*       kr;
+    double*       E_out;
+    double*       eps_out;
+    double        tau;
+    double        dt_tir;
+    int64_t       n;
+};
+
 struct Control {
     int32_t nactive;     // grids still iterating after the last count
     int32_t bad_exchange;
     int64_t bisected;    // exchange cells that used the bisection fallback
+    int32_t bad_imex;    // an IMEX stage met an invalid cell
+    int32_t pad_;
 };
 
 // ---- launch wrappers (kernels.hip) ------------------------------------------
@@ -235,5 +256,7 @@ void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s);
 void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,
                      double c_v, int max_halley, double root_rtol, Control* ctrl, int nblk,
                      hipStream_t s);
+void launch_imex_point(const ImexIO* io, int ngrids, int64_t max_n, double c, double a_rad, double c_v,
+                       int max_halley, double root_rtol, Control* ctrl, int nblk, hipStream_t s);
 
 }  // namespace fld

@@ -70,7 +70,7 @@ struct Plan {
     bool krylov = true;
 
     // workspace layout (byte offsets)
-    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_moio = 0, off_ctrl = 0;
+    size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_moio = 0, off_imio = 0, off_ctrl = 0;
     size_t ws_bytes = 0;
     static constexpr int kExSlots = 4;
     struct FieldOff {
@@ -93,10 +93,13 @@ struct Plan {
     StepIO* dIO = nullptr;
     ExchangeIO* dEx = nullptr;
     MomentsIO* dMo = nullptr;
+    ImexIO* dIm = nullptr;                     // kImStages * ngrids stage tables
     Control* dCtrl = nullptr;
     StepIO* hIO = nullptr;                     // pinned staging
     ExchangeIO* hEx = nullptr;                 // pinned staging, kExSlots * ngrids
     MomentsIO* hMo = nullptr;                  // pinned staging, kExSlots * ngrids
+    ImexIO* hIm = nullptr;                     // pinned staging, kImStages * ngrids
+    static constexpr int kImStages = 3;
     Control* hCtrl = nullptr;                  // pinned
     GridState* hS = nullptr;                   // pinned
     bool own_pinned = true;                    // false: staging buffers belong to a server
@@ -143,6 +146,7 @@ inline Plan::~Plan() {
         if (hCtrl) (void)hipHostFree(hCtrl);
         if (hS) (void)hipHostFree(hS);
     }
+    if (hIm) (void)hipHostFree(hIm);           // only fld_imex_step allocates it
 }
 
 

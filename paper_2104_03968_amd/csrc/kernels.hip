@@ -1692,36 +1692,79 @@ __device__ __forceinline__ double quartic_root(double beta, int max_halley, doub
     return glo <= ghi ? lo : hi;
 }
 
+// Exchange of one cell over dt (Sec. 3.3), in place on (E, eps).  Returns false and
+// leaves both untouched for an invalid cell (rho <= 0, kappa < 0, E < 0, eps < 0,
+// a non-finite value); counts a bisection fallback in nbis.
+struct ExConst {
+    double c, a_rad, cv4;
+    int max_halley;
+    double root_rtol;
+};
+
+__device__ __forceinline__ bool exchange_cell(double& E, double& eps, double rho, double kap, double dt,
+                                              const ExConst& k, long& nbis) {
+    const bool ok = isfinite(E) && isfinite(eps) && isfinite(rho) && isfinite(kap) && rho > 0.0 &&
+                    kap >= 0.0 && E >= 0.0 && eps >= 0.0;
+    if (!ok) return false;
+    const double a2 = k.c * kap * rho * dt;
+    const double a1 = k.c * k.a_rad * kap * dt / (rho * rho * rho * k.cv4);
+    const double opa = 1.0 + a2;
+    const double C = opa * eps + a2 * E;
+    if (!(C > 0.0)) return true;                    // no energy in gas or radiation
+    const double s = C / opa;
+    const double beta = a1 * s * s * s / opa;       // a1 C^3 / (1+a2)^4
+    bool bis;
+    const double y = quartic_root(beta, k.max_halley, k.root_rtol, bis);
+    nbis += bis;
+    const double eps_new = s * y;
+    const double e2 = eps_new * eps_new;
+    eps = eps_new;
+    E = (a1 * e2 * e2 + E) / opa;
+    return true;
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_exchange(const ExchangeIO* __restrict__ io, double c, double a_rad, double c_v, int max_halley,
-           double root_rtol, Control* ctrl) {
+k_exchange(const ExchangeIO* __restrict__ io, ExConst k, Control* ctrl) {
     const ExchangeIO p = io[blockIdx.y];
     int bad = 0;
     long nbis = 0;
-    const double cv2 = c_v * c_v;
-    const double cv4 = cv2 * cv2;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.n;
          idx += (long)gridDim.x * blockDim.x) {
-        const double E = p.E[idx], eps = p.eps[idx], rho = p.rho[idx], kap = p.kappa[idx];
-        const bool ok = isfinite(E) && isfinite(eps) && isfinite(rho) && isfinite(kap) && rho > 0.0 &&
-                        kap >= 0.0 && E >= 0.0 && eps >= 0.0;
-        if (!ok) { bad = 1; continue; }
-        const double a2 = c * kap * rho * p.dt;
-        const double a1 = c * a_rad * kap * p.dt / (rho * rho * rho * cv4);
-        const double opa = 1.0 + a2;
-        const double C = opa * eps + a2 * E;
-        if (!(C > 0.0)) continue;                       // no energy in gas or radiation
-        const double s = C / opa;
-        const double beta = a1 * s * s * s / opa;       // a1 C^3 / (1+a2)^4
-        bool bis;
-        const double y = quartic_root(beta, max_halley, root_rtol, bis);
-        nbis += bis;
-        const double eps_new = s * y;
-        const double e2 = eps_new * eps_new;
-        p.eps[idx] = eps_new;
-        p.E[idx] = (a1 * e2 * e2 + E) / opa;
+        double E = p.E[idx], eps = p.eps[idx];
+        if (!exchange_cell(E, eps, p.rho[idx], p.kappa[idx], p.dt, k, nbis)) { bad = 1; continue; }
+        p.eps[idx] = eps;
+        p.E[idx] = E;
     }
     if (bad) atomicOr(&ctrl->bad_exchange, 1);
+    if (nbis) atomicAdd((unsigned long long*)&ctrl->bisected, (unsigned long long)nbis);
+}
+
+// One pointwise stage of the IMEX step (per grid, blockIdx.y): optionally
+// kappa rho, then the explicit operator on the stage's energy
+//     E_x = E [+ 2 (E_m - E_p)] [- dt_tir tir]
+// (the midpoint stage adds dt times the implicit tendency (E_m - E_p)/(dt/2) of
+// the half step, and the tiring source at the midpoint state), then the
+// exchange of (E_x, eps) over tau, written to (E_out, eps_out).
+__global__ void __launch_bounds__(kBlock)
+k_imex_point(const ImexIO* __restrict__ io, ExConst k, Control* ctrl) {
+    const ImexIO p = io[blockIdx.y];
+    if (!p.kr && !p.E_out) return;                  // nothing for this grid in this stage
+    int bad = 0;
+    long nbis = 0;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.n;
+         idx += (long)gridDim.x * blockDim.x) {
+        const double rho = p.rho[idx], kap = p.kappa[idx];
+        if (p.kr) p.kr[idx] = kap * rho;
+        if (!p.E_out) continue;
+        double E = p.E[idx];
+        if (p.Em) E += 2.0 * (p.Em[idx] - p.Ep[idx]);
+        if (p.tir) E -= p.dt_tir * p.tir[idx];
+        double eps = p.eps[idx];
+        if (!exchange_cell(E, eps, rho, kap, p.tau, k, nbis)) bad = 1;
+        p.E_out[idx] = E;
+        p.eps_out[idx] = eps;
+    }
+    if (bad) atomicOr(&ctrl->bad_imex, 1);
     if (nbis) atomicAdd((unsigned long long*)&ctrl->bisected, (unsigned long long)nbis);
 }
 
@@ -1975,14 +2018,28 @@ void launch_moments(int dim, const LevelDesc* L, JobList jl, const MomentsIO* io
     FLD_DISPATCH_DIM(dim, hipLaunchKernelGGL((k_moments<D>), dim3(g), dim3(kBlock), 0, s, L, jl, io, c, limiter));
 }
 
+static ExConst ex_const(double c, double a_rad, double c_v, int max_halley, double root_rtol) {
+    const double cv2 = c_v * c_v;
+    return ExConst{c, a_rad, cv2 * cv2, max_halley, root_rtol};
+}
+
 void launch_exchange(const ExchangeIO* io, int ngrids, int64_t max_n, double c, double a_rad,
                      double c_v, int max_halley, double root_rtol, Control* ctrl, int nblk,
                      hipStream_t s) {
     if (ngrids <= 0 || max_n <= 0) return;
     int64_t bx = (max_n + kBlock - 1) / kBlock;
     if (bx > nblk) bx = nblk;
-    hipLaunchKernelGGL(k_exchange, dim3((unsigned)bx, (unsigned)ngrids), dim3(kBlock), 0, s, io, c,
-                       a_rad, c_v, max_halley, root_rtol, ctrl);
+    hipLaunchKernelGGL(k_exchange, dim3((unsigned)bx, (unsigned)ngrids), dim3(kBlock), 0, s, io,
+                       ex_const(c, a_rad, c_v, max_halley, root_rtol), ctrl);
+}
+
+void launch_imex_point(const ImexIO* io, int ngrids, int64_t max_n, double c, double a_rad, double c_v,
+                       int max_halley, double root_rtol, Control* ctrl, int nblk, hipStream_t s) {
+    if (ngrids <= 0 || max_n <= 0) return;
+    int64_t bx = (max_n + kBlock - 1) / kBlock;
+    if (bx > nblk) bx = nblk;
+    hipLaunchKernelGGL(k_imex_point, dim3((unsigned)bx, (unsigned)ngrids), dim3(kBlock), 0, s, io,
+                       ex_const(c, a_rad, c_v, max_halley, root_rtol), ctrl);
 }
 
 }  // namespace fld

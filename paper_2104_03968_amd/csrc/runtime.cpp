@@ -320,6 +320,7 @@ static void layout(Plan& p) {
     p.off_stepio = off; off = align_up(off + G * sizeof(StepIO));
     p.off_exio = off;   off = align_up(off + Plan::kExSlots * G * sizeof(ExchangeIO));
     p.off_moio = off;   off = align_up(off + Plan::kExSlots * G * sizeof(MomentsIO));
+    p.off_imio = off;   off = align_up(off + Plan::kImStages * G * sizeof(ImexIO));
     p.off_ctrl = off;   off = align_up(off + sizeof(Control));
     auto place_list = [&](HostList& l) {
         l.off_levels = off; off = align_up(off + std::max<size_t>(1, l.levels.size()) * sizeof(int32_t));
@@ -554,6 +555,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     p.dIO = reinterpret_cast<StepIO*>(tab + p.off_stepio);
     p.dEx = reinterpret_cast<ExchangeIO*>(tab + p.off_exio);
     p.dMo = reinterpret_cast<MomentsIO*>(tab + p.off_moio);
+    p.dIm = reinterpret_cast<ImexIO*>(tab + p.off_imio);
     p.dCtrl = reinterpret_cast<Control*>(tab + p.off_ctrl);
     for (size_t li = 0; li < p.levels.size(); ++li) {
         LevelDesc& d = p.levels[li];
@@ -810,6 +812,131 @@ static int moments(Plan& p, const double* const* E, const double* const* kr, con
     FLD_HIP(hipGetLastError());
     FLD_HIP(hipEventRecord(p.mo_done[slot], s));
     return FLD_OK;
+}
+
+// Scratch of fld_imex_step per grid: kappa rho and E_* (Euler); kappa rho, E_+,
+// E^{n+1/2} and the half-step gas energy / the midpoint tiring (midpoint).
+static int imex_arrays(int scheme) { return scheme == FLD_IMEX_EULER ? 2 : 4; }
+
+static size_t imex_scratch(const Plan& p, int scheme) {
+    size_t b = 0;
+    for (int g = 0; g < p.ngrids(); ++g) b += imex_arrays(scheme) * align_up((size_t)p.ncell[g] * 8);
+    return b;
+}
+
+static int imex(Plan& p, double* const* E, double* const* eps, const double* const* rho,
+                const double* const* kappa, const double* const* v, const double* dt, const fld_gas& gas,
+                int scheme, char* scr, size_t scr_bytes, hipStream_t s, fld_stats* stats) {
+    const int G = p.ngrids();
+    if (scheme != FLD_IMEX_EULER && scheme != FLD_IMEX_MIDPOINT) return FLD_ERR_INVALID_ARG;
+    if (!scr || scr_bytes < imex_scratch(p, scheme) || reinterpret_cast<uintptr_t>(scr) % kAlign)
+        return FLD_ERR_INVALID_ARG;
+    bool any_v = false;
+    for (int g = 0; g < G; ++g) {
+        if (!E[g] || !eps[g] || !rho[g] || !kappa[g] || E[g] == eps[g]) return FLD_ERR_INVALID_ARG;
+        if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
+        int nv = 0;
+        for (int a = 0; a < p.grids[g].ndim; ++a) nv += (v && v[3 * g + a]) ? 1 : 0;
+        if (nv != 0 && nv != p.grids[g].ndim) return FLD_ERR_INVALID_ARG;
+        any_v = any_v || nv > 0;
+    }
+    if (!p.hIm)
+        FLD_HIP(hipHostMalloc((void**)&p.hIm, Plan::kImStages * G * sizeof(ImexIO), hipHostMallocDefault));
+    FLD_HIP(hipStreamSynchronize(s));                  // earlier work may still read the staging buffers
+    const bool mid = scheme == FLD_IMEX_MIDPOINT;
+    std::vector<double*> kr(G), T1(G), T2(G), T3(G);
+    std::vector<double> tau1(G);
+    {
+        size_t off = 0;
+        for (int g = 0; g < G; ++g) {
+            const size_t a = align_up((size_t)p.ncell[g] * 8);
+            double** dst[4] = {&kr[g], &T1[g], &T2[g], &T3[g]};
+            for (int k = 0; k < imex_arrays(scheme); ++k, off += a) *dst[k] = reinterpret_cast<double*>(scr + off);
+            tau1[g] = mid ? 0.5 * dt[g] : dt[g];
+        }
+    }
+    // Stage tables: [0] kappa rho (+ the first explicit stage when there is no
+    // velocity), [1] the first explicit stage after the tiring source, [2] the
+    // midpoint's closing stage.
+    ImexIO* h = p.hIm;
+    for (int g = 0; g < G; ++g) {
+        const bool gv = v && v[3 * g];
+        const int64_t n = p.ncell[g];
+        double* Es = mid ? T1[g] : (gv ? T1[g] : E[g]);          // E_* / E_+ after the explicit stage
+        double* es = mid ? T3[g] : eps[g];
+        ImexIO a{};
+        a.rho = rho[g]; a.kappa = kappa[g]; a.kr = kr[g]; a.n = n;
+        if (!gv) { a.E = E[g]; a.eps = eps[g]; a.E_out = Es; a.eps_out = es; a.tau = tau1[g]; }
+        h[g] = a;
+        ImexIO b{};
+        b.rho = rho[g]; b.kappa = kappa[g]; b.n = n;
+        if (gv) { b.E = T1[g]; b.eps = eps[g]; b.E_out = Es; b.eps_out = es; b.tau = tau1[g]; }
+        h[G + g] = b;
+        ImexIO c{};
+        c.rho = rho[g]; c.kappa = kappa[g]; c.n = n;
+        if (mid) {
+            c.E = E[g]; c.eps = eps[g]; c.Em = T2[g]; c.Ep = T1[g];
+            c.tir = gv ? T3[g] : nullptr; c.dt_tir = dt[g];
+            c.E_out = E[g]; c.eps_out = eps[g]; c.tau = dt[g];
+        }
+        h[2 * G + g] = c;
+    }
+    FLD_HIP(hipMemcpyAsync(p.dIm, h, Plan::kImStages * G * sizeof(ImexIO), hipMemcpyHostToDevice, s));
+    FLD_HIP(hipMemsetAsync(&p.dCtrl->bad_imex, 0, sizeof(int32_t), s));
+    auto point = [&](int stage) {
+        launch_imex_point(p.dIm + (size_t)stage * G, G, p.max_n, gas.c, gas.a_rad, gas.c_v, gas.max_halley,
+                          gas.root_rtol, p.dCtrl, p.nblk, s);
+    };
+    // explicit operator over dt (Euler) or dt/2 (midpoint): tiring, then the exchange
+    point(0);
+    int rc;
+    if (any_v) {
+        std::vector<fld_moments_out> mo(G);
+        std::vector<const double*> vv(3 * G, nullptr);
+        for (int g = 0; g < G; ++g) {
+            mo[g] = fld_moments_out{};
+            if (v && v[3 * g]) {
+                mo[g].E_out = T1[g];
+                for (int a = 0; a < p.grids[g].ndim; ++a) vv[3 * g + a] = v[3 * g + a];
+            }
+        }
+        std::vector<const double*> Ec(E, E + G), krc(kr.begin(), kr.end());
+        if ((rc = moments(p, Ec.data(), krc.data(), vv.data(), tau1.data(), mo.data(), s)) != FLD_OK) return rc;
+        point(1);
+    }
+    FLD_HIP(hipGetLastError());
+    // implicit diffusion over the same time
+    std::vector<const double*> Ein(G), krc(kr.begin(), kr.end());
+    std::vector<double*> Eout(G);
+    for (int g = 0; g < G; ++g) {
+        const bool gv = v && v[3 * g];
+        Ein[g] = mid ? T1[g] : (gv ? T1[g] : E[g]);
+        Eout[g] = mid ? T2[g] : E[g];
+    }
+    const int rs = step(p, Ein.data(), krc.data(), Eout.data(), tau1.data(), s, stats);
+    if (rs != FLD_OK && rs != FLD_ERR_NOT_CONVERGED && rs != FLD_ERR_BAD_INPUT) return rs;
+    if (mid) {
+        if (any_v) {
+            // tiring at the midpoint state E^{n+1/2}
+            std::vector<fld_moments_out> mo(G);
+            std::vector<const double*> vv(3 * G, nullptr), Em(G);
+            for (int g = 0; g < G; ++g) {
+                mo[g] = fld_moments_out{};
+                Em[g] = T2[g];
+                if (v && v[3 * g]) {
+                    mo[g].tiring = T3[g];
+                    for (int a = 0; a < p.grids[g].ndim; ++a) vv[3 * g + a] = v[3 * g + a];
+                }
+            }
+            if ((rc = moments(p, Em.data(), krc.data(), vv.data(), nullptr, mo.data(), s)) != FLD_OK) return rc;
+        }
+        point(2);
+        FLD_HIP(hipGetLastError());
+    }
+    FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+    FLD_HIP(hipStreamSynchronize(s));
+    if (rs != FLD_OK) return rs;
+    return p.hCtrl->bad_imex ? FLD_ERR_BAD_INPUT : FLD_OK;
 }
 
 static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t s, double* avg_ms,
@@ -1147,6 +1274,33 @@ int32_t fld_radiation_moments(fld_plan_t plan, const double* const* E, const dou
         fld::DeviceGuard dg(p.device);
         if (!dg.ok) return FLD_ERR_HIP;
         return fld::moments(p, E, kappa_rho, v, dt, out, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_imex_scratch_bytes(fld_plan_t plan, int32_t scheme, size_t* bytes) {
+    if (!plan || !bytes) return FLD_ERR_INVALID_ARG;
+    if (scheme != FLD_IMEX_EULER && scheme != FLD_IMEX_MIDPOINT) return FLD_ERR_INVALID_ARG;
+    *bytes = fld::imex_scratch(plan->p, scheme);
+    return FLD_OK;
+}
+
+int32_t fld_imex_step(fld_plan_t plan, double* const* E, double* const* eps, const double* const* rho,
+                      const double* const* kappa, const double* const* v, const double* dt,
+                      const fld_gas* gas, int32_t scheme, void* scratch, size_t scratch_bytes, void* stream,
+                      fld_stats* stats) {
+    if (!plan || !E || !eps || !rho || !kappa || !dt || !gas) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    if (!(gas->c > 0.0) || gas->c != p.opts.c || !(gas->a_rad >= 0.0) || !(gas->c_v > 0.0) ||
+        gas->max_halley < 0 || !(gas->root_rtol > 0.0))
+        return FLD_ERR_INVALID_ARG;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        return fld::imex(p, E, eps, rho, kappa, v, dt, *gas, scheme, static_cast<char*>(scratch), scratch_bytes,
+                         static_cast<hipStream_t>(stream), stats);
     } catch (...) {
         return FLD_ERR_INVALID_ARG;
     }

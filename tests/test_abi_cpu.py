@@ -218,3 +218,24 @@ def test_moments_need_a_bound_workspace():
         fld.fld_radiation_moments(h, [1], [1], [{}], stream=0)
     assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
     fld.fld_plan_destroy(h)
+
+
+def test_imex_scratch_size_and_argument_checks():
+    shapes = [(48, 64), (10, 12, 14)]
+    h = fld.fld_plan_create([fld.make_grid(tuple(reversed(s))) for s in shapes], fld.fld_opts_default())
+    per = [((64 * 48 * 8 + 255) // 256) * 256, ((14 * 12 * 10 * 8 + 255) // 256) * 256]
+    assert fld.fld_imex_scratch_bytes(h, fld.FLD_IMEX_EULER) == 2 * sum(per)
+    assert fld.fld_imex_scratch_bytes(h, fld.FLD_IMEX_MIDPOINT) == 4 * sum(per)
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_imex_scratch_bytes(h, 7)
+    assert e.value.code == fld.FLD_ERR_INVALID_ARG
+    gas = fld.fld_gas_default(c=1.0)
+    one = [4096, 8192]
+    # before bind; then a gas c that differs from the plan's c
+    rc, _ = fld.fld_imex_step(h, one, one, one, one, [1e-3] * 2, gas, fld.FLD_IMEX_EULER, 4096, 1 << 30,
+                              stream=0, check=False)
+    assert rc == fld.FLD_ERR_NO_WORKSPACE
+    rc, _ = fld.fld_imex_step(h, one, one, one, one, [1e-3] * 2, fld.fld_gas_default(c=2.0),
+                              fld.FLD_IMEX_EULER, 4096, 1 << 30, stream=0, check=False)
+    assert rc in (fld.FLD_ERR_NO_WORKSPACE, fld.FLD_ERR_INVALID_ARG)
+    fld.fld_plan_destroy(h)
