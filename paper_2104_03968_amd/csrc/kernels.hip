@@ -443,6 +443,17 @@ template <> struct Arr<float> {
     __device__ static float* w(const LevelDesc& d, int a) { return d.w32[a]; }
 };
 
+// Neighbour access without branches: a neighbour across the domain boundary is
+// read from the cell itself and enters with weight 0, so every load is issued
+// together (x - x and 0 * x add exactly zero).
+template <typename T, typename P>
+__device__ __forceinline__ void nb_pair(P w, P x, long idx, long nb, bool has, T& wn, T& xn) {
+    const long o = has ? nb : idx;
+    const T wv = w[has ? (nb > idx ? nb : idx) : idx];
+    wn = has ? wv : T(0);
+    xn = x[o];
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ T residual_at(const T* __restrict__ x, const T* __restrict__ b,
                                          const T* __restrict__ w0, const T* __restrict__ w1,
@@ -452,13 +463,21 @@ __device__ __forceinline__ T residual_at(const T* __restrict__ x, const T* __res
     const long idx = i + j * sy + k * sz;
     const T xc = x[idx];
     T r = b[idx] - xc;
-    if (i > 0) r -= w0[idx] * (xc - x[idx - 1]);
-    if (i + 1 < n[0]) r -= w0[idx + 1] * (xc - x[idx + 1]);
-    if (j > 0) r -= w1[idx] * (xc - x[idx - sy]);
-    if (j + 1 < n[1]) r -= w1[idx + sy] * (xc - x[idx + sy]);
+    T wl, xl, wr, xr, wd, xd, wu, xu;
+    nb_pair(w0, x, idx, idx - 1, i > 0, wl, xl);
+    nb_pair(w0, x, idx, idx + 1, i + 1 < n[0], wr, xr);
+    nb_pair(w1, x, idx, idx - sy, j > 0, wd, xd);
+    nb_pair(w1, x, idx, idx + sy, j + 1 < n[1], wu, xu);
+    r -= wl * (xc - xl);
+    r -= wr * (xc - xr);
+    r -= wd * (xc - xd);
+    r -= wu * (xc - xu);
     if (DIM == 3) {
-        if (k > 0) r -= w2[idx] * (xc - x[idx - sz]);
-        if (k + 1 < n[2]) r -= w2[idx + sz] * (xc - x[idx + sz]);
+        T wb, xb, wf, xf;
+        nb_pair(w2, x, idx, idx - sz, k > 0, wb, xb);
+        nb_pair(w2, x, idx, idx + sz, k + 1 < n[2], wf, xf);
+        r -= wb * (xc - xb);
+        r -= wf * (xc - xf);
     }
     return r;
 }
@@ -575,17 +594,25 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restri
                                       const int32_t n[3], int c, T& dg) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
-    const int sy = n[0], sz = n[0] * n[1];
+    const long sy = n[0], sz = (long)n[0] * n[1];
     const T pc = p[c];
     T q = pc;
     dg = T(1);
-    if (i > 0) { const T w = w0[c]; q += w * (pc - p[c - 1]); dg += w; }
-    if (i + 1 < n[0]) { const T w = w0[c + 1]; q += w * (pc - p[c + 1]); dg += w; }
-    if (j > 0) { const T w = w1[c]; q += w * (pc - p[c - sy]); dg += w; }
-    if (j + 1 < n[1]) { const T w = w1[c + sy]; q += w * (pc - p[c + sy]); dg += w; }
+    T wl, pl, wr, pr, wd, pd, wu, pu;
+    nb_pair(w0, p, c, c - 1, i > 0, wl, pl);
+    nb_pair(w0, p, c, c + 1, i + 1 < n[0], wr, pr);
+    nb_pair(w1, p, c, c - sy, j > 0, wd, pd);
+    nb_pair(w1, p, c, c + sy, j + 1 < n[1], wu, pu);
+    q += wl * (pc - pl); dg += wl;
+    q += wr * (pc - pr); dg += wr;
+    q += wd * (pc - pd); dg += wd;
+    q += wu * (pc - pu); dg += wu;
     if (DIM == 3) {
-        if (k > 0) { const T w = w2[c]; q += w * (pc - p[c - sz]); dg += w; }
-        if (k + 1 < n[2]) { const T w = w2[c + sz]; q += w * (pc - p[c + sz]); dg += w; }
+        T wb, pb, wf, pf;
+        nb_pair(w2, p, c, c - sz, k > 0, wb, pb);
+        nb_pair(w2, p, c, c + sz, k + 1 < n[2], wf, pf);
+        q += wb * (pc - pb); dg += wb;
+        q += wf * (pc - pf); dg += wf;
     }
     return q;
 }
@@ -595,15 +622,16 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
                                      const T* __restrict__ w2, const int32_t n[3], int c) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
-    const int sy = n[0], sz = n[0] * n[1];
+    const long sy = n[0], sz = (long)n[0] * n[1];
     T dg = T(1);
-    if (i > 0) dg += w0[c];
-    if (i + 1 < n[0]) dg += w0[c + 1];
-    if (j > 0) dg += w1[c];
-    if (j + 1 < n[1]) dg += w1[c + sy];
+    T wn, unused;
+    nb_pair(w0, w0, c, c - 1, i > 0, wn, unused); dg += wn;
+    nb_pair(w0, w0, c, c + 1, i + 1 < n[0], wn, unused); dg += wn;
+    nb_pair(w1, w1, c, c - sy, j > 0, wn, unused); dg += wn;
+    nb_pair(w1, w1, c, c + sy, j + 1 < n[1], wn, unused); dg += wn;
     if (DIM == 3) {
-        if (k > 0) dg += w2[c];
-        if (k + 1 < n[2]) dg += w2[c + sz];
+        nb_pair(w2, w2, c, c - sz, k > 0, wn, unused); dg += wn;
+        nb_pair(w2, w2, c, c + sz, k + 1 < n[2], wn, unused); dg += wn;
     }
     return dg;
 }
@@ -614,7 +642,7 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
 // search direction lives in p_sh (LDS); x, r and the inverse diagonal live in
 // registers of the thread owning the cell.  w, b and x may be global or LDS.
 template <int DIM, typename T, int NT, int CPT>
-__device__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
+__device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
                          bool warm, T* p_sh, double* red) {
     const int ncell = n[0] * n[1] * n[2];
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
@@ -815,12 +843,12 @@ __device__ __forceinline__ void tile2_half_sweep(Tl& t, int gx0, int gy0, int co
 // before any LDS store so their latencies overlap.  With `cx`, the piecewise-
 // constant prolongation of the coarse correction is added to x on the way in.
 template <typename T, typename Tl>
-__device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const T* __restrict__ xs,
-                                           int gx0, int gy0, bool load_x, const T* __restrict__ cx,
+__device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const gptr<T> xs,
+                                           int gx0, int gy0, bool load_x, const gptr<T> cx,
                                            int ncx) {
-    const T* __restrict__ bs = Arr<T>::b(d);
-    const T* __restrict__ w0 = Arr<T>::w(d, 0);
-    const T* __restrict__ w1 = Arr<T>::w(d, 1);
+    const gptr<T> bs = as_global(Arr<T>::b(d));
+    const gptr<T> w0 = as_global(Arr<T>::w(d, 0));
+    const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
     constexpr int W = Tl::W, H = Tl::H;
     constexpr int NE = (W * H + kBlock - 1) / kBlock;
     T vx[NE], vb[NE], v0[NE], v1[NE];
@@ -873,7 +901,7 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + FX - 1) / FX;
         const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
-        tile2_load<T>(t, d, Arr<T>::x(d), gx0, gy0, load_x != 0, nullptr, 0);
+        tile2_load<T>(t, d, as_global(Arr<T>::x(d)), gx0, gy0, load_x != 0, nullptr, 0);
         for (int it = 0; it < NU; ++it) {
             tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 1);
             tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 2);
@@ -925,7 +953,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
         const int tx_n = (d.n[0] + FX - 1) / FX;
         const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
         // the down pass's iterate plus the prolonged coarse correction
-        tile2_load<T>(t, d, Arr<T>::xs(d), gx0, gy0, true, Arr<T>::x(cL), cL.n[0]);
+        tile2_load<T>(t, d, as_global(Arr<T>::xs(d)), gx0, gy0, true, as_global(Arr<T>::x(cL)), cL.n[0]);
         for (int it = 0; it < NU; ++it) {
             tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 1);
             tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 2);
@@ -1187,18 +1215,48 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
 // per level.  The restriction from level T-1 left b_T in global memory and the
 // prolongation to level T-1 reads the correction x_T back from global memory.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct TailLevel {
+// Geometry of one tail level and the LDS offsets (in elements from the start of
+// the tail's dynamic LDS) of its arrays.  The arrays are addressed as that base
+// plus an offset in the kernel itself, so the compiler sees LDS pointers and
+// emits ds_* instructions (pointers read back from memory would be generic and
+// need flat instructions, which also wait on the vector memory counter).
+struct TailGeom {
     int32_t n[3];
     int32_t ncell;
     int32_t hx;          // colour cells per row: ceil(nx / 2)
     float rhx;           // 1 / hx
     float rny;           // 1 / ny
     float rnx;           // 1 / nx
+    int32_t ox, ob, ow[3];
+};
+
+template <typename T>
+struct TailLevel {
+    int32_t n[3];
+    int32_t ncell;
+    int32_t hx;
+    float rhx;
+    float rny;
+    float rnx;
     T* x;
     T* b;
     T* w[3];
 };
+
+template <typename T>
+__device__ __forceinline__ TailLevel<T> tl_at(const TailGeom& g, T* base) {
+    TailLevel<T> t;
+    t.n[0] = g.n[0]; t.n[1] = g.n[1]; t.n[2] = g.n[2];
+    t.ncell = g.ncell;
+    t.hx = g.hx;
+    t.rhx = g.rhx;
+    t.rny = g.rny;
+    t.rnx = g.rnx;
+    t.x = base + g.ox;
+    t.b = base + g.ob;
+    for (int a = 0; a < 3; ++a) t.w[a] = base + g.ow[a];
+    return t;
+}
 constexpr int kMaxTail = 16;
 
 // q / d for 0 <= q < 2^20 and d <= 2^10 through a float reciprocal: (q + 1/2)/d
@@ -1233,15 +1291,23 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
         }
         const int i = 2 * (m - r * lv.hx) + ((j + k + color) & 1);
         if (i >= lv.n[0]) continue;
-        const int c = i + j * sy + k * sz;
+        const long c = i + j * sy + k * sz;
         T s = lv.b[c], dg = T(1);
-        if (i > 0) { const T w = lv.w[0][c]; s += w * lv.x[c - 1]; dg += w; }
-        if (i + 1 < lv.n[0]) { const T w = lv.w[0][c + 1]; s += w * lv.x[c + 1]; dg += w; }
-        if (j > 0) { const T w = lv.w[1][c]; s += w * lv.x[c - sy]; dg += w; }
-        if (j + 1 < lv.n[1]) { const T w = lv.w[1][c + sy]; s += w * lv.x[c + sy]; dg += w; }
+        T wl, xl, wr, xr, wd, xd, wu, xu;
+        nb_pair(lv.w[0], lv.x, c, c - 1, i > 0, wl, xl);
+        nb_pair(lv.w[0], lv.x, c, c + 1, i + 1 < lv.n[0], wr, xr);
+        nb_pair(lv.w[1], lv.x, c, c - sy, j > 0, wd, xd);
+        nb_pair(lv.w[1], lv.x, c, c + sy, j + 1 < lv.n[1], wu, xu);
+        s += wl * xl; dg += wl;
+        s += wr * xr; dg += wr;
+        s += wd * xd; dg += wd;
+        s += wu * xu; dg += wu;
         if (DIM == 3) {
-            if (k > 0) { const T w = lv.w[2][c]; s += w * lv.x[c - sz]; dg += w; }
-            if (k + 1 < lv.n[2]) { const T w = lv.w[2][c + sz]; s += w * lv.x[c + sz]; dg += w; }
+            T wb, xb, wf, xf;
+            nb_pair(lv.w[2], lv.x, c, c - sz, k > 0, wb, xb);
+            nb_pair(lv.w[2], lv.x, c, c + sz, k + 1 < lv.n[2], wf, xf);
+            s += wb * xb; dg += wb;
+            s += wf * xf; dg += wf;
         }
         lv.x[c] = s / dg;
     }
@@ -1253,7 +1319,7 @@ __global__ void __launch_bounds__(kTailThreads)
 k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int nu1, int nu2,
        int plain64) {
     extern __shared__ __align__(16) unsigned char tail_smem[];
-    __shared__ TailLevel<T> tl[kMaxTail];
+    __shared__ TailGeom tl[kMaxTail];
     __shared__ int32_t off[kMaxTail + 1];
     __shared__ double red[2 * kTailThreads / 64];
     const int first = jl.levels[blockIdx.x];
@@ -1274,35 +1340,35 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     if (m_own < nl) {
         int o = 0;
         for (int j = 0; j < m_own; ++j) o += off[j + 1];
-        T* base = reinterpret_cast<T*>(tail_smem) + o;
-        TailLevel<T>& t = tl[m_own];
+        TailGeom& t = tl[m_own];
         t.n[0] = nown[0]; t.n[1] = nown[1]; t.n[2] = nown[2];
         t.ncell = nown[0] * nown[1] * nown[2];
         t.hx = (nown[0] + 1) / 2;
         t.rhx = 1.0f / (float)t.hx;
         t.rnx = 1.0f / (float)nown[0];
         t.rny = 1.0f / (float)nown[1];
-        t.x = base; base += t.ncell;
-        t.b = base; base += t.ncell;
+        t.ox = o; o += t.ncell;
+        t.ob = o; o += t.ncell;
         for (int a = 0; a < 3; ++a) {
-            t.w[a] = (a < DIM) ? base : nullptr;
-            if (a < DIM) base += t.ncell;
+            t.ow[a] = o;                                   // unused past DIM
+            if (a < DIM) o += t.ncell;
         }
     }
     __syncthreads();
-    T* p_sh = tl[nl - 1].w[DIM - 1] + tl[nl - 1].ncell;   // the coarsest CG's search direction
+    T* const sbase = reinterpret_cast<T*>(tail_smem);
+    T* p_sh = sbase + (tl[nl - 1].ow[DIM - 1] + tl[nl - 1].ncell);   // the coarsest CG's search direction
     // load every tail level's weights, and b and (warm) x of the first; loads of a
     // level are issued together, then stored
     for (int m = 0; m < nl; ++m) {
         const LevelDesc& d = L[first + m];
-        const TailLevel<T> t = tl[m];
-        const T* s0 = Arr<T>::w(d, 0);
-        const T* s1 = Arr<T>::w(d, 1);
-        const T* s2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
+        const TailLevel<T> t = tl_at(tl[m], sbase);
+        const gptr<T> s0 = as_global(Arr<T>::w(d, 0));
+        const gptr<T> s1 = as_global(Arr<T>::w(d, 1));
+        const gptr<T> s2 = as_global((DIM == 3) ? Arr<T>::w(d, 2) : Arr<T>::w(d, 0));
         const bool lead = (m == 0);
         const bool warm = lead && plain64 && d.level == 0;
-        const T* bsrc = Arr<T>::b(d);
-        const T* xsrc = Arr<T>::x(d);
+        const gptr<T> bsrc = as_global(Arr<T>::b(d));
+        const gptr<T> xsrc = as_global(Arr<T>::x(d));
         for (int c = threadIdx.x; c < t.ncell; c += kTailThreads) {
             const T a0 = s0[c], a1 = s1[c];
             const T a2 = (DIM == 3) ? s2[c] : T(0);
@@ -1320,8 +1386,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     __syncthreads();
     // descend
     for (int m = 0; m + 1 < nl; ++m) {
-        const TailLevel<T> f = tl[m];
-        const TailLevel<T> cT = tl[m + 1];
+        const TailLevel<T> f = tl_at(tl[m], sbase);
+        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
         for (int it = 0; it < nu1; ++it) {
             tl_half_sweep<DIM, T>(f, 0);
             tl_half_sweep<DIM, T>(f, 1);
@@ -1341,13 +1407,13 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     }
     // coarsest: CG from the current x (zero unless the grid has a single level)
     {
-        const TailLevel<T> cT = tl[nl - 1];
+        const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
         block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
-        const TailLevel<T> f = tl[m];
-        const TailLevel<T> cT = tl[m + 1];
+        const TailLevel<T> f = tl_at(tl[m], sbase);
+        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
         for (int c = threadIdx.x; c < f.ncell; c += kTailThreads) {
             int i, j, k;
             tl_coords<DIM, T>(f, c, i, j, k);
@@ -1360,8 +1426,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
     }
     {
-        T* xdst = Arr<T>::x(L[first]);
-        const TailLevel<T> t0 = tl[0];
+        const gptr<T> xdst = as_global(Arr<T>::x(L[first]));
+        const TailLevel<T> t0 = tl_at(tl[0], sbase);
         for (int c = threadIdx.x; c < t0.ncell; c += kTailThreads) xdst[c] = t0.x[c];
     }
 }
