@@ -454,11 +454,8 @@ __device__ __forceinline__ void nb_pair(P w, P x, long idx, long nb, bool has, T
     xn = x[o];
 }
 
-template <int DIM, typename T>
-__device__ __forceinline__ T residual_at(const T* __restrict__ x, const T* __restrict__ b,
-                                         const T* __restrict__ w0, const T* __restrict__ w1,
-                                         const T* __restrict__ w2, const int32_t n[3],
-                                         int i, int j, int k) {
+template <int DIM, typename T, typename P>
+__device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32_t n[3], int i, int j, int k) {
     const long sy = n[0], sz = (long)n[0] * n[1];
     const long idx = i + j * sy + k * sz;
     const T xc = x[idx];
@@ -502,21 +499,29 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const int k = (DIM == 3) ? rest / ty_n : 0;
         const int i = tx * kSX + 2 * (threadIdx.x & 63) + ((j + k + color) & 1);
         if (i >= d.n[0] || j >= d.n[1]) continue;
-        T* __restrict__ x = Arr<T>::x(d);
-        const T* __restrict__ b = Arr<T>::b(d);
-        const T* __restrict__ w0 = Arr<T>::w(d, 0);
-        const T* __restrict__ w1 = Arr<T>::w(d, 1);
+        const gptr<T> x = as_global(Arr<T>::x(d));
+        const gptr<T> b = as_global(Arr<T>::b(d));
+        const gptr<T> w0 = as_global(Arr<T>::w(d, 0));
+        const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
         const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
         const long idx = i + j * sy + k * sz;
         T s = b[idx], dg = T(1);
-        if (i > 0) { const T w = w0[idx]; s += w * x[idx - 1]; dg += w; }
-        if (i + 1 < d.n[0]) { const T w = w0[idx + 1]; s += w * x[idx + 1]; dg += w; }
-        if (j > 0) { const T w = w1[idx]; s += w * x[idx - sy]; dg += w; }
-        if (j + 1 < d.n[1]) { const T w = w1[idx + sy]; s += w * x[idx + sy]; dg += w; }
+        T wl, xl, wr, xr, wd, xd, wu, xu;
+        nb_pair(w0, x, idx, idx - 1, i > 0, wl, xl);
+        nb_pair(w0, x, idx, idx + 1, i + 1 < d.n[0], wr, xr);
+        nb_pair(w1, x, idx, idx - sy, j > 0, wd, xd);
+        nb_pair(w1, x, idx, idx + sy, j + 1 < d.n[1], wu, xu);
+        s += wl * xl; dg += wl;
+        s += wr * xr; dg += wr;
+        s += wd * xd; dg += wd;
+        s += wu * xu; dg += wu;
         if (DIM == 3) {
-            const T* __restrict__ w2 = Arr<T>::w(d, 2);
-            if (k > 0) { const T w = w2[idx]; s += w * x[idx - sz]; dg += w; }
-            if (k + 1 < d.n[2]) { const T w = w2[idx + sz]; s += w * x[idx + sz]; dg += w; }
+            const gptr<T> w2 = as_global(Arr<T>::w(d, 2));
+            T wb, xb, wf, xf;
+            nb_pair(w2, x, idx, idx - sz, k > 0, wb, xb);
+            nb_pair(w2, x, idx, idx + sz, k + 1 < d.n[2], wf, xf);
+            s += wb * xb; dg += wb;
+            s += wf * xf; dg += wf;
         }
         x[idx] = s / dg;
     }
@@ -537,11 +542,11 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
         int I, J, K;
         cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
         if (I >= cL.n[0] || J >= cL.n[1]) continue;
-        const T* x = Arr<T>::x(f);
-        const T* b = Arr<T>::b(f);
-        const T* w0 = Arr<T>::w(f, 0);
-        const T* w1 = Arr<T>::w(f, 1);
-        const T* w2 = (DIM == 3) ? Arr<T>::w(f, 2) : nullptr;
+        const gptr<T> x = as_global(Arr<T>::x(f));
+        const gptr<T> b = as_global(Arr<T>::b(f));
+        const gptr<T> w0 = as_global(Arr<T>::w(f, 0));
+        const gptr<T> w1 = as_global(Arr<T>::w(f, 1));
+        const gptr<T> w2 = as_global((DIM == 3) ? Arr<T>::w(f, 2) : Arr<T>::w(f, 0));
         T s = T(0);
 #pragma unroll
         for (int c = 0; c < (1 << DIM); ++c) {
@@ -549,8 +554,8 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
                                      DIM == 3 ? 2 * K + (c >> 2) : 0);
         }
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
-        Arr<T>::b(cL)[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
-        Arr<T>::x(cL)[cidx] = T(0);
+        as_global(Arr<T>::b(cL))[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
+        as_global(Arr<T>::x(cL))[cidx] = T(0);
     }
 }
 
@@ -570,7 +575,7 @@ k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         if (i >= f.n[0] || j >= f.n[1]) continue;
         const long idx = i + (long)f.n[0] * (j + (long)f.n[1] * k);
         const long cidx = (i >> 1) + (long)cL.n[0] * ((j >> 1) + (long)cL.n[1] * (k >> 1));
-        Arr<T>::x(f)[idx] += Arr<T>::x(cL)[cidx];
+        as_global(Arr<T>::x(f))[idx] += as_global(Arr<T>::x(cL))[cidx];
     }
 }
 
@@ -1532,14 +1537,16 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
         double r2 = 0.0, unused = 0.0;
         if (i < d.n[0] && j < d.n[1]) {
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            const double r = residual_at<DIM, double>(d.X, d.B0, d.w[0], d.w[1], d.w[2], d.n, i, j, k);
+            const double r = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
+                                                       as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
+                                                       d.n, i, j, k);
             r2 = r * r;
-            d.R[idx] = r;
+            as_global(d.R)[idx] = r;
             if (MIXED) {
-                d.b32[idx] = (float)r;
-                if (zero_x) d.x32[idx] = 0.0f;
+                as_global(d.b32)[idx] = (float)r;
+                if (zero_x) as_global(d.x32)[idx] = 0.0f;
             } else if (zero_x) {
-                d.x[idx] = 0.0;
+                as_global(d.x)[idx] = 0.0;
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
@@ -1555,10 +1562,15 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
 // The search direction is double-buffered by iteration parity so that q = A p
 // can read neighbours' new p without a second pass.
 // ---------------------------------------------------------------------------
+// The preconditioned residual z: the V-cycle's level-0 iterate (FP32 in mixed
+// precision), read through a global pointer.
 template <bool MIXED>
-__device__ __forceinline__ double z_at(const LevelDesc& d, long idx) {
-    return MIXED ? (double)d.x32[idx] : d.x[idx];
-}
+struct ZArr {
+    gptr<double> x64;
+    gptr<float> x32;
+    __device__ explicit ZArr(const LevelDesc& d) : x64(as_global(d.x)), x32(as_global(d.x32)) {}
+    __device__ double operator[](long idx) const { return MIXED ? (double)x32[idx] : x64[idx]; }
+};
 
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
@@ -1578,11 +1590,20 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         double a = 0.0, unused = 0.0;
         if (i < d.n[0] && j < d.n[1]) {
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            a = d.R[idx] * z_at<MIXED>(d, idx);
+            a = as_global(d.R)[idx] * ZArr<MIXED>(d)[idx];
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
+}
+
+// Neighbour weight and search-direction value for k_cg_pq (see nb_pair).
+template <typename F>
+__device__ __forceinline__ void nb_p(gptr<double> w, long idx, long nb, bool has, const F& p_at, double& wn,
+                                     double& pn) {
+    const double wv = w[has ? (nb > idx ? nb : idx) : idx];
+    wn = has ? wv : 0.0;
+    pn = p_at(has ? nb : idx);
 }
 
 template <int DIM, bool MIXED>
@@ -1604,25 +1625,38 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
         const double beta = g.beta;
         const int par = g.iter & 1;
-        double* __restrict__ Pn = d.P[par];
-        const double* __restrict__ Po = d.P[par ^ 1];
+        const gptr<double> Pn = as_global(d.P[par]);
+        const gptr<double> Po = as_global(d.P[par ^ 1]);
+        const ZArr<MIXED> z(d);
         double pq = 0.0, unused = 0.0;
         if (i < d.n[0] && j < d.n[1]) {
             const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
             const long idx = i + j * sy + k * sz;
-            auto p_at = [&](long c) { return restart ? z_at<MIXED>(d, c) : z_at<MIXED>(d, c) + beta * Po[c]; };
+            auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
+            // every neighbour load is issued (from the cell itself across the boundary,
+            // with weight 0: pc - pc adds exactly zero)
             const double pc = p_at(idx);
+            const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
+            double wl, pl, wr, pr, wd, pd, wu, pu;
+            nb_p(w0, idx, idx - 1, i > 0, p_at, wl, pl);
+            nb_p(w0, idx, idx + 1, i + 1 < d.n[0], p_at, wr, pr);
+            nb_p(w1, idx, idx - sy, j > 0, p_at, wd, pd);
+            nb_p(w1, idx, idx + sy, j + 1 < d.n[1], p_at, wu, pu);
             double q = pc;
-            if (i > 0) q += d.w[0][idx] * (pc - p_at(idx - 1));
-            if (i + 1 < d.n[0]) q += d.w[0][idx + 1] * (pc - p_at(idx + 1));
-            if (j > 0) q += d.w[1][idx] * (pc - p_at(idx - sy));
-            if (j + 1 < d.n[1]) q += d.w[1][idx + sy] * (pc - p_at(idx + sy));
+            q += wl * (pc - pl);
+            q += wr * (pc - pr);
+            q += wd * (pc - pd);
+            q += wu * (pc - pu);
             if (DIM == 3) {
-                if (k > 0) q += d.w[2][idx] * (pc - p_at(idx - sz));
-                if (k + 1 < d.n[2]) q += d.w[2][idx + sz] * (pc - p_at(idx + sz));
+                const gptr<double> w2 = as_global(d.w[2]);
+                double wb, pb, wf, pf;
+                nb_p(w2, idx, idx - sz, k > 0, p_at, wb, pb);
+                nb_p(w2, idx, idx + sz, k + 1 < d.n[2], p_at, wf, pf);
+                q += wb * (pc - pb);
+                q += wf * (pc - pf);
             }
             Pn[idx] = pc;
-            d.Q[idx] = q;
+            as_global(d.Q)[idx] = q;
             pq = pc * q;
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
@@ -1647,19 +1681,20 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         int i, j, k;
         cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         const double alpha = g.alpha;
-        const double* __restrict__ P = d.P[g.iter & 1];
+        const gptr<double> P = as_global(d.P[g.iter & 1]);
         double r2 = 0.0, unused = 0.0;
         if (i < d.n[0] && j < d.n[1]) {
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            d.X[idx] += alpha * P[idx];
-            const double r = d.R[idx] - alpha * d.Q[idx];
-            d.R[idx] = r;
+            const gptr<double> X = as_global(d.X), R = as_global(d.R);
+            X[idx] += alpha * P[idx];
+            const double r = R[idx] - alpha * as_global(d.Q)[idx];
+            R[idx] = r;
             r2 = r * r;
             if (MIXED) {
-                d.b32[idx] = (float)r;
-                d.x32[idx] = 0.0f;
+                as_global(d.b32)[idx] = (float)r;
+                as_global(d.x32)[idx] = 0.0f;
             } else {
-                d.x[idx] = 0.0;
+                as_global(d.x)[idx] = 0.0;
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
