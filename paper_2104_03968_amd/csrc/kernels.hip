@@ -810,36 +810,56 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
 }
 
 // ---------------------------------------------------------------------------
-// Fused 2D level kernels.  A 64 x 16 tile is staged in LDS with a halo of
-// width HALO and every half sweep is computed on a region that shrinks by one
+// Fused 2D level kernels.  A tile of FX x FY cells is staged in LDS with a halo
+// of width HALO and every half sweep is computed on a region that shrinks by one
 // ring, so the tile's cells come out exactly as a global red-black sweep would
 // leave them (the halo recomputes what neighbouring tiles compute).  Cells
 // outside the domain hold x = b = 0 and zero face weights, so updating them
 // keeps them 0 and no boundary test is needed inside the sweep.  A pass never
 // reads the array it writes (tiles overlap through their halos): down reads x
 // (when it starts from a stored iterate) and writes xs; up reads xs and writes x.
+//
+// The tile is stored by colour: plane q holds the cells of global parity
+// (i + j) % 2 = q, row by row, cell li of row lj at index li / 2.  A half sweep
+// then reads its operands at unit stride (its neighbours are all in the other
+// plane: left at k + s - 1, right at k + s, up and down at k, where the cell
+// is li = 2k + s), so all lanes of a wave work and LDS accesses do not collide.
 // ---------------------------------------------------------------------------
 template <typename T, int W_, int H_>
 struct Tile2 {
     static constexpr int W = W_;
     static constexpr int H = H_;
-    T x[H][W];
-    T b[H][W];
-    T w0[H][W];
-    T w1[H][W];
+    static constexpr int KW = W_ / 2;      // cells of one colour per row
+    static_assert(W_ % 2 == 0, "tile width must be even");
+    T x[2][H][KW];
+    T b[2][H][KW];
+    T w0[2][H][KW];
+    T w1[2][H][KW];
+    // cell (li, lj) of a tile whose corner has parity G = (gx0 + gy0) & 1
+    __device__ T& X(int li, int lj, int G) { return x[(li + lj + G) & 1][lj][li >> 1]; }
+    __device__ T& B(int li, int lj, int G) { return b[(li + lj + G) & 1][lj][li >> 1]; }
+    __device__ T& W0(int li, int lj, int G) { return w0[(li + lj + G) & 1][lj][li >> 1]; }
+    __device__ T& W1(int li, int lj, int G) { return w1[(li + lj + G) & 1][lj][li >> 1]; }
 };
 
 template <typename Tl>
-__device__ __forceinline__ void tile2_half_sweep(Tl& t, int gx0, int gy0, int color, int m) {
+__device__ __forceinline__ void tile2_half_sweep(Tl& t, int G, int color, int m) {
     // update the cells of `color` with local coordinates in [m, W-m) x [m, H-m)
-    const int lane = threadIdx.x & 63;
-    for (int lj = m + (threadIdx.x >> 6); lj < Tl::H - m; lj += kBlock / 64) {
-        const int li = m + (((gx0 + m + gy0 + lj) ^ color) & 1) + 2 * lane;
-        if (li >= Tl::W - m) continue;
-        const auto wl = t.w0[lj][li], wr = t.w0[lj][li + 1], wd = t.w1[lj][li], wu = t.w1[lj + 1][li];
-        const auto s = t.b[lj][li] + wl * t.x[lj][li - 1] + wr * t.x[lj][li + 1] + wd * t.x[lj - 1][li] +
-                       wu * t.x[lj + 1][li];
-        t.x[lj][li] = s / (decltype(s)(1) + wl + wr + wd + wu);
+    constexpr int KW = Tl::KW;
+    const int o = color ^ 1;
+    const int n = (Tl::H - 2 * m) * KW;
+    for (int e = threadIdx.x; e < n; e += kBlock) {
+        const int r = e / KW;
+        const int k = e - r * KW;
+        const int lj = m + r;
+        const int sft = (color + lj + G) & 1;          // this colour's cells in row lj: li = 2k + sft
+        const int li = 2 * k + sft;
+        if (li < m || li >= Tl::W - m) continue;
+        const auto wl = t.w0[color][lj][k], wr = t.w0[o][lj][k + sft], wd = t.w1[color][lj][k],
+                   wu = t.w1[o][lj + 1][k];
+        const auto s = t.b[color][lj][k] + wl * t.x[o][lj][k + sft - 1] + wr * t.x[o][lj][k + sft] +
+                       wd * t.x[o][lj - 1][k] + wu * t.x[o][lj + 1][k];
+        t.x[color][lj][k] = s / (decltype(s)(1) + wl + wr + wd + wu);
     }
     __syncthreads();
 }
@@ -856,6 +876,7 @@ __device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const gptr
     const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
     constexpr int W = Tl::W, H = Tl::H;
     constexpr int NE = (W * H + kBlock - 1) / kBlock;
+    const int G = (gx0 + gy0) & 1;
     T vx[NE], vb[NE], v0[NE], v1[NE];
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
@@ -880,10 +901,10 @@ __device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const gptr
         const int e = threadIdx.x + r * kBlock;
         if (e < W * H) {
             const int lj = e / W, li = e - lj * W;
-            t.x[lj][li] = vx[r];
-            t.b[lj][li] = vb[r];
-            t.w0[lj][li] = v0[r];
-            t.w1[lj][li] = v1[r];
+            t.X(li, lj, G) = vx[r];
+            t.B(li, lj, G) = vb[r];
+            t.W0(li, lj, G) = v0[r];
+            t.W1(li, lj, G) = v1[r];
         }
     }
     __syncthreads();
@@ -906,10 +927,11 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + FX - 1) / FX;
         const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
+        const int G = (gx0 + gy0) & 1;
         tile2_load<T>(t, d, as_global(Arr<T>::x(d)), gx0, gy0, load_x != 0, nullptr, 0);
         for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 1);
-            tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 2);
+            tile2_half_sweep(t, G, 0, 2 * it + 1);
+            tile2_half_sweep(t, G, 1, 2 * it + 2);
         }
         // smoothed iterate of the interior (to xs: other tiles may still read x), and the
         // residual averaged onto the coarse cells
@@ -917,7 +939,7 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
         for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
             const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
-            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
+            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
         }
         const gptr<T> cb = as_global(Arr<T>::b(cL));
         for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
@@ -928,10 +950,11 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int li = HALO + 2 * ci + (q & 1), lj = HALO + 2 * cj + (q >> 1);
-                    const T xc = t.x[lj][li];
-                    sum += t.b[lj][li] - xc - t.w0[lj][li] * (xc - t.x[lj][li - 1]) -
-                           t.w0[lj][li + 1] * (xc - t.x[lj][li + 1]) - t.w1[lj][li] * (xc - t.x[lj - 1][li]) -
-                           t.w1[lj + 1][li] * (xc - t.x[lj + 1][li]);
+                    const T xc = t.X(li, lj, G);
+                    sum += t.B(li, lj, G) - xc - t.W0(li, lj, G) * (xc - t.X(li - 1, lj, G)) -
+                           t.W0(li + 1, lj, G) * (xc - t.X(li + 1, lj, G)) -
+                           t.W1(li, lj, G) * (xc - t.X(li, lj - 1, G)) -
+                           t.W1(li, lj + 1, G) * (xc - t.X(li, lj + 1, G));
                 }
                 cb[CI + (long)cL.n[0] * CJ] = sum * T(0.25);
             }
@@ -957,17 +980,18 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
         const int lt = tt - jl.prefix[jb];
         const int tx_n = (d.n[0] + FX - 1) / FX;
         const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
+        const int G = (gx0 + gy0) & 1;
         // the down pass's iterate plus the prolonged coarse correction
         tile2_load<T>(t, d, as_global(Arr<T>::xs(d)), gx0, gy0, true, as_global(Arr<T>::x(cL)), cL.n[0]);
         for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep(t, gx0, gy0, 1, 2 * it + 1);
-            tile2_half_sweep(t, gx0, gy0, 0, 2 * it + 2);
+            tile2_half_sweep(t, G, 1, 2 * it + 1);
+            tile2_half_sweep(t, G, 0, 2 * it + 2);
         }
         const gptr<T> xo = as_global(Arr<T>::x(d));
         for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
             const int lj = e / FX, li = e - lj * FX;
             const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
-            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.x[HALO + lj][HALO + li];
+            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
         }
         __syncthreads();
     }
