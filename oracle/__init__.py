@@ -17,3 +17,7 @@ from .imex import *  # noqa: F401,F403,E402
 from . import imex as _imex  # noqa: E402
 
 __all__ = list(__all__) + list(_imex.__all__)
+from .aniso import *  # noqa: F401,F403,E402
+from . import aniso as _aniso  # noqa: E402
+
+__all__ = list(__all__) + list(_aniso.__all__)

@@ -36,7 +36,7 @@ __all__ = [
     "smooth_field", "span", "lognormal", "cell_centres",
     "GridInput", "pulse_2d", "random_grid", "gas_for", "c2_inputs",
     "c3_inputs", "c4_layout", "c4_grid", "c4_inputs", "c5_stream", "Request",
-    "E1_HEATCOOL", "E4_THIN", "CGS",
+    "E1_HEATCOOL", "E4_THIN", "CGS", "e1_grid", "e4_grid",
 ]
 
 N_MODES = 32
@@ -283,3 +283,32 @@ E1_HEATCOOL = dict(rho=1e-7, kappa=0.4, gamma=5.0 / 3.0, mu=0.6, E=1e12,
 # Optically thin front test (section "Optically thin limit"): diffusion only.
 E4_THIN = dict(x_lo=-0.5, x_hi=1.5, n=256, rho=0.025, kappa=0.4, d=0.05,
                E1=1.4e11, E0=1.4e-11, dt=1e-13)
+
+
+def e1_grid(e0: float, n: int = 8) -> GridInput:
+    """The heating/cooling box as an n x n grid of uniform cells (the periodic
+    boundaries of the test play no part: every field is uniform), with initial gas
+    energy density ``e0``; CGS constants, c_v = k_b / ((gamma - 1) mu m_p)."""
+    p = E1_HEATCOOL
+    shape = (n, n)
+    c_v = CGS["k_b"] / ((p["gamma"] - 1.0) * p["mu"] * CGS["m_p"])
+    g = GridInput(E=np.full(shape, p["E"]), kappa_rho=np.full(shape, p["kappa"] * p["rho"]),
+                  dt=p["dts"][0], h=(1.0 / n, 1.0 / n), c=CGS["c"], a_r=CGS["a_r"], c_v=c_v)
+    g.rho = np.full(shape, p["rho"])
+    g.kappa = np.full(shape, p["kappa"])
+    g.eps = np.full(shape, float(e0))
+    return g
+
+
+def e4_grid(ny: int = 4) -> GridInput:
+    """The optically thin slab as an n x ny grid (x across the front, ny copies):
+    E = E0 + (1 - erf(x / d)) E1 / 2 at the cell centres, kappa rho uniform, CGS c."""
+    from math import erf
+    p = E4_THIN
+    hx = (p["x_hi"] - p["x_lo"]) / p["n"]
+    xc = p["x_lo"] + (np.arange(p["n"]) + 0.5) * hx
+    row = p["E0"] + 0.5 * (1.0 - np.array([erf(x / p["d"]) for x in xc])) * p["E1"]
+    E = np.tile(row, (ny, 1))
+    return GridInput(E=E, kappa_rho=np.full(E.shape, p["rho"] * p["kappa"]), dt=p["dt"], h=(hx, hx),
+                     c=CGS["c"])
+
