@@ -211,6 +211,20 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in,
 int32_t fld_step(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho,
                  double* const* E_out, const double* dt, void* stream, fld_stats* stats);
 
+/* fld_step with a diagonal-tensor diffusion coefficient (the anisotropic D the
+   paper reports testing, Sec. 5, with the notation of Sec. 3 carried over per
+   grid direction): the caller gives one kappa rho per direction, and the faces
+   normal to direction a use
+     R_a = |grad E| / ((kappa rho)_a E),  D_a = c lambda(R_a) / (kappa rho)_a,
+   harmonic-mean face values of D_a and the weights dt D_a / h_a^2; the solve is
+   that of fld_step.  kappa_rho_dir: host array of 3 * ngrids device pointers,
+   kappa_rho_dir[3 g + a] for a < ndim of grid g (N_g doubles each; entries past
+   ndim are ignored).  Equal arrays give fld_step's result.  Same ownership,
+   synchronisation and status codes as fld_step (BAD_INPUT covers every
+   direction's opacity). */
+int32_t fld_step_aniso(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho_dir,
+                       double* const* E_out, const double* dt, void* stream, fld_stats* stats);
+
 /* Point-implicit gas-radiation energy exchange (Sec. 3.3), in place, per cell
    of every grid g: with a1 = c a_rad kappa dt / (rho^3 c_v^4) and
    a2 = c kappa rho dt, eps' is the unique root in ]0, eps + E[ of

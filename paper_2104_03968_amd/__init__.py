@@ -155,6 +155,7 @@ _sig = {
     "fld_plan_level_view": (C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(fld_level_view)]),
     "fld_coefficients": (C.c_int32, [_P, _PP, _PP, C.POINTER(C.c_double), _P]),
     "fld_step": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
+    "fld_step_aniso": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
     "fld_exchange": (C.c_int32, [_P, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas), _P]),
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
     "fld_plan_tuning": (C.c_int32, [_P, C.POINTER(fld_tuning)]),
@@ -304,6 +305,17 @@ def fld_step(plan: int, E_in, kappa_rho, E_out, dt, stream=None, check: bool = T
                        _stream(stream), stats)
     if check:
         _check(rc, "fld_step")
+    return rc, [s.as_dict() for s in stats]
+
+
+def fld_step_aniso(plan: int, E_in, kappa_rho_dir, E_out, dt, stream=None, check: bool = True):
+    """kappa_rho_dir: per grid a list of ndim tensors (x first).  Returns (status, stats)."""
+    n = len(E_in)
+    kp = _vptrs(kappa_rho_dir, n)
+    stats = (fld_stats * n)()
+    rc = _lib.fld_step_aniso(plan, _ptrs(E_in), kp, _ptrs(E_out), _dts(dt, n), _stream(stream), stats)
+    if check:
+        _check(rc, "fld_step_aniso")
     return rc, [s.as_dict() for s in stats]
 
 
@@ -566,6 +578,9 @@ class Plan:
 
     def step(self, E_in, kappa_rho, E_out, dt, stream=None, check: bool = True):
         return fld_step(self.handle, E_in, kappa_rho, E_out, dt, stream, check)
+
+    def step_aniso(self, E_in, kappa_rho_dir, E_out, dt, stream=None, check: bool = True):
+        return fld_step_aniso(self.handle, E_in, kappa_rho_dir, E_out, dt, stream, check)
 
     def exchange(self, E, eps, rho, kappa, dt, gas: Optional[fld_gas] = None, stream=None):
         fld_exchange(self.handle, E, eps, rho, kappa, dt, gas or fld_gas_default(), stream)

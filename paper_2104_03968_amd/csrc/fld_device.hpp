@@ -133,6 +133,7 @@ struct StepIO {
     const double* kr;
     double*       E_out;
     double        dt;
+    const double* krd[3];   // per-direction kappa rho (diagonal-tensor D); NULL: kr for every direction
 };
 
 // Per-call pointers of fld_exchange (one entry per grid).

@@ -348,15 +348,34 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
             const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             const double e = p.E_in[idx];
-            const double kk = p.kr[idx];
-            const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
-            if (!ok) atomicOr(&S[d.grid].bad, 1);
-            const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter);
             double wx = 0.0, wy = 0.0, wz = 0.0;
-            if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter), Dc, dt, d.hinv[0]);
-            if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter), Dc, dt, d.hinv[1]);
-            if (DIM == 3 && k > 0)
-                wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter), Dc, dt, d.hinv[2]);
+            if (!p.krd[0]) {
+                const double kk = p.kr[idx];
+                const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
+                if (!ok) atomicOr(&S[d.grid].bad, 1);
+                const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter);
+                if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter), Dc, dt, d.hinv[0]);
+                if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter), Dc, dt, d.hinv[1]);
+                if (DIM == 3 && k > 0)
+                    wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter), Dc, dt, d.hinv[2]);
+            } else {
+                // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
+                bool ok = (e > 0.0) && isfinite(e);
+                for (int a = 0; a < DIM; ++a) {
+                    const double kk = p.krd[a][idx];
+                    ok = ok && (kk > 0.0) && isfinite(kk);
+                }
+                if (!ok) atomicOr(&S[d.grid].bad, 1);
+                if (i > 0)
+                    wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter),
+                                cell_D<DIM>(p.E_in, p.krd[0], i, j, k, d.n, c12, c, limiter), dt, d.hinv[0]);
+                if (j > 0)
+                    wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter),
+                                cell_D<DIM>(p.E_in, p.krd[1], i, j, k, d.n, c12, c, limiter), dt, d.hinv[1]);
+                if (DIM == 3 && k > 0)
+                    wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter),
+                                cell_D<DIM>(p.E_in, p.krd[2], i, j, k, d.n, c12, c, limiter), dt, d.hinv[2]);
+            }
             d.w[0][idx] = wx;
             d.w[1][idx] = wy;
             if (DIM == 3) d.w[2][idx] = wz;

@@ -683,14 +683,21 @@ void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* o) {
     o->q_b = (st.bsum != 0.0) ? std::sqrt(st.bnorm2) / (std::sqrt(N) * std::fabs(st.bsum / N)) : INFINITY;
 }
 
+// krd: NULL, or 3 * ngrids per-direction kappa rho pointers (diagonal-tensor D; kr unused).
 static int step(Plan& p, const double* const* E_in, const double* const* kr, double* const* E_out,
-                const double* dt, hipStream_t s, fld_stats* stats) {
+                const double* dt, hipStream_t s, fld_stats* stats, const double* const* krd = nullptr) {
     const int G = p.ngrids();
     std::vector<StepIO> io(G);
     for (int g = 0; g < G; ++g) {
-        if (!E_in[g] || !kr[g] || !E_out[g]) return FLD_ERR_INVALID_ARG;
+        if (!E_in[g] || !E_out[g] || (!krd && !kr[g])) return FLD_ERR_INVALID_ARG;
         if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
-        io[g] = StepIO{E_in[g], kr[g], E_out[g], dt[g]};
+        io[g] = StepIO{E_in[g], krd ? krd[3 * g] : kr[g], E_out[g], dt[g]};
+        if (krd) {
+            for (int a = 0; a < p.grids[g].ndim; ++a) {
+                if (!krd[3 * g + a]) return FLD_ERR_INVALID_ARG;
+                io[g].krd[a] = krd[3 * g + a];
+            }
+        }
     }
     int rc = plan_upload_io(p, io.data(), s);
     if (rc != FLD_OK) return rc;
@@ -1220,6 +1227,22 @@ int32_t fld_step(fld_plan_t plan, const double* const* E_in, const double* const
         hipStream_t s = static_cast<hipStream_t>(stream);
         FLD_HIP(hipStreamSynchronize(s));            // earlier work may still read the staging buffer
         return fld::step(p, E_in, kappa_rho, E_out, dt, s, stats);
+    } catch (...) {
+        return FLD_ERR_INVALID_ARG;
+    }
+}
+
+int32_t fld_step_aniso(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho_dir,
+                       double* const* E_out, const double* dt, void* stream, fld_stats* stats) {
+    if (!plan || !E_in || !kappa_rho_dir || !E_out || !dt) return FLD_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (!p.ws) return FLD_ERR_NO_WORKSPACE;
+    try {
+        fld::DeviceGuard dg(p.device);
+        if (!dg.ok) return FLD_ERR_HIP;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        FLD_HIP(hipStreamSynchronize(s));
+        return fld::step(p, E_in, nullptr, E_out, dt, s, stats, kappa_rho_dir);
     } catch (...) {
         return FLD_ERR_INVALID_ARG;
     }

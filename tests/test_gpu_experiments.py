@@ -49,19 +49,25 @@ def test_heating_cooling_relaxation_on_device(fac, dt):
     plan = fld.Plan([g.E.shape], h=[g.h], c=g.c)
     E, eps, rho, kap = dev(g.E), dev(g.eps), dev(g.rho), dev(g.kappa)
     gas = fld.fld_gas_default(c=g.c, a_rad=g.a_r, c_v=g.c_v)
-    Eo, eo = g.E[:2, :2].copy(), g.eps[:2, :2].copy()       # the oracle on a 2 x 2 copy (uniform)
+    # the oracle on one cell of the uniform box: no faces, so its implicit stage is the
+    # identity exactly (on a larger copy its sparse LU of I + dt L, with face weights
+    # ~1e8 here, would add cond(A) eps to E at every step)
+    Eo, eo = g.E[:1, :1].copy(), g.eps[:1, :1].copy()
     hist = [g.eps[0, 0]]
     steps = int(round(5e-9 / dt))
     for s in range(steps):
         rc, _ = plan.imex_step([E], [eps], [rho], [kap], [dt], gas=gas, scheme="euler")
         assert rc == fld.FLD_OK
-        Eo, eo = O.imex_step(Eo, eo, g.rho[:2, :2], g.kappa[:2, :2], dt, g.h, c=g.c, a_r=g.a_r, c_v=g.c_v,
+        Eo, eo = O.imex_step(Eo, eo, g.rho[:1, :1], g.kappa[:1, :1], dt, g.h, c=g.c, a_r=g.a_r, c_v=g.c_v,
                              scheme="euler")
         if s % 50 == 0 or s == steps - 1:
             e_gpu, E_gpu = eps.cpu().numpy(), E.cpu().numpy()
             assert np.all(e_gpu == e_gpu[0, 0]) and np.all(E_gpu == E_gpu[0, 0])      # stays uniform
+            # the exchange roots agree to a few ulp of E + eps per step
             assert abs(e_gpu[0, 0] - eo[0, 0]) <= 1e-9 * e_eq, (s, e_gpu[0, 0], eo[0, 0])
-            assert abs(E_gpu[0, 0] - Eo[0, 0]) <= 1e-13 * E_eq
+            assert abs(E_gpu[0, 0] - Eo[0, 0]) <= 1e-12 * E_eq, (s, E_gpu[0, 0], Eo[0, 0])
+            # the total carries one rounding of E per step
+            assert E_gpu[0, 0] + e_gpu[0, 0] == pytest.approx(g.E[0, 0] + g.eps[0, 0], rel=1e-12)
             hist.append(e_gpu[0, 0])
     hist = np.array(hist)
     d = np.diff(hist)
