@@ -21,3 +21,7 @@ from .aniso import *  # noqa: F401,F403,E402
 from . import aniso as _aniso  # noqa: E402
 
 __all__ = list(__all__) + list(_aniso.__all__)
+from .bc import *  # noqa: F401,F403,E402
+from . import bc as _bc  # noqa: E402
+
+__all__ = list(__all__) + list(_bc.__all__)
