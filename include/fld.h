@@ -55,7 +55,8 @@ extern "C" {
 #define FLD_ERR_UNKNOWN_TICKET  -5
 #define FLD_ERR_HIP             -6   /* a HIP runtime call failed              */
 #define FLD_ERR_NO_WORKSPACE    -7   /* plan has no (or too small) workspace   */
-#define FLD_ERR_UNSUPPORTED     -8   /* option not built (e.g. a BC other than zero flux) */
+#define FLD_ERR_UNSUPPORTED     -8   /* option not built (a BC other than zero flux or fixed
+                                        gradient)                                  */
 #define FLD_ERR_SHUTDOWN        -9   /* server is shutting down               */
 
 /* ---- options ------------------------------------------------------------ */
@@ -68,6 +69,13 @@ extern "C" {
                                         eq. fld_lambda approximates to ~7 %                  */
 
 #define FLD_BC_ZERO_FLUX        0    /* Neumann, zero gradient (Sec. 3.4)      */
+#define FLD_BC_FIXED_GRADIENT   1    /* Neumann with the gradient dE/dx_a given in
+                                        bc_grad (Sec. 3.4): ghosts continue the mirror
+                                        image with that slope, E_{-k} = E_{k-1} -
+                                        (2k-1) h G below and E_{n-1+k} = E_{n-k} +
+                                        (2k-1) h G above, for the 4th-order gradient;
+                                        the face flux -D G, D the boundary cell's,
+                                        enters the right-hand side                 */
 
 #define FLD_PREC_FP64           0    /* every step in FP64                     */
 #define FLD_PREC_MIXED          1    /* FP32 V-cycles inside FP64 defect correction:
@@ -85,7 +93,8 @@ typedef struct fld_grid {
 typedef struct fld_opts {
     double  c;            /* speed of light in the caller's units [1]               */
     int32_t limiter;      /* FLD_LIMITER_* [LP]                                      */
-    int32_t bc[6];        /* per face x-,x+,y-,y+,z-,z+: FLD_BC_* [ZERO_FLUX]        */
+    int32_t bc[6];        /* per face x-,x+,y-,y+,z-,z+: FLD_BC_* [ZERO_FLUX] (z faces
+                             ignored in 2D)                                          */
     int32_t precision;    /* FLD_PREC_* [FP64]                                       */
     double  rtol;         /* stop when ||E^n - A E||_2 <= rtol ||E^n||_2 [1e-10]     */
     int32_t max_cycles;   /* V-cycles (= outer iterations) per step [50]            */
@@ -118,6 +127,8 @@ typedef struct fld_opts {
                              sweeps when fused = 1, nu1, nu2 >= 1 and nu1 + nu2 is
                              even.  tile_rows, tile_wide, max_blocks, tile_depth and
                              fused3_levels must be 0 with autotune                  */
+    double  bc_grad[6];   /* per face: the prescribed gradient of FLD_BC_FIXED_GRADIENT
+                             faces (ignored on zero-flux faces) [0]                  */
 } fld_opts;
 
 /* Per-grid result of fld_step. */

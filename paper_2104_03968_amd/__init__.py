@@ -52,6 +52,7 @@ FLD_IMEX_EULER = 0
 FLD_IMEX_MIDPOINT = 1
 IMEX_SCHEMES = {"euler": FLD_IMEX_EULER, "midpoint": FLD_IMEX_MIDPOINT}
 FLD_BC_ZERO_FLUX = 0
+FLD_BC_FIXED_GRADIENT = 1
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
 FLD_KERNEL_SMOOTH = 0
@@ -77,7 +78,7 @@ class fld_opts(C.Structure):
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32),
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
-                ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32)]
+                ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6)]
 
 
 class fld_tuning(C.Structure):
@@ -232,9 +233,10 @@ def fld_opts_default(**kw) -> fld_opts:
     for k, v in kw.items():
         if k not in names:
             raise TypeError(f"unknown solver option {k!r}")
-        if k == "bc":
+        if k in ("bc", "bc_grad"):
+            arr = getattr(o, k)
             for i, x in enumerate(v):
-                o.bc[i] = x
+                arr[i] = x
         else:
             setattr(o, k, v)
     return o

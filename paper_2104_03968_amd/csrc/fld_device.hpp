@@ -68,6 +68,11 @@ struct LevelDesc {
     int32_t fine;        // index of the next finer level, -1 at level 0
     int32_t nlev;        // levels of the owning grid (a grid's levels are consecutive entries)
     double  hinv[3];     // 1/h per axis (level 0 values are the grid's)
+    // level 0 only: prescribed gradient dE/dx_a at the faces x-, x+, y-, y+, z-, z+ (0 for
+    // zero flux), and that gradient times the cell width (the ghosts' linear part)
+    int32_t has_bc;      // any face with a nonzero prescribed gradient
+    double  bcg[6];
+    double  bcgh[6];
     double* x;           // FP64 solution (level 0) / correction (coarser)
     double* b;           // FP64 right-hand side
     double* w[3];        // FP64 lower-face weights dt*D_face/h^2

@@ -286,6 +286,31 @@ __device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, in
     }
 }
 
+// The same gradient where faces prescribe a gradient G: the ghost at index i
+// outside [0, n) is the mirror image plus the linear part of slope G, -(2k-1) h G
+// below (i = -k) and +(2k-1) h G above (i = n-1+k); gh = {h G_lo, h G_hi} per axis.
+__device__ __forceinline__ double ghost_lin(int i, int n, double ghlo, double ghhi) {
+    return i < 0 ? (double)(2 * i + 1) * ghlo : (i >= n ? (double)(2 * (i - n) + 1) * ghhi : 0.0);
+}
+
+template <int DIM>
+__device__ __forceinline__ void grad4_bc_at(const double* __restrict__ E, int i, int j, int k, const int32_t n[3],
+                                            const double c12[3], const double gh[6], double g[3]) {
+    const long sy = n[0], sz = (long)n[0] * n[1];
+    const long row = (long)j * sy + (long)k * sz;
+    auto ex = [&](int q) { return E[mirror(q, n[0]) + row] + ghost_lin(q, n[0], gh[0], gh[1]); };
+    g[0] = ((ex(i - 2) - ex(i + 2)) + 8.0 * (ex(i + 1) - ex(i - 1))) * c12[0];
+    const long col = i + (long)k * sz;
+    auto ey = [&](int q) { return E[col + mirror(q, n[1]) * sy] + ghost_lin(q, n[1], gh[2], gh[3]); };
+    g[1] = ((ey(j - 2) - ey(j + 2)) + 8.0 * (ey(j + 1) - ey(j - 1))) * c12[1];
+    g[2] = 0.0;
+    if (DIM == 3) {
+        const long pil = i + (long)j * sy;
+        auto ez = [&](int q) { return E[pil + mirror(q, n[2]) * sz] + ghost_lin(q, n[2], gh[4], gh[5]); };
+        g[2] = ((ez(k - 2) - ez(k + 2)) + 8.0 * (ez(k + 1) - ez(k - 1))) * c12[2];
+    }
+}
+
 // Flux limiter lambda(R) (Sec. 2.2): the rational bridging law of eq. fld_lambda,
 // 1/3, Minerbo's two branches (meeting with equal value and slope at R = 3/2), or
 // Levermore and Pomraning's (coth R - 1/R)/R, by its series below R = 0.1 where
@@ -311,12 +336,13 @@ __device__ __forceinline__ double limiter_of(double R, int limiter) {
 template <int DIM>
 __device__ __forceinline__ double cell_D(const double* __restrict__ E, const double* __restrict__ kr,
                                          int i, int j, int k, const int32_t n[3], const double c12[3],
-                                         double c, int limiter) {
+                                         double c, int limiter, const double* gh = nullptr) {
     const long idx = i + (long)n[0] * (j + (long)n[1] * k);
     const double e = E[idx];
     const double kk = kr[idx];
     double g[3];
-    grad4_at<DIM>(E, i, j, k, n, c12, g);
+    if (gh) grad4_bc_at<DIM>(E, i, j, k, n, c12, gh, g);
+    else grad4_at<DIM>(E, i, j, k, n, c12, g);
     double g2 = g[0] * g[0] + g[1] * g[1];
     if (DIM == 3) g2 += g[2] * g[2];
     const double R = sqrt(g2) / (kk * e);
@@ -349,15 +375,18 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             const double e = p.E_in[idx];
             double wx = 0.0, wy = 0.0, wz = 0.0;
+            const double* gh = d.has_bc ? d.bcgh : nullptr;
+            double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
             if (!p.krd[0]) {
                 const double kk = p.kr[idx];
                 const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
                 if (!ok) atomicOr(&S[d.grid].bad, 1);
-                const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter);
-                if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter), Dc, dt, d.hinv[0]);
-                if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter), Dc, dt, d.hinv[1]);
+                const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
+                Da[0] = Da[1] = Da[2] = Dc;
+                if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
+                if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
                 if (DIM == 3 && k > 0)
-                    wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter), Dc, dt, d.hinv[2]);
+                    wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
             } else {
                 // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
                 bool ok = (e > 0.0) && isfinite(e);
@@ -366,15 +395,16 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     ok = ok && (kk > 0.0) && isfinite(kk);
                 }
                 if (!ok) atomicOr(&S[d.grid].bad, 1);
+                for (int a = 0; a < DIM; ++a) Da[a] = cell_D<DIM>(p.E_in, p.krd[a], i, j, k, d.n, c12, c, limiter, gh);
                 if (i > 0)
-                    wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter),
-                                cell_D<DIM>(p.E_in, p.krd[0], i, j, k, d.n, c12, c, limiter), dt, d.hinv[0]);
+                    wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter, gh), Da[0], dt,
+                                d.hinv[0]);
                 if (j > 0)
-                    wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter),
-                                cell_D<DIM>(p.E_in, p.krd[1], i, j, k, d.n, c12, c, limiter), dt, d.hinv[1]);
+                    wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter, gh), Da[1], dt,
+                                d.hinv[1]);
                 if (DIM == 3 && k > 0)
-                    wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter),
-                                cell_D<DIM>(p.E_in, p.krd[2], i, j, k, d.n, c12, c, limiter), dt, d.hinv[2]);
+                    wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter, gh), Da[2], dt,
+                                d.hinv[2]);
             }
             d.w[0][idx] = wx;
             d.w[1][idx] = wy;
@@ -384,10 +414,19 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 d.w32[1][idx] = (float)wy;
                 if (DIM == 3) d.w32[2][idx] = (float)wz;
             }
-            d.B0[idx] = e;
+            // fixed-gradient faces: the flux -D G through the face, D the cell's own, enters b
+            double bsrc = e;
+            if (d.has_bc) {
+                const int ci[3] = {i, j, k};
+                for (int a = 0; a < DIM; ++a) {
+                    if (ci[a] == 0) bsrc += dt * d.hinv[a] * (-Da[a] * d.bcg[2 * a]);
+                    if (ci[a] == d.n[a] - 1) bsrc += dt * d.hinv[a] * (Da[a] * d.bcg[2 * a + 1]);
+                }
+            }
+            d.B0[idx] = bsrc;
             d.X[idx] = e;
-            s2 = e * e;
-            s1 = e;
+            s2 = bsrc * bsrc;
+            s1 = bsrc;
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
                            max_cycles, sh, &flag);
@@ -1508,7 +1547,8 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
         const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
         const double e = m.E[idx], kk = m.kr[idx];
         double g[3];
-        grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
+        if (d.has_bc) grad4_bc_at<DIM>(m.E, i, j, k, d.n, c12, d.bcgh, g);
+        else grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
         double g2 = g[0] * g[0] + g[1] * g[1];
         if (DIM == 3) g2 += g[2] * g[2];
         const double gn = sqrt(g2);

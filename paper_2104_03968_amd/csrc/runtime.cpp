@@ -50,8 +50,11 @@ struct DeviceGuard {
 int validate_opts(const fld_opts& o) {
     if (!(o.c > 0.0) || !std::isfinite(o.c)) return FLD_ERR_INVALID_ARG;
     if (o.limiter < FLD_LIMITER_LP || o.limiter > FLD_LIMITER_LP_EXACT) return FLD_ERR_INVALID_ARG;
-    for (int f = 0; f < 6; ++f)
-        if (o.bc[f] != FLD_BC_ZERO_FLUX) return FLD_ERR_UNSUPPORTED;
+    for (int f = 0; f < 6; ++f) {
+        if (o.bc[f] < 0) return FLD_ERR_INVALID_ARG;
+        if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT) return FLD_ERR_UNSUPPORTED;
+        if (!std::isfinite(o.bc_grad[f])) return FLD_ERR_INVALID_ARG;
+    }
     if (o.precision != FLD_PREC_FP64 && o.precision != FLD_PREC_MIXED) return FLD_ERR_INVALID_ARG;
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return FLD_ERR_INVALID_ARG;
     if (o.max_cycles < 1 || o.max_cycles > 100000) return FLD_ERR_INVALID_ARG;
@@ -157,6 +160,14 @@ static void build_levels(Plan& p) {
             d.level = lev;
             d.coarse = -1;
             d.fine = lev == 0 ? -1 : (int32_t)p.levels.size() - 1;
+            if (lev == 0) {
+                for (int f = 0; f < 2 * gr.ndim; ++f) {
+                    const double G = p.opts.bc[f] == FLD_BC_FIXED_GRADIENT ? p.opts.bc_grad[f] : 0.0;
+                    d.bcg[f] = G;
+                    d.bcgh[f] = G * gr.h[f / 2];
+                    if (G != 0.0) d.has_bc = 1;
+                }
+            }
             if (lev > 0) p.levels.back().coarse = (int32_t)p.levels.size();
             p.levels.push_back(d);
             bool can = true;
@@ -1085,7 +1096,10 @@ void fld_opts_default(fld_opts* o) {
     std::memset(o, 0, sizeof(*o));
     o->c = 1.0;
     o->limiter = FLD_LIMITER_LP;
-    for (int f = 0; f < 6; ++f) o->bc[f] = FLD_BC_ZERO_FLUX;
+    for (int f = 0; f < 6; ++f) {
+        o->bc[f] = FLD_BC_ZERO_FLUX;
+        o->bc_grad[f] = 0.0;
+    }
     o->precision = FLD_PREC_FP64;
     o->rtol = 1e-10;
     o->max_cycles = 50;

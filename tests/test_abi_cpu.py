@@ -59,7 +59,8 @@ def test_plan_create_validates_grids(n, ok):
 @pytest.mark.parametrize("kw,code", [
     (dict(rtol=0.0), -1), (dict(rtol=2.0), -1), (dict(c=-1.0), -1), (dict(limiter=7), -1),
     (dict(precision=3), -1), (dict(max_cycles=0), -1), (dict(nu1=0, nu2=0), -1),
-    (dict(bc=[1, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED)])
+    (dict(bc=[2, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1)])
 def test_plan_create_validates_options(kw, code):
     with pytest.raises(fld.FLDError) as e:
         fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(**kw))
@@ -239,3 +240,11 @@ def test_imex_scratch_size_and_argument_checks():
                               fld.FLD_IMEX_EULER, 4096, 1 << 30, stream=0, check=False)
     assert rc in (fld.FLD_ERR_NO_WORKSPACE, fld.FLD_ERR_INVALID_ARG)
     fld.fld_plan_destroy(h)
+
+
+def test_fixed_gradient_boundaries_are_accepted():
+    o = fld.fld_opts_default(bc=[1, 1, 0, 0, 0, 0], bc_grad=[0.5, -2.0, 0, 0, 0, 0])
+    assert list(o.bc)[:2] == [fld.FLD_BC_FIXED_GRADIENT] * 2 and list(o.bc_grad)[:2] == [0.5, -2.0]
+    h = fld.fld_plan_create([fld.make_grid((16, 16))], o)
+    fld.fld_plan_destroy(h)
+
