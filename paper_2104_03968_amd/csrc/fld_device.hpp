@@ -33,6 +33,14 @@ constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
     return ((n[0] + kTX - 1) / kTX) * ((n[1] + kTY - 1) / kTY) * n[2];
 }
+// Level-0 cell tiles (coefficients, residuals, CG vectors, outputs): kTX x kCY0
+// cells, kCPT0 per thread, one reduction partial per tile.
+constexpr int kCY0 = 16;
+constexpr int kCPT0 = kTX * kCY0 / kBlock;
+static_assert(kTX * kCY0 == kCPT0 * kBlock, "level-0 tile must be a whole number of cells per thread");
+__host__ __device__ inline int32_t l0_tiles(const int32_t n[3]) {
+    return ((n[0] + kTX - 1) / kTX) * ((n[1] + kCY0 - 1) / kCY0) * n[2];
+}
 __host__ __device__ inline int32_t smooth_tiles(const int32_t n[3]) {
     return ((n[0] + kSX - 1) / kSX) * ((n[1] + kTY - 1) / kTY) * n[2];
 }

@@ -103,6 +103,20 @@ __device__ __forceinline__ void cell_of_tile(const int32_t n[3], int lt, int tid
     j = ty * kTY + (tid / kTX);
 }
 
+// Level-0 cell tiles: kTX x kCY0 cells (x fastest), kCPT0 per thread; element e
+// of the tile is cell (e % kTX, e / kTX).  Reductions keep one partial per tile.
+template <int DIM>
+__device__ __forceinline__ void cell_of_l0tile(const int32_t n[3], int lt, int e, int& i, int& j, int& k) {
+    const int tx_n = (n[0] + kTX - 1) / kTX;
+    const int ty_n = (n[1] + kCY0 - 1) / kCY0;
+    const int tx = lt % tx_n;
+    const int rest = lt / tx_n;
+    const int ty = rest % ty_n;
+    k = (DIM == 3) ? rest / ty_n : 0;
+    i = tx * kTX + (e & (kTX - 1));
+    j = ty * kCY0 + e / kTX;
+}
+
 // Sum the level-0 per-tile partials of one grid in a fixed order: thread t adds
 // partials t, t + kBlock, t + 2 kBlock, ... in turn, then a fixed-order block sum.
 // The loads are issued kSumBatch at a time so they overlap; the additions keep
@@ -365,68 +379,71 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const int lt = t - jl.prefix[jb];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         const StepIO& p = io[d.grid];
         const double dt = p.dt;
         double s2 = 0.0, s1 = 0.0;
-        if (i < d.n[0] && j < d.n[1]) {
-            const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            const double e = p.E_in[idx];
-            double wx = 0.0, wy = 0.0, wz = 0.0;
-            const double* gh = d.has_bc ? d.bcgh : nullptr;
-            double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
-            if (!p.krd[0]) {
-                const double kk = p.kr[idx];
-                const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
-                if (!ok) atomicOr(&S[d.grid].bad, 1);
-                const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
-                Da[0] = Da[1] = Da[2] = Dc;
-                if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
-                if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
-                if (DIM == 3 && k > 0)
-                    wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
-            } else {
-                // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
-                bool ok = (e > 0.0) && isfinite(e);
-                for (int a = 0; a < DIM; ++a) {
-                    const double kk = p.krd[a][idx];
-                    ok = ok && (kk > 0.0) && isfinite(kk);
+#pragma unroll 1
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1]) {
+                const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                const double e = p.E_in[idx];
+                double wx = 0.0, wy = 0.0, wz = 0.0;
+                const double* gh = d.has_bc ? d.bcgh : nullptr;
+                double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
+                if (!p.krd[0]) {
+                    const double kk = p.kr[idx];
+                    const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
+                    if (!ok) atomicOr(&S[d.grid].bad, 1);
+                    const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
+                    Da[0] = Da[1] = Da[2] = Dc;
+                    if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
+                    if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
+                    if (DIM == 3 && k > 0)
+                        wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
+                } else {
+                    // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
+                    bool ok = (e > 0.0) && isfinite(e);
+                    for (int a = 0; a < DIM; ++a) {
+                        const double kk = p.krd[a][idx];
+                        ok = ok && (kk > 0.0) && isfinite(kk);
+                    }
+                    if (!ok) atomicOr(&S[d.grid].bad, 1);
+                    for (int a = 0; a < DIM; ++a) Da[a] = cell_D<DIM>(p.E_in, p.krd[a], i, j, k, d.n, c12, c, limiter, gh);
+                    if (i > 0)
+                        wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter, gh), Da[0], dt,
+                                    d.hinv[0]);
+                    if (j > 0)
+                        wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter, gh), Da[1], dt,
+                                    d.hinv[1]);
+                    if (DIM == 3 && k > 0)
+                        wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter, gh), Da[2], dt,
+                                    d.hinv[2]);
                 }
-                if (!ok) atomicOr(&S[d.grid].bad, 1);
-                for (int a = 0; a < DIM; ++a) Da[a] = cell_D<DIM>(p.E_in, p.krd[a], i, j, k, d.n, c12, c, limiter, gh);
-                if (i > 0)
-                    wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter, gh), Da[0], dt,
-                                d.hinv[0]);
-                if (j > 0)
-                    wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter, gh), Da[1], dt,
-                                d.hinv[1]);
-                if (DIM == 3 && k > 0)
-                    wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter, gh), Da[2], dt,
-                                d.hinv[2]);
-            }
-            d.w[0][idx] = wx;
-            d.w[1][idx] = wy;
-            if (DIM == 3) d.w[2][idx] = wz;
-            if (MIXED) {
-                d.w32[0][idx] = (float)wx;
-                d.w32[1][idx] = (float)wy;
-                if (DIM == 3) d.w32[2][idx] = (float)wz;
-            }
-            // fixed-gradient faces: the flux -D G through the face, D the cell's own, enters b
-            double bsrc = e;
-            if (d.has_bc) {
-                const int ci[3] = {i, j, k};
-                for (int a = 0; a < DIM; ++a) {
-                    if (ci[a] == 0) bsrc += dt * d.hinv[a] * (-Da[a] * d.bcg[2 * a]);
-                    if (ci[a] == d.n[a] - 1) bsrc += dt * d.hinv[a] * (Da[a] * d.bcg[2 * a + 1]);
+                d.w[0][idx] = wx;
+                d.w[1][idx] = wy;
+                if (DIM == 3) d.w[2][idx] = wz;
+                if (MIXED) {
+                    d.w32[0][idx] = (float)wx;
+                    d.w32[1][idx] = (float)wy;
+                    if (DIM == 3) d.w32[2][idx] = (float)wz;
                 }
+                // fixed-gradient faces: the flux -D G through the face, D the cell's own, enters b
+                double bsrc = e;
+                if (d.has_bc) {
+                    const int ci[3] = {i, j, k};
+                    for (int a = 0; a < DIM; ++a) {
+                        if (ci[a] == 0) bsrc += dt * d.hinv[a] * (-Da[a] * d.bcg[2 * a]);
+                        if (ci[a] == d.n[a] - 1) bsrc += dt * d.hinv[a] * (Da[a] * d.bcg[2 * a + 1]);
+                    }
+                }
+                d.B0[idx] = bsrc;
+                d.X[idx] = e;
+                s2 += bsrc * bsrc;
+                s1 += bsrc;
             }
-            d.B0[idx] = bsrc;
-            d.X[idx] = e;
-            s2 = bsrc * bsrc;
-            s1 = bsrc;
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
                            max_cycles, sh, &flag);
@@ -1540,56 +1557,59 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const MomentsIO& m = io[d.grid];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
-        if (i >= d.n[0] || j >= d.n[1]) continue;
-        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-        const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
-        const double e = m.E[idx], kk = m.kr[idx];
-        double g[3];
-        if (d.has_bc) grad4_bc_at<DIM>(m.E, i, j, k, d.n, c12, d.bcgh, g);
-        else grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
-        double g2 = g[0] * g[0] + g[1] * g[1];
-        if (DIM == 3) g2 += g[2] * g[2];
-        const double gn = sqrt(g2);
-        const double R = gn / (kk * e);
-        const double lam = limiter_of(R, limiter);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const double Fa = -c * lam / kk * g[a];
-            if (m.F[a]) m.F[a][idx] = Fa;
-            if (m.fr[a]) m.fr[a][idx] = kk * Fa / c;
-        }
-        const double f = R < 1e100 ? lam + lam * lam * R * R : lam + (lam * R) * (lam * R);
-        if (m.edd) m.edd[idx] = f;
-        double nv[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) nv[a] = (a < DIM && gn > 0.0) ? g[a] / gn : 0.0;
-        const double iso = 0.5 * (1.0 - f), aniso = 0.5 * (3.0 * f - 1.0);
-        double P[DIM][DIM];
-        int q = 0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-#pragma unroll
-            for (int b = a; b < DIM; ++b, ++q) {
-                double tt = aniso * nv[a] * nv[b];
-                if (a == b) tt = tt + iso;
-                P[a][b] = e * tt;
-                P[b][a] = P[a][b];
-                if (m.P[q]) m.P[q][idx] = P[a][b];
-            }
-        }
-        if (m.v[0]) {
-            double tir = 0.0;
-#pragma unroll
+#pragma unroll 1
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
+            if (i >= d.n[0] || j >= d.n[1]) continue;
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
+            const double e = m.E[idx], kk = m.kr[idx];
+            double g[3];
+            if (d.has_bc) grad4_bc_at<DIM>(m.E, i, j, k, d.n, c12, d.bcgh, g);
+            else grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
+            double g2 = g[0] * g[0] + g[1] * g[1];
+            if (DIM == 3) g2 += g[2] * g[2];
+            const double gn = sqrt(g2);
+            const double R = gn / (kk * e);
+            const double lam = limiter_of(R, limiter);
+    #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                double dv[3];
-                grad4_at<DIM>(m.v[a], i, j, k, d.n, c12, dv);        // dv[b] = d v_a / d x_b
-#pragma unroll
-                for (int b = 0; b < DIM; ++b) tir = tir + P[a][b] * dv[b];
+                const double Fa = -c * lam / kk * g[a];
+                if (m.F[a]) m.F[a][idx] = Fa;
+                if (m.fr[a]) m.fr[a][idx] = kk * Fa / c;
             }
-            if (m.tiring) m.tiring[idx] = tir;
-            if (m.E_out) m.E_out[idx] = e - m.dt * tir;
+            const double f = R < 1e100 ? lam + lam * lam * R * R : lam + (lam * R) * (lam * R);
+            if (m.edd) m.edd[idx] = f;
+            double nv[3];
+    #pragma unroll
+            for (int a = 0; a < 3; ++a) nv[a] = (a < DIM && gn > 0.0) ? g[a] / gn : 0.0;
+            const double iso = 0.5 * (1.0 - f), aniso = 0.5 * (3.0 * f - 1.0);
+            double P[DIM][DIM];
+            int q = 0;
+    #pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+    #pragma unroll
+                for (int b = a; b < DIM; ++b, ++q) {
+                    double tt = aniso * nv[a] * nv[b];
+                    if (a == b) tt = tt + iso;
+                    P[a][b] = e * tt;
+                    P[b][a] = P[a][b];
+                    if (m.P[q]) m.P[q][idx] = P[a][b];
+                }
+            }
+            if (m.v[0]) {
+                double tir = 0.0;
+    #pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    double dv[3];
+                    grad4_at<DIM>(m.v[a], i, j, k, d.n, c12, dv);        // dv[b] = d v_a / d x_b
+    #pragma unroll
+                    for (int b = 0; b < DIM; ++b) tir = tir + P[a][b] * dv[b];
+                }
+                if (m.tiring) m.tiring[idx] = tir;
+                if (m.E_out) m.E_out[idx] = e - m.dt * tir;
+            }
         }
     }
 }
@@ -1615,21 +1635,24 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
         // recursive residual met the target), whose true residual is checked here
         if (select == 0 ? !g.active : (g.status != FLD_OK || g.active)) continue;   // uniform per tile
         const int lt = t - jl.prefix[jb];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         double r2 = 0.0, unused = 0.0;
-        if (i < d.n[0] && j < d.n[1]) {
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            const double r = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
-                                                       as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
-                                                       d.n, i, j, k);
-            r2 = r * r;
-            as_global(d.R)[idx] = r;
-            if (MIXED) {
-                as_global(d.b32)[idx] = (float)r;
-                if (zero_x) as_global(d.x32)[idx] = 0.0f;
-            } else if (zero_x) {
-                as_global(d.x)[idx] = 0.0;
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1]) {
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                const double r = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
+                                                           as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
+                                                           d.n, i, j, k);
+                r2 += r * r;
+                as_global(d.R)[idx] = r;
+                if (MIXED) {
+                    as_global(d.b32)[idx] = (float)r;
+                    if (zero_x) as_global(d.x32)[idx] = 0.0f;
+                } else if (zero_x) {
+                    as_global(d.x)[idx] = 0.0;
+                }
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
@@ -1668,12 +1691,15 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
         const int lt = t - jl.prefix[jb];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         double a = 0.0, unused = 0.0;
-        if (i < d.n[0] && j < d.n[1]) {
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            a = as_global(d.R)[idx] * ZArr<MIXED>(d)[idx];
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1]) {
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                a += as_global(d.R)[idx] * ZArr<MIXED>(d)[idx];
+            }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
@@ -1703,8 +1729,6 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         GridState& g = S[d.grid];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
         const double beta = g.beta;
         const int par = g.iter & 1;
@@ -1712,35 +1736,40 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const gptr<double> Po = as_global(d.P[par ^ 1]);
         const ZArr<MIXED> z(d);
         double pq = 0.0, unused = 0.0;
-        if (i < d.n[0] && j < d.n[1]) {
-            const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
-            const long idx = i + j * sy + k * sz;
-            auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
-            // every neighbour load is issued (from the cell itself across the boundary,
-            // with weight 0: pc - pc adds exactly zero)
-            const double pc = p_at(idx);
-            const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
-            double wl, pl, wr, pr, wd, pd, wu, pu;
-            nb_p(w0, idx, idx - 1, i > 0, p_at, wl, pl);
-            nb_p(w0, idx, idx + 1, i + 1 < d.n[0], p_at, wr, pr);
-            nb_p(w1, idx, idx - sy, j > 0, p_at, wd, pd);
-            nb_p(w1, idx, idx + sy, j + 1 < d.n[1], p_at, wu, pu);
-            double q = pc;
-            q += wl * (pc - pl);
-            q += wr * (pc - pr);
-            q += wd * (pc - pd);
-            q += wu * (pc - pu);
-            if (DIM == 3) {
-                const gptr<double> w2 = as_global(d.w[2]);
-                double wb, pb, wf, pf;
-                nb_p(w2, idx, idx - sz, k > 0, p_at, wb, pb);
-                nb_p(w2, idx, idx + sz, k + 1 < d.n[2], p_at, wf, pf);
-                q += wb * (pc - pb);
-                q += wf * (pc - pf);
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1]) {
+                const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+                const long idx = i + j * sy + k * sz;
+                auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
+                // every neighbour load is issued (from the cell itself across the boundary,
+                // with weight 0: pc - pc adds exactly zero)
+                const double pc = p_at(idx);
+                const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
+                double wl, pl, wr, pr, wd, pd, wu, pu;
+                nb_p(w0, idx, idx - 1, i > 0, p_at, wl, pl);
+                nb_p(w0, idx, idx + 1, i + 1 < d.n[0], p_at, wr, pr);
+                nb_p(w1, idx, idx - sy, j > 0, p_at, wd, pd);
+                nb_p(w1, idx, idx + sy, j + 1 < d.n[1], p_at, wu, pu);
+                double q = pc;
+                q += wl * (pc - pl);
+                q += wr * (pc - pr);
+                q += wd * (pc - pd);
+                q += wu * (pc - pu);
+                if (DIM == 3) {
+                    const gptr<double> w2 = as_global(d.w[2]);
+                    double wb, pb, wf, pf;
+                    nb_p(w2, idx, idx - sz, k > 0, p_at, wb, pb);
+                    nb_p(w2, idx, idx + sz, k + 1 < d.n[2], p_at, wf, pf);
+                    q += wb * (pc - pb);
+                    q += wf * (pc - pf);
+                }
+                Pn[idx] = pc;
+                as_global(d.Q)[idx] = q;
+                pq += pc * q;
             }
-            Pn[idx] = pc;
-            as_global(d.Q)[idx] = q;
-            pq = pc * q;
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
@@ -1761,23 +1790,26 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         GridState& g = S[d.grid];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, lt, threadIdx.x, i, j, k);
         const double alpha = g.alpha;
         const gptr<double> P = as_global(d.P[g.iter & 1]);
         double r2 = 0.0, unused = 0.0;
-        if (i < d.n[0] && j < d.n[1]) {
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            const gptr<double> X = as_global(d.X), R = as_global(d.R);
-            X[idx] += alpha * P[idx];
-            const double r = R[idx] - alpha * as_global(d.Q)[idx];
-            R[idx] = r;
-            r2 = r * r;
-            if (MIXED) {
-                as_global(d.b32)[idx] = (float)r;
-                as_global(d.x32)[idx] = 0.0f;
-            } else {
-                as_global(d.x)[idx] = 0.0;
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1]) {
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                const gptr<double> X = as_global(d.X), R = as_global(d.R);
+                X[idx] += alpha * P[idx];
+                const double r = R[idx] - alpha * as_global(d.Q)[idx];
+                R[idx] = r;
+                r2 += r * r;
+                if (MIXED) {
+                    as_global(d.b32)[idx] = (float)r;
+                    as_global(d.x32)[idx] = 0.0f;
+                } else {
+                    as_global(d.x)[idx] = 0.0;
+                }
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
@@ -1794,11 +1826,14 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         if (!S[d.grid].active) continue;
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
-        if (i >= d.n[0] || j >= d.n[1]) continue;
-        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-        d.X[idx] += (double)d.x32[idx];
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
+            if (i >= d.n[0] || j >= d.n[1]) continue;
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            d.X[idx] += (double)d.x32[idx];
+        }
     }
 }
 
@@ -1810,11 +1845,14 @@ k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        int i, j, k;
-        cell_of_tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
-        if (i >= d.n[0] || j >= d.n[1]) continue;
-        const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-        io[d.grid].E_out[idx] = d.X[idx];
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
+            if (i >= d.n[0] || j >= d.n[1]) continue;
+            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+            io[d.grid].E_out[idx] = d.X[idx];
+        }
     }
 }
 

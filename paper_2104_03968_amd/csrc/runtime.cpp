@@ -96,6 +96,7 @@ void finish_list(HostList& l, const std::vector<LevelDesc>& L, int (*tiles)(cons
 }
 
 int tiles_cell(const LevelDesc& d) { return cell_tiles(d.n); }
+int tiles_l0(const LevelDesc& d) { return l0_tiles(d.n); }
 int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
 
@@ -241,7 +242,7 @@ static void build_lists(Plan& p) {
                 D.coarsest.levels.push_back(l0 + p.nlev[g] - 1);
             }
         }
-        finish_list(D.l0_cell, p.levels, tiles_cell);
+        finish_list(D.l0_cell, p.levels, tiles_l0);
         finish_list(D.coarsest, p.levels, tiles_one);
         finish_list(D.tail, p.levels, tiles_one);
         // one same-address atomic per tile is cheaper than a finalize launch only for a few tiles
@@ -380,7 +381,7 @@ static void layout(Plan& p) {
                 f.Q = take(n * 8);
             }
             f.has_part = true;
-            f.part = take(2 * (size_t)cell_tiles(d.n) * 8);
+            f.part = take(2 * (size_t)l0_tiles(d.n) * 8);
         }
         if (!p.mixed) {
             f.has_x = f.has_b = true;
@@ -596,7 +597,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     std::vector<GridState> st(p.ngrids());
     for (int g = 0; g < p.ngrids(); ++g) {
         st[g] = init ? init[g] : GridState{};
-        st[g].ntiles0 = cell_tiles(p.levels[p.level0[g]].n);
+        st[g].ntiles0 = l0_tiles(p.levels[p.level0[g]].n);
         st[g].done = 0;
     }
     FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
