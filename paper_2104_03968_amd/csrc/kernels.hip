@@ -117,6 +117,17 @@ __device__ __forceinline__ void cell_of_l0tile(const int32_t n[3], int lt, int e
     j = ty * kCY0 + e / kTX;
 }
 
+// Cell m of level-0 tile lt for this thread: its flat index, clamped to the nearest
+// cell inside the level so that loads never need a branch, and whether it is inside.
+template <int DIM>
+__device__ __forceinline__ long l0_cell(const LevelDesc& d, int lt, int m, int& i, int& j, int& k, bool& ok) {
+    cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m * kBlock, i, j, k);
+    ok = i < d.n[0] && j < d.n[1];
+    i = min(i, d.n[0] - 1);
+    j = min(j, d.n[1] - 1);
+    return i + (long)d.n[0] * (j + (long)d.n[1] * k);
+}
+
 // Sum the level-0 per-tile partials of one grid in a fixed order: thread t adds
 // partials t, t + kBlock, t + 2 kBlock, ... in turn, then a fixed-order block sum.
 // The loads are issued kSumBatch at a time so they overlap; the additions keep
@@ -1636,23 +1647,29 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
         if (select == 0 ? !g.active : (g.status != FLD_OK || g.active)) continue;   // uniform per tile
         const int lt = t - jl.prefix[jb];
         double r2 = 0.0, unused = 0.0;
+        double rv[kCPT0];
+        long ix[kCPT0];
+        bool ok[kCPT0];
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
-            if (i < d.n[0] && j < d.n[1]) {
-                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-                const double r = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
-                                                           as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
-                                                           d.n, i, j, k);
-                r2 += r * r;
-                as_global(d.R)[idx] = r;
-                if (MIXED) {
-                    as_global(d.b32)[idx] = (float)r;
-                    if (zero_x) as_global(d.x32)[idx] = 0.0f;
-                } else if (zero_x) {
-                    as_global(d.x)[idx] = 0.0;
-                }
+            ix[m_] = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
+            rv[m_] = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
+                                              as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
+                                              d.n, i, j, k);
+        }
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            if (!ok[m_]) continue;
+            const long idx = ix[m_];
+            const double r = rv[m_];
+            r2 += r * r;
+            as_global(d.R)[idx] = r;
+            if (MIXED) {
+                as_global(d.b32)[idx] = (float)r;
+                if (zero_x) as_global(d.x32)[idx] = 0.0f;
+            } else if (zero_x) {
+                as_global(d.x)[idx] = 0.0;
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
@@ -1692,15 +1709,19 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         if (!S[d.grid].active) continue;
         const int lt = t - jl.prefix[jb];
         double a = 0.0, unused = 0.0;
+        const gptr<double> Rg = as_global(d.R);
+        const ZArr<MIXED> z(d);
+        double rv[kCPT0], zv[kCPT0];
+        bool ok[kCPT0];
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
-            if (i < d.n[0] && j < d.n[1]) {
-                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-                a += as_global(d.R)[idx] * ZArr<MIXED>(d)[idx];
-            }
+            const long idx = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
+            rv[m_] = Rg[idx];
+            zv[m_] = z[idx];
         }
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) a += ok[m_] ? rv[m_] * zv[m_] : 0.0;
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
@@ -1739,10 +1760,10 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
-            if (i < d.n[0] && j < d.n[1]) {
+            bool ok;
+            const long idx = l0_cell<DIM>(d, lt, m_, i, j, k, ok);     // loads of a clamped cell are
+            {                                                             // issued unconditionally
                 const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
-                const long idx = i + j * sy + k * sz;
                 auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
                 // every neighbour load is issued (from the cell itself across the boundary,
                 // with weight 0: pc - pc adds exactly zero)
@@ -1766,9 +1787,11 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                     q += wb * (pc - pb);
                     q += wf * (pc - pf);
                 }
-                Pn[idx] = pc;
-                as_global(d.Q)[idx] = q;
-                pq += pc * q;
+                if (ok) {
+                    Pn[idx] = pc;
+                    as_global(d.Q)[idx] = q;
+                    pq += pc * q;
+                }
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
@@ -1793,23 +1816,32 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         const double alpha = g.alpha;
         const gptr<double> P = as_global(d.P[g.iter & 1]);
         double r2 = 0.0, unused = 0.0;
+        const gptr<double> X = as_global(d.X), R = as_global(d.R), Q = as_global(d.Q);
+        double xv[kCPT0], pv[kCPT0], rv[kCPT0], qv[kCPT0];
+        long ix[kCPT0];
+        bool ok[kCPT0];
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
-            if (i < d.n[0] && j < d.n[1]) {
-                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-                const gptr<double> X = as_global(d.X), R = as_global(d.R);
-                X[idx] += alpha * P[idx];
-                const double r = R[idx] - alpha * as_global(d.Q)[idx];
-                R[idx] = r;
-                r2 += r * r;
-                if (MIXED) {
-                    as_global(d.b32)[idx] = (float)r;
-                    as_global(d.x32)[idx] = 0.0f;
-                } else {
-                    as_global(d.x)[idx] = 0.0;
-                }
+            ix[m_] = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
+            xv[m_] = X[ix[m_]];
+            pv[m_] = P[ix[m_]];
+            rv[m_] = R[ix[m_]];
+            qv[m_] = Q[ix[m_]];
+        }
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            if (!ok[m_]) continue;
+            const long idx = ix[m_];
+            X[idx] = xv[m_] + alpha * pv[m_];
+            const double r = rv[m_] - alpha * qv[m_];
+            R[idx] = r;
+            r2 += r * r;
+            if (MIXED) {
+                as_global(d.b32)[idx] = (float)r;
+                as_global(d.x32)[idx] = 0.0f;
+            } else {
+                as_global(d.x)[idx] = 0.0;
             }
         }
         tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
@@ -1829,10 +1861,10 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
-            if (i >= d.n[0] || j >= d.n[1]) continue;
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            d.X[idx] += (double)d.x32[idx];
+            bool ok;
+            const long idx = l0_cell<DIM>(d, t - jl.prefix[jb], m_, i, j, k, ok);
+            const double v = as_global(d.X)[idx] + (double)as_global(d.x32)[idx];
+            if (ok) as_global(d.X)[idx] = v;
         }
     }
 }
@@ -1848,10 +1880,10 @@ k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
-            if (i >= d.n[0] || j >= d.n[1]) continue;
-            const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
-            io[d.grid].E_out[idx] = d.X[idx];
+            bool ok;
+            const long idx = l0_cell<DIM>(d, t - jl.prefix[jb], m_, i, j, k, ok);
+            const double v = as_global(d.X)[idx];
+            if (ok) as_global(io[d.grid].E_out)[idx] = v;
         }
     }
 }
