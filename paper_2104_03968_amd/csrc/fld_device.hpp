@@ -34,12 +34,16 @@ __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
     return ((n[0] + kTX - 1) / kTX) * ((n[1] + kTY - 1) / kTY) * n[2];
 }
 // Level-0 cell tiles (coefficients, residuals, CG vectors, outputs): kTX x kCY0
-// cells, kCPT0 per thread, one reduction partial per tile.
+// cells in 2D, kTX x kCY3 x kCZ3 in 3D; kCPT0 per thread, one reduction partial
+// per tile.  A 2D level has n[2] = 1 (every axis of a 3D grid has >= 2 cells).
 constexpr int kCY0 = 16;
+constexpr int kCY3 = 4;
+constexpr int kCZ3 = 4;
 constexpr int kCPT0 = kTX * kCY0 / kBlock;
-static_assert(kTX * kCY0 == kCPT0 * kBlock, "level-0 tile must be a whole number of cells per thread");
+static_assert(kTX * kCY0 == kCPT0 * kBlock && kCY3 * kCZ3 == kCY0, "level-0 tiles of kCPT0 cells per thread");
 __host__ __device__ inline int32_t l0_tiles(const int32_t n[3]) {
-    return ((n[0] + kTX - 1) / kTX) * ((n[1] + kCY0 - 1) / kCY0) * n[2];
+    if (n[2] == 1) return ((n[0] + kTX - 1) / kTX) * ((n[1] + kCY0 - 1) / kCY0);
+    return ((n[0] + kTX - 1) / kTX) * ((n[1] + kCY3 - 1) / kCY3) * ((n[2] + kCZ3 - 1) / kCZ3);
 }
 __host__ __device__ inline int32_t smooth_tiles(const int32_t n[3]) {
     return ((n[0] + kSX - 1) / kSX) * ((n[1] + kTY - 1) / kTY) * n[2];

@@ -103,18 +103,24 @@ __device__ __forceinline__ void cell_of_tile(const int32_t n[3], int lt, int tid
     j = ty * kTY + (tid / kTX);
 }
 
-// Level-0 cell tiles: kTX x kCY0 cells (x fastest), kCPT0 per thread; element e
-// of the tile is cell (e % kTX, e / kTX).  Reductions keep one partial per tile.
+// Level-0 cell tiles, kCPT0 cells per thread and one reduction partial per tile:
+// in 2D kTX x kCY0 cells (x fastest), in 3D kTX x kCY3 x kCZ3 (a thread's cells are
+// one column of kCZ3 planes, so the z-neighbours of its cells are its own loads).
 template <int DIM>
 __device__ __forceinline__ void cell_of_l0tile(const int32_t n[3], int lt, int e, int& i, int& j, int& k) {
     const int tx_n = (n[0] + kTX - 1) / kTX;
-    const int ty_n = (n[1] + kCY0 - 1) / kCY0;
     const int tx = lt % tx_n;
     const int rest = lt / tx_n;
-    const int ty = rest % ty_n;
-    k = (DIM == 3) ? rest / ty_n : 0;
     i = tx * kTX + (e & (kTX - 1));
-    j = ty * kCY0 + e / kTX;
+    if (DIM == 3) {
+        const int ty_n = (n[1] + kCY3 - 1) / kCY3;
+        j = (rest % ty_n) * kCY3 + ((e / kTX) % kCY3);
+        k = (rest / ty_n) * kCZ3 + e / (kTX * kCY3);
+    } else {
+        const int ty_n = (n[1] + kCY0 - 1) / kCY0;
+        j = (rest % ty_n) * kCY0 + e / kTX;
+        k = rest / ty_n;
+    }
 }
 
 // Cell m of level-0 tile lt for this thread: its flat index, clamped to the nearest
@@ -122,9 +128,10 @@ __device__ __forceinline__ void cell_of_l0tile(const int32_t n[3], int lt, int e
 template <int DIM>
 __device__ __forceinline__ long l0_cell(const LevelDesc& d, int lt, int m, int& i, int& j, int& k, bool& ok) {
     cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m * kBlock, i, j, k);
-    ok = i < d.n[0] && j < d.n[1];
+    ok = i < d.n[0] && j < d.n[1] && k < d.n[2];
     i = min(i, d.n[0] - 1);
     j = min(j, d.n[1] - 1);
+    k = min(k, d.n[2] - 1);
     return i + (long)d.n[0] * (j + (long)d.n[1] * k);
 }
 
@@ -393,11 +400,11 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         const StepIO& p = io[d.grid];
         const double dt = p.dt;
         double s2 = 0.0, s1 = 0.0;
-#pragma unroll 1
+#pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
             cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
-            if (i < d.n[0] && j < d.n[1]) {
+            if (i < d.n[0] && j < d.n[1] && k < d.n[2]) {
                 const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
                 const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
                 const double e = p.E_in[idx];
@@ -1568,11 +1575,11 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
         const MomentsIO& m = io[d.grid];
-#pragma unroll 1
+#pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
             cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
-            if (i >= d.n[0] || j >= d.n[1]) continue;
+            if (i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) continue;
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
             const double e = m.E[idx], kk = m.kr[idx];
@@ -1757,7 +1764,7 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const gptr<double> Po = as_global(d.P[par ^ 1]);
         const ZArr<MIXED> z(d);
         double pq = 0.0, unused = 0.0;
-#pragma unroll
+#pragma unroll 1
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
             bool ok;
