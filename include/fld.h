@@ -115,7 +115,7 @@ typedef struct fld_opts {
                              kernels (sweeps + restriction, prolongation + sweeps)
                              when nu1, nu2 are in 1..3; 0: one kernel per colour
                              sweep and per transfer [1]                             */
-    int32_t tile_rows;    /* fused 2D tile rows: 4, 8, 16 or 32; 0 = 16 [0]         */
+    int32_t tile_rows;    /* fused 2D tile rows: 4, 8, 16 or 32; 0 = 8 [0]          */
     int32_t tile_wide;    /* fused 2D tile width: 0 = 64 cells, 1 = 128 cells less
                              the halo (a colour cell per lane of a 64-lane wave) [0].
                              INVALID_ARG if the tile does not fit the 160 KB LDS   */
@@ -129,6 +129,8 @@ typedef struct fld_opts {
                              fused3_levels must be 0 with autotune                  */
     double  bc_grad[6];   /* per face: the prescribed gradient of FLD_BC_FIXED_GRADIENT
                              faces (ignored on zero-flux faces) [0]                  */
+    int32_t tile_rows_coarse; /* fused 2D tile rows of the levels below the finest: 4, 8,
+                             16 or 32; 0 = as tile_rows [0].  Must be 0 with autotune */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -354,6 +356,7 @@ typedef struct fld_tuning {
     int32_t fused3;       /* 1 if 3D grids run fused sweeps (the tuner may prefer the
                              per-colour kernels)                                    */
     int32_t fused3_levels;/* leading 3D levels with fused sweeps                    */
+    int32_t tile_rows_coarse; /* fused 2D tile rows below the finest level              */
 } fld_tuning;
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);

@@ -78,13 +78,15 @@ class fld_opts(C.Structure):
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32),
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
-                ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6)]
+                ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6),
+                ("tile_rows_coarse", C.c_int32)]
 
 
 class fld_tuning(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
                 ("source", C.c_int32), ("candidates", C.c_int32), ("vcycle_us", C.c_double),
-                ("tile_depth", C.c_int32), ("fused3", C.c_int32), ("fused3_levels", C.c_int32)]
+                ("tile_depth", C.c_int32), ("fused3", C.c_int32), ("fused3_levels", C.c_int32),
+                ("tile_rows_coarse", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

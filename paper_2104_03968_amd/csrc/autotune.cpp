@@ -2,11 +2,11 @@
 // transfers, tails; the solver state is only read) is timed for each
 // candidate launch shape and the fastest is kept.  The candidates are, one
 // dimension after the other: the fused 2D tile (64-wide or full-wave-wide,
-// 4/8/16/32 rows); for 3D grids the fused sweep's planes per block (16/32/64),
-// then how many leading levels run fused (or none: per-colour kernels); and
-// the cap on persistent workgroups.
+// 4/8/16/32 rows), then the rows of the levels below the finest; for 3D grids
+// the fused sweep's planes per block (16/32/64), then how many leading levels
+// run fused (or none: per-colour kernels); and the cap on persistent workgroups.
 // Choices are cached in a text file, one line per plan class:
-//     <key> TAB <wide> <rows> <max_blocks> <depth> <sweep3> <levels3> <microseconds>
+//     <key> TAB <wide> <rows> <max_blocks> <depth> <sweep3> <levels3> <microseconds> <coarse rows>
 // keyed by the device architecture, precision, sweep counts and the size
 // class of the plan's grids, so later plans of the same class skip the timing.
 // The cache file is $FLD_AUTOTUNE_CACHE, else $HOME/.cache/fld_autotune.txt;
@@ -52,7 +52,7 @@ std::string plan_key(const Plan& p) {
         cus = prop.multiProcessorCount;
     }
     char buf[512];
-    int n = std::snprintf(buf, sizeof(buf), "v3|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
+    int n = std::snprintf(buf, sizeof(buf), "v4|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
                           p.mixed ? "mixed" : "fp64", p.opts.nu1, p.opts.nu2, p.krylov ? 1 : 0, p.opts.fused);
     for (int dim = 2; dim <= 3; ++dim) {
         int count = 0;
@@ -83,8 +83,8 @@ bool cache_lookup(const std::string& key, Shape& out) {
         if (key != line) continue;
         Shape s{};
         double us = 0;
-        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %lf", &s.wide, &s.rows, &s.nblk, &s.depth, &s.sweep3,
-                        &s.levels3, &us) == 7) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %lf %d", &s.wide, &s.rows, &s.nblk, &s.depth, &s.sweep3,
+                        &s.levels3, &us, &s.rows_c) == 8) {
             out = s;                                   // the last record of a key wins
             found = true;
         }
@@ -98,8 +98,8 @@ void cache_store(const std::string& key, const Shape& s, double us) {
     if (path.empty()) return;
     FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%d %d %d %d %d %d %.3f\n", key.c_str(), s.wide, s.rows, s.nblk, s.depth, s.sweep3,
-                 s.levels3, us);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %.3f %d\n", key.c_str(), s.wide, s.rows, s.nblk, s.depth, s.sweep3,
+                 s.levels3, us, s.rows_c);
     std::fclose(f);
 }
 
@@ -119,13 +119,13 @@ int max_list_tiles(const Plan& p) {
     return m;
 }
 
-// Microseconds of one multigrid V-cycle with shape s (median of a few timed runs).
+// Microseconds of one multigrid V-cycle with shape s (median of five timed pairs).
 int time_shape(Plan& p, const Shape& s, hipEvent_t e0, hipEvent_t e1, double& us) {
     int rc = plan_set_shape(p, s);
     if (rc != FLD_OK) return rc;
     plan_vcycle_mg(p, nullptr);                       // warm-up (instruction cache, lists)
     std::vector<double> t;
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < 5; ++r) {
         FLD_HIP(hipEventRecord(e0, nullptr));
         for (int k = 0; k < 2; ++k) plan_vcycle_mg(p, nullptr);
         FLD_HIP(hipEventRecord(e1, nullptr));
@@ -136,7 +136,7 @@ int time_shape(Plan& p, const Shape& s, hipEvent_t e0, hipEvent_t e1, double& us
         t.push_back(500.0 * ms);                      // per V-cycle, microseconds
     }
     std::sort(t.begin(), t.end());
-    us = t[1];
+    us = t[2];
     return FLD_OK;
 }
 
@@ -199,8 +199,21 @@ int plan_autotune(Plan& p) {
                 Shape s = best;
                 s.wide = wide;
                 s.rows = rows;
+                s.rows_c = rows;
                 c.push_back(s);
             }
+        if ((rc = stage(c)) != FLD_OK) return rc;
+        // then the rows of the coarser levels alone (fewer tiles there: shorter ones
+        // can fill the chip where the finest level prefers taller ones)
+        c.clear();
+        for (int rows : {4, 8, 16, 32}) {
+            if (rows == best.rows_c || !fused2_shape_ok(p.mixed, p.opts.nu1, best.wide, rows, true) ||
+                !fused2_shape_ok(p.mixed, p.opts.nu2, best.wide, rows, false))
+                continue;
+            Shape s = best;
+            s.rows_c = rows;
+            c.push_back(s);
+        }
         if ((rc = stage(c)) != FLD_OK) return rc;
     }
     if (any3) {

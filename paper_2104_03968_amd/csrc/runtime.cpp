@@ -65,13 +65,17 @@ int validate_opts(const fld_opts& o) {
     if (o.autotune < 0 || o.autotune > 2) return FLD_ERR_INVALID_ARG;
     if (o.tile_rows != 0 && o.tile_rows != 4 && o.tile_rows != 8 && o.tile_rows != 16 && o.tile_rows != 32)
         return FLD_ERR_INVALID_ARG;
+    if (o.tile_rows_coarse != 0 && o.tile_rows_coarse != 4 && o.tile_rows_coarse != 8 &&
+        o.tile_rows_coarse != 16 && o.tile_rows_coarse != 32)
+        return FLD_ERR_INVALID_ARG;
     if (o.tile_wide != 0 && o.tile_wide != 1) return FLD_ERR_INVALID_ARG;
     if (o.max_blocks < 0 || o.max_blocks > (1 << 20)) return FLD_ERR_INVALID_ARG;
     // the tuner picks the launch shape itself
     if (o.tile_depth != 0 && o.tile_depth != 16 && o.tile_depth != 32 && o.tile_depth != 64)
         return FLD_ERR_INVALID_ARG;
     if (o.fused3_levels < 0 || o.fused3_levels > 64) return FLD_ERR_INVALID_ARG;
-    if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks || o.tile_depth || o.fused3_levels))
+    if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks || o.tile_depth || o.fused3_levels ||
+                       o.tile_rows_coarse))
         return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
@@ -133,8 +137,9 @@ void finish_fused(const Plan& p, DimLists& D) {
         HostList& up = D.up2[dpt];
         dn.prefix.assign(1, 0);
         up.prefix.assign(1, 0);
-        for (int32_t li : dn.levels) dn.prefix.push_back(dn.prefix.back() + fused_tiles(p.levels[li].n, fxd, p.tile_rows));
-        for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, p.tile_rows));
+        const int rows = dpt == 0 ? p.tile_rows : p.tile_rows_c;
+        for (int32_t li : dn.levels) dn.prefix.push_back(dn.prefix.back() + fused_tiles(p.levels[li].n, fxd, rows));
+        for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, rows));
     }
 }
 
@@ -309,13 +314,16 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     for (auto& g : p.grids)
         if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
     p.tile_wide = opts.tile_wide;
-    p.tile_rows = opts.tile_rows ? opts.tile_rows : 16;
+    p.tile_rows = opts.tile_rows ? opts.tile_rows : 8;
+    p.tile_rows_c = opts.tile_rows_coarse ? opts.tile_rows_coarse : p.tile_rows;
     p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
     p.tile_depth = opts.tile_depth ? opts.tile_depth : 32;
     p.sweep3_levels = opts.fused3_levels;
     if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) &&
         !(fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows, true) &&
-          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false)))
+          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false) &&
+          fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows_c, true) &&
+          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_c, false)))
         return FLD_ERR_INVALID_ARG;                            // the tile does not fit the LDS
     build_levels(p);
     build_lists(p);
@@ -442,7 +450,7 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
         }
         if (D.fused) {
             launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.tile_wide,
-                         p.tile_rows, p.nblk, s);
+                         d == 0 ? p.tile_rows : p.tile_rows_c, p.nblk, s);
             continue;
         }
         for (int it = 0; it < p.opts.nu1; ++it) {
@@ -460,7 +468,8 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
             continue;
         }
         if (D.fused) {
-            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, p.tile_rows, p.nblk, s);
+            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, d == 0 ? p.tile_rows : p.tile_rows_c,
+                       p.nblk, s);
             continue;
         }
         launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
@@ -527,20 +536,23 @@ static int upload_list(Plan& p, HostList& l) {
 }
 
 LaunchShape plan_shape(const Plan& p) {
-    return LaunchShape{p.tile_wide, p.tile_rows, p.nblk, p.tile_depth, p.sweep3, p.sweep3_levels};
+    return LaunchShape{p.tile_wide, p.tile_rows, p.nblk, p.tile_depth, p.sweep3, p.sweep3_levels, p.tile_rows_c};
 }
 
 int plan_set_shape(Plan& p, const LaunchShape& sh) {
     if (!p.ws) return FLD_ERR_NO_WORKSPACE;
     for (auto& D : p.dl)
         if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows, true) &&
-                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows, false)))
+                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows, false) &&
+                         fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows_c, true) &&
+                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_c, false)))
             return FLD_ERR_INVALID_ARG;
     if (sh.nblk < 1 || (sh.depth != 16 && sh.depth != 32 && sh.depth != 64) || (sh.sweep3 != 0 && sh.sweep3 != 1) ||
         sh.levels3 < 0)
         return FLD_ERR_INVALID_ARG;
     p.tile_wide = sh.wide;
     p.tile_rows = sh.rows;
+    p.tile_rows_c = sh.rows_c;
     p.nblk = sh.nblk;
     p.tile_depth = sh.depth;
     p.sweep3 = sh.sweep3;
@@ -1014,11 +1026,13 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_DOWN:
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0,
-                                                             p.tile_wide, p.tile_rows, p.nblk, s);
+                                                             p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
+                                                             p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2,
-                                                         p.tile_wide, p.tile_rows, p.nblk, s);
+                                                         p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
+                                                         p.nblk, s);
                     break;
                 case FLD_KERNEL_SWEEP3:
                     if (has_level && D.fused3)
@@ -1360,6 +1374,7 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
         if (D.fused3 && !D.l0_cell.empty() && p.sweep3) l3 = std::max(l3, D.levels3);
     out->fused3 = l3 > 0 ? 1 : 0;
     out->fused3_levels = l3;
+    out->tile_rows_coarse = p.tile_rows_c;
     return FLD_OK;
 }
 

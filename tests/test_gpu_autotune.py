@@ -59,6 +59,17 @@ def test_every_tile_shape_gives_identical_results(precision):
         assert rel_l2(ref[i], x_or) <= 1e-10 * O.q_b(g.E) * 1.01
 
 
+@pytest.mark.parametrize("rows,rows_c", [(8, 4), (16, 4), (4, 32), (32, 8)])
+def test_coarse_tile_rows_give_identical_results(rows, rows_c):
+    grids = batch()
+    ref, sref, _ = run_step(grids)
+    xs, st, rc = run_step(grids, tile_rows=rows, tile_rows_coarse=rows_c)
+    assert rc == 0
+    for i in range(len(grids)):
+        assert np.array_equal(xs[i], ref[i]), (rows, rows_c, i)
+        assert st[i]["cycles"] == sref[i]["cycles"]
+
+
 @pytest.mark.parametrize("max_blocks", [1, 7, 300, 1 << 16])
 def test_block_cap_gives_identical_results(max_blocks):
     grids = batch() + [W.random_grid((24, 40, 32), 91100, dt=3e-3)]
@@ -103,7 +114,8 @@ def test_autotuned_plan_matches_default_and_caches(precision, tmp_path, monkeypa
     assert len(lines) == 1
     key, rec = lines[0].split("\t")
     assert ("mixed" if precision else "fp64") in key
-    wide, rows, nblk, depth, sweep3, levels3, us = rec.split()
+    wide, rows, nblk, depth, sweep3, levels3, us, rows_c = rec.split()
+    assert int(rows_c) == t["tile_rows_coarse"]
     assert (int(wide), int(rows), int(nblk)) == (t["tile_wide"], t["tile_rows"], t["max_blocks"])
     assert int(depth) == t["tile_depth"]
 
@@ -129,7 +141,7 @@ def test_stale_cache_record_is_retimed(tmp_path, monkeypatch):
     p = fld.Plan([g.E.shape], h=[g.h], autotune=1)
     key = cache.read_text().split("\t")[0]
     p.close()
-    cache.write_text(f"{key}\t1 32 2048 32 1 0 1.0\n")
+    cache.write_text(f"{key}\t1 32 2048 32 1 0 1.0 32\n")
     q = fld.Plan([g.E.shape], h=[g.h], autotune=1)
     t = q.tuning()
     assert t["source"] == 1 and fits(0, t["tile_wide"], t["tile_rows"])
