@@ -957,50 +957,88 @@ __device__ __forceinline__ void tile2_half_sweep(Tl& t, int G, int color, int m)
     __syncthreads();
 }
 
-// Stage the tile and its halo in LDS.  All global loads of a thread are issued
-// before any LDS store so their latencies overlap.  With `cx`, the piecewise-
-// constant prolongation of the coarse correction is added to x on the way in.
-template <typename T, typename Tl>
-__device__ __forceinline__ void tile2_load(Tl& t, const LevelDesc& d, const gptr<T> xs,
-                                           int gx0, int gy0, bool load_x, const gptr<T> cx,
-                                           int ncx) {
+// A tile's operands in registers between their loads and their LDS stores.  The
+// loads are branch-free (a cell outside the level loads its nearest in-level cell
+// and is stored as 0), so a block can issue the next tile's loads and sweep the
+// current one while they are in flight.
+template <typename T, int NE>
+struct Tile2Regs {
+    T x[NE], c[NE], b[NE], w0[NE], w1[NE];
+    uint32_t ok;          // bit r: element r lies inside the level
+};
+
+template <typename T, typename Tl, int NE>
+__device__ __forceinline__ void tile2_fetch(Tile2Regs<T, NE>& v, const LevelDesc& d, const gptr<T> xs, int gx0,
+                                            int gy0, bool load_x, const gptr<T> cx, int ncx) {
+    static_assert(NE <= 32, "ok mask");
     const gptr<T> bs = as_global(Arr<T>::b(d));
     const gptr<T> w0 = as_global(Arr<T>::w(d, 0));
     const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
     constexpr int W = Tl::W, H = Tl::H;
-    constexpr int NE = (W * H + kBlock - 1) / kBlock;
-    const int G = (gx0 + gy0) & 1;
-    T vx[NE], vb[NE], v0[NE], v1[NE];
+    v.ok = 0;
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
         const int e = threadIdx.x + r * kBlock;
-        vx[r] = T(0);
-        vb[r] = T(0);
-        v0[r] = T(0);
-        v1[r] = T(0);
-        const int lj = e / W, li = e - lj * W;
+        const int ec = min(e, W * H - 1);
+        const int lj = ec / W, li = ec - lj * W;
         const int gi = gx0 + li, gj = gy0 + lj;
-        if (e < W * H && gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1]) {
-            const long idx = gi + (long)d.n[0] * gj;
-            vb[r] = bs[idx];
-            v0[r] = w0[idx];
-            v1[r] = w1[idx];
-            if (load_x) vx[r] = xs[idx];
-            if (cx) vx[r] += cx[(gi >> 1) + (long)ncx * (gj >> 1)];
-        }
+        const bool ok = e < W * H && gi >= 0 && gi < d.n[0] && gj >= 0 && gj < d.n[1];
+        const int ic = min(max(gi, 0), d.n[0] - 1), jc = min(max(gj, 0), d.n[1] - 1);
+        const long idx = ic + (long)d.n[0] * jc;
+        v.ok |= (ok ? 1u : 0u) << r;
+        v.b[r] = bs[idx];
+        v.w0[r] = w0[idx];
+        v.w1[r] = w1[idx];
+        v.x[r] = load_x ? xs[idx] : T(0);
+        v.c[r] = cx ? cx[(ic >> 1) + (long)ncx * (jc >> 1)] : T(0);
     }
+}
+
+// Store fetched operands to the tile (x plus the prolonged coarse correction when
+// add_c); cells outside the level hold x = b = 0 and zero face weights.
+template <typename T, typename Tl, int NE>
+__device__ __forceinline__ void tile2_put(Tl& t, const Tile2Regs<T, NE>& v, int gx0, int gy0, bool add_c) {
+    constexpr int W = Tl::W, H = Tl::H;
+    const int G = (gx0 + gy0) & 1;
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
         const int e = threadIdx.x + r * kBlock;
         if (e < W * H) {
             const int lj = e / W, li = e - lj * W;
-            t.X(li, lj, G) = vx[r];
-            t.B(li, lj, G) = vb[r];
-            t.W0(li, lj, G) = v0[r];
-            t.W1(li, lj, G) = v1[r];
+            const bool ok = (v.ok >> r) & 1u;
+            T xx = v.x[r];
+            if (add_c) xx += v.c[r];
+            t.X(li, lj, G) = ok ? xx : T(0);
+            t.B(li, lj, G) = ok ? v.b[r] : T(0);
+            t.W0(li, lj, G) = ok ? v.w0[r] : T(0);
+            t.W1(li, lj, G) = ok ? v.w1[r] : T(0);
         }
     }
     __syncthreads();
+}
+
+// One tile of a fused 2D launch: its level, the coarser level, its corner and
+// whether its grid is still iterating.
+struct Tile2Job {
+    const LevelDesc* d;
+    const LevelDesc* c;
+    int gx0, gy0;
+    bool act;
+};
+
+template <int FX, int FY, int HALO>
+__device__ __forceinline__ Tile2Job tile2_job(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
+                                              const JobList& jl, int tt) {
+    Tile2Job j;
+    const int jb = find_job(jl.prefix, jl.njobs, tt);
+    j.d = &L[jl.levels[jb]];
+    j.c = &L[j.d->coarse];
+    j.act = S[j.d->grid].active != 0;
+    const int lt = tt - jl.prefix[jb];
+    const int tx_n = (j.d->n[0] + FX - 1) / FX;
+    j.gx0 = (lt % tx_n) * FX - HALO;
+    j.gy0 = (lt / tx_n) * FY - HALO;
+    return j;
 }
 
 template <typename T, int NU, int WIDE, int FY>
@@ -1009,50 +1047,80 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
     constexpr int HALO = 2 * NU + 1;
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
+    constexpr int NE = (Tl::W * Tl::H + kBlock - 1) / kBlock;
     __shared__ Tl t;
     const XcdOrder order(jl.total);
-    for (int k = order.first(); order.more(k); k += order.per) {
-        const int tt = order.tile(k);
-        const int jb = find_job(jl.prefix, jl.njobs, tt);
-        const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
-        const LevelDesc& cL = L[d.coarse];
-        const int lt = tt - jl.prefix[jb];
-        const int tx_n = (d.n[0] + FX - 1) / FX;
-        const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
-        const int G = (gx0 + gy0) & 1;
-        tile2_load<T>(t, d, as_global(Arr<T>::x(d)), gx0, gy0, load_x != 0, nullptr, 0);
-        for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep(t, G, 0, 2 * it + 1);
-            tile2_half_sweep(t, G, 1, 2 * it + 2);
+    int k = order.first();
+    if (!order.more(k)) return;
+    Tile2Job cj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(k));
+    Tile2Regs<T, NE> v;
+    tile2_fetch<T, Tl, NE>(v, *cj.d, as_global(Arr<T>::x(*cj.d)), cj.gx0, cj.gy0, load_x != 0, nullptr, 0);
+    // the current tile's job, kept in scalars (an aggregate copied across iterations
+    // would be placed in LDS by the compiler)
+    const LevelDesc* cd = cj.d;
+    const LevelDesc* cc = cj.c;
+    int cgx = cj.gx0, cgy = cj.gy0, cact = cj.act ? 1 : 0;
+    while (true) {
+        if (cact) tile2_put<T, Tl, NE>(t, v, cgx, cgy, false);
+        // the next tile's loads are in flight while this one is swept
+        const int kn = k + order.per;
+        const bool more = order.more(kn);
+        const LevelDesc* nd = cd;
+        const LevelDesc* nc = cc;
+        int ngx = cgx, ngy = cgy, nact = cact;
+        if (more) {
+            const Tile2Job nj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(kn));
+            nd = nj.d;
+            nc = nj.c;
+            ngx = nj.gx0;
+            ngy = nj.gy0;
+            nact = nj.act ? 1 : 0;
+            tile2_fetch<T, Tl, NE>(v, *nd, as_global(Arr<T>::x(*nd)), ngx, ngy, load_x != 0, nullptr, 0);
         }
-        // smoothed iterate of the interior (to xs: other tiles may still read x), and the
-        // residual averaged onto the coarse cells
-        const gptr<T> xo = as_global(Arr<T>::xs(d));
-        for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
-            const int lj = e / FX, li = e - lj * FX;
-            const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
-            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
-        }
-        const gptr<T> cb = as_global(Arr<T>::b(cL));
-        for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
-            const int cj = e / (FX / 2), ci = e - cj * (FX / 2);
-            const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj;
-            if (CI < cL.n[0] && CJ < cL.n[1]) {
-                T sum = T(0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int li = HALO + 2 * ci + (q & 1), lj = HALO + 2 * cj + (q >> 1);
-                    const T xc = t.X(li, lj, G);
-                    sum += t.B(li, lj, G) - xc - t.W0(li, lj, G) * (xc - t.X(li - 1, lj, G)) -
-                           t.W0(li + 1, lj, G) * (xc - t.X(li + 1, lj, G)) -
-                           t.W1(li, lj, G) * (xc - t.X(li, lj - 1, G)) -
-                           t.W1(li, lj + 1, G) * (xc - t.X(li, lj + 1, G));
-                }
-                cb[CI + (long)cL.n[0] * CJ] = sum * T(0.25);
+        if (cact) {
+            const LevelDesc& d = *cd;
+            const LevelDesc& cL = *cc;
+            const int gx0 = cgx, gy0 = cgy;
+            const int G = (gx0 + gy0) & 1;
+            for (int it = 0; it < NU; ++it) {
+                tile2_half_sweep(t, G, 0, 2 * it + 1);
+                tile2_half_sweep(t, G, 1, 2 * it + 2);
             }
+            // smoothed iterate of the interior (to xs: other tiles may still read x), and the
+            // residual averaged onto the coarse cells
+            const gptr<T> xo = as_global(Arr<T>::xs(d));
+            for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+                const int lj = e / FX, li = e - lj * FX;
+                const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
+                if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
+            }
+            const gptr<T> cb = as_global(Arr<T>::b(cL));
+            for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
+                const int cj_ = e / (FX / 2), ci = e - cj_ * (FX / 2);
+                const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj_;
+                if (CI < cL.n[0] && CJ < cL.n[1]) {
+                    T sum = T(0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int li = HALO + 2 * ci + (q & 1), lj = HALO + 2 * cj_ + (q >> 1);
+                        const T xc = t.X(li, lj, G);
+                        sum += t.B(li, lj, G) - xc - t.W0(li, lj, G) * (xc - t.X(li - 1, lj, G)) -
+                               t.W0(li + 1, lj, G) * (xc - t.X(li + 1, lj, G)) -
+                               t.W1(li, lj, G) * (xc - t.X(li, lj - 1, G)) -
+                               t.W1(li, lj + 1, G) * (xc - t.X(li, lj + 1, G));
+                    }
+                    cb[CI + (long)cL.n[0] * CJ] = sum * T(0.25);
+                }
+            }
+            __syncthreads();                           // t is rewritten by the next tile
         }
-        __syncthreads();                               // t is reloaded by the next tile
+        if (!more) break;
+        k = kn;
+        cd = nd;
+        cc = nc;
+        cgx = ngx;
+        cgy = ngy;
+        cact = nact;
     }
 }
 
@@ -1062,31 +1130,55 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
     constexpr int HALO = 2 * NU;
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
+    constexpr int NE = (Tl::W * Tl::H + kBlock - 1) / kBlock;
     __shared__ Tl t;
     const XcdOrder order(jl.total);
-    for (int k = order.first(); order.more(k); k += order.per) {
-        const int tt = order.tile(k);
-        const int jb = find_job(jl.prefix, jl.njobs, tt);
-        const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
-        const LevelDesc& cL = L[d.coarse];
-        const int lt = tt - jl.prefix[jb];
-        const int tx_n = (d.n[0] + FX - 1) / FX;
-        const int gx0 = (lt % tx_n) * FX - HALO, gy0 = (lt / tx_n) * FY - HALO;
-        const int G = (gx0 + gy0) & 1;
-        // the down pass's iterate plus the prolonged coarse correction
-        tile2_load<T>(t, d, as_global(Arr<T>::xs(d)), gx0, gy0, true, as_global(Arr<T>::x(cL)), cL.n[0]);
-        for (int it = 0; it < NU; ++it) {
-            tile2_half_sweep(t, G, 1, 2 * it + 1);
-            tile2_half_sweep(t, G, 0, 2 * it + 2);
+    int k = order.first();
+    if (!order.more(k)) return;
+    // the down pass's iterate plus the prolonged coarse correction
+    Tile2Job cj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(k));
+    Tile2Regs<T, NE> v;
+    tile2_fetch<T, Tl, NE>(v, *cj.d, as_global(Arr<T>::xs(*cj.d)), cj.gx0, cj.gy0, true,
+                           as_global(Arr<T>::x(*cj.c)), cj.c->n[0]);
+    const LevelDesc* cd = cj.d;
+    int cgx = cj.gx0, cgy = cj.gy0, cact = cj.act ? 1 : 0;
+    while (true) {
+        if (cact) tile2_put<T, Tl, NE>(t, v, cgx, cgy, true);
+        const int kn = k + order.per;
+        const bool more = order.more(kn);
+        const LevelDesc* nd = cd;
+        int ngx = cgx, ngy = cgy, nact = cact;
+        if (more) {
+            const Tile2Job nj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(kn));
+            nd = nj.d;
+            ngx = nj.gx0;
+            ngy = nj.gy0;
+            nact = nj.act ? 1 : 0;
+            tile2_fetch<T, Tl, NE>(v, *nd, as_global(Arr<T>::xs(*nd)), ngx, ngy, true,
+                                   as_global(Arr<T>::x(*nj.c)), nj.c->n[0]);
         }
-        const gptr<T> xo = as_global(Arr<T>::x(d));
-        for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
-            const int lj = e / FX, li = e - lj * FX;
-            const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
-            if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
+        if (cact) {
+            const LevelDesc& d = *cd;
+            const int gx0 = cgx, gy0 = cgy;
+            const int G = (gx0 + gy0) & 1;
+            for (int it = 0; it < NU; ++it) {
+                tile2_half_sweep(t, G, 1, 2 * it + 1);
+                tile2_half_sweep(t, G, 0, 2 * it + 2);
+            }
+            const gptr<T> xo = as_global(Arr<T>::x(d));
+            for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+                const int lj = e / FX, li = e - lj * FX;
+                const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
+                if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        if (!more) break;
+        k = kn;
+        cd = nd;
+        cgx = ngx;
+        cgy = ngy;
+        cact = nact;
     }
 }
 
