@@ -106,6 +106,12 @@ int tiles_one(const LevelDesc&) { return 1; }
 
 constexpr int kSweep3MinBlocks = 256;
 
+// Workgroup cap of the level-0 cell kernels (coefficients, residual, CG vectors,
+// output, moments): streaming passes with a reduction per tile, which gain from
+// many workgroups whatever cap the stencil kernels are tuned to.
+constexpr int kCellBlocks = 8192;
+inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
+
 // Fused-tile prefixes of the down / up lists (2D) and the sweep lists (3D) for the
 // plan's launch shape.
 void finish_fused(const Plan& p, DimLists& D) {
@@ -497,16 +503,16 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             const double rt = p.opts.rtol;
             const int mc = p.opts.max_cycles;
             const bool ff = D.fin_fused;
-            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, p.nblk, s);
+            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
-            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, p.nblk, s);
+            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
-            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, p.nblk, s);
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_CG, rt, mc, s);
         } else {
-            if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, p.nblk, s);
+            if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, cell_blocks(p), s);
             launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, D.fin_fused ? FIN_R_CYCLE : -1,
-                            p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                            p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
             if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_CYCLE, p.opts.rtol, p.opts.max_cycles, s);
         }
     }
@@ -664,11 +670,11 @@ int plan_prologue(Plan& p, hipStream_t s) {
         if (D.l0_cell.empty()) continue;
         const JobList& l0 = D.l0_cell.dev;
         launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, D.fin_fused ? FIN_B : -1,
-                     p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                     p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
         for (auto& c : D.coarsen) launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
         launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, D.fin_fused ? FIN_R_INIT : -1, p.opts.rtol,
-                        p.opts.max_cycles, p.nblk, s);
+                        p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
     }
     FLD_HIP(hipGetLastError());
@@ -683,7 +689,7 @@ void plan_verify(Plan& p, hipStream_t s) {
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 1, 1, D.fin_fused ? FIN_R_VERIFY : -1,
-                        p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                        p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused)
             launch_finalize(p.dL, p.dS, D.l0_cell.dev, FIN_R_VERIFY, p.opts.rtol, p.opts.max_cycles, s);
     }
@@ -692,7 +698,7 @@ void plan_verify(Plan& p, hipStream_t s) {
 void plan_output(Plan& p, hipStream_t s) {
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
-        launch_output(D.dim, p.dL, D.l0_cell.dev, p.dIO, p.nblk, s);
+        launch_output(D.dim, p.dL, D.l0_cell.dev, p.dIO, cell_blocks(p), s);
     }
 }
 
@@ -839,7 +845,7 @@ static int moments(Plan& p, const double* const* E, const double* const* kr, con
     MomentsIO* d = p.dMo + (size_t)slot * G;
     FLD_HIP(hipMemcpyAsync(d, h, G * sizeof(MomentsIO), hipMemcpyHostToDevice, s));
     for (auto& D : p.dl)
-        if (!D.l0_cell.empty()) launch_moments(D.dim, p.dL, D.l0_cell.dev, d, p.opts.c, p.opts.limiter, p.nblk, s);
+        if (!D.l0_cell.empty()) launch_moments(D.dim, p.dL, D.l0_cell.dev, d, p.opts.c, p.opts.limiter, cell_blocks(p), s);
     FLD_HIP(hipGetLastError());
     FLD_HIP(hipEventRecord(p.mo_done[slot], s));
     return FLD_OK;
@@ -1012,7 +1018,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_RESIDUAL:
                     launch_residual(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, 0, 0, -1, p.opts.rtol,
-                                    p.opts.max_cycles, p.nblk, s);
+                                    p.opts.max_cycles, cell_blocks(p), s);
                     break;
                 case FLD_KERNEL_RESTRICT:
                     if (has_level) launch_restrict(D.dim, p.mixed, p.dL, p.dS, D.restrict_[level].dev, p.nblk, s);
@@ -1022,7 +1028,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_COEFF:
                     launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
-                                 -1, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                                 -1, p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
                     break;
                 case FLD_KERNEL_DOWN:
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0,
@@ -1232,7 +1238,7 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
         for (auto& D : p.dl) {
             if (D.l0_cell.empty()) continue;
             fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
-                              D.fin_fused ? fld::FIN_B : -1, p.opts.rtol, p.opts.max_cycles, p.nblk, s);
+                              D.fin_fused ? fld::FIN_B : -1, p.opts.rtol, p.opts.max_cycles, fld::cell_blocks(p), s);
             if (!D.fin_fused)
                 fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
             for (auto& c : D.coarsen) fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
