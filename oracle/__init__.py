@@ -25,3 +25,7 @@ from .bc import *  # noqa: F401,F403,E402
 from . import bc as _bc  # noqa: E402
 
 __all__ = list(__all__) + list(_bc.__all__)
+from .multigrid import *  # noqa: F401,F403,E402
+from . import multigrid as _multigrid  # noqa: E402
+
+__all__ = list(__all__) + list(_multigrid.__all__)
