@@ -77,6 +77,13 @@ extern "C" {
                                         the face flux -D G, D the boundary cell's,
                                         enters the right-hand side                 */
 
+#define FLD_COARSE_REDISCRETISED 0   /* coarse faces: mean of the sub-face weights
+                                        times 1/4 (the operator rebuilt at 2h)  */
+#define FLD_COARSE_GALERKIN     1    /* coarse operator R A P of the piecewise-
+                                        constant prolongation P and the child-mean
+                                        restriction R = P^T / 2^d: sum of the sub-face
+                                        weights over 2^d                          */
+
 #define FLD_PREC_FP64           0    /* every step in FP64                     */
 #define FLD_PREC_MIXED          1    /* FP32 V-cycles inside FP64 defect correction:
                                         residual, update and stop test in FP64 */
@@ -131,6 +138,18 @@ typedef struct fld_opts {
                              faces (ignored on zero-flux faces) [0]                  */
     int32_t tile_rows_coarse; /* fused 2D tile rows of the levels below the finest: 4, 8,
                              16 or 32; 0 = as tile_rows [0].  Must be 0 with autotune */
+    int32_t fmg;          /* 1: the first outer iteration of each step is a full-
+                             multigrid cycle (Sec. 3.4: an FMG cycle first, then
+                             V-cycles until the requested residual): the right-hand
+                             side is averaged down the hierarchy, the coarsest
+                             levels are solved, and on each finer level the
+                             bilinear (trilinear) interpolation of the coarser
+                             solution starts one V-cycle.  With krylov = 1 or mixed
+                             precision it solves for the correction of the initial
+                             residual and CG restarts from the corrected iterate;
+                             with plain FP64 V-cycles it replaces E^n as the start.
+                             It counts as one cycle in fld_stats [0]              */
+    int32_t coarse_op;    /* FLD_COARSE_* [REDISCRETISED]                          */
 } fld_opts;
 
 /* Per-grid result of fld_step. */

@@ -55,6 +55,9 @@ FLD_BC_ZERO_FLUX = 0
 FLD_BC_FIXED_GRADIENT = 1
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
+FLD_COARSE_REDISCRETISED = 0
+FLD_COARSE_GALERKIN = 1
+COARSE_OPS = {"rediscretised": FLD_COARSE_REDISCRETISED, "galerkin": FLD_COARSE_GALERKIN}
 FLD_KERNEL_SMOOTH = 0
 FLD_KERNEL_RESIDUAL = 1
 FLD_KERNEL_RESTRICT = 2
@@ -79,7 +82,7 @@ class fld_opts(C.Structure):
                 ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32),
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
                 ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6),
-                ("tile_rows_coarse", C.c_int32)]
+                ("tile_rows_coarse", C.c_int32), ("fmg", C.c_int32), ("coarse_op", C.c_int32)]
 
 
 class fld_tuning(C.Structure):
@@ -239,6 +242,8 @@ def fld_opts_default(**kw) -> fld_opts:
             arr = getattr(o, k)
             for i, x in enumerate(v):
                 arr[i] = x
+        elif k == "coarse_op" and isinstance(v, str):
+            o.coarse_op = COARSE_OPS[v]
         else:
             setattr(o, k, v)
     return o

@@ -133,6 +133,7 @@ enum FinMode : int32_t {
     FIN_RZ = 4,          // CG: rho = r . z, beta
     FIN_PQ = 5,          // CG: alpha = rho / p . q
     FIN_CG = 6,          // CG: recursive ||r||^2, stop test
+    FIN_R_FMG = 7,       // true residual after the full-multigrid start: counts a cycle, (re)starts CG
 };
 
 // Which levels a launch covers.  Level j of the list is LevelDesc levels[j];
@@ -214,13 +215,22 @@ void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
                   hipStream_t s);
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
                      int max_cycles, hipStream_t s);
-void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s);
+// galerkin: coarse weights of R A P (piecewise-constant P, child-mean R); 0: rediscretised.
+void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int galerkin, int nblk, hipStream_t s);
 void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                    int color, int nblk, hipStream_t s);
 void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                      int nblk, hipStream_t s);
 void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                     int nblk, hipStream_t s);
+// Full-multigrid start.  restrict_rhs: the coarse right-hand side is the mean of the
+// children's right-hand sides (restriction list of a depth) and the coarse iterate 0;
+// fmg_interp: the fine iterate is the bilinear / trilinear interpolation of the coarse
+// one, mirrored at domain faces (prolongation list of a depth).
+void launch_restrict_rhs(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                         int nblk, hipStream_t s);
+void launch_fmg_interp(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                       int nblk, hipStream_t s);
 void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          hipStream_t s);
 // Tail: one workgroup per job runs the V-cycle of every level from the job's level down
@@ -262,7 +272,8 @@ void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
                   int max_cycles, int nblk, hipStream_t s);
 void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
                   int max_cycles, int nblk, hipStream_t s);
-void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+// X += the level-0 V-cycle iterate (FP32 when mixed, else FP64).
+void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
                    hipStream_t s);

@@ -51,6 +51,9 @@ struct DimLists {
     int levels3 = 0;                           // leading depths that run fused sweeps
     HostList coarsest;                         // coarsest level of grids without a tail
     HostList tail;                             // first tail level of grids with a tail
+    // per depth d: the tails / coarsest levels of the grids with wide levels below d
+    // (the V-cycles of the full-multigrid start that begin at depth d)
+    std::vector<HostList> tail_from, coarsest_from;
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
     bool fin_fused = false;                    // finish reductions in the last block (small grids)
     int maxdepth = 0;
@@ -127,6 +130,8 @@ struct Plan {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t fmg_graph = nullptr;            // the full-multigrid start (plans with fmg = 1)
+    hipGraphExec_t fmg_graph_exec = nullptr;
 
     ~Plan();
     int ngrids() const { return (int)grids.size(); }
@@ -135,6 +140,8 @@ struct Plan {
 inline Plan::~Plan() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (fmg_graph_exec) (void)hipGraphExecDestroy(fmg_graph_exec);
+    if (fmg_graph) (void)hipGraphDestroy(fmg_graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : ex_done)
         if (e) (void)hipEventDestroy(e);

@@ -185,8 +185,10 @@ __device__ void finalize_grid(GridState& g, double s2, double s1, int mode, doub
             g.active = g.bad ? 0 : 1;
             g.bad = 0;                               // read once per step; cleared for the next one
             break;
+        case FIN_R_FMG:
         case FIN_R_INIT:
         case FIN_R_VERIFY:
+            if (mode == FIN_R_FMG) g.cycles += 1;
             g.rnorm2 = s2;
             g.iter = 0;                              // (re)start CG from this residual
             g.stall = 0;
@@ -469,12 +471,16 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
 }
 
 // ---------------------------------------------------------------------------
-// Coarse-level face weights: average the fine weights of the sub-faces that
-// make up a coarse face, and scale by 1/4 for the doubled cell width.
+// Coarse-level face weights.  Rediscretised: average the fine weights of the
+// sub-faces that make up a coarse face, and scale by 1/4 for the doubled cell
+// width.  Galerkin: the coarse operator R A P of the piecewise-constant
+// prolongation P and the child-mean restriction R = P^T / 2^DIM, which keeps the
+// unit diagonal and gives each coarse face the sum of its sub-face weights over
+// 2^DIM (faces inside a coarse cell cancel), twice the rediscretised weight.
 // ---------------------------------------------------------------------------
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
-k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
+k_coarsen(const LevelDesc* __restrict__ L, JobList jl, int galerkin) {
     const XcdOrder order(jl.total);
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
@@ -487,7 +493,8 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl) {
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
         const long fsy = f.n[0], fsz = (long)f.n[0] * f.n[1];
         const long f0 = 2 * I + 2 * J * fsy + (DIM == 3 ? 2 * K * fsz : 0);
-        const double sc = (DIM == 3) ? 0.0625 : 0.125;    // 1/2^(DIM-1) * 1/4
+        // 1/2^(DIM-1) * 1/4, or 1/2^DIM for the Galerkin product
+        const double sc = galerkin ? ((DIM == 3) ? 0.125 : 0.25) : ((DIM == 3) ? 0.0625 : 0.125);
         double wc[3] = {0.0, 0.0, 0.0};
         // x faces: sub-faces at fine x = 2I over (j, j+1) [and (k, k+1)]
         if (I > 0) {
@@ -669,6 +676,68 @@ k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         const long idx = i + (long)f.n[0] * (j + (long)f.n[1] * k);
         const long cidx = (i >> 1) + (long)cL.n[0] * ((j >> 1) + (long)cL.n[1] * (k >> 1));
         as_global(Arr<T>::x(f))[idx] += as_global(Arr<T>::x(cL))[cidx];
+    }
+}
+
+// Full-multigrid start, first half: the coarse right-hand side is the mean of the
+// 2^DIM children's right-hand sides (the restriction of the V-cycle applied to b
+// itself), and the coarse iterate starts from zero.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_rhs(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& f = L[jl.levels[jb]];
+        if (!S[f.grid].active) continue;
+        const LevelDesc& cL = L[f.coarse];
+        int I, J, K;
+        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        if (I >= cL.n[0] || J >= cL.n[1]) continue;
+        const gptr<T> b = as_global(Arr<T>::b(f));
+        const long sy = f.n[0], sz = (long)f.n[0] * f.n[1];
+        const long f0 = 2 * I + 2 * J * sy + (DIM == 3 ? 2 * K * sz : 0);
+        T s = b[f0] + b[f0 + 1] + b[f0 + sy] + b[f0 + sy + 1];
+        if (DIM == 3) s += b[f0 + sz] + b[f0 + sz + 1] + b[f0 + sz + sy] + b[f0 + sz + sy + 1];
+        const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
+        as_global(Arr<T>::b(cL))[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
+        as_global(Arr<T>::x(cL))[cidx] = T(0);
+    }
+}
+
+// Full-multigrid start, second half: the fine iterate is the linear interpolation
+// of the coarse solution between coarse cell centres, per axis weight 3/4 on the
+// parent and 1/4 on the coarse neighbour on the child's side (that neighbour is
+// the parent itself at a domain face, the mirror image of zero flux).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_fmg_interp(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& f = L[jl.levels[jb]];
+        if (!S[f.grid].active) continue;
+        const LevelDesc& cL = L[f.coarse];
+        int i, j, k;
+        cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        if (i >= f.n[0] || j >= f.n[1]) continue;
+        const gptr<T> xc = as_global(Arr<T>::x(cL));
+        const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+        // the coarse neighbour on the child's side, clamped into the grid
+        const int I1 = min(max(I0 + ((i & 1) ? 1 : -1), 0), cL.n[0] - 1);
+        const int J1 = min(max(J0 + ((j & 1) ? 1 : -1), 0), cL.n[1] - 1);
+        const int K1 = (DIM == 3) ? min(max(K0 + ((k & 1) ? 1 : -1), 0), cL.n[2] - 1) : 0;
+        const long sy = cL.n[0], sz = (long)cL.n[0] * cL.n[1];
+        const T w0 = T(0.75), w1 = T(0.25);
+        auto row = [&](int jj, int kk) {
+            const long r = jj * sy + kk * sz;
+            return w0 * xc[I0 + r] + w1 * xc[I1 + r];
+        };
+        T v = w0 * row(J0, K0) + w1 * row(J1, K0);
+        if (DIM == 3) v = w0 * v + w1 * (w0 * row(J0, K1) + w1 * row(J1, K1));
+        as_global(Arr<T>::x(f))[i + (long)f.n[0] * (j + (long)f.n[1] * k)] = v;
     }
 }
 
@@ -1948,7 +2017,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
     }
 }
 
-template <int DIM>
+template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
     const XcdOrder order(jl.total);
@@ -1962,7 +2031,8 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
             int i, j, k;
             bool ok;
             const long idx = l0_cell<DIM>(d, t - jl.prefix[jb], m_, i, j, k, ok);
-            const double v = as_global(d.X)[idx] + (double)as_global(d.x32)[idx];
+            const double z = MIXED ? (double)as_global(d.x32)[idx] : as_global(d.x)[idx];
+            const double v = as_global(d.X)[idx] + z;
             if (ok) as_global(d.X)[idx] = v;
         }
     }
@@ -2151,12 +2221,12 @@ void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, dou
     hipLaunchKernelGGL(k_finalize, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, mode, rtol, max_cycles);
 }
 
-void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int nblk, hipStream_t s) {
+void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int galerkin, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_coarsen<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl);
-        else hipLaunchKernelGGL((k_coarsen<D, false>), dim3(g), dim3(kBlock), 0, s, L, jl);
+        if (mixed) hipLaunchKernelGGL((k_coarsen<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl, galerkin);
+        else hipLaunchKernelGGL((k_coarsen<D, false>), dim3(g), dim3(kBlock), 0, s, L, jl, galerkin);
     });
 }
 
@@ -2187,6 +2257,26 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_prolong<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+void launch_restrict_rhs(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                         int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_restrict_rhs<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_restrict_rhs<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
+}
+
+void launch_fmg_interp(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
+                       int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (fp32) hipLaunchKernelGGL((k_fmg_interp<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_fmg_interp<D, double>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
     });
 }
 
@@ -2342,11 +2432,14 @@ void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, Job
     FLD_CG_LAUNCH(k_cg_update);
 }
 
-void launch_correct(int dim, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
+void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for_xcd(jl.total, nblk);
-    FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_correct<D>), dim3(g), dim3(kBlock), 0, s, L, S, jl); });
+    FLD_DISPATCH_DIM(dim, {
+        if (mixed) hipLaunchKernelGGL((k_correct<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+        else hipLaunchKernelGGL((k_correct<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    });
 }
 
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,

@@ -77,6 +77,8 @@ int validate_opts(const fld_opts& o) {
     if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks || o.tile_depth || o.fused3_levels ||
                        o.tile_rows_coarse))
         return FLD_ERR_INVALID_ARG;
+    if (o.fmg != 0 && o.fmg != 1) return FLD_ERR_INVALID_ARG;
+    if (o.coarse_op != FLD_COARSE_REDISCRETISED && o.coarse_op != FLD_COARSE_GALERKIN) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
 
@@ -256,6 +258,19 @@ static void build_lists(Plan& p) {
         finish_list(D.l0_cell, p.levels, tiles_l0);
         finish_list(D.coarsest, p.levels, tiles_one);
         finish_list(D.tail, p.levels, tiles_one);
+        // (built only for plans that start each step with full multigrid)
+        const int nfrom = p.opts.fmg ? maxdepth : 0;
+        D.tail_from.assign(nfrom, HostList{});
+        D.coarsest_from.assign(nfrom, HostList{});
+        for (int dpt = 0; dpt < nfrom; ++dpt) {
+            for (int g = 0; g < p.ngrids(); ++g) {
+                if (p.grids[g].ndim != D.dim || wide(g) <= dpt) continue;
+                if (p.tail_lev[g] >= 0) D.tail_from[dpt].levels.push_back(p.level0[g] + p.tail_lev[g]);
+                else D.coarsest_from[dpt].levels.push_back(p.level0[g] + p.nlev[g] - 1);
+            }
+            finish_list(D.tail_from[dpt], p.levels, tiles_one);
+            finish_list(D.coarsest_from[dpt], p.levels, tiles_one);
+        }
         // one same-address atomic per tile is cheaper than a finalize launch only for a few tiles
         int max_tiles = 0;
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
@@ -364,6 +379,8 @@ static void layout(Plan& p) {
         for (auto& l : D.smooth) place_list(l);
         for (auto& l : D.restrict_) place_list(l);
         for (auto& l : D.prolong) place_list(l);
+        for (auto& l : D.tail_from) place_list(l);
+        for (auto& l : D.coarsest_from) place_list(l);
     }
     p.table_bytes = off;
     p.foff.assign(NL, Plan::FieldOff{});
@@ -434,7 +451,11 @@ static void layout(Plan& p) {
 // The multigrid part of one V-cycle of one dimension's grids (FP64 mode: on the
 // solution, or on the CG preconditioner's iterate; mixed: the FP32 correction
 // solve of the current residual).  Reads the solver state, never writes it.
-static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
+// d0 > 0 runs the V-cycle of the levels from depth d0 down (a full-multigrid
+// stage) over the grids with a level there, with the given tail / coarsest lists;
+// load0: the level at d0 starts from its stored iterate instead of zero.
+static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int load0, const JobList& tail,
+                            const JobList& coarsest) {
     const bool f32 = p.mixed;
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;   // level-0 V-cycle starts from the iterate
     const int dim = D.dim;
@@ -443,10 +464,10 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
     // even, so the level's result ends in x
     const int L3 = (D.fused3 && p.sweep3) ? D.levels3 : 0;
     const int nu1 = p.opts.nu1, nu2 = p.opts.nu2, fz = p.tile_depth;
-    for (int d = 0; d < D.maxdepth; ++d) {
+    for (int d = d0; d < D.maxdepth; ++d) {
         if (d < L3) {
             for (int k = 1; k <= nu1; ++k) {
-                const bool load = k > 1 || (d == 0 && plain64);
+                const bool load = k > 1 || (d == d0 && load0);
                 const bool restr = k == nu1;
                 const int mode = restr ? (load ? 2 : 3) : (load ? 0 : 1);
                 launch_sweep3(f32, p.dL, p.dS, restr ? D.sr3[d].dev : D.sw3[d].dev, mode, 0, k % 2 == 0, fz,
@@ -455,7 +476,7 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
             continue;
         }
         if (D.fused) {
-            launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == 0 ? plain64 : 0, p.tile_wide,
+            launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == d0 ? load0 : 0, p.tile_wide,
                          d == 0 ? p.tile_rows : p.tile_rows_c, p.nblk, s);
             continue;
         }
@@ -465,9 +486,9 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
         }
         launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     }
-    launch_tail(dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
-    launch_coarse_solve(dim, f32, p.dL, p.dS, D.coarsest.dev, s);
-    for (int d = D.maxdepth - 1; d >= 0; --d) {
+    launch_tail(dim, f32, p.dL, p.dS, tail, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_coarse_solve(dim, f32, p.dL, p.dS, coarsest, s);
+    for (int d = D.maxdepth - 1; d >= d0; --d) {
         if (d < L3) {
             for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
                 launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, fz, p.nblk, s);
@@ -483,6 +504,45 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
         }
+    }
+}
+
+static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
+    const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
+    enqueue_mg_from(p, D, s, 0, plain64, D.tail.dev, D.coarsest.dev);
+}
+
+// Full-multigrid cycle on the V-cycle's level-0 arrays (Sec. 3.4 starts each solve
+// with one): the right-hand side averaged down to every grid's deepest wide level,
+// the tail V-cycle / coarsest solve there from zero, then per depth, coarse to
+// fine, the interpolated coarser solution as the start of one V-cycle of that
+// depth's levels.
+static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
+    const bool f32 = p.mixed;
+    for (int d = 0; d < D.maxdepth; ++d) launch_restrict_rhs(D.dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
+    const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
+    launch_tail(D.dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
+    for (int d = D.maxdepth - 1; d >= 0; --d) {
+        launch_fmg_interp(D.dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
+        enqueue_mg_from(p, D, s, d, 1, D.tail_from[d].dev, D.coarsest_from[d].dev);
+    }
+}
+
+// The first outer iteration of a step with the full-multigrid start: the FMG cycle
+// in place of the V-cycle, then the FP64 update and residual.  Under CG the result
+// corrects the iterate and CG restarts from its true residual.
+static void enqueue_fmg_cycle(Plan& p, hipStream_t s) {
+    for (auto& D : p.dl) {
+        if (D.l0_cell.empty()) continue;
+        enqueue_fmg(p, D, s);
+        const JobList& l0 = D.l0_cell.dev;
+        const bool corr = p.krylov || p.mixed;
+        if (corr) launch_correct(D.dim, p.mixed, p.dL, p.dS, l0, cell_blocks(p), s);
+        const int fin = p.krylov ? FIN_R_FMG : FIN_R_CYCLE;
+        launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, corr ? 1 : 0, D.fin_fused ? fin : -1, p.opts.rtol,
+                        p.opts.max_cycles, cell_blocks(p), s);
+        if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, fin, p.opts.rtol, p.opts.max_cycles, s);
     }
 }
 
@@ -510,7 +570,7 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_CG, rt, mc, s);
         } else {
-            if (p.mixed) launch_correct(dim, p.dL, p.dS, l0, cell_blocks(p), s);
+            if (p.mixed) launch_correct(dim, true, p.dL, p.dS, l0, cell_blocks(p), s);
             launch_residual(dim, p.mixed, p.dL, p.dS, l0, 0, p.mixed ? 1 : 0, D.fin_fused ? FIN_R_CYCLE : -1,
                             p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
             if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_CYCLE, p.opts.rtol, p.opts.max_cycles, s);
@@ -521,6 +581,8 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
 static int capture_graph(Plan& p) {
     if (p.graph_exec) { (void)hipGraphExecDestroy(p.graph_exec); p.graph_exec = nullptr; }
     if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
+    if (p.fmg_graph_exec) { (void)hipGraphExecDestroy(p.fmg_graph_exec); p.fmg_graph_exec = nullptr; }
+    if (p.fmg_graph) { (void)hipGraphDestroy(p.fmg_graph); p.fmg_graph = nullptr; }
     if (!p.cap_stream) FLD_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
     FLD_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
     enqueue_cycle(p, p.cap_stream);
@@ -528,6 +590,14 @@ static int capture_graph(Plan& p) {
     FLD_HIP(hipStreamEndCapture(p.cap_stream, &g));
     p.graph = g;
     FLD_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+    if (p.opts.fmg) {
+        FLD_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_fmg_cycle(p, p.cap_stream);
+        hipGraph_t f = nullptr;
+        FLD_HIP(hipStreamEndCapture(p.cap_stream, &f));
+        p.fmg_graph = f;
+        FLD_HIP(hipGraphInstantiate(&p.fmg_graph_exec, p.fmg_graph, nullptr, nullptr, 0));
+    }
     return FLD_OK;
 }
 
@@ -639,6 +709,8 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
         for (auto& l : D.smooth) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.restrict_) if ((rc = upload(l)) != FLD_OK) return rc;
         for (auto& l : D.prolong) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.tail_from) if ((rc = upload(l)) != FLD_OK) return rc;
+        for (auto& l : D.coarsest_from) if ((rc = upload(l)) != FLD_OK) return rc;
     }
     if (!p.hIO) FLD_HIP(hipHostMalloc((void**)&p.hIO, p.ngrids() * sizeof(StepIO), hipHostMallocDefault));
     if (!p.hCtrl) FLD_HIP(hipHostMalloc((void**)&p.hCtrl, sizeof(Control), hipHostMallocDefault));
@@ -672,7 +744,8 @@ int plan_prologue(Plan& p, hipStream_t s) {
         launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, D.fin_fused ? FIN_B : -1,
                      p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
-        for (auto& c : D.coarsen) launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
+        for (auto& c : D.coarsen)
+            launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.opts.coarse_op == FLD_COARSE_GALERKIN, p.nblk, s);
         launch_residual(D.dim, p.mixed, p.dL, p.dS, l0, 0, zero_x, D.fin_fused ? FIN_R_INIT : -1, p.opts.rtol,
                         p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_R_INIT, p.opts.rtol, p.opts.max_cycles, s);
@@ -736,7 +809,13 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
     // many grids are still active.  The first burst is sized from the previous
     // step's cycle count so a typical step needs one or two host round trips.
     int done = 0;
-    int burst = std::max(1, std::min(p.last_cycles > 0 ? p.last_cycles : 4, p.opts.max_cycles));
+    if (p.opts.fmg) {
+        if (p.fmg_graph_exec) FLD_HIP(hipGraphLaunch(p.fmg_graph_exec, s));
+        else enqueue_fmg_cycle(p, s);
+        FLD_HIP(hipGetLastError());
+        done = 1;
+    }
+    int burst = std::max(1, std::min(p.last_cycles > 0 ? p.last_cycles - done : 4, p.opts.max_cycles - done));
     while (done < p.opts.max_cycles) {
         const int nrun = std::min(burst, p.opts.max_cycles - done);
         for (int r = 0; r < nrun; ++r) {
@@ -1130,6 +1209,8 @@ void fld_opts_default(fld_opts* o) {
     o->autotune = 0;
     o->krylov = 1;
     o->fused = 1;
+    o->fmg = 0;
+    o->coarse_op = FLD_COARSE_REDISCRETISED;
 }
 
 void fld_gas_default(fld_gas* g) {
@@ -1241,7 +1322,8 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
                               D.fin_fused ? fld::FIN_B : -1, p.opts.rtol, p.opts.max_cycles, fld::cell_blocks(p), s);
             if (!D.fin_fused)
                 fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
-            for (auto& c : D.coarsen) fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.nblk, s);
+            for (auto& c : D.coarsen)
+                fld::launch_coarsen(D.dim, p.mixed, p.dL, c.dev, p.opts.coarse_op == FLD_COARSE_GALERKIN, p.nblk, s);
         }
         FLD_HIP(hipGetLastError());
         FLD_HIP(hipStreamSynchronize(s));            // staging buffer free on return

@@ -1,0 +1,127 @@
+"""GPU parity of the multigrid options (Sec. 3.4): the coarse face weights of every
+level against the oracle's rediscretised and Galerkin rules, and full steps with the
+full-multigrid start and / or Galerkin coarse operators against the oracle's solve.
+
+Tolerances: a coarse weight is a positive sum of fine weights times a power of two,
+so against the oracle's rule applied to the device's own finer level it agrees to a
+few ulp (1e-14 relative); against the oracle's own level 0 it carries the level-0
+face tolerance.  Steps: 1e-10 relative L2, as every step test (the run stops at
+rtol = 1e-10 / q_b)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as O                     # noqa: E402
+import workloads as W                  # noqa: E402
+import paper_2104_03968_amd as fld     # noqa: E402
+from tests.gpu_common import dev, rel_l2, run_step   # noqa: E402
+from tests.test_gpu_parity import face_tolerance     # noqa: E402
+
+RULES = {"rediscretised": O.coarse_weights_rediscretised, "galerkin": O.coarse_weights_galerkin}
+
+
+@pytest.mark.parametrize("coarse_op", ["rediscretised", "galerkin"])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", [(96, 128), (16, 24, 20), (64, 64)])
+def test_coarse_weights_every_level(shape, precision, coarse_op):
+    g = W.pulse_2d() if shape == (64, 64) else W.random_grid(shape, 91000 + sum(shape), dt=4e-3)
+    plan = fld.Plan([g.E.shape], h=[g.h], precision=precision, coarse_op=coarse_op, c=g.c)
+    plan.coefficients([dev(g.E)], [dev(g.kappa_rho)], [g.dt])
+    torch.cuda.synchronize()
+    rule = RULES[coarse_op]
+    nl = plan.levels(0)
+    assert nl >= 3
+    prev = [w.cpu().numpy() for w in plan.level_tensors(0, 0)["w"]]
+    # level 1 against the oracle's own level 0
+    w_or = O.face_weights(O.diffusion_coefficient(g.E, g.kappa_rho, g.h, g.c), g.dt, g.h)
+    tol0 = max(float(t.max()) for t in face_tolerance(g)) + 1e-14
+    lv1 = plan.level_tensors(0, 1)
+    for d, (wg, wo) in enumerate(zip(lv1["w"], rule(w_or))):
+        wg = wg.cpu().numpy()
+        assert np.all((wg == 0) == (wo == 0))
+        err = np.abs(wg - wo) / np.where(wo == 0, 1.0, np.abs(wo))
+        assert err.max() <= tol0, (d, err.max())
+    # every level against the rule applied to the device's finer level
+    for lev in range(1, nl):
+        lv = plan.level_tensors(0, lev)
+        want = rule(prev)
+        got = [w.cpu().numpy() for w in lv["w"]]
+        for d in range(g.E.ndim):
+            err = np.abs(got[d] - want[d]) / np.where(want[d] == 0, 1.0, np.abs(want[d]))
+            assert err.max() <= 1e-14, (lev, d, err.max())
+            if precision == 1:
+                assert np.array_equal(lv["w32"][d].cpu().numpy(), got[d].astype(np.float32))
+        prev = got
+    plan.close()
+
+
+def _batch():
+    return [W.random_grid((96, 128), 92001, dt=5e-3), W.pulse_2d(),
+            W.random_grid((130, 96), 92002, dt=2e-3), W.random_grid((16, 24, 20), 92003, dt=3e-3),
+            W.random_grid((17, 20, 23), 92004, dt=2e-3)]
+
+
+@pytest.mark.parametrize("fmg,coarse_op", [(1, "rediscretised"), (0, "galerkin"), (1, "galerkin")])
+@pytest.mark.parametrize("precision,krylov", [(0, 1), (0, 0), (1, 1), (1, 0)])
+def test_steps_match_oracle(fmg, coarse_op, precision, krylov):
+    grids = _batch()
+    rtol = min(1e-10 / O.q_b(g.E) for g in grids)
+    xs, stats, rc = run_step(grids, precision=precision, rtol=rtol, krylov=krylov, fmg=fmg,
+                             coarse_op=coarse_op, max_cycles=200)
+    assert rc == 0, stats
+    for g, x, st in zip(grids, xs, stats):
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="direct")
+        assert st["status"] == 0 and st["cycles"] >= 1
+        assert st["rel_residual"] <= rtol
+        assert rel_l2(x, x_or) <= 1e-10, (g.E.shape, rel_l2(x, x_or), st)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fmg_batched_equals_alone(precision):
+    grids = _batch()
+    xs, _, rc = run_step(grids, precision=precision, fmg=1)
+    assert rc == 0
+    for i in (0, 3):
+        (x1,), _, rc1 = run_step([grids[i]], precision=precision, fmg=1)
+        assert rc1 == 0
+        assert np.array_equal(x1, xs[i])
+
+
+@pytest.mark.parametrize("shape,seed", [((256, 256), 93001), ((48, 64, 40), 93002)])
+@pytest.mark.parametrize("precision,krylov", [(0, 1), (0, 0), (1, 0)])
+def test_fmg_cycle_beats_a_v_cycle(shape, seed, precision, krylov):
+    """One outer iteration: the full-multigrid cycle leaves a smaller residual than the
+    V-cycle iteration it replaces (both stop after one cycle)."""
+    g = W.random_grid(shape, seed, dt=1e-2)
+    res = {}
+    for fmg in (0, 1):
+        _, (st,), rc = run_step([g], precision=precision, krylov=krylov, fmg=fmg, max_cycles=1)
+        assert st["cycles"] == 1
+        res[fmg] = st["rel_residual"]
+    print(shape, precision, krylov, res)
+    assert res[1] < res[0]
+
+
+def test_fmg_with_fixed_gradient_boundaries():
+    g = W.random_grid((64, 96), 94001, dt=3e-3)
+    G = [0.5, -0.25, 0.0, 1.0, 0.0, 0.0]
+    rtol = 1e-10 / O.q_b(g.E)
+    x_or, info = O.diffusion_step_bc(g.E, g.kappa_rho, g.dt, g.h, grad_bc=G, c=g.c, method="direct")
+    for fmg in (0, 1):
+        (x,), (st,), rc = run_step([g], rtol=rtol, fmg=fmg, bc=[1, 1, 0, 1, 0, 0], bc_grad=G)
+        assert rc == 0
+        assert rel_l2(x, x_or) <= 1e-10
+
+
+def test_converged_start_takes_no_cycles():
+    """A uniform field is its own solution: the initial residual already meets the
+    target, so the step reports zero cycles with or without the start."""
+    E = np.full((64, 64), 3.0)
+    g = W.GridInput(E=E, kappa_rho=np.full(E.shape, 5.0), dt=1e-3, h=(1 / 64, 1 / 64), c=1.0)
+    for fmg in (0, 1):
+        (x,), (st,), rc = run_step([g], fmg=fmg)
+        assert rc == 0 and st["cycles"] == 0
+        assert np.array_equal(x, E)
