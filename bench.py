@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--profile-reps", type=int, default=200)
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="launch shape: 0 defaults, 1 autotuner (cached), 2 re-time")
-    ap.add_argument("--fmg", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--fmg", type=int, default=1, choices=[0, 1],
                     help="1: each step starts with a full-multigrid cycle")
+    ap.add_argument("--fmg-depths", type=int, default=None,
+                    help="full-multigrid start: V-cycles on the finest k levels only (0 = all; "
+                         "default: the library's)")
     ap.add_argument("--coarse-op", default="rediscretised", choices=["rediscretised", "galerkin"],
                     help="coarse-level operator of the multigrid hierarchy")
     return ap.parse_args()
@@ -284,7 +287,7 @@ def main():
     elif cfg == "c3":
         grids = [W.c3_inputs(256)]
         workload = ("3D 256^3 FLD step, the 2D 1024^2 field recipe in 3D, dt=1e-3, rtol=1e-10, "
-                    f"{prec} (FP32 V-cycles in FP64 defect correction)" )
+                    + ("mixed (FP32 V-cycles in FP64 defect correction)" if prec == "mixed" else "fp64"))
     else:
         lay = W.c4_layout()
         grids = [W.c4_grid(j, n, dt) for j, (n, dt) in enumerate(lay)]
@@ -292,7 +295,8 @@ def main():
     ncells = sum(g.E.size for g in grids)
     shapes = [g.E.shape for g in grids]
     plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c,
-                    autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op)
+                    autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
+                    **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
     tuning = plan.tuning()
     log(f"bench: launch shape {tuning}")
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -361,7 +365,7 @@ def main():
         "dtype": "f64" if precision == fld.FLD_PREC_FP64 else "f32-in-f64",
         "data": "synthetic",
         "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
-                   "rtol": 1e-10, "fmg": args.fmg, "coarse_op": args.coarse_op,
+                   "rtol": 1e-10, "fmg": plan.opts.fmg, "fmg_depths": plan.opts.fmg_depths, "coarse_op": args.coarse_op,
                    "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
                                                      "fused3_levels", "tile_rows_coarse", "source")}},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},

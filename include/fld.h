@@ -148,8 +148,12 @@ typedef struct fld_opts {
                              precision it solves for the correction of the initial
                              residual and CG restarts from the corrected iterate;
                              with plain FP64 V-cycles it replaces E^n as the start.
-                             It counts as one cycle in fld_stats [0]              */
+                             It counts as one cycle in fld_stats.  Request servers
+                             iterate V-cycles only [1]                            */
     int32_t coarse_op;    /* FLD_COARSE_* [REDISCRETISED]                          */
+    int32_t fmg_depths;   /* with fmg: only the finest fmg_depths levels run the V-cycle
+                             of their full-multigrid stage; coarser ones pass the
+                             interpolated solution on as it is (0 = every level) [2] */
 } fld_opts;
 
 /* Per-grid result of fld_step. */

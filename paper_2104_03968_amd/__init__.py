@@ -82,7 +82,8 @@ class fld_opts(C.Structure):
                 ("autotune", C.c_int32), ("krylov", C.c_int32), ("fused", C.c_int32),
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
                 ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6),
-                ("tile_rows_coarse", C.c_int32), ("fmg", C.c_int32), ("coarse_op", C.c_int32)]
+                ("tile_rows_coarse", C.c_int32), ("fmg", C.c_int32), ("coarse_op", C.c_int32),
+                ("fmg_depths", C.c_int32)]
 
 
 class fld_tuning(C.Structure):

@@ -78,6 +78,7 @@ int validate_opts(const fld_opts& o) {
                        o.tile_rows_coarse))
         return FLD_ERR_INVALID_ARG;
     if (o.fmg != 0 && o.fmg != 1) return FLD_ERR_INVALID_ARG;
+    if (o.fmg_depths < 0 || o.fmg_depths > 64) return FLD_ERR_INVALID_ARG;
     if (o.coarse_op != FLD_COARSE_REDISCRETISED && o.coarse_op != FLD_COARSE_GALERKIN) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
@@ -523,9 +524,10 @@ static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
     launch_tail(D.dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
     launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
+    const int nv = p.opts.fmg_depths > 0 ? p.opts.fmg_depths : D.maxdepth;
     for (int d = D.maxdepth - 1; d >= 0; --d) {
         launch_fmg_interp(D.dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
-        enqueue_mg_from(p, D, s, d, 1, D.tail_from[d].dev, D.coarsest_from[d].dev);
+        if (d < nv) enqueue_mg_from(p, D, s, d, 1, D.tail_from[d].dev, D.coarsest_from[d].dev);
     }
 }
 
@@ -1209,7 +1211,8 @@ void fld_opts_default(fld_opts* o) {
     o->autotune = 0;
     o->krylov = 1;
     o->fused = 1;
-    o->fmg = 0;
+    o->fmg = 1;
+    o->fmg_depths = 2;
     o->coarse_op = FLD_COARSE_REDISCRETISED;
 }
 

@@ -417,6 +417,7 @@ int32_t fld_server_create(const fld_server_opts* o, void* arena_dev, size_t aren
         s.opts.rtol = o->rtol;
         s.opts.max_cycles = o->max_cycles;
         s.opts.use_graph = 0;
+        s.opts.fmg = 0;                       // requests advance by rounds of V-cycles
         int rc = fld::validate_opts(s.opts);
         if (rc != FLD_OK) return rc;
         if (hipGetDevice(&s.device) != hipSuccess) return FLD_ERR_HIP;

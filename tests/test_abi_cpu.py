@@ -38,7 +38,7 @@ def test_defaults():
     o = fld.fld_opts_default()
     assert o.c == 1.0 and o.rtol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.max_cycles == 50
     assert o.limiter == fld.FLD_LIMITER_LP and o.precision == fld.FLD_PREC_FP64
-    assert o.fmg == 0 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
+    assert o.fmg == 1 and o.fmg_depths == 2 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
     assert fld.fld_opts_default(coarse_op="galerkin").coarse_op == fld.FLD_COARSE_GALERKIN
     g = fld.fld_gas_default()
     assert g.max_halley == 100 and g.root_rtol == pytest.approx(8.88e-16, rel=1e-2)
@@ -63,7 +63,8 @@ def test_plan_create_validates_grids(n, ok):
     (dict(precision=3), -1), (dict(max_cycles=0), -1), (dict(nu1=0, nu2=0), -1),
     (dict(bc=[2, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
     (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1),
-    (dict(fmg=2), -1), (dict(fmg=-1), -1), (dict(coarse_op=2), -1), (dict(coarse_op=-1), -1)])
+    (dict(fmg=2), -1), (dict(fmg=-1), -1), (dict(coarse_op=2), -1), (dict(coarse_op=-1), -1),
+    (dict(fmg_depths=-1), -1), (dict(fmg_depths=65), -1)])
 def test_plan_create_validates_options(kw, code):
     with pytest.raises(fld.FLDError) as e:
         fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(**kw))
@@ -260,11 +261,11 @@ def test_fmg_and_galerkin_plans():
     Galerkin coarse operator changes no layout."""
     grids = [fld.make_grid((64, 96)), fld.make_grid((16, 24, 20)), fld.make_grid((37, 50))]
     sizes = {}
-    for kw in (dict(), dict(fmg=1), dict(coarse_op="galerkin"), dict(fmg=1, precision=1, krylov=0)):
+    for kw in (dict(fmg=0), dict(fmg=1), dict(fmg=0, coarse_op="galerkin"), dict(fmg=1, precision=1, krylov=0)):
         h = fld.fld_plan_create(grids, fld.fld_opts_default(**kw))
         sizes[tuple(sorted(kw.items()))] = fld.fld_plan_workspace_bytes(h)
         assert [fld.fld_plan_levels(h, i) for i in range(3)] == [6, 3, 1]
         fld.fld_plan_destroy(h)
-    base = sizes[()]
-    assert sizes[(("coarse_op", "galerkin"),)] == base
+    base = sizes[(("fmg", 0),)]
+    assert sizes[(("coarse_op", "galerkin"), ("fmg", 0))] == base
     assert 0 <= sizes[(("fmg", 1),)] - base <= 64 * 1024

@@ -64,7 +64,8 @@ def _batch():
             W.random_grid((17, 20, 23), 92004, dt=2e-3)]
 
 
-@pytest.mark.parametrize("fmg,coarse_op", [(1, "rediscretised"), (0, "galerkin"), (1, "galerkin")])
+@pytest.mark.parametrize("fmg,coarse_op", [(0, "rediscretised"), (1, "rediscretised"), (0, "galerkin"),
+                                           (1, "galerkin")])
 @pytest.mark.parametrize("precision,krylov", [(0, 1), (0, 0), (1, 1), (1, 0)])
 def test_steps_match_oracle(fmg, coarse_op, precision, krylov):
     grids = _batch()
@@ -90,15 +91,17 @@ def test_fmg_batched_equals_alone(precision):
         assert np.array_equal(x1, xs[i])
 
 
+@pytest.mark.parametrize("depths", [0, 2])
 @pytest.mark.parametrize("shape,seed", [((256, 256), 93001), ((48, 64, 40), 93002)])
 @pytest.mark.parametrize("precision,krylov", [(0, 1), (0, 0), (1, 0)])
-def test_fmg_cycle_beats_a_v_cycle(shape, seed, precision, krylov):
+def test_fmg_cycle_beats_a_v_cycle(shape, seed, precision, krylov, depths):
     """One outer iteration: the full-multigrid cycle leaves a smaller residual than the
     V-cycle iteration it replaces (both stop after one cycle)."""
     g = W.random_grid(shape, seed, dt=1e-2)
     res = {}
     for fmg in (0, 1):
-        _, (st,), rc = run_step([g], precision=precision, krylov=krylov, fmg=fmg, max_cycles=1)
+        _, (st,), rc = run_step([g], precision=precision, krylov=krylov, fmg=fmg, fmg_depths=depths,
+                                max_cycles=1)
         assert st["cycles"] == 1
         res[fmg] = st["rel_residual"]
     print(shape, precision, krylov, res)
@@ -125,3 +128,15 @@ def test_converged_start_takes_no_cycles():
         (x,), (st,), rc = run_step([g], fmg=fmg)
         assert rc == 0 and st["cycles"] == 0
         assert np.array_equal(x, E)
+
+
+@pytest.mark.parametrize("depths", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision,krylov", [(0, 1), (1, 0), (0, 0)])
+def test_fmg_depths_match_oracle(depths, precision, krylov):
+    grids = _batch()
+    rtol = min(1e-10 / O.q_b(g.E) for g in grids)
+    xs, stats, rc = run_step(grids, precision=precision, rtol=rtol, krylov=krylov, fmg=1, fmg_depths=depths)
+    assert rc == 0, stats
+    for g, x in zip(grids, xs):
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="direct")
+        assert rel_l2(x, x_or) <= 1e-10

@@ -124,14 +124,21 @@ def test_face_weights_full_size_config2():
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("krylov", [1, 0])
 @pytest.mark.parametrize("nu", [1, 2, 3, 4])
-def test_config1_step_matches_lu(precision, krylov, nu):
+@pytest.mark.parametrize("fmg", [1, 0])
+def test_config1_step_matches_lu(precision, krylov, nu, fmg):
     g = W.pulse_2d()
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="lu")
-    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, nu1=nu, nu2=nu)
+    (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, nu1=nu, nu2=nu,
+                               fmg=fmg)
     assert rc == 0 and st["status"] == 0, st
     assert rel_l2(x, x_or) <= 1e-10, (rel_l2(x, x_or), st)
     assert st["q_b"] == pytest.approx(O.q_b(g.E), rel=1e-12)
-    assert abs(x.sum() - g.E.sum()) / g.E.sum() < 1e-12
+    # zero flux: 1^T A = 1^T, so sum x - sum b = -sum r, and |sum r| <= ||r||_1 <= sqrt(N) ||r||_2
+    dsum = abs(x.sum() - g.E.sum())
+    assert dsum <= np.sqrt(g.E.size) * st["rel_residual"] * np.linalg.norm(g.E) + 1e-13 * g.E.sum()
+    if not fmg:
+        # from the start E^n (sum b exactly) the V-cycles keep the mean far tighter
+        assert dsum / g.E.sum() < 1e-12
 
 
 @pytest.mark.parametrize("shape,dt", [((37, 100), 5e-3), ((96, 96), 1e-2), ((3, 5), 1e-2), ((2, 2), 1e-1),
