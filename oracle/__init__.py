@@ -29,3 +29,7 @@ from .multigrid import *  # noqa: F401,F403,E402
 from . import multigrid as _multigrid  # noqa: E402
 
 __all__ = list(__all__) + list(_multigrid.__all__)
+from .dirichlet import *  # noqa: F401,F403,E402
+from . import dirichlet as _dirichlet  # noqa: E402
+
+__all__ = list(__all__) + list(_dirichlet.__all__)

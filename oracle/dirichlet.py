@@ -1,0 +1,147 @@
+"""Plain FP64 oracle of the FLD step with Dirichlet boundaries (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
+leg may use this module.  It shares no code with the HIP path.
+
+Sec. 3.4 lets a boundary define E^{n+1} in the ghost cells (Dirichlet conditions)
+beside the Neumann (fixed-gradient) ones.  Readings, per face with ghost value E_B:
+
+* both ghost layers hold E_B; the 4th-order gradient of Sec. 3.2 (and so R,
+  lambda and D of the cells next to the face) uses them;
+* the ghost couples to the boundary cell like an interior neighbour over the
+  centre distance h, with the boundary cell's own lagged D (the ghost carries no
+  opacity, so there is no harmonic mean to take): the cell's row of eq. discdiff
+  (times dt) gains alpha = dt D / h^2 on the diagonal and alpha E_B on the
+  right-hand side.  The operator stays symmetric positive definite with
+  lambda_min >= 1; energy now leaves or enters through the face.
+
+Faces are listed x-, x+, y-, y+, z-, z+.  ``kind`` per face is "zero_flux",
+"gradient" (the fixed-gradient faces of ``oracle.bc``) or "dirichlet"; ``value``
+per face is the prescribed gradient or ghost value.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import fld as _fld
+
+__all__ = ["pad_general", "gradient4_general", "dirichlet_diagonal", "boundary_rhs",
+           "diffusion_step_general"]
+
+KINDS = ("zero_flux", "gradient", "dirichlet")
+
+
+def _faces(kind, value, nd):
+    k = ["zero_flux"] * 6
+    v = [0.0] * 6
+    for f in range(2 * nd):
+        if kind is not None and kind[f] is not None:
+            if kind[f] not in KINDS:
+                raise ValueError(f"unknown boundary kind {kind[f]!r}")
+            k[f] = kind[f]
+        if value is not None and value[f] is not None:
+            v[f] = float(value[f])
+    return k, v
+
+
+def pad_general(E: np.ndarray, d: int, h: float, kind_lo: str, val_lo: float, kind_hi: str,
+                val_hi: float) -> np.ndarray:
+    """E with two ghost layers along dimension d (x = 0): mirror image for zero flux, mirror
+    plus the linear part of slope G for a fixed gradient, E_B in both layers for Dirichlet."""
+    nd = E.ndim
+    a = _fld._axis(nd, d)
+    M = np.moveaxis(E, a, 0)
+
+    def ghosts(edge0, edge1, kind, val, sign):
+        if kind == "dirichlet":
+            return [np.full_like(edge0, val), np.full_like(edge0, val)]
+        g = val if kind == "gradient" else 0.0
+        # [inner ghost, outer ghost]: E_{-1} = E_0 -/+ h G, E_{-2} = E_1 -/+ 3 h G
+        return [edge0 + sign * h * g, edge1 + sign * 3.0 * h * g]
+
+    lo = ghosts(M[0], M[1], kind_lo, val_lo, -1.0)
+    hi = ghosts(M[-1], M[-2], kind_hi, val_hi, 1.0)
+    P = np.concatenate([np.stack([lo[1], lo[0]]), M, np.stack([hi[0], hi[1]])], axis=0)
+    return np.moveaxis(P, 0, a)
+
+
+def gradient4_general(E: np.ndarray, h: Sequence[float], kind=None, value=None) -> List[np.ndarray]:
+    """The 4th-order central gradient (Sec. 3.2) over the ghosts of ``pad_general``."""
+    nd = E.ndim
+    k, v = _faces(kind, value, nd)
+    out = []
+    for d in range(nd):
+        a = _fld._axis(nd, d)
+        P = pad_general(E, d, h[d], k[2 * d], v[2 * d], k[2 * d + 1], v[2 * d + 1])
+        n = E.shape[a]
+
+        def sh(q):
+            sl = [slice(None)] * nd
+            sl[a] = slice(2 + q, 2 + q + n)
+            return P[tuple(sl)]
+        out.append(((sh(-2) - sh(2)) + 8.0 * (sh(1) - sh(-1))) / (12.0 * h[d]))
+    return out
+
+
+def _boundary_slices(shape, d):
+    nd = len(shape)
+    a = _fld._axis(nd, d)
+    lo = [slice(None)] * nd
+    hi = [slice(None)] * nd
+    lo[a] = 0
+    hi[a] = shape[a] - 1
+    return tuple(lo), tuple(hi)
+
+
+def dirichlet_diagonal(D: np.ndarray, dt: float, h: Sequence[float], kind=None) -> np.ndarray:
+    """alpha per cell: dt D / h_d^2 for each Dirichlet face of the cell."""
+    nd = D.ndim
+    k, _ = _faces(kind, None, nd)
+    alpha = np.zeros_like(D)
+    for d in range(nd):
+        lo, hi = _boundary_slices(D.shape, d)
+        if k[2 * d] == "dirichlet":
+            alpha[lo] += dt * D[lo] / (h[d] * h[d])
+        if k[2 * d + 1] == "dirichlet":
+            alpha[hi] += dt * D[hi] / (h[d] * h[d])
+    return alpha
+
+
+def boundary_rhs(D: np.ndarray, dt: float, h: Sequence[float], kind=None, value=None) -> np.ndarray:
+    """What the faces add to b = E^n: alpha E_B on Dirichlet faces, dt/h times the flux
+    -D G (below) or D G (above) through fixed-gradient faces."""
+    nd = D.ndim
+    k, v = _faces(kind, value, nd)
+    s = np.zeros_like(D)
+    for d in range(nd):
+        for side, sl in enumerate(_boundary_slices(D.shape, d)):
+            f = 2 * d + side
+            if k[f] == "dirichlet":
+                s[sl] += dt * D[sl] / (h[d] * h[d]) * v[f]
+            elif k[f] == "gradient":
+                s[sl] += dt / h[d] * (D[sl] * v[f] if side else -D[sl] * v[f])
+    return s
+
+
+def diffusion_step_general(E: np.ndarray, kappa_rho: np.ndarray, dt: float, h: Sequence[float],
+                           kind: Optional[Sequence] = None, value: Optional[Sequence] = None,
+                           c: float = 1.0, limiter: str = "lp", method: str = "auto", tol=None):
+    """One backward-Euler FLD step (Sec. 3.4) with per-face zero-flux, fixed-gradient or
+    Dirichlet boundaries.  ``info.extra`` holds b and alpha."""
+    E = np.asarray(E, dtype=np.float64)
+    kr = np.asarray(kappa_rho, dtype=np.float64)
+    gr = gradient4_general(E, h, kind, value)
+    R = np.sqrt(sum(x * x for x in gr)) / (kr * E)
+    D = c * _fld.flux_limiter(R, limiter) / kr
+    w = _fld.face_weights(D, dt, h)
+    alpha = dirichlet_diagonal(D, dt, h, kind)
+    A = (_fld.assemble_operator(w) + sp.diags(alpha.ravel())).tocsr()
+    b = E + boundary_rhs(D, dt, h, kind, value)
+    x, info = _fld.solve(A, b, method=method, tol=tol, w=w)
+    info.extra["b"] = b
+    info.extra["alpha"] = alpha
+    info.extra["A"] = A
+    return x, info
