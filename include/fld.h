@@ -69,6 +69,14 @@ extern "C" {
                                         eq. fld_lambda approximates to ~7 %                  */
 
 #define FLD_BC_ZERO_FLUX        0    /* Neumann, zero gradient (Sec. 3.4)      */
+#define FLD_BC_DIRICHLET        2    /* the ghost cells hold E_B = bc_value (Sec. 3.4):
+                                        both ghost layers for the 4th-order gradient;
+                                        the ghost couples to the boundary cell over one
+                                        cell width with the cell's own D, adding
+                                        dt D / h^2 to the diagonal and that times E_B
+                                        to the right-hand side.  Plans with Dirichlet
+                                        faces run one kernel per colour sweep (no
+                                        fused level kernels)                        */
 #define FLD_BC_FIXED_GRADIENT   1    /* Neumann with the gradient dE/dx_a given in
                                         bc_grad (Sec. 3.4): ghosts continue the mirror
                                         image with that slope, E_{-k} = E_{k-1} -
@@ -154,6 +162,8 @@ typedef struct fld_opts {
     int32_t fmg_depths;   /* with fmg: only the finest fmg_depths levels run the V-cycle
                              of their full-multigrid stage; coarser ones pass the
                              interpolated solution on as it is (0 = every level) [2] */
+    double  bc_value[6];  /* per face: the ghost value E_B of FLD_BC_DIRICHLET faces,
+                             finite and >= 0 (ignored elsewhere) [0]                 */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -193,6 +203,8 @@ typedef struct fld_level_view {
     float*  x32;
     float*  b32;
     float*  w32[3];
+    double* ad;           /* plans with Dirichlet faces: the extra diagonal dt D / h^2
+                             of the ghost couplings (FP64), else NULL               */
 } fld_level_view;
 
 /* Library version, major*10000 + minor*100 + patch. */

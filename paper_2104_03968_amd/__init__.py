@@ -53,6 +53,7 @@ FLD_IMEX_MIDPOINT = 1
 IMEX_SCHEMES = {"euler": FLD_IMEX_EULER, "midpoint": FLD_IMEX_MIDPOINT}
 FLD_BC_ZERO_FLUX = 0
 FLD_BC_FIXED_GRADIENT = 1
+FLD_BC_DIRICHLET = 2
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
 FLD_COARSE_REDISCRETISED = 0
@@ -83,7 +84,7 @@ class fld_opts(C.Structure):
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
                 ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6),
                 ("tile_rows_coarse", C.c_int32), ("fmg", C.c_int32), ("coarse_op", C.c_int32),
-                ("fmg_depths", C.c_int32)]
+                ("fmg_depths", C.c_int32), ("bc_value", C.c_double * 6)]
 
 
 class fld_tuning(C.Structure):
@@ -117,7 +118,7 @@ class fld_gas(C.Structure):
 class fld_level_view(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("x", C.c_void_p), ("b", C.c_void_p),
                 ("w", C.c_void_p * 3), ("x32", C.c_void_p), ("b32", C.c_void_p),
-                ("w32", C.c_void_p * 3)]
+                ("w32", C.c_void_p * 3), ("ad", C.c_void_p)]
 
 
 class fld_server_opts(C.Structure):
@@ -239,7 +240,7 @@ def fld_opts_default(**kw) -> fld_opts:
     for k, v in kw.items():
         if k not in names:
             raise TypeError(f"unknown solver option {k!r}")
-        if k in ("bc", "bc_grad"):
+        if k in ("bc", "bc_grad", "bc_value"):
             arr = getattr(o, k)
             for i, x in enumerate(v):
                 arr[i] = x
@@ -581,6 +582,7 @@ class Plan:
                "x32": view(v.x32, torch.float32, 4), "b32": view(v.b32, torch.float32, 4)}
         out["w"] = [view(v.w[d], torch.float64, 8) for d in range(v.ndim)]
         out["w32"] = [view(v.w32[d], torch.float32, 4) for d in range(v.ndim)]
+        out["ad"] = view(v.ad, torch.float64, 8)
         return out
 
     def coefficients(self, E_in, kappa_rho, dt, stream=None):

@@ -82,9 +82,13 @@ struct LevelDesc {
     double  hinv[3];     // 1/h per axis (level 0 values are the grid's)
     // level 0 only: prescribed gradient dE/dx_a at the faces x-, x+, y-, y+, z-, z+ (0 for
     // zero flux), and that gradient times the cell width (the ghosts' linear part)
-    int32_t has_bc;      // any face with a nonzero prescribed gradient
+    int32_t has_bc;      // any face with a nonzero prescribed gradient or a Dirichlet value
     double  bcg[6];
     double  bcgh[6];
+    int32_t dir_mask;    // level 0: bit f set for the Dirichlet faces
+    double  bcv[6];      // level 0: the ghost value E_B of each Dirichlet face
+    double* ad;          // every level of a plan with Dirichlet faces: the extra diagonal of
+    float*  ad32;        //   the ghost couplings, dt D / h^2 per Dirichlet face (NULL without)
     double* x;           // FP64 solution (level 0) / correction (coarser)
     double* b;           // FP64 right-hand side
     double* w[3];        // FP64 lower-face weights dt*D_face/h^2

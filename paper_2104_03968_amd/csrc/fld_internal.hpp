@@ -71,6 +71,7 @@ struct Plan {
     DimLists dl[2];                            // [0] = 2D, [1] = 3D
     bool mixed = false;
     bool krylov = true;
+    bool has_dir = false;                      // some face is FLD_BC_DIRICHLET
 
     // workspace layout (byte offsets)
     size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_moio = 0, off_imio = 0, off_ctrl = 0;
@@ -82,6 +83,7 @@ struct Plan {
         bool has_x = false, has_b = false, has_x32 = false, has_scratch = false, has_part = false;
         bool has_xs = false;
         bool lev0 = false, has_cg = false;
+        size_t ad = 0, ad32 = 0;                // Dirichlet ghost couplings (plans with Dirichlet faces)
     };
     std::vector<FieldOff> foff;                // per level (relative to the grid's field base)
     std::vector<size_t> field_off;             // byte offset of each grid's fields in the workspace

@@ -323,25 +323,35 @@ __device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, in
 // The same gradient where faces prescribe a gradient G: the ghost at index i
 // outside [0, n) is the mirror image plus the linear part of slope G, -(2k-1) h G
 // below (i = -k) and +(2k-1) h G above (i = n-1+k); gh = {h G_lo, h G_hi} per axis.
+// Dirichlet faces (bit of dir_mask) put their value E_B in both ghost layers.
 __device__ __forceinline__ double ghost_lin(int i, int n, double ghlo, double ghhi) {
     return i < 0 ? (double)(2 * i + 1) * ghlo : (i >= n ? (double)(2 * (i - n) + 1) * ghhi : 0.0);
 }
 
 template <int DIM>
 __device__ __forceinline__ void grad4_bc_at(const double* __restrict__ E, int i, int j, int k, const int32_t n[3],
-                                            const double c12[3], const double gh[6], double g[3]) {
+                                            const double c12[3], const LevelDesc& bc, double g[3]) {
     const long sy = n[0], sz = (long)n[0] * n[1];
+    const double* gh = bc.bcgh;
+    const int dm = bc.dir_mask;
+    // ghost or interior value at index q of an axis of m cells whose faces are 2a, 2a+1
+    auto val = [&](long base, long stride, int q, int m, int a) {
+        const double in = E[base + mirror(q, m) * stride] + ghost_lin(q, m, gh[2 * a], gh[2 * a + 1]);
+        if (q < 0 && (dm >> (2 * a)) & 1) return bc.bcv[2 * a];
+        if (q >= m && (dm >> (2 * a + 1)) & 1) return bc.bcv[2 * a + 1];
+        return in;
+    };
     const long row = (long)j * sy + (long)k * sz;
-    auto ex = [&](int q) { return E[mirror(q, n[0]) + row] + ghost_lin(q, n[0], gh[0], gh[1]); };
-    g[0] = ((ex(i - 2) - ex(i + 2)) + 8.0 * (ex(i + 1) - ex(i - 1))) * c12[0];
+    g[0] = ((val(row, 1, i - 2, n[0], 0) - val(row, 1, i + 2, n[0], 0)) +
+            8.0 * (val(row, 1, i + 1, n[0], 0) - val(row, 1, i - 1, n[0], 0))) * c12[0];
     const long col = i + (long)k * sz;
-    auto ey = [&](int q) { return E[col + mirror(q, n[1]) * sy] + ghost_lin(q, n[1], gh[2], gh[3]); };
-    g[1] = ((ey(j - 2) - ey(j + 2)) + 8.0 * (ey(j + 1) - ey(j - 1))) * c12[1];
+    g[1] = ((val(col, sy, j - 2, n[1], 1) - val(col, sy, j + 2, n[1], 1)) +
+            8.0 * (val(col, sy, j + 1, n[1], 1) - val(col, sy, j - 1, n[1], 1))) * c12[1];
     g[2] = 0.0;
     if (DIM == 3) {
         const long pil = i + (long)j * sy;
-        auto ez = [&](int q) { return E[pil + mirror(q, n[2]) * sz] + ghost_lin(q, n[2], gh[4], gh[5]); };
-        g[2] = ((ez(k - 2) - ez(k + 2)) + 8.0 * (ez(k + 1) - ez(k - 1))) * c12[2];
+        g[2] = ((val(pil, sz, k - 2, n[2], 2) - val(pil, sz, k + 2, n[2], 2)) +
+                8.0 * (val(pil, sz, k + 1, n[2], 2) - val(pil, sz, k - 1, n[2], 2))) * c12[2];
     }
 }
 
@@ -370,12 +380,12 @@ __device__ __forceinline__ double limiter_of(double R, int limiter) {
 template <int DIM>
 __device__ __forceinline__ double cell_D(const double* __restrict__ E, const double* __restrict__ kr,
                                          int i, int j, int k, const int32_t n[3], const double c12[3],
-                                         double c, int limiter, const double* gh = nullptr) {
+                                         double c, int limiter, const LevelDesc* bc = nullptr) {
     const long idx = i + (long)n[0] * (j + (long)n[1] * k);
     const double e = E[idx];
     const double kk = kr[idx];
     double g[3];
-    if (gh) grad4_bc_at<DIM>(E, i, j, k, n, c12, gh, g);
+    if (bc) grad4_bc_at<DIM>(E, i, j, k, n, c12, *bc, g);
     else grad4_at<DIM>(E, i, j, k, n, c12, g);
     double g2 = g[0] * g[0] + g[1] * g[1];
     if (DIM == 3) g2 += g[2] * g[2];
@@ -411,7 +421,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
                 const double e = p.E_in[idx];
                 double wx = 0.0, wy = 0.0, wz = 0.0;
-                const double* gh = d.has_bc ? d.bcgh : nullptr;
+                const LevelDesc* gh = d.has_bc ? &d : nullptr;
                 double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
                 if (!p.krd[0]) {
                     const double kk = p.kr[idx];
@@ -450,14 +460,28 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     d.w32[1][idx] = (float)wy;
                     if (DIM == 3) d.w32[2][idx] = (float)wz;
                 }
-                // fixed-gradient faces: the flux -D G through the face, D the cell's own, enters b
+                // fixed-gradient faces: the flux -D G through the face, D the cell's own, enters b;
+                // Dirichlet faces couple the cell to its ghost (value E_B, one cell width away,
+                // the cell's own D): alpha = dt D / h^2 on the diagonal, alpha E_B in b
                 double bsrc = e;
+                double al = 0.0;
                 if (d.has_bc) {
                     const int ci[3] = {i, j, k};
                     for (int a = 0; a < DIM; ++a) {
-                        if (ci[a] == 0) bsrc += dt * d.hinv[a] * (-Da[a] * d.bcg[2 * a]);
-                        if (ci[a] == d.n[a] - 1) bsrc += dt * d.hinv[a] * (Da[a] * d.bcg[2 * a + 1]);
+                        const double wa = dt * Da[a] * d.hinv[a] * d.hinv[a];
+                        if (ci[a] == 0) {
+                            if ((d.dir_mask >> (2 * a)) & 1) { al += wa; bsrc += wa * d.bcv[2 * a]; }
+                            else bsrc += dt * d.hinv[a] * (-Da[a] * d.bcg[2 * a]);
+                        }
+                        if (ci[a] == d.n[a] - 1) {
+                            if ((d.dir_mask >> (2 * a + 1)) & 1) { al += wa; bsrc += wa * d.bcv[2 * a + 1]; }
+                            else bsrc += dt * d.hinv[a] * (Da[a] * d.bcg[2 * a + 1]);
+                        }
                     }
+                }
+                if (d.ad) {                                 // every cell: coarsening reads them all
+                    d.ad[idx] = al;
+                    if (MIXED) d.ad32[idx] = (float)al;
                 }
                 d.B0[idx] = bsrc;
                 d.X[idx] = e;
@@ -514,6 +538,17 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl, int galerkin) {
             cL.w[a][cidx] = wc[a];
             if (MIXED) cL.w32[a][cidx] = (float)wc[a];
         }
+        // Dirichlet couplings: the 2^(DIM-1) children on a face carry alpha each; the
+        // rediscretised coarse coupling is their mean over 4 (ghost two fine widths away),
+        // the Galerkin one their sum over 2^DIM
+        if (cL.ad) {
+            const double* a = f.ad;
+            double sa = a[f0] + a[f0 + 1] + a[f0 + fsy] + a[f0 + fsy + 1];
+            if (DIM == 3) sa += a[f0 + fsz] + a[f0 + fsz + 1] + a[f0 + fsz + fsy] + a[f0 + fsz + fsy + 1];
+            const double ac = sa * (galerkin ? ((DIM == 3) ? 0.125 : 0.25) : ((DIM == 3) ? 0.0625 : 0.125));
+            cL.ad[cidx] = ac;
+            if (MIXED) cL.ad32[cidx] = (float)ac;
+        }
     }
 }
 
@@ -535,12 +570,14 @@ template <> struct Arr<double> {
     __device__ static double* xs(const LevelDesc& d) { return d.xs; }
     __device__ static double* b(const LevelDesc& d) { return d.b; }
     __device__ static double* w(const LevelDesc& d, int a) { return d.w[a]; }
+    __device__ static double* ad(const LevelDesc& d) { return d.ad; }
 };
 template <> struct Arr<float> {
     __device__ static float* x(const LevelDesc& d) { return d.x32; }
     __device__ static float* xs(const LevelDesc& d) { return d.xs32; }
     __device__ static float* b(const LevelDesc& d) { return d.b32; }
     __device__ static float* w(const LevelDesc& d, int a) { return d.w32[a]; }
+    __device__ static float* ad(const LevelDesc& d) { return d.ad32; }
 };
 
 // Neighbour access without branches: a neighbour across the domain boundary is
@@ -555,7 +592,8 @@ __device__ __forceinline__ void nb_pair(P w, P x, long idx, long nb, bool has, T
 }
 
 template <int DIM, typename T, typename P>
-__device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32_t n[3], int i, int j, int k) {
+__device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32_t n[3], int i, int j, int k,
+                                         P a = nullptr, bool has_a = false) {
     const long sy = n[0], sz = (long)n[0] * n[1];
     const long idx = i + j * sy + k * sz;
     const T xc = x[idx];
@@ -576,6 +614,7 @@ __device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32
         r -= wb * (xc - xb);
         r -= wf * (xc - xf);
     }
+    if (has_a) r -= a[idx] * xc;                 // Dirichlet ghost coupling (ghost value 0)
     return r;
 }
 
@@ -623,6 +662,7 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
+        if (Arr<T>::ad(d)) dg += as_global(Arr<T>::ad(d))[idx];
         x[idx] = s / dg;
     }
 }
@@ -651,7 +691,8 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
 #pragma unroll
         for (int c = 0; c < (1 << DIM); ++c) {
             s += residual_at<DIM, T>(x, b, w0, w1, w2, f.n, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1),
-                                     DIM == 3 ? 2 * K + (c >> 2) : 0);
+                                     DIM == 3 ? 2 * K + (c >> 2) : 0, as_global(Arr<T>::ad(f)),
+                                     Arr<T>::ad(f) != nullptr);
         }
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
         as_global(Arr<T>::b(cL))[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
@@ -758,7 +799,7 @@ __device__ __forceinline__ void cell_coords(const int32_t n[3], int c, int& i, i
 template <int DIM, typename T>
 __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restrict__ w0,
                                       const T* __restrict__ w1, const T* __restrict__ w2,
-                                      const int32_t n[3], int c, T& dg) {
+                                      const int32_t n[3], int c, T& dg, const T* a, bool has_a) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
     const long sy = n[0], sz = (long)n[0] * n[1];
@@ -781,12 +822,16 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restri
         q += wb * (pc - pb); dg += wb;
         q += wf * (pc - pf); dg += wf;
     }
+    if (has_a) {
+        q += a[c] * pc;
+        dg += a[c];
+    }
     return q;
 }
 
 template <int DIM, typename T>
 __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restrict__ w1,
-                                     const T* __restrict__ w2, const int32_t n[3], int c) {
+                                     const T* __restrict__ w2, const int32_t n[3], int c, const T* a, bool has_a) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
     const long sy = n[0], sz = (long)n[0] * n[1];
@@ -800,6 +845,7 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
         nb_pair(w2, w2, c, c - sz, k > 0, wn, unused); dg += wn;
         nb_pair(w2, w2, c, c + sz, k + 1 < n[2], wn, unused); dg += wn;
     }
+    if (has_a) dg += a[c];
     return dg;
 }
 
@@ -810,7 +856,7 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
 // registers of the thread owning the cell.  w, b and x may be global or LDS.
 template <int DIM, typename T, int NT, int CPT>
 __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
-                         bool warm, T* p_sh, double* red) {
+                         bool warm, T* p_sh, double* red, const T* a, bool has_a) {
     const int ncell = n[0] * n[1] * n[2];
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
     const double tol2 = 1e-12;                 // (1e-6)^2 relative
@@ -822,7 +868,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
         r[m] = T(0);
         dinv[m] = T(0);
         if (c < ncell) {
-            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c);
+            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c, a, has_a);
             xr[m] = warm ? x[c] : T(0);
             p_sh[c] = xr[m];
         }
@@ -834,7 +880,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
         if (c < ncell) {
             T dg;
             r[m] = b[c];
-            if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg);
+            if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a);
         }
     }
     __syncthreads();
@@ -860,7 +906,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
                 q[m] = T(0);
                 if (c < ncell) {
                     T dg;
-                    q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg);
+                    q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a);
                     pq += (double)p_sh[c] * (double)q[m];
                 }
             }
@@ -912,11 +958,13 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     const T* w2 = (DIM == 3) ? Arr<T>::w(d, 2) : nullptr;
     T* xg = Arr<T>::x(d);
     const T* bg = Arr<T>::b(d);
+    const T* ag = Arr<T>::ad(d);
+    const bool has_a = ag != nullptr;
     // The finest level of a single-level FP64 grid holds the solution itself: iterate
     // from it.  Every other coarsest level solves for a correction from zero.
     const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
-        block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red);
+        block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red, ag, has_a);
         return;
     }
     const int maxit = 2000;
@@ -932,7 +980,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     __syncthreads();
     for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
         T dg;
-        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg);
+        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg, ag, has_a);
         const T rc = bg[c] - ax;
         const T z = rc / dg;
         r[c] = rc;
@@ -947,7 +995,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
         double pq = 0.0, unused = 0.0;
         for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
             T dg;
-            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg);
+            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg, ag, has_a);
             q[c] = qc;
             pq += (double)p[c] * (double)qc;
         }
@@ -1511,6 +1559,7 @@ struct TailGeom {
     float rny;           // 1 / ny
     float rnx;           // 1 / nx
     int32_t ox, ob, ow[3];
+    int32_t oa, has_a;   // Dirichlet ghost couplings (plans with Dirichlet faces)
 };
 
 template <typename T>
@@ -1524,6 +1573,8 @@ struct TailLevel {
     T* x;
     T* b;
     T* w[3];
+    T* a;
+    int32_t has_a;
 };
 
 template <typename T>
@@ -1538,6 +1589,8 @@ __device__ __forceinline__ TailLevel<T> tl_at(const TailGeom& g, T* base) {
     t.x = base + g.ox;
     t.b = base + g.ob;
     for (int a = 0; a < 3; ++a) t.w[a] = base + g.ow[a];
+    t.a = base + g.oa;
+    t.has_a = g.has_a;
     return t;
 }
 constexpr int kMaxTail = 16;
@@ -1592,6 +1645,7 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
+        if (lv.has_a) dg += lv.a[c];
         lv.x[c] = s / dg;
     }
     __syncthreads();
@@ -1608,6 +1662,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     const int first = jl.levels[blockIdx.x];
     const LevelDesc& d0 = L[first];
     if (!S[d0.grid].active) return;
+    const int hasa = Arr<T>::ad(d0) != nullptr ? 1 : 0;
     // the grid's levels from `first` down are consecutive descriptors: thread m reads
     // level m's (no chain through the coarse links), then the LDS layout follows
     const int nl = min(d0.nlev - d0.level, kMaxTail);
@@ -1616,7 +1671,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     if (m_own < nl) {
         const LevelDesc& d = L[first + m_own];
         nown[0] = d.n[0]; nown[1] = d.n[1]; nown[2] = d.n[2];
-        off[m_own + 1] = (2 + DIM) * d.n[0] * d.n[1] * d.n[2];
+        off[m_own + 1] = (2 + DIM + hasa) * d.n[0] * d.n[1] * d.n[2];
     }
     if (threadIdx.x == 0) off[0] = 0;
     __syncthreads();
@@ -1636,10 +1691,12 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
             t.ow[a] = o;                                   // unused past DIM
             if (a < DIM) o += t.ncell;
         }
+        t.oa = o;                                          // unused without Dirichlet faces
+        t.has_a = hasa;
     }
     __syncthreads();
     T* const sbase = reinterpret_cast<T*>(tail_smem);
-    T* p_sh = sbase + (tl[nl - 1].ow[DIM - 1] + tl[nl - 1].ncell);   // the coarsest CG's search direction
+    T* p_sh = sbase + (tl[nl - 1].oa + hasa * tl[nl - 1].ncell);   // the coarsest CG's search direction
     // load every tail level's weights, and b and (warm) x of the first; loads of a
     // level are issued together, then stored
     for (int m = 0; m < nl; ++m) {
@@ -1652,9 +1709,11 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         const bool warm = lead && plain64 && d.level == 0;
         const gptr<T> bsrc = as_global(Arr<T>::b(d));
         const gptr<T> xsrc = as_global(Arr<T>::x(d));
+        const gptr<T> asrc = as_global(hasa ? Arr<T>::ad(d) : Arr<T>::w(d, 0));
         for (int c = threadIdx.x; c < t.ncell; c += kTailThreads) {
             const T a0 = s0[c], a1 = s1[c];
             const T a2 = (DIM == 3) ? s2[c] : T(0);
+            if (hasa) t.a[c] = asrc[c];
             const T bb = lead ? bsrc[c] : T(0);
             const T xx = warm ? xsrc[c] : T(0);
             t.w[0][c] = a0;
@@ -1682,7 +1741,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
 #pragma unroll
             for (int q = 0; q < (1 << DIM); ++q)
                 sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
-                                           2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0);
+                                           2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
+                                           f.has_a != 0);
             cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
             cT.x[c] = T(0);
         }
@@ -1691,7 +1751,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     // coarsest: CG from the current x (zero unless the grid has a single level)
     {
         const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
-        block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red);
+        block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red, cT.a,
+                                                 cT.has_a != 0);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
@@ -1745,7 +1806,7 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
             const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
             const double e = m.E[idx], kk = m.kr[idx];
             double g[3];
-            if (d.has_bc) grad4_bc_at<DIM>(m.E, i, j, k, d.n, c12, d.bcgh, g);
+            if (d.has_bc) grad4_bc_at<DIM>(m.E, i, j, k, d.n, c12, d, g);
             else grad4_at<DIM>(m.E, i, j, k, d.n, c12, g);
             double g2 = g[0] * g[0] + g[1] * g[1];
             if (DIM == 3) g2 += g[2] * g[2];
@@ -1824,7 +1885,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
             ix[m_] = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
             rv[m_] = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
                                               as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
-                                              d.n, i, j, k);
+                                              d.n, i, j, k, as_global(d.ad), d.ad != nullptr);
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
@@ -1955,6 +2016,7 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                     q += wb * (pc - pb);
                     q += wf * (pc - pf);
                 }
+                if (d.ad) q += as_global(d.ad)[idx] * pc;
                 if (ok) {
                     Pn[idx] = pc;
                     as_global(d.Q)[idx] = q;

@@ -52,8 +52,11 @@ int validate_opts(const fld_opts& o) {
     if (o.limiter < FLD_LIMITER_LP || o.limiter > FLD_LIMITER_LP_EXACT) return FLD_ERR_INVALID_ARG;
     for (int f = 0; f < 6; ++f) {
         if (o.bc[f] < 0) return FLD_ERR_INVALID_ARG;
-        if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT) return FLD_ERR_UNSUPPORTED;
+        if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT && o.bc[f] != FLD_BC_DIRICHLET)
+            return FLD_ERR_UNSUPPORTED;
         if (!std::isfinite(o.bc_grad[f])) return FLD_ERR_INVALID_ARG;
+        if (o.bc[f] == FLD_BC_DIRICHLET && !(o.bc_value[f] >= 0.0 && std::isfinite(o.bc_value[f])))
+            return FLD_ERR_INVALID_ARG;
     }
     if (o.precision != FLD_PREC_FP64 && o.precision != FLD_PREC_MIXED) return FLD_ERR_INVALID_ARG;
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return FLD_ERR_INVALID_ARG;
@@ -181,6 +184,11 @@ static void build_levels(Plan& p) {
                     d.bcg[f] = G;
                     d.bcgh[f] = G * gr.h[f / 2];
                     if (G != 0.0) d.has_bc = 1;
+                    if (p.opts.bc[f] == FLD_BC_DIRICHLET) {
+                        d.dir_mask |= 1 << f;
+                        d.bcv[f] = p.opts.bc_value[f];
+                        d.has_bc = 1;
+                    }
                 }
             }
             if (lev > 0) p.levels.back().coarse = (int32_t)p.levels.size();
@@ -206,7 +214,7 @@ static size_t tail_bytes(const Plan& p, int g, int t) {
     size_t cells = 0;
     for (int l = t; l < L; ++l) {
         const LevelDesc& d = p.levels[l0 + l];
-        cells += (size_t)(2 + dim) * d.n[0] * d.n[1] * d.n[2];
+        cells += (size_t)(2 + dim + (p.has_dir ? 1 : 0)) * d.n[0] * d.n[1] * d.n[2];
     }
     const LevelDesc& c = p.levels[l0 + L - 1];
     cells += (size_t)c.n[0] * c.n[1] * c.n[2];
@@ -277,7 +285,9 @@ static void build_lists(Plan& p) {
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
             max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
         D.fin_fused = max_tiles <= 32;
-        D.fused = D.dim == 2 && p.opts.fused && fused2_supported(p.opts.nu1) && fused2_supported(p.opts.nu2);
+        // the fused level kernels know no Dirichlet couplings: such plans sweep per colour
+        D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && fused2_supported(p.opts.nu1) &&
+                  fused2_supported(p.opts.nu2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
         for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
@@ -286,7 +296,7 @@ static void build_lists(Plan& p) {
         }
         // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
         // even for its result to end in x
-        D.fused3 = D.dim == 3 && p.opts.fused && fused3_supported(p.mixed) && p.opts.nu1 >= 1 &&
+        D.fused3 = D.dim == 3 && p.opts.fused && !p.has_dir && fused3_supported(p.mixed) && p.opts.nu1 >= 1 &&
                    p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0;
         D.sw3.resize(D.fused3 ? maxdepth : 0);
         D.sr3.resize(D.fused3 ? maxdepth : 0);
@@ -332,6 +342,12 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.opts = opts;
     p.mixed = opts.precision == FLD_PREC_MIXED;
     p.krylov = opts.krylov != 0;
+    p.has_dir = false;
+    for (int f = 0; f < 6; ++f) {
+        if (opts.bc[f] != FLD_BC_DIRICHLET) continue;
+        for (int g = 0; g < ngrids; ++g)
+            if (f < 2 * grids[g].ndim) p.has_dir = true;
+    }
     p.grids.assign(grids, grids + ngrids);
     for (auto& g : p.grids)
         if (g.ndim == 2) { g.n[2] = 1; g.h[2] = 1.0; }
@@ -400,6 +416,10 @@ static void layout(Plan& p) {
         const bool lev0 = d.level == 0;
         // FP64 weights at every level (coarse weights derive from them)
         for (int a = 0; a < d.ndim; ++a) f.w[a] = take(n * 8);
+        if (p.has_dir) {
+            f.ad = take(n * 8);
+            if (p.mixed) f.ad32 = take(n * 4);
+        }
         if (lev0) {
             // outer FP64 iteration: iterate, right-hand side, residual (+ CG vectors)
             f.lev0 = true;
@@ -682,6 +702,8 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
         d.Q = dp(f.Q, f.has_cg);
         d.xs = (f.has_xs && !p.mixed) ? reinterpret_cast<double*>(ws + f.xs) : nullptr;
         d.xs32 = (f.has_xs && p.mixed) ? reinterpret_cast<float*>(ws + f.xs) : nullptr;
+        d.ad = p.has_dir ? reinterpret_cast<double*>(ws + f.ad) : nullptr;
+        d.ad32 = (p.has_dir && p.mixed) ? reinterpret_cast<float*>(ws + f.ad32) : nullptr;
     }
     FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
     std::vector<GridState> st(p.ngrids());
@@ -1299,6 +1321,7 @@ int32_t fld_plan_level_view(fld_plan_t plan, int32_t g, int32_t level, fld_level
     out->b = level == 0 ? d.B0 : d.b;
     out->x32 = d.x32;
     out->b32 = d.b32;
+    out->ad = d.ad;
     return FLD_OK;
 }
 

@@ -61,7 +61,9 @@ def test_plan_create_validates_grids(n, ok):
 @pytest.mark.parametrize("kw,code", [
     (dict(rtol=0.0), -1), (dict(rtol=2.0), -1), (dict(c=-1.0), -1), (dict(limiter=7), -1),
     (dict(precision=3), -1), (dict(max_cycles=0), -1), (dict(nu1=0, nu2=0), -1),
-    (dict(bc=[2, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[3, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[2, 0, 0, 0, 0, 0], bc_value=[-1.0, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[0, 2, 0, 0, 0, 0], bc_value=[0, float("inf"), 0, 0, 0, 0]), -1),
     (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1),
     (dict(fmg=2), -1), (dict(fmg=-1), -1), (dict(coarse_op=2), -1), (dict(coarse_op=-1), -1),
     (dict(fmg_depths=-1), -1), (dict(fmg_depths=65), -1)])
@@ -269,3 +271,23 @@ def test_fmg_and_galerkin_plans():
     base = sizes[(("fmg", 0),)]
     assert sizes[(("coarse_op", "galerkin"), ("fmg", 0))] == base
     assert 0 <= sizes[(("fmg", 1),)] - base <= 64 * 1024
+
+
+def test_dirichlet_plans_add_one_coupling_array_per_level():
+    grids = [fld.make_grid((64, 48)), fld.make_grid((16, 16, 8))]
+    sizes = {}
+    for prec in (0, 1):
+        for bc in ([0] * 6, [2, 0, 0, 2, 0, 0]):
+            h = fld.fld_plan_create(grids, fld.fld_opts_default(precision=prec, bc=bc, bc_value=[1.0] * 6))
+            sizes[(prec, bc[0])] = fld.fld_plan_workspace_bytes(h)
+            fld.fld_plan_destroy(h)
+    # per-colour sweeps (no xs arrays of the fused kernels) with 8 B per cell and level of
+    # couplings (+4 B in mixed precision): compare against zero-flux plans that also sweep
+    # per colour
+    for prec in (0, 1):
+        h = fld.fld_plan_create(grids, fld.fld_opts_default(precision=prec, fused=0))
+        base = fld.fld_plan_workspace_bytes(h)
+        fld.fld_plan_destroy(h)
+        n = 64 * 48 + 32 * 24 + 16 * 12 + 8 * 6 + 4 * 3 + 16 * 16 * 8 + 8 * 8 * 4 + 4 * 4 * 2
+        extra = sizes[(prec, 2)] - base
+        assert (8 + 4 * prec) * n <= extra <= (8 + 4 * prec) * n + 2 * 256 * 8 + 4096
