@@ -1,4 +1,5 @@
-"""Plain FP64 oracle of the FLD step with Dirichlet boundaries (TEST INFRASTRUCTURE).
+"""Plain FP64 oracle of the FLD step with Dirichlet and periodic boundaries
+(TEST INFRASTRUCTURE).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
 leg may use this module.  It shares no code with the HIP path.
@@ -15,9 +16,13 @@ beside the Neumann (fixed-gradient) ones.  Readings, per face with ghost value E
   right-hand side.  The operator stays symmetric positive definite with
   lambda_min >= 1; energy now leaves or enters through the face.
 
+Periodic axes (both faces "periodic") wrap: the ghosts are the cells at the other
+end, and the face between the last and the first cell is an interior face like any
+other (harmonic mean of the two D, stored in the first cell's lower-face slot).
+
 Faces are listed x-, x+, y-, y+, z-, z+.  ``kind`` per face is "zero_flux",
-"gradient" (the fixed-gradient faces of ``oracle.bc``) or "dirichlet"; ``value``
-per face is the prescribed gradient or ghost value.
+"gradient" (the fixed-gradient faces of ``oracle.bc``), "dirichlet" or "periodic";
+``value`` per face is the prescribed gradient or ghost value.
 """
 from __future__ import annotations
 
@@ -29,9 +34,9 @@ import scipy.sparse as sp
 from . import fld as _fld
 
 __all__ = ["pad_general", "gradient4_general", "dirichlet_diagonal", "boundary_rhs",
-           "diffusion_step_general"]
+           "face_weights_general", "assemble_general", "diffusion_step_general"]
 
-KINDS = ("zero_flux", "gradient", "dirichlet")
+KINDS = ("zero_flux", "gradient", "dirichlet", "periodic")
 
 
 def _faces(kind, value, nd):
@@ -44,6 +49,9 @@ def _faces(kind, value, nd):
             k[f] = kind[f]
         if value is not None and value[f] is not None:
             v[f] = float(value[f])
+    for d in range(nd):
+        if (k[2 * d] == "periodic") != (k[2 * d + 1] == "periodic"):
+            raise ValueError("a periodic axis needs both of its faces periodic")
     return k, v
 
 
@@ -62,8 +70,11 @@ def pad_general(E: np.ndarray, d: int, h: float, kind_lo: str, val_lo: float, ki
         # [inner ghost, outer ghost]: E_{-1} = E_0 -/+ h G, E_{-2} = E_1 -/+ 3 h G
         return [edge0 + sign * h * g, edge1 + sign * 3.0 * h * g]
 
-    lo = ghosts(M[0], M[1], kind_lo, val_lo, -1.0)
-    hi = ghosts(M[-1], M[-2], kind_hi, val_hi, 1.0)
+    if kind_lo == "periodic":
+        lo, hi = [M[-1], M[-2]], [M[0], M[1]]
+    else:
+        lo = ghosts(M[0], M[1], kind_lo, val_lo, -1.0)
+        hi = ghosts(M[-1], M[-2], kind_hi, val_hi, 1.0)
     P = np.concatenate([np.stack([lo[1], lo[0]]), M, np.stack([hi[0], hi[1]])], axis=0)
     return np.moveaxis(P, 0, a)
 
@@ -126,6 +137,41 @@ def boundary_rhs(D: np.ndarray, dt: float, h: Sequence[float], kind=None, value=
     return s
 
 
+def face_weights_general(D: np.ndarray, dt: float, h: Sequence[float], kind=None) -> List[np.ndarray]:
+    """Lower-face weights (``oracle.fld.face_weights``) plus, on periodic axes, the face
+    between the last and the first cell in the first cell's slot."""
+    nd = D.ndim
+    k, _ = _faces(kind, None, nd)
+    w = _fld.face_weights(D, dt, h)
+    for d in range(nd):
+        if k[2 * d] != "periodic":
+            continue
+        lo, hi = _boundary_slices(D.shape, d)
+        DL, DR = D[hi], D[lo]
+        w[d][lo] = dt * (2.0 * DL * DR / (DL + DR)) / (h[d] * h[d])
+    return w
+
+
+def assemble_general(w: Sequence[np.ndarray], kind=None) -> sp.csr_matrix:
+    """``oracle.fld.assemble_operator`` plus the wrap-around faces of periodic axes."""
+    shape = w[0].shape
+    nd = len(shape)
+    k, _ = _faces(kind, None, nd)
+    A = _fld.assemble_operator(w).tolil()
+    idx = np.arange(int(np.prod(shape))).reshape(shape)
+    for d in range(nd):
+        if k[2 * d] != "periodic":
+            continue
+        lo, hi = _boundary_slices(shape, d)
+        first, last, wf = idx[lo].ravel(), idx[hi].ravel(), w[d][lo].ravel()
+        for a, b, x in zip(first, last, wf):
+            A[a, a] += x
+            A[b, b] += x
+            A[a, b] -= x
+            A[b, a] -= x
+    return A.tocsr()
+
+
 def diffusion_step_general(E: np.ndarray, kappa_rho: np.ndarray, dt: float, h: Sequence[float],
                            kind: Optional[Sequence] = None, value: Optional[Sequence] = None,
                            c: float = 1.0, limiter: str = "lp", method: str = "auto", tol=None):
@@ -136,9 +182,9 @@ def diffusion_step_general(E: np.ndarray, kappa_rho: np.ndarray, dt: float, h: S
     gr = gradient4_general(E, h, kind, value)
     R = np.sqrt(sum(x * x for x in gr)) / (kr * E)
     D = c * _fld.flux_limiter(R, limiter) / kr
-    w = _fld.face_weights(D, dt, h)
+    w = face_weights_general(D, dt, h, kind)
     alpha = dirichlet_diagonal(D, dt, h, kind)
-    A = (_fld.assemble_operator(w) + sp.diags(alpha.ravel())).tocsr()
+    A = (assemble_general(w, kind) + sp.diags(alpha.ravel())).tocsr()
     b = E + boundary_rhs(D, dt, h, kind, value)
     x, info = _fld.solve(A, b, method=method, tol=tol, w=w)
     info.extra["b"] = b

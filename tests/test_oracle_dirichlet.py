@@ -135,4 +135,4 @@ def test_general_rule_reduces_to_the_other_boundary_oracles(shape):
 
 def test_unknown_kind_is_rejected():
     with pytest.raises(ValueError):
-        O.gradient4_general(np.ones((4, 4)), (0.25, 0.25), ["periodic"] * 4, None)
+        O.gradient4_general(np.ones((4, 4)), (0.25, 0.25), ["open"] * 4, None)
