@@ -77,6 +77,12 @@ extern "C" {
                                         to the right-hand side.  Plans with Dirichlet
                                         faces run one kernel per colour sweep (no
                                         fused level kernels)                        */
+#define FLD_BC_PERIODIC         3    /* both faces of an axis: the ghosts are the cells at
+                                        the other end and the face between the last
+                                        and the first cell is an interior face (harmonic
+                                        mean of their D).  One face of an axis periodic
+                                        and the other not is INVALID_ARG.  Such plans
+                                        also sweep per colour                       */
 #define FLD_BC_FIXED_GRADIENT   1    /* Neumann with the gradient dE/dx_a given in
                                         bc_grad (Sec. 3.4): ghosts continue the mirror
                                         image with that slope, E_{-k} = E_{k-1} -

@@ -54,6 +54,7 @@ IMEX_SCHEMES = {"euler": FLD_IMEX_EULER, "midpoint": FLD_IMEX_MIDPOINT}
 FLD_BC_ZERO_FLUX = 0
 FLD_BC_FIXED_GRADIENT = 1
 FLD_BC_DIRICHLET = 2
+FLD_BC_PERIODIC = 3
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
 FLD_COARSE_REDISCRETISED = 0

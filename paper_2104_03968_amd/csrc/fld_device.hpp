@@ -85,6 +85,7 @@ struct LevelDesc {
     int32_t has_bc;      // any face with a nonzero prescribed gradient or a Dirichlet value
     double  bcg[6];
     double  bcgh[6];
+    int32_t per_mask;    // every level: bit a set for periodic axes
     int32_t dir_mask;    // level 0: bit f set for the Dirichlet faces
     double  bcv[6];      // level 0: the ghost value E_B of each Dirichlet face
     double* ad;          // every level of a plan with Dirichlet faces: the extra diagonal of
@@ -230,7 +231,7 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
 // Full-multigrid start.  restrict_rhs: the coarse right-hand side is the mean of the
 // children's right-hand sides (restriction list of a depth) and the coarse iterate 0;
 // fmg_interp: the fine iterate is the bilinear / trilinear interpolation of the coarse
-// one, mirrored at domain faces (prolongation list of a depth).
+// one, mirrored at domain faces and wrapped on periodic axes (prolongation list of a depth).
 void launch_restrict_rhs(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          int nblk, hipStream_t s);
 void launch_fmg_interp(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,

@@ -323,7 +323,8 @@ __device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, in
 // The same gradient where faces prescribe a gradient G: the ghost at index i
 // outside [0, n) is the mirror image plus the linear part of slope G, -(2k-1) h G
 // below (i = -k) and +(2k-1) h G above (i = n-1+k); gh = {h G_lo, h G_hi} per axis.
-// Dirichlet faces (bit of dir_mask) put their value E_B in both ghost layers.
+// Dirichlet faces (bit of dir_mask) put their value E_B in both ghost layers;
+// periodic axes (bit of per_mask) take the cells at the other end.
 __device__ __forceinline__ double ghost_lin(int i, int n, double ghlo, double ghhi) {
     return i < 0 ? (double)(2 * i + 1) * ghlo : (i >= n ? (double)(2 * (i - n) + 1) * ghhi : 0.0);
 }
@@ -335,7 +336,9 @@ __device__ __forceinline__ void grad4_bc_at(const double* __restrict__ E, int i,
     const double* gh = bc.bcgh;
     const int dm = bc.dir_mask;
     // ghost or interior value at index q of an axis of m cells whose faces are 2a, 2a+1
+    const int pmask = bc.per_mask;
     auto val = [&](long base, long stride, int q, int m, int a) {
+        if ((pmask >> a) & 1) return E[base + (q < 0 ? q + m : (q >= m ? q - m : q)) * stride];
         const double in = E[base + mirror(q, m) * stride] + ghost_lin(q, m, gh[2 * a], gh[2 * a + 1]);
         if (q < 0 && (dm >> (2 * a)) & 1) return bc.bcv[2 * a];
         if (q >= m && (dm >> (2 * a + 1)) & 1) return bc.bcv[2 * a + 1];
@@ -422,6 +425,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 const double e = p.E_in[idx];
                 double wx = 0.0, wy = 0.0, wz = 0.0;
                 const LevelDesc* gh = d.has_bc ? &d : nullptr;
+                const int pm = d.per_mask;
                 double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
                 if (!p.krd[0]) {
                     const double kk = p.kr[idx];
@@ -429,10 +433,13 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     if (!ok) atomicOr(&S[d.grid].bad, 1);
                     const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
                     Da[0] = Da[1] = Da[2] = Dc;
-                    if (i > 0) wx = face_w(cell_D<DIM>(p.E_in, p.kr, i - 1, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
-                    if (j > 0) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, j - 1, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
-                    if (DIM == 3 && k > 0)
-                        wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, k - 1, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
+                    // the face below; on a periodic axis the first cell's is the wrap face
+                    const int im = i > 0 ? i - 1 : d.n[0] - 1, jm = j > 0 ? j - 1 : d.n[1] - 1;
+                    const int km = k > 0 ? k - 1 : d.n[2] - 1;
+                    if (i > 0 || (pm & 1)) wx = face_w(cell_D<DIM>(p.E_in, p.kr, im, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
+                    if (j > 0 || (pm & 2)) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, jm, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
+                    if (DIM == 3 && (k > 0 || (pm & 4)))
+                        wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, km, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
                 } else {
                     // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
                     bool ok = (e > 0.0) && isfinite(e);
@@ -442,14 +449,16 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     }
                     if (!ok) atomicOr(&S[d.grid].bad, 1);
                     for (int a = 0; a < DIM; ++a) Da[a] = cell_D<DIM>(p.E_in, p.krd[a], i, j, k, d.n, c12, c, limiter, gh);
-                    if (i > 0)
-                        wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], i - 1, j, k, d.n, c12, c, limiter, gh), Da[0], dt,
+                    const int im = i > 0 ? i - 1 : d.n[0] - 1, jm = j > 0 ? j - 1 : d.n[1] - 1;
+                    const int km = k > 0 ? k - 1 : d.n[2] - 1;
+                    if (i > 0 || (pm & 1))
+                        wx = face_w(cell_D<DIM>(p.E_in, p.krd[0], im, j, k, d.n, c12, c, limiter, gh), Da[0], dt,
                                     d.hinv[0]);
-                    if (j > 0)
-                        wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, j - 1, k, d.n, c12, c, limiter, gh), Da[1], dt,
+                    if (j > 0 || (pm & 2))
+                        wy = face_w(cell_D<DIM>(p.E_in, p.krd[1], i, jm, k, d.n, c12, c, limiter, gh), Da[1], dt,
                                     d.hinv[1]);
-                    if (DIM == 3 && k > 0)
-                        wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, k - 1, d.n, c12, c, limiter, gh), Da[2], dt,
+                    if (DIM == 3 && (k > 0 || (pm & 4)))
+                        wz = face_w(cell_D<DIM>(p.E_in, p.krd[2], i, j, km, d.n, c12, c, limiter, gh), Da[2], dt,
                                     d.hinv[2]);
                 }
                 d.w[0][idx] = wx;
@@ -521,17 +530,18 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl, int galerkin) {
         const double sc = galerkin ? ((DIM == 3) ? 0.125 : 0.25) : ((DIM == 3) ? 0.0625 : 0.125);
         double wc[3] = {0.0, 0.0, 0.0};
         // x faces: sub-faces at fine x = 2I over (j, j+1) [and (k, k+1)]
-        if (I > 0) {
+        const int pm = f.per_mask;                        // periodic: the wrap faces coarsen too
+        if (I > 0 || (pm & 1)) {
             double s = f.w[0][f0] + f.w[0][f0 + fsy];
             if (DIM == 3) s += f.w[0][f0 + fsz] + f.w[0][f0 + fsy + fsz];
             wc[0] = s * sc;
         }
-        if (J > 0) {
+        if (J > 0 || (pm & 2)) {
             double s = f.w[1][f0] + f.w[1][f0 + 1];
             if (DIM == 3) s += f.w[1][f0 + fsz] + f.w[1][f0 + 1 + fsz];
             wc[1] = s * sc;
         }
-        if (DIM == 3 && K > 0) {
+        if (DIM == 3 && (K > 0 || (pm & 4))) {
             wc[2] = (f.w[2][f0] + f.w[2][f0 + 1] + f.w[2][f0 + fsy] + f.w[2][f0 + 1 + fsy]) * sc;
         }
         for (int a = 0; a < DIM; ++a) {
@@ -582,35 +592,48 @@ template <> struct Arr<float> {
 
 // Neighbour access without branches: a neighbour across the domain boundary is
 // read from the cell itself and enters with weight 0, so every load is issued
-// together (x - x and 0 * x add exactly zero).
+// together (x - x and 0 * x add exactly zero).  nb_lo / nb_hi give the neighbour
+// below / above a cell at coordinate i of n along an axis of stride s, wrapped when
+// the axis is periodic (the face between the last and the first cell sits in the
+// first cell's lower-face slot).  The face below a cell is its own slot, the face
+// above is the upper neighbour's.
 template <typename T, typename P>
-__device__ __forceinline__ void nb_pair(P w, P x, long idx, long nb, bool has, T& wn, T& xn) {
-    const long o = has ? nb : idx;
-    const T wv = w[has ? (nb > idx ? nb : idx) : idx];
+__device__ __forceinline__ void nb_lo(P w, P x, long idx, int i, int n, long s, bool per, T& wn, T& xn) {
+    const bool has = i > 0 || per;
+    const long nb = i > 0 ? idx - s : (per ? idx + (long)(n - 1) * s : idx);
+    const T wv = w[idx];
     wn = has ? wv : T(0);
-    xn = x[o];
+    xn = x[nb];
+}
+template <typename T, typename P>
+__device__ __forceinline__ void nb_hi(P w, P x, long idx, int i, int n, long s, bool per, T& wn, T& xn) {
+    const bool has = i + 1 < n || per;
+    const long nb = i + 1 < n ? idx + s : (per ? idx - (long)(n - 1) * s : idx);
+    const T wv = w[nb];
+    wn = has ? wv : T(0);
+    xn = x[nb];
 }
 
 template <int DIM, typename T, typename P>
 __device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32_t n[3], int i, int j, int k,
-                                         P a = nullptr, bool has_a = false) {
+                                         P a = nullptr, bool has_a = false, int pm = 0) {
     const long sy = n[0], sz = (long)n[0] * n[1];
     const long idx = i + j * sy + k * sz;
     const T xc = x[idx];
     T r = b[idx] - xc;
     T wl, xl, wr, xr, wd, xd, wu, xu;
-    nb_pair(w0, x, idx, idx - 1, i > 0, wl, xl);
-    nb_pair(w0, x, idx, idx + 1, i + 1 < n[0], wr, xr);
-    nb_pair(w1, x, idx, idx - sy, j > 0, wd, xd);
-    nb_pair(w1, x, idx, idx + sy, j + 1 < n[1], wu, xu);
+    nb_lo(w0, x, idx, i, n[0], 1, ((pm) >> 0) & 1, wl, xl);
+    nb_hi(w0, x, idx, i, n[0], 1, ((pm) >> 0) & 1, wr, xr);
+    nb_lo(w1, x, idx, j, n[1], sy, ((pm) >> 1) & 1, wd, xd);
+    nb_hi(w1, x, idx, j, n[1], sy, ((pm) >> 1) & 1, wu, xu);
     r -= wl * (xc - xl);
     r -= wr * (xc - xr);
     r -= wd * (xc - xd);
     r -= wu * (xc - xu);
     if (DIM == 3) {
         T wb, xb, wf, xf;
-        nb_pair(w2, x, idx, idx - sz, k > 0, wb, xb);
-        nb_pair(w2, x, idx, idx + sz, k + 1 < n[2], wf, xf);
+        nb_lo(w2, x, idx, k, n[2], sz, ((pm) >> 2) & 1, wb, xb);
+        nb_hi(w2, x, idx, k, n[2], sz, ((pm) >> 2) & 1, wf, xf);
         r -= wb * (xc - xb);
         r -= wf * (xc - xf);
     }
@@ -644,12 +667,13 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
         const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
         const long idx = i + j * sy + k * sz;
+        const int pm = d.per_mask;
         T s = b[idx], dg = T(1);
         T wl, xl, wr, xr, wd, xd, wu, xu;
-        nb_pair(w0, x, idx, idx - 1, i > 0, wl, xl);
-        nb_pair(w0, x, idx, idx + 1, i + 1 < d.n[0], wr, xr);
-        nb_pair(w1, x, idx, idx - sy, j > 0, wd, xd);
-        nb_pair(w1, x, idx, idx + sy, j + 1 < d.n[1], wu, xu);
+        nb_lo(w0, x, idx, i, d.n[0], 1, ((pm) >> 0) & 1, wl, xl);
+        nb_hi(w0, x, idx, i, d.n[0], 1, ((pm) >> 0) & 1, wr, xr);
+        nb_lo(w1, x, idx, j, d.n[1], sy, ((pm) >> 1) & 1, wd, xd);
+        nb_hi(w1, x, idx, j, d.n[1], sy, ((pm) >> 1) & 1, wu, xu);
         s += wl * xl; dg += wl;
         s += wr * xr; dg += wr;
         s += wd * xd; dg += wd;
@@ -657,8 +681,8 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         if (DIM == 3) {
             const gptr<T> w2 = as_global(Arr<T>::w(d, 2));
             T wb, xb, wf, xf;
-            nb_pair(w2, x, idx, idx - sz, k > 0, wb, xb);
-            nb_pair(w2, x, idx, idx + sz, k + 1 < d.n[2], wf, xf);
+            nb_lo(w2, x, idx, k, d.n[2], sz, ((pm) >> 2) & 1, wb, xb);
+            nb_hi(w2, x, idx, k, d.n[2], sz, ((pm) >> 2) & 1, wf, xf);
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
@@ -692,7 +716,7 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
         for (int c = 0; c < (1 << DIM); ++c) {
             s += residual_at<DIM, T>(x, b, w0, w1, w2, f.n, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1),
                                      DIM == 3 ? 2 * K + (c >> 2) : 0, as_global(Arr<T>::ad(f)),
-                                     Arr<T>::ad(f) != nullptr);
+                                     Arr<T>::ad(f) != nullptr, f.per_mask);
         }
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
         as_global(Arr<T>::b(cL))[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
@@ -767,9 +791,15 @@ k_fmg_interp(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, J
         const gptr<T> xc = as_global(Arr<T>::x(cL));
         const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
         // the coarse neighbour on the child's side, clamped into the grid
-        const int I1 = min(max(I0 + ((i & 1) ? 1 : -1), 0), cL.n[0] - 1);
-        const int J1 = min(max(J0 + ((j & 1) ? 1 : -1), 0), cL.n[1] - 1);
-        const int K1 = (DIM == 3) ? min(max(K0 + ((k & 1) ? 1 : -1), 0), cL.n[2] - 1) : 0;
+        // (wrapped on periodic axes)
+        const int pm = f.per_mask;
+        auto side = [&](int c0, int odd, int nc, int per) {
+            const int c1 = c0 + (odd ? 1 : -1);
+            return per ? (c1 + nc) % nc : min(max(c1, 0), nc - 1);
+        };
+        const int I1 = side(I0, i & 1, cL.n[0], pm & 1);
+        const int J1 = side(J0, j & 1, cL.n[1], (pm >> 1) & 1);
+        const int K1 = (DIM == 3) ? side(K0, k & 1, cL.n[2], (pm >> 2) & 1) : 0;
         const long sy = cL.n[0], sz = (long)cL.n[0] * cL.n[1];
         const T w0 = T(0.75), w1 = T(0.25);
         auto row = [&](int jj, int kk) {
@@ -799,7 +829,7 @@ __device__ __forceinline__ void cell_coords(const int32_t n[3], int c, int& i, i
 template <int DIM, typename T>
 __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restrict__ w0,
                                       const T* __restrict__ w1, const T* __restrict__ w2,
-                                      const int32_t n[3], int c, T& dg, const T* a, bool has_a) {
+                                      const int32_t n[3], int c, T& dg, const T* a, bool has_a, int pm) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
     const long sy = n[0], sz = (long)n[0] * n[1];
@@ -807,18 +837,18 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restri
     T q = pc;
     dg = T(1);
     T wl, pl, wr, pr, wd, pd, wu, pu;
-    nb_pair(w0, p, c, c - 1, i > 0, wl, pl);
-    nb_pair(w0, p, c, c + 1, i + 1 < n[0], wr, pr);
-    nb_pair(w1, p, c, c - sy, j > 0, wd, pd);
-    nb_pair(w1, p, c, c + sy, j + 1 < n[1], wu, pu);
+    nb_lo(w0, p, c, i, n[0], 1, ((pm) >> 0) & 1, wl, pl);
+    nb_hi(w0, p, c, i, n[0], 1, ((pm) >> 0) & 1, wr, pr);
+    nb_lo(w1, p, c, j, n[1], sy, ((pm) >> 1) & 1, wd, pd);
+    nb_hi(w1, p, c, j, n[1], sy, ((pm) >> 1) & 1, wu, pu);
     q += wl * (pc - pl); dg += wl;
     q += wr * (pc - pr); dg += wr;
     q += wd * (pc - pd); dg += wd;
     q += wu * (pc - pu); dg += wu;
     if (DIM == 3) {
         T wb, pb, wf, pf;
-        nb_pair(w2, p, c, c - sz, k > 0, wb, pb);
-        nb_pair(w2, p, c, c + sz, k + 1 < n[2], wf, pf);
+        nb_lo(w2, p, c, k, n[2], sz, ((pm) >> 2) & 1, wb, pb);
+        nb_hi(w2, p, c, k, n[2], sz, ((pm) >> 2) & 1, wf, pf);
         q += wb * (pc - pb); dg += wb;
         q += wf * (pc - pf); dg += wf;
     }
@@ -831,19 +861,20 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restri
 
 template <int DIM, typename T>
 __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restrict__ w1,
-                                     const T* __restrict__ w2, const int32_t n[3], int c, const T* a, bool has_a) {
+                                     const T* __restrict__ w2, const int32_t n[3], int c, const T* a, bool has_a,
+                                     int pm) {
     int i, j, k;
     cell_coords<DIM, T>(n, c, i, j, k);
     const long sy = n[0], sz = (long)n[0] * n[1];
     T dg = T(1);
     T wn, unused;
-    nb_pair(w0, w0, c, c - 1, i > 0, wn, unused); dg += wn;
-    nb_pair(w0, w0, c, c + 1, i + 1 < n[0], wn, unused); dg += wn;
-    nb_pair(w1, w1, c, c - sy, j > 0, wn, unused); dg += wn;
-    nb_pair(w1, w1, c, c + sy, j + 1 < n[1], wn, unused); dg += wn;
+    nb_lo(w0, w0, c, i, n[0], 1, ((pm) >> 0) & 1, wn, unused); dg += wn;
+    nb_hi(w0, w0, c, i, n[0], 1, ((pm) >> 0) & 1, wn, unused); dg += wn;
+    nb_lo(w1, w1, c, j, n[1], sy, ((pm) >> 1) & 1, wn, unused); dg += wn;
+    nb_hi(w1, w1, c, j, n[1], sy, ((pm) >> 1) & 1, wn, unused); dg += wn;
     if (DIM == 3) {
-        nb_pair(w2, w2, c, c - sz, k > 0, wn, unused); dg += wn;
-        nb_pair(w2, w2, c, c + sz, k + 1 < n[2], wn, unused); dg += wn;
+        nb_lo(w2, w2, c, k, n[2], sz, ((pm) >> 2) & 1, wn, unused); dg += wn;
+        nb_hi(w2, w2, c, k, n[2], sz, ((pm) >> 2) & 1, wn, unused); dg += wn;
     }
     if (has_a) dg += a[c];
     return dg;
@@ -856,7 +887,7 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
 // registers of the thread owning the cell.  w, b and x may be global or LDS.
 template <int DIM, typename T, int NT, int CPT>
 __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b, T* x,
-                         bool warm, T* p_sh, double* red, const T* a, bool has_a) {
+                         bool warm, T* p_sh, double* red, const T* a, bool has_a, int pm) {
     const int ncell = n[0] * n[1] * n[2];
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
     const double tol2 = 1e-12;                 // (1e-6)^2 relative
@@ -868,7 +899,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
         r[m] = T(0);
         dinv[m] = T(0);
         if (c < ncell) {
-            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c, a, has_a);
+            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c, a, has_a, pm);
             xr[m] = warm ? x[c] : T(0);
             p_sh[c] = xr[m];
         }
@@ -880,7 +911,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
         if (c < ncell) {
             T dg;
             r[m] = b[c];
-            if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a);
+            if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a, pm);
         }
     }
     __syncthreads();
@@ -906,7 +937,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
                 q[m] = T(0);
                 if (c < ncell) {
                     T dg;
-                    q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a);
+                    q[m] = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a, pm);
                     pq += (double)p_sh[c] * (double)q[m];
                 }
             }
@@ -964,7 +995,8 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     // from it.  Every other coarsest level solves for a correction from zero.
     const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
-        block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red, ag, has_a);
+        block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red, ag, has_a,
+                                                     d.per_mask);
         return;
     }
     const int maxit = 2000;
@@ -980,7 +1012,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     __syncthreads();
     for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
         T dg;
-        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg, ag, has_a);
+        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg, ag, has_a, d.per_mask);
         const T rc = bg[c] - ax;
         const T z = rc / dg;
         r[c] = rc;
@@ -995,7 +1027,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
         double pq = 0.0, unused = 0.0;
         for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
             T dg;
-            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg, ag, has_a);
+            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg, ag, has_a, d.per_mask);
             q[c] = qc;
             pq += (double)p[c] * (double)qc;
         }
@@ -1560,6 +1592,7 @@ struct TailGeom {
     float rnx;           // 1 / nx
     int32_t ox, ob, ow[3];
     int32_t oa, has_a;   // Dirichlet ghost couplings (plans with Dirichlet faces)
+    int32_t pm;          // periodic axes (bit per axis)
 };
 
 template <typename T>
@@ -1575,6 +1608,7 @@ struct TailLevel {
     T* w[3];
     T* a;
     int32_t has_a;
+    int32_t pm;
 };
 
 template <typename T>
@@ -1591,6 +1625,7 @@ __device__ __forceinline__ TailLevel<T> tl_at(const TailGeom& g, T* base) {
     for (int a = 0; a < 3; ++a) t.w[a] = base + g.ow[a];
     t.a = base + g.oa;
     t.has_a = g.has_a;
+    t.pm = g.pm;
     return t;
 }
 constexpr int kMaxTail = 16;
@@ -1630,18 +1665,18 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
         const long c = i + j * sy + k * sz;
         T s = lv.b[c], dg = T(1);
         T wl, xl, wr, xr, wd, xd, wu, xu;
-        nb_pair(lv.w[0], lv.x, c, c - 1, i > 0, wl, xl);
-        nb_pair(lv.w[0], lv.x, c, c + 1, i + 1 < lv.n[0], wr, xr);
-        nb_pair(lv.w[1], lv.x, c, c - sy, j > 0, wd, xd);
-        nb_pair(lv.w[1], lv.x, c, c + sy, j + 1 < lv.n[1], wu, xu);
+        nb_lo(lv.w[0], lv.x, c, i, lv.n[0], 1, ((lv.pm) >> 0) & 1, wl, xl);
+        nb_hi(lv.w[0], lv.x, c, i, lv.n[0], 1, ((lv.pm) >> 0) & 1, wr, xr);
+        nb_lo(lv.w[1], lv.x, c, j, lv.n[1], sy, ((lv.pm) >> 1) & 1, wd, xd);
+        nb_hi(lv.w[1], lv.x, c, j, lv.n[1], sy, ((lv.pm) >> 1) & 1, wu, xu);
         s += wl * xl; dg += wl;
         s += wr * xr; dg += wr;
         s += wd * xd; dg += wd;
         s += wu * xu; dg += wu;
         if (DIM == 3) {
             T wb, xb, wf, xf;
-            nb_pair(lv.w[2], lv.x, c, c - sz, k > 0, wb, xb);
-            nb_pair(lv.w[2], lv.x, c, c + sz, k + 1 < lv.n[2], wf, xf);
+            nb_lo(lv.w[2], lv.x, c, k, lv.n[2], sz, ((lv.pm) >> 2) & 1, wb, xb);
+            nb_hi(lv.w[2], lv.x, c, k, lv.n[2], sz, ((lv.pm) >> 2) & 1, wf, xf);
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
@@ -1693,6 +1728,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
         t.oa = o;                                          // unused without Dirichlet faces
         t.has_a = hasa;
+        t.pm = d0.per_mask;
     }
     __syncthreads();
     T* const sbase = reinterpret_cast<T*>(tail_smem);
@@ -1742,7 +1778,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
             for (int q = 0; q < (1 << DIM); ++q)
                 sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
                                            2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
-                                           f.has_a != 0);
+                                           f.has_a != 0, f.pm);
             cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
             cT.x[c] = T(0);
         }
@@ -1752,7 +1788,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     {
         const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
         block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red, cT.a,
-                                                 cT.has_a != 0);
+                                                 cT.has_a != 0, cT.pm);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
@@ -1885,7 +1921,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
             ix[m_] = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
             rv[m_] = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
                                               as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
-                                              d.n, i, j, k, as_global(d.ad), d.ad != nullptr);
+                                              d.n, i, j, k, as_global(d.ad), d.ad != nullptr, d.per_mask);
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
@@ -1958,11 +1994,14 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
 
 // Neighbour weight and search-direction value for k_cg_pq (see nb_pair).
 template <typename F>
-__device__ __forceinline__ void nb_p(gptr<double> w, long idx, long nb, bool has, const F& p_at, double& wn,
-                                     double& pn) {
-    const double wv = w[has ? (nb > idx ? nb : idx) : idx];
+__device__ __forceinline__ void nb_p(gptr<double> w, long idx, int i, int n, long st, bool per, bool upper,
+                                     const F& p_at, double& wn, double& pn) {
+    const bool has = upper ? (i + 1 < n || per) : (i > 0 || per);
+    const long nb = upper ? (i + 1 < n ? idx + st : (per ? idx - (long)(n - 1) * st : idx))
+                          : (i > 0 ? idx - st : (per ? idx + (long)(n - 1) * st : idx));
+    const double wv = w[upper ? nb : idx];
     wn = has ? wv : 0.0;
-    pn = p_at(has ? nb : idx);
+    pn = p_at(nb);
 }
 
 template <int DIM, bool MIXED>
@@ -1999,10 +2038,11 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                 const double pc = p_at(idx);
                 const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
                 double wl, pl, wr, pr, wd, pd, wu, pu;
-                nb_p(w0, idx, idx - 1, i > 0, p_at, wl, pl);
-                nb_p(w0, idx, idx + 1, i + 1 < d.n[0], p_at, wr, pr);
-                nb_p(w1, idx, idx - sy, j > 0, p_at, wd, pd);
-                nb_p(w1, idx, idx + sy, j + 1 < d.n[1], p_at, wu, pu);
+                const int pm = d.per_mask;
+                nb_p(w0, idx, i, d.n[0], 1, pm & 1, false, p_at, wl, pl);
+                nb_p(w0, idx, i, d.n[0], 1, pm & 1, true, p_at, wr, pr);
+                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, false, p_at, wd, pd);
+                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, true, p_at, wu, pu);
                 double q = pc;
                 q += wl * (pc - pl);
                 q += wr * (pc - pr);
@@ -2011,8 +2051,8 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                 if (DIM == 3) {
                     const gptr<double> w2 = as_global(d.w[2]);
                     double wb, pb, wf, pf;
-                    nb_p(w2, idx, idx - sz, k > 0, p_at, wb, pb);
-                    nb_p(w2, idx, idx + sz, k + 1 < d.n[2], p_at, wf, pf);
+                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, false, p_at, wb, pb);
+                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, true, p_at, wf, pf);
                     q += wb * (pc - pb);
                     q += wf * (pc - pf);
                 }

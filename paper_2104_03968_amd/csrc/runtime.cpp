@@ -52,12 +52,15 @@ int validate_opts(const fld_opts& o) {
     if (o.limiter < FLD_LIMITER_LP || o.limiter > FLD_LIMITER_LP_EXACT) return FLD_ERR_INVALID_ARG;
     for (int f = 0; f < 6; ++f) {
         if (o.bc[f] < 0) return FLD_ERR_INVALID_ARG;
-        if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT && o.bc[f] != FLD_BC_DIRICHLET)
+        if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT && o.bc[f] != FLD_BC_DIRICHLET &&
+            o.bc[f] != FLD_BC_PERIODIC)
             return FLD_ERR_UNSUPPORTED;
         if (!std::isfinite(o.bc_grad[f])) return FLD_ERR_INVALID_ARG;
         if (o.bc[f] == FLD_BC_DIRICHLET && !(o.bc_value[f] >= 0.0 && std::isfinite(o.bc_value[f])))
             return FLD_ERR_INVALID_ARG;
     }
+    for (int a = 0; a < 3; ++a)
+        if ((o.bc[2 * a] == FLD_BC_PERIODIC) != (o.bc[2 * a + 1] == FLD_BC_PERIODIC)) return FLD_ERR_INVALID_ARG;
     if (o.precision != FLD_PREC_FP64 && o.precision != FLD_PREC_MIXED) return FLD_ERR_INVALID_ARG;
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) return FLD_ERR_INVALID_ARG;
     if (o.max_cycles < 1 || o.max_cycles > 100000) return FLD_ERR_INVALID_ARG;
@@ -178,6 +181,8 @@ static void build_levels(Plan& p) {
             d.level = lev;
             d.coarse = -1;
             d.fine = lev == 0 ? -1 : (int32_t)p.levels.size() - 1;
+            for (int a = 0; a < gr.ndim; ++a)
+                if (p.opts.bc[2 * a] == FLD_BC_PERIODIC) d.per_mask |= 1 << a;
             if (lev == 0) {
                 for (int f = 0; f < 2 * gr.ndim; ++f) {
                     const double G = p.opts.bc[f] == FLD_BC_FIXED_GRADIENT ? p.opts.bc_grad[f] : 0.0;
@@ -189,6 +194,7 @@ static void build_levels(Plan& p) {
                         d.bcv[f] = p.opts.bc_value[f];
                         d.has_bc = 1;
                     }
+                    if (p.opts.bc[f] == FLD_BC_PERIODIC) d.has_bc = 1;   // wrapped gradient ghosts
                 }
             }
             if (lev > 0) p.levels.back().coarse = (int32_t)p.levels.size();
@@ -285,8 +291,9 @@ static void build_lists(Plan& p) {
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
             max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
         D.fin_fused = max_tiles <= 32;
-        // the fused level kernels know no Dirichlet couplings: such plans sweep per colour
-        D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && fused2_supported(p.opts.nu1) &&
+        // the fused level kernels know no Dirichlet couplings or wrapped neighbours: such plans
+        // sweep per colour
+        D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && !p.has_per && fused2_supported(p.opts.nu1) &&
                   fused2_supported(p.opts.nu2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
@@ -296,7 +303,8 @@ static void build_lists(Plan& p) {
         }
         // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
         // even for its result to end in x
-        D.fused3 = D.dim == 3 && p.opts.fused && !p.has_dir && fused3_supported(p.mixed) && p.opts.nu1 >= 1 &&
+        D.fused3 = D.dim == 3 && p.opts.fused && !p.has_dir && !p.has_per && fused3_supported(p.mixed) &&
+                   p.opts.nu1 >= 1 &&
                    p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0;
         D.sw3.resize(D.fused3 ? maxdepth : 0);
         D.sr3.resize(D.fused3 ? maxdepth : 0);
@@ -343,10 +351,13 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.mixed = opts.precision == FLD_PREC_MIXED;
     p.krylov = opts.krylov != 0;
     p.has_dir = false;
+    p.has_per = false;
     for (int f = 0; f < 6; ++f) {
-        if (opts.bc[f] != FLD_BC_DIRICHLET) continue;
-        for (int g = 0; g < ngrids; ++g)
-            if (f < 2 * grids[g].ndim) p.has_dir = true;
+        for (int g = 0; g < ngrids; ++g) {
+            if (f >= 2 * grids[g].ndim) continue;
+            if (opts.bc[f] == FLD_BC_DIRICHLET) p.has_dir = true;
+            if (opts.bc[f] == FLD_BC_PERIODIC) p.has_per = true;
+        }
     }
     p.grids.assign(grids, grids + ngrids);
     for (auto& g : p.grids)

@@ -61,7 +61,8 @@ def test_plan_create_validates_grids(n, ok):
 @pytest.mark.parametrize("kw,code", [
     (dict(rtol=0.0), -1), (dict(rtol=2.0), -1), (dict(c=-1.0), -1), (dict(limiter=7), -1),
     (dict(precision=3), -1), (dict(max_cycles=0), -1), (dict(nu1=0, nu2=0), -1),
-    (dict(bc=[3, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[4, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[3, 0, 0, 0, 0, 0]), -1), (dict(bc=[0, 0, 0, 3, 0, 0]), -1),
     (dict(bc=[2, 0, 0, 0, 0, 0], bc_value=[-1.0, 0, 0, 0, 0, 0]), -1),
     (dict(bc=[0, 2, 0, 0, 0, 0], bc_value=[0, float("inf"), 0, 0, 0, 0]), -1),
     (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1),
