@@ -215,7 +215,8 @@ struct Control {
 // All launches are asynchronous on `s`.  `nblk` caps the persistent grid size.
 // Reductions finish on the device: the block that completes a grid's last tile sums
 // the grid's tile partials in a fixed order and applies the FinMode update.
-void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+// bc: the plan has faces other than zero flux (selects the instantiation that handles them).
+void launch_coeff(int dim, bool mixed, int bc, const LevelDesc* L, GridState* S, JobList jl,
                   const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s);
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
@@ -259,7 +260,8 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
 bool fused3_supported(bool fp32);
 void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
                    int from_xs, int fz, int nblk, hipStream_t s);
-void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
+// bc: the plan has Dirichlet or periodic faces.
+void launch_tail(int dim, bool fp32, int bc, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s);
 // LDS bytes of a tail whose finest level has cells n0 and whose levels halve down to
 // `levels` levels: x, b and DIM face arrays per level plus one coarsest vector.

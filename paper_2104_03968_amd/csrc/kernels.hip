@@ -400,7 +400,9 @@ __device__ __forceinline__ double face_w(double DL, double DR, double dt, double
     return dt * (2.0 * DL * DR / (DL + DR)) * (hinv * hinv);
 }
 
-template <int DIM, bool MIXED>
+// BC: the plan has faces other than zero flux (fixed gradient, Dirichlet, periodic); the
+// zero-flux instantiation carries none of their code.
+template <int DIM, bool MIXED, bool BC>
 __global__ void __launch_bounds__(kBlock)
 k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         const StepIO* __restrict__ io, double c, int limiter, int fin, double rtol, int max_cycles) {
@@ -424,8 +426,8 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
                 const double e = p.E_in[idx];
                 double wx = 0.0, wy = 0.0, wz = 0.0;
-                const LevelDesc* gh = d.has_bc ? &d : nullptr;
-                const int pm = d.per_mask;
+                const LevelDesc* gh = (BC && d.has_bc) ? &d : nullptr;
+                const int pm = BC ? d.per_mask : 0;
                 double Da[3] = {0.0, 0.0, 0.0};               // the cell's D along each direction
                 if (!p.krd[0]) {
                     const double kk = p.kr[idx];
@@ -474,7 +476,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 // the cell's own D): alpha = dt D / h^2 on the diagonal, alpha E_B in b
                 double bsrc = e;
                 double al = 0.0;
-                if (d.has_bc) {
+                if (BC && d.has_bc) {
                     const int ci[3] = {i, j, k};
                     for (int a = 0; a < DIM; ++a) {
                         const double wa = dt * Da[a] * d.hinv[a] * d.hinv[a];
@@ -488,7 +490,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                         }
                     }
                 }
-                if (d.ad) {                                 // every cell: coarsening reads them all
+                if (BC && d.ad) {                           // every cell: coarsening reads them all
                     d.ad[idx] = al;
                     if (MIXED) d.ad32[idx] = (float)al;
                 }
@@ -1649,8 +1651,9 @@ __device__ __forceinline__ void tl_coords(const TailLevel<T>& lv, int c, int& i,
 
 // Levels are passed by value: a copy in registers, since the LDS stores of a phase
 // could otherwise alias the descriptor table in LDS and force its re-reading.
-template <int DIM, typename T>
+template <int DIM, typename T, bool BC>
 __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) {
+    const int pmask = BC ? lv.pm : 0;
     const int sy = lv.n[0], sz = lv.n[0] * lv.n[1];
     const int rows = lv.n[1] * lv.n[2];
     for (int m = threadIdx.x; m < rows * lv.hx; m += kTailThreads) {
@@ -1665,28 +1668,29 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
         const long c = i + j * sy + k * sz;
         T s = lv.b[c], dg = T(1);
         T wl, xl, wr, xr, wd, xd, wu, xu;
-        nb_lo(lv.w[0], lv.x, c, i, lv.n[0], 1, ((lv.pm) >> 0) & 1, wl, xl);
-        nb_hi(lv.w[0], lv.x, c, i, lv.n[0], 1, ((lv.pm) >> 0) & 1, wr, xr);
-        nb_lo(lv.w[1], lv.x, c, j, lv.n[1], sy, ((lv.pm) >> 1) & 1, wd, xd);
-        nb_hi(lv.w[1], lv.x, c, j, lv.n[1], sy, ((lv.pm) >> 1) & 1, wu, xu);
+        nb_lo(lv.w[0], lv.x, c, i, lv.n[0], 1, ((pmask) >> 0) & 1, wl, xl);
+        nb_hi(lv.w[0], lv.x, c, i, lv.n[0], 1, ((pmask) >> 0) & 1, wr, xr);
+        nb_lo(lv.w[1], lv.x, c, j, lv.n[1], sy, ((pmask) >> 1) & 1, wd, xd);
+        nb_hi(lv.w[1], lv.x, c, j, lv.n[1], sy, ((pmask) >> 1) & 1, wu, xu);
         s += wl * xl; dg += wl;
         s += wr * xr; dg += wr;
         s += wd * xd; dg += wd;
         s += wu * xu; dg += wu;
         if (DIM == 3) {
             T wb, xb, wf, xf;
-            nb_lo(lv.w[2], lv.x, c, k, lv.n[2], sz, ((lv.pm) >> 2) & 1, wb, xb);
-            nb_hi(lv.w[2], lv.x, c, k, lv.n[2], sz, ((lv.pm) >> 2) & 1, wf, xf);
+            nb_lo(lv.w[2], lv.x, c, k, lv.n[2], sz, ((pmask) >> 2) & 1, wb, xb);
+            nb_hi(lv.w[2], lv.x, c, k, lv.n[2], sz, ((pmask) >> 2) & 1, wf, xf);
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
-        if (lv.has_a) dg += lv.a[c];
+        if (BC && lv.has_a) dg += lv.a[c];
         lv.x[c] = s / dg;
     }
     __syncthreads();
 }
 
-template <int DIM, typename T>
+// BC: the plan has Dirichlet or periodic faces (extra diagonal, wrapped neighbours).
+template <int DIM, typename T, bool BC>
 __global__ void __launch_bounds__(kTailThreads)
 k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int nu1, int nu2,
        int plain64) {
@@ -1697,7 +1701,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     const int first = jl.levels[blockIdx.x];
     const LevelDesc& d0 = L[first];
     if (!S[d0.grid].active) return;
-    const int hasa = Arr<T>::ad(d0) != nullptr ? 1 : 0;
+    const int hasa = (BC && Arr<T>::ad(d0) != nullptr) ? 1 : 0;
     // the grid's levels from `first` down are consecutive descriptors: thread m reads
     // level m's (no chain through the coarse links), then the LDS layout follows
     const int nl = min(d0.nlev - d0.level, kMaxTail);
@@ -1728,7 +1732,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
         t.oa = o;                                          // unused without Dirichlet faces
         t.has_a = hasa;
-        t.pm = d0.per_mask;
+        t.pm = BC ? d0.per_mask : 0;
     }
     __syncthreads();
     T* const sbase = reinterpret_cast<T*>(tail_smem);
@@ -1767,8 +1771,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         const TailLevel<T> f = tl_at(tl[m], sbase);
         const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
         for (int it = 0; it < nu1; ++it) {
-            tl_half_sweep<DIM, T>(f, 0);
-            tl_half_sweep<DIM, T>(f, 1);
+            tl_half_sweep<DIM, T, BC>(f, 0);
+            tl_half_sweep<DIM, T, BC>(f, 1);
         }
         for (int c = threadIdx.x; c < cT.ncell; c += kTailThreads) {
             int I, J, K;
@@ -1778,7 +1782,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
             for (int q = 0; q < (1 << DIM); ++q)
                 sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
                                            2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
-                                           f.has_a != 0, f.pm);
+                                           BC && f.has_a != 0, BC ? f.pm : 0);
             cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
             cT.x[c] = T(0);
         }
@@ -1788,7 +1792,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     {
         const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
         block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red, cT.a,
-                                                 cT.has_a != 0, cT.pm);
+                                                 BC && cT.has_a != 0, BC ? cT.pm : 0);
     }
     // ascend
     for (int m = nl - 2; m >= 0; --m) {
@@ -1801,8 +1805,8 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
         __syncthreads();
         for (int it = 0; it < nu2; ++it) {
-            tl_half_sweep<DIM, T>(f, 1);
-            tl_half_sweep<DIM, T>(f, 0);
+            tl_half_sweep<DIM, T, BC>(f, 1);
+            tl_half_sweep<DIM, T, BC>(f, 0);
         }
     }
     {
@@ -2306,15 +2310,17 @@ inline int blocks_for_xcd(int total, int nblk) {
 #define FLD_DISPATCH_DIM(dim, ...) \
     do { if ((dim) == 3) { constexpr int D = 3; __VA_ARGS__; } else { constexpr int D = 2; __VA_ARGS__; } } while (0)
 
-void launch_coeff(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
+void launch_coeff(int dim, bool mixed, int bc, const LevelDesc* L, GridState* S, JobList jl,
                   const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     if (jl.total <= 0) return;
     const int g = blocks_for_xcd(jl.total, nblk);
+#define FLD_COEFF(M, B) hipLaunchKernelGGL((k_coeff<D, M, B>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles)
     FLD_DISPATCH_DIM(dim, {
-        if (mixed) hipLaunchKernelGGL((k_coeff<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
-        else hipLaunchKernelGGL((k_coeff<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles);
+        if (bc) { if (mixed) FLD_COEFF(true, true); else FLD_COEFF(false, true); }
+        else { if (mixed) FLD_COEFF(true, false); else FLD_COEFF(false, false); }
     });
+#undef FLD_COEFF
 }
 
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
@@ -2474,22 +2480,31 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
     }));
 }
 
+template <int DIM, typename T, bool BC>
+static hipError_t tail_lds(size_t smem) {
+    return hipFuncSetAttribute((const void*)k_tail<DIM, T, BC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+}
 int prepare_tail(int dim, bool fp32, size_t smem) {
-    hipError_t e;
-    if (dim == 3) e = fp32 ? hipFuncSetAttribute((const void*)k_tail<3, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)
-                           : hipFuncSetAttribute((const void*)k_tail<3, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    else e = fp32 ? hipFuncSetAttribute((const void*)k_tail<2, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)
-                  : hipFuncSetAttribute((const void*)k_tail<2, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    return e == hipSuccess ? 0 : -1;
+    hipError_t e0, e1;
+    if (dim == 3) {
+        e0 = fp32 ? tail_lds<3, float, false>(smem) : tail_lds<3, double, false>(smem);
+        e1 = fp32 ? tail_lds<3, float, true>(smem) : tail_lds<3, double, true>(smem);
+    } else {
+        e0 = fp32 ? tail_lds<2, float, false>(smem) : tail_lds<2, double, false>(smem);
+        e1 = fp32 ? tail_lds<2, float, true>(smem) : tail_lds<2, double, true>(smem);
+    }
+    return (e0 == hipSuccess && e1 == hipSuccess) ? 0 : -1;
 }
 
-void launch_tail(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
+void launch_tail(int dim, bool fp32, int bc, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s) {
     if (jl.njobs <= 0) return;
+#define FLD_TAIL(T_, B) hipLaunchKernelGGL((k_tail<D, T_, B>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64)
     FLD_DISPATCH_DIM(dim, {
-        if (fp32) hipLaunchKernelGGL((k_tail<D, float>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64);
-        else hipLaunchKernelGGL((k_tail<D, double>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64);
+        if (bc) { if (fp32) FLD_TAIL(float, true); else FLD_TAIL(double, true); }
+        else { if (fp32) FLD_TAIL(float, false); else FLD_TAIL(double, false); }
     });
+#undef FLD_TAIL
 }
 
 void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,

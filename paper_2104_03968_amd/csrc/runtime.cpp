@@ -352,11 +352,13 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.krylov = opts.krylov != 0;
     p.has_dir = false;
     p.has_per = false;
+    p.any_bc = false;
     for (int f = 0; f < 6; ++f) {
         for (int g = 0; g < ngrids; ++g) {
             if (f >= 2 * grids[g].ndim) continue;
             if (opts.bc[f] == FLD_BC_DIRICHLET) p.has_dir = true;
             if (opts.bc[f] == FLD_BC_PERIODIC) p.has_per = true;
+            if (opts.bc[f] != FLD_BC_ZERO_FLUX) p.any_bc = true;
         }
     }
     p.grids.assign(grids, grids + ngrids);
@@ -518,7 +520,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         }
         launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     }
-    launch_tail(dim, f32, p.dL, p.dS, tail, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_tail(dim, f32, p.has_dir || p.has_per, p.dL, p.dS, tail, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
     launch_coarse_solve(dim, f32, p.dL, p.dS, coarsest, s);
     for (int d = D.maxdepth - 1; d >= d0; --d) {
         if (d < L3) {
@@ -553,7 +555,7 @@ static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
     const bool f32 = p.mixed;
     for (int d = 0; d < D.maxdepth; ++d) launch_restrict_rhs(D.dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
-    launch_tail(D.dim, f32, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_tail(D.dim, f32, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
     launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
     const int nv = p.opts.fmg_depths > 0 ? p.opts.fmg_depths : D.maxdepth;
     for (int d = D.maxdepth - 1; d >= 0; --d) {
@@ -776,7 +778,7 @@ int plan_prologue(Plan& p, hipStream_t s) {
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const JobList& l0 = D.l0_cell.dev;
-        launch_coeff(D.dim, p.mixed, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, D.fin_fused ? FIN_B : -1,
+        launch_coeff(D.dim, p.mixed, p.any_bc, p.dL, p.dS, l0, p.dIO, p.opts.c, p.opts.limiter, D.fin_fused ? FIN_B : -1,
                      p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
         if (!D.fin_fused) launch_finalize(p.dL, p.dS, l0, FIN_B, p.opts.rtol, p.opts.max_cycles, s);
         for (auto& c : D.coarsen)
@@ -1141,7 +1143,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level) launch_prolong(D.dim, p.mixed, p.dL, p.dS, D.prolong[level].dev, p.nblk, s);
                     break;
                 case FLD_KERNEL_COEFF:
-                    launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
+                    launch_coeff(D.dim, p.mixed, p.any_bc, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
                                  -1, p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
                     break;
                 case FLD_KERNEL_DOWN:
@@ -1159,7 +1161,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                         launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, p.tile_depth, p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
-                    launch_tail(D.dim, p.mixed, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
+                    launch_tail(D.dim, p.mixed, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
                     break;
                 default: break;
             }
@@ -1355,7 +1357,7 @@ int32_t fld_coefficients(fld_plan_t plan, const double* const* E_in, const doubl
         FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, G * sizeof(fld::StepIO), hipMemcpyHostToDevice, s));
         for (auto& D : p.dl) {
             if (D.l0_cell.empty()) continue;
-            fld::launch_coeff(D.dim, p.mixed, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
+            fld::launch_coeff(D.dim, p.mixed, p.any_bc, p.dL, p.dS, D.l0_cell.dev, p.dIO, p.opts.c, p.opts.limiter,
                               D.fin_fused ? fld::FIN_B : -1, p.opts.rtol, p.opts.max_cycles, fld::cell_blocks(p), s);
             if (!D.fin_fused)
                 fld::launch_finalize(p.dL, p.dS, D.l0_cell.dev, fld::FIN_B, p.opts.rtol, p.opts.max_cycles, s);
