@@ -153,7 +153,7 @@ def measured_traffic(cfg: str, kname: str, launch: dict):
     import hashlib
     src = os.path.join(ROOT, "paper_2104_03968_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    keys = ("tile_rows", "tile_wide", "max_blocks", "tile_depth", "fused3_levels", "tile_rows_coarse")
+    keys = ("tile_rows", "tile_wide", "max_blocks", "tile_depth", "fused3_levels", "tile_rows_coarse", "tile_rows_up")
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("traffic_record: "):
@@ -367,7 +367,8 @@ def main():
         "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
                    "rtol": 1e-10, "fmg": plan.opts.fmg, "fmg_depths": plan.opts.fmg_depths, "coarse_op": args.coarse_op,
                    "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
-                                                     "fused3_levels", "tile_rows_coarse", "source")}},
+                                                     "fused3_levels", "tile_rows_coarse", "tile_rows_up",
+                                                     "source")}},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

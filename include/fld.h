@@ -170,6 +170,9 @@ typedef struct fld_opts {
                              interpolated solution on as it is (0 = every level) [2] */
     double  bc_value[6];  /* per face: the ghost value E_B of FLD_BC_DIRICHLET faces,
                              finite and >= 0 (ignored elsewhere) [0]                 */
+    int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass: 4, 8, 16
+                             or 32; 0 = as tile_rows (which then sets the finest
+                             level's down pass alone) [0].  Must be 0 with autotune  */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
@@ -398,6 +401,8 @@ typedef struct fld_tuning {
                              per-colour kernels)                                    */
     int32_t fused3_levels;/* leading 3D levels with fused sweeps                    */
     int32_t tile_rows_coarse; /* fused 2D tile rows below the finest level              */
+    int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass (tile_rows:
+                             its down pass)                                          */
 } fld_tuning;
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);

@@ -2,11 +2,13 @@
 // transfers, tails; the solver state is only read) is timed for each
 // candidate launch shape and the fastest is kept.  The candidates are, one
 // dimension after the other: the fused 2D tile (64-wide or full-wave-wide,
-// 4/8/16/32 rows), then the rows of the levels below the finest; for 3D grids
+// 4/8/16/32 rows), then the rows of the levels below the finest, then the
+// finest level's rows again beside them, for its down and its up pass apart;
+// for 3D grids
 // the fused sweep's planes per block (16/32/64), then how many leading levels
 // run fused (or none: per-colour kernels); and the cap on persistent workgroups.
 // Choices are cached in a text file, one line per plan class:
-//     <key> TAB <wide> <rows> <max_blocks> <depth> <sweep3> <levels3> <microseconds> <coarse rows>
+//     <key> TAB <wide> <rows> <max_blocks> <depth> <sweep3> <levels3> <microseconds> <coarse rows> <up rows>
 // keyed by the device architecture, precision, sweep counts and the size
 // class of the plan's grids, so later plans of the same class skip the timing.
 // The cache file is $FLD_AUTOTUNE_CACHE, else $HOME/.cache/fld_autotune.txt;
@@ -52,7 +54,7 @@ std::string plan_key(const Plan& p) {
         cus = prop.multiProcessorCount;
     }
     char buf[512];
-    int n = std::snprintf(buf, sizeof(buf), "v4|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
+    int n = std::snprintf(buf, sizeof(buf), "v6|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
                           p.mixed ? "mixed" : "fp64", p.opts.nu1, p.opts.nu2, p.krylov ? 1 : 0, p.opts.fused);
     for (int dim = 2; dim <= 3; ++dim) {
         int count = 0;
@@ -83,8 +85,8 @@ bool cache_lookup(const std::string& key, Shape& out) {
         if (key != line) continue;
         Shape s{};
         double us = 0;
-        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %lf %d", &s.wide, &s.rows, &s.nblk, &s.depth, &s.sweep3,
-                        &s.levels3, &us, &s.rows_c) == 8) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %lf %d %d", &s.wide, &s.rows, &s.nblk, &s.depth, &s.sweep3,
+                        &s.levels3, &us, &s.rows_c, &s.rows_u) == 9) {
             out = s;                                   // the last record of a key wins
             found = true;
         }
@@ -98,8 +100,8 @@ void cache_store(const std::string& key, const Shape& s, double us) {
     if (path.empty()) return;
     FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%d %d %d %d %d %d %.3f %d\n", key.c_str(), s.wide, s.rows, s.nblk, s.depth, s.sweep3,
-                 s.levels3, us, s.rows_c);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %.3f %d %d\n", key.c_str(), s.wide, s.rows, s.nblk, s.depth, s.sweep3,
+                 s.levels3, us, s.rows_c, s.rows_u);
     std::fclose(f);
 }
 
@@ -200,6 +202,7 @@ int plan_autotune(Plan& p) {
                 s.wide = wide;
                 s.rows = rows;
                 s.rows_c = rows;
+                s.rows_u = rows;
                 c.push_back(s);
             }
         if ((rc = stage(c)) != FLD_OK) return rc;
@@ -212,6 +215,25 @@ int plan_autotune(Plan& p) {
                 continue;
             Shape s = best;
             s.rows_c = rows;
+            c.push_back(s);
+        }
+        if ((rc = stage(c)) != FLD_OK) return rc;
+        // and the finest level's rows once more, now beside the chosen coarse rows (the
+        // first stage moved all levels together), for its down pass and then its up pass
+        // apart (the down pass's wider halo favours taller tiles)
+        c.clear();
+        for (int rows : {4, 8, 16, 32}) {
+            if (rows == best.rows || !fused2_shape_ok(p.mixed, p.opts.nu1, best.wide, rows, true)) continue;
+            Shape s = best;
+            s.rows = rows;
+            c.push_back(s);
+        }
+        if ((rc = stage(c)) != FLD_OK) return rc;
+        c.clear();
+        for (int rows : {4, 8, 16, 32}) {
+            if (rows == best.rows_u || !fused2_shape_ok(p.mixed, p.opts.nu2, best.wide, rows, false)) continue;
+            Shape s = best;
+            s.rows_u = rows;
             c.push_back(s);
         }
         if ((rc = stage(c)) != FLD_OK) return rc;

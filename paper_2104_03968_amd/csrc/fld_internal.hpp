@@ -120,6 +120,7 @@ struct Plan {
     int tile_wide = 0;
     int tile_rows = 16;
     int tile_rows_c = 16;                      // fused 2D tile rows below the finest level
+    int tile_rows_u = 16;                      // fused 2D tile rows of the finest level's up pass
     int nblk = 2048;
     int tile_depth = 32;                       // fused 3D sweep: planes per block
     int sweep3 = 1;                            // 1: fused 3D sweeps where available; 0: per colour
@@ -182,7 +183,7 @@ int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s);
 int plan_autotune(Plan& p);
 void plan_vcycle_mg(Plan& p, hipStream_t s);             // the timed part: smoothing, transfers, tails
 struct LaunchShape {
-    int wide, rows, nblk, depth, sweep3, levels3, rows_c;
+    int wide, rows, nblk, depth, sweep3, levels3, rows_c, rows_u;
 };
 int plan_set_shape(Plan& p, const LaunchShape& s);         // rebuild and upload the fused lists
 LaunchShape plan_shape(const Plan& p);

@@ -74,6 +74,9 @@ int validate_opts(const fld_opts& o) {
     if (o.tile_rows_coarse != 0 && o.tile_rows_coarse != 4 && o.tile_rows_coarse != 8 &&
         o.tile_rows_coarse != 16 && o.tile_rows_coarse != 32)
         return FLD_ERR_INVALID_ARG;
+    if (o.tile_rows_up != 0 && o.tile_rows_up != 4 && o.tile_rows_up != 8 && o.tile_rows_up != 16 &&
+        o.tile_rows_up != 32)
+        return FLD_ERR_INVALID_ARG;
     if (o.tile_wide != 0 && o.tile_wide != 1) return FLD_ERR_INVALID_ARG;
     if (o.max_blocks < 0 || o.max_blocks > (1 << 20)) return FLD_ERR_INVALID_ARG;
     // the tuner picks the launch shape itself
@@ -81,7 +84,7 @@ int validate_opts(const fld_opts& o) {
         return FLD_ERR_INVALID_ARG;
     if (o.fused3_levels < 0 || o.fused3_levels > 64) return FLD_ERR_INVALID_ARG;
     if (o.autotune && (o.tile_rows || o.tile_wide || o.max_blocks || o.tile_depth || o.fused3_levels ||
-                       o.tile_rows_coarse))
+                       o.tile_rows_coarse || o.tile_rows_up))
         return FLD_ERR_INVALID_ARG;
     if (o.fmg != 0 && o.fmg != 1) return FLD_ERR_INVALID_ARG;
     if (o.fmg_depths < 0 || o.fmg_depths > 64) return FLD_ERR_INVALID_ARG;
@@ -153,8 +156,9 @@ void finish_fused(const Plan& p, DimLists& D) {
         dn.prefix.assign(1, 0);
         up.prefix.assign(1, 0);
         const int rows = dpt == 0 ? p.tile_rows : p.tile_rows_c;
+        const int rows_up = dpt == 0 ? p.tile_rows_u : p.tile_rows_c;
         for (int32_t li : dn.levels) dn.prefix.push_back(dn.prefix.back() + fused_tiles(p.levels[li].n, fxd, rows));
-        for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, rows));
+        for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, rows_up));
     }
 }
 
@@ -367,6 +371,7 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.tile_wide = opts.tile_wide;
     p.tile_rows = opts.tile_rows ? opts.tile_rows : 8;
     p.tile_rows_c = opts.tile_rows_coarse ? opts.tile_rows_coarse : p.tile_rows;
+    p.tile_rows_u = opts.tile_rows_up ? opts.tile_rows_up : p.tile_rows;
     p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
     p.tile_depth = opts.tile_depth ? opts.tile_depth : 32;
     p.sweep3_levels = opts.fused3_levels;
@@ -374,7 +379,8 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
         !(fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows, true) &&
           fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false) &&
           fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows_c, true) &&
-          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_c, false)))
+          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_c, false) &&
+          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_u, false)))
         return FLD_ERR_INVALID_ARG;                            // the tile does not fit the LDS
     build_levels(p);
     build_lists(p);
@@ -529,7 +535,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             continue;
         }
         if (D.fused) {
-            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, d == 0 ? p.tile_rows : p.tile_rows_c,
+            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, d == 0 ? p.tile_rows_u : p.tile_rows_c,
                        p.nblk, s);
             continue;
         }
@@ -647,7 +653,8 @@ static int upload_list(Plan& p, HostList& l) {
 }
 
 LaunchShape plan_shape(const Plan& p) {
-    return LaunchShape{p.tile_wide, p.tile_rows, p.nblk, p.tile_depth, p.sweep3, p.sweep3_levels, p.tile_rows_c};
+    return LaunchShape{p.tile_wide, p.tile_rows, p.nblk, p.tile_depth, p.sweep3, p.sweep3_levels, p.tile_rows_c,
+                       p.tile_rows_u};
 }
 
 int plan_set_shape(Plan& p, const LaunchShape& sh) {
@@ -656,7 +663,8 @@ int plan_set_shape(Plan& p, const LaunchShape& sh) {
         if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows, true) &&
                          fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows, false) &&
                          fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows_c, true) &&
-                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_c, false)))
+                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_c, false) &&
+                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_u, false)))
             return FLD_ERR_INVALID_ARG;
     if (sh.nblk < 1 || (sh.depth != 16 && sh.depth != 32 && sh.depth != 64) || (sh.sweep3 != 0 && sh.sweep3 != 1) ||
         sh.levels3 < 0)
@@ -664,6 +672,7 @@ int plan_set_shape(Plan& p, const LaunchShape& sh) {
     p.tile_wide = sh.wide;
     p.tile_rows = sh.rows;
     p.tile_rows_c = sh.rows_c;
+    p.tile_rows_u = sh.rows_u;
     p.nblk = sh.nblk;
     p.tile_depth = sh.depth;
     p.sweep3 = sh.sweep3;
@@ -1153,7 +1162,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2,
-                                                         p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
+                                                         p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
                                                          p.nblk, s);
                     break;
                 case FLD_KERNEL_SWEEP3:
@@ -1502,6 +1511,7 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     out->fused3 = l3 > 0 ? 1 : 0;
     out->fused3_levels = l3;
     out->tile_rows_coarse = p.tile_rows_c;
+    out->tile_rows_up = p.tile_rows_u;
     return FLD_OK;
 }
 

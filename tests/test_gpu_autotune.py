@@ -59,14 +59,14 @@ def test_every_tile_shape_gives_identical_results(precision):
         assert rel_l2(ref[i], x_or) <= 1e-10 * O.q_b(g.E) * 1.01
 
 
-@pytest.mark.parametrize("rows,rows_c", [(8, 4), (16, 4), (4, 32), (32, 8)])
-def test_coarse_tile_rows_give_identical_results(rows, rows_c):
+@pytest.mark.parametrize("rows,rows_c,rows_u", [(8, 4, 0), (16, 4, 8), (4, 32, 16), (32, 8, 4)])
+def test_coarse_tile_rows_give_identical_results(rows, rows_c, rows_u):
     grids = batch()
     ref, sref, _ = run_step(grids)
-    xs, st, rc = run_step(grids, tile_rows=rows, tile_rows_coarse=rows_c)
+    xs, st, rc = run_step(grids, tile_rows=rows, tile_rows_coarse=rows_c, tile_rows_up=rows_u)
     assert rc == 0
     for i in range(len(grids)):
-        assert np.array_equal(xs[i], ref[i]), (rows, rows_c, i)
+        assert np.array_equal(xs[i], ref[i]), (rows, rows_c, rows_u, i)
         assert st[i]["cycles"] == sref[i]["cycles"]
 
 
@@ -114,8 +114,8 @@ def test_autotuned_plan_matches_default_and_caches(precision, tmp_path, monkeypa
     assert len(lines) == 1
     key, rec = lines[0].split("\t")
     assert ("mixed" if precision else "fp64") in key
-    wide, rows, nblk, depth, sweep3, levels3, us, rows_c = rec.split()
-    assert int(rows_c) == t["tile_rows_coarse"]
+    wide, rows, nblk, depth, sweep3, levels3, us, rows_c, rows_u = rec.split()
+    assert int(rows_c) == t["tile_rows_coarse"] and int(rows_u) == t["tile_rows_up"]
     assert (int(wide), int(rows), int(nblk)) == (t["tile_wide"], t["tile_rows"], t["max_blocks"])
     assert int(depth) == t["tile_depth"]
 
