@@ -177,7 +177,7 @@ def cpu_baseline(g, steps_gas: bool):
 
 
 def serve_stream(args):
-    """Config 5: the served Poisson stream through the request server."""
+    """The served Poisson stream through the request server."""
     import threading
     import torch
     import workloads as W

@@ -103,7 +103,7 @@ def test_face_weights_match_oracle(shape, limiter):
     plan.close()
 
 
-def test_face_weights_full_size_config2():
+def test_face_weights_full_size_1024_squared():
     g = W.c2_inputs(1024)
     plan = fld.Plan([g.E.shape], h=[g.h])
     plan.coefficients([dev(g.E)], [dev(g.kappa_rho)], [g.dt])
@@ -125,7 +125,7 @@ def test_face_weights_full_size_config2():
 @pytest.mark.parametrize("krylov", [1, 0])
 @pytest.mark.parametrize("nu", [1, 2, 3, 4])
 @pytest.mark.parametrize("fmg", [1, 0])
-def test_config1_step_matches_lu(precision, krylov, nu, fmg):
+def test_pulse_64_squared_step_matches_lu(precision, krylov, nu, fmg):
     g = W.pulse_2d()
     x_or, info = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="lu")
     (x,), (st,), rc = run_step([g], precision=precision, rtol=_rtol_for(g), krylov=krylov, nu1=nu, nu2=nu,
@@ -211,7 +211,7 @@ def test_fused_and_per_colour_kernels_agree(precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_stiff_trajectory_converges_quickly(precision):
-    """A config-4 grid (288^2, dt = 9.2e-3, coarsest 9^2) whose third step sharpens D
+    """A grid of the 512-grid batch (288^2, dt = 9.2e-3, coarsest 9^2) whose third step sharpens D
     enough that plain V-cycles need ~30 iterations; CG with the V-cycle stays <= 16."""
     n, dt = W.c4_layout()[118]
     g = W.c4_grid(118, n, dt)

@@ -193,8 +193,8 @@ def test_conservation_and_residual_certificate():
     assert err / np.linalg.norm(x) <= O.q_b(g.E) * r / np.linalg.norm(g.E) * (1 + 1e-12)
 
 
-def test_config1_symmetry():
-    """The config-1 pulse sits on a cell corner: inputs are D4-symmetric, so D and E^{n+1} are."""
+def test_pulse_64_squared_symmetry():
+    """The 64^2 pulse sits on a cell corner: inputs are D4-symmetric, so D and E^{n+1} are."""
     g = W.pulse_2d()
     D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h, g.c)
     for T in (D.T, D[::-1, :], D[:, ::-1], D[::-1, ::-1].T):

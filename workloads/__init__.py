@@ -149,7 +149,7 @@ class GridInput:
 
 def pulse_2d(n: int = 64, kappa_rho: float = 10.0, amp: float = 1e3, sigma: float = 0.05,
              dt: float = 1e-3, c: float = 1.0, limiter: str = "lp") -> GridInput:
-    """Config 1: Gaussian pulse on the unit square, constant kappa*rho.
+    """The 64^2 pulse workload: a Gaussian pulse on the unit square, constant kappa*rho.
 
     ``E = 1 + amp*exp(-r^2/(2 sigma^2))`` with r measured from (1/2, 1/2).
     """
@@ -194,13 +194,13 @@ def gas_for(g: GridInput, seed: int, u_span=(-0.5, 0.5)) -> GridInput:
 
 
 def c2_inputs(n: int = 1024) -> GridInput:
-    """Config 2: 2D n x n, log10(kappa rho) in [-2, 2], log-normal E, gas, dt = 1e-3."""
+    """The 2D workload with gas: n x n, log10(kappa rho) in [-2, 2], log-normal E, dt = 1e-3."""
     g = random_grid((n, n), 2000, dt=1e-3)
     return gas_for(g, 2003)
 
 
 def c3_inputs(n: int = 256, backend: str = "numpy", device=None) -> GridInput:
-    """Config 3: 3D n^3 with the config-2 field recipe in 3D (seeds 3001, 3002), dt = 1e-3."""
+    """The 3D workload: n^3 with the 2D workload's field recipe in 3D (seeds 3001, 3002), dt = 1e-3."""
     return random_grid((n, n, n), 3000, dt=1e-3, backend=backend, device=device)
 
 
@@ -209,7 +209,7 @@ C4_SIDES = tuple(range(64, 513, 32))           # {64, 96, ..., 512}: 15 values
 
 def c4_layout(n_grids: int = 512, sides: Sequence[int] = C4_SIDES, seed: int = 4000,
               dt_range=(1e-4, 1e-2)):
-    """Config 4 sizes and time steps: side ``n_j ~ U(sides)``, ``dt_j ~ U[dt_range]``."""
+    """Sizes and time steps of the 512-grid batch: side ``n_j ~ U(sides)``, ``dt_j ~ U[dt_range]``."""
     rng = np.random.default_rng(seed)
     ns = rng.choice(np.asarray(sides), size=n_grids)
     dts = rng.uniform(dt_range[0], dt_range[1], size=n_grids)
@@ -217,12 +217,12 @@ def c4_layout(n_grids: int = 512, sides: Sequence[int] = C4_SIDES, seed: int = 4
 
 
 def c4_grid(j: int, n: int, dt: float, backend: str = "numpy", device=None) -> GridInput:
-    """Grid ``j`` of config 4 (its own opacity / energy fields)."""
+    """Grid ``j`` of the 512-grid batch (its own opacity / energy fields)."""
     return random_grid((n, n), 4 * 10 ** 6 + 10 * j, dt=dt, backend=backend, device=device)
 
 
 def c4_inputs(n_grids: int = 512, **kw) -> List[GridInput]:
-    """Config 4: independent 2D grids with seeded sides, dt and fields."""
+    """The 512-grid batch: independent 2D grids with seeded sides, dt and fields."""
     return [c4_grid(j, n, dt) for j, (n, dt) in enumerate(c4_layout(n_grids, **kw))]
 
 
@@ -250,7 +250,7 @@ C5_SIDES_3D = tuple(range(32, 193, 16))        # {32, 48, ..., 192}
 def c5_stream(n_requests: int = 4096, rate: float = 2000.0, seed: int = 5000,
               sides_2d: Sequence[int] = C5_SIDES_2D, sides_3d: Sequence[int] = C5_SIDES_3D,
               dt_range=(1e-4, 1e-2)) -> List[Request]:
-    """Config 5: Poisson arrivals of mixed 2D / 3D solves (exponential gaps)."""
+    """The served stream: Poisson arrivals of mixed 2D / 3D solves (exponential gaps)."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n_requests)
     t = np.cumsum(gaps) - gaps[0]
