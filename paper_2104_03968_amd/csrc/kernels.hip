@@ -296,9 +296,9 @@ k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
 // ---------------------------------------------------------------------------
 // K1: coefficients.  R = |grad E|/(kappa rho E) with the 4th-order central
 // gradient (mirrored ghosts), lambda(R), D = c lambda/(kappa rho), and the
-// lower-face weights dt * 2 D_L D_R/(D_L + D_R) / h^2.  The D of a lower
-// neighbour is recomputed from its own stencil (same arithmetic as that
-// neighbour's thread), so each face is written once with no second pass.
+// lower-face weights dt * 2 D_L D_R/(D_L + D_R) / h^2.  A first pass stores each
+// cell's D; the face pass reads the two D of each face (with a diagonal-tensor D
+// the face pass recomputes the lower neighbour's from its own stencil).
 // ---------------------------------------------------------------------------
 // 4th-order central gradient of E at cell (i, j, k) with mirrored ghosts (Sec. 3.2,
 // eq. ileyk_flux); c12 = 1 / (12 h) per axis.  g[2] is 0 in 2D.
@@ -400,6 +400,35 @@ __device__ __forceinline__ double face_w(double DL, double DR, double dt, double
     return dt * (2.0 * DL * DR / (DL + DR)) * (hinv * hinv);
 }
 
+// First pass of the coefficients: D = c lambda(R) / (kappa rho) once per level-0 cell,
+// stored in the level's residual array (free until the initial residual), so the face
+// pass reads each face's two D instead of recomputing the neighbour's stencil.  Grids
+// with a diagonal-tensor D compute theirs in the face pass.
+template <int DIM, bool BC>
+__global__ void __launch_bounds__(kBlock)
+k_cell_D(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__ io, double c, int limiter) {
+    const XcdOrder order(jl.total);
+    for (int k_ = order.first(); order.more(k_); k_ += order.per) {
+        const int t = order.tile(k_);
+        const int jb = find_job(jl.prefix, jl.njobs, t);
+        const LevelDesc& d = L[jl.levels[jb]];
+        const StepIO& p = io[d.grid];
+        if (p.krd[0]) continue;                                  // uniform per tile
+        const int lt = t - jl.prefix[jb];
+        const LevelDesc* gh = (BC && d.has_bc) ? &d : nullptr;
+        const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            int i, j, k;
+            cell_of_l0tile<DIM>(d.n, lt, threadIdx.x + m_ * kBlock, i, j, k);
+            if (i < d.n[0] && j < d.n[1] && k < d.n[2]) {
+                const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
+                d.R[idx] = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
+            }
+        }
+    }
+}
+
 // BC: the plan has faces other than zero flux (fixed gradient, Dirichlet, periodic); the
 // zero-flux instantiation carries none of their code.
 template <int DIM, bool MIXED, bool BC>
@@ -433,15 +462,18 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     const double kk = p.kr[idx];
                     const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
                     if (!ok) atomicOr(&S[d.grid].bad, 1);
-                    const double Dc = cell_D<DIM>(p.E_in, p.kr, i, j, k, d.n, c12, c, limiter, gh);
+                    // cell D from the pass before (k_cell_D, kept in the residual array)
+                    const double* Dg = d.R;
+                    const double Dc = Dg[idx];
                     Da[0] = Da[1] = Da[2] = Dc;
                     // the face below; on a periodic axis the first cell's is the wrap face
-                    const int im = i > 0 ? i - 1 : d.n[0] - 1, jm = j > 0 ? j - 1 : d.n[1] - 1;
-                    const int km = k > 0 ? k - 1 : d.n[2] - 1;
-                    if (i > 0 || (pm & 1)) wx = face_w(cell_D<DIM>(p.E_in, p.kr, im, j, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[0]);
-                    if (j > 0 || (pm & 2)) wy = face_w(cell_D<DIM>(p.E_in, p.kr, i, jm, k, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[1]);
-                    if (DIM == 3 && (k > 0 || (pm & 4)))
-                        wz = face_w(cell_D<DIM>(p.E_in, p.kr, i, j, km, d.n, c12, c, limiter, gh), Dc, dt, d.hinv[2]);
+                    const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+                    const long ixm = i > 0 ? idx - 1 : idx + (d.n[0] - 1);
+                    const long iym = j > 0 ? idx - sy : idx + (d.n[1] - 1) * sy;
+                    const long izm = k > 0 ? idx - sz : idx + (d.n[2] - 1) * sz;
+                    if (i > 0 || (pm & 1)) wx = face_w(Dg[ixm], Dc, dt, d.hinv[0]);
+                    if (j > 0 || (pm & 2)) wy = face_w(Dg[iym], Dc, dt, d.hinv[1]);
+                    if (DIM == 3 && (k > 0 || (pm & 4))) wz = face_w(Dg[izm], Dc, dt, d.hinv[2]);
                 } else {
                     // diagonal-tensor D: the faces normal to direction a use (kappa rho)_a
                     bool ok = (e > 0.0) && isfinite(e);
@@ -2317,6 +2349,8 @@ void launch_coeff(int dim, bool mixed, int bc, const LevelDesc* L, GridState* S,
     const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_COEFF(M, B) hipLaunchKernelGGL((k_coeff<D, M, B>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles)
     FLD_DISPATCH_DIM(dim, {
+        if (bc) hipLaunchKernelGGL((k_cell_D<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl, io, c, limiter);
+        else hipLaunchKernelGGL((k_cell_D<D, false>), dim3(g), dim3(kBlock), 0, s, L, jl, io, c, limiter);
         if (bc) { if (mixed) FLD_COEFF(true, true); else FLD_COEFF(false, true); }
         else { if (mixed) FLD_COEFF(true, false); else FLD_COEFF(false, false); }
     });
