@@ -24,9 +24,10 @@ constexpr int kSX = 128;
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseCPT = 4;
 constexpr int kCoarseMaxLDS = kCoarseThreads * kCoarseCPT;   // 4096 cells
-// LDS tail: one 256-thread workgroup per grid; its coarsest CG holds up to 8 cells a thread.
-constexpr int kTailThreads = 256;
-constexpr int kTailCPT = 8;
+// LDS tail: one 512-thread workgroup per grid (measured ahead of 256 and 1024); its
+// coarsest CG holds up to 4 cells a thread.
+constexpr int kTailThreads = 512;
+constexpr int kTailCPT = 4;
 constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 
 // Tile counts of one level for the two tilings (host and device agree on these).
