@@ -870,15 +870,13 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         }
         FLD_HIP(hipGetLastError());
         done += nrun;
+        // CG stops on its recursive residual: the grids that stopped are confirmed on the
+        // true FP64 residual in the same round trip (a grid that misses the target
+        // restarts; grids still iterating are not touched)
+        if (p.krylov) plan_verify(p, s);
         launch_count(p.dS, G, p.dCtrl, s);
         FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         FLD_HIP(hipStreamSynchronize(s));
-        if (p.hCtrl->nactive == 0 && p.krylov) {
-            plan_verify(p, s);
-            launch_count(p.dS, G, p.dCtrl, s);
-            FLD_HIP(hipMemcpyAsync(p.hCtrl, p.dCtrl, sizeof(Control), hipMemcpyDeviceToHost, s));
-            FLD_HIP(hipStreamSynchronize(s));
-        }
         if (p.hCtrl->nactive == 0) break;
         burst = std::max(1, burst / 2);
     }
