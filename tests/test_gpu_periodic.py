@@ -126,3 +126,20 @@ def test_equal_direction_opacities_reproduce_the_isotropic_step_bitwise(kinds):
     for i in range(len(gs)):
         assert torch.equal(a[i], b[i]) and sa[i]["cycles"] == sb[i]["cycles"]
     plan.close()
+
+
+def test_moments_use_the_wrapped_ghosts():
+    g = W.random_grid((40, 52), 66500, dt=1e-3)
+    kinds = ["periodic"] * 4
+    plan = fld.Plan([g.E.shape], h=[g.h], **_opts(kinds, None))
+    (out,) = plan.radiation_moments([dev(g.E)], [dev(g.kappa_rho)], want=("F",))
+    torch.cuda.synchronize()
+    gr = O.gradient4_general(g.E, g.h, kinds, None)
+    gn = np.sqrt(sum(x * x for x in gr))
+    lam = O.flux_limiter(gn / (g.kappa_rho * g.E))
+    for a in range(2):
+        Fo = -lam / g.kappa_rho * gr[a]
+        Fg = out["F"][a].cpu().numpy()
+        scale = np.abs(g.E).max() / (g.kappa_rho * min(g.h)) * 1e-12
+        assert np.all(np.abs(Fg - Fo) <= 1e-9 * np.abs(Fo) + scale), a
+    plan.close()
