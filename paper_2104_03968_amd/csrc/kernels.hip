@@ -358,6 +358,31 @@ __device__ __forceinline__ void grad4_bc_at(const double* __restrict__ E, int i,
     }
 }
 
+// The 4th-order gradient of a field with mirrored ghosts, wrapped on the periodic
+// axes of pmask (the velocity of the photon-tiring term, whose own boundary values
+// are not the radiation's).
+template <int DIM>
+__device__ __forceinline__ void grad4_per_at(const double* __restrict__ F, int i, int j, int k, const int32_t n[3],
+                                             const double c12[3], int pmask, double g[3]) {
+    const long sy = n[0], sz = (long)n[0] * n[1];
+    auto at = [&](long base, long stride, int q, int m, int a) {
+        const int qq = ((pmask >> a) & 1) ? (q < 0 ? q + m : (q >= m ? q - m : q)) : mirror(q, m);
+        return F[base + qq * stride];
+    };
+    const long row = (long)j * sy + (long)k * sz;
+    g[0] = ((at(row, 1, i - 2, n[0], 0) - at(row, 1, i + 2, n[0], 0)) +
+            8.0 * (at(row, 1, i + 1, n[0], 0) - at(row, 1, i - 1, n[0], 0))) * c12[0];
+    const long col = i + (long)k * sz;
+    g[1] = ((at(col, sy, j - 2, n[1], 1) - at(col, sy, j + 2, n[1], 1)) +
+            8.0 * (at(col, sy, j + 1, n[1], 1) - at(col, sy, j - 1, n[1], 1))) * c12[1];
+    g[2] = 0.0;
+    if (DIM == 3) {
+        const long pil = i + (long)j * sy;
+        g[2] = ((at(pil, sz, k - 2, n[2], 2) - at(pil, sz, k + 2, n[2], 2)) +
+                8.0 * (at(pil, sz, k + 1, n[2], 2) - at(pil, sz, k - 1, n[2], 2))) * c12[2];
+    }
+}
+
 // Flux limiter lambda(R) (Sec. 2.2): the rational bridging law of eq. fld_lambda,
 // 1/3, Minerbo's two branches (meeting with equal value and slope at R = 3/2), or
 // Levermore and Pomraning's (coth R - 1/R)/R, by its series below R = 0.1 where
@@ -1915,7 +1940,8 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
     #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
                     double dv[3];
-                    grad4_at<DIM>(m.v[a], i, j, k, d.n, c12, dv);        // dv[b] = d v_a / d x_b
+                    if (d.per_mask) grad4_per_at<DIM>(m.v[a], i, j, k, d.n, c12, d.per_mask, dv);
+                    else grad4_at<DIM>(m.v[a], i, j, k, d.n, c12, dv);   // dv[b] = d v_a / d x_b
     #pragma unroll
                     for (int b = 0; b < DIM; ++b) tir = tir + P[a][b] * dv[b];
                 }

@@ -143,3 +143,29 @@ def test_moments_use_the_wrapped_ghosts():
         scale = np.abs(g.E).max() / (g.kappa_rho * min(g.h)) * 1e-12
         assert np.all(np.abs(Fg - Fo) <= 1e-9 * np.abs(Fo) + scale), a
     plan.close()
+
+
+def test_photon_tiring_wraps_the_velocity_gradient():
+    """P : grad v on a periodic grid: both the radiation and the velocity gradients wrap."""
+    g = W.random_grid((40, 56), 66600, dt=1e-3)
+    kinds = ["periodic"] * 4
+    v = [W.smooth_field(g.E.shape, 66601 + a) for a in range(2)]
+    plan = fld.Plan([g.E.shape], h=[g.h], **_opts(kinds, None))
+    (out,) = plan.radiation_moments([dev(g.E)], [dev(g.kappa_rho)], v=[[dev(a) for a in v]], dt=[g.dt],
+                                    want=("tiring",))
+    torch.cuda.synchronize()
+    got = out["tiring"].cpu().numpy()
+    plan.close()
+    gr = O.gradient4_general(g.E, g.h, kinds, None)
+    gn = np.sqrt(sum(x * x for x in gr))
+    R = gn / (g.kappa_rho * g.E)
+    lam = O.flux_limiter(R)
+    P = O.pressure_tensor(g.E, O.eddington_factor(lam, R), gr)
+    comp = {ij: q for q, ij in enumerate(O.tensor_components(2))}
+    dv = [O.gradient4_general(v[a], g.h, kinds, None) for a in range(2)]
+    want = sum(P[comp[(min(a, b), max(a, b))]] * dv[a][b] for a in range(2) for b in range(2))
+    assert rel_l2(got, want) <= 1e-12
+    # mirrored velocity ghosts would differ at the walls: the check has teeth
+    dvm = [O.gradient4(v[a], g.h) for a in range(2)]
+    mirr = sum(P[comp[(min(a, b), max(a, b))]] * dvm[a][b] for a in range(2) for b in range(2))
+    assert rel_l2(mirr, want) > 1e-6
