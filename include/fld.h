@@ -173,6 +173,12 @@ typedef struct fld_opts {
     int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass: 4, 8, 16
                              or 32; 0 = as tile_rows (which then sets the finest
                              level's down pass alone) [0].  Must be 0 with autotune  */
+    int32_t nu_coarse;    /* red-black sweeps before and after the coarse correction on
+                             the levels below the finest, and on every level of a
+                             grid small enough to be cycled whole in one LDS block;
+                             0..16, 0 = nu1 before and nu2 after [0].  A value the
+                             fused kernels do not take (fused 2D: 1..3; fused 3D:
+                             >= 1) sweeps per colour instead, like nu1 and nu2    */
 } fld_opts;
 
 /* Per-grid result of fld_step. */

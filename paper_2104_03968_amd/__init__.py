@@ -85,7 +85,8 @@ class fld_opts(C.Structure):
                 ("tile_rows", C.c_int32), ("tile_wide", C.c_int32), ("max_blocks", C.c_int32),
                 ("tile_depth", C.c_int32), ("fused3_levels", C.c_int32), ("bc_grad", C.c_double * 6),
                 ("tile_rows_coarse", C.c_int32), ("fmg", C.c_int32), ("coarse_op", C.c_int32),
-                ("fmg_depths", C.c_int32), ("bc_value", C.c_double * 6), ("tile_rows_up", C.c_int32)]
+                ("fmg_depths", C.c_int32), ("bc_value", C.c_double * 6), ("tile_rows_up", C.c_int32),
+                ("nu_coarse", C.c_int32)]
 
 
 class fld_tuning(C.Structure):

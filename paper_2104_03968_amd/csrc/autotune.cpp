@@ -54,8 +54,9 @@ std::string plan_key(const Plan& p) {
         cus = prop.multiProcessorCount;
     }
     char buf[512];
-    int n = std::snprintf(buf, sizeof(buf), "v6|%s|cu%d|%s|nu%d,%d|k%d|f%d", arch.c_str(), cus,
-                          p.mixed ? "mixed" : "fp64", p.opts.nu1, p.opts.nu2, p.krylov ? 1 : 0, p.opts.fused);
+    int n = std::snprintf(buf, sizeof(buf), "v7|%s|cu%d|%s|nu%d,%d,%d,%d|k%d|f%d", arch.c_str(), cus,
+                          p.mixed ? "mixed" : "fp64", p.opts.nu1, p.opts.nu2, p.nuc1, p.nuc2, p.krylov ? 1 : 0,
+                          p.opts.fused);
     for (int dim = 2; dim <= 3; ++dim) {
         int count = 0;
         double total = 0, largest = 0;
@@ -196,7 +197,9 @@ int plan_autotune(Plan& p) {
             for (int rows : {4, 8, 16, 32}) {
                 if (wide == best.wide && rows == best.rows) continue;
                 if (!fused2_shape_ok(p.mixed, p.opts.nu1, wide, rows, true) ||
-                    !fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false))
+                    !fused2_shape_ok(p.mixed, p.opts.nu2, wide, rows, false) ||
+                    !fused2_shape_ok(p.mixed, p.nuc1, wide, rows, true) ||
+                    !fused2_shape_ok(p.mixed, p.nuc2, wide, rows, false))
                     continue;
                 Shape s = best;
                 s.wide = wide;
@@ -210,8 +213,8 @@ int plan_autotune(Plan& p) {
         // can fill the chip where the finest level prefers taller ones)
         c.clear();
         for (int rows : {4, 8, 16, 32}) {
-            if (rows == best.rows_c || !fused2_shape_ok(p.mixed, p.opts.nu1, best.wide, rows, true) ||
-                !fused2_shape_ok(p.mixed, p.opts.nu2, best.wide, rows, false))
+            if (rows == best.rows_c || !fused2_shape_ok(p.mixed, p.nuc1, best.wide, rows, true) ||
+                !fused2_shape_ok(p.mixed, p.nuc2, best.wide, rows, false))
                 continue;
             Shape s = best;
             s.rows_c = rows;

@@ -74,6 +74,7 @@ struct Plan {
     bool has_dir = false;                      // some face is FLD_BC_DIRICHLET
     bool has_per = false;                      // some axis is periodic
     bool any_bc = false;                       // some face is not zero flux
+    int nuc1 = 2, nuc2 = 2;                    // sweeps on the levels below the finest
 
     // workspace layout (byte offsets)
     size_t off_levels = 0, off_state = 0, off_stepio = 0, off_exio = 0, off_moio = 0, off_imio = 0, off_ctrl = 0;

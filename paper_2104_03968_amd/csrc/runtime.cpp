@@ -88,6 +88,7 @@ int validate_opts(const fld_opts& o) {
         return FLD_ERR_INVALID_ARG;
     if (o.fmg != 0 && o.fmg != 1) return FLD_ERR_INVALID_ARG;
     if (o.fmg_depths < 0 || o.fmg_depths > 64) return FLD_ERR_INVALID_ARG;
+    if (o.nu_coarse < 0 || o.nu_coarse > 16) return FLD_ERR_INVALID_ARG;
     if (o.coarse_op != FLD_COARSE_REDISCRETISED && o.coarse_op != FLD_COARSE_GALERKIN) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
 }
@@ -149,8 +150,9 @@ void finish_fused(const Plan& p, DimLists& D) {
         D.levels3 = 0;
         while (D.levels3 < nd && D.sw3[D.levels3].prefix.back() >= kSweep3MinBlocks) ++D.levels3;
     }
-    const int fxd = fused_fx(2 * p.opts.nu1 + 1, p.tile_wide), fxu = fused_fx(2 * p.opts.nu2, p.tile_wide);
     for (size_t dpt = 0; dpt < D.down2.size(); ++dpt) {
+        const int n1 = dpt == 0 ? p.opts.nu1 : p.nuc1, n2 = dpt == 0 ? p.opts.nu2 : p.nuc2;
+        const int fxd = fused_fx(2 * n1 + 1, p.tile_wide), fxu = fused_fx(2 * n2, p.tile_wide);
         HostList& dn = D.down2[dpt];
         HostList& up = D.up2[dpt];
         dn.prefix.assign(1, 0);
@@ -298,7 +300,7 @@ static void build_lists(Plan& p) {
         // the fused level kernels know no Dirichlet couplings or wrapped neighbours: such plans
         // sweep per colour
         D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && !p.has_per && fused2_supported(p.opts.nu1) &&
-                  fused2_supported(p.opts.nu2);
+                  fused2_supported(p.opts.nu2) && fused2_supported(p.nuc1) && fused2_supported(p.nuc2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
         for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
@@ -309,7 +311,8 @@ static void build_lists(Plan& p) {
         // even for its result to end in x
         D.fused3 = D.dim == 3 && p.opts.fused && !p.has_dir && !p.has_per && fused3_supported(p.mixed) &&
                    p.opts.nu1 >= 1 &&
-                   p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0;
+                   p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0 && p.nuc1 >= 1 && p.nuc2 >= 1 &&
+                   (p.nuc1 + p.nuc2) % 2 == 0;
         D.sw3.resize(D.fused3 ? maxdepth : 0);
         D.sr3.resize(D.fused3 ? maxdepth : 0);
         for (int dpt = 0; dpt < (int)D.sw3.size(); ++dpt) {
@@ -354,6 +357,8 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.opts = opts;
     p.mixed = opts.precision == FLD_PREC_MIXED;
     p.krylov = opts.krylov != 0;
+    p.nuc1 = opts.nu_coarse ? opts.nu_coarse : opts.nu1;
+    p.nuc2 = opts.nu_coarse ? opts.nu_coarse : opts.nu2;
     p.has_dir = false;
     p.has_per = false;
     p.any_bc = false;
@@ -375,11 +380,12 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
     p.tile_depth = opts.tile_depth ? opts.tile_depth : 32;
     p.sweep3_levels = opts.fused3_levels;
-    if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) &&
+    if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) && fused2_supported(p.nuc1) &&
+        fused2_supported(p.nuc2) &&
         !(fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows, true) &&
           fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows, false) &&
-          fused2_shape_ok(p.mixed, opts.nu1, p.tile_wide, p.tile_rows_c, true) &&
-          fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_c, false) &&
+          fused2_shape_ok(p.mixed, p.nuc1, p.tile_wide, p.tile_rows_c, true) &&
+          fused2_shape_ok(p.mixed, p.nuc2, p.tile_wide, p.tile_rows_c, false) &&
           fused2_shape_ok(p.mixed, opts.nu2, p.tile_wide, p.tile_rows_u, false)))
         return FLD_ERR_INVALID_ARG;                            // the tile does not fit the LDS
     build_levels(p);
@@ -503,8 +509,9 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
     // reads x and writes xs when k is odd, the reverse when k is even; nu1 + nu2 is
     // even, so the level's result ends in x
     const int L3 = (D.fused3 && p.sweep3) ? D.levels3 : 0;
-    const int nu1 = p.opts.nu1, nu2 = p.opts.nu2, fz = p.tile_depth;
+    const int fz = p.tile_depth;
     for (int d = d0; d < D.maxdepth; ++d) {
+        const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1;
         if (d < L3) {
             for (int k = 1; k <= nu1; ++k) {
                 const bool load = k > 1 || (d == d0 && load0);
@@ -516,31 +523,33 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             continue;
         }
         if (D.fused) {
-            launch_down2(f32, p.dL, p.dS, D.down2[d].dev, p.opts.nu1, d == d0 ? load0 : 0, p.tile_wide,
+            launch_down2(f32, p.dL, p.dS, D.down2[d].dev, nu1, d == d0 ? load0 : 0, p.tile_wide,
                          d == 0 ? p.tile_rows : p.tile_rows_c, p.nblk, s);
             continue;
         }
-        for (int it = 0; it < p.opts.nu1; ++it) {
+        for (int it = 0; it < nu1; ++it) {
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
         }
         launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     }
-    launch_tail(dim, f32, p.has_dir || p.has_per, p.dL, p.dS, tail, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    // the tail's levels are below the finest unless the whole grid lives in it
+    launch_tail(dim, f32, p.has_dir || p.has_per, p.dL, p.dS, tail, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
     launch_coarse_solve(dim, f32, p.dL, p.dS, coarsest, s);
     for (int d = D.maxdepth - 1; d >= d0; --d) {
+        const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1, nu2 = d == 0 ? p.opts.nu2 : p.nuc2;
         if (d < L3) {
             for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
                 launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, fz, p.nblk, s);
             continue;
         }
         if (D.fused) {
-            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, p.opts.nu2, p.tile_wide, d == 0 ? p.tile_rows_u : p.tile_rows_c,
+            launch_up2(f32, p.dL, p.dS, D.up2[d].dev, nu2, p.tile_wide, d == 0 ? p.tile_rows_u : p.tile_rows_c,
                        p.nblk, s);
             continue;
         }
         launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
-        for (int it = 0; it < p.opts.nu2; ++it) {
+        for (int it = 0; it < nu2; ++it) {
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 1, p.nblk, s);
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
         }
@@ -561,7 +570,7 @@ static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
     const bool f32 = p.mixed;
     for (int d = 0; d < D.maxdepth; ++d) launch_restrict_rhs(D.dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
-    launch_tail(D.dim, f32, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, plain64, s);
+    launch_tail(D.dim, f32, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
     launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
     const int nv = p.opts.fmg_depths > 0 ? p.opts.fmg_depths : D.maxdepth;
     for (int d = D.maxdepth - 1; d >= 0; --d) {
@@ -662,8 +671,8 @@ int plan_set_shape(Plan& p, const LaunchShape& sh) {
     for (auto& D : p.dl)
         if (D.fused && !(fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows, true) &&
                          fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows, false) &&
-                         fused2_shape_ok(p.mixed, p.opts.nu1, sh.wide, sh.rows_c, true) &&
-                         fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_c, false) &&
+                         fused2_shape_ok(p.mixed, p.nuc1, sh.wide, sh.rows_c, true) &&
+                         fused2_shape_ok(p.mixed, p.nuc2, sh.wide, sh.rows_c, false) &&
                          fused2_shape_ok(p.mixed, p.opts.nu2, sh.wide, sh.rows_u, false)))
             return FLD_ERR_INVALID_ARG;
     if (sh.nblk < 1 || (sh.depth != 16 && sh.depth != 32 && sh.depth != 64) || (sh.sweep3 != 0 && sh.sweep3 != 1) ||
@@ -1154,12 +1163,14 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                                  -1, p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
                     break;
                 case FLD_KERNEL_DOWN:
-                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev, p.opts.nu1, 0,
+                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
+                                                             level == 0 ? p.opts.nu1 : p.nuc1, 0,
                                                              p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
                                                              p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
-                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev, p.opts.nu2,
+                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
+                                                         level == 0 ? p.opts.nu2 : p.nuc2,
                                                          p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
                                                          p.nblk, s);
                     break;
@@ -1168,7 +1179,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                         launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, p.tile_depth, p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
-                    launch_tail(D.dim, p.mixed, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.opts.nu1, p.opts.nu2, 0, s);
+                    launch_tail(D.dim, p.mixed, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, 0, s);
                     break;
                 default: break;
             }

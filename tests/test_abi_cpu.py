@@ -39,6 +39,7 @@ def test_defaults():
     assert o.c == 1.0 and o.rtol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.max_cycles == 50
     assert o.limiter == fld.FLD_LIMITER_LP and o.precision == fld.FLD_PREC_FP64
     assert o.fmg == 1 and o.fmg_depths == 2 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
+    assert o.nu_coarse == 0 and o.tile_rows_up == 0
     assert fld.fld_opts_default(coarse_op="galerkin").coarse_op == fld.FLD_COARSE_GALERKIN
     g = fld.fld_gas_default()
     assert g.max_halley == 100 and g.root_rtol == pytest.approx(8.88e-16, rel=1e-2)
@@ -67,7 +68,7 @@ def test_plan_create_validates_grids(n, ok):
     (dict(bc=[0, 2, 0, 0, 0, 0], bc_value=[0, float("inf"), 0, 0, 0, 0]), -1),
     (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1),
     (dict(fmg=2), -1), (dict(fmg=-1), -1), (dict(coarse_op=2), -1), (dict(coarse_op=-1), -1),
-    (dict(fmg_depths=-1), -1), (dict(fmg_depths=65), -1)])
+    (dict(fmg_depths=-1), -1), (dict(fmg_depths=65), -1), (dict(nu_coarse=-1), -1), (dict(nu_coarse=17), -1)])
 def test_plan_create_validates_options(kw, code):
     with pytest.raises(fld.FLDError) as e:
         fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(**kw))
@@ -89,7 +90,12 @@ def test_plan_create_validates_options(kw, code):
     (dict(tile_rows_coarse=4), True), (dict(tile_rows_coarse=12), False),
     (dict(autotune=1, tile_rows_coarse=8), False), (dict(tile_wide=1, tile_rows_coarse=32), False),
     (dict(tile_rows_up=16), True), (dict(tile_rows_up=6), False), (dict(autotune=1, tile_rows_up=8), False),
-    (dict(tile_wide=1, tile_rows_up=32), True), (dict(tile_wide=1, tile_rows=16, tile_rows_up=4), True)])
+    (dict(tile_wide=1, tile_rows_up=32), True), (dict(tile_wide=1, tile_rows=16, tile_rows_up=4), True),
+    # the coarse levels' tile carries the nu_coarse halo; a count the fused kernels do not
+    # take sends the plan to the per-colour sweeps, which have no tile to fit
+    (dict(tile_wide=1, tile_rows_coarse=32, nu_coarse=1), True),
+    (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1, nu_coarse=2), False),
+    (dict(tile_wide=1, tile_rows=32, nu_coarse=4), True), (dict(nu_coarse=16), True)])
 def test_launch_shape_options(kw, ok):
     g = fld.make_grid((256, 256))
     if ok:

@@ -140,3 +140,37 @@ def test_fmg_depths_match_oracle(depths, precision, krylov):
     for g, x in zip(grids, xs):
         x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c, method="direct")
         assert rel_l2(x, x_or) <= 1e-10
+
+
+@pytest.mark.parametrize("nu_coarse", [1, 3, 4])
+@pytest.mark.parametrize("precision,krylov", [(0, 1), (0, 0), (1, 1), (1, 0)])
+def test_coarse_sweep_count_matches_oracle(nu_coarse, precision, krylov):
+    """Sweeps on the coarse levels only: 1 and 3 keep the fused 2D kernels, 4 sends the 2D
+    grids to the per-colour sweeps; the 3D grid runs its two finest levels fused."""
+    grids = _batch() + [W.random_grid((48, 64, 40), 93003, dt=2e-3)]
+    rtol = min(1e-10 / O.q_b(g.E) for g in grids)
+    xs, stats, rc = run_step(grids, precision=precision, rtol=rtol, krylov=krylov, nu_coarse=nu_coarse,
+                             fused3_levels=2, max_cycles=200)
+    assert rc == 0, stats
+    for g, x, st in zip(grids, xs, stats):
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c)
+        assert st["status"] == 0 and st["rel_residual"] <= rtol
+        assert rel_l2(x, x_or) <= 1e-10, (g.E.shape, rel_l2(x, x_or), st)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coarse_sweep_count_default_and_batching(precision):
+    """nu_coarse equal to nu1 = nu2 is the default bit for bit, and a batch with
+    nu_coarse = 3 gives each grid what it gives alone."""
+    grids = _batch()
+    x0, _, rc0 = run_step(grids, precision=precision)
+    x2, _, rc2 = run_step(grids, precision=precision, nu_coarse=2)
+    assert rc0 == 0 and rc2 == 0
+    for a, b in zip(x0, x2):
+        assert np.array_equal(a, b)
+    xs, _, rc = run_step(grids, precision=precision, nu_coarse=3)
+    assert rc == 0
+    for i in (0, 3):
+        (x1,), _, rc1 = run_step([grids[i]], precision=precision, nu_coarse=3)
+        assert rc1 == 0
+        assert np.array_equal(x1, xs[i])
