@@ -53,6 +53,8 @@ def parse():
                          "default: the library's)")
     ap.add_argument("--coarse-op", default="rediscretised", choices=["rediscretised", "galerkin"],
                     help="coarse-level operator of the multigrid hierarchy")
+    ap.add_argument("--nu", type=int, nargs=2, default=(2, 2), metavar=("NU1", "NU2"),
+                    help="red-black sweeps before and after the coarse correction")
     ap.add_argument("--nu-coarse", type=int, default=0,
                     help="red-black sweeps before and after the correction on the coarse levels "
                          "(0 = nu1 and nu2, as on the finest level)")
@@ -299,7 +301,7 @@ def main():
     shapes = [g.E.shape for g in grids]
     plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c,
                     autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
-                    nu_coarse=args.nu_coarse, **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
+                    nu1=args.nu[0], nu2=args.nu[1], nu_coarse=args.nu_coarse, **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
     tuning = plan.tuning()
     log(f"bench: launch shape {tuning}")
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -369,7 +371,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
                    "rtol": 1e-10, "fmg": plan.opts.fmg, "fmg_depths": plan.opts.fmg_depths, "coarse_op": args.coarse_op,
-                   "nu_coarse": plan.opts.nu_coarse,
+                   "nu": [plan.opts.nu1, plan.opts.nu2], "nu_coarse": plan.opts.nu_coarse,
                    "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
                                                      "fused3_levels", "tile_rows_coarse", "tile_rows_up",
                                                      "source")}},

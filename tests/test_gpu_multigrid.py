@@ -174,3 +174,19 @@ def test_coarse_sweep_count_default_and_batching(precision):
         (x1,), _, rc1 = run_step([grids[i]], precision=precision, nu_coarse=3)
         assert rc1 == 0
         assert np.array_equal(x1, xs[i])
+
+
+@pytest.mark.parametrize("nu,nu_coarse", [((1, 1), 0), ((3, 3), 0), ((1, 1), 3)])
+@pytest.mark.parametrize("precision,krylov", [(0, 1), (1, 1), (1, 0)])
+def test_finest_sweep_counts_match_oracle(nu, nu_coarse, precision, krylov):
+    """Other sweep counts on the finest level, through the fused 2D kernels and the fused
+    3D sweeps of the two finest levels of the 3D grid."""
+    grids = _batch() + [W.random_grid((48, 64, 40), 93004, dt=2e-3)]
+    rtol = min(1e-10 / O.q_b(g.E) for g in grids)
+    xs, stats, rc = run_step(grids, precision=precision, rtol=rtol, krylov=krylov, nu1=nu[0], nu2=nu[1],
+                             nu_coarse=nu_coarse, fused3_levels=2, max_cycles=200)
+    assert rc == 0, stats
+    for g, x, st in zip(grids, xs, stats):
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h, g.c)
+        assert st["status"] == 0 and st["rel_residual"] <= rtol
+        assert rel_l2(x, x_or) <= 1e-10, (g.E.shape, rel_l2(x, x_or), st)
