@@ -173,3 +173,22 @@ def test_autotuner_times_the_3d_sweep_depths(tmp_path, monkeypatch):
         (xr,), (sr,), _ = run_step([g], precision=precision)
         assert rc == 0 and np.array_equal(x, xr) and st["cycles"] == sr["cycles"]
         p.close()
+
+
+def test_coarse_sweep_count_has_its_own_cache_record(tmp_path, monkeypatch):
+    """The coarse tile carries the halo of nu_coarse sweeps, so a plan with another count is
+    timed afresh under its own key rather than handed a shape tuned for the default; the
+    tuned plan reproduces the untuned one bit for bit."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FLD_AUTOTUNE_CACHE", str(cache))
+    g = W.random_grid((256, 256), 91300, dt=4e-3)
+    fld.Plan([g.E.shape], h=[g.h], autotune=1).close()
+    p = fld.Plan([g.E.shape], h=[g.h], autotune=1, nu_coarse=3)
+    t = p.tuning()
+    assert t["source"] == 1 and t["candidates"] >= 2
+    (x,), (st,), rc = _solve(p, [g])
+    p.close()
+    keys = [line.split("\t")[0] for line in cache.read_text().splitlines()]
+    assert len(keys) == 2 and keys[0] != keys[1]
+    (xr,), (sr,), rcr = run_step([g], nu_coarse=3)
+    assert rc == 0 and rcr == 0 and np.array_equal(x, xr) and st["cycles"] == sr["cycles"]
