@@ -120,7 +120,8 @@ typedef struct fld_opts {
     double  rtol;         /* stop when ||E^n - A E||_2 <= rtol ||E^n||_2 [1e-10]     */
     int32_t max_cycles;   /* V-cycles (= outer iterations) per step [50]            */
     int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after the coarse
-                             correction [2, 2]                                      */
+                             correction [2, 2]; 2D grids keep the fused level
+                             kernels for counts 1..3 and sweep per colour otherwise */
     int32_t use_graph;    /* replay V-cycles from a captured hipGraph [1]           */
     int32_t autotune;     /* launch shape: 0 = from the tile fields below; 1 = from
                              the autotuner's cache, timed at bind time on a miss;
@@ -176,9 +177,10 @@ typedef struct fld_opts {
     int32_t nu_coarse;    /* red-black sweeps before and after the coarse correction on
                              the levels below the finest, and on every level of a
                              grid small enough to be cycled whole in one LDS block;
-                             0..16, 0 = nu1 before and nu2 after [0].  A value the
-                             fused kernels do not take (fused 2D: 1..3; fused 3D:
-                             >= 1) sweeps per colour instead, like nu1 and nu2    */
+                             0..16, 0 = nu1 before and nu2 after [0].  As for nu1
+                             and nu2, a count outside 1..3 sends the plan's 2D grids
+                             to the per-colour sweeps on every level, the finest
+                             included                                              */
 } fld_opts;
 
 /* Per-grid result of fld_step. */
