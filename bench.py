@@ -1,15 +1,18 @@
 """Throughput benchmark of the FLD radiation-energy step on one MI355X.
 
-Default workload: the 2D 1024 x 1024 FP64 configuration with gas -- every step
-is one implicit diffusion solve to a 1e-10 relative residual followed by the
-implicit gas-radiation energy exchange, on seeded synthetic fields that stay
-resident in HBM.  ``--steps K`` steps are timed after ``--warmup W`` untimed
-ones (the trajectory continues through both).
+Default workload: the 3D 256^3 FP64 configuration -- every step is one
+implicit backward-Euler diffusion solve to a 1e-10 relative residual on seeded
+synthetic fields that stay resident in HBM.  ``--steps K`` steps are timed
+after ``--warmup W`` untimed ones (the trajectory continues through both).
 
 One JSON line is printed: cell-updates/s (cells x steps / wall time), per-step
 latency percentiles, the roofline of the dominant kernel (timed with HIP events
-right after the timed region, on the same stream) and the FP64 CPU oracle timed
-on one step of the same grid on this host's cores.
+right after the timed region, on the same stream), the effective bandwidth of a
+whole outer iteration and of its multigrid V-cycle (algorithmic bytes of every
+kernel over the pass's time), and the FP64 CPU oracle timed on a bounded sample
+of the workload on this host's cores.  Extras (``--no-extras`` skips them): the
+same grid in the other precision with its speed-up, five steps of both
+precisions certified against the FP64 oracle, and the 2D 1024^2 step with gas.
 
 ``--config c5`` runs the served stream instead: Poisson arrivals of mixed 2D and
 3D solves submitted to the continuous-batching server on their schedule, with
@@ -37,12 +40,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=384, help="c5: requests in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5: mean arrival rate (1/s)")
     ap.add_argument("--arena-gb", type=float, default=32.0, help="c5: server arena")
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default fp64 (the served stream: mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline: no other precision, error certificates, 1024^2 line, "
+                         "moments or IMEX timings")
+    ap.add_argument("--krylov", type=int, default=1, choices=[0, 1],
+                    help="1: V-cycle-preconditioned CG; 0: plain V-cycles (defect correction)")
     ap.add_argument("--profile-reps", type=int, default=200)
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="launch shape: 0 defaults, 1 autotuner (cached), 2 re-time")
@@ -202,6 +211,7 @@ def serve_stream(args):
     # warm-up: one small request of each dimension (compiles nothing, but pages in the code)
     for shape in ((128, 128), (32, 32, 32)):
         g = W.random_grid(shape, 1, 1e-3, backend="torch", device=dev)
+        torch.cuda.synchronize()
         t = srv.submit(g.E.contiguous(), g.kappa_rho.contiguous(), g.dt, h=g.h)
         srv.wait(t, 60.0)
         srv.release(t)
@@ -260,6 +270,173 @@ def serve_stream(args):
     print(json.dumps(out), flush=True)
 
 
+def host_info(threads_used: int) -> dict:
+    """CPU model, affinity and thread settings of this host (for the CPU baseline)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+           if os.environ.get(k) is not None}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "sched_affinity": affinity,
+            "thread_env": env, "threads_used": threads_used}
+
+
+def certified_error(g_host, E_n, x):
+    """Relative residual of the device's step under the oracle's own FP64 operator (built
+    from E_n) and the bound q_b * residual it gives on the error against the oracle's
+    exact step (A is SPD with lambda_min >= 1 and conserves the mean)."""
+    import oracle as O
+    D = O.diffusion_coefficient(E_n, g_host.kappa_rho, g_host.h, g_host.c)
+    w = O.face_weights(D, g_host.dt, g_host.h)
+    r = E_n - O.apply_operator(w, x)
+    rel = float(np.linalg.norm(r) / np.linalg.norm(E_n))
+    return rel, O.q_b(E_n) * rel
+
+
+def build_config(W, cfg: str):
+    """The seeded inputs of a configuration, whether it has gas, and its description."""
+    if cfg == "c1":
+        return [W.pulse_2d()], False, "2D 64x64 Gaussian pulse, kappa*rho=10, one backward-Euler FLD step"
+    if cfg == "c2":
+        return ([W.c2_inputs(1024)], True,
+                "2D 1024x1024 FP64 FLD step + implicit gas-radiation exchange, log10(kappa*rho) "
+                "in [-2,2] (32 Fourier modes), log-normal E (sigma=1), dt=1e-3, rtol=1e-10")
+    if cfg == "c3":
+        return ([W.c3_inputs(256)], False,
+                "3D 256^3 FLD step, log10(kappa*rho) in [-2,2] and log-normal E (sigma=1) from "
+                "32 Fourier modes, dt=1e-3, rtol=1e-10")
+    lay = W.c4_layout()
+    return ([W.c4_grid(j, n, dt) for j, (n, dt) in enumerate(lay)], False,
+            "512 independent 2D grids, sides U{64..512 step 32}, dt U[1e-4,1e-2], one launch per phase")
+
+
+def run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, steps, warmup, want_roofline=True):
+    """Time `steps` steps (after `warmup`) of one configuration in one precision.
+    Returns the measurement dict, the plan (open) and the device state."""
+    plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids], precision=precision, rtol=1e-10,
+                    c=grids[0].c, autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
+                    nu1=args.nu[0], nu2=args.nu[1], nu_coarse=args.nu_coarse, krylov=args.krylov,
+                    **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
+    tuning = plan.tuning()
+    log(f"bench {cfg}: launch shape {tuning}")
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    E = [to(g.E) for g in grids]
+    K = [to(g.kappa_rho) for g in grids]
+    dts = [g.dt for g in grids]
+    st_ = {}
+    if has_gas:
+        st_["eps"] = [to(g.eps) for g in grids]
+        st_["rho"] = [to(g.rho) for g in grids]
+        st_["kap"] = [to(g.kappa) for g in grids]
+        st_["gas"] = fld.fld_gas_default(c=grids[0].c, a_rad=grids[0].a_r, c_v=grids[0].c_v)
+    stream = torch.cuda.current_stream()
+    cycles = []
+
+    def one_step():
+        rc, st = plan.step(E, K, E, dts, stream=stream, check=False)
+        if rc != 0:
+            raise RuntimeError(f"fld_step failed: {fld.fld_strerror(rc)} {st[:2]}")
+        if has_gas:
+            plan.exchange(E, st_["eps"], st_["rho"], st_["kap"], dts, st_["gas"], stream=stream)
+        cycles.append(max(s["cycles"] for s in st))
+        return st
+
+    ncells = sum(g.E.size for g in grids)
+    log(f"bench {cfg}: {len(grids)} grid(s), {ncells} cells; warmup {warmup}")
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    cycles.clear()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        one_step()
+        if has_gas:
+            stream.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = ncells * steps / elapsed
+    log(f"bench {cfg}: {steps} steps in {elapsed:.4f} s -> {value:.4e} cell-updates/s, cycles {cycles}")
+    if has_gas:
+        rc, nbis = plan.exchange_status(stream)
+        assert rc == 0, "exchange rejected cells"
+    out = {"value": value, "ms_per_step": elapsed / steps * 1e3,
+           "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+           "vcycles_per_step": float(np.mean(cycles)) if cycles else None, "tuning": tuning}
+    if want_roofline:
+        ndim = len(grids[0].E.shape)
+        word = 4 if precision == fld.FLD_PREC_MIXED else 8
+        kid, kname, bpc = dominant_kernel(fld, ndim, word, bool(plan.opts.fused), bool(tuning["fused3"]))
+        ms, cells = plan.profile(kid, 0, args.profile_reps, stream)
+        achieved = bpc * cells / (ms * 1e-3) / 1e9
+        log(f"bench {cfg}: level-0 {kname} {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg, kname, tuning),
+                           "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"}
+        out["vcycle"] = vcycle_bandwidth(fld, plan, stream, max(20, args.profile_reps // 10))
+    return out, plan, E, K, st_
+
+
+def vcycle_bandwidth(fld, plan, stream, reps):
+    """Effective bandwidth of a whole outer iteration and of its multigrid V-cycle: the
+    algorithmic bytes of every kernel of the pass (fld_plan_cycle_bytes) over the pass's
+    mean time (HIP events on the bench stream, the iteration replayed from its graph)."""
+    out = {}
+    for name, what, kid in (("iteration", fld.FLD_CYCLE_ITERATION, fld.FLD_KERNEL_VCYCLE),
+                            ("multigrid", fld.FLD_CYCLE_MG, fld.FLD_KERNEL_MG)):
+        nbytes, launches = plan.cycle_bytes(what)
+        ms, _ = plan.profile(kid, 0, reps, stream)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"bytes": nbytes, "launches": launches, "us": ms * 1e3, "achieved_GBps": gbs,
+                     "frac": gbs / HBM_PEAK_GBS}
+        log(f"bench: {name}: {nbytes / 1e6:.1f} MB in {ms * 1e3:.1f} us ({launches} launches) -> {gbs:.0f} GB/s")
+    return out
+
+
+def mixed_vs_fp64_steps(fld, torch, grids, dev, nsteps: int, autotune: int):
+    """The 256^3 step sequence in both precisions from the seeded input, untimed: per step the
+    device's rel. residual, its residual under the oracle's operator and the error bound
+    against the oracle's step it gives, and the mixed result's distance from the FP64 GPU
+    result of the same step (each precision follows its own trajectory)."""
+    g = grids[0]
+    res = {}
+    outs = {}
+    for name, prec in (("fp64", fld.FLD_PREC_FP64), ("mixed", fld.FLD_PREC_MIXED)):
+        plan = fld.Plan([g.E.shape], h=[g.h], precision=prec, rtol=1e-10, c=g.c, autotune=autotune)
+        E = torch.from_numpy(np.ascontiguousarray(g.E)).to(dev)
+        K = torch.from_numpy(np.ascontiguousarray(g.kappa_rho)).to(dev)
+        out = torch.empty_like(E)
+        steps = []
+        outs[name] = []
+        for k in range(nsteps):
+            E_n = E.cpu().numpy()
+            rc, (st,) = plan.step([E], [K], [out], [g.dt], check=False)
+            torch.cuda.synchronize()
+            x = out.cpu().numpy()
+            rel, bound = certified_error(g, E_n, x)
+            steps.append({"step": k, "cycles": int(st["cycles"]), "device_rel_residual": st["rel_residual"],
+                          "oracle_operator_rel_residual": rel, "error_vs_fp64_oracle_bound": bound})
+            outs[name].append(x if k == 0 else None)
+            E.copy_(out)
+            log(f"bench c3 {name} step {k}: cycles {st['cycles']} res {rel:.3e} error bound {bound:.3e}")
+        res[name] = steps
+        plan.close()
+    x64, x32 = outs["fp64"][0], outs["mixed"][0]
+    res["first_step_mixed_vs_fp64_gpu_rel_l2"] = float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64))
+    return res
+
+
 def main():
     args = parse()
     if args.config == "c5" and args.gpus == 1:
@@ -276,128 +453,89 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cfg = args.config
-    prec = args.precision or ("mixed" if cfg == "c3" else "fp64")
+    prec = args.precision or "fp64"
     precision = fld.FLD_PREC_MIXED if prec == "mixed" else fld.FLD_PREC_FP64
     log(f"bench: building inputs for {cfg} ({prec})")
-
-    has_gas = False
-    if cfg == "c1":
-        grids = [W.pulse_2d()]
-        workload = "2D 64x64 Gaussian pulse, kappa*rho=10, one backward-Euler FLD step"
-    elif cfg == "c2":
-        grids = [W.c2_inputs(1024)]
-        has_gas = True
-        workload = ("2D 1024x1024 FP64 FLD step + implicit gas-radiation exchange, log10(kappa*rho) "
-                    "in [-2,2] (32 Fourier modes), log-normal E (sigma=1), dt=1e-3, rtol=1e-10")
-    elif cfg == "c3":
-        grids = [W.c3_inputs(256)]
-        workload = ("3D 256^3 FLD step, the 2D 1024^2 field recipe in 3D, dt=1e-3, rtol=1e-10, "
-                    + ("mixed (FP32 V-cycles in FP64 defect correction)" if prec == "mixed" else "fp64"))
-    else:
-        lay = W.c4_layout()
-        grids = [W.c4_grid(j, n, dt) for j, (n, dt) in enumerate(lay)]
-        workload = "512 independent 2D grids, sides U{64..512 step 32}, dt U[1e-4,1e-2], one launch per phase"
+    grids, has_gas, workload = build_config(W, cfg)
     ncells = sum(g.E.size for g in grids)
-    shapes = [g.E.shape for g in grids]
-    plan = fld.Plan(shapes, h=[g.h for g in grids], precision=precision, rtol=1e-10, c=grids[0].c,
-                    autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
-                    nu1=args.nu[0], nu2=args.nu[1], nu_coarse=args.nu_coarse, **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
-    tuning = plan.tuning()
-    log(f"bench: launch shape {tuning}")
-    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    E = [to(g.E) for g in grids]
-    K = [to(g.kappa_rho) for g in grids]
-    dts = [g.dt for g in grids]
-    if has_gas:
-        eps = [to(g.eps) for g in grids]
-        rho = [to(g.rho) for g in grids]
-        kap = [to(g.kappa) for g in grids]
-        gas = fld.fld_gas_default(c=grids[0].c, a_rad=grids[0].a_r, c_v=grids[0].c_v)
-    stream = torch.cuda.current_stream()
 
-    cycles = []
-
-    def one_step():
-        rc, st = plan.step(E, K, E, dts, stream=stream, check=False)
-        if rc != 0:
-            raise RuntimeError(f"fld_step failed: {fld.fld_strerror(rc)} {st[:2]}")
-        if has_gas:
-            plan.exchange(E, eps, rho, kap, dts, gas, stream=stream)
-        cycles.append(max(s["cycles"] for s in st))
-        return st
-
-    log(f"bench: {len(grids)} grid(s), {ncells} cells; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    cycles.clear()
-    lat = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        st = one_step()
-        if has_gas:
-            stream.synchronize()
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    value = ncells * args.steps / elapsed
-    log(f"bench: {args.steps} steps in {elapsed:.4f} s -> {value:.4e} cell-updates/s, cycles {cycles}")
-    if has_gas:
-        rc, nbis = plan.exchange_status(stream)
-        assert rc == 0, "exchange rejected cells"
-
-    # dominant kernel at level 0, timed with HIP events on the same stream
-    ndim = len(shapes[0])
-    word = 4 if precision == fld.FLD_PREC_MIXED else 8
-    kid, kname, bpc = dominant_kernel(fld, ndim, word, bool(plan.opts.fused), bool(tuning["fused3"]))
-    ms, cells = plan.profile(kid, 0, args.profile_reps, stream)
-    achieved = bpc * cells / (ms * 1e-3) / 1e9
-    log(f"bench: level-0 {kname} {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")
-
+    m, plan, E, K, st_ = run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, args.steps, args.warmup)
+    tuning = m["tuning"]
     out = {
         "metric": "cell-updates/s of implicit FLD step at 1e-10 residual; p50/p99 solve latency",
-        "value": value,
+        "value": m["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if precision == fld.FLD_PREC_FP64 else "f32-in-f64",
         "data": "synthetic",
-        "config": {"workload": workload, "cells": ncells, "grids": len(grids), "precision": prec,
+        "config": {"workload": workload + (", fp64" if prec == "fp64" else ", FP32 V-cycles in FP64 defect correction"),
+                   "cells": ncells, "grids": len(grids), "precision": prec,
                    "rtol": 1e-10, "fmg": plan.opts.fmg, "fmg_depths": plan.opts.fmg_depths, "coarse_op": args.coarse_op,
-                   "nu": [plan.opts.nu1, plan.opts.nu2], "nu_coarse": plan.opts.nu_coarse,
+                   "krylov": plan.opts.krylov, "nu": [plan.opts.nu1, plan.opts.nu2], "nu_coarse": plan.opts.nu_coarse,
                    "launch": {k: tuning[k] for k in ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
                                                      "fused3_levels", "tile_rows_coarse", "tile_rows_up",
                                                      "source")}},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
-        "vcycles_per_step": float(np.mean(cycles)) if cycles else None,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(cfg, kname, tuning),
-                     "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"},
+        "step_latency_ms": m["latency_ms"],
+        "vcycles_per_step": m["vcycles_per_step"],
+        "roofline": m["roofline"],
+        "vcycle_bandwidth": m["vcycle"],
     }
-    out["radiation_moments"] = time_moments(fld, plan, grids, E, K, stream)
-    if has_gas:
-        log("bench: timing the IMEX step (tiring + exchange + implicit diffusion)")
-        out["imex_step"] = time_imex(fld, plan, grids, E, eps, rho, kap, gas, stream)
-    if not args.no_cpu_baseline:
-        g0 = grids[0] if cfg != "c4" else grids[0]
-        log("bench: timing the FP64 CPU oracle on one step of the first grid")
-        t, info = cpu_baseline(g0, has_gas)
-        out["cpu_baseline"] = {"value": g0.E.size / t, "unit": "cell-updates/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": (f"one FLD step of a {'x'.join(map(str, g0.E.shape))} grid "
-                                          f"({info.method}, {info.iterations} iterations, {t:.1f} s; "
-                                          "scipy sparse + numpy, single-threaded)"),
-                               "host_cpus": os.cpu_count()}
+    if not args.no_extras:
+        out["radiation_moments"] = time_moments(fld, plan, grids, E, K, torch.cuda.current_stream())
+        if has_gas:
+            log("bench: timing the IMEX step (tiring + exchange + implicit diffusion)")
+            out["imex_step"] = time_imex(fld, plan, grids, E, st_["eps"], st_["rho"], st_["kap"], st_["gas"],
+                                         torch.cuda.current_stream())
     plan.close()
+    del E, K, st_
+    if not args.no_extras:
+        extra = {}
+        if cfg in ("c3", "c4"):
+            other = fld.FLD_PREC_MIXED if precision == fld.FLD_PREC_FP64 else fld.FLD_PREC_FP64
+            mo, p2, *_ = run_timed(fld, torch, args, cfg, grids, has_gas, other, dev, args.steps, args.warmup)
+            p2.close()
+            key = "mixed" if other == fld.FLD_PREC_MIXED else "fp64"
+            mo.pop("tuning")
+            mo["speedup_vs_fp64"] = (mo["value"] / m["value"]) if key == "mixed" else (m["value"] / mo["value"])
+            extra[key] = mo
+        if cfg == "c3":
+            extra["per_step_error_vs_fp64_oracle"] = mixed_vs_fp64_steps(fld, torch, grids, dev, 5, args.autotune)
+        if cfg != "c2":
+            g2, gas2, _ = build_config(W, "c2")
+            m2, p3, *_ = run_timed(fld, torch, args, "c2", g2, gas2, fld.FLD_PREC_FP64, dev, args.steps, args.warmup)
+            p3.close()
+            m2.pop("tuning")
+            extra["c2_1024sq_fp64_with_exchange"] = m2
+        out["extra"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(W, cfg, grids, has_gas)
     print(json.dumps(out), flush=True)
+
+
+def run_cpu_baseline(W, cfg, grids, has_gas):
+    """The FP64 oracle on a bounded sample of the workload, on this host's cores."""
+    if cfg == "c3":
+        g0 = W.c3_inputs(160)
+        sample = ("one FLD step of the 3D recipe on a 160^3 grid (one 256^3 step takes the oracle "
+                  "about a minute)")
+    elif cfg == "c4":
+        g0 = grids[0]
+        sample = f"one FLD step of the first grid of the batch ({g0.E.shape[0]}^2)"
+    else:
+        g0 = grids[0]
+        sample = f"one FLD step of the {'x'.join(map(str, g0.E.shape))} grid" + (" with exchange" if has_gas else "")
+    log(f"bench: timing the FP64 CPU oracle: {sample}")
+    t, info = cpu_baseline(g0, has_gas)
+    return {"value": g0.E.size / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {info.method}, {info.iterations} iterations, {t:.1f} s; scipy sparse + numpy "
+                      "(sparse matrix-vector products single-threaded)",
+            "host": host_info(1)}
 
 
 if __name__ == "__main__":

@@ -394,6 +394,7 @@ int32_t fld_imex_step(fld_plan_t plan, double* const* E, double* const* eps,
 #define FLD_KERNEL_UP        8   /* fused 2D: prolongation + nu2 sweeps at `level`           */
 #define FLD_KERNEL_TAIL      9   /* the LDS tail of every grid                             */
 #define FLD_KERNEL_SWEEP3   10   /* fused 3D: one red-black sweep from the stored iterate at `level` */
+#define FLD_KERNEL_MG       11   /* the multigrid part of one V-cycle (every level, no CG update) */
 
 /* Launch shape of a bound plan, and where it came from. */
 typedef struct fld_tuning {
@@ -414,6 +415,21 @@ typedef struct fld_tuning {
 } fld_tuning;
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);
+
+/* Algorithmic bytes of one pass of a driver: each kernel it launches counted by
+   the arrays it must read and write once per cell it covers (faces, iterates,
+   right-hand sides, CG vectors; coarse levels at their own size), summed over
+   the pass, without launching anything.  Dividing by the pass's measured time
+   gives its effective bandwidth.  what: FLD_CYCLE_ITERATION one outer iteration
+   as fld_step replays it (V-cycle, CG update or defect correction, FP64 stop
+   test), FLD_CYCLE_MG its multigrid part (as FLD_KERNEL_MG times it),
+   FLD_CYCLE_FMG the first outer iteration of a step with the full-multigrid
+   start.  *launches (may be NULL) receives the kernel launches of the pass.
+   Host only.  Errors: INVALID_ARG, NO_WORKSPACE. */
+#define FLD_CYCLE_ITERATION 0
+#define FLD_CYCLE_MG        1
+#define FLD_CYCLE_FMG       2
+int32_t fld_plan_cycle_bytes(fld_plan_t plan, int32_t what, double* bytes, int64_t* launches);
 
 /* Time `reps` back-to-back launches of one kernel of the plan (launch shape
    as fld_step uses it) between two HIP events on `stream`; *avg_ms receives
@@ -458,6 +474,12 @@ typedef struct fld_request {
                                         admitted, so they must stay valid and unchanged
                                         until it is done; 0: host pointers, copied by
                                         fld_submit before it returns                    */
+    void*         stream;     /* device inputs: the hipStream_t that writes them (NULL:
+                                 the null stream).  fld_submit records an event on it,
+                                 and the server's copy at admission waits for that
+                                 event, so work the caller enqueued on this stream
+                                 before fld_submit is complete when the inputs are
+                                 read.  Ignored for host inputs.                       */
 } fld_request;
 
 typedef struct fld_result {

@@ -47,7 +47,7 @@ import scipy.sparse.linalg as spla
 __all__ = [
     "LIMITERS", "pad_mirror", "gradient4", "radiation_parameter", "flux_limiter",
     "diffusion_coefficient", "face_weights", "assemble_operator", "apply_operator",
-    "relative_residual", "q_b", "solve", "SolveInfo", "diffusion_step", "exchange",
+    "relative_residual", "q_b", "solve", "SolveInfo", "OracleNotConverged", "diffusion_step", "exchange",
     "exchange_coefficients", "fld_step", "residual_floor_tol",
 ]
 
@@ -264,6 +264,14 @@ class SolveInfo:
     extra: Dict = field(default_factory=dict)
 
 
+class OracleNotConverged(RuntimeError):
+    """The solve ended above its tolerance; ``info`` holds where it stopped."""
+
+    def __init__(self, msg: str, info: "SolveInfo"):
+        super().__init__(msg)
+        self.info = info
+
+
 def _pcg(A, b, x0, tol, maxiter):
     """Jacobi-preconditioned conjugate gradients on SPD A (plain textbook loop)."""
     dinv = 1.0 / A.diagonal()
@@ -353,6 +361,10 @@ def solve(A, b: np.ndarray, method: str = "auto", tol: Optional[float] = None,
     rel = float(np.linalg.norm(bb - A @ x) / np.linalg.norm(bb))
     info = SolveInfo(method=method, iterations=it, rel_residual=rel, tol=tol, tol_kind=kind,
                      seconds=time.perf_counter() - t0)
+    if not rel <= tol:
+        # an answer that misses its own stop rule is no reference: refuse it
+        raise OracleNotConverged(f"{method} stopped at relative residual {rel:.3e} > tol {tol:.3e} "
+                                 f"after {it} iterations (N = {N})", info)
     return x.reshape(shape), info
 
 

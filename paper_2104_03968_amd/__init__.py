@@ -71,6 +71,10 @@ FLD_KERNEL_DOWN = 7
 FLD_KERNEL_UP = 8
 FLD_KERNEL_TAIL = 9
 FLD_KERNEL_SWEEP3 = 10
+FLD_KERNEL_MG = 11
+FLD_CYCLE_ITERATION = 0
+FLD_CYCLE_MG = 1
+FLD_CYCLE_FMG = 2
 
 
 class fld_grid(C.Structure):
@@ -131,7 +135,7 @@ class fld_server_opts(C.Structure):
 
 class fld_request(C.Structure):
     _fields_ = [("grid", fld_grid), ("dt", C.c_double), ("E_in", C.c_void_p), ("kappa_rho", C.c_void_p),
-                ("inputs_on_device", C.c_int32)]
+                ("inputs_on_device", C.c_int32), ("stream", C.c_void_p)]
 
 
 class fld_result(C.Structure):
@@ -175,6 +179,7 @@ _sig = {
                                   C.c_int32, _P, C.c_size_t, _P, C.POINTER(fld_stats)]),
     "fld_profile_kernel": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
+    "fld_plan_cycle_bytes": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fld_server_opts_default": (None, [C.POINTER(fld_server_opts)]),
     "fld_server_create": (C.c_int32, [C.POINTER(fld_server_opts), _P, C.c_size_t, _PP]),
     "fld_server_destroy": (C.c_int32, [_P]),
@@ -404,6 +409,14 @@ def fld_plan_tuning(plan: int) -> dict:
     return t.as_dict()
 
 
+def fld_plan_cycle_bytes(plan: int, what: int = FLD_CYCLE_ITERATION):
+    """Returns (algorithmic bytes, kernel launches) of one pass of a driver (host only)."""
+    b = C.c_double()
+    n = C.c_int64()
+    _check(_lib.fld_plan_cycle_bytes(plan, what, C.byref(b), C.byref(n)), "fld_plan_cycle_bytes")
+    return b.value, n.value
+
+
 def fld_profile_kernel(plan: int, kernel: int, level: int = 0, reps: int = 100, stream=None):
     """Returns (mean ms per launch, cells per launch)."""
     ms = C.c_double()
@@ -431,8 +444,10 @@ def fld_server_destroy(server: int) -> None:
     _check(_lib.fld_server_destroy(server), "fld_server_destroy")
 
 
-def fld_submit(server: int, grid: fld_grid, dt: float, E_in, kappa_rho, on_device: bool = True):
-    """Returns (status, ticket)."""
+def fld_submit(server: int, grid: fld_grid, dt: float, E_in, kappa_rho, on_device: bool = True,
+               stream=None):
+    """Returns (status, ticket).  Device inputs are read at admission, after the work
+    enqueued on `stream` (default: torch's current stream) before this call."""
     req = fld_request()
     req.grid = grid
     req.dt = float(dt)
@@ -441,6 +456,7 @@ def fld_submit(server: int, grid: fld_grid, dt: float, E_in, kappa_rho, on_devic
     req.kappa_rho = kappa_rho if isinstance(kappa_rho, int) else (kappa_rho.data_ptr() if on_device else
                                                                   kappa_rho.ctypes.data)
     req.inputs_on_device = 1 if on_device else 0
+    req.stream = _stream(stream) if on_device else None
     t = C.c_uint64()
     rc = _lib.fld_submit(server, C.byref(req), C.byref(t))
     return rc, t.value
@@ -476,16 +492,23 @@ class Server:
         import torch
         self.device = torch.device(device if device is not None else "cuda")
         self.opts = fld_server_opts_default(**opts)
+        self._inputs = {}
         with torch.cuda.device(self.device):
             self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
             self.handle = fld_server_create(self.opts, self.arena.data_ptr(), int(arena_bytes))
 
-    def submit(self, E_in, kappa_rho, dt: float, h=None, on_device: bool = True):
-        """E_in, kappa_rho: (ny, nx) / (nz, ny, nx) float64 tensors (device) or arrays (host)."""
+    def submit(self, E_in, kappa_rho, dt: float, h=None, on_device: bool = True, stream=None):
+        """E_in, kappa_rho: (ny, nx) / (nz, ny, nx) float64 tensors (device) or arrays (host).
+
+        Device tensors are read when the request is admitted, after the work enqueued on
+        `stream` (default: torch's current stream) before this call; the server keeps a
+        reference to them until the ticket is released."""
         shape = tuple(E_in.shape)
         grid = make_grid(tuple(reversed(shape)), h)
-        rc, t = fld_submit(self.handle, grid, dt, E_in, kappa_rho, on_device)
+        rc, t = fld_submit(self.handle, grid, dt, E_in, kappa_rho, on_device, stream)
         _check(rc, "fld_submit")
+        if on_device:
+            self._inputs[t] = (E_in, kappa_rho)
         return t
 
     def result_tensor(self, res: fld_result, shape):
@@ -504,7 +527,10 @@ class Server:
         return fld_poll(self.handle, ticket)
 
     def release(self, ticket: int):
-        return fld_release(self.handle, ticket)
+        rc = fld_release(self.handle, ticket)
+        if rc == FLD_OK:
+            self._inputs.pop(ticket, None)
+        return rc
 
     def info(self) -> dict:
         return fld_server_info_get(self.handle)
@@ -621,6 +647,9 @@ class Plan:
 
     def tuning(self) -> dict:
         return fld_plan_tuning(self.handle)
+
+    def cycle_bytes(self, what: int = FLD_CYCLE_ITERATION):
+        return fld_plan_cycle_bytes(self.handle, what)
 
     def radiation_moments(self, E, kappa_rho, v=None, dt=None, want=("F", "f_r", "edd", "P"), stream=None):
         """Allocate the requested outputs (torch, on the plan's device) and run

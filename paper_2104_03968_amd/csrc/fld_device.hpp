@@ -149,7 +149,20 @@ struct JobList {
     const int32_t* prefix;
     int32_t njobs;
     int32_t total;       // prefix[njobs]
+    int64_t cells;       // cells of the listed levels (host bookkeeping; kernels ignore it)
 };
+
+// Algorithmic-byte accounting.  While a thread has an Acct installed (acct_set),
+// every launch wrapper adds the bytes its kernel must move (each array it reads
+// or writes counted once, per the kernel's own access pattern) and its launch to
+// the Acct instead of launching, so a driver such as one outer iteration can be
+// replayed on the host to count what it moves.
+struct Acct {
+    double bytes = 0.0;
+    int64_t launches = 0;
+};
+void acct_set(Acct* a);      // nullptr: launch normally
+Acct* acct_get();
 
 // Per-call pointers of fld_step (one entry per grid).
 struct StepIO {

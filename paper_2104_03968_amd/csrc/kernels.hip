@@ -2365,6 +2365,24 @@ inline int blocks_for_xcd(int total, int nblk) {
 }  // namespace
 
 // ---- launch wrappers ---------------------------------------------------------
+// Each wrapper also states its kernel's algorithmic bytes for the accounting mode
+// (acct_set): every array the kernel reads or writes counted once per cell it
+// covers, w the word of the level arrays, d the dimension; a coarse level has
+// 1/2^d of the fine cells.
+namespace {
+thread_local Acct* t_acct = nullptr;
+// In accounting mode: add `bytes` and one launch, and tell the wrapper not to launch.
+inline bool acct_add(double bytes) {
+    if (!t_acct) return false;
+    t_acct->bytes += bytes;
+    t_acct->launches += 1;
+    return true;
+}
+}  // namespace
+
+void acct_set(Acct* a) { t_acct = a; }
+Acct* acct_get() { return t_acct; }
+
 #define FLD_DISPATCH_DIM(dim, ...) \
     do { if ((dim) == 3) { constexpr int D = 3; __VA_ARGS__; } else { constexpr int D = 2; __VA_ARGS__; } } while (0)
 
@@ -2372,6 +2390,8 @@ void launch_coeff(int dim, bool mixed, int bc, const LevelDesc* L, GridState* S,
                   const StepIO* io, double c, int limiter, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
     if (jl.total <= 0) return;
+    // D pass: E, kappa rho read, D written; face pass: E, kappa rho, D read, faces, b, x written
+    if (acct_add(jl.cells * (8.0 * 3 + 8.0 * (3 + dim + 2) + (mixed ? 4.0 * (dim + 2) : 0.0)))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_COEFF(M, B) hipLaunchKernelGGL((k_coeff<D, M, B>), dim3(g), dim3(kBlock), 0, s, L, S, jl, io, c, limiter, fin, rtol, max_cycles)
     FLD_DISPATCH_DIM(dim, {
@@ -2386,11 +2406,14 @@ void launch_coeff(int dim, bool mixed, int bc, const LevelDesc* L, GridState* S,
 void launch_finalize(const LevelDesc* L, GridState* S, JobList jl, int mode, double rtol,
                      int max_cycles, hipStream_t s) {
     if (jl.njobs <= 0) return;
+    if (acct_add(0.0)) return;                           // a grid's tile partials: negligible
     hipLaunchKernelGGL(k_finalize, dim3(jl.njobs), dim3(kBlock), 0, s, L, S, jl, mode, rtol, max_cycles);
 }
 
 void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int galerkin, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // fine faces read, coarse faces written (list: the fine levels)
+    if (acct_add(jl.cells * (8.0 * dim + (mixed ? 4.0 * dim : 8.0 * dim) / (1 << dim)))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_coarsen<D, true>), dim3(g), dim3(kBlock), 0, s, L, jl, galerkin);
@@ -2401,6 +2424,8 @@ void launch_coarsen(int dim, bool mixed, const LevelDesc* L, JobList jl, int gal
 void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                    int color, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // x of every cell, b of the updated half, every face array, x of the updated half written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (2 + dim))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_smooth<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl, color);
@@ -2411,6 +2436,8 @@ void launch_smooth(int dim, bool fp32, const LevelDesc* L, const GridState* S, J
 void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                      int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // list: coarse cells; the children's x, b and faces read, coarse b and x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * ((1 << dim) * (2 + dim) + 2))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_restrict<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -2421,6 +2448,8 @@ void launch_restrict(int dim, bool fp32, const LevelDesc* L, const GridState* S,
 void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                     int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // list: fine cells; x read and written, the coarse correction read
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (2.0 + 1.0 / (1 << dim)))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_prolong<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -2431,6 +2460,8 @@ void launch_prolong(int dim, bool fp32, const LevelDesc* L, const GridState* S, 
 void launch_restrict_rhs(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // list: coarse cells; the children's b read, coarse b and x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * ((1 << dim) + 2))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_restrict_rhs<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -2441,6 +2472,8 @@ void launch_restrict_rhs(int dim, bool fp32, const LevelDesc* L, const GridState
 void launch_fmg_interp(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                        int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // list: fine cells; the coarse solution read, x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (1.0 + 1.0 / (1 << dim)))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_fmg_interp<D, float>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -2456,6 +2489,16 @@ bool fused3_supported(bool fp32) {
 void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
                    int from_xs, int fz, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    {   // b and three face arrays read, the iterate read (not from zero) and written; the
+        // restricting sweep writes the coarse b and x, the prolonging one reads coarse x
+        const double w = fp32 ? 4.0 : 8.0;
+        const bool from_zero = mode == SW_ZERO || mode == SW_ZERO_RESTR;
+        const bool restr = mode == SW_LOAD_RESTR || mode == SW_ZERO_RESTR;
+        double words = 5.0 + (from_zero ? 0.0 : 1.0);
+        if (restr) words += 2.0 / 8.0;
+        if (mode == SW_PROLONG) words += 1.0 / 8.0;
+        if (acct_add(jl.cells * w * words)) return;
+    }
     const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_SWEEP3(M)                                                                                   \
     do {                                                                                               \
@@ -2523,6 +2566,9 @@ void up2_t(const LevelDesc* L, const GridState* S, JobList jl, int g, hipStream_
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
                   int wide, int fy, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // b and two face arrays read (+ x when it starts from the iterate), xs written,
+    // coarse b and x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (4.0 + (load_x ? 1.0 : 0.0) + 2.0 / 4.0))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
         if (fp32) down2_t<float, NU, WIDE, FY>(L, S, jl, load_x, g, s);
@@ -2533,6 +2579,8 @@ void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
                 int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // xs, b, two face arrays and the coarse correction read, x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (5.0 + 1.0 / 4.0))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
         if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, g, s);
@@ -2559,6 +2607,9 @@ int prepare_tail(int dim, bool fp32, size_t smem) {
 void launch_tail(int dim, bool fp32, int bc, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s) {
     if (jl.njobs <= 0) return;
+    // list: each grid's first tail level; its b and the face arrays of every tail level
+    // (2^d / (2^d - 1) times the first level's) read once, its x written
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (2.0 + dim * (double)(1 << dim) / ((1 << dim) - 1)))) return;
 #define FLD_TAIL(T_, B) hipLaunchKernelGGL((k_tail<D, T_, B>), dim3(jl.njobs), dim3(kTailThreads), smem, s, L, S, jl, nu1, nu2, plain64)
     FLD_DISPATCH_DIM(dim, {
         if (bc) { if (fp32) FLD_TAIL(float, true); else FLD_TAIL(double, true); }
@@ -2570,6 +2621,7 @@ void launch_tail(int dim, bool fp32, int bc, const LevelDesc* L, const GridState
 void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                          hipStream_t s) {
     if (jl.njobs <= 0) return;
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (2 + dim))) return;   // b, faces read, x written
     FLD_DISPATCH_DIM(dim, {
         if (fp32) hipLaunchKernelGGL((k_coarse_solve<D, float>), dim3(jl.njobs), dim3(kCoarseThreads), 0, s, L, S, jl);
         else hipLaunchKernelGGL((k_coarse_solve<D, double>), dim3(jl.njobs), dim3(kCoarseThreads), 0, s, L, S, jl);
@@ -2579,6 +2631,10 @@ void launch_coarse_solve(int dim, bool fp32, const LevelDesc* L, const GridState
 void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl,
                      int select, int zero_x, int fin, double rtol, int max_cycles, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
+    // X, B0 and the face arrays read, R written; mixed: the FP32 right-hand side (and a
+    // zeroed FP32 iterate), else a zeroed FP64 iterate
+    if (acct_add(jl.cells * (8.0 * (3 + dim) + (mixed ? 4.0 + (zero_x ? 4.0 : 0.0) : (zero_x ? 8.0 : 0.0)))))
+        return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_residual<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, select, zero_x, fin, rtol, max_cycles);
@@ -2586,8 +2642,9 @@ void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobL
     });
 }
 
-#define FLD_CG_LAUNCH(kern)                                                                          \
+#define FLD_CG_LAUNCH(kern, bytes_per_cell)                                                          \
     if (jl.total <= 0) return;                                                                       \
+    if (acct_add(jl.cells * (bytes_per_cell))) return;                                               \
     const int g = blocks_for_xcd(jl.total, nblk);                                                        \
     FLD_DISPATCH_DIM(dim, {                                                                          \
         if (mixed) hipLaunchKernelGGL((kern<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles); \
@@ -2596,22 +2653,25 @@ void launch_residual(int dim, bool mixed, const LevelDesc* L, GridState* S, JobL
 
 void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
-    FLD_CG_LAUNCH(k_cg_rz);
+    FLD_CG_LAUNCH(k_cg_rz, 8.0 + (mixed ? 4.0 : 8.0));              // r, z read
 }
 
 void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                   hipStream_t s) {
-    FLD_CG_LAUNCH(k_cg_pq);
+    // z, the old direction and the face arrays read; p and q written
+    FLD_CG_LAUNCH(k_cg_pq, (mixed ? 4.0 : 8.0) + 8.0 + 8.0 * dim + 16.0);
 }
 
 void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
                       hipStream_t s) {
-    FLD_CG_LAUNCH(k_cg_update);
+    // X, p, R, q read; X, R written; the next V-cycle's right-hand side / iterate written
+    FLD_CG_LAUNCH(k_cg_update, 32.0 + 16.0 + 8.0);
 }
 
 void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s) {
     if (jl.total <= 0) return;
+    if (acct_add(jl.cells * (16.0 + (mixed ? 4.0 : 8.0)))) return;     // X and z read, X written
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, {
         if (mixed) hipLaunchKernelGGL((k_correct<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
@@ -2622,15 +2682,18 @@ void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S,
 void launch_output(int dim, const LevelDesc* L, JobList jl, const StepIO* io, int nblk,
                    hipStream_t s) {
     if (jl.total <= 0) return;
+    if (acct_add(jl.cells * 16.0)) return;                               // X read, E_out written
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_DISPATCH_DIM(dim, { hipLaunchKernelGGL((k_output<D>), dim3(g), dim3(kBlock), 0, s, L, jl, io); });
 }
 
 void launch_count(const GridState* S, int ngrids, Control* ctrl, hipStream_t s) {
+    if (acct_add(0.0)) return;
     hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, s, S, ngrids, ctrl);
 }
 
 void launch_set_active(GridState* S, int ngrids, int value, hipStream_t s) {
+    if (acct_add(0.0)) return;
     hipLaunchKernelGGL(k_set_active, dim3((ngrids + kBlock - 1) / kBlock), dim3(kBlock), 0, s, S, ngrids, value);
 }
 

@@ -657,7 +657,9 @@ static int upload_list(Plan& p, HostList& l) {
     if (!l.levels.empty())
         FLD_HIP(hipMemcpy(lv, l.levels.data(), l.levels.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back()};
+    int64_t cells = 0;
+    for (int32_t li : l.levels) cells += (int64_t)p.levels[li].n[0] * p.levels[li].n[1] * p.levels[li].n[2];
+    l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back(), cells};
     return FLD_OK;
 }
 
@@ -1189,6 +1191,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
             else enqueue_cycle(p, s);
             launch_set_active(p.dS, G, 1, s);
         }
+        if (kernel == FLD_KERNEL_MG) plan_vcycle_mg(p, s);
         if (kernel == FLD_KERNEL_EXCHANGE) {
             const fld_gas* g = &p.last_gas;
             launch_exchange(p.dEx + (size_t)p.ex_last * G, G, p.max_n, g->c, g->a_rad, g->c_v, g->max_halley,
@@ -1209,6 +1212,26 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / reps;
     *cells = nc;
+    return FLD_OK;
+}
+
+// Algorithmic bytes (and launches) of one pass of a driver, counted by replaying it
+// with the launch wrappers in accounting mode: what = FLD_CYCLE_ITERATION one outer
+// iteration (V-cycle, CG update or defect correction, stop test), FLD_CYCLE_MG the
+// multigrid part of a V-cycle, FLD_CYCLE_FMG the first outer iteration of a step with
+// the full-multigrid start.
+int plan_cycle_bytes(Plan& p, int what, double* bytes, int64_t* launches) {
+    Acct a;
+    acct_set(&a);
+    switch (what) {
+        case FLD_CYCLE_ITERATION: enqueue_cycle(p, nullptr); break;
+        case FLD_CYCLE_MG: plan_vcycle_mg(p, nullptr); break;
+        case FLD_CYCLE_FMG: enqueue_fmg_cycle(p, nullptr); break;
+        default: acct_set(nullptr); return FLD_ERR_INVALID_ARG;
+    }
+    acct_set(nullptr);
+    *bytes = a.bytes;
+    if (launches) *launches = a.launches;
     return FLD_OK;
 }
 
@@ -1524,9 +1547,15 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     return FLD_OK;
 }
 
+int32_t fld_plan_cycle_bytes(fld_plan_t plan, int32_t what, double* bytes, int64_t* launches) {
+    if (!plan || !bytes) return FLD_ERR_INVALID_ARG;
+    if (!plan->p.ws) return FLD_ERR_NO_WORKSPACE;
+    return fld::plan_cycle_bytes(plan->p, what, bytes, launches);
+}
+
 int32_t fld_profile_kernel(fld_plan_t plan, int32_t kernel, int32_t level, int32_t reps, void* stream,
                            double* avg_ms, int64_t* cells) {
-    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_SWEEP3)
+    if (!plan || !avg_ms || !cells || reps < 1 || kernel < 0 || kernel > FLD_KERNEL_MG)
         return FLD_ERR_INVALID_ARG;
     Plan& p = plan->p;
     if (!p.ws) return FLD_ERR_NO_WORKSPACE;

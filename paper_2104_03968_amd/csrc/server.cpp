@@ -103,6 +103,7 @@ struct Request {
     int64_t n = 0;
     const double* E_dev = nullptr;            // device inputs (caller keeps them until done)
     const double* kr_dev = nullptr;
+    hipEvent_t ready = nullptr;               // device inputs: written once this event completes
     std::vector<double> E_host, kr_host;      // host inputs, copied at submit
     size_t plan_bytes = 0;                    // single-grid plan workspace
     size_t off_ws = kNoOff, off_in = kNoOff, off_out = kNoOff;
@@ -112,6 +113,10 @@ struct Request {
     int status = FLD_PENDING;
     fld_stats stats{};
     double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+
+    ~Request() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 }  // namespace
@@ -251,6 +256,8 @@ int Server::start_request(Request* r, int slot) {
     double* out = reinterpret_cast<double*>(arena_base + r->off_out);
     const size_t nb = 8 * (size_t)r->n;
     if (r->E_dev) {
+        // the caller's producer stream may still be writing the inputs
+        if (r->ready) FLD_HIP(hipStreamWaitEvent(stream, r->ready, 0));
         FLD_HIP(hipMemcpyAsync(inE, r->E_dev, nb, hipMemcpyDeviceToDevice, stream));
         FLD_HIP(hipMemcpyAsync(inK, r->kr_dev, nb, hipMemcpyDeviceToDevice, stream));
     } else {
@@ -474,6 +481,16 @@ int32_t fld_submit(fld_server_t server, const fld_request* req, uint64_t* ticket
         if (req->inputs_on_device) {
             r->E_dev = req->E_in;
             r->kr_dev = req->kappa_rho;
+            int cur = -1;
+            if (hipGetDevice(&cur) != hipSuccess) return FLD_ERR_HIP;
+            if (cur != s.device && hipSetDevice(s.device) != hipSuccess) return FLD_ERR_HIP;
+            hipError_t e = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(r->ready, static_cast<hipStream_t>(req->stream));
+            if (cur != s.device) (void)hipSetDevice(cur);
+            if (e != hipSuccess) {
+                fld::set_error("fld_submit: input event", e);
+                return FLD_ERR_HIP;
+            }
         } else {
             r->E_host.assign(req->E_in, req->E_in + r->n);
             r->kr_host.assign(req->kappa_rho, req->kappa_rho + r->n);

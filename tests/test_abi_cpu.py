@@ -177,6 +177,9 @@ def test_calls_before_bind_fail_cleanly():
     with pytest.raises(fld.FLDError) as e:
         fld.fld_plan_tuning(h)
     assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_plan_cycle_bytes(h, fld.FLD_CYCLE_ITERATION)
+    assert e.value.code == fld.FLD_ERR_NO_WORKSPACE
     fld.fld_plan_destroy(h)
 
 

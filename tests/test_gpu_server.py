@@ -139,3 +139,30 @@ def test_rejections_and_tickets():
     assert rc == fld.FLD_ERR_BAD_INPUT
     assert srv.release(t) == 0 and srv.release(t) == fld.FLD_ERR_UNKNOWN_TICKET
     srv.close()
+
+
+def test_device_inputs_are_read_after_their_producer_stream():
+    """Inputs still being written on another stream when they are submitted: the server's
+    copy waits for the work enqueued on that stream before fld_submit, so the request sees
+    the final values (zeros would be rejected as bad input)."""
+    g = _inputs(31, (96, 128), 3e-3)
+    ref = _run(fld.Server(1 << 28), [g])[0][0]
+    side = torch.cuda.Stream()
+    E = torch.zeros(g.E.shape, dtype=torch.float64, device="cuda")
+    K = torch.zeros(g.E.shape, dtype=torch.float64, device="cuda")
+    src_E, src_K = dev(g.E), dev(g.kappa_rho)
+    torch.cuda.synchronize()
+    big = torch.ones((4096, 4096), dtype=torch.float32, device="cuda")
+    srv = fld.Server(1 << 28)
+    with torch.cuda.stream(side):
+        for _ in range(8):                      # keep the producer stream busy for a while
+            big = torch.mm(big, big) * 1e-4
+        E.copy_(src_E)
+        K.copy_(src_K)
+        t = srv.submit(E, K, g.dt, h=g.h, stream=side)
+    rc, res = srv.wait(t, 120.0)
+    assert rc == 0, rc
+    x = srv.result_tensor(res, g.E.shape).cpu().numpy()
+    assert np.array_equal(x, ref)
+    assert srv.release(t) == 0
+    srv.close()

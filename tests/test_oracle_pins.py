@@ -415,3 +415,14 @@ def test_heating_cooling_relaxation(golden_dir):
             assert 0.02 * e_eq < a < e_eq and abs(a - b) / a < 0.05          # same time scale
         else:
             assert e_eq < a < 2 * e_eq and abs(a - b) / a < 0.05
+
+
+def test_solve_refuses_an_unconverged_answer():
+    """A solve that stops above its tolerance raises instead of returning its best iterate."""
+    g = W.c2_inputs(64)
+    D = O.diffusion_coefficient(g.E, g.kappa_rho, g.h)
+    w = O.face_weights(D, g.dt, g.h)
+    A = O.assemble_operator(w)
+    with pytest.raises(O.OracleNotConverged) as e:
+        O.solve(A, g.E, method="cg", tol=1e-13, w=w, maxiter=3)
+    assert e.value.info.rel_residual > 1e-13 and e.value.info.iterations == 3
