@@ -63,13 +63,19 @@ __host__ __device__ constexpr size_t fused_lds(int word, int halo, int wide, int
 }
 constexpr size_t kFusedLdsMax = 160 * 1024;
 
-// Fused 3D sweep blocks: kS3X x FY interior columns and fz planes (fz even, tunable);
-// FY by word size, and one row less where the sweep also restricts (a wider halo).
-constexpr int kS3X = 64;
-__host__ __device__ constexpr int sweep3_fy(int word) { return word == 4 ? 8 : 4; }
-__host__ __device__ constexpr int sweep3_fy_restrict(int word) { return word == 4 ? 6 : 4; }
-__host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], int fy, int fz) {
-    return ((n[0] + kS3X - 1) / kS3X) * ((n[1] + fy - 1) / fy) * ((n[2] + fz - 1) / fz);
+// Fused 3D sweep blocks: a window of kR3PX x kR3PY xy positions, one per thread,
+// holding FX x FY interior columns and a halo of 2 positions (4 where the sweep also
+// restricts, which keeps the interior on even coordinates), marched over fz planes
+// (fz even, tunable).
+constexpr int kR3PX = 64;
+constexpr int kR3PY = 16;
+constexpr int kR3Threads = kR3PX * kR3PY;
+__host__ __device__ constexpr int sweep3_halo(bool restr) { return restr ? 4 : 2; }
+__host__ __device__ constexpr int sweep3_fx(bool restr) { return kR3PX - 2 * sweep3_halo(restr); }
+__host__ __device__ constexpr int sweep3_fy(bool restr) { return kR3PY - 2 * sweep3_halo(restr); }
+__host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], bool restr, int fz) {
+    const int fx = sweep3_fx(restr), fy = sweep3_fy(restr);
+    return ((n[0] + fx - 1) / fx) * ((n[1] + fy - 1) / fy) * ((n[2] + fz - 1) / fz);
 }
 
 struct LevelDesc {

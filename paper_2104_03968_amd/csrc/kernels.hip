@@ -23,6 +23,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace fld {
 
 namespace {
@@ -1392,88 +1394,71 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
 
 // ---------------------------------------------------------------------------
 // Fused 3D sweeps.  One launch runs one whole red-black sweep (colour c0, then
-// 1-c0) over FX x FY x fz cell blocks: a block marches along z through its
-// planes, holding a ring of x planes and of b / face-weight planes in LDS.
-// At step zt it stores plane zt (loaded two steps earlier into registers) and
-// issues the loads of plane zt+2, then updates colour c0 on plane zt-1 and
-// colour 1-c0 on plane zt-2 -- the first colour must be final on planes
-// zt-3..zt-1 before the second reads them -- and writes plane zt-2 out.  The xy halo
-// (colour c0 on one ring more than 1-c0) is recomputed exactly as the
-// neighbouring blocks compute it.  Modes add the transfers of the V-cycle:
+// 1-c0) over blocks of FX x FY interior columns and fz planes.  A block of
+// kR3PX x kR3PY threads owns a window of as many xy positions (the interior plus a
+// halo of H positions), one position per thread, and marches along z.  Each thread
+// keeps its own position's iterate and operator (b and the three lower faces) for
+// the planes in flight in registers; only the iterate and the x / y lower faces go
+// through LDS, in a ring of plane slots, for the in-plane neighbours.  At step zt:
+//   A  store plane zt (loaded two steps earlier) to its slot, load plane zt + 2
+//   -- barrier --
+//   C  colour c0 on plane zt - 1 (on HC rings around the interior): the in-plane
+//      neighbours from the slot, the z-neighbours are the thread's own registers
+//      (zt - 2 not yet updated, zt as loaded)
+//   D  colour 1 - c0 on plane zt - 2 (HC - 1 rings): the z-neighbours zt - 3 and
+//      zt - 1 are again the thread's own registers, both updated by C; the position
+//      that updates in D is the one that updated in C (the colour flips with z)
+//   plane zt - 2 is final on the interior and is written out.
+// The halo recomputes exactly what the neighbouring blocks compute.  Restricting
+// sweeps (H = 4, HC = 2) also store D's results to the slot and form the residual of
+// the final iterate on plane zt - 3 into an LDS plane; after a second barrier one
+// thread per coarse cell adds its eight children, two planes in turn, and writes the
+// coarse right-hand side (and a zero coarse iterate).  Modes:
 //   SW_LOAD      start from the stored iterate
 //   SW_ZERO      start from zero (nothing loaded)
-//   SW_*_RESTR   also compute the residual of the final iterate on plane zt-3
-//                and average it onto the coarse right-hand side (one more halo
-//                ring, one more plane of lag)
-//   SW_PROLONG   add the piecewise-constant prolongation of the coarse
-//                correction to the iterate as it is loaded
-// Each cell update and residual uses the operand order of the per-colour
-// kernels (k_smooth, residual_at, k_restrict), so both paths give bitwise
-// equal results.  A sweep never writes the array it reads.
+//   SW_*_RESTR   also restrict the final residual onto the coarse level
+//   SW_PROLONG   add the piecewise-constant prolongation of the coarse correction to
+//                the iterate as it is loaded
+// Each cell update and residual uses the operand order of the per-colour kernels
+// (k_smooth, residual_at, k_restrict), so both paths give bitwise equal results.
+// A sweep never writes the array it reads.  Cells outside the level hold x = b = 0
+// and zero faces, which leaves every sum exact.
 // ---------------------------------------------------------------------------
 enum SweepMode : int { SW_LOAD = 0, SW_ZERO = 1, SW_LOAD_RESTR = 2, SW_ZERO_RESTR = 3, SW_PROLONG = 4 };
 
-template <typename T, int W, int H, int RX, int RB>
-struct Sweep3Tile {
-    T x[RX][H][W];
-    T b[RB][H][W];
-    T w0[RB][H][W];
-    T w1[RB][H][W];
-    T w2[RB][H][W];
-};
-
-template <typename T, int MODE>
-struct Sweep3Shape {
+template <int MODE>
+struct Sweep3Mode {
     static constexpr bool RESTR = MODE == SW_LOAD_RESTR || MODE == SW_ZERO_RESTR;
     static constexpr bool LOADX = MODE == SW_LOAD || MODE == SW_LOAD_RESTR || MODE == SW_PROLONG;
     static constexpr bool PROL = MODE == SW_PROLONG;
-    static constexpr int HALO = RESTR ? 3 : 2;
-    static constexpr int FX = kS3X;
-    static constexpr int FY = RESTR ? sweep3_fy_restrict(sizeof(T)) : sweep3_fy(sizeof(T));
-    static constexpr int W = FX + 2 * HALO, H = FY + 2 * HALO;
-    static constexpr int RX = HALO + 2;          // x planes zt-RX+1 .. zt
-    static constexpr int RB = HALO + 1;          // b / w planes zt-RB+1 .. zt
-    using Tile = Sweep3Tile<T, W, H, RX, RB>;
+    static constexpr int H = sweep3_halo(RESTR);    // halo positions of the window
+    static constexpr int HC = RESTR ? 2 : 1;         // rings of the first colour around the interior
+    static constexpr int HX = HC + 1;                // rings whose iterate is read
+    static constexpr int FX = sweep3_fx(RESTR), FY = sweep3_fy(RESTR);
+    static constexpr int R = RESTR ? 6 : 4;          // LDS plane slots
 };
 
-// Update colour c on plane p (ring slots s_m, s_0, s_p of planes p-1, p, p+1) over
-// local [m, W-m) x [m, H-m).
-template <typename T, typename Tl, int W, int H>
-__device__ __forceinline__ void sweep3_stage(Tl& t, int gx0, int gy0, int gp, int c, int m, int xs_m,
-                                             int xs_0, int xs_p, int bs_0, int bs_p) {
-    constexpr int PW = W / 2;
-    for (int e = threadIdx.x; e < PW * H; e += kBlock) {
-        const int lj = e / PW, pc = e - lj * PW;
-        if (lj < m || lj >= H - m) continue;
-        const int li = 2 * pc + ((gx0 + gy0 + lj + gp + c) & 1);
-        if (li < m || li >= W - m) continue;
-        T s = t.b[bs_0][lj][li], dg = T(1);
-        T w = t.w0[bs_0][lj][li];
-        s += w * t.x[xs_0][lj][li - 1]; dg += w;
-        w = t.w0[bs_0][lj][li + 1];
-        s += w * t.x[xs_0][lj][li + 1]; dg += w;
-        w = t.w1[bs_0][lj][li];
-        s += w * t.x[xs_0][lj - 1][li]; dg += w;
-        w = t.w1[bs_0][lj + 1][li];
-        s += w * t.x[xs_0][lj + 1][li]; dg += w;
-        w = t.w2[bs_0][lj][li];
-        s += w * t.x[xs_m][lj][li]; dg += w;
-        w = t.w2[bs_p][lj][li];
-        s += w * t.x[xs_p][lj][li]; dg += w;
-        t.x[xs_0][lj][li] = s / dg;
-    }
-}
+template <typename T, int R, bool RESTR>
+struct Sweep3Lds {
+    T x[R][kR3PY][kR3PX];
+    T w0[R][kR3PY][kR3PX];
+    T w1[R][kR3PY][kR3PX];
+    T res[RESTR ? kR3PY : 1][kR3PX];
+};
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kR3Threads)
 k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int c0, int from_xs,
          int fz) {
-    using Sh = Sweep3Shape<T, MODE>;
-    constexpr int HALO = Sh::HALO, FX = Sh::FX, FY = Sh::FY, W = Sh::W, H = Sh::H, RX = Sh::RX, RB = Sh::RB;
-    constexpr int NE = (W * H + kBlock - 1) / kBlock;
-    static_assert((FX / 2) * (FY / 2) <= kBlock, "one coarse cell per thread");
-    static_assert(FX % 2 == 0 && FY % 2 == 0, "blocks cover whole coarse cells");
-    __shared__ typename Sh::Tile t;
+    using M = Sweep3Mode<MODE>;
+    constexpr int H = M::H, HC = M::HC, HX = M::HX, FX = M::FX, FY = M::FY, R = M::R;
+    constexpr int NB = 6;                             // register ring of planes (zt - 3 .. zt + 2)
+    __shared__ Sweep3Lds<T, R, M::RESTR> t;
+    const int lx = threadIdx.x % kR3PX, ly = threadIdx.x / kR3PX;
+    // rings outside the interior: o >= H is interior; o >= H - HC takes the first colour,
+    // o >= H - HC + 1 the second, o >= H - HX has its iterate read by a neighbour
+    const int o = min(min(lx, kR3PX - 1 - lx), min(ly, kR3PY - 1 - ly));
+    const bool in_c = o >= H - HC, in_d = o >= H - HC + 1, in_r = o >= H;
     const XcdOrder order(jl.total);
     for (int k = order.first(); order.more(k); k += order.per) {
         const int tt = order.tile(k);
@@ -1484,149 +1469,161 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
         const int tx_n = (n0 + FX - 1) / FX, ty_n = (n1 + FY - 1) / FY;
         const int tx = lt % tx_n, rest = lt / tx_n;
-        const int gx0 = tx * FX - HALO, gy0 = (rest % ty_n) * FY - HALO;
+        const int gx0 = tx * FX - H, gy0 = (rest % ty_n) * FY - H;
         const int z0 = (rest / ty_n) * fz, z1 = min(z0 + fz, n2);
-        const int zs = z0 - HALO, ze = z1 + HALO;          // planes loaded: [zs, ze)
+        const int zs = z0 - HX, ze = z1 + HX;          // planes stored, and steps: [zs, ze)
+        const int gx = gx0 + lx, gy = gy0 + ly;
+        const bool in_xy = gx >= 0 && gx < n0 && gy >= 0 && gy < n1;
         const long sy = n0, sz = (long)n0 * n1;
-        const gptr<T> xin = as_global(Sh::LOADX ? (from_xs ? Arr<T>::xs(d) : Arr<T>::x(d)) : Arr<T>::x(d));
+        const long cxy = min(max(gx, 0), n0 - 1) + (long)min(max(gy, 0), n1 - 1) * sy;   // clamped column
+        const gptr<T> xin = as_global(M::LOADX ? (from_xs ? Arr<T>::xs(d) : Arr<T>::x(d)) : Arr<T>::x(d));
         const gptr<T> xout = as_global(from_xs ? Arr<T>::x(d) : Arr<T>::xs(d));
         const gptr<T> bg = as_global(Arr<T>::b(d));
         const gptr<T> w0g = as_global(Arr<T>::w(d, 0));
         const gptr<T> w1g = as_global(Arr<T>::w(d, 1));
         const gptr<T> w2g = as_global(Arr<T>::w(d, 2));
-        gptr<T> cx = nullptr;
+        gptr<T> cx = nullptr, cb = nullptr;
         int cn0 = 0, cn1 = 0;
-        if (Sh::PROL || Sh::RESTR) {
+        long ccol = 0;
+        if (M::PROL || M::RESTR) {
             const LevelDesc& cL = L[d.coarse];
             cx = as_global(Arr<T>::x(cL));
+            cb = as_global(Arr<T>::b(cL));
             cn0 = cL.n[0];
             cn1 = cL.n[1];
+            ccol = (min(max(gx, 0), n0 - 1) >> 1) + (long)cn0 * (min(max(gy, 0), n1 - 1) >> 1);
         }
-        // Plane loads are branch-free (a cell outside the level loads its nearest
-        // in-level cell; the value is replaced by 0 when it is stored to LDS), so every
-        // thread issues the same loads, nothing uses them before the store two steps
-        // later, and the wait for that plane does not also wait for the next one.
-        struct Regs {
-            T x[NE], c[NE], b[NE], w0[NE], w1[NE], w2[NE];
-            uint32_t ok;        // bit r: element r lies inside the level
+        // the thread's planes in flight: iterate, b, lower faces (and the coarse correction)
+        T X[NB], B[NB], W0[NB], W1[NB], W2[NB], CC[NB];
+        // branch-free loads of plane gk at the clamped column (masked when stored)
+        auto load = [&](auto Sl, int gk) {
+            constexpr int q = decltype(Sl)::value;
+            const int kc = min(max(gk, 0), n2 - 1);
+            const long idx = cxy + kc * sz;
+            if (M::LOADX) X[q] = xin[idx];
+            B[q] = bg[idx];
+            W0[q] = w0g[idx];
+            W1[q] = w1g[idx];
+            W2[q] = w2g[idx];
+            if (M::PROL) CC[q] = cx[ccol + (long)cn0 * cn1 * (kc >> 1)];
         };
-        auto load_plane = [&](Regs& v, int gk) {
-            v.ok = 0;
-#pragma unroll
-            for (int r = 0; r < NE; ++r) {
-                const int e = threadIdx.x + r * kBlock;
-                const int ec = min(e, W * H - 1);
-                const int lj = ec / W, li = ec - lj * W;
-                const int gi = gx0 + li, gj = gy0 + lj;
-                const bool ok = e < W * H && gk >= 0 && gk < n2 && gi >= 0 && gi < n0 && gj >= 0 && gj < n1;
-                // out-of-level cells load their nearest in-level cell (a line read anyway)
-                const int ic = min(max(gi, 0), n0 - 1), jc = min(max(gj, 0), n1 - 1), kc = min(max(gk, 0), n2 - 1);
-                const long idx = ic + jc * sy + kc * sz;
-                v.ok |= (ok ? 1u : 0u) << r;
-                v.b[r] = bg[idx];
-                v.w0[r] = w0g[idx];
-                v.w1[r] = w1g[idx];
-                v.w2[r] = w2g[idx];
-                if (Sh::LOADX) v.x[r] = xin[idx];
-                if (Sh::PROL) v.c[r] = cx[(ic >> 1) + (long)cn0 * ((jc >> 1) + (long)cn1 * (kc >> 1))];
-            }
-        };
-        // restriction: thread e < (FX/2)(FY/2) owns one coarse cell of the block and sums
-        // its 8 children over two planes
         T racc = T(0);
-        gptr<T> cb = nullptr;
-        int cI = 0, cJ = 0, cnx = 0, cny = 0;
-        bool rown = false;
-        if (Sh::RESTR) {
-            const LevelDesc& cL = L[d.coarse];
-            cb = as_global(Arr<T>::b(cL));
-            cnx = cL.n[0];
-            cny = cL.n[1];
-            const int e = threadIdx.x, cj = e / (FX / 2), ci = e - cj * (FX / 2);
-            cI = (gx0 + HALO) / 2 + ci;
-            cJ = (gy0 + HALO) / 2 + cj;
-            rown = e < (FX / 2) * (FY / 2) && cI < cnx && cJ < cny;
-        }
-        // step zt: store plane zt (loaded two steps earlier), load plane zt + 2 into the
-        // same registers, then the two colour stages, the output and the restriction.
-        // ze - zs is even (fz and the halos are), so the steps pair up.
-        auto step = [&](int zt, Regs& v) {
-            const int px = (zt - zs) % RX, pb = (zt - zs) % RB;
-#pragma unroll
-            for (int r = 0; r < NE; ++r) {
-                const int e = threadIdx.x + r * kBlock;
-                if (e < W * H) {
-                    const int lj = e / W, li = e - lj * W;
-                    const bool ok = (v.ok >> r) & 1u;
-                    T xx = Sh::LOADX ? v.x[r] : T(0);
-                    if (Sh::PROL) xx += v.c[r];
-                    t.x[px][lj][li] = ok ? xx : T(0);
-                    t.b[pb][lj][li] = ok ? v.b[r] : T(0);
-                    t.w0[pb][lj][li] = ok ? v.w0[r] : T(0);
-                    t.w1[pb][lj][li] = ok ? v.w1[r] : T(0);
-                    t.w2[pb][lj][li] = ok ? v.w2[r] : T(0);
-                }
+        // coarse cell of the restriction owners: thread e < (FX/2)(FY/2)
+        const int rci = threadIdx.x % (FX / 2), rcj = threadIdx.x / (FX / 2);
+        const bool rown = M::RESTR && threadIdx.x < (FX / 2) * (FY / 2) && (gx0 + H) / 2 + rci < cn0 &&
+                          (gy0 + H) / 2 + rcj < cn1;
+        auto step = [&](auto Sc, int zt) {
+            constexpr int q = decltype(Sc)::value;               // register slot of plane zt
+            constexpr int q1 = (q + NB - 1) % NB, q2 = (q + NB - 2) % NB, q3 = (q + NB - 3) % NB;
+            const int s0 = (zt - zs) % R;
+            // A: plane zt enters the window (zero outside the level)
+            {
+                const bool in = in_xy && zt >= 0 && zt < n2;
+                T xv = M::LOADX ? X[q] : T(0);
+                if (M::PROL) xv += CC[q];
+                X[q] = in ? xv : T(0);
+                B[q] = in ? B[q] : T(0);
+                W0[q] = in ? W0[q] : T(0);
+                W1[q] = in ? W1[q] : T(0);
+                W2[q] = in ? W2[q] : T(0);
+                t.x[s0][ly][lx] = X[q];
+                t.w0[s0][ly][lx] = W0[q];
+                t.w1[s0][ly][lx] = W1[q];
             }
-            load_plane(v, zt + 2);                                // past ze: all clamped, unused
+            if (zt + 2 < ze) load(std::integral_constant<int, (q + 2) % NB>{}, zt + 2);
             __syncthreads();
-            // ring slot of plane p (p >= zs)
-            auto sx = [&](int p) { return (p - zs) % RX; };
-            auto sb = [&](int p) { return (p - zs) % RB; };
-            const int p1 = zt - 1;                                // first colour
-            if (p1 >= z0 - (HALO - 1) && p1 < z1 + (HALO - 1))
-                sweep3_stage<T, typename Sh::Tile, W, H>(t, gx0, gy0, p1, c0, 1, sx(p1 - 1), sx(p1), sx(p1 + 1),
-                                                         sb(p1), sb(p1 + 1));
-            __syncthreads();
-            const int p2 = zt - 2;                                // second colour
-            const bool p2ok = p2 >= z0 - (HALO - 2) && p2 < z1 + (HALO - 2);
-            if (p2ok)
-                sweep3_stage<T, typename Sh::Tile, W, H>(t, gx0, gy0, p2, c0 ^ 1, 2, sx(p2 - 1), sx(p2), sx(p2 + 1),
-                                                         sb(p2), sb(p2 + 1));
-            __syncthreads();
-            if (p2 >= z0 && p2 < z1) {                            // plane p2 is final
-                const int s0 = sx(p2);
-                for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
-                    const int lj = e / FX, li = e - lj * FX;
-                    const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
-                    if (gi < n0 && gj < n1) xout[gi + gj * sy + p2 * sz] = t.x[s0][HALO + lj][HALO + li];
-                }
+            // C: colour c0 on plane zt - 1
+            const int p1 = zt - 1;
+            const bool act = ((gx + gy + p1) & 1) == c0;          // this position's colour on p1
+            if (p1 >= z0 - HC && p1 < z1 + HC && p1 >= 0 && p1 < n2 && in_c && in_xy && act) {
+                const int s1 = (p1 - zs) % R;
+                T sm = B[q1], dg = T(1);
+                T w = W0[q1];
+                sm += w * t.x[s1][ly][lx - 1]; dg += w;
+                w = t.w0[s1][ly][lx + 1];
+                sm += w * t.x[s1][ly][lx + 1]; dg += w;
+                w = W1[q1];
+                sm += w * t.x[s1][ly - 1][lx]; dg += w;
+                w = t.w1[s1][ly + 1][lx];
+                sm += w * t.x[s1][ly + 1][lx]; dg += w;
+                w = W2[q1];
+                sm += w * X[q2]; dg += w;
+                w = W2[q];
+                sm += w * X[q]; dg += w;
+                X[q1] = sm / dg;
+                t.x[s1][ly][lx] = X[q1];
             }
-            if (Sh::RESTR) {
+            // D: colour 1 - c0 on plane zt - 2 (the same positions as C)
+            const int p2 = zt - 2;
+            if (p2 >= z0 - (HC - 1) && p2 < z1 + (HC - 1) && p2 >= 0 && p2 < n2 && in_d && in_xy && act) {
+                const int s2 = (p2 - zs) % R;
+                T sm = B[q2], dg = T(1);
+                T w = W0[q2];
+                sm += w * t.x[s2][ly][lx - 1]; dg += w;
+                w = t.w0[s2][ly][lx + 1];
+                sm += w * t.x[s2][ly][lx + 1]; dg += w;
+                w = W1[q2];
+                sm += w * t.x[s2][ly - 1][lx]; dg += w;
+                w = t.w1[s2][ly + 1][lx];
+                sm += w * t.x[s2][ly + 1][lx]; dg += w;
+                w = W2[q2];
+                sm += w * X[q3]; dg += w;
+                w = W2[q1];
+                sm += w * X[q1]; dg += w;
+                X[q2] = sm / dg;
+                if (M::RESTR) t.x[s2][ly][lx] = X[q2];
+            }
+            // plane zt - 2 is final on the interior
+            if (p2 >= z0 && p2 < z1 && in_r && in_xy) xout[cxy + p2 * sz] = X[q2];
+            if (M::RESTR) {
+                // residual of the final iterate on plane zt - 3 (its in-plane neighbours and the
+                // plane below from the slots, the plane above from the registers)
                 const int p3 = zt - 3;
-                if (p3 >= z0 && p3 < z1 && rown) {
-                    const int m_ = sx(p3 - 1), o_ = sx(p3), q_ = sx(p3 + 1), b0_ = sb(p3), bp_ = sb(p3 + 1);
-                    if (((p3 - z0) & 1) == 0) racc = T(0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int li = HALO + 2 * (cI - (gx0 + HALO) / 2) + (q & 1);
-                        const int lj = HALO + 2 * (cJ - (gy0 + HALO) / 2) + (q >> 1);
-                        const T xc = t.x[o_][lj][li];
-                        T r = t.b[b0_][lj][li] - xc;
-                        r -= t.w0[b0_][lj][li] * (xc - t.x[o_][lj][li - 1]);
-                        r -= t.w0[b0_][lj][li + 1] * (xc - t.x[o_][lj][li + 1]);
-                        r -= t.w1[b0_][lj][li] * (xc - t.x[o_][lj - 1][li]);
-                        r -= t.w1[b0_][lj + 1][li] * (xc - t.x[o_][lj + 1][li]);
-                        r -= t.w2[b0_][lj][li] * (xc - t.x[m_][lj][li]);
-                        r -= t.w2[bp_][lj][li] * (xc - t.x[q_][lj][li]);
-                        racc += r;
+                const bool rp = p3 >= z0 && p3 < z1;                // uniform
+                if (rp) {
+                    T r = T(0);
+                    if (in_r && in_xy) {
+                        const int s3 = (p3 - zs) % R, s4 = (p3 - 1 - zs) % R;
+                        const T xc = X[q3];
+                        r = B[q3] - xc;
+                        r -= W0[q3] * (xc - t.x[s3][ly][lx - 1]);
+                        r -= t.w0[s3][ly][lx + 1] * (xc - t.x[s3][ly][lx + 1]);
+                        r -= W1[q3] * (xc - t.x[s3][ly - 1][lx]);
+                        r -= t.w1[s3][ly + 1][lx] * (xc - t.x[s3][ly + 1][lx]);
+                        r -= W2[q3] * (xc - t.x[s4][ly][lx]);
+                        r -= W2[q2] * (xc - X[q2]);
                     }
-                    if ((p3 - z0) & 1) {
-                        // the coarse level's sweeps start from zero (per-colour kernels read it)
-                        const long cidx = cI + (long)cnx * (cJ + (long)cny * (p3 >> 1));
-                        cb[cidx] = racc * T(0.125);
-                        cx[cidx] = T(0);
+                    t.res[M::RESTR ? ly : 0][lx] = r;
+                    __syncthreads();
+                    if (rown) {
+                        const int ax = H + 2 * rci, ay = H + 2 * rcj;
+                        if (((p3 - z0) & 1) == 0) racc = T(0);
+                        racc += t.res[ay][ax];
+                        racc += t.res[ay][ax + 1];
+                        racc += t.res[ay + 1][ax];
+                        racc += t.res[ay + 1][ax + 1];
+                        if ((p3 - z0) & 1) {
+                            // the coarse level's sweeps start from zero (per-colour kernels read it)
+                            const long cidx = (gx0 + H) / 2 + rci + (long)cn0 * ((gy0 + H) / 2 + rcj +
+                                                                              (long)cn1 * (p3 >> 1));
+                            cb[cidx] = racc * T(0.125);
+                            cx[cidx] = T(0);
+                        }
                     }
                 }
             }
-            __syncthreads();                                      // ring slots are rewritten next step
         };
-        Regs ra, rb;
-        load_plane(ra, zs);
-        load_plane(rb, zs + 1);
-        for (int zt = zs; zt < ze; zt += 2) {
-            step(zt, ra);
-            step(zt + 1, rb);
+        load(std::integral_constant<int, 0>{}, zs);
+        load(std::integral_constant<int, 1>{}, zs + 1);
+        for (int zb = zs; zb < ze; zb += NB) {
+            step(std::integral_constant<int, 0>{}, zb);
+            if (zb + 1 < ze) step(std::integral_constant<int, 1>{}, zb + 1);
+            if (zb + 2 < ze) step(std::integral_constant<int, 2>{}, zb + 2);
+            if (zb + 3 < ze) step(std::integral_constant<int, 3>{}, zb + 3);
+            if (zb + 4 < ze) step(std::integral_constant<int, 4>{}, zb + 4);
+            if (zb + 5 < ze) step(std::integral_constant<int, 5>{}, zb + 5);
         }
+        __syncthreads();                                       // the slots are reused by the next tile
     }
 }
 
@@ -2502,9 +2499,9 @@ void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
     const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_SWEEP3(M)                                                                                   \
     do {                                                                                               \
-        if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(kBlock), 0, s, L, S, jl, c0,  \
+        if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(kR3Threads), 0, s, L, S, jl, c0, \
                                      from_xs, fz);                                                     \
-        else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(kBlock), 0, s, L, S, jl, c0,      \
+        else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(kR3Threads), 0, s, L, S, jl, c0,  \
                                 from_xs, fz);                                                          \
     } while (0)
     switch (mode) {

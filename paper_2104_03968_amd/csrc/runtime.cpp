@@ -128,17 +128,15 @@ inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
 // Fused-tile prefixes of the down / up lists (2D) and the sweep lists (3D) for the
 // plan's launch shape.
 void finish_fused(const Plan& p, DimLists& D) {
-    const int word = p.mixed ? 4 : 8;
     for (size_t dpt = 0; dpt < D.sw3.size(); ++dpt) {
         HostList& a = D.sw3[dpt];
         HostList& r = D.sr3[dpt];
         a.prefix.assign(1, 0);
         r.prefix.assign(1, 0);
         for (int32_t li : a.levels)
-            a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, sweep3_fy(word), p.tile_depth));
+            a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, false, p.tile_depth));
         for (int32_t li : r.levels)
-            r.prefix.push_back(r.prefix.back() +
-                               sweep3_tiles(p.levels[li].n, sweep3_fy_restrict(word), p.tile_depth));
+            r.prefix.push_back(r.prefix.back() + sweep3_tiles(p.levels[li].n, true, p.tile_depth));
     }
     // a fused sweep marches through its planes in sequence, so a level needs many blocks
     // to fill the chip: by default only the leading depths with at least one block per

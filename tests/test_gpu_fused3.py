@@ -90,7 +90,7 @@ def test_fused_sweeps_any_depth_and_sweep_count(nu, depth, precision):
 def test_fp64_fused_finest_level_default_rule(depth):
     """A grid wide enough for the default rule to fuse its finest level in FP64 (at
     least 256 sweep blocks at depth 16) at every plane depth, against the oracle."""
-    g = W.random_grid((128, 128, 96), 93400, dt=2e-3)
+    g = W.random_grid((96, 192, 192), 93400, dt=2e-3)
     for lv in (0, 1):
         kw = {} if lv == 0 else {"fused3_levels": 1}
         plan = fld.Plan([g.E.shape], h=[g.h], tile_depth=depth, **kw)
