@@ -63,19 +63,28 @@ __host__ __device__ constexpr size_t fused_lds(int word, int halo, int wide, int
 }
 constexpr size_t kFusedLdsMax = 160 * 1024;
 
-// Fused 3D sweep blocks: a window of kR3PX x kR3PY xy positions, one per thread,
-// holding FX x FY interior columns and a halo of 2 positions (4 where the sweep also
-// restricts, which keeps the interior on even coordinates), marched over fz planes
-// (fz even, tunable).
-constexpr int kR3PX = 64;
-constexpr int kR3PY = 16;
-constexpr int kR3Threads = kR3PX * kR3PY;
-__host__ __device__ constexpr int sweep3_halo(bool restr) { return restr ? 4 : 2; }
-__host__ __device__ constexpr int sweep3_fx(bool restr) { return kR3PX - 2 * sweep3_halo(restr); }
-__host__ __device__ constexpr int sweep3_fy(bool restr) { return kR3PY - 2 * sweep3_halo(restr); }
+// Fused 3D sweep blocks: a window of px x py xy positions, one per thread, holding
+// 64 x FY interior columns and a halo of 2 positions (3 where the sweep also
+// restricts), marched over fz planes (fz even, tunable).  The interior is 64 cells
+// wide, so a 2^k-wide level splits into whole tiles; FY = 11 (8 restricting).
+__host__ __device__ constexpr int sweep3_halo(bool restr) { return restr ? 3 : 2; }
+__host__ __device__ constexpr int sweep3_fx(bool) { return 64; }
+__host__ __device__ constexpr int sweep3_fy(bool restr) { return restr ? 8 : 11; }
+__host__ __device__ constexpr int sweep3_px(bool restr) { return sweep3_fx(restr) + 2 * sweep3_halo(restr); }
+__host__ __device__ constexpr int sweep3_py(bool restr) { return sweep3_fy(restr) + 2 * sweep3_halo(restr); }
+__host__ __device__ constexpr int sweep3_threads(bool restr) { return sweep3_px(restr) * sweep3_py(restr); }
+static_assert(sweep3_threads(false) <= 1024 && sweep3_threads(true) <= 1024, "one workgroup per window");
 __host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], bool restr, int fz) {
     const int fx = sweep3_fx(restr), fy = sweep3_fy(restr);
     return ((n[0] + fx - 1) / fx) * ((n[1] + fy - 1) / fy) * ((n[2] + fz - 1) / fz);
+}
+
+// z-march CG direction update (3D level 0): a window of kPqPX x kPqPY positions, 64 x 13
+// interior columns with one halo position around them, fz planes per block.
+constexpr int kPqPX = 66;
+constexpr int kPqPY = 15;
+__host__ __device__ inline int32_t pq3_tiles(const int32_t n[3], int fz) {
+    return ((n[0] + kPqPX - 3) / (kPqPX - 2)) * ((n[1] + kPqPY - 3) / (kPqPY - 2)) * ((n[2] + fz - 1) / fz);
 }
 
 struct LevelDesc {
@@ -297,8 +306,13 @@ void launch_cg_rz(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
                   int max_cycles, int nblk, hipStream_t s);
 void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
                   int max_cycles, int nblk, hipStream_t s);
+// zero_z: also clear the level-0 V-cycle iterate (needed where the V-cycle's first
+// sweep of level 0 reads it: the per-colour kernels).
 void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol,
-                  int max_cycles, int nblk, hipStream_t s);
+                  int max_cycles, int zero_z, int nblk, hipStream_t s);
+// The same on the z-march tiles of a pq3 list (3D grids without Dirichlet or periodic faces):
+// each tile stores its partial of p . q; a launch_finalize over the same list finishes.
+void launch_cg_pq3(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fz, int nblk, hipStream_t s);
 // X += the level-0 V-cycle iterate (FP32 when mixed, else FP64).
 void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);

@@ -47,6 +47,7 @@ struct DimLists {
     std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
     bool fused = false;
     std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
+    std::vector<int> fz_r;                     // per depth, planes per block of the restricting sweep
     bool fused3 = false;                       // fused 3D sweeps available (lists and xs laid out)
     int levels3 = 0;                           // leading depths that run fused sweeps
     HostList coarsest;                         // coarsest level of grids without a tail
@@ -56,6 +57,8 @@ struct DimLists {
     std::vector<HostList> tail_from, coarsest_from;
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
     bool fin_fused = false;                    // finish reductions in the last block (small grids)
+    HostList pq3;                              // level 0, z-march CG tiles (3D, zero-flux operators)
+    int fz_pq = 16;                            // planes per z-march CG tile
     int maxdepth = 0;
 };
 
@@ -124,6 +127,7 @@ struct Plan {
     int tile_rows_u = 16;                      // fused 2D tile rows of the finest level's up pass
     int nblk = 2048;
     int tile_depth = 32;                       // fused 3D sweep: planes per block
+    int ncu = 256;                             // compute units of the plan's device (block balancing)
     int sweep3 = 1;                            // 1: fused 3D sweeps where available; 0: per colour
     int sweep3_levels = 0;                     // leading 3D depths with fused sweeps (0: by block count)
     int tune_source = 0;                       // 0 defaults / options, 1 timed at bind, 2 cache

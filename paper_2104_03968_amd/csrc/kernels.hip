@@ -291,7 +291,8 @@ k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
     const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
     if (!run) return;                                // uniform per block
     double s2, s1;
-    sum_parts(d.part, g.ntiles0, mode == FIN_B ? 2 : 1, s2, s1, sh);
+    // the tiles of the list's reducing kernel (level-0 cell tiles, or the z-march tiles)
+    sum_parts(d.part, jl.prefix[blockIdx.x + 1] - jl.prefix[blockIdx.x], mode == FIN_B ? 2 : 1, s2, s1, sh);
     if (threadIdx.x == 0) finalize_grid(g, s2, s1, mode, rtol, max_cycles);
 }
 
@@ -1395,7 +1396,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
 // ---------------------------------------------------------------------------
 // Fused 3D sweeps.  One launch runs one whole red-black sweep (colour c0, then
 // 1-c0) over blocks of FX x FY interior columns and fz planes.  A block of
-// kR3PX x kR3PY threads owns a window of as many xy positions (the interior plus a
+// PX x PY threads owns a window of as many xy positions (the interior plus a
 // halo of H positions), one position per thread, and marches along z.  Each thread
 // keeps its own position's iterate and operator (b and the three lower faces) for
 // the planes in flight in registers; only the iterate and the x / y lower faces go
@@ -1410,7 +1411,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
 //      that updates in D is the one that updated in C (the colour flips with z)
 //   plane zt - 2 is final on the interior and is written out.
 // The halo recomputes exactly what the neighbouring blocks compute.  Restricting
-// sweeps (H = 4, HC = 2) also store D's results to the slot and form the residual of
+// sweeps (H = 3, HC = 2) also store D's results to the slot and form the residual of
 // the final iterate on plane zt - 3 into an LDS plane; after a second barrier one
 // thread per coarse cell adds its eight children, two planes in turn, and writes the
 // coarse right-hand side (and a zero coarse iterate).  Modes:
@@ -1435,29 +1436,34 @@ struct Sweep3Mode {
     static constexpr int HC = RESTR ? 2 : 1;         // rings of the first colour around the interior
     static constexpr int HX = HC + 1;                // rings whose iterate is read
     static constexpr int FX = sweep3_fx(RESTR), FY = sweep3_fy(RESTR);
+    static constexpr int PX = sweep3_px(RESTR), PY = sweep3_py(RESTR);
     static constexpr int R = RESTR ? 6 : 4;          // LDS plane slots
 };
 
-template <typename T, int R, bool RESTR>
+template <typename T, int R, int PX, int PY, bool RESTR>
 struct Sweep3Lds {
-    T x[R][kR3PY][kR3PX];
-    T w0[R][kR3PY][kR3PX];
-    T w1[R][kR3PY][kR3PX];
-    T res[RESTR ? kR3PY : 1][kR3PX];
+    T x[R][PY][PX];
+    T w0[R][PY][PX];
+    T w1[R][PY][PX];
+    T res[RESTR ? PY : 1][PX];
 };
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kR3Threads)
+__global__ void __launch_bounds__(1024)
 k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int c0, int from_xs,
          int fz) {
     using M = Sweep3Mode<MODE>;
     constexpr int H = M::H, HC = M::HC, HX = M::HX, FX = M::FX, FY = M::FY, R = M::R;
-    constexpr int NB = 6;                             // register ring of planes (zt - 3 .. zt + 2)
-    __shared__ Sweep3Lds<T, R, M::RESTR> t;
-    const int lx = threadIdx.x % kR3PX, ly = threadIdx.x / kR3PX;
+    constexpr int PX = M::PX, PY = M::PY;
+    // planes are loaded PF steps ahead; the registers hold planes zt - 3 .. zt + PF
+    // (three steps ahead measured no faster than two)
+    constexpr int PF = 2, NB = PF + 4;
+    static_assert(HX == H, "every window position is read by a neighbour");
+    __shared__ Sweep3Lds<T, R, PX, PY, M::RESTR> t;
+    const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
     // rings outside the interior: o >= H is interior; o >= H - HC takes the first colour,
-    // o >= H - HC + 1 the second, o >= H - HX has its iterate read by a neighbour
-    const int o = min(min(lx, kR3PX - 1 - lx), min(ly, kR3PY - 1 - ly));
+    // o >= H - HC + 1 the second
+    const int o = min(min(lx, PX - 1 - lx), min(ly, PY - 1 - ly));
     const bool in_c = o >= H - HC, in_d = o >= H - HC + 1, in_r = o >= H;
     const XcdOrder order(jl.total);
     for (int k = order.first(); order.more(k); k += order.per) {
@@ -1530,7 +1536,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 t.w0[s0][ly][lx] = W0[q];
                 t.w1[s0][ly][lx] = W1[q];
             }
-            if (zt + 2 < ze) load(std::integral_constant<int, (q + 2) % NB>{}, zt + 2);
+            if (zt + PF < ze) load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
             __syncthreads();
             // C: colour c0 on plane zt - 1
             const int p1 = zt - 1;
@@ -1613,6 +1619,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 }
             }
         };
+        static_assert(PF == 2 && NB == 6, "the prologue and the unrolled march below assume these");
         load(std::integral_constant<int, 0>{}, zs);
         load(std::integral_constant<int, 1>{}, zs + 1);
         for (int zb = zs; zb < ze; zb += NB) {
@@ -2128,10 +2135,116 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
     }
 }
 
+// The same direction update and product on 3D grids without Dirichlet or periodic
+// faces as a z-march: a block owns a window of kPqPX x kPqPY xy positions (64 x 13
+// interior columns and one halo position around them, one position per thread) and
+// walks fz planes, forming p = z + beta p_old once per cell of the window; the in-plane
+// neighbours' p and the x / y faces come from an LDS ring of three plane slots, the
+// z-neighbours from the thread's own registers, so every plane of z, p_old and the
+// faces is read once.  q follows k_cg_pq's operand order.  One partial of p . q per
+// block tile, summed over the tile's cells in a fixed order (each thread's planes in
+// turn, then a fixed-order block sum); a separate finalize sums the tile partials.
+template <bool MIXED>
+__global__ void __launch_bounds__(1024)
+k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fz) {
+    constexpr int PX = kPqPX, PY = kPqPY, FX = PX - 2, FY = PY - 2, R = 3, NB = 5;
+    __shared__ double sp[R][PY][PX];
+    __shared__ double sw0[R][PY][PX];
+    __shared__ double sw1[R][PY][PX];
+    __shared__ double sh[2 * 1024 / 64];
+    const bool pos = threadIdx.x < PX * PY;                 // threads past the window only reduce
+    const int lx = pos ? threadIdx.x % PX : 1, ly = pos ? threadIdx.x / PX : 1;
+    const bool inner = pos && lx >= 1 && lx < PX - 1 && ly >= 1 && ly < PY - 1;
+    const XcdOrder order(jl.total);
+    for (int k = order.first(); order.more(k); k += order.per) {
+        const int tt = order.tile(k);
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[jl.levels[jb]];
+        GridState& g = S[d.grid];
+        if (!g.active) continue;
+        const int lt = tt - jl.prefix[jb];
+        const bool restart = g.iter == 0;                  // p = z (the old direction is not read)
+        const double beta = g.beta;
+        const int par = g.iter & 1;
+        const gptr<double> Pn = as_global(d.P[par]);
+        const gptr<double> Po = as_global(d.P[par ^ 1]);
+        const gptr<double> Qg = as_global(d.Q);
+        const ZArr<MIXED> zv(d);
+        const gptr<double> w0g = as_global(d.w[0]), w1g = as_global(d.w[1]), w2g = as_global(d.w[2]);
+        const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+        const int tx_n = (n0 + FX - 1) / FX, ty_n = (n1 + FY - 1) / FY;
+        const int tx = lt % tx_n, rest = lt / tx_n;
+        const int gx = tx * FX - 1 + lx, gy = (rest % ty_n) * FY - 1 + ly;
+        const int z0 = (rest / ty_n) * fz, z1 = min(z0 + fz, n2);
+        const int zs = z0 - 1, ze = z1 + 1;
+        const bool in_xy = pos && gx >= 0 && gx < n0 && gy >= 0 && gy < n1;
+        const long sz = (long)n0 * n1;
+        const long cxy = min(max(gx, 0), n0 - 1) + (long)min(max(gy, 0), n1 - 1) * n0;
+        double Z[NB], PO[NB], W0[NB], W1[NB], W2[NB], PV[NB];
+        auto load = [&](auto Sl, int gk) {
+            constexpr int q = decltype(Sl)::value;
+            const long idx = cxy + min(max(gk, 0), n2 - 1) * sz;
+            Z[q] = zv[idx];
+            if (!restart) PO[q] = Po[idx];
+            W0[q] = w0g[idx];
+            W1[q] = w1g[idx];
+            W2[q] = w2g[idx];
+        };
+        double acc = 0.0;
+        auto step = [&](auto Sc, int zt) {
+            constexpr int q = decltype(Sc)::value, q1 = (q + NB - 1) % NB, q2 = (q + NB - 2) % NB;
+            const int s0 = (zt - zs) % R;
+            {
+                const bool in = in_xy && zt >= 0 && zt < n2;
+                const double pnew = restart ? Z[q] : Z[q] + beta * PO[q];
+                PV[q] = in ? pnew : 0.0;
+                W0[q] = in ? W0[q] : 0.0;
+                W1[q] = in ? W1[q] : 0.0;
+                W2[q] = in ? W2[q] : 0.0;
+                if (pos) {
+                    sp[s0][ly][lx] = PV[q];
+                    sw0[s0][ly][lx] = W0[q];
+                    sw1[s0][ly][lx] = W1[q];
+                }
+            }
+            if (zt + 2 < ze) load(std::integral_constant<int, (q + 2) % NB>{}, zt + 2);
+            __syncthreads();
+            const int p1 = zt - 1;
+            if (p1 >= z0 && p1 < z1 && inner && in_xy) {
+                const int s1 = (p1 - zs) % R;
+                const double pc = PV[q1];
+                double qv = pc;
+                qv += W0[q1] * (pc - sp[s1][ly][lx - 1]);
+                qv += sw0[s1][ly][lx + 1] * (pc - sp[s1][ly][lx + 1]);
+                qv += W1[q1] * (pc - sp[s1][ly - 1][lx]);
+                qv += sw1[s1][ly + 1][lx] * (pc - sp[s1][ly + 1][lx]);
+                qv += W2[q1] * (pc - PV[q2]);
+                qv += W2[q] * (pc - PV[q]);
+                const long idx = cxy + p1 * sz;
+                Pn[idx] = pc;
+                Qg[idx] = qv;
+                acc += pc * qv;
+            }
+        };
+        load(std::integral_constant<int, 0>{}, zs);
+        load(std::integral_constant<int, 1>{}, zs + 1);
+        for (int zb = zs; zb < ze; zb += NB) {
+            step(std::integral_constant<int, 0>{}, zb);
+            if (zb + 1 < ze) step(std::integral_constant<int, 1>{}, zb + 1);
+            if (zb + 2 < ze) step(std::integral_constant<int, 2>{}, zb + 2);
+            if (zb + 3 < ze) step(std::integral_constant<int, 3>{}, zb + 3);
+            if (zb + 4 < ze) step(std::integral_constant<int, 4>{}, zb + 4);
+        }
+        double unused = 0.0;
+        block_sum2<1024>(acc, unused, sh);                 // its barriers also free the slots
+        if (threadIdx.x == 0) d.part[lt] = acc;
+    }
+}
+
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fin, double rtol,
-        int max_cycles) {
+        int max_cycles, int zero_z) {
     __shared__ double sh[2 * kBlock / 64];
     __shared__ int flag;
     const XcdOrder order(jl.total);
@@ -2168,8 +2281,8 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
             r2 += r * r;
             if (MIXED) {
                 as_global(d.b32)[idx] = (float)r;
-                as_global(d.x32)[idx] = 0.0f;
-            } else {
+                if (zero_z) as_global(d.x32)[idx] = 0.0f;
+            } else if (zero_z) {
                 as_global(d.x)[idx] = 0.0;
             }
         }
@@ -2499,10 +2612,10 @@ void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
     const int g = blocks_for_xcd(jl.total, nblk);
 #define FLD_SWEEP3(M)                                                                                   \
     do {                                                                                               \
-        if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(kR3Threads), 0, s, L, S, jl, c0, \
-                                     from_xs, fz);                                                     \
-        else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(kR3Threads), 0, s, L, S, jl, c0,  \
-                                from_xs, fz);                                                          \
+        if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(Sweep3Mode<M>::PX * Sweep3Mode<M>::PY), \
+                                     0, s, L, S, jl, c0, from_xs, fz);                                 \
+        else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(Sweep3Mode<M>::PX * Sweep3Mode<M>::PY), \
+                                0, s, L, S, jl, c0, from_xs, fz);                                      \
     } while (0)
     switch (mode) {
         case SW_LOAD: FLD_SWEEP3(SW_LOAD); break;
@@ -2659,10 +2772,26 @@ void launch_cg_pq(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList
     FLD_CG_LAUNCH(k_cg_pq, (mixed ? 4.0 : 8.0) + 8.0 + 8.0 * dim + 16.0);
 }
 
-void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles, int nblk,
-                      hipStream_t s) {
-    // X, p, R, q read; X, R written; the next V-cycle's right-hand side / iterate written
-    FLD_CG_LAUNCH(k_cg_update, 32.0 + 16.0 + 8.0);
+void launch_cg_pq3(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fz, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    // z, the old direction and the three face arrays read once; p and q written
+    if (acct_add(jl.cells * ((mixed ? 4.0 : 8.0) + 8.0 + 24.0 + 16.0))) return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+    if (mixed) hipLaunchKernelGGL((k_cg_pq3<true>), dim3(g), dim3(1024), 0, s, L, S, jl, fz);
+    else hipLaunchKernelGGL((k_cg_pq3<false>), dim3(g), dim3(1024), 0, s, L, S, jl, fz);
+}
+
+void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles,
+                      int zero_z, int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    // X, p, R, q read; X, R written; the next V-cycle's FP32 right-hand side and its
+    // zeroed iterate written where they are separate arrays / read
+    if (acct_add(jl.cells * (32.0 + 16.0 + (mixed ? 4.0 : 0.0) + (zero_z ? (mixed ? 4.0 : 8.0) : 0.0)))) return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+    FLD_DISPATCH_DIM(dim, {
+        if (mixed) hipLaunchKernelGGL((k_cg_update<D, true>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles, zero_z);
+        else hipLaunchKernelGGL((k_cg_update<D, false>), dim3(g), dim3(kBlock), 0, s, L, S, jl, fin, rtol, max_cycles, zero_z);
+    });
 }
 
 void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,

@@ -128,6 +128,7 @@ inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
 // Fused-tile prefixes of the down / up lists (2D) and the sweep lists (3D) for the
 // plan's launch shape.
 void finish_fused(const Plan& p, DimLists& D) {
+    D.fz_r.assign(D.sw3.size(), p.tile_depth);
     for (size_t dpt = 0; dpt < D.sw3.size(); ++dpt) {
         HostList& a = D.sw3[dpt];
         HostList& r = D.sr3[dpt];
@@ -135,8 +136,17 @@ void finish_fused(const Plan& p, DimLists& D) {
         r.prefix.assign(1, 0);
         for (int32_t li : a.levels)
             a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, false, p.tile_depth));
+        // the restricting sweep's narrower window makes more blocks: march twice as deep
+        // when that needs fewer block steps per compute unit (blocks run in rounds of one
+        // per compute unit, each round as long as a block's fz + 6 steps)
+        auto rounds = [&](int fz) {
+            int64_t tiles = 0;
+            for (int32_t li : r.levels) tiles += sweep3_tiles(p.levels[li].n, true, fz);
+            return ((tiles + p.ncu - 1) / p.ncu) * (fz + 6);
+        };
+        if (2 * p.tile_depth <= 64 && rounds(2 * p.tile_depth) < rounds(p.tile_depth)) D.fz_r[dpt] = 2 * p.tile_depth;
         for (int32_t li : r.levels)
-            r.prefix.push_back(r.prefix.back() + sweep3_tiles(p.levels[li].n, true, p.tile_depth));
+            r.prefix.push_back(r.prefix.back() + sweep3_tiles(p.levels[li].n, true, D.fz_r[dpt]));
     }
     // a fused sweep marches through its planes in sequence, so a level needs many blocks
     // to fill the chip: by default only the leading depths with at least one block per
@@ -295,6 +305,22 @@ static void build_lists(Plan& p) {
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
             max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
         D.fin_fused = max_tiles <= 32;
+        // 3D grids with zero-flux operators (no Dirichlet couplings, no wrapped neighbours)
+        // run the CG direction update as a z-march; its plane depth balances the blocks
+        // over the compute units (rounds of one block per unit, fz + 2 steps each)
+        D.pq3.prefix.assign(1, 0);
+        if (D.dim == 3 && !p.has_dir && !p.has_per && !D.fin_fused && !D.l0_cell.empty()) {
+            int64_t best = -1;
+            for (int fz : {8, 16, 32, 64}) {
+                int64_t tiles = 0;
+                for (int32_t li : D.l0_cell.levels) tiles += pq3_tiles(p.levels[li].n, fz);
+                const int64_t cost = ((tiles + p.ncu - 1) / p.ncu) * (fz + 2);
+                if (best < 0 || cost < best) { best = cost; D.fz_pq = fz; }
+            }
+            D.pq3.levels = D.l0_cell.levels;
+            D.pq3.prefix.assign(1, 0);
+            for (int32_t li : D.pq3.levels) D.pq3.prefix.push_back(D.pq3.prefix.back() + pq3_tiles(p.levels[li].n, D.fz_pq));
+        }
         // the fused level kernels know no Dirichlet couplings or wrapped neighbours: such plans
         // sweep per colour
         D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && !p.has_per && fused2_supported(p.opts.nu1) &&
@@ -377,6 +403,14 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.tile_rows_u = opts.tile_rows_up ? opts.tile_rows_up : p.tile_rows;
     p.nblk = opts.max_blocks ? opts.max_blocks : 2048;
     p.tile_depth = opts.tile_depth ? opts.tile_depth : 32;
+    {   // compute units of the current device (the plan's), for balancing block counts
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p.ncu = cus;
+        else
+            (void)hipGetLastError();
+    }
     p.sweep3_levels = opts.fused3_levels;
     if (opts.fused && fused2_supported(opts.nu1) && fused2_supported(opts.nu2) && fused2_supported(p.nuc1) &&
         fused2_supported(p.nuc2) &&
@@ -409,6 +443,7 @@ static void layout(Plan& p) {
     };
     for (auto& D : p.dl) {
         place_list(D.l0_cell);
+        place_list(D.pq3);
         place_list(D.coarsest);
         place_list(D.tail);
         for (auto& l : D.coarsen) place_list(l);
@@ -515,8 +550,8 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
                 const bool load = k > 1 || (d == d0 && load0);
                 const bool restr = k == nu1;
                 const int mode = restr ? (load ? 2 : 3) : (load ? 0 : 1);
-                launch_sweep3(f32, p.dL, p.dS, restr ? D.sr3[d].dev : D.sw3[d].dev, mode, 0, k % 2 == 0, fz,
-                              p.nblk, s);
+                launch_sweep3(f32, p.dL, p.dS, restr ? D.sr3[d].dev : D.sw3[d].dev, mode, 0, k % 2 == 0,
+                              restr ? D.fz_r[d] : fz, p.nblk, s);
             }
             continue;
         }
@@ -552,6 +587,13 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             launch_smooth(dim, f32, p.dL, p.dS, D.smooth[d].dev, 0, p.nblk, s);
         }
     }
+}
+
+// Whether the first smoothing kernel of level 0 in a V-cycle reads the iterate (the
+// per-colour kernels do; fused sweeps from zero and the fused 2D down pass do not).
+static bool level0_reads_iterate(const Plan& p, const DimLists& D) {
+    if (D.dim == 3) return !(D.fused3 && p.sweep3 && D.levels3 >= 1);
+    return !D.fused;
 }
 
 static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
@@ -613,9 +655,15 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             const bool ff = D.fin_fused;
             launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
-            launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, cell_blocks(p), s);
-            if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
-            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, cell_blocks(p), s);
+            if (!D.pq3.empty()) {
+                launch_cg_pq3(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, cell_blocks(p), s);
+                launch_finalize(p.dL, p.dS, D.pq3.dev, FIN_PQ, rt, mc, s);
+            } else {
+                launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, cell_blocks(p), s);
+                if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
+            }
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, level0_reads_iterate(p, D) ? 1 : 0,
+                             cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_CG, rt, mc, s);
         } else {
             if (p.mixed) launch_correct(dim, true, p.dL, p.dS, l0, cell_blocks(p), s);
@@ -750,6 +798,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     for (auto& D : p.dl) {
         int rc;
         if ((rc = upload(D.l0_cell)) != FLD_OK) return rc;
+        if ((rc = upload(D.pq3)) != FLD_OK) return rc;
         if ((rc = upload(D.coarsest)) != FLD_OK) return rc;
         if ((rc = upload(D.tail)) != FLD_OK) return rc;
         for (auto& l : D.coarsen) if ((rc = upload(l)) != FLD_OK) return rc;
