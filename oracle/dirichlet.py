@@ -20,9 +20,24 @@ Periodic axes (both faces "periodic") wrap: the ghosts are the cells at the othe
 end, and the face between the last and the first cell is an interior face like any
 other (harmonic mean of the two D, stored in the first cell's lower-face slot).
 
+Continuous faces (Sec. 3.4 lists a linear extrapolation of E^{n+1} into the ghost
+cells as the third kind of boundary).  Readings:
+
+* the ghosts continue the line through the two cells next to the face:
+  E_{-k} = E_0 + k (E_0 - E_1) below, E_{n-1+k} = E_{n-1} + k (E_{n-1} - E_{n-2})
+  above (k = 1, 2); the 4th-order gradient of R uses them, which keeps it exact for
+  linear profiles;
+* in eq. discdiff the ghost of the implicit solve is the same extrapolation of the
+  unknown E^{n+1}, coupled to the boundary cell through the boundary face.  The paper
+  gives no opacity for the ghost, so the boundary face takes the flux coefficient of
+  the first interior face (the coefficient, like E, is continued across the face): the
+  boundary cell's row gains w_B (x_0 - x_ghost) = w_B (x_1 - x_0) with w_B the weight
+  of the face between cells 0 and 1.  A stays an M-matrix (that row loses its coupling
+  along the axis) but is no longer symmetric, and energy crosses the face.
+
 Faces are listed x-, x+, y-, y+, z-, z+.  ``kind`` per face is "zero_flux",
-"gradient" (the fixed-gradient faces of ``oracle.bc``), "dirichlet" or "periodic";
-``value`` per face is the prescribed gradient or ghost value.
+"gradient" (the fixed-gradient faces of ``oracle.bc``), "dirichlet", "periodic" or
+"continuous"; ``value`` per face is the prescribed gradient or ghost value.
 """
 from __future__ import annotations
 
@@ -34,9 +49,9 @@ import scipy.sparse as sp
 from . import fld as _fld
 
 __all__ = ["pad_general", "gradient4_general", "dirichlet_diagonal", "boundary_rhs",
-           "face_weights_general", "assemble_general", "diffusion_step_general"]
+           "face_weights_general", "assemble_general", "continuous_coupling", "diffusion_step_general"]
 
-KINDS = ("zero_flux", "gradient", "dirichlet", "periodic")
+KINDS = ("zero_flux", "gradient", "dirichlet", "periodic", "continuous")
 
 
 def _faces(kind, value, nd):
@@ -66,6 +81,10 @@ def pad_general(E: np.ndarray, d: int, h: float, kind_lo: str, val_lo: float, ki
     def ghosts(edge0, edge1, kind, val, sign):
         if kind == "dirichlet":
             return [np.full_like(edge0, val), np.full_like(edge0, val)]
+        if kind == "continuous":
+            # the line through the boundary cell and its inner neighbour, one and two
+            # cell widths beyond the face
+            return [edge0 + (edge0 - edge1), edge0 + 2.0 * (edge0 - edge1)]
         g = val if kind == "gradient" else 0.0
         # [inner ghost, outer ghost]: E_{-1} = E_0 -/+ h G, E_{-2} = E_1 -/+ 3 h G
         return [edge0 + sign * h * g, edge1 + sign * 3.0 * h * g]
@@ -172,11 +191,48 @@ def assemble_general(w: Sequence[np.ndarray], kind=None) -> sp.csr_matrix:
     return A.tocsr()
 
 
+def continuous_coupling(w: Sequence[np.ndarray], kind=None) -> sp.csr_matrix:
+    """What the continuous faces add to A: for a boundary cell c with inner neighbour c1,
+    the ghost x_g = 2 x_c - x_c1 couples through the boundary face with the weight w_B of
+    the face between c and c1, so row c gains w_B (x_c - x_g) = w_B (x_c1 - x_c)."""
+    shape = w[0].shape
+    nd = len(shape)
+    k, _ = _faces(kind, None, nd)
+    N = int(np.prod(shape))
+    idx = np.arange(N).reshape(shape)
+    rows, cols, vals = [], [], []
+    for d in range(nd):
+        a = _fld._axis(nd, d)
+        n = shape[a]
+        if n < 2:
+            continue
+        for side in (0, 1):
+            if k[2 * d + side] != "continuous":
+                continue
+            sl_c = [slice(None)] * nd
+            sl_1 = [slice(None)] * nd
+            sl_w = [slice(None)] * nd
+            sl_c[a] = 0 if side == 0 else n - 1
+            sl_1[a] = 1 if side == 0 else n - 2
+            sl_w[a] = 1 if side == 0 else n - 1      # lower-face slot of the face between c and c1
+            c = idx[tuple(sl_c)].ravel()
+            c1 = idx[tuple(sl_1)].ravel()
+            wB = w[d][tuple(sl_w)].ravel()
+            rows += [c, c]
+            cols += [c, c1]
+            vals += [-wB, wB]
+    if not rows:
+        return sp.csr_matrix((N, N))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
 def diffusion_step_general(E: np.ndarray, kappa_rho: np.ndarray, dt: float, h: Sequence[float],
                            kind: Optional[Sequence] = None, value: Optional[Sequence] = None,
                            c: float = 1.0, limiter: str = "lp", method: str = "auto", tol=None):
-    """One backward-Euler FLD step (Sec. 3.4) with per-face zero-flux, fixed-gradient or
-    Dirichlet boundaries.  ``info.extra`` holds b and alpha."""
+    """One backward-Euler FLD step (Sec. 3.4) with per-face zero-flux, fixed-gradient,
+    Dirichlet, periodic or continuous boundaries.  ``info.extra`` holds b, alpha and A.
+    With continuous faces A is not symmetric: ``method="auto"`` then takes the sparse
+    direct solve (SuperLU) instead of CG."""
     E = np.asarray(E, dtype=np.float64)
     kr = np.asarray(kappa_rho, dtype=np.float64)
     gr = gradient4_general(E, h, kind, value)
@@ -184,8 +240,11 @@ def diffusion_step_general(E: np.ndarray, kappa_rho: np.ndarray, dt: float, h: S
     D = c * _fld.flux_limiter(R, limiter) / kr
     w = face_weights_general(D, dt, h, kind)
     alpha = dirichlet_diagonal(D, dt, h, kind)
-    A = (assemble_general(w, kind) + sp.diags(alpha.ravel())).tocsr()
+    A = (assemble_general(w, kind) + sp.diags(alpha.ravel()) + continuous_coupling(w, kind)).tocsr()
     b = E + boundary_rhs(D, dt, h, kind, value)
+    k, _ = _faces(kind, None, E.ndim)
+    if method == "auto" and "continuous" in k and E.size > 4096:
+        method = "direct"
     x, info = _fld.solve(A, b, method=method, tol=tol, w=w)
     info.extra["b"] = b
     info.extra["alpha"] = alpha
