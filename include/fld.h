@@ -90,6 +90,17 @@ extern "C" {
                                         (2k-1) h G above, for the 4th-order gradient;
                                         the face flux -D G, D the boundary cell's,
                                         enters the right-hand side                 */
+#define FLD_BC_CONTINUOUS       4    /* E^{n+1} extrapolated linearly into the ghosts
+                                        (Sec. 3.4, continuous conditions): E_{-k} =
+                                        E_0 + k (E_0 - E_1), likewise above, for the
+                                        4th-order gradient and for the implicit solve,
+                                        where the boundary face carries the flux
+                                        coefficient of the first interior face, so the
+                                        boundary cell's row loses its coupling along
+                                        that axis.  The operator is then not
+                                        symmetric: such plans need krylov = 0 (plain
+                                        V-cycles; INVALID_ARG otherwise) and sweep per
+                                        colour                                      */
 
 #define FLD_COARSE_REDISCRETISED 0   /* coarse faces: mean of the sub-face weights
                                         times 1/4 (the operator rebuilt at 2h)  */

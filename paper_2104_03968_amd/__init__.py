@@ -55,6 +55,7 @@ FLD_BC_ZERO_FLUX = 0
 FLD_BC_FIXED_GRADIENT = 1
 FLD_BC_DIRICHLET = 2
 FLD_BC_PERIODIC = 3
+FLD_BC_CONTINUOUS = 4
 FLD_PREC_FP64 = 0
 FLD_PREC_MIXED = 1
 FLD_COARSE_REDISCRETISED = 0

@@ -102,6 +102,7 @@ struct LevelDesc {
     double  bcg[6];
     double  bcgh[6];
     int32_t per_mask;    // every level: bit a set for periodic axes
+    int32_t cont_mask;   // every level: bit f set for the continuous faces (linear extrapolation)
     int32_t dir_mask;    // level 0: bit f set for the Dirichlet faces
     double  bcv[6];      // level 0: the ghost value E_B of each Dirichlet face
     double* ad;          // every level of a plan with Dirichlet faces: the extra diagonal of

@@ -76,6 +76,10 @@ struct Plan {
     bool krylov = true;
     bool has_dir = false;                      // some face is FLD_BC_DIRICHLET
     bool has_per = false;                      // some axis is periodic
+    bool has_cont = false;                     // some face is continuous (linear extrapolation)
+    // the operator differs from zero flux at some face (extra diagonal, wrapped or cut
+    // neighbours): per-colour kernels and the boundary instantiation of the tail
+    bool nb_bc() const { return has_dir || has_per || has_cont; }
     bool any_bc = false;                       // some face is not zero flux
     int nuc1 = 2, nuc2 = 2;                    // sweeps on the levels below the finest
 

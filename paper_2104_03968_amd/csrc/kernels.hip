@@ -66,6 +66,10 @@ struct XcdOrder {
     __device__ bool more(int k) const { return k < chunk && x * chunk + k < total; }
 };
 
+// The neighbour mask of a level's operator: periodic axes (bits 0-2) and continuous
+// faces (bits 3-8).
+__device__ __forceinline__ int nb_mask(const LevelDesc& d) { return d.per_mask | (d.cont_mask << 3); }
+
 __device__ __forceinline__ int mirror(int i, int n) {
     // even reflection across a zero-flux face: -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2
     return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
@@ -327,7 +331,9 @@ __device__ __forceinline__ void grad4_at(const double* __restrict__ E, int i, in
 // outside [0, n) is the mirror image plus the linear part of slope G, -(2k-1) h G
 // below (i = -k) and +(2k-1) h G above (i = n-1+k); gh = {h G_lo, h G_hi} per axis.
 // Dirichlet faces (bit of dir_mask) put their value E_B in both ghost layers;
-// periodic axes (bit of per_mask) take the cells at the other end.
+// periodic axes (bit of per_mask) take the cells at the other end; continuous faces
+// (bit of cont_mask) continue the line through the two cells next to the face,
+// E_{-k} = E_0 + k (E_0 - E_1) and E_{n-1+k} = E_{n-1} + k (E_{n-1} - E_{n-2}).
 __device__ __forceinline__ double ghost_lin(int i, int n, double ghlo, double ghhi) {
     return i < 0 ? (double)(2 * i + 1) * ghlo : (i >= n ? (double)(2 * (i - n) + 1) * ghhi : 0.0);
 }
@@ -340,8 +346,17 @@ __device__ __forceinline__ void grad4_bc_at(const double* __restrict__ E, int i,
     const int dm = bc.dir_mask;
     // ghost or interior value at index q of an axis of m cells whose faces are 2a, 2a+1
     const int pmask = bc.per_mask;
+    const int cm = bc.cont_mask;
     auto val = [&](long base, long stride, int q, int m, int a) {
         if ((pmask >> a) & 1) return E[base + (q < 0 ? q + m : (q >= m ? q - m : q)) * stride];
+        if (q < 0 && ((cm >> (2 * a)) & 1)) {
+            const double e0 = E[base], e1 = E[base + stride];
+            return e0 + (double)(-q) * (e0 - e1);
+        }
+        if (q >= m && ((cm >> (2 * a + 1)) & 1)) {
+            const double e0 = E[base + (long)(m - 1) * stride], e1 = E[base + (long)(m - 2) * stride];
+            return e0 + (double)(q - m + 1) * (e0 - e1);
+        }
         const double in = E[base + mirror(q, m) * stride] + ghost_lin(q, m, gh[2 * a], gh[2 * a + 1]);
         if (q < 0 && (dm >> (2 * a)) & 1) return bc.bcv[2 * a];
         if (q >= m && (dm >> (2 * a + 1)) & 1) return bc.bcv[2 * a + 1];
@@ -659,17 +674,24 @@ template <> struct Arr<float> {
 // the axis is periodic (the face between the last and the first cell sits in the
 // first cell's lower-face slot).  The face below a cell is its own slot, the face
 // above is the upper neighbour's.
+// bm holds the periodic axes (bit a) and the continuous faces (bit 3 + f, face f = 2a
+// below, 2a + 1 above): a continuous face takes the boundary cell's coupling to its
+// inner neighbour out of that cell's row (the linearly extrapolated ghost cancels it).
 template <typename T, typename P>
-__device__ __forceinline__ void nb_lo(P w, P x, long idx, int i, int n, long s, bool per, T& wn, T& xn) {
-    const bool has = i > 0 || per;
+__device__ __forceinline__ void nb_lo(P w, P x, long idx, int i, int n, long s, int bm, int a, T& wn, T& xn) {
+    const bool per = (bm >> a) & 1;
+    const bool cut = i == n - 1 && ((bm >> (4 + 2 * a)) & 1);
+    const bool has = (i > 0 || per) && !cut;
     const long nb = i > 0 ? idx - s : (per ? idx + (long)(n - 1) * s : idx);
     const T wv = w[idx];
     wn = has ? wv : T(0);
     xn = x[nb];
 }
 template <typename T, typename P>
-__device__ __forceinline__ void nb_hi(P w, P x, long idx, int i, int n, long s, bool per, T& wn, T& xn) {
-    const bool has = i + 1 < n || per;
+__device__ __forceinline__ void nb_hi(P w, P x, long idx, int i, int n, long s, int bm, int a, T& wn, T& xn) {
+    const bool per = (bm >> a) & 1;
+    const bool cut = i == 0 && ((bm >> (3 + 2 * a)) & 1);
+    const bool has = (i + 1 < n || per) && !cut;
     const long nb = i + 1 < n ? idx + s : (per ? idx - (long)(n - 1) * s : idx);
     const T wv = w[nb];
     wn = has ? wv : T(0);
@@ -684,18 +706,18 @@ __device__ __forceinline__ T residual_at(P x, P b, P w0, P w1, P w2, const int32
     const T xc = x[idx];
     T r = b[idx] - xc;
     T wl, xl, wr, xr, wd, xd, wu, xu;
-    nb_lo(w0, x, idx, i, n[0], 1, ((pm) >> 0) & 1, wl, xl);
-    nb_hi(w0, x, idx, i, n[0], 1, ((pm) >> 0) & 1, wr, xr);
-    nb_lo(w1, x, idx, j, n[1], sy, ((pm) >> 1) & 1, wd, xd);
-    nb_hi(w1, x, idx, j, n[1], sy, ((pm) >> 1) & 1, wu, xu);
+    nb_lo(w0, x, idx, i, n[0], 1, pm, 0, wl, xl);
+    nb_hi(w0, x, idx, i, n[0], 1, pm, 0, wr, xr);
+    nb_lo(w1, x, idx, j, n[1], sy, pm, 1, wd, xd);
+    nb_hi(w1, x, idx, j, n[1], sy, pm, 1, wu, xu);
     r -= wl * (xc - xl);
     r -= wr * (xc - xr);
     r -= wd * (xc - xd);
     r -= wu * (xc - xu);
     if (DIM == 3) {
         T wb, xb, wf, xf;
-        nb_lo(w2, x, idx, k, n[2], sz, ((pm) >> 2) & 1, wb, xb);
-        nb_hi(w2, x, idx, k, n[2], sz, ((pm) >> 2) & 1, wf, xf);
+        nb_lo(w2, x, idx, k, n[2], sz, pm, 2, wb, xb);
+        nb_hi(w2, x, idx, k, n[2], sz, pm, 2, wf, xf);
         r -= wb * (xc - xb);
         r -= wf * (xc - xf);
     }
@@ -729,13 +751,13 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const gptr<T> w1 = as_global(Arr<T>::w(d, 1));
         const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
         const long idx = i + j * sy + k * sz;
-        const int pm = d.per_mask;
+        const int pm = nb_mask(d);
         T s = b[idx], dg = T(1);
         T wl, xl, wr, xr, wd, xd, wu, xu;
-        nb_lo(w0, x, idx, i, d.n[0], 1, ((pm) >> 0) & 1, wl, xl);
-        nb_hi(w0, x, idx, i, d.n[0], 1, ((pm) >> 0) & 1, wr, xr);
-        nb_lo(w1, x, idx, j, d.n[1], sy, ((pm) >> 1) & 1, wd, xd);
-        nb_hi(w1, x, idx, j, d.n[1], sy, ((pm) >> 1) & 1, wu, xu);
+        nb_lo(w0, x, idx, i, d.n[0], 1, pm, 0, wl, xl);
+        nb_hi(w0, x, idx, i, d.n[0], 1, pm, 0, wr, xr);
+        nb_lo(w1, x, idx, j, d.n[1], sy, pm, 1, wd, xd);
+        nb_hi(w1, x, idx, j, d.n[1], sy, pm, 1, wu, xu);
         s += wl * xl; dg += wl;
         s += wr * xr; dg += wr;
         s += wd * xd; dg += wd;
@@ -743,8 +765,8 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         if (DIM == 3) {
             const gptr<T> w2 = as_global(Arr<T>::w(d, 2));
             T wb, xb, wf, xf;
-            nb_lo(w2, x, idx, k, d.n[2], sz, ((pm) >> 2) & 1, wb, xb);
-            nb_hi(w2, x, idx, k, d.n[2], sz, ((pm) >> 2) & 1, wf, xf);
+            nb_lo(w2, x, idx, k, d.n[2], sz, pm, 2, wb, xb);
+            nb_hi(w2, x, idx, k, d.n[2], sz, pm, 2, wf, xf);
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
@@ -778,7 +800,7 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
         for (int c = 0; c < (1 << DIM); ++c) {
             s += residual_at<DIM, T>(x, b, w0, w1, w2, f.n, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1),
                                      DIM == 3 ? 2 * K + (c >> 2) : 0, as_global(Arr<T>::ad(f)),
-                                     Arr<T>::ad(f) != nullptr, f.per_mask);
+                                     Arr<T>::ad(f) != nullptr, nb_mask(f));
         }
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
         as_global(Arr<T>::b(cL))[cidx] = s * T(DIM == 3 ? 0.125 : 0.25);
@@ -899,18 +921,18 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ p, const T* __restri
     T q = pc;
     dg = T(1);
     T wl, pl, wr, pr, wd, pd, wu, pu;
-    nb_lo(w0, p, c, i, n[0], 1, ((pm) >> 0) & 1, wl, pl);
-    nb_hi(w0, p, c, i, n[0], 1, ((pm) >> 0) & 1, wr, pr);
-    nb_lo(w1, p, c, j, n[1], sy, ((pm) >> 1) & 1, wd, pd);
-    nb_hi(w1, p, c, j, n[1], sy, ((pm) >> 1) & 1, wu, pu);
+    nb_lo(w0, p, c, i, n[0], 1, pm, 0, wl, pl);
+    nb_hi(w0, p, c, i, n[0], 1, pm, 0, wr, pr);
+    nb_lo(w1, p, c, j, n[1], sy, pm, 1, wd, pd);
+    nb_hi(w1, p, c, j, n[1], sy, pm, 1, wu, pu);
     q += wl * (pc - pl); dg += wl;
     q += wr * (pc - pr); dg += wr;
     q += wd * (pc - pd); dg += wd;
     q += wu * (pc - pu); dg += wu;
     if (DIM == 3) {
         T wb, pb, wf, pf;
-        nb_lo(w2, p, c, k, n[2], sz, ((pm) >> 2) & 1, wb, pb);
-        nb_hi(w2, p, c, k, n[2], sz, ((pm) >> 2) & 1, wf, pf);
+        nb_lo(w2, p, c, k, n[2], sz, pm, 2, wb, pb);
+        nb_hi(w2, p, c, k, n[2], sz, pm, 2, wf, pf);
         q += wb * (pc - pb); dg += wb;
         q += wf * (pc - pf); dg += wf;
     }
@@ -930,16 +952,78 @@ __device__ __forceinline__ T diag_at(const T* __restrict__ w0, const T* __restri
     const long sy = n[0], sz = (long)n[0] * n[1];
     T dg = T(1);
     T wn, unused;
-    nb_lo(w0, w0, c, i, n[0], 1, ((pm) >> 0) & 1, wn, unused); dg += wn;
-    nb_hi(w0, w0, c, i, n[0], 1, ((pm) >> 0) & 1, wn, unused); dg += wn;
-    nb_lo(w1, w1, c, j, n[1], sy, ((pm) >> 1) & 1, wn, unused); dg += wn;
-    nb_hi(w1, w1, c, j, n[1], sy, ((pm) >> 1) & 1, wn, unused); dg += wn;
+    nb_lo(w0, w0, c, i, n[0], 1, pm, 0, wn, unused); dg += wn;
+    nb_hi(w0, w0, c, i, n[0], 1, pm, 0, wn, unused); dg += wn;
+    nb_lo(w1, w1, c, j, n[1], sy, pm, 1, wn, unused); dg += wn;
+    nb_hi(w1, w1, c, j, n[1], sy, pm, 1, wn, unused); dg += wn;
     if (DIM == 3) {
-        nb_lo(w2, w2, c, k, n[2], sz, ((pm) >> 2) & 1, wn, unused); dg += wn;
-        nb_hi(w2, w2, c, k, n[2], sz, ((pm) >> 2) & 1, wn, unused); dg += wn;
+        nb_lo(w2, w2, c, k, n[2], sz, pm, 2, wn, unused); dg += wn;
+        nb_hi(w2, w2, c, k, n[2], sz, pm, 2, wn, unused); dg += wn;
     }
     if (has_a) dg += a[c];
     return dg;
+}
+
+// Block-wide red-black Gauss-Seidel on one level of up to NT * CPT cells, iterate in
+// p_sh (LDS): each colour update x_c += (b_c - (A x)_c) / A_cc, the residual norm checked
+// every 8 sweeps against tol2 (squared, relative to the starting residual).
+template <int DIM, typename T, int NT, int CPT>
+__device__ __forceinline__ void block_rbgs(const int32_t n[3], const T* w0, const T* w1, const T* w2, const T* b,
+                                           T* x, bool warm, T* p_sh, double* red, const T* a, bool has_a, int pm,
+                                           int maxit, double tol2) {
+    const int ncell = n[0] * n[1] * n[2];
+    T dinv[CPT];
+    int col[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
+        dinv[m] = T(0);
+        col[m] = -1;
+        if (c < ncell) {
+            int i, j, k;
+            cell_coords<DIM, T>(n, c, i, j, k);
+            col[m] = (i + j + k) & 1;
+            dinv[m] = T(1) / diag_at<DIM, T>(w0, w1, w2, n, c, a, has_a, pm);
+            p_sh[c] = warm ? x[c] : T(0);
+        }
+    }
+    __syncthreads();
+    double rr0 = -1.0;
+    for (int it = 0; it < 4 * maxit; ++it) {
+        for (int color = 0; color < 2; ++color) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                const int c = threadIdx.x + m * NT;
+                if (col[m] == color) {
+                    T dg;
+                    const T ax = apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a, pm);
+                    p_sh[c] += (b[c] - ax) * dinv[m];
+                }
+            }
+            __syncthreads();
+        }
+        if ((it & 7) == 7 || it == 0) {
+            double rr = 0.0, unused = 0.0;
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                const int c = threadIdx.x + m * NT;
+                if (c < ncell) {
+                    T dg;
+                    const double r = (double)b[c] - (double)apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a, pm);
+                    rr += r * r;
+                }
+            }
+            block_sum2<NT>(rr, unused, red);
+            if (rr0 < 0.0) rr0 = rr;
+            if (!(rr > tol2 * rr0)) break;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
+        if (c < ncell) x[c] = p_sh[c];
+    }
+    __syncthreads();
 }
 
 // Block-wide Jacobi-preconditioned CG on one level of up to NT * CPT cells.
@@ -953,6 +1037,13 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
     const int ncell = n[0] * n[1] * n[2];
     const int maxit = ncell < 2000 ? ncell + 4 : 2000;
     const double tol2 = 1e-12;                 // (1e-6)^2 relative
+    if ((pm >> 3) != 0) {
+        // continuous faces (a single-level grid's level 0): the operator is not symmetric,
+        // so conjugate gradients do not apply; red-black Gauss-Seidel to the same
+        // tolerance instead (the operator is an M-matrix with unit row sums)
+        block_rbgs<DIM, T, NT, CPT>(n, w0, w1, w2, b, x, warm, p_sh, red, a, has_a, pm, maxit, tol2);
+        return;
+    }
     T xr[CPT], r[CPT], dinv[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -1058,7 +1149,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     const bool warm = (d.level == 0) && (sizeof(T) == sizeof(double));
     if (ncell <= kCoarseMaxLDS) {
         block_cg<DIM, T, kCoarseThreads, kCoarseCPT>(d.n, w0, w1, w2, bg, xg, warm, p_sh, red, ag, has_a,
-                                                     d.per_mask);
+                                                     nb_mask(d));
         return;
     }
     const int maxit = 2000;
@@ -1074,7 +1165,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     __syncthreads();
     for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
         T dg;
-        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg, ag, has_a, d.per_mask);
+        const T ax = apply_at<DIM, T>(xg, w0, w1, w2, d.n, c, dg, ag, has_a, nb_mask(d));
         const T rc = bg[c] - ax;
         const T z = rc / dg;
         r[c] = rc;
@@ -1089,7 +1180,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
         double pq = 0.0, unused = 0.0;
         for (int c = threadIdx.x; c < ncell; c += kCoarseThreads) {
             T dg;
-            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg, ag, has_a, d.per_mask);
+            const T qc = apply_at<DIM, T>(p, w0, w1, w2, d.n, c, dg, ag, has_a, nb_mask(d));
             q[c] = qc;
             pq += (double)p[c] * (double)qc;
         }
@@ -1655,7 +1746,7 @@ struct TailGeom {
     float rnx;           // 1 / nx
     int32_t ox, ob, ow[3];
     int32_t oa, has_a;   // Dirichlet ghost couplings (plans with Dirichlet faces)
-    int32_t pm;          // periodic axes (bit per axis)
+    int32_t pm;          // neighbour mask (nb_mask): periodic axes, continuous faces
 };
 
 template <typename T>
@@ -1729,18 +1820,18 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
         const long c = i + j * sy + k * sz;
         T s = lv.b[c], dg = T(1);
         T wl, xl, wr, xr, wd, xd, wu, xu;
-        nb_lo(lv.w[0], lv.x, c, i, lv.n[0], 1, ((pmask) >> 0) & 1, wl, xl);
-        nb_hi(lv.w[0], lv.x, c, i, lv.n[0], 1, ((pmask) >> 0) & 1, wr, xr);
-        nb_lo(lv.w[1], lv.x, c, j, lv.n[1], sy, ((pmask) >> 1) & 1, wd, xd);
-        nb_hi(lv.w[1], lv.x, c, j, lv.n[1], sy, ((pmask) >> 1) & 1, wu, xu);
+        nb_lo(lv.w[0], lv.x, c, i, lv.n[0], 1, pmask, 0, wl, xl);
+        nb_hi(lv.w[0], lv.x, c, i, lv.n[0], 1, pmask, 0, wr, xr);
+        nb_lo(lv.w[1], lv.x, c, j, lv.n[1], sy, pmask, 1, wd, xd);
+        nb_hi(lv.w[1], lv.x, c, j, lv.n[1], sy, pmask, 1, wu, xu);
         s += wl * xl; dg += wl;
         s += wr * xr; dg += wr;
         s += wd * xd; dg += wd;
         s += wu * xu; dg += wu;
         if (DIM == 3) {
             T wb, xb, wf, xf;
-            nb_lo(lv.w[2], lv.x, c, k, lv.n[2], sz, ((pmask) >> 2) & 1, wb, xb);
-            nb_hi(lv.w[2], lv.x, c, k, lv.n[2], sz, ((pmask) >> 2) & 1, wf, xf);
+            nb_lo(lv.w[2], lv.x, c, k, lv.n[2], sz, pmask, 2, wb, xb);
+            nb_hi(lv.w[2], lv.x, c, k, lv.n[2], sz, pmask, 2, wf, xf);
             s += wb * xb; dg += wb;
             s += wf * xf; dg += wf;
         }
@@ -1793,7 +1884,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
         t.oa = o;                                          // unused without Dirichlet faces
         t.has_a = hasa;
-        t.pm = BC ? d0.per_mask : 0;
+        t.pm = BC ? nb_mask(L[first + m_own]) : 0;          // continuous faces cut level 0 only
     }
     __syncthreads();
     T* const sbase = reinterpret_cast<T*>(tail_smem);
@@ -1987,7 +2078,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
             ix[m_] = l0_cell<DIM>(d, lt, m_, i, j, k, ok[m_]);
             rv[m_] = residual_at<DIM, double>(as_global(d.X), as_global(d.B0), as_global(d.w[0]),
                                               as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0]),
-                                              d.n, i, j, k, as_global(d.ad), d.ad != nullptr, d.per_mask);
+                                              d.n, i, j, k, as_global(d.ad), d.ad != nullptr, nb_mask(d));
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {

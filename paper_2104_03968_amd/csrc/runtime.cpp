@@ -53,8 +53,10 @@ int validate_opts(const fld_opts& o) {
     for (int f = 0; f < 6; ++f) {
         if (o.bc[f] < 0) return FLD_ERR_INVALID_ARG;
         if (o.bc[f] != FLD_BC_ZERO_FLUX && o.bc[f] != FLD_BC_FIXED_GRADIENT && o.bc[f] != FLD_BC_DIRICHLET &&
-            o.bc[f] != FLD_BC_PERIODIC)
+            o.bc[f] != FLD_BC_PERIODIC && o.bc[f] != FLD_BC_CONTINUOUS)
             return FLD_ERR_UNSUPPORTED;
+        // continuous faces make the operator unsymmetric: no conjugate gradients
+        if (o.bc[f] == FLD_BC_CONTINUOUS && o.krylov) return FLD_ERR_INVALID_ARG;
         if (!std::isfinite(o.bc_grad[f])) return FLD_ERR_INVALID_ARG;
         if (o.bc[f] == FLD_BC_DIRICHLET && !(o.bc_value[f] >= 0.0 && std::isfinite(o.bc_value[f])))
             return FLD_ERR_INVALID_ARG;
@@ -197,6 +199,11 @@ static void build_levels(Plan& p) {
             d.fine = lev == 0 ? -1 : (int32_t)p.levels.size() - 1;
             for (int a = 0; a < gr.ndim; ++a)
                 if (p.opts.bc[2 * a] == FLD_BC_PERIODIC) d.per_mask |= 1 << a;
+            // continuous faces cut the finest operator only: the coarse levels keep the
+            // zero-flux operator, which stays symmetric (the coarsest solve is CG); cutting
+            // them too made the coarse corrections diverge on stiff grids
+            for (int f = 0; f < 2 * gr.ndim; ++f)
+                if (lev == 0 && p.opts.bc[f] == FLD_BC_CONTINUOUS) d.cont_mask |= 1 << f;
             if (lev == 0) {
                 for (int f = 0; f < 2 * gr.ndim; ++f) {
                     const double G = p.opts.bc[f] == FLD_BC_FIXED_GRADIENT ? p.opts.bc_grad[f] : 0.0;
@@ -209,6 +216,7 @@ static void build_levels(Plan& p) {
                         d.has_bc = 1;
                     }
                     if (p.opts.bc[f] == FLD_BC_PERIODIC) d.has_bc = 1;   // wrapped gradient ghosts
+                    if (p.opts.bc[f] == FLD_BC_CONTINUOUS) d.has_bc = 1; // extrapolated gradient ghosts
                 }
             }
             if (lev > 0) p.levels.back().coarse = (int32_t)p.levels.size();
@@ -309,7 +317,7 @@ static void build_lists(Plan& p) {
         // run the CG direction update as a z-march; its plane depth balances the blocks
         // over the compute units (rounds of one block per unit, fz + 2 steps each)
         D.pq3.prefix.assign(1, 0);
-        if (D.dim == 3 && !p.has_dir && !p.has_per && !D.fin_fused && !D.l0_cell.empty()) {
+        if (D.dim == 3 && !p.nb_bc() && !D.fin_fused && !D.l0_cell.empty()) {
             int64_t best = -1;
             for (int fz : {8, 16, 32, 64}) {
                 int64_t tiles = 0;
@@ -323,7 +331,7 @@ static void build_lists(Plan& p) {
         }
         // the fused level kernels know no Dirichlet couplings or wrapped neighbours: such plans
         // sweep per colour
-        D.fused = D.dim == 2 && p.opts.fused && !p.has_dir && !p.has_per && fused2_supported(p.opts.nu1) &&
+        D.fused = D.dim == 2 && p.opts.fused && !p.nb_bc() && fused2_supported(p.opts.nu1) &&
                   fused2_supported(p.opts.nu2) && fused2_supported(p.nuc1) && fused2_supported(p.nuc2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
@@ -333,7 +341,7 @@ static void build_lists(Plan& p) {
         }
         // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
         // even for its result to end in x
-        D.fused3 = D.dim == 3 && p.opts.fused && !p.has_dir && !p.has_per && fused3_supported(p.mixed) &&
+        D.fused3 = D.dim == 3 && p.opts.fused && !p.nb_bc() && fused3_supported(p.mixed) &&
                    p.opts.nu1 >= 1 &&
                    p.opts.nu2 >= 1 && (p.opts.nu1 + p.opts.nu2) % 2 == 0 && p.nuc1 >= 1 && p.nuc2 >= 1 &&
                    (p.nuc1 + p.nuc2) % 2 == 0;
@@ -385,12 +393,14 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     p.nuc2 = opts.nu_coarse ? opts.nu_coarse : opts.nu2;
     p.has_dir = false;
     p.has_per = false;
+    p.has_cont = false;
     p.any_bc = false;
     for (int f = 0; f < 6; ++f) {
         for (int g = 0; g < ngrids; ++g) {
             if (f >= 2 * grids[g].ndim) continue;
             if (opts.bc[f] == FLD_BC_DIRICHLET) p.has_dir = true;
             if (opts.bc[f] == FLD_BC_PERIODIC) p.has_per = true;
+            if (opts.bc[f] == FLD_BC_CONTINUOUS) p.has_cont = true;
             if (opts.bc[f] != FLD_BC_ZERO_FLUX) p.any_bc = true;
         }
     }
@@ -567,7 +577,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         launch_restrict(dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     }
     // the tail's levels are below the finest unless the whole grid lives in it
-    launch_tail(dim, f32, p.has_dir || p.has_per, p.dL, p.dS, tail, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
+    launch_tail(dim, f32, p.nb_bc(), p.dL, p.dS, tail, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
     launch_coarse_solve(dim, f32, p.dL, p.dS, coarsest, s);
     for (int d = D.maxdepth - 1; d >= d0; --d) {
         const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1, nu2 = d == 0 ? p.opts.nu2 : p.nuc2;
@@ -610,7 +620,7 @@ static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
     const bool f32 = p.mixed;
     for (int d = 0; d < D.maxdepth; ++d) launch_restrict_rhs(D.dim, f32, p.dL, p.dS, D.restrict_[d].dev, p.nblk, s);
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
-    launch_tail(D.dim, f32, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
+    launch_tail(D.dim, f32, p.nb_bc(), p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
     launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
     const int nv = p.opts.fmg_depths > 0 ? p.opts.fmg_depths : D.maxdepth;
     for (int d = D.maxdepth - 1; d >= 0; --d) {
@@ -1228,7 +1238,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                         launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, p.tile_depth, p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
-                    launch_tail(D.dim, p.mixed, p.has_dir || p.has_per, p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, 0, s);
+                    launch_tail(D.dim, p.mixed, p.nb_bc(), p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, 0, s);
                     break;
                 default: break;
             }

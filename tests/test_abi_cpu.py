@@ -62,7 +62,7 @@ def test_plan_create_validates_grids(n, ok):
 @pytest.mark.parametrize("kw,code", [
     (dict(rtol=0.0), -1), (dict(rtol=2.0), -1), (dict(c=-1.0), -1), (dict(limiter=7), -1),
     (dict(precision=3), -1), (dict(max_cycles=0), -1), (dict(nu1=0, nu2=0), -1),
-    (dict(bc=[4, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
+    (dict(bc=[5, 0, 0, 0, 0, 0]), fld.FLD_ERR_UNSUPPORTED), (dict(bc=[-1, 0, 0, 0, 0, 0]), -1),
     (dict(bc=[3, 0, 0, 0, 0, 0]), -1), (dict(bc=[0, 0, 0, 3, 0, 0]), -1),
     (dict(bc=[2, 0, 0, 0, 0, 0], bc_value=[-1.0, 0, 0, 0, 0, 0]), -1),
     (dict(bc=[0, 2, 0, 0, 0, 0], bc_value=[0, float("inf"), 0, 0, 0, 0]), -1),
@@ -303,3 +303,13 @@ def test_dirichlet_plans_add_one_coupling_array_per_level():
         n = 64 * 48 + 32 * 24 + 16 * 12 + 8 * 6 + 4 * 3 + 16 * 16 * 8 + 8 * 8 * 4 + 4 * 4 * 2
         extra = sizes[(prec, 2)] - base
         assert (8 + 4 * prec) * n <= extra <= (8 + 4 * prec) * n + 2 * 256 * 8 + 4096
+
+
+def test_continuous_faces_need_plain_vcycles():
+    """Continuous faces make the operator unsymmetric: CG plans are refused."""
+    bc = [fld.FLD_BC_CONTINUOUS, fld.FLD_BC_ZERO_FLUX, 0, 0, 0, 0]
+    with pytest.raises(fld.FLDError) as e:
+        fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(bc=bc))
+    assert e.value.code == fld.FLD_ERR_INVALID_ARG
+    h = fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(bc=bc, krylov=0))
+    fld.fld_plan_destroy(h)
