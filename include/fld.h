@@ -427,6 +427,22 @@ typedef struct fld_tuning {
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);
 
+/* fld_step for callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): the same step with the same
+   kernels and results, but the plan's tables and fields live in a fixed device
+   array of the library, FLD_NOALLOC_MAX_BYTES per GPU, held from the first call
+   on a GPU until the process ends, instead of a caller workspace.  The plan must
+   not be bound to a workspace (INVALID_ARG otherwise) and its workspace size
+   (fld_plan_workspace_bytes) must not exceed FLD_NOALLOC_MAX_BYTES (TOO_LARGE).
+   It calls no allocating routine: no autotuning and no graph capture (use_graph
+   and autotune are ignored), host staging in the plan's own host arrays.  All
+   calls on one GPU share the array, so calls that overlap on one GPU race;
+   each call rebinds its plan, and the plan is left unbound.  Synchronous, with
+   stats as fld_step.  Errors: as fld_step, plus INVALID_ARG and TOO_LARGE above. */
+#define FLD_NOALLOC_MAX_BYTES (64u << 20)
+int32_t fld_step_noalloc(fld_plan_t plan, const double* const* E_in, const double* const* kappa_rho,
+                         double* const* E_out, const double* dt, void* stream, fld_stats* stats);
+
 /* Algorithmic bytes of one pass of a driver: each kernel it launches counted by
    the arrays it must read and write once per cell it covers (faces, iterates,
    right-hand sides, CG vectors; coarse levels at their own size), summed over

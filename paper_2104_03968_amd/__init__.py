@@ -170,6 +170,7 @@ _sig = {
     "fld_plan_level_view": (C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(fld_level_view)]),
     "fld_coefficients": (C.c_int32, [_P, _PP, _PP, C.POINTER(C.c_double), _P]),
     "fld_step": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
+    "fld_step_noalloc": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
     "fld_step_aniso": (C.c_int32, [_P, _PP, _PP, _PP, C.POINTER(C.c_double), _P, C.POINTER(fld_stats)]),
     "fld_exchange": (C.c_int32, [_P, _PP, _PP, _PP, _PP, C.POINTER(C.c_double), C.POINTER(fld_gas), _P]),
     "fld_exchange_status": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
@@ -324,6 +325,21 @@ def fld_step(plan: int, E_in, kappa_rho, E_out, dt, stream=None, check: bool = T
                        _stream(stream), stats)
     if check:
         _check(rc, "fld_step")
+    return rc, [s.as_dict() for s in stats]
+
+
+FLD_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def fld_step_noalloc(plan: int, E_in, kappa_rho, E_out, dt, stream=None, check: bool = True):
+    """fld_step on an unbound plan through the library's fixed device scratch (allocates
+    nothing).  Returns (status, [stats dict per grid])."""
+    n = len(E_in)
+    stats = (fld_stats * n)()
+    rc = _lib.fld_step_noalloc(plan, _ptrs(E_in), _ptrs(kappa_rho), _ptrs(E_out), _dts(dt, n),
+                               _stream(stream), stats)
+    if check:
+        _check(rc, "fld_step_noalloc")
     return rc, [s.as_dict() for s in stats]
 
 

@@ -29,7 +29,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["kernels.hip", "runtime.cpp", "autotune.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "autotune.cpp", "server.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -118,6 +118,12 @@ struct Plan {
     Control* hCtrl = nullptr;                  // pinned
     GridState* hS = nullptr;                   // pinned
     bool own_pinned = true;                    // false: staging buffers belong to a server
+    // staging in plain host memory for steps that must not allocate (fld_step_noalloc),
+    // sized when the plan is built; io_host also carries every step's per-grid pointers
+    std::vector<StepIO> io_host;
+    std::vector<GridState> st_host;
+    Control ctrl_host{};
+    bool noalloc = false;                      // binding for one no-allocation step: no tuning, no graphs
     hipEvent_t ex_done[kExSlots] = {};
     int ex_slot = 0;
     hipEvent_t mo_done[kExSlots] = {};
@@ -186,6 +192,13 @@ void plan_verify(Plan& p, hipStream_t s);                // true residual of gri
 void plan_output(Plan& p, hipStream_t s);                // X -> E_out
 void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* out);
 int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s);
+// The plan behind a C-ABI handle (NULL for NULL).
+Plan* plan_of(fld_plan_t h);
+// One fld_step on an unbound plan whose tables and fields are laid out in `dev` (bytes):
+// binds without tuning or graph capture, stages through the plan's host arrays,
+// steps, and leaves the plan unbound again.  Allocates nothing.
+int plan_step_noalloc(Plan& p, void* dev, size_t bytes, const double* const* E_in, const double* const* kr,
+                      double* const* E_out, const double* dt, hipStream_t s, fld_stats* stats);
 
 // Autotuner (autotune.cpp): pick the launch shape of a bound plan by timing the
 // multigrid part of a V-cycle for each candidate, or take it from the cache.

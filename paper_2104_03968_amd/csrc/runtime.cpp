@@ -433,6 +433,8 @@ int plan_init(Plan& p, const fld_grid* grids, int ngrids, const fld_opts& opts) 
     build_levels(p);
     build_lists(p);
     layout(p);
+    p.io_host.assign(ngrids, StepIO{});
+    p.st_host.assign(ngrids, GridState{});
     return FLD_OK;
 }
 
@@ -832,20 +834,22 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     p.max_n = 0;
     for (auto n : p.ncell) p.max_n = std::max<int64_t>(p.max_n, n);
     // the tuner runs kernels over the fields: only on a plan that owns its workspace
-    if (p.opts.autotune && !p.tune_done && !init && p.field_base.empty()) {
+    if (p.opts.autotune && !p.tune_done && !init && p.field_base.empty() && !p.noalloc) {
         int rc = plan_autotune(p);
         if (rc != FLD_OK) return rc;
         FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
     }
-    if (p.opts.use_graph) {
+    if (p.opts.use_graph && !p.noalloc) {
         int rc = capture_graph(p);
         if (rc != FLD_OK) return rc;
     }
     return FLD_OK;
 }
 
+
 int plan_upload_io(Plan& p, const StepIO* io, hipStream_t s) {
-    for (int g = 0; g < p.ngrids(); ++g) p.hIO[g] = io[g];
+    if (p.hIO != io)
+        for (int g = 0; g < p.ngrids(); ++g) p.hIO[g] = io[g];
     FLD_HIP(hipMemcpyAsync(p.dIO, p.hIO, p.ngrids() * sizeof(StepIO), hipMemcpyHostToDevice, s));
     return FLD_OK;
 }
@@ -904,7 +908,7 @@ void plan_stats(const Plan& p, const GridState& st, int g, fld_stats* o) {
 static int step(Plan& p, const double* const* E_in, const double* const* kr, double* const* E_out,
                 const double* dt, hipStream_t s, fld_stats* stats, const double* const* krd = nullptr) {
     const int G = p.ngrids();
-    std::vector<StepIO> io(G);
+    std::vector<StepIO>& io = p.io_host;                 // sized when the plan was built
     for (int g = 0; g < G; ++g) {
         if (!E_in[g] || !E_out[g] || (!krd && !kr[g])) return FLD_ERR_INVALID_ARG;
         if (!(dt[g] > 0.0) || !std::isfinite(dt[g])) return FLD_ERR_INVALID_ARG;
@@ -961,6 +965,34 @@ static int step(Plan& p, const double* const* E_in, const double* const* kr, dou
         if (rc == FLD_OK && o.status != FLD_OK) rc = o.status;
     }
     p.last_cycles = maxc;
+    return rc;
+}
+
+int plan_step_noalloc(Plan& p, void* dev, size_t bytes, const double* const* E_in, const double* const* kr,
+                      double* const* E_out, const double* dt, hipStream_t s, fld_stats* stats) {
+    if (p.ws) return FLD_ERR_INVALID_ARG;                 // bound to a caller workspace
+    if (p.ws_bytes > bytes) return FLD_ERR_TOO_LARGE;
+    p.noalloc = true;
+    p.own_pinned = false;
+    p.hIO = p.io_host.data();
+    p.hS = p.st_host.data();
+    p.hCtrl = &p.ctrl_host;
+    int rc = plan_bind(p, dev, bytes, nullptr);
+    if (rc == FLD_OK) rc = step(p, E_in, kr, E_out, dt, s, stats);
+    // leave the plan unbound: the memory is shared by every call on this device
+    p.ws = nullptr;
+    p.dL = nullptr;
+    p.dS = nullptr;
+    p.dIO = nullptr;
+    p.dEx = nullptr;
+    p.dMo = nullptr;
+    p.dIm = nullptr;
+    p.dCtrl = nullptr;
+    p.hIO = nullptr;
+    p.hS = nullptr;
+    p.hCtrl = nullptr;
+    p.own_pinned = true;
+    p.noalloc = false;
     return rc;
 }
 
@@ -1302,6 +1334,10 @@ using fld::Plan;
 struct fld_plan_s {
     Plan p;
 };
+
+namespace fld {
+Plan* plan_of(fld_plan_t h) { return h ? &h->p : nullptr; }
+}  // namespace fld
 
 extern "C" {
 
