@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=384, help="c5: requests in the stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5: mean arrival rate (1/s)")
     ap.add_argument("--arena-gb", type=float, default=32.0, help="c5: server arena")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="c5: requests per plan of the batched comparison on the same requests")
+    ap.add_argument("--cycles-per-round", type=int, default=None,
+                    help="c5: V-cycles between the server's admission / retirement points")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default fp64 (the served stream: mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -207,7 +211,8 @@ def serve_stream(args):
         inputs.append((g.E.contiguous(), g.kappa_rho.contiguous(), g.h))
     torch.cuda.synchronize()
     precision = fld.FLD_PREC_FP64 if args.precision == "fp64" else fld.FLD_PREC_MIXED
-    srv = fld.Server(int(args.arena_gb * (1 << 30)), precision=precision, rtol=1e-10)
+    sopts = {} if args.cycles_per_round is None else {"cycles_per_round": args.cycles_per_round}
+    srv = fld.Server(int(args.arena_gb * (1 << 30)), precision=precision, rtol=1e-10, **sopts)
     # warm-up: one small request of each dimension (compiles nothing, but pages in the code)
     for shape in ((128, 128), (32, 32, 32)):
         g = W.random_grid(shape, 1, 1e-3, backend="torch", device=dev)
@@ -230,13 +235,14 @@ def serve_stream(args):
     th = threading.Thread(target=client)
     t_start = time.perf_counter()
     th.start()
-    lat, done_t, cycles, statuses = [], [], [], []
+    lat, wait, done_t, cycles, statuses = [], [], [], [], []
     for i in range(len(reqs)):
         while tickets[i] is None:
             time.sleep(1e-4)
         rc, res = srv.wait(tickets[i], 600.0)
         statuses.append(rc)
         lat.append(res.t_done - res.t_submit)
+        wait.append(res.t_admit - res.t_submit)
         done_t.append(res.t_done)
         cycles.append(res.stats.cycles)
         srv.release(tickets[i])
@@ -247,6 +253,7 @@ def serve_stream(args):
     cells = sum(r.cells for r in reqs)
     makespan = t_end - t_start
     offered = cells / max(reqs[-1].t_arrival, 1e-9)
+    batched = None if args.no_extras else batched_same_requests(reqs, inputs, precision, args.batch)
     out = {
         "metric": "cell-updates/s of implicit FLD step at 1e-10 residual; p50/p99 solve latency",
         "value": cells / makespan,
@@ -261,13 +268,49 @@ def serve_stream(args):
                                 "continuous batching, arena admission"),
                    "cells": cells, "arena_gb": args.arena_gb},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "admission_wait_ms": {"p50": float(np.percentile(wait, 50) * 1e3),
+                              "p99": float(np.percentile(wait, 99) * 1e3)},
         "offered_cell_updates_per_s": offered,
+        "achieved_over_offered": (cells / makespan) / offered,
+        "batched_same_requests": batched,
         "makespan_s": makespan,
         "failed": int(sum(1 for s_ in statuses if s_ != 0)),
         "vcycles_per_request": float(np.mean(cycles)),
         "server": {"rounds": info["rounds"], "completed": info["completed"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def batched_same_requests(reqs, inputs, precision, batch):
+    """The same requests as back-to-back batched steps: consecutive groups of `batch`
+    (in arrival order) in one multi-grid plan each, with the server's solver options
+    (rtol 1e-10, plain starts, CG).  Plans are built and warmed outside the clock; the
+    figure is the cells over the summed step times, the rate the batched path reaches
+    on this stream when nothing waits for arrivals."""
+    import torch
+    import paper_2104_03968_amd as fld
+    total_s, steps = 0.0, 0
+    for i0 in range(0, len(reqs), batch):
+        grp = range(i0, min(i0 + batch, len(reqs)))
+        plan = fld.Plan([tuple(inputs[i][0].shape) for i in grp], h=[inputs[i][2] for i in grp],
+                        precision=precision, rtol=1e-10, fmg=0, autotune=0)
+        E = [inputs[i][0] for i in grp]
+        K = [inputs[i][1] for i in grp]
+        out = [torch.empty_like(e) for e in E]
+        dts = [reqs[i].dt for i in grp]
+        plan.step(E, K, out, dts)                   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(E, K, out, dts)
+        torch.cuda.synchronize()
+        total_s += time.perf_counter() - t0
+        steps += 1
+        plan.close()
+        del out
+    cells = sum(r.cells for r in reqs)
+    log(f"bench c5: batched reference {steps} plans of <= {batch} requests, {total_s:.3f} s of steps")
+    return {"value": cells / total_s, "unit": "cell-updates/s", "batch": batch, "plans": steps,
+            "step_s": total_s}
 
 
 def host_info(threads_used: int) -> dict:

@@ -90,7 +90,9 @@ __host__ __device__ inline int32_t pq3_tiles(const int32_t n[3], int fz) {
 struct LevelDesc {
     int32_t n[3];        // nx, ny, nz (nz = 1 in 2D)
     int32_t ndim;
-    int32_t grid;        // owning grid
+    int32_t grid;        // owning grid (index of the plan's per-grid call tables)
+    int32_t sidx;        // index of the grid's solver state in the state array (the grid, or
+                         // a request server's slot)
     int32_t level;       // 0 = finest
     int32_t coarse;      // index of the next coarser level, -1 at the coarsest
     int32_t fine;        // index of the next finer level, -1 at level 0

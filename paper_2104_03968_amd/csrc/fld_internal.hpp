@@ -124,6 +124,16 @@ struct Plan {
     std::vector<GridState> st_host;
     Control ctrl_host{};
     bool noalloc = false;                      // binding for one no-allocation step: no tuning, no graphs
+    // Binding into shared state slots (the request server): the solver state of grid g
+    // lives at ext_state[grid_slot[g]] instead of the workspace; ext_state_init: the bind
+    // also writes fresh states there.  With bind_staging (pinned, bind_staging_bytes) the
+    // bind's table upload is one asynchronous copy on bind_stream, else one synchronous copy.
+    GridState* ext_state = nullptr;
+    std::vector<int32_t> grid_slot;
+    bool ext_state_init = true;
+    hipStream_t bind_stream = nullptr;
+    char* bind_staging = nullptr;
+    size_t bind_staging_bytes = 0;
     hipEvent_t ex_done[kExSlots] = {};
     int ex_slot = 0;
     hipEvent_t mo_done[kExSlots] = {};

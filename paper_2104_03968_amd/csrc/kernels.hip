@@ -291,7 +291,7 @@ k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
            int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
     const LevelDesc& d = L[jl.levels[blockIdx.x]];
-    GridState& g = S[d.grid];
+    GridState& g = S[d.sidx];
     const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
     if (!run) return;                                // uniform per block
     double s2, s1;
@@ -504,7 +504,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 if (!p.krd[0]) {
                     const double kk = p.kr[idx];
                     const bool ok = (e > 0.0) && isfinite(e) && (kk > 0.0) && isfinite(kk);
-                    if (!ok) atomicOr(&S[d.grid].bad, 1);
+                    if (!ok) atomicOr(&S[d.sidx].bad, 1);
                     // cell D from the pass before (k_cell_D, kept in the residual array)
                     const double* Dg = d.R;
                     const double Dc = Dg[idx];
@@ -524,7 +524,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                         const double kk = p.krd[a][idx];
                         ok = ok && (kk > 0.0) && isfinite(kk);
                     }
-                    if (!ok) atomicOr(&S[d.grid].bad, 1);
+                    if (!ok) atomicOr(&S[d.sidx].bad, 1);
                     for (int a = 0; a < DIM; ++a) Da[a] = cell_D<DIM>(p.E_in, p.krd[a], i, j, k, d.n, c12, c, limiter, gh);
                     const int im = i > 0 ? i - 1 : d.n[0] - 1, jm = j > 0 ? j - 1 : d.n[1] - 1;
                     const int km = k > 0 ? k - 1 : d.n[2] - 1;
@@ -575,7 +575,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 s1 += bsrc;
             }
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -735,7 +735,7 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
+        if (!S[d.sidx].active) continue;
         const int lt = t - jl.prefix[jb];
         const int tx_n = (d.n[0] + kSX - 1) / kSX;
         const int ty_n = (d.n[1] + kTY - 1) / kTY;
@@ -785,7 +785,7 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
-        if (!S[f.grid].active) continue;
+        if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int I, J, K;
         cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
@@ -817,7 +817,7 @@ k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
-        if (!S[f.grid].active) continue;
+        if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int i, j, k;
         cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
@@ -839,7 +839,7 @@ k_restrict_rhs(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
-        if (!S[f.grid].active) continue;
+        if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int I, J, K;
         cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
@@ -867,7 +867,7 @@ k_fmg_interp(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, J
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& f = L[jl.levels[jb]];
-        if (!S[f.grid].active) continue;
+        if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int i, j, k;
         cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
@@ -1135,7 +1135,7 @@ k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     __shared__ T p_sh[kCoarseMaxLDS];
     __shared__ double red[2 * kCoarseThreads / 64];
     const LevelDesc& d = L[jl.levels[blockIdx.x]];
-    if (!S[d.grid].active) return;
+    if (!S[d.sidx].active) return;
     const int ncell = d.n[0] * d.n[1] * d.n[2];
     const T* w0 = Arr<T>::w(d, 0);
     const T* w1 = Arr<T>::w(d, 1);
@@ -1335,7 +1335,7 @@ __device__ __forceinline__ Tile2Job tile2_job(const LevelDesc* __restrict__ L, c
     const int jb = find_job(jl.prefix, jl.njobs, tt);
     j.d = &L[jl.levels[jb]];
     j.c = &L[j.d->coarse];
-    j.act = S[j.d->grid].active != 0;
+    j.act = S[j.d->sidx].active != 0;
     const int lt = tt - jl.prefix[jb];
     const int tx_n = (j.d->n[0] + FX - 1) / FX;
     j.gx0 = (lt % tx_n) * FX - HALO;
@@ -1561,7 +1561,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
+        if (!S[d.sidx].active) continue;
         const int lt = tt - jl.prefix[jb];
         const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
         const int tx_n = (n0 + FX - 1) / FX, ty_n = (n1 + FY - 1) / FY;
@@ -1852,7 +1852,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     __shared__ double red[2 * kTailThreads / 64];
     const int first = jl.levels[blockIdx.x];
     const LevelDesc& d0 = L[first];
-    if (!S[d0.grid].active) return;
+    if (!S[d0.sidx].active) return;
     const int hasa = (BC && Arr<T>::ad(d0) != nullptr) ? 1 : 0;
     // the grid's levels from `first` down are consecutive descriptors: thread m reads
     // level m's (no chain through the coarse links), then the LDS layout follows
@@ -2063,7 +2063,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        const GridState& g = S[d.grid];
+        const GridState& g = S[d.sidx];
         // select 0: grids still iterating; 1: grids that stopped with FLD_OK (their
         // recursive residual met the target), whose true residual is checked here
         if (select == 0 ? !g.active : (g.status != FLD_OK || g.active)) continue;   // uniform per tile
@@ -2094,7 +2094,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
                 as_global(d.x)[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2128,7 +2128,7 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
+        if (!S[d.sidx].active) continue;
         const int lt = t - jl.prefix[jb];
         double a = 0.0, unused = 0.0;
         const gptr<double> Rg = as_global(d.R);
@@ -2144,7 +2144,7 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) a += ok[m_] ? rv[m_] * zv[m_] : 0.0;
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2172,7 +2172,7 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        GridState& g = S[d.grid];
+        GridState& g = S[d.sidx];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
@@ -2221,7 +2221,7 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                 }
             }
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2251,7 +2251,7 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[jl.levels[jb]];
-        GridState& g = S[d.grid];
+        GridState& g = S[d.sidx];
         if (!g.active) continue;
         const int lt = tt - jl.prefix[jb];
         const bool restart = g.iter == 0;                  // p = z (the old direction is not read)
@@ -2343,7 +2343,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        GridState& g = S[d.grid];
+        GridState& g = S[d.sidx];
         if (!g.active) continue;
         const int lt = t - jl.prefix[jb];
         const double alpha = g.alpha;
@@ -2377,7 +2377,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
                 as_global(d.x)[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.grid], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2390,7 +2390,7 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
         const LevelDesc& d = L[jl.levels[jb]];
-        if (!S[d.grid].active) continue;
+        if (!S[d.sidx].active) continue;
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;

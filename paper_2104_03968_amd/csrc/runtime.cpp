@@ -194,6 +194,7 @@ static void build_levels(Plan& p) {
             for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = hinv[a]; }
             d.ndim = gr.ndim;
             d.grid = g;
+            d.sidx = g;
             d.level = lev;
             d.coarse = -1;
             d.fine = lev == 0 ? -1 : (int32_t)p.levels.size() - 1;
@@ -757,6 +758,17 @@ int plan_set_shape(Plan& p, const LaunchShape& sh) {
     return FLD_OK;
 }
 
+// Copy a list into the table image and point its JobList at the device copy.
+static void stage_list(Plan& p, HostList& l, char* img) {
+    if (!l.levels.empty())
+        std::memcpy(img + l.off_levels, l.levels.data(), l.levels.size() * sizeof(int32_t));
+    std::memcpy(img + l.off_prefix, l.prefix.data(), l.prefix.size() * sizeof(int32_t));
+    int64_t cells = 0;
+    for (int32_t li : l.levels) cells += (int64_t)p.levels[li].n[0] * p.levels[li].n[1] * p.levels[li].n[2];
+    l.dev = JobList{reinterpret_cast<int32_t*>(p.ws + l.off_levels), reinterpret_cast<int32_t*>(p.ws + l.off_prefix),
+                    (int32_t)l.levels.size(), l.prefix.back(), cells};
+}
+
 int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     if (!dev) return FLD_ERR_INVALID_ARG;
     if (bytes < p.ws_bytes) return FLD_ERR_NO_WORKSPACE;
@@ -764,7 +776,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     p.ws = static_cast<char*>(dev);
     char* const tab = p.ws;
     p.dL = reinterpret_cast<LevelDesc*>(tab + p.off_levels);
-    p.dS = reinterpret_cast<GridState*>(tab + p.off_state);
+    p.dS = p.ext_state ? p.ext_state : reinterpret_cast<GridState*>(tab + p.off_state);
     p.dIO = reinterpret_cast<StepIO*>(tab + p.off_stepio);
     p.dEx = reinterpret_cast<ExchangeIO*>(tab + p.off_exio);
     p.dMo = reinterpret_cast<MomentsIO*>(tab + p.off_moio);
@@ -795,38 +807,53 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
         d.xs32 = (f.has_xs && p.mixed) ? reinterpret_cast<float*>(ws + f.xs) : nullptr;
         d.ad = p.has_dir ? reinterpret_cast<double*>(ws + f.ad) : nullptr;
         d.ad32 = (p.has_dir && p.mixed) ? reinterpret_cast<float*>(ws + f.ad32) : nullptr;
+        d.sidx = p.ext_state ? p.grid_slot[d.grid] : d.grid;
     }
-    FLD_HIP(hipMemcpy(p.dL, p.levels.data(), p.levels.size() * sizeof(LevelDesc), hipMemcpyHostToDevice));
-    std::vector<GridState> st(p.ngrids());
-    for (int g = 0; g < p.ngrids(); ++g) {
-        st[g] = init ? init[g] : GridState{};
-        st[g].ntiles0 = l0_tiles(p.levels[p.level0[g]].n);
-        st[g].done = 0;
+    // every table of the workspace's table region, built on the host and uploaded at once
+    const int G = p.ngrids();
+    const size_t state_bytes = (p.ext_state && p.ext_state_init) ? G * sizeof(GridState) : 0;
+    std::vector<char> host_img;
+    char* img = nullptr;
+    const bool async = p.bind_staging && p.bind_staging_bytes >= p.table_bytes + state_bytes;
+    if (async) {
+        img = p.bind_staging;
+    } else {
+        host_img.assign(p.table_bytes + state_bytes, 0);
+        img = host_img.data();
     }
-    FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
-    Control c0{};
-    FLD_HIP(hipMemcpy(p.dCtrl, &c0, sizeof(Control), hipMemcpyHostToDevice));
-    auto upload = [&](HostList& l) { return upload_list(p, l); };
+    std::memset(img, 0, p.table_bytes);
+    std::memcpy(img + p.off_levels, p.levels.data(), p.levels.size() * sizeof(LevelDesc));
+    GridState* st = p.ext_state ? reinterpret_cast<GridState*>(img + p.table_bytes)
+                                : reinterpret_cast<GridState*>(img + p.off_state);
+    if (!p.ext_state || p.ext_state_init) {
+        for (int g = 0; g < G; ++g) {
+            st[g] = init ? init[g] : GridState{};
+            st[g].ntiles0 = l0_tiles(p.levels[p.level0[g]].n);
+            st[g].done = 0;
+        }
+    }
     for (auto& D : p.dl) {
-        int rc;
-        if ((rc = upload(D.l0_cell)) != FLD_OK) return rc;
-        if ((rc = upload(D.pq3)) != FLD_OK) return rc;
-        if ((rc = upload(D.coarsest)) != FLD_OK) return rc;
-        if ((rc = upload(D.tail)) != FLD_OK) return rc;
-        for (auto& l : D.coarsen) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.down2) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.up2) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.sw3) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.sr3) if ((rc = upload(l)) != FLD_OK) return rc;
+        stage_list(p, D.l0_cell, img);
+        stage_list(p, D.pq3, img);
+        stage_list(p, D.coarsest, img);
+        stage_list(p, D.tail, img);
+        for (auto* v : {&D.coarsen, &D.down2, &D.up2, &D.sw3, &D.sr3, &D.smooth, &D.restrict_, &D.prolong,
+                        &D.tail_from, &D.coarsest_from})
+            for (auto& l : *v) stage_list(p, l, img);
         if (!D.tail.empty() && prepare_tail(D.dim, p.mixed, D.tail_smem) != 0) {
             g_last_error = "hipFuncSetAttribute(max dynamic LDS) failed for the tail kernel";
             return FLD_ERR_HIP;
         }
-        for (auto& l : D.smooth) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.restrict_) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.prolong) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.tail_from) if ((rc = upload(l)) != FLD_OK) return rc;
-        for (auto& l : D.coarsest_from) if ((rc = upload(l)) != FLD_OK) return rc;
+    }
+    if (async) {
+        FLD_HIP(hipMemcpyAsync(p.ws, img, p.table_bytes, hipMemcpyHostToDevice, p.bind_stream));
+        for (int g = 0; g < G && state_bytes; ++g)
+            FLD_HIP(hipMemcpyAsync(p.ext_state + p.grid_slot[g], st + g, sizeof(GridState), hipMemcpyHostToDevice,
+                                   p.bind_stream));
+    } else {
+        FLD_HIP(hipMemcpy(p.ws, img, p.table_bytes, hipMemcpyHostToDevice));
+        for (int g = 0; g < G && state_bytes; ++g)
+            FLD_HIP(hipMemcpy(p.ext_state + p.grid_slot[g], st + g, sizeof(GridState), hipMemcpyHostToDevice));
     }
     if (!p.hIO) FLD_HIP(hipHostMalloc((void**)&p.hIO, p.ngrids() * sizeof(StepIO), hipHostMallocDefault));
     if (!p.hCtrl) FLD_HIP(hipHostMalloc((void**)&p.hCtrl, sizeof(Control), hipHostMallocDefault));
@@ -834,10 +861,11 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     p.max_n = 0;
     for (auto n : p.ncell) p.max_n = std::max<int64_t>(p.max_n, n);
     // the tuner runs kernels over the fields: only on a plan that owns its workspace
-    if (p.opts.autotune && !p.tune_done && !init && p.field_base.empty() && !p.noalloc) {
+    if (p.opts.autotune && !p.tune_done && !init && p.field_base.empty() && !p.noalloc && !p.ext_state) {
+        std::vector<GridState> fresh(st, st + G);                // the tuner leaves its own states
         int rc = plan_autotune(p);
         if (rc != FLD_OK) return rc;
-        FLD_HIP(hipMemcpy(p.dS, st.data(), st.size() * sizeof(GridState), hipMemcpyHostToDevice));
+        FLD_HIP(hipMemcpy(p.dS, fresh.data(), fresh.size() * sizeof(GridState), hipMemcpyHostToDevice));
     }
     if (p.opts.use_graph && !p.noalloc) {
         int rc = capture_graph(p);

@@ -128,7 +128,16 @@ struct Server {
     char* arena_base = nullptr;
     Arena arena;
     size_t off_tables = kNoOff, tables_bytes = 0;   // composite plan tables
+    size_t off_states = kNoOff;               // solver state of every slot (composite and request plans)
+    GridState* d_states = nullptr;
     hipStream_t stream = nullptr;
+    // pinned staging of the plans' table uploads: one region per slot for the request
+    // plans, two alternating regions for the composite (an event guards each)
+    static constexpr size_t kReqStage = 128 * 1024;
+    char* pin_stage_req = nullptr;
+    char* pin_stage_comp[2] = {nullptr, nullptr};
+    hipEvent_t comp_ev[2] = {nullptr, nullptr};
+    int comp_buf = 0;
     // pinned staging shared by the composite and the request plans
     StepIO* pin_io = nullptr;
     GridState* pin_req = nullptr;             // one state per slot (request plans)
@@ -182,6 +191,11 @@ Server::~Server() {
     if (pin_req) (void)hipHostFree(pin_req);
     if (pin_comp) (void)hipHostFree(pin_comp);
     if (pin_ctrl) (void)hipHostFree(pin_ctrl);
+    if (pin_stage_req) (void)hipHostFree(pin_stage_req);
+    for (int k = 0; k < 2; ++k) {
+        if (pin_stage_comp[k]) (void)hipHostFree(pin_stage_comp[k]);
+        if (comp_ev[k]) (void)hipEventDestroy(comp_ev[k]);
+    }
 }
 
 void Server::fail_all(int code) {
@@ -242,13 +256,21 @@ int Server::admit_locked(std::vector<Request*>& admitted) {
 }
 
 // Copy a newly admitted request's inputs into the arena and run its coefficient
-// pass and initial residual on its own single-grid plan (asynchronous).
+// pass and initial residual on its own single-grid plan, whose solver state is the
+// request's slot of the shared state array (asynchronous: the table upload, the input
+// copies and the prologue are ordered on the server stream; nothing waits here).
 int Server::start_request(Request* r, int slot) {
     Plan& p = *r->plan;
     p.own_pinned = false;
     p.hIO = pin_io + slot;
     p.hS = pin_req + slot;
     p.hCtrl = pin_ctrl;
+    p.ext_state = d_states;
+    p.grid_slot.assign(1, slot);
+    p.ext_state_init = true;
+    p.bind_stream = stream;
+    p.bind_staging = pin_stage_req + (size_t)slot * kReqStage;   // free: the slot's last user is retired
+    p.bind_staging_bytes = kReqStage;
     int rc = plan_bind(p, arena_base + r->off_ws, r->plan_bytes, nullptr);
     if (rc != FLD_OK) return rc;
     double* inE = reinterpret_cast<double*>(arena_base + r->off_in);
@@ -267,23 +289,23 @@ int Server::start_request(Request* r, int slot) {
     const StepIO io{inE, inK, out, r->dt};
     if ((rc = plan_upload_io(p, &io, stream)) != FLD_OK) return rc;
     if ((rc = plan_prologue(p, stream)) != FLD_OK) return rc;
-    FLD_HIP(hipMemcpyAsync(pin_req + slot, p.dS, sizeof(GridState), hipMemcpyDeviceToHost, stream));
     r->t_start = now_s();
     return FLD_OK;
 }
 
-// Composite plan over the resident requests (fields stay where each request's
-// plan put them; only descriptors, lists and solver states are rebuilt).
+// Composite plan over the resident requests: fields stay where each request's plan
+// put them and the solver states stay in their slots, so a rebuild is the host
+// work of the descriptors and lists plus one asynchronous table upload, ordered on
+// the stream after the rounds that used the previous tables.
 int Server::rebuild() {
     comp.reset();
     dirty = false;
     if (resident.empty()) return FLD_OK;
     std::vector<fld_grid> grids;
-    std::vector<GridState> states;
     auto c = std::make_unique<Plan>();
     for (Request* r : resident) {
         grids.push_back(r->grid);
-        states.push_back(r->state);
+        c->grid_slot.push_back(slot_of[r->ticket]);
         c->field_base.push_back(reinterpret_cast<char*>(r->plan->ws) + r->plan->field_off[0]);
     }
     int rc = plan_init(*c, grids.data(), (int)grids.size(), opts);
@@ -296,7 +318,15 @@ int Server::rebuild() {
     c->hIO = pin_io;
     c->hS = pin_comp;
     c->hCtrl = pin_ctrl;
-    if ((rc = plan_bind(*c, arena_base + off_tables, tables_bytes, states.data())) != FLD_OK) return rc;
+    c->ext_state = d_states;
+    c->ext_state_init = false;                 // the states carry over
+    comp_buf ^= 1;                             // the other staging region: its last copy is done
+    FLD_HIP(hipEventSynchronize(comp_ev[comp_buf]));
+    c->bind_stream = stream;
+    c->bind_staging = pin_stage_comp[comp_buf];
+    c->bind_staging_bytes = tables_bytes;
+    if ((rc = plan_bind(*c, arena_base + off_tables, tables_bytes, nullptr)) != FLD_OK) return rc;
+    FLD_HIP(hipEventRecord(comp_ev[comp_buf], stream));
     comp = std::move(c);
     return FLD_OK;
 }
@@ -309,12 +339,14 @@ int Server::round() {
     for (int i = 0; i < k; ++i) plan_cycle(c, stream);
     if (c.krylov) plan_verify(c, stream);
     FLD_HIP(hipGetLastError());
-    FLD_HIP(hipMemcpyAsync(pin_comp, c.dS, G * sizeof(GridState), hipMemcpyDeviceToHost, stream));
+    // every slot's state in one copy (the resident requests are a subset of the slots)
+    FLD_HIP(hipMemcpyAsync(pin_comp, d_states, (size_t)sopts.max_slots * sizeof(GridState), hipMemcpyDeviceToHost,
+                           stream));
     FLD_HIP(hipStreamSynchronize(stream));
     std::vector<Request*> finished;
     for (int g = 0; g < G; ++g) {
         Request* r = resident[g];
-        r->state = pin_comp[g];
+        r->state = pin_comp[slot_of[r->ticket]];
         if (!r->state.active) finished.push_back(r);
     }
     info.rounds++;
@@ -367,12 +399,9 @@ void Server::run() {
         for (Request* r : admitted)
             if ((rc = start_request(r, slot_of[r->ticket])) != FLD_OK) break;
         if (rc == FLD_OK && !admitted.empty()) {
-            if (hipStreamSynchronize(stream) != hipSuccess) rc = FLD_ERR_HIP;
+            // no wait: the prologues wrote the states into their slots in stream order
             std::lock_guard<std::mutex> lk(mu);
-            for (Request* r : admitted) {
-                r->state = pin_req[slot_of[r->ticket]];
-                resident.push_back(r);
-            }
+            for (Request* r : admitted) resident.push_back(r);
             info.resident = (int32_t)resident.size();
             dirty = true;
         }
@@ -434,6 +463,17 @@ int32_t fld_server_create(const fld_server_opts* o, void* arena_dev, size_t aren
         s.off_tables = s.arena.alloc(s.tables_bytes);
         if (s.off_tables == fld::kNoOff) return FLD_ERR_TOO_LARGE;
         const size_t M = (size_t)o->max_slots;
+        s.off_states = s.arena.alloc(M * sizeof(fld::GridState));
+        if (s.off_states == fld::kNoOff) return FLD_ERR_TOO_LARGE;
+        s.d_states = reinterpret_cast<fld::GridState*>(s.arena_base + s.off_states);
+        if (hipMemset(s.d_states, 0, M * sizeof(fld::GridState)) != hipSuccess) return FLD_ERR_HIP;
+        if (hipHostMalloc((void**)&s.pin_stage_req, M * fld::Server::kReqStage, hipHostMallocDefault) != hipSuccess)
+            return FLD_ERR_HIP;
+        for (int k = 0; k < 2; ++k) {
+            if (hipHostMalloc((void**)&s.pin_stage_comp[k], s.tables_bytes, hipHostMallocDefault) != hipSuccess)
+                return FLD_ERR_HIP;
+            if (hipEventCreateWithFlags(&s.comp_ev[k], hipEventDisableTiming) != hipSuccess) return FLD_ERR_HIP;
+        }
         if (hipHostMalloc((void**)&s.pin_io, M * sizeof(fld::StepIO), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&s.pin_req, M * sizeof(fld::GridState), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&s.pin_comp, M * sizeof(fld::GridState), hipHostMallocDefault) != hipSuccess ||

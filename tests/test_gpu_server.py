@@ -166,3 +166,20 @@ def test_device_inputs_are_read_after_their_producer_stream():
     assert np.array_equal(x, ref)
     assert srv.release(t) == 0
     srv.close()
+
+
+@pytest.mark.parametrize("cycles_per_round", [1, 2])
+@pytest.mark.parametrize("order", [(3, 1), (0, 1), (3, 0, 1)])
+def test_a_grid_keeps_converging_when_earlier_grids_leave(order, cycles_per_round):
+    """The grids admitted first finish first; the rebuilt composite then holds the
+    remaining grid at a lower index while its solver state stays in the same slot.
+    Every kernel must find that state (and the per-grid work of the fused tiles)
+    through the slot, so the result is bitwise the one the grid gets alone."""
+    items = [_inputs(i, MIX[i][0], MIX[i][1]) for i in order]
+    srv = fld.Server(1 << 30, precision=1, rtol=2e-11, cycles_per_round=cycles_per_round)
+    alone = _run(srv, [items[-1]])[0][0]
+    mixed = _run(srv, items)
+    assert srv.info()["failed"] == 0
+    assert np.array_equal(mixed[-1][0], alone)
+    assert mixed[-1][1].stats.cycles > max(r.stats.cycles for _, r in mixed[:-1])
+    srv.close()
