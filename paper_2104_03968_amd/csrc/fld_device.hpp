@@ -168,7 +168,17 @@ struct JobList {
     int32_t njobs;
     int32_t total;       // prefix[njobs]
     int64_t cells;       // cells of the listed levels (host bookkeeping; kernels ignore it)
+    int32_t lev0;        // levels[0] (-1 for an empty list): a one-job launch reads its level
+    int32_t pad_;        // from the kernel arguments instead of memory
 };
+
+// The job-list lookups of a tile's kernel.  prefix[0] is 0 and prefix[njobs] is total,
+// so a one-job list needs no load from the list at all: its level comes from lev0.
+__host__ __device__ inline int job_level(const JobList& jl, int jb) { return jl.njobs == 1 ? jl.lev0 : jl.levels[jb]; }
+__host__ __device__ inline int job_start(const JobList& jl, int jb) { return jb == 0 ? 0 : jl.prefix[jb]; }
+__host__ __device__ inline int job_tiles(const JobList& jl, int jb) {
+    return (jb + 1 == jl.njobs ? jl.total : jl.prefix[jb + 1]) - job_start(jl, jb);
+}
 
 // Algorithmic-byte accounting.  While a thread has an Acct installed (acct_set),
 // every launch wrapper adds the bytes its kernel must move (each array it reads

@@ -290,13 +290,13 @@ __global__ void __launch_bounds__(kBlock)
 k_finalize(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int mode, double rtol,
            int max_cycles) {
     __shared__ double sh[2 * kBlock / 64];
-    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    const LevelDesc& d = L[job_level(jl, blockIdx.x)];
     GridState& g = S[d.sidx];
     const bool run = (mode == FIN_B) || (mode == FIN_R_VERIFY ? (g.status == FLD_OK && !g.active) : g.active);
     if (!run) return;                                // uniform per block
     double s2, s1;
     // the tiles of the list's reducing kernel (level-0 cell tiles, or the z-march tiles)
-    sum_parts(d.part, jl.prefix[blockIdx.x + 1] - jl.prefix[blockIdx.x], mode == FIN_B ? 2 : 1, s2, s1, sh);
+    sum_parts(d.part, job_tiles(jl, blockIdx.x), mode == FIN_B ? 2 : 1, s2, s1, sh);
     if (threadIdx.x == 0) finalize_grid(g, s2, s1, mode, rtol, max_cycles);
 }
 
@@ -454,10 +454,10 @@ k_cell_D(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         const StepIO& p = io[d.grid];
         if (p.krd[0]) continue;                                  // uniform per tile
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         const LevelDesc* gh = (BC && d.has_bc) ? &d : nullptr;
         const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
 #pragma unroll
@@ -484,8 +484,8 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
-        const int lt = t - jl.prefix[jb];
+        const LevelDesc& d = L[job_level(jl, jb)];
+        const int lt = t - job_start(jl, jb);
         const StepIO& p = io[d.grid];
         const double dt = p.dt;
         double s2 = 0.0, s1 = 0.0;
@@ -575,7 +575,7 @@ k_coeff(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                 s1 += bsrc;
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], s2, s1, 2, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), s2, s1, 2, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -595,10 +595,10 @@ k_coarsen(const LevelDesc* __restrict__ L, JobList jl, int galerkin) {
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& f = L[job_level(jl, jb)];
         const LevelDesc& cL = L[f.coarse];
         int I, J, K;
-        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        cell_of_tile<DIM>(cL.n, t - job_start(jl, jb), threadIdx.x, I, J, K);
         if (I >= cL.n[0] || J >= cL.n[1]) continue;
         const long cidx = I + (long)cL.n[0] * (J + (long)cL.n[1] * K);
         const long fsy = f.n[0], fsz = (long)f.n[0] * f.n[1];
@@ -734,9 +734,9 @@ k_smooth(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         if (!S[d.sidx].active) continue;
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         const int tx_n = (d.n[0] + kSX - 1) / kSX;
         const int ty_n = (d.n[1] + kTY - 1) / kTY;
         const int tx = lt % tx_n;
@@ -784,11 +784,11 @@ k_restrict(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, Job
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& f = L[job_level(jl, jb)];
         if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int I, J, K;
-        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        cell_of_tile<DIM>(cL.n, t - job_start(jl, jb), threadIdx.x, I, J, K);
         if (I >= cL.n[0] || J >= cL.n[1]) continue;
         const gptr<T> x = as_global(Arr<T>::x(f));
         const gptr<T> b = as_global(Arr<T>::b(f));
@@ -816,11 +816,11 @@ k_prolong(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& f = L[job_level(jl, jb)];
         if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int i, j, k;
-        cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        cell_of_tile<DIM>(f.n, t - job_start(jl, jb), threadIdx.x, i, j, k);
         if (i >= f.n[0] || j >= f.n[1]) continue;
         const long idx = i + (long)f.n[0] * (j + (long)f.n[1] * k);
         const long cidx = (i >> 1) + (long)cL.n[0] * ((j >> 1) + (long)cL.n[1] * (k >> 1));
@@ -838,11 +838,11 @@ k_restrict_rhs(const LevelDesc* __restrict__ L, const GridState* __restrict__ S,
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& f = L[job_level(jl, jb)];
         if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int I, J, K;
-        cell_of_tile<DIM>(cL.n, t - jl.prefix[jb], threadIdx.x, I, J, K);
+        cell_of_tile<DIM>(cL.n, t - job_start(jl, jb), threadIdx.x, I, J, K);
         if (I >= cL.n[0] || J >= cL.n[1]) continue;
         const gptr<T> b = as_global(Arr<T>::b(f));
         const long sy = f.n[0], sz = (long)f.n[0] * f.n[1];
@@ -866,11 +866,11 @@ k_fmg_interp(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, J
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& f = L[jl.levels[jb]];
+        const LevelDesc& f = L[job_level(jl, jb)];
         if (!S[f.sidx].active) continue;
         const LevelDesc& cL = L[f.coarse];
         int i, j, k;
-        cell_of_tile<DIM>(f.n, t - jl.prefix[jb], threadIdx.x, i, j, k);
+        cell_of_tile<DIM>(f.n, t - job_start(jl, jb), threadIdx.x, i, j, k);
         if (i >= f.n[0] || j >= f.n[1]) continue;
         const gptr<T> xc = as_global(Arr<T>::x(cL));
         const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
@@ -1134,7 +1134,7 @@ __global__ void __launch_bounds__(kCoarseThreads)
 k_coarse_solve(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
     __shared__ T p_sh[kCoarseMaxLDS];
     __shared__ double red[2 * kCoarseThreads / 64];
-    const LevelDesc& d = L[jl.levels[blockIdx.x]];
+    const LevelDesc& d = L[job_level(jl, blockIdx.x)];
     if (!S[d.sidx].active) return;
     const int ncell = d.n[0] * d.n[1] * d.n[2];
     const T* w0 = Arr<T>::w(d, 0);
@@ -1333,10 +1333,10 @@ __device__ __forceinline__ Tile2Job tile2_job(const LevelDesc* __restrict__ L, c
                                               const JobList& jl, int tt) {
     Tile2Job j;
     const int jb = find_job(jl.prefix, jl.njobs, tt);
-    j.d = &L[jl.levels[jb]];
+    j.d = &L[job_level(jl, jb)];
     j.c = &L[j.d->coarse];
     j.act = S[j.d->sidx].active != 0;
-    const int lt = tt - jl.prefix[jb];
+    const int lt = tt - job_start(jl, jb);
     const int tx_n = (j.d->n[0] + FX - 1) / FX;
     j.gx0 = (lt % tx_n) * FX - HALO;
     j.gy0 = (lt / tx_n) * FY - HALO;
@@ -1560,9 +1560,9 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
     for (int k = order.first(); order.more(k); k += order.per) {
         const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         if (!S[d.sidx].active) continue;
-        const int lt = tt - jl.prefix[jb];
+        const int lt = tt - job_start(jl, jb);
         const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
         const int tx_n = (n0 + FX - 1) / FX, ty_n = (n1 + FY - 1) / FY;
         const int tx = lt % tx_n, rest = lt / tx_n;
@@ -1850,7 +1850,7 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
     __shared__ TailGeom tl[kMaxTail];
     __shared__ int32_t off[kMaxTail + 1];
     __shared__ double red[2 * kTailThreads / 64];
-    const int first = jl.levels[blockIdx.x];
+    const int first = job_level(jl, blockIdx.x);
     const LevelDesc& d0 = L[first];
     if (!S[d0.sidx].active) return;
     const int hasa = (BC && Arr<T>::ad(d0) != nullptr) ? 1 : 0;
@@ -1987,12 +1987,12 @@ k_moments(const LevelDesc* __restrict__ L, JobList jl, const MomentsIO* __restri
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         const MomentsIO& m = io[d.grid];
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
-            cell_of_l0tile<DIM>(d.n, t - jl.prefix[jb], threadIdx.x + m_ * kBlock, i, j, k);
+            cell_of_l0tile<DIM>(d.n, t - job_start(jl, jb), threadIdx.x + m_ * kBlock, i, j, k);
             if (i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) continue;
             const long idx = i + (long)d.n[0] * (j + (long)d.n[1] * k);
             const double c12[3] = {d.hinv[0] / 12.0, d.hinv[1] / 12.0, d.hinv[2] / 12.0};
@@ -2062,12 +2062,12 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         const GridState& g = S[d.sidx];
         // select 0: grids still iterating; 1: grids that stopped with FLD_OK (their
         // recursive residual met the target), whose true residual is checked here
         if (select == 0 ? !g.active : (g.status != FLD_OK || g.active)) continue;   // uniform per tile
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         double r2 = 0.0, unused = 0.0;
         double rv[kCPT0];
         long ix[kCPT0];
@@ -2094,7 +2094,7 @@ k_residual(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList j
                 as_global(d.x)[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), r2, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2127,9 +2127,9 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         if (!S[d.sidx].active) continue;
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         double a = 0.0, unused = 0.0;
         const gptr<double> Rg = as_global(d.R);
         const ZArr<MIXED> z(d);
@@ -2144,7 +2144,7 @@ k_cg_rz(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) a += ok[m_] ? rv[m_] * zv[m_] : 0.0;
-        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], a, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), a, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2171,10 +2171,10 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         GridState& g = S[d.sidx];
         if (!g.active) continue;
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
         const double beta = g.beta;
         const int par = g.iter & 1;
@@ -2221,7 +2221,7 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
                 }
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], pq, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), pq, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2250,10 +2250,10 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
     for (int k = order.first(); order.more(k); k += order.per) {
         const int tt = order.tile(k);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         GridState& g = S[d.sidx];
         if (!g.active) continue;
-        const int lt = tt - jl.prefix[jb];
+        const int lt = tt - job_start(jl, jb);
         const bool restart = g.iter == 0;                  // p = z (the old direction is not read)
         const double beta = g.beta;
         const int par = g.iter & 1;
@@ -2342,10 +2342,10 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         GridState& g = S[d.sidx];
         if (!g.active) continue;
-        const int lt = t - jl.prefix[jb];
+        const int lt = t - job_start(jl, jb);
         const double alpha = g.alpha;
         const gptr<double> P = as_global(d.P[g.iter & 1]);
         double r2 = 0.0, unused = 0.0;
@@ -2377,7 +2377,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
                 as_global(d.x)[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, jl.prefix[jb + 1] - jl.prefix[jb], r2, unused, 1, fin, rtol,
+        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), r2, unused, 1, fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2389,13 +2389,13 @@ k_correct(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobL
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
         if (!S[d.sidx].active) continue;
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
             bool ok;
-            const long idx = l0_cell<DIM>(d, t - jl.prefix[jb], m_, i, j, k, ok);
+            const long idx = l0_cell<DIM>(d, t - job_start(jl, jb), m_, i, j, k, ok);
             const double z = MIXED ? (double)as_global(d.x32)[idx] : as_global(d.x)[idx];
             const double v = as_global(d.X)[idx] + z;
             if (ok) as_global(d.X)[idx] = v;
@@ -2410,12 +2410,12 @@ k_output(const LevelDesc* __restrict__ L, JobList jl, const StepIO* __restrict__
     for (int k_ = order.first(); order.more(k_); k_ += order.per) {
         const int t = order.tile(k_);
         const int jb = find_job(jl.prefix, jl.njobs, t);
-        const LevelDesc& d = L[jl.levels[jb]];
+        const LevelDesc& d = L[job_level(jl, jb)];
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
             int i, j, k;
             bool ok;
-            const long idx = l0_cell<DIM>(d, t - jl.prefix[jb], m_, i, j, k, ok);
+            const long idx = l0_cell<DIM>(d, t - job_start(jl, jb), m_, i, j, k, ok);
             const double v = as_global(d.X)[idx];
             if (ok) as_global(io[d.grid].E_out)[idx] = v;
         }

@@ -718,7 +718,7 @@ static int upload_list(Plan& p, HostList& l) {
     FLD_HIP(hipMemcpy(pf, l.prefix.data(), l.prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     int64_t cells = 0;
     for (int32_t li : l.levels) cells += (int64_t)p.levels[li].n[0] * p.levels[li].n[1] * p.levels[li].n[2];
-    l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back(), cells};
+    l.dev = JobList{lv, pf, (int32_t)l.levels.size(), l.prefix.back(), cells, l.levels.empty() ? -1 : l.levels[0], 0};
     return FLD_OK;
 }
 
@@ -766,7 +766,7 @@ static void stage_list(Plan& p, HostList& l, char* img) {
     int64_t cells = 0;
     for (int32_t li : l.levels) cells += (int64_t)p.levels[li].n[0] * p.levels[li].n[1] * p.levels[li].n[2];
     l.dev = JobList{reinterpret_cast<int32_t*>(p.ws + l.off_levels), reinterpret_cast<int32_t*>(p.ws + l.off_prefix),
-                    (int32_t)l.levels.size(), l.prefix.back(), cells};
+                    (int32_t)l.levels.size(), l.prefix.back(), cells, l.levels.empty() ? -1 : l.levels[0], 0};
 }
 
 int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
