@@ -135,7 +135,7 @@ struct GridState {
     double  rnorm2;      // last ||b - A x||^2 (recursive in CG, true after a check)
     double  rprev2;      // best ||r||^2 so far (stagnation test)
     double  tol2;        // rtol^2 ||b||^2
-    double  rho;         // CG: r . z
+    double  rho[2];      // CG: r . z of the iterations of even / odd parity
     double  alpha;       // CG step length
     double  beta;        // CG direction update
     int32_t active;      // 1 while iterations are still needed
@@ -147,6 +147,13 @@ struct GridState {
     int32_t iter;        // CG iterations since the last (re)start
     int32_t done;        // tiles of the running reduction finished so far (last block resets)
 };
+
+// fin argument of k_cg_pq / k_cg_update: every block forms the CG scalar it needs
+// (beta / alpha) from the previous kernel's tile partials itself, in place of a
+// k_finalize launch between the two (grids of up to kFoldMaxTiles level-0 tiles);
+// k_cg_pq then leaves its partials after the r.z ones.
+constexpr int kFinFold = -2;
+constexpr int kFoldMaxTiles = 2048;
 
 // Finalization modes of k_finalize (one block per grid, fixed-order sums).
 enum FinMode : int32_t {
@@ -291,10 +298,12 @@ int prepare_tail(int dim, bool fp32, size_t smem);
 // Tile shapes: wide in {0,1}, fy in {4,8,16,32}, as long as the tile fits the LDS.
 bool fused2_supported(int nu);
 bool fused2_shape_ok(bool fp32, int nu, int wide, int fy, bool down);
+// threads: workgroup size of the fused 2D level kernels, kBlock or 1024 (more waves
+// per tile: shorter per-wave chains on small levels)
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
-                  int wide, int fy, int nblk, hipStream_t s);
+                  int wide, int fy, int threads, int nblk, hipStream_t s);
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
-                int nblk, hipStream_t s);
+                int threads, int nblk, hipStream_t s);
 // Fused 3D sweeps (one red-black sweep per launch, colour c0 first), reading x (or xs
 // with from_xs) and writing the other; modes: 0 from the iterate, 1 from zero, 2 / 3 the
 // same plus restriction of the final residual, 4 from the iterate plus the prolonged

@@ -57,6 +57,7 @@ struct DimLists {
     std::vector<HostList> tail_from, coarsest_from;
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
     bool fin_fused = false;                    // finish reductions in the last block (small grids)
+    bool fold = false;                         // CG scalars formed in the consuming kernels (mid-sized grids)
     HostList pq3;                              // level 0, z-march CG tiles (3D, zero-flux operators)
     int fz_pq = 16;                            // planes per z-march CG tile
     int maxdepth = 0;
@@ -145,6 +146,11 @@ struct Plan {
     int tile_rows = 16;
     int tile_rows_c = 16;                      // fused 2D tile rows below the finest level
     int tile_rows_u = 16;                      // fused 2D tile rows of the finest level's up pass
+    // fused 2D workgroup size: the finest level's tiles are many and bandwidth-bound
+    // (256 threads keep more tiles resident); a coarse level has few tiles, and the
+    // length of each wave's dependent chain sets its time (1024 threads split it)
+    int tile_threads = 256;
+    int tile_threads_c = 1024;
     int nblk = 2048;
     int tile_depth = 32;                       // fused 3D sweep: planes per block
     int ncu = 256;                             // compute units of the plan's device (block balancing)

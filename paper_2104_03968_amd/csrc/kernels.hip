@@ -175,6 +175,19 @@ __device__ __forceinline__ void sum_parts(const double* __restrict__ part, int n
     sum_parts_with([&](int i) { return part[i]; }, ntiles, stride, a, b, sh);
 }
 
+// The CG scalars from a summed reduction: beta = r.z / (previous r.z) (0 on a restart)
+// and alpha = r.z / p.q (0 when p.q is not a positive finite number: breakdown).  The
+// iteration's r.z sits in rho[iter & 1] and the previous one in the other slot, so a
+// kernel whose blocks form these scalars from the partials themselves can record the
+// new r.z in one block while the others still read the previous one.
+__device__ __forceinline__ double cg_beta(const GridState& g, double rz) {
+    const double prev = g.rho[(g.iter + 1) & 1];
+    return (g.iter > 0 && prev != 0.0) ? rz / prev : 0.0;
+}
+__device__ __forceinline__ double cg_alpha(const GridState& g, double pq) {
+    return (pq > 0.0 && isfinite(pq)) ? g.rho[g.iter & 1] / pq : 0.0;
+}
+
 // Stop test / CG scalar update of one grid from the summed partials (thread 0).
 __device__ void finalize_grid(GridState& g, double s2, double s1, int mode, double rtol, int max_cycles) {
     switch (mode) {
@@ -224,14 +237,12 @@ __device__ void finalize_grid(GridState& g, double s2, double s1, int mode, doub
             }
             break;
         case FIN_RZ:
-            g.beta = (g.iter > 0 && g.rho != 0.0) ? s2 / g.rho : 0.0;
-            g.rho = s2;
+            g.beta = cg_beta(g, s2);
+            g.rho[g.iter & 1] = s2;
             break;
         case FIN_PQ:
-            if (s2 > 0.0 && isfinite(s2)) {
-                g.alpha = g.rho / s2;
-            } else {                                 // breakdown: no descent direction left
-                g.alpha = 0.0;
+            g.alpha = cg_alpha(g, s2);
+            if (g.alpha == 0.0) {                    // breakdown: no descent direction left
                 g.active = 0;
                 g.status = (g.rnorm2 <= g.tol2) ? FLD_OK : FLD_ERR_NOT_CONVERGED;
             }
@@ -271,16 +282,17 @@ __device__ __forceinline__ void sum_parts_coherent(const double* part, int ntile
 // the host uses it for grids of a few tiles only.
 __device__ __forceinline__ void tile_reduce_finish(const LevelDesc& d, GridState& g, int lt, int ntiles,
                                                    double a, double b, int stride, int fin, double rtol,
-                                                   int max_cycles, double* sh, int* flag) {
+                                                   int max_cycles, double* sh, int* flag, double* part = nullptr) {
+    if (!part) part = d.part;
     block_sum2<kBlock>(a, b, sh);
     if (threadIdx.x == 0) {
-        d.part[stride * lt] = a;
-        if (stride == 2) d.part[stride * lt + 1] = b;
+        part[stride * lt] = a;
+        if (stride == 2) part[stride * lt + 1] = b;
     }
     if (fin < 0) return;
     if (!grid_tile_done(g, ntiles, flag)) return;
     double s2, s1;
-    sum_parts_coherent(d.part, ntiles, stride, s2, s1, sh);
+    sum_parts_coherent(part, ntiles, stride, s2, s1, sh);
     if (threadIdx.x == 0) finalize_grid(g, s2, s1, fin, rtol, max_cycles);
 }
 
@@ -1237,13 +1249,13 @@ struct Tile2 {
     __device__ T& W1(int li, int lj, int G) { return w1[(li + lj + G) & 1][lj][li >> 1]; }
 };
 
-template <typename Tl>
+template <int NT, typename Tl>
 __device__ __forceinline__ void tile2_half_sweep(Tl& t, int G, int color, int m) {
     // update the cells of `color` with local coordinates in [m, W-m) x [m, H-m)
     constexpr int KW = Tl::KW;
     const int o = color ^ 1;
     const int n = (Tl::H - 2 * m) * KW;
-    for (int e = threadIdx.x; e < n; e += kBlock) {
+    for (int e = threadIdx.x; e < n; e += NT) {
         const int r = e / KW;
         const int k = e - r * KW;
         const int lj = m + r;
@@ -1269,7 +1281,7 @@ struct Tile2Regs {
     uint32_t ok;          // bit r: element r lies inside the level
 };
 
-template <typename T, typename Tl, int NE>
+template <typename T, typename Tl, int NE, int NT>
 __device__ __forceinline__ void tile2_fetch(Tile2Regs<T, NE>& v, const LevelDesc& d, const gptr<T> xs, int gx0,
                                             int gy0, bool load_x, const gptr<T> cx, int ncx) {
     static_assert(NE <= 32, "ok mask");
@@ -1280,7 +1292,7 @@ __device__ __forceinline__ void tile2_fetch(Tile2Regs<T, NE>& v, const LevelDesc
     v.ok = 0;
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-        const int e = threadIdx.x + r * kBlock;
+        const int e = threadIdx.x + r * NT;
         const int ec = min(e, W * H - 1);
         const int lj = ec / W, li = ec - lj * W;
         const int gi = gx0 + li, gj = gy0 + lj;
@@ -1298,13 +1310,13 @@ __device__ __forceinline__ void tile2_fetch(Tile2Regs<T, NE>& v, const LevelDesc
 
 // Store fetched operands to the tile (x plus the prolonged coarse correction when
 // add_c); cells outside the level hold x = b = 0 and zero face weights.
-template <typename T, typename Tl, int NE>
+template <typename T, typename Tl, int NE, int NT>
 __device__ __forceinline__ void tile2_put(Tl& t, const Tile2Regs<T, NE>& v, int gx0, int gy0, bool add_c) {
     constexpr int W = Tl::W, H = Tl::H;
     const int G = (gx0 + gy0) & 1;
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-        const int e = threadIdx.x + r * kBlock;
+        const int e = threadIdx.x + r * NT;
         if (e < W * H) {
             const int lj = e / W, li = e - lj * W;
             const bool ok = (v.ok >> r) & 1u;
@@ -1343,27 +1355,27 @@ __device__ __forceinline__ Tile2Job tile2_job(const LevelDesc* __restrict__ L, c
     return j;
 }
 
-template <typename T, int NU, int WIDE, int FY>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int NU, int WIDE, int FY, int NT>
+__global__ void __launch_bounds__(NT)
 k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int load_x) {
     constexpr int HALO = 2 * NU + 1;
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
-    constexpr int NE = (Tl::W * Tl::H + kBlock - 1) / kBlock;
+    constexpr int NE = (Tl::W * Tl::H + NT - 1) / NT;
     __shared__ Tl t;
     const XcdOrder order(jl.total);
     int k = order.first();
     if (!order.more(k)) return;
     Tile2Job cj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(k));
     Tile2Regs<T, NE> v;
-    tile2_fetch<T, Tl, NE>(v, *cj.d, as_global(Arr<T>::x(*cj.d)), cj.gx0, cj.gy0, load_x != 0, nullptr, 0);
+    tile2_fetch<T, Tl, NE, NT>(v, *cj.d, as_global(Arr<T>::x(*cj.d)), cj.gx0, cj.gy0, load_x != 0, nullptr, 0);
     // the current tile's job, kept in scalars (an aggregate copied across iterations
     // would be placed in LDS by the compiler)
     const LevelDesc* cd = cj.d;
     const LevelDesc* cc = cj.c;
     int cgx = cj.gx0, cgy = cj.gy0, cact = cj.act ? 1 : 0;
     while (true) {
-        if (cact) tile2_put<T, Tl, NE>(t, v, cgx, cgy, false);
+        if (cact) tile2_put<T, Tl, NE, NT>(t, v, cgx, cgy, false);
         // the next tile's loads are in flight while this one is swept
         const int kn = k + order.per;
         const bool more = order.more(kn);
@@ -1377,7 +1389,7 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
             ngx = nj.gx0;
             ngy = nj.gy0;
             nact = nj.act ? 1 : 0;
-            tile2_fetch<T, Tl, NE>(v, *nd, as_global(Arr<T>::x(*nd)), ngx, ngy, load_x != 0, nullptr, 0);
+            tile2_fetch<T, Tl, NE, NT>(v, *nd, as_global(Arr<T>::x(*nd)), ngx, ngy, load_x != 0, nullptr, 0);
         }
         if (cact) {
             const LevelDesc& d = *cd;
@@ -1385,19 +1397,19 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
             const int gx0 = cgx, gy0 = cgy;
             const int G = (gx0 + gy0) & 1;
             for (int it = 0; it < NU; ++it) {
-                tile2_half_sweep(t, G, 0, 2 * it + 1);
-                tile2_half_sweep(t, G, 1, 2 * it + 2);
+                tile2_half_sweep<NT>(t, G, 0, 2 * it + 1);
+                tile2_half_sweep<NT>(t, G, 1, 2 * it + 2);
             }
             // smoothed iterate of the interior (to xs: other tiles may still read x), and the
             // residual averaged onto the coarse cells
             const gptr<T> xo = as_global(Arr<T>::xs(d));
-            for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+            for (int e = threadIdx.x; e < FX * FY; e += NT) {
                 const int lj = e / FX, li = e - lj * FX;
                 const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
                 if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
             }
             const gptr<T> cb = as_global(Arr<T>::b(cL));
-            for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += kBlock) {
+            for (int e = threadIdx.x; e < (FX / 2) * (FY / 2); e += NT) {
                 const int cj_ = e / (FX / 2), ci = e - cj_ * (FX / 2);
                 const int CI = (gx0 + HALO) / 2 + ci, CJ = (gy0 + HALO) / 2 + cj_;
                 if (CI < cL.n[0] && CJ < cL.n[1]) {
@@ -1426,13 +1438,13 @@ k_down2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLis
     }
 }
 
-template <typename T, int NU, int WIDE, int FY>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int NU, int WIDE, int FY, int NT>
+__global__ void __launch_bounds__(NT)
 k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl) {
     constexpr int HALO = 2 * NU;
     constexpr int FX = fused_fx(HALO, WIDE);
     using Tl = Tile2<T, FX + 2 * HALO, FY + 2 * HALO>;
-    constexpr int NE = (Tl::W * Tl::H + kBlock - 1) / kBlock;
+    constexpr int NE = (Tl::W * Tl::H + NT - 1) / NT;
     __shared__ Tl t;
     const XcdOrder order(jl.total);
     int k = order.first();
@@ -1440,12 +1452,12 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
     // the down pass's iterate plus the prolonged coarse correction
     Tile2Job cj = tile2_job<FX, FY, HALO>(L, S, jl, order.tile(k));
     Tile2Regs<T, NE> v;
-    tile2_fetch<T, Tl, NE>(v, *cj.d, as_global(Arr<T>::xs(*cj.d)), cj.gx0, cj.gy0, true,
+    tile2_fetch<T, Tl, NE, NT>(v, *cj.d, as_global(Arr<T>::xs(*cj.d)), cj.gx0, cj.gy0, true,
                            as_global(Arr<T>::x(*cj.c)), cj.c->n[0]);
     const LevelDesc* cd = cj.d;
     int cgx = cj.gx0, cgy = cj.gy0, cact = cj.act ? 1 : 0;
     while (true) {
-        if (cact) tile2_put<T, Tl, NE>(t, v, cgx, cgy, true);
+        if (cact) tile2_put<T, Tl, NE, NT>(t, v, cgx, cgy, true);
         const int kn = k + order.per;
         const bool more = order.more(kn);
         const LevelDesc* nd = cd;
@@ -1456,7 +1468,7 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
             ngx = nj.gx0;
             ngy = nj.gy0;
             nact = nj.act ? 1 : 0;
-            tile2_fetch<T, Tl, NE>(v, *nd, as_global(Arr<T>::xs(*nd)), ngx, ngy, true,
+            tile2_fetch<T, Tl, NE, NT>(v, *nd, as_global(Arr<T>::xs(*nd)), ngx, ngy, true,
                                    as_global(Arr<T>::x(*nj.c)), nj.c->n[0]);
         }
         if (cact) {
@@ -1464,11 +1476,11 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
             const int gx0 = cgx, gy0 = cgy;
             const int G = (gx0 + gy0) & 1;
             for (int it = 0; it < NU; ++it) {
-                tile2_half_sweep(t, G, 1, 2 * it + 1);
-                tile2_half_sweep(t, G, 0, 2 * it + 2);
+                tile2_half_sweep<NT>(t, G, 1, 2 * it + 1);
+                tile2_half_sweep<NT>(t, G, 0, 2 * it + 2);
             }
             const gptr<T> xo = as_global(Arr<T>::x(d));
-            for (int e = threadIdx.x; e < FX * FY; e += kBlock) {
+            for (int e = threadIdx.x; e < FX * FY; e += NT) {
                 const int lj = e / FX, li = e - lj * FX;
                 const int gi = gx0 + HALO + li, gj = gy0 + HALO + lj;
                 if (gi < d.n[0] && gj < d.n[1]) xo[gi + (long)d.n[0] * gj] = t.X(HALO + li, HALO + lj, G);
@@ -2175,54 +2187,82 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         GridState& g = S[d.sidx];
         if (!g.active) continue;
         const int lt = t - job_start(jl, jb);
+        const int nt = job_tiles(jl, jb);
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
-        const double beta = g.beta;
         const int par = g.iter & 1;
         const gptr<double> Pn = as_global(d.P[par]);
         const gptr<double> Po = as_global(d.P[par ^ 1]);
+        const gptr<double> Qg = as_global(d.Q);
+        const gptr<double> AD = as_global(d.ad);
         const ZArr<MIXED> z(d);
-        double pq = 0.0, unused = 0.0;
-#pragma unroll 1
+        const gptr<double> wa[3] = {as_global(d.w[0]), as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0])};
+        const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+        const int pm = d.per_mask;
+        // every operand of the tile is loaded first (the loads of a clamped cell are issued
+        // unconditionally; a boundary neighbour is the cell itself, with weight 0, so
+        // pc - pc adds exactly zero), so their latency overlaps the folded reduction below
+        constexpr int NB = 2 * DIM;
+        double zc[kCPT0], poc[kCPT0], av[kCPT0], zn[kCPT0][NB], pon[kCPT0][NB], wn[kCPT0][NB];
+        long ix[kCPT0];
+        bool ok[kCPT0];
+#pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
-            int i, j, k;
-            bool ok;
-            const long idx = l0_cell<DIM>(d, lt, m_, i, j, k, ok);     // loads of a clamped cell are
-            {                                                             // issued unconditionally
-                const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
-                auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
-                // every neighbour load is issued (from the cell itself across the boundary,
-                // with weight 0: pc - pc adds exactly zero)
-                const double pc = p_at(idx);
-                const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
-                double wl, pl, wr, pr, wd, pd, wu, pu;
-                const int pm = d.per_mask;
-                nb_p(w0, idx, i, d.n[0], 1, pm & 1, false, p_at, wl, pl);
-                nb_p(w0, idx, i, d.n[0], 1, pm & 1, true, p_at, wr, pr);
-                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, false, p_at, wd, pd);
-                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, true, p_at, wu, pu);
-                double q = pc;
-                q += wl * (pc - pl);
-                q += wr * (pc - pr);
-                q += wd * (pc - pd);
-                q += wu * (pc - pu);
-                if (DIM == 3) {
-                    const gptr<double> w2 = as_global(d.w[2]);
-                    double wb, pb, wf, pf;
-                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, false, p_at, wb, pb);
-                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, true, p_at, wf, pf);
-                    q += wb * (pc - pb);
-                    q += wf * (pc - pf);
-                }
-                if (d.ad) q += as_global(d.ad)[idx] * pc;
-                if (ok) {
-                    Pn[idx] = pc;
-                    as_global(d.Q)[idx] = q;
-                    pq += pc * q;
-                }
+            int c3[3];
+            ix[m_] = l0_cell<DIM>(d, lt, m_, c3[0], c3[1], c3[2], ok[m_]);
+            const long idx = ix[m_];
+            zc[m_] = z[idx];
+            poc[m_] = restart ? 0.0 : Po[idx];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {                       // x-, x+, y-, y+, z-, z+
+                const int a = q >> 1;
+                const bool upper = (q & 1) != 0;
+                const long st = a == 0 ? 1 : (a == 1 ? sy : sz);
+                const int n = d.n[a], i = c3[a];
+                const bool per = ((pm >> a) & 1) != 0;
+                const bool has = upper ? (i + 1 < n || per) : (i > 0 || per);
+                const long nb = upper ? (i + 1 < n ? idx + st : (per ? idx - (long)(n - 1) * st : idx))
+                                      : (i > 0 ? idx - st : (per ? idx + (long)(n - 1) * st : idx));
+                const double wv = wa[a][upper ? nb : idx];
+                wn[m_][q] = has ? wv : 0.0;
+                zn[m_][q] = z[nb];
+                pon[m_][q] = restart ? 0.0 : Po[nb];
+            }
+            av[m_] = d.ad ? AD[idx] : 0.0;
+        }
+        double beta;
+        if (fin == kFinFold) {
+            // r.z from k_cg_rz's tile partials, summed here in k_finalize's order; the
+            // grid's first tile records it (rho of this iteration's parity, beta)
+            double rz, unused_;
+            sum_parts(d.part, nt, 1, rz, unused_, sh);
+            beta = cg_beta(g, rz);
+            if (lt == 0 && threadIdx.x == 0) {
+                g.rho[par] = rz;
+                g.beta = beta;
+            }
+        } else {
+            beta = g.beta;
+        }
+        double pq = 0.0, unused = 0.0;
+#pragma unroll
+        for (int m_ = 0; m_ < kCPT0; ++m_) {
+            const double pc = restart ? zc[m_] : zc[m_] + beta * poc[m_];
+            double q = pc;
+#pragma unroll
+            for (int qq = 0; qq < NB; ++qq) {
+                const double pnb = restart ? zn[m_][qq] : zn[m_][qq] + beta * pon[m_][qq];
+                q += wn[m_][qq] * (pc - pnb);
+            }
+            if (d.ad) q += av[m_] * pc;
+            if (ok[m_]) {
+                Pn[ix[m_]] = pc;
+                Qg[ix[m_]] = q;
+                pq += pc * q;
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), pq, unused, 1, fin, rtol,
-                           max_cycles, sh, &flag);
+        // folded: p.q partials after the r.z ones (k_cg_update sums them)
+        tile_reduce_finish(d, g, lt, nt, pq, unused, 1, fin == kFinFold ? -1 : fin, rtol, max_cycles, sh, &flag,
+                           fin == kFinFold ? d.part + g.ntiles0 : d.part);
     }
 }
 
@@ -2346,7 +2386,6 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
         GridState& g = S[d.sidx];
         if (!g.active) continue;
         const int lt = t - job_start(jl, jb);
-        const double alpha = g.alpha;
         const gptr<double> P = as_global(d.P[g.iter & 1]);
         double r2 = 0.0, unused = 0.0;
         const gptr<double> X = as_global(d.X), R = as_global(d.R), Q = as_global(d.Q);
@@ -2361,6 +2400,24 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
             pv[m_] = P[ix[m_]];
             rv[m_] = R[ix[m_]];
             qv[m_] = Q[ix[m_]];
+        }
+        double alpha;
+        if (fin == kFinFold) {
+            // p . q from k_cg_pq's partials (after the r.z ones), summed in k_finalize's
+            // order; the grid's first tile records alpha (and a breakdown ends the grid)
+            double pq, unused_;
+            sum_parts(d.part + g.ntiles0, job_tiles(jl, jb), 1, pq, unused_, sh);
+            alpha = cg_alpha(g, pq);
+            if (lt == 0 && threadIdx.x == 0) {
+                g.alpha = alpha;
+                if (alpha == 0.0) {
+                    g.active = 0;
+                    g.status = (g.rnorm2 <= g.tol2) ? FLD_OK : FLD_ERR_NOT_CONVERGED;
+                }
+            }
+            if (alpha == 0.0) continue;              // uniform per tile
+        } else {
+            alpha = g.alpha;
         }
 #pragma unroll
         for (int m_ = 0; m_ < kCPT0; ++m_) {
@@ -2377,7 +2434,7 @@ k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList 
                 as_global(d.x)[idx] = 0.0;
             }
         }
-        tile_reduce_finish(d, S[d.sidx], lt, job_tiles(jl, jb), r2, unused, 1, fin, rtol,
+        tile_reduce_finish(d, g, lt, job_tiles(jl, jb), r2, unused, 1, fin == kFinFold ? -1 : fin, rtol,
                            max_cycles, sh, &flag);
     }
 }
@@ -2753,39 +2810,47 @@ namespace {
 // Instantiates a fused kernel only for shapes whose tile fits the LDS; the host
 // never selects the others (fused2_shape_ok).
 template <typename T, int NU, int WIDE, int FY>
-void down2_t(const LevelDesc* L, const GridState* S, JobList jl, int load_x, int g, hipStream_t s) {
-    if constexpr (fused_lds(sizeof(T), 2 * NU + 1, WIDE, FY) <= kFusedLdsMax)
-        hipLaunchKernelGGL((k_down2<T, NU, WIDE, FY>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
+void down2_t(const LevelDesc* L, const GridState* S, JobList jl, int load_x, int threads, int g, hipStream_t s) {
+    if constexpr (fused_lds(sizeof(T), 2 * NU + 1, WIDE, FY) <= kFusedLdsMax) {
+        if (threads == 1024)
+            hipLaunchKernelGGL((k_down2<T, NU, WIDE, FY, 1024>), dim3(g), dim3(1024), 0, s, L, S, jl, load_x);
+        else
+            hipLaunchKernelGGL((k_down2<T, NU, WIDE, FY, kBlock>), dim3(g), dim3(kBlock), 0, s, L, S, jl, load_x);
+    }
 }
 template <typename T, int NU, int WIDE, int FY>
-void up2_t(const LevelDesc* L, const GridState* S, JobList jl, int g, hipStream_t s) {
-    if constexpr (fused_lds(sizeof(T), 2 * NU, WIDE, FY) <= kFusedLdsMax)
-        hipLaunchKernelGGL((k_up2<T, NU, WIDE, FY>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+void up2_t(const LevelDesc* L, const GridState* S, JobList jl, int threads, int g, hipStream_t s) {
+    if constexpr (fused_lds(sizeof(T), 2 * NU, WIDE, FY) <= kFusedLdsMax) {
+        if (threads == 1024)
+            hipLaunchKernelGGL((k_up2<T, NU, WIDE, FY, 1024>), dim3(g), dim3(1024), 0, s, L, S, jl);
+        else
+            hipLaunchKernelGGL((k_up2<T, NU, WIDE, FY, kBlock>), dim3(g), dim3(kBlock), 0, s, L, S, jl);
+    }
 }
 }  // namespace
 
 void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int load_x,
-                  int wide, int fy, int nblk, hipStream_t s) {
+                  int wide, int fy, int threads, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     // b and two face arrays read (+ x when it starts from the iterate), xs written,
     // coarse b and x written
     if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (4.0 + (load_x ? 1.0 : 0.0) + 2.0 / 4.0))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
-        if (fp32) down2_t<float, NU, WIDE, FY>(L, S, jl, load_x, g, s);
-        else down2_t<double, NU, WIDE, FY>(L, S, jl, load_x, g, s);
+        if (fp32) down2_t<float, NU, WIDE, FY>(L, S, jl, load_x, threads, g, s);
+        else down2_t<double, NU, WIDE, FY>(L, S, jl, load_x, threads, g, s);
     }));
 }
 
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
-                int nblk, hipStream_t s) {
+                int threads, int nblk, hipStream_t s) {
     if (jl.total <= 0) return;
     // xs, b, two face arrays and the coarse correction read, x written
     if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) * (5.0 + 1.0 / 4.0))) return;
     const int g = blocks_for_xcd(jl.total, nblk);
     FLD_NU_DISPATCH(nu, FLD_SHAPE_DISPATCH(wide, fy, {
-        if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, g, s);
-        else up2_t<double, NU, WIDE, FY>(L, S, jl, g, s);
+        if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, threads, g, s);
+        else up2_t<double, NU, WIDE, FY>(L, S, jl, threads, g, s);
     }));
 }
 

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <string>
 #include <vector>
@@ -314,11 +315,14 @@ static void build_lists(Plan& p) {
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
             max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
         D.fin_fused = max_tiles <= 32;
+        // mid-sized grids: k_cg_pq and k_cg_update form beta and alpha from the partials
+        // themselves (each block reads every partial of its grid: only for few tiles)
+        D.fold = !D.fin_fused && max_tiles <= kFoldMaxTiles;
         // 3D grids with zero-flux operators (no Dirichlet couplings, no wrapped neighbours)
         // run the CG direction update as a z-march; its plane depth balances the blocks
         // over the compute units (rounds of one block per unit, fz + 2 steps each)
         D.pq3.prefix.assign(1, 0);
-        if (D.dim == 3 && !p.nb_bc() && !D.fin_fused && !D.l0_cell.empty()) {
+        if (D.dim == 3 && !p.nb_bc() && !D.fin_fused && !D.fold && !D.l0_cell.empty()) {
             int64_t best = -1;
             for (int fz : {8, 16, 32, 64}) {
                 int64_t tiles = 0;
@@ -570,7 +574,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         }
         if (D.fused) {
             launch_down2(f32, p.dL, p.dS, D.down2[d].dev, nu1, d == d0 ? load0 : 0, p.tile_wide,
-                         d == 0 ? p.tile_rows : p.tile_rows_c, p.nblk, s);
+                         d == 0 ? p.tile_rows : p.tile_rows_c, d == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
             continue;
         }
         for (int it = 0; it < nu1; ++it) {
@@ -591,7 +595,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         }
         if (D.fused) {
             launch_up2(f32, p.dL, p.dS, D.up2[d].dev, nu2, p.tile_wide, d == 0 ? p.tile_rows_u : p.tile_rows_c,
-                       p.nblk, s);
+                       d == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
             continue;
         }
         launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
@@ -666,17 +670,21 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             const double rt = p.opts.rtol;
             const int mc = p.opts.max_cycles;
             const bool ff = D.fin_fused;
+            // the r.z and p.q reductions finish in the last tile's block (few tiles), in the
+            // next kernel's blocks (D.fold), or in a k_finalize launch
+            const bool fin_launch = !ff && !D.fold;
             launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
-            if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
+            if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
             if (!D.pq3.empty()) {
                 launch_cg_pq3(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, cell_blocks(p), s);
                 launch_finalize(p.dL, p.dS, D.pq3.dev, FIN_PQ, rt, mc, s);
             } else {
-                launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : -1, rt, mc, cell_blocks(p), s);
-                if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
-            }
-            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : -1, rt, mc, level0_reads_iterate(p, D) ? 1 : 0,
+                launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : (D.fold ? kFinFold : -1), rt, mc,
                              cell_blocks(p), s);
+                if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_PQ, rt, mc, s);
+            }
+            launch_cg_update(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_CG : (D.fold ? kFinFold : -1), rt, mc,
+                             level0_reads_iterate(p, D) ? 1 : 0, cell_blocks(p), s);
             if (!ff) launch_finalize(p.dL, p.dS, l0, FIN_CG, rt, mc, s);
         } else {
             if (p.mixed) launch_correct(dim, true, p.dL, p.dS, l0, cell_blocks(p), s);
@@ -1285,13 +1293,13 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
                                                              level == 0 ? p.opts.nu1 : p.nuc1, 0,
                                                              p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
-                                                             p.nblk, s);
+                                                             level == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
                                                          level == 0 ? p.opts.nu2 : p.nuc2,
                                                          p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
-                                                         p.nblk, s);
+                                                         level == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
                     break;
                 case FLD_KERNEL_SWEEP3:
                     if (has_level && D.fused3)
