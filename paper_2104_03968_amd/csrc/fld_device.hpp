@@ -29,6 +29,7 @@ constexpr int kCoarseMaxLDS = kCoarseThreads * kCoarseCPT;   // 4096 cells
 constexpr int kTailThreads = 512;
 constexpr int kTailCPT = 4;
 constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
+constexpr int kTailWaveCells = 256;                         // tail levels run by one wavefront
 
 // Tile counts of one level for the two tilings (host and device agree on these).
 __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {

@@ -81,15 +81,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Barrier of the NT threads that run a phase: the workgroup, or for NT = 64 the one
+// wavefront (its LDS operations complete in order; the fences keep the compiler from
+// moving memory accesses across the phase boundary).
+template <int NT>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (NT == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Deterministic block sum of two values; every thread receives the totals.
 template <int NT>
 __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
     a = wave_sum(a);
     b = wave_sum(b);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();                       // sh may still be read from a previous call
+    group_sync<NT>();                      // sh may still be read from a previous call
     if (lane == 0) { sh[2 * wid] = a; sh[2 * wid + 1] = b; }
-    __syncthreads();
+    group_sync<NT>();
     double sa = 0.0, sb = 0.0;
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
@@ -999,7 +1013,7 @@ __device__ __forceinline__ void block_rbgs(const int32_t n[3], const T* w0, cons
             p_sh[c] = warm ? x[c] : T(0);
         }
     }
-    __syncthreads();
+    group_sync<NT>();
     double rr0 = -1.0;
     for (int it = 0; it < 4 * maxit; ++it) {
         for (int color = 0; color < 2; ++color) {
@@ -1012,7 +1026,7 @@ __device__ __forceinline__ void block_rbgs(const int32_t n[3], const T* w0, cons
                     p_sh[c] += (b[c] - ax) * dinv[m];
                 }
             }
-            __syncthreads();
+            group_sync<NT>();
         }
         if ((it & 7) == 7 || it == 0) {
             double rr = 0.0, unused = 0.0;
@@ -1035,7 +1049,7 @@ __device__ __forceinline__ void block_rbgs(const int32_t n[3], const T* w0, cons
         const int c = threadIdx.x + m * NT;
         if (c < ncell) x[c] = p_sh[c];
     }
-    __syncthreads();
+    group_sync<NT>();
 }
 
 // Block-wide Jacobi-preconditioned CG on one level of up to NT * CPT cells.
@@ -1069,7 +1083,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
             p_sh[c] = xr[m];
         }
     }
-    __syncthreads();
+    group_sync<NT>();
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = threadIdx.x + m * NT;
@@ -1079,7 +1093,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
             if (warm) r[m] -= apply_at<DIM, T>(p_sh, w0, w1, w2, n, c, dg, a, has_a, pm);
         }
     }
-    __syncthreads();
+    group_sync<NT>();
     double rz = 0.0, rr0 = 0.0;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -1130,7 +1144,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
                 const int c = threadIdx.x + m * NT;
                 if (c < ncell) p_sh[c] = r[m] * dinv[m] + beta * p_sh[c];
             }
-            __syncthreads();
+            group_sync<NT>();
         }
     }
 #pragma unroll
@@ -1138,7 +1152,7 @@ __device__ __forceinline__ void block_cg(const int32_t n[3], const T* w0, const 
         const int c = threadIdx.x + m * NT;
         if (c < ncell) x[c] = xr[m];
     }
-    __syncthreads();
+    group_sync<NT>();
 }
 
 template <int DIM, typename T>
@@ -1815,12 +1829,12 @@ __device__ __forceinline__ void tl_coords(const TailLevel<T>& lv, int c, int& i,
 
 // Levels are passed by value: a copy in registers, since the LDS stores of a phase
 // could otherwise alias the descriptor table in LDS and force its re-reading.
-template <int DIM, typename T, bool BC>
+template <int DIM, typename T, bool BC, int NT>
 __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) {
     const int pmask = BC ? lv.pm : 0;
     const int sy = lv.n[0], sz = lv.n[0] * lv.n[1];
     const int rows = lv.n[1] * lv.n[2];
-    for (int m = threadIdx.x; m < rows * lv.hx; m += kTailThreads) {
+    for (int m = threadIdx.x; m < rows * lv.hx; m += NT) {
         const int r = fdiv(m, lv.rhx);
         int j = r, k = 0;
         if (DIM == 3) {
@@ -1850,7 +1864,57 @@ __device__ __forceinline__ void tl_half_sweep(const TailLevel<T> lv, int color) 
         if (BC && lv.has_a) dg += lv.a[c];
         lv.x[c] = s / dg;
     }
-    __syncthreads();
+    group_sync<NT>();
+}
+
+// The V-cycle of the tail levels from m0 down (level m0's b set, its x zero or warm),
+// run by NT threads: the workgroup, or one wavefront for small levels.
+template <int DIM, typename T, bool BC, int NT, int CPT>
+__device__ __forceinline__ void tail_vcycle(const TailGeom* tl, T* sbase, int m0, int nl, int nu1, int nu2, T* p_sh,
+                                            double* red) {
+    // descend
+    for (int m = m0; m + 1 < nl; ++m) {
+        const TailLevel<T> f = tl_at(tl[m], sbase);
+        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
+        for (int it = 0; it < nu1; ++it) {
+            tl_half_sweep<DIM, T, BC, NT>(f, 0);
+            tl_half_sweep<DIM, T, BC, NT>(f, 1);
+        }
+        for (int c = threadIdx.x; c < cT.ncell; c += NT) {
+            int I, J, K;
+            tl_coords<DIM, T>(cT, c, I, J, K);
+            T sum = T(0);
+#pragma unroll
+            for (int q = 0; q < (1 << DIM); ++q)
+                sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
+                                           2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
+                                           BC && f.has_a != 0, BC ? f.pm : 0);
+            cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
+            cT.x[c] = T(0);
+        }
+        group_sync<NT>();
+    }
+    // coarsest: CG from the current x (zero unless the grid has a single level)
+    {
+        const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
+        block_cg<DIM, T, NT, CPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red, cT.a,
+                                  BC && cT.has_a != 0, BC ? cT.pm : 0);
+    }
+    // ascend
+    for (int m = nl - 2; m >= m0; --m) {
+        const TailLevel<T> f = tl_at(tl[m], sbase);
+        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
+        for (int c = threadIdx.x; c < f.ncell; c += NT) {
+            int i, j, k;
+            tl_coords<DIM, T>(f, c, i, j, k);
+            f.x[c] += cT.x[(i >> 1) + cT.n[0] * ((j >> 1) + cT.n[1] * (k >> 1))];
+        }
+        group_sync<NT>();
+        for (int it = 0; it < nu2; ++it) {
+            tl_half_sweep<DIM, T, BC, NT>(f, 1);
+            tl_half_sweep<DIM, T, BC, NT>(f, 0);
+        }
+    }
 }
 
 // BC: the plan has Dirichlet or periodic faces (extra diagonal, wrapped neighbours).
@@ -1930,47 +1994,56 @@ k_tail(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList
         }
     }
     __syncthreads();
-    // descend
-    for (int m = 0; m + 1 < nl; ++m) {
-        const TailLevel<T> f = tl_at(tl[m], sbase);
-        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
-        for (int it = 0; it < nu1; ++it) {
-            tl_half_sweep<DIM, T, BC>(f, 0);
-            tl_half_sweep<DIM, T, BC>(f, 1);
-        }
-        for (int c = threadIdx.x; c < cT.ncell; c += kTailThreads) {
-            int I, J, K;
-            tl_coords<DIM, T>(cT, c, I, J, K);
-            T sum = T(0);
+    // Levels of at most kTailWaveCells cells run on one wavefront, without workgroup
+    // barriers (they leave most of the block idle anyway): from the first such level
+    // ws down, when the coarsest level has at most 64 cells (the wavefront's CG then
+    // sums its products in the order the whole block would).
+    int ws = nl;
+    if (tl[nl - 1].ncell <= 64) {
+        ws = nl - 1;
+        while (ws > 0 && tl[ws - 1].ncell <= kTailWaveCells) --ws;
+    }
+    if (ws == nl) {
+        tail_vcycle<DIM, T, BC, kTailThreads, kTailCPT>(tl, sbase, 0, nl, nu1, nu2, p_sh, red);
+    } else {
+        // the workgroup smooths and restricts the levels above ws, one wavefront runs
+        // the V-cycle from ws, the workgroup prolongs and smooths back up
+        for (int m = 0; m < ws; ++m) {
+            const TailLevel<T> f = tl_at(tl[m], sbase);
+            const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
+            for (int it = 0; it < nu1; ++it) {
+                tl_half_sweep<DIM, T, BC, kTailThreads>(f, 0);
+                tl_half_sweep<DIM, T, BC, kTailThreads>(f, 1);
+            }
+            for (int c = threadIdx.x; c < cT.ncell; c += kTailThreads) {
+                int I, J, K;
+                tl_coords<DIM, T>(cT, c, I, J, K);
+                T sum = T(0);
 #pragma unroll
-            for (int q = 0; q < (1 << DIM); ++q)
-                sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
-                                           2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
-                                           BC && f.has_a != 0, BC ? f.pm : 0);
-            cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
-            cT.x[c] = T(0);
+                for (int q = 0; q < (1 << DIM); ++q)
+                    sum += residual_at<DIM, T>(f.x, f.b, f.w[0], f.w[1], f.w[2], f.n, 2 * I + (q & 1),
+                                               2 * J + ((q >> 1) & 1), DIM == 3 ? 2 * K + (q >> 2) : 0, f.a,
+                                               BC && f.has_a != 0, BC ? f.pm : 0);
+                cT.b[c] = sum * T(DIM == 3 ? 0.125 : 0.25);
+                cT.x[c] = T(0);
+            }
+            __syncthreads();
         }
+        if (threadIdx.x < 64) tail_vcycle<DIM, T, BC, 64, 1>(tl, sbase, ws, nl, nu1, nu2, p_sh, red);
         __syncthreads();
-    }
-    // coarsest: CG from the current x (zero unless the grid has a single level)
-    {
-        const TailLevel<T> cT = tl_at(tl[nl - 1], sbase);
-        block_cg<DIM, T, kTailThreads, kTailCPT>(cT.n, cT.w[0], cT.w[1], cT.w[2], cT.b, cT.x, true, p_sh, red, cT.a,
-                                                 BC && cT.has_a != 0, BC ? cT.pm : 0);
-    }
-    // ascend
-    for (int m = nl - 2; m >= 0; --m) {
-        const TailLevel<T> f = tl_at(tl[m], sbase);
-        const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
-        for (int c = threadIdx.x; c < f.ncell; c += kTailThreads) {
-            int i, j, k;
-            tl_coords<DIM, T>(f, c, i, j, k);
-            f.x[c] += cT.x[(i >> 1) + cT.n[0] * ((j >> 1) + cT.n[1] * (k >> 1))];
-        }
-        __syncthreads();
-        for (int it = 0; it < nu2; ++it) {
-            tl_half_sweep<DIM, T, BC>(f, 1);
-            tl_half_sweep<DIM, T, BC>(f, 0);
+        for (int m = ws - 1; m >= 0; --m) {
+            const TailLevel<T> f = tl_at(tl[m], sbase);
+            const TailLevel<T> cT = tl_at(tl[m + 1], sbase);
+            for (int c = threadIdx.x; c < f.ncell; c += kTailThreads) {
+                int i, j, k;
+                tl_coords<DIM, T>(f, c, i, j, k);
+                f.x[c] += cT.x[(i >> 1) + cT.n[0] * ((j >> 1) + cT.n[1] * (k >> 1))];
+            }
+            __syncthreads();
+            for (int it = 0; it < nu2; ++it) {
+                tl_half_sweep<DIM, T, BC, kTailThreads>(f, 1);
+                tl_half_sweep<DIM, T, BC, kTailThreads>(f, 0);
+            }
         }
     }
     {
