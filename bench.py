@@ -171,7 +171,11 @@ def measured_traffic(cfg: str, kname: str, launch: dict):
     import hashlib
     src = os.path.join(ROOT, "paper_2104_03968_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    keys = ("tile_rows", "tile_wide", "max_blocks", "tile_depth", "fused3_levels", "tile_rows_coarse", "tile_rows_up")
+    # the launch parameters the dominant kernel's own dispatch depends on
+    keys = {"k_sweep3": ("tile_depth", "max_blocks", "fused3_levels"),
+            "k_up2": ("tile_rows_up", "tile_wide", "max_blocks"),
+            "k_smooth": ("max_blocks",)}.get(kname, ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
+                                                    "fused3_levels", "tile_rows_coarse", "tile_rows_up"))
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("traffic_record: "):
@@ -563,11 +567,7 @@ def main():
 
 def run_cpu_baseline(W, cfg, grids, has_gas):
     """The FP64 oracle on a bounded sample of the workload, on this host's cores."""
-    if cfg == "c3":
-        g0 = W.c3_inputs(160)
-        sample = ("one FLD step of the 3D recipe on a 160^3 grid (one 256^3 step takes the oracle "
-                  "about a minute)")
-    elif cfg == "c4":
+    if cfg == "c4":
         g0 = grids[0]
         sample = f"one FLD step of the first grid of the batch ({g0.E.shape[0]}^2)"
     else:

@@ -55,8 +55,8 @@ extern "C" {
 #define FLD_ERR_UNKNOWN_TICKET  -5
 #define FLD_ERR_HIP             -6   /* a HIP runtime call failed              */
 #define FLD_ERR_NO_WORKSPACE    -7   /* plan has no (or too small) workspace   */
-#define FLD_ERR_UNSUPPORTED     -8   /* option not built (a BC other than zero flux or fixed
-                                        gradient)                                  */
+#define FLD_ERR_UNSUPPORTED     -8   /* option not built (a boundary code other than the
+                                        five FLD_BC_* kinds)                       */
 #define FLD_ERR_SHUTDOWN        -9   /* server is shutting down               */
 
 /* ---- options ------------------------------------------------------------ */
@@ -250,7 +250,9 @@ void fld_gas_default(fld_gas* g);
    hierarchy of each grid (halve every axis while all are even and >= 4), the
    workspace layout and the launch work-lists.  Host only: no device memory
    is allocated.  Errors: INVALID_ARG (null, ngrids < 1, ndim not 2/3, an axis
-   < 2, h <= 0, bad option), UNSUPPORTED (a BC other than zero flux). */
+   < 2, h <= 0, bad option, a periodic axis with one periodic face, continuous
+   faces with krylov = 1), UNSUPPORTED (a boundary code that is not an FLD_BC_*
+   kind). */
 int32_t fld_plan_create(const fld_grid* grids, int32_t ngrids, const fld_opts* opts,
                         fld_plan_t* out);
 int32_t fld_plan_destroy(fld_plan_t plan);
