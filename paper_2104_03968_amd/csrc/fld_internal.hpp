@@ -45,6 +45,7 @@ struct DimLists {
     std::vector<HostList> prolong;             // per depth, cell tiles of the fine level
     std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
     std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
+    std::vector<int> thr_dn, thr_up;           // per depth, workgroup size of those tiles (256 or 1024)
     bool fused = false;
     std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
     std::vector<int> fz_r;                     // per depth, planes per block of the restricting sweep
@@ -146,11 +147,6 @@ struct Plan {
     int tile_rows = 16;
     int tile_rows_c = 16;                      // fused 2D tile rows below the finest level
     int tile_rows_u = 16;                      // fused 2D tile rows of the finest level's up pass
-    // fused 2D workgroup size: the finest level's tiles are many and bandwidth-bound
-    // (256 threads keep more tiles resident); a coarse level has few tiles, and the
-    // length of each wave's dependent chain sets its time (1024 threads split it)
-    int tile_threads = 256;
-    int tile_threads_c = 1024;
     int nblk = 2048;
     int tile_depth = 32;                       // fused 3D sweep: planes per block
     int ncu = 256;                             // compute units of the plan's device (block balancing)

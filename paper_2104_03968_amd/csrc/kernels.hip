@@ -2262,46 +2262,6 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
         const int lt = t - job_start(jl, jb);
         const int nt = job_tiles(jl, jb);
         const bool restart = g.iter == 0;            // p = z (the old direction is not read)
-        const int par = g.iter & 1;
-        const gptr<double> Pn = as_global(d.P[par]);
-        const gptr<double> Po = as_global(d.P[par ^ 1]);
-        const gptr<double> Qg = as_global(d.Q);
-        const gptr<double> AD = as_global(d.ad);
-        const ZArr<MIXED> z(d);
-        const gptr<double> wa[3] = {as_global(d.w[0]), as_global(d.w[1]), as_global(DIM == 3 ? d.w[2] : d.w[0])};
-        const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
-        const int pm = d.per_mask;
-        // every operand of the tile is loaded first (the loads of a clamped cell are issued
-        // unconditionally; a boundary neighbour is the cell itself, with weight 0, so
-        // pc - pc adds exactly zero), so their latency overlaps the folded reduction below
-        constexpr int NB = 2 * DIM;
-        double zc[kCPT0], poc[kCPT0], av[kCPT0], zn[kCPT0][NB], pon[kCPT0][NB], wn[kCPT0][NB];
-        long ix[kCPT0];
-        bool ok[kCPT0];
-#pragma unroll
-        for (int m_ = 0; m_ < kCPT0; ++m_) {
-            int c3[3];
-            ix[m_] = l0_cell<DIM>(d, lt, m_, c3[0], c3[1], c3[2], ok[m_]);
-            const long idx = ix[m_];
-            zc[m_] = z[idx];
-            poc[m_] = restart ? 0.0 : Po[idx];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {                       // x-, x+, y-, y+, z-, z+
-                const int a = q >> 1;
-                const bool upper = (q & 1) != 0;
-                const long st = a == 0 ? 1 : (a == 1 ? sy : sz);
-                const int n = d.n[a], i = c3[a];
-                const bool per = ((pm >> a) & 1) != 0;
-                const bool has = upper ? (i + 1 < n || per) : (i > 0 || per);
-                const long nb = upper ? (i + 1 < n ? idx + st : (per ? idx - (long)(n - 1) * st : idx))
-                                      : (i > 0 ? idx - st : (per ? idx + (long)(n - 1) * st : idx));
-                const double wv = wa[a][upper ? nb : idx];
-                wn[m_][q] = has ? wv : 0.0;
-                zn[m_][q] = z[nb];
-                pon[m_][q] = restart ? 0.0 : Po[nb];
-            }
-            av[m_] = d.ad ? AD[idx] : 0.0;
-        }
         double beta;
         if (fin == kFinFold) {
             // r.z from k_cg_rz's tile partials, summed here in k_finalize's order; the
@@ -2310,27 +2270,56 @@ k_cg_pq(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, 
             sum_parts(d.part, nt, 1, rz, unused_, sh);
             beta = cg_beta(g, rz);
             if (lt == 0 && threadIdx.x == 0) {
-                g.rho[par] = rz;
+                g.rho[g.iter & 1] = rz;
                 g.beta = beta;
             }
         } else {
             beta = g.beta;
         }
+        const int par = g.iter & 1;
+        const gptr<double> Pn = as_global(d.P[par]);
+        const gptr<double> Po = as_global(d.P[par ^ 1]);
+        const ZArr<MIXED> z(d);
         double pq = 0.0, unused = 0.0;
-#pragma unroll
+        // one cell at a time: the stencil loads of all four cells in flight at once need
+        // more registers than the occupancy a large batch's bandwidth wants
+#pragma unroll 1
         for (int m_ = 0; m_ < kCPT0; ++m_) {
-            const double pc = restart ? zc[m_] : zc[m_] + beta * poc[m_];
-            double q = pc;
-#pragma unroll
-            for (int qq = 0; qq < NB; ++qq) {
-                const double pnb = restart ? zn[m_][qq] : zn[m_][qq] + beta * pon[m_][qq];
-                q += wn[m_][qq] * (pc - pnb);
-            }
-            if (d.ad) q += av[m_] * pc;
-            if (ok[m_]) {
-                Pn[ix[m_]] = pc;
-                Qg[ix[m_]] = q;
-                pq += pc * q;
+            int i, j, k;
+            bool ok;
+            const long idx = l0_cell<DIM>(d, lt, m_, i, j, k, ok);     // loads of a clamped cell are
+            {                                                             // issued unconditionally
+                const long sy = d.n[0], sz = (long)d.n[0] * d.n[1];
+                auto p_at = [&](long c) { return restart ? z[c] : z[c] + beta * Po[c]; };
+                // every neighbour load is issued (from the cell itself across the boundary,
+                // with weight 0: pc - pc adds exactly zero)
+                const double pc = p_at(idx);
+                const gptr<double> w0 = as_global(d.w[0]), w1 = as_global(d.w[1]);
+                double wl, pl, wr, pr, wd, pd, wu, pu;
+                const int pm = d.per_mask;
+                nb_p(w0, idx, i, d.n[0], 1, pm & 1, false, p_at, wl, pl);
+                nb_p(w0, idx, i, d.n[0], 1, pm & 1, true, p_at, wr, pr);
+                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, false, p_at, wd, pd);
+                nb_p(w1, idx, j, d.n[1], sy, (pm >> 1) & 1, true, p_at, wu, pu);
+                double q = pc;
+                q += wl * (pc - pl);
+                q += wr * (pc - pr);
+                q += wd * (pc - pd);
+                q += wu * (pc - pu);
+                if (DIM == 3) {
+                    const gptr<double> w2 = as_global(d.w[2]);
+                    double wb, pb, wf, pf;
+                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, false, p_at, wb, pb);
+                    nb_p(w2, idx, k, d.n[2], sz, (pm >> 2) & 1, true, p_at, wf, pf);
+                    q += wb * (pc - pb);
+                    q += wf * (pc - pf);
+                }
+                if (d.ad) q += as_global(d.ad)[idx] * pc;
+                if (ok) {
+                    Pn[idx] = pc;
+                    as_global(d.Q)[idx] = q;
+                    pq += pc * q;
+                }
             }
         }
         // folded: p.q partials after the r.z ones (k_cg_update sums them)

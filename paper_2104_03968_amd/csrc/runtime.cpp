@@ -161,6 +161,8 @@ void finish_fused(const Plan& p, DimLists& D) {
         D.levels3 = 0;
         while (D.levels3 < nd && D.sw3[D.levels3].prefix.back() >= kSweep3MinBlocks) ++D.levels3;
     }
+    D.thr_dn.assign(D.down2.size(), kBlock);
+    D.thr_up.assign(D.up2.size(), kBlock);
     for (size_t dpt = 0; dpt < D.down2.size(); ++dpt) {
         const int n1 = dpt == 0 ? p.opts.nu1 : p.nuc1, n2 = dpt == 0 ? p.opts.nu2 : p.nuc2;
         const int fxd = fused_fx(2 * n1 + 1, p.tile_wide), fxu = fused_fx(2 * n2, p.tile_wide);
@@ -172,6 +174,11 @@ void finish_fused(const Plan& p, DimLists& D) {
         const int rows_up = dpt == 0 ? p.tile_rows_u : p.tile_rows_c;
         for (int32_t li : dn.levels) dn.prefix.push_back(dn.prefix.back() + fused_tiles(p.levels[li].n, fxd, rows));
         for (int32_t li : up.levels) up.prefix.push_back(up.prefix.back() + fused_tiles(p.levels[li].n, fxu, rows_up));
+        // a depth with no more tiles than compute units is bound by each tile's dependent
+        // chain: 1024-thread tiles split it four ways; with more tiles, 256-thread tiles
+        // keep more of them resident
+        D.thr_dn[dpt] = dn.prefix.back() <= p.ncu ? 1024 : kBlock;
+        D.thr_up[dpt] = up.prefix.back() <= p.ncu ? 1024 : kBlock;
     }
 }
 
@@ -315,9 +322,12 @@ static void build_lists(Plan& p) {
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j)
             max_tiles = std::max(max_tiles, D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j]);
         D.fin_fused = max_tiles <= 32;
-        // mid-sized grids: k_cg_pq and k_cg_update form beta and alpha from the partials
-        // themselves (each block reads every partial of its grid: only for few tiles)
-        D.fold = !D.fin_fused && max_tiles <= kFoldMaxTiles;
+        // mid-sized plans: k_cg_pq and k_cg_update form beta and alpha from the partials
+        // themselves (each block reads every partial of its grid: only for few tiles, and
+        // only where launches are latency-bound: no more tiles in all than blocks launched)
+        int64_t all_tiles = 0;
+        for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j) all_tiles += D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j];
+        D.fold = !D.fin_fused && max_tiles <= kFoldMaxTiles && all_tiles <= kCellBlocks;
         // 3D grids with zero-flux operators (no Dirichlet couplings, no wrapped neighbours)
         // run the CG direction update as a z-march; its plane depth balances the blocks
         // over the compute units (rounds of one block per unit, fz + 2 steps each)
@@ -574,7 +584,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         }
         if (D.fused) {
             launch_down2(f32, p.dL, p.dS, D.down2[d].dev, nu1, d == d0 ? load0 : 0, p.tile_wide,
-                         d == 0 ? p.tile_rows : p.tile_rows_c, d == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
+                         d == 0 ? p.tile_rows : p.tile_rows_c, D.thr_dn[d], p.nblk, s);
             continue;
         }
         for (int it = 0; it < nu1; ++it) {
@@ -595,7 +605,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         }
         if (D.fused) {
             launch_up2(f32, p.dL, p.dS, D.up2[d].dev, nu2, p.tile_wide, d == 0 ? p.tile_rows_u : p.tile_rows_c,
-                       d == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
+                       D.thr_up[d], p.nblk, s);
             continue;
         }
         launch_prolong(dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
@@ -1293,13 +1303,13 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
                                                              level == 0 ? p.opts.nu1 : p.nuc1, 0,
                                                              p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
-                                                             level == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
+                                                             D.thr_dn[level], p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
                                                          level == 0 ? p.opts.nu2 : p.nuc2,
                                                          p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
-                                                         level == 0 ? p.tile_threads : p.tile_threads_c, p.nblk, s);
+                                                         D.thr_up[level], p.nblk, s);
                     break;
                 case FLD_KERNEL_SWEEP3:
                     if (has_level && D.fused3)
