@@ -163,7 +163,7 @@ def time_imex(fld, plan, grids, E, eps, rho, kap, gas, stream, reps: int = 5):
     return out
 
 
-def measured_traffic(cfg: str, kname: str, launch: dict):
+def measured_traffic(cfg: str, kname: str, ctype: str, launch: dict):
     """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
     record kept under profiles/ (copy-calibrated), or None when there is no record for this
     workload and launch shape, or kernels.hip has changed since the counters were taken."""
@@ -181,7 +181,7 @@ def measured_traffic(cfg: str, kname: str, launch: dict):
             if not line.startswith("traffic_record: "):
                 continue
             rec = json.loads(line[len("traffic_record: "):])
-            if (rec.get("config") == cfg and rec.get("kernel", "").startswith(kname + "<")
+            if (rec.get("config") == cfg and rec.get("kernel", "").startswith(f"{kname}<{ctype}")
                     and rec.get("kernels_sha256") == sha
                     and all(rec.get("launch", {}).get(k) == launch.get(k) for k in keys)):
                 return float(rec["bytes_per_launch"])
@@ -429,7 +429,8 @@ def run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, steps, warm
         achieved = bpc * cells / (ms * 1e-3) / 1e9
         log(f"bench {cfg}: level-0 {kname} {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg, kname, tuning),
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(cfg, kname, "float" if word == 4 else "double", tuning),
                            "kernel": f"{kname} level 0 ({cells} cells, {bpc} B/cell, {ms * 1e3:.2f} us/launch)"}
         out["vcycle"] = vcycle_bandwidth(fld, plan, stream, max(20, args.profile_reps // 10))
     return out, plan, E, K, st_
