@@ -68,9 +68,9 @@ def parse():
                     help="coarse-level operator of the multigrid hierarchy")
     ap.add_argument("--nu", type=int, nargs=2, default=(2, 2), metavar=("NU1", "NU2"),
                     help="red-black sweeps before and after the coarse correction")
-    ap.add_argument("--nu-coarse", type=int, default=0,
+    ap.add_argument("--nu-coarse", type=int, default=None,
                     help="red-black sweeps before and after the correction on the coarse levels "
-                         "(0 = nu1 and nu2, as on the finest level)")
+                         "(0 = nu1 and nu2, as on the finest level; default: the library's)")
     return ap.parse_args()
 
 
@@ -371,8 +371,9 @@ def run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, steps, warm
     Returns the measurement dict, the plan (open) and the device state."""
     plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids], precision=precision, rtol=1e-10,
                     c=grids[0].c, autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
-                    nu1=args.nu[0], nu2=args.nu[1], nu_coarse=args.nu_coarse, krylov=args.krylov,
-                    **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}))
+                    nu1=args.nu[0], nu2=args.nu[1], krylov=args.krylov,
+                    **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}),
+                    **({} if args.nu_coarse is None else {"nu_coarse": args.nu_coarse}))
     tuning = plan.tuning()
     log(f"bench {cfg}: launch shape {tuning}")
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)

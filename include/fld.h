@@ -188,7 +188,7 @@ typedef struct fld_opts {
     int32_t nu_coarse;    /* red-black sweeps before and after the coarse correction on
                              the levels below the finest, and on every level of a
                              grid small enough to be cycled whole in one LDS block;
-                             0..16, 0 = nu1 before and nu2 after [0].  As for nu1
+                             0..16, 0 = nu1 before and nu2 after [3].  As for nu1
                              and nu2, a count outside 1..3 sends the plan's 2D grids
                              to the per-colour sweeps on every level, the finest
                              included                                              */

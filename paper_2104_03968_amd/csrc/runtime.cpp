@@ -1422,6 +1422,9 @@ void fld_opts_default(fld_opts* o) {
     o->max_cycles = 50;
     o->nu1 = 2;
     o->nu2 = 2;
+    // three sweeps on the coarse levels: about one outer iteration fewer per step, which
+    // pays for the extra sweeps on every benchmark workload
+    o->nu_coarse = 3;
     o->use_graph = 1;
     o->autotune = 0;
     o->krylov = 1;

@@ -39,7 +39,7 @@ def test_defaults():
     assert o.c == 1.0 and o.rtol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.max_cycles == 50
     assert o.limiter == fld.FLD_LIMITER_LP and o.precision == fld.FLD_PREC_FP64
     assert o.fmg == 1 and o.fmg_depths == 2 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
-    assert o.nu_coarse == 0 and o.tile_rows_up == 0
+    assert o.nu_coarse == 3 and o.tile_rows_up == 0
     assert fld.fld_opts_default(coarse_op="galerkin").coarse_op == fld.FLD_COARSE_GALERKIN
     g = fld.fld_gas_default()
     assert g.max_halley == 100 and g.root_rtol == pytest.approx(8.88e-16, rel=1e-2)
@@ -83,7 +83,9 @@ def test_plan_create_validates_options(kw, code):
     (dict(autotune=1, max_blocks=1024), False),
     # an FP64 128-wide, 32-row tile with the nu = 2 halo needs more than the 160 KB of LDS
     (dict(tile_wide=1, tile_rows=32), False), (dict(tile_wide=1, tile_rows=32, precision=1), True),
-    (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1), True),
+    (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1, nu_coarse=1), True),
+    # ... and the default three coarse sweeps' halo does not fit a 32-row coarse tile
+    (dict(tile_wide=1, tile_rows=32, nu1=1, nu2=1), False),
     (dict(tile_wide=1, tile_rows=32, fused=0), True), (dict(tile_depth=16), True),
     (dict(tile_depth=64), True), (dict(tile_depth=24), False), (dict(autotune=1, tile_depth=32), False),
     (dict(fused3_levels=2), True), (dict(fused3_levels=-1), False), (dict(autotune=1, fused3_levels=1), False),

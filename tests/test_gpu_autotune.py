@@ -183,12 +183,12 @@ def test_coarse_sweep_count_has_its_own_cache_record(tmp_path, monkeypatch):
     monkeypatch.setenv("FLD_AUTOTUNE_CACHE", str(cache))
     g = W.random_grid((256, 256), 91300, dt=4e-3)
     fld.Plan([g.E.shape], h=[g.h], autotune=1).close()
-    p = fld.Plan([g.E.shape], h=[g.h], autotune=1, nu_coarse=3)
+    p = fld.Plan([g.E.shape], h=[g.h], autotune=1, nu_coarse=2)
     t = p.tuning()
     assert t["source"] == 1 and t["candidates"] >= 2
     (x,), (st,), rc = _solve(p, [g])
     p.close()
     keys = [line.split("\t")[0] for line in cache.read_text().splitlines()]
     assert len(keys) == 2 and keys[0] != keys[1]
-    (xr,), (sr,), rcr = run_step([g], nu_coarse=3)
+    (xr,), (sr,), rcr = run_step([g], nu_coarse=2)
     assert rc == 0 and rcr == 0 and np.array_equal(x, xr) and st["cycles"] == sr["cycles"]

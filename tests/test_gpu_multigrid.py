@@ -160,13 +160,18 @@ def test_coarse_sweep_count_matches_oracle(nu_coarse, precision, krylov):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_coarse_sweep_count_default_and_batching(precision):
-    """nu_coarse equal to nu1 = nu2 is the default bit for bit, and a batch with
-    nu_coarse = 3 gives each grid what it gives alone."""
+    """Three coarse sweeps are the default bit for bit, nu_coarse = 0 is nu1 = nu2 on every
+    level bit for bit, and a batch with nu_coarse = 3 gives each grid what it gives alone."""
     grids = _batch()
     x0, _, rc0 = run_step(grids, precision=precision)
-    x2, _, rc2 = run_step(grids, precision=precision, nu_coarse=2)
-    assert rc0 == 0 and rc2 == 0
-    for a, b in zip(x0, x2):
+    x3, _, rc3 = run_step(grids, precision=precision, nu_coarse=3)
+    assert rc0 == 0 and rc3 == 0
+    for a, b in zip(x0, x3):
+        assert np.array_equal(a, b)
+    y0, _, rcy0 = run_step(grids, precision=precision, nu_coarse=0)
+    y2, _, rcy2 = run_step(grids, precision=precision, nu_coarse=2)
+    assert rcy0 == 0 and rcy2 == 0
+    for a, b in zip(y0, y2):
         assert np.array_equal(a, b)
     xs, _, rc = run_step(grids, precision=precision, nu_coarse=3)
     assert rc == 0
