@@ -172,7 +172,7 @@ def measured_traffic(cfg: str, kname: str, ctype: str, launch: dict):
     src = os.path.join(ROOT, "paper_2104_03968_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     # the launch parameters the dominant kernel's own dispatch depends on
-    keys = {"k_sweep3": ("tile_depth", "max_blocks", "fused3_levels"),
+    keys = {"k_sweep3": ("tile_depth", "max_blocks"),
             "k_up2": ("tile_rows_up", "tile_wide", "max_blocks"),
             "k_smooth": ("max_blocks",)}.get(kname, ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
                                                     "fused3_levels", "tile_rows_coarse", "tile_rows_up"))

@@ -49,6 +49,7 @@ struct DimLists {
     bool fused = false;
     std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
     std::vector<int> fz_r;                     // per depth, planes per block of the restricting sweep
+    std::vector<int> fz_s;                     // per depth, planes per block of the plain sweeps
     bool fused3 = false;                       // fused 3D sweeps available (lists and xs laid out)
     int levels3 = 0;                           // leading depths that run fused sweeps
     HostList coarsest;                         // coarsest level of grids without a tail

@@ -120,7 +120,6 @@ int tiles_l0(const LevelDesc& d) { return l0_tiles(d.n); }
 int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
 
-constexpr int kSweep3MinBlocks = 256;
 
 // Workgroup cap of the level-0 cell kernels (coefficients, residual, CG vectors,
 // output, moments): streaming passes with a reduction per tile, which gain from
@@ -132,34 +131,42 @@ inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
 // plan's launch shape.
 void finish_fused(const Plan& p, DimLists& D) {
     D.fz_r.assign(D.sw3.size(), p.tile_depth);
+    D.fz_s.assign(D.sw3.size(), p.tile_depth);
+    // blocks run in rounds of one per compute unit, each round as long as a block's march
+    // (fz planes plus its halo steps): the plane depth that needs the fewest block steps
+    auto rounds = [&](const HostList& l, bool restr, int fz) {
+        int64_t tiles = 0;
+        for (int32_t li : l.levels) tiles += sweep3_tiles(p.levels[li].n, restr, fz);
+        return ((tiles + p.ncu - 1) / p.ncu) * (fz + (restr ? 6 : 4));
+    };
     for (size_t dpt = 0; dpt < D.sw3.size(); ++dpt) {
         HostList& a = D.sw3[dpt];
         HostList& r = D.sr3[dpt];
+        // the finest depth's plain sweep marches the tuned depth; a coarser depth's, and
+        // every restricting sweep (its narrower window makes more blocks), the depth of
+        // fewest block steps among 8 .. 64 planes (the tuned depth on a tie)
+        if (dpt > 0)
+            for (int fz : {8, 16, 32, 64})
+                if (rounds(a, false, fz) < rounds(a, false, D.fz_s[dpt])) D.fz_s[dpt] = fz;
+        for (int fz : {8, 16, 32, 64})
+            if (rounds(r, true, fz) < rounds(r, true, D.fz_r[dpt])) D.fz_r[dpt] = fz;
         a.prefix.assign(1, 0);
         r.prefix.assign(1, 0);
         for (int32_t li : a.levels)
-            a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, false, p.tile_depth));
-        // the restricting sweep's narrower window makes more blocks: march twice as deep
-        // when that needs fewer block steps per compute unit (blocks run in rounds of one
-        // per compute unit, each round as long as a block's fz + 6 steps)
-        auto rounds = [&](int fz) {
-            int64_t tiles = 0;
-            for (int32_t li : r.levels) tiles += sweep3_tiles(p.levels[li].n, true, fz);
-            return ((tiles + p.ncu - 1) / p.ncu) * (fz + 6);
-        };
-        if (2 * p.tile_depth <= 64 && rounds(2 * p.tile_depth) < rounds(p.tile_depth)) D.fz_r[dpt] = 2 * p.tile_depth;
+            a.prefix.push_back(a.prefix.back() + sweep3_tiles(p.levels[li].n, false, D.fz_s[dpt]));
         for (int32_t li : r.levels)
             r.prefix.push_back(r.prefix.back() + sweep3_tiles(p.levels[li].n, true, D.fz_r[dpt]));
     }
     // a fused sweep marches through its planes in sequence, so a level needs many blocks
-    // to fill the chip: by default only the leading depths with at least one block per
-    // compute unit (kSweep3MinBlocks) run fused, the coarser ones per colour
+    // to fill the chip: by default only the leading depths whose plain sweep has at least
+    // one block per two compute units run fused, the coarser ones per colour (at 256^3 the
+    // two finest, as the autotuner also picks)
     const int nd = (int)D.sw3.size();
     if (p.sweep3_levels > 0) {
         D.levels3 = std::min(p.sweep3_levels, nd);
     } else {
         D.levels3 = 0;
-        while (D.levels3 < nd && D.sw3[D.levels3].prefix.back() >= kSweep3MinBlocks) ++D.levels3;
+        while (D.levels3 < nd && 2 * D.sw3[D.levels3].prefix.back() >= p.ncu) ++D.levels3;
     }
     D.thr_dn.assign(D.down2.size(), kBlock);
     D.thr_up.assign(D.up2.size(), kBlock);
@@ -569,7 +576,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
     // reads x and writes xs when k is odd, the reverse when k is even; nu1 + nu2 is
     // even, so the level's result ends in x
     const int L3 = (D.fused3 && p.sweep3) ? D.levels3 : 0;
-    const int fz = p.tile_depth;
+
     for (int d = d0; d < D.maxdepth; ++d) {
         const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1;
         if (d < L3) {
@@ -578,7 +585,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
                 const bool restr = k == nu1;
                 const int mode = restr ? (load ? 2 : 3) : (load ? 0 : 1);
                 launch_sweep3(f32, p.dL, p.dS, restr ? D.sr3[d].dev : D.sw3[d].dev, mode, 0, k % 2 == 0,
-                              restr ? D.fz_r[d] : fz, p.nblk, s);
+                              restr ? D.fz_r[d] : D.fz_s[d], p.nblk, s);
             }
             continue;
         }
@@ -600,7 +607,8 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1, nu2 = d == 0 ? p.opts.nu2 : p.nuc2;
         if (d < L3) {
             for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
-                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, fz, p.nblk, s);
+                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, D.fz_s[d], p.nblk,
+                              s);
             continue;
         }
         if (D.fused) {
@@ -1313,7 +1321,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                     break;
                 case FLD_KERNEL_SWEEP3:
                     if (has_level && D.fused3)
-                        launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, p.tile_depth, p.nblk, s);
+                        launch_sweep3(p.mixed, p.dL, p.dS, D.sw3[level].dev, 0, 0, 0, D.fz_s[level], p.nblk, s);
                     break;
                 case FLD_KERNEL_TAIL:
                     launch_tail(D.dim, p.mixed, p.nb_bc(), p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, 0, s);

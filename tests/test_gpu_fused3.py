@@ -24,8 +24,8 @@ def grids3():
 
 def run_fused(grids, levels, **kw):
     """One step with the fused sweeps forced onto the first `levels` depths (the default
-    rule fuses only depths with at least one sweep block per compute unit, which these
-    test grids do not reach); checks that the plan really runs them and returns
+    rule fuses only depths with at least one sweep block per two compute units, which
+    these test grids do not reach); checks that the plan really runs them and returns
     (xs, stats, rc)."""
     plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids], fused3_levels=levels,
                     **{k: v for k, v in kw.items() if k != "max_cycles"},
@@ -89,7 +89,8 @@ def test_fused_sweeps_any_depth_and_sweep_count(nu, depth, precision):
 @pytest.mark.parametrize("depth", [16, 32, 64])
 def test_fp64_fused_finest_level_default_rule(depth):
     """A grid wide enough for the default rule to fuse its finest level in FP64 (at
-    least 256 sweep blocks at depth 16) at every plane depth, against the oracle."""
+    least one sweep block per two compute units at depth 16) at every plane depth,
+    against the oracle."""
     g = W.random_grid((96, 192, 192), 93400, dt=2e-3)
     for lv in (0, 1):
         kw = {} if lv == 0 else {"fused3_levels": 1}
