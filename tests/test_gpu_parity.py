@@ -253,6 +253,27 @@ def test_batched_equals_alone_bitwise():
         assert rel_l2(xb[i], x_or) <= 1e-10 * O.q_b(g.E) * 1.01
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reduction_placement_does_not_change_a_result(precision):
+    """Where a grid's r.z and p.q sums are finished depends on the plan, not on the grid:
+    alone, a 600^2 grid (380 level-0 tiles) has its CG scalars formed by the blocks of
+    the kernels that use them; batched with a 2944^2 grid (more tiles than any block
+    count), by k_finalize launches; with 32 or fewer tiles, by the last tile's block.
+    Every place sums the same partials in the same order, so the results are bitwise
+    equal."""
+    a = W.random_grid((600, 600), 610000, dt=4e-3)
+    big = W.random_grid((2944, 2944), 610001, dt=1e-3)
+    small = W.random_grid((64, 96), 610002, dt=4e-3)
+    (xa,), (sa,), ra = run_step([a], precision=precision)
+    xb, sb, rb = run_step([a, big, small], precision=precision)
+    (xs,), (ss,), rs = run_step([small], precision=precision)
+    assert ra == 0 and rb == 0 and rs == 0
+    assert np.array_equal(xa, xb[0]) and sa["cycles"] == sb[0]["cycles"]
+    assert np.array_equal(xs, xb[2]) and ss["cycles"] == sb[2]["cycles"]
+    x_or, _ = O.diffusion_step(a.E, a.kappa_rho, a.dt, a.h)
+    assert rel_l2(xa, x_or) <= 1e-10 * O.q_b(a.E) * 1.01
+
+
 # ------------------------------------------------------------------ failure paths
 def test_bad_input_reported():
     g = W.random_grid((32, 32), 1000, dt=1e-3)
