@@ -492,7 +492,7 @@ def main():
         serve_stream(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs one GPU's share of the work; --gpus must be 1"}))
         log("bench.py: only single-GPU runs are supported (the workload is one GPU's share)")
         sys.exit(2)
     import torch
