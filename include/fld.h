@@ -179,7 +179,8 @@ typedef struct fld_opts {
     int32_t coarse_op;    /* FLD_COARSE_* [REDISCRETISED]                          */
     int32_t fmg_depths;   /* with fmg: only the finest fmg_depths levels run the V-cycle
                              of their full-multigrid stage; coarser ones pass the
-                             interpolated solution on as it is (0 = every level) [2] */
+                             interpolated solution on as it is (0 = every level;
+                             -1 = by dimension: the finest 2 in 2D, 3 in 3D) [-1]   */
     double  bc_value[6];  /* per face: the ghost value E_B of FLD_BC_DIRICHLET faces,
                              finite and >= 0 (ignored elsewhere) [0]                 */
     int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass: 4, 8, 16

@@ -90,7 +90,7 @@ int validate_opts(const fld_opts& o) {
                        o.tile_rows_coarse || o.tile_rows_up))
         return FLD_ERR_INVALID_ARG;
     if (o.fmg != 0 && o.fmg != 1) return FLD_ERR_INVALID_ARG;
-    if (o.fmg_depths < 0 || o.fmg_depths > 64) return FLD_ERR_INVALID_ARG;
+    if (o.fmg_depths < -1 || o.fmg_depths > 64) return FLD_ERR_INVALID_ARG;
     if (o.nu_coarse < 0 || o.nu_coarse > 16) return FLD_ERR_INVALID_ARG;
     if (o.coarse_op != FLD_COARSE_REDISCRETISED && o.coarse_op != FLD_COARSE_GALERKIN) return FLD_ERR_INVALID_ARG;
     return FLD_OK;
@@ -647,7 +647,9 @@ static void enqueue_fmg(Plan& p, DimLists& D, hipStream_t s) {
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
     launch_tail(D.dim, f32, p.nb_bc(), p.dL, p.dS, D.tail.dev, D.tail_smem, p.nuc1, p.nuc2, plain64, s);
     launch_coarse_solve(D.dim, f32, p.dL, p.dS, D.coarsest.dev, s);
-    const int nv = p.opts.fmg_depths > 0 ? p.opts.fmg_depths : D.maxdepth;
+    // by dimension: the 3D stages below the two finest still pay for their V-cycles
+    const int fd = p.opts.fmg_depths >= 0 ? p.opts.fmg_depths : (D.dim == 3 ? 3 : 2);
+    const int nv = fd > 0 ? fd : D.maxdepth;
     for (int d = D.maxdepth - 1; d >= 0; --d) {
         launch_fmg_interp(D.dim, f32, p.dL, p.dS, D.prolong[d].dev, p.nblk, s);
         if (d < nv) enqueue_mg_from(p, D, s, d, 1, D.tail_from[d].dev, D.coarsest_from[d].dev);
@@ -1438,7 +1440,7 @@ void fld_opts_default(fld_opts* o) {
     o->krylov = 1;
     o->fused = 1;
     o->fmg = 1;
-    o->fmg_depths = 2;
+    o->fmg_depths = -1;
     o->coarse_op = FLD_COARSE_REDISCRETISED;
 }
 

@@ -38,7 +38,7 @@ def test_defaults():
     o = fld.fld_opts_default()
     assert o.c == 1.0 and o.rtol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.max_cycles == 50
     assert o.limiter == fld.FLD_LIMITER_LP and o.precision == fld.FLD_PREC_FP64
-    assert o.fmg == 1 and o.fmg_depths == 2 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
+    assert o.fmg == 1 and o.fmg_depths == -1 and o.coarse_op == fld.FLD_COARSE_REDISCRETISED
     assert o.nu_coarse == 3 and o.tile_rows_up == 0
     assert fld.fld_opts_default(coarse_op="galerkin").coarse_op == fld.FLD_COARSE_GALERKIN
     g = fld.fld_gas_default()
@@ -68,7 +68,7 @@ def test_plan_create_validates_grids(n, ok):
     (dict(bc=[0, 2, 0, 0, 0, 0], bc_value=[0, float("inf"), 0, 0, 0, 0]), -1),
     (dict(bc=[1, 0, 0, 0, 0, 0], bc_grad=[float("nan"), 0, 0, 0, 0, 0]), -1),
     (dict(fmg=2), -1), (dict(fmg=-1), -1), (dict(coarse_op=2), -1), (dict(coarse_op=-1), -1),
-    (dict(fmg_depths=-1), -1), (dict(fmg_depths=65), -1), (dict(nu_coarse=-1), -1), (dict(nu_coarse=17), -1)])
+    (dict(fmg_depths=-2), -1), (dict(fmg_depths=65), -1), (dict(nu_coarse=-1), -1), (dict(nu_coarse=17), -1)])
 def test_plan_create_validates_options(kw, code):
     with pytest.raises(fld.FLDError) as e:
         fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(**kw))

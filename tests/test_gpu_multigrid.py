@@ -130,7 +130,7 @@ def test_converged_start_takes_no_cycles():
         assert np.array_equal(x, E)
 
 
-@pytest.mark.parametrize("depths", [0, 1, 2, 3])
+@pytest.mark.parametrize("depths", [0, 1, 2, 3, -1])
 @pytest.mark.parametrize("precision,krylov", [(0, 1), (1, 0), (0, 0)])
 def test_fmg_depths_match_oracle(depths, precision, krylov):
     grids = _batch()
