@@ -239,6 +239,18 @@ def test_reported_residual_is_the_oracle_residual():
     assert 1 <= st["cycles"] <= 20
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vanishing_time_step(precision):
+    """dt -> 0: A -> I + O(dt), so the step stays within O(dt |L|) of E^n and one or two
+    cycles reach the stop rule; against the oracle's step."""
+    g = W.random_grid((96, 80), 620000, dt=1e-12)
+    (x,), (st,), rc = run_step([g], precision=precision)
+    assert rc == 0 and st["cycles"] <= 2, st
+    assert rel_l2(x, g.E) <= 1e-6
+    x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h)
+    assert rel_l2(x, x_or) <= 1e-10 * O.q_b(g.E) * 1.01
+
+
 # ------------------------------------------------------------------ batching
 def test_batched_equals_alone_bitwise():
     shapes = [(64, 64), (96, 96), (37, 100), (160, 160), (24, 24, 24)]
