@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--nu-coarse", type=int, default=None,
                     help="red-black sweeps before and after the correction on the coarse levels "
                          "(0 = nu1 and nu2, as on the finest level; default: the library's)")
+    ap.add_argument("--fused", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="2D fused level passes: 2 = LDS tiles only, 3 = row-marching windows wherever "
+                         "fused, 0 = per-colour kernels (default: the library's rule)")
     return ap.parse_args()
 
 
@@ -78,19 +81,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def dominant_kernel(fld, ndim: int, word: int, fused: bool, fused3: bool):
+def dominant_kernel(fld, ndim: int, word: int, fused: bool, fused3: bool, march: bool = False):
     """The kernel that dominates a step and its algorithmic bytes per cell of level 0.
 
-    2D (fused level kernels): the level-0 up pass reads the down pass's iterate,
-    b, both face arrays and a quarter-size coarse correction, and writes x:
-    (5 + 1/4) words.  3D fused sweeps: one whole red-black sweep reads x, b and
+    2D (fused level kernels, LDS tiles or row-marching windows): the level-0 up pass
+    reads the down pass's iterate, b, both face arrays and a quarter-size coarse
+    correction, and writes x: (5 + 1/4) words.  3D fused sweeps: one whole red-black sweep reads x, b and
     the three face arrays once and writes x: 6 words.  3D per-colour kernels:
     one half sweep reads x of every cell, b of the updated half, every face
     weight (each face touches one cell of each colour) and writes x of the
     updated half: (2 + d) words.
     """
     if ndim == 2 and fused:
-        return fld.FLD_KERNEL_UP, "k_up2", word * 5 + word / 4
+        return fld.FLD_KERNEL_UP, "k_march2" if march else "k_up2", word * 5 + word / 4
     if ndim == 3 and fused3:
         return fld.FLD_KERNEL_SWEEP3, "k_sweep3", word * 6
     return fld.FLD_KERNEL_SMOOTH, "k_smooth", word * (2 + ndim)
@@ -174,6 +177,7 @@ def measured_traffic(cfg: str, kname: str, ctype: str, launch: dict):
     # the launch parameters the dominant kernel's own dispatch depends on
     keys = {"k_sweep3": ("tile_depth", "max_blocks"),
             "k_up2": ("tile_rows_up", "tile_wide", "max_blocks"),
+            "k_march2": ("max_blocks",),
             "k_smooth": ("max_blocks",)}.get(kname, ("tile_rows", "tile_wide", "max_blocks", "tile_depth",
                                                     "fused3_levels", "tile_rows_coarse", "tile_rows_up"))
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -373,7 +377,8 @@ def run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, steps, warm
                     c=grids[0].c, autotune=args.autotune, fmg=args.fmg, coarse_op=args.coarse_op,
                     nu1=args.nu[0], nu2=args.nu[1], krylov=args.krylov,
                     **({} if args.fmg_depths is None else {"fmg_depths": args.fmg_depths}),
-                    **({} if args.nu_coarse is None else {"nu_coarse": args.nu_coarse}))
+                    **({} if args.nu_coarse is None else {"nu_coarse": args.nu_coarse}),
+                    **({} if args.fused is None else {"fused": args.fused}))
     tuning = plan.tuning()
     log(f"bench {cfg}: launch shape {tuning}")
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -429,7 +434,8 @@ def run_timed(fld, torch, args, cfg, grids, has_gas, precision, dev, steps, warm
         nuc = o.nu_coarse or 0
         # the fused 2D level kernels take 1 to 3 sweeps; other counts run per colour
         fused2 = bool(o.fused) and all(1 <= v <= 3 for v in (o.nu1, o.nu2, nuc or o.nu1, nuc or o.nu2))
-        kid, kname, bpc = dominant_kernel(fld, ndim, word, fused2, bool(tuning["fused3"]))
+        kid, kname, bpc = dominant_kernel(fld, ndim, word, fused2, bool(tuning["fused3"]),
+                                          tuning.get("march_levels", 0) > 0)
         ms, cells = plan.profile(kid, 0, args.profile_reps, stream)
         achieved = bpc * cells / (ms * 1e-3) / 1e9
         log(f"bench {cfg}: level-0 {kname} {ms * 1e3:.2f} us for {cells} cells ({bpc} B/cell) -> {achieved:.0f} GB/s")

@@ -144,10 +144,13 @@ typedef struct fld_opts {
                              iteration, stopped on the recursive residual and
                              confirmed on the true FP64 residual; 0: plain V-cycle
                              iteration (defect correction in mixed precision) [1]   */
-    int32_t fused;        /* 2D: run each multigrid level as two fused LDS-tiled
-                             kernels (sweeps + restriction, prolongation + sweeps)
-                             when nu1, nu2 are in 1..3; 0: one kernel per colour
-                             sweep and per transfer [1]                             */
+    int32_t fused;        /* 2D: run each multigrid level as two fused kernels
+                             (sweeps + restriction, prolongation + sweeps) when nu1,
+                             nu2 are in 1..3: 1 = LDS tiles, or windows that march
+                             along the rows on depths with at least four windows per
+                             compute unit; 2 = tiles only; 3 = march wherever fused;
+                             0: one kernel per colour sweep and per transfer.  Every
+                             choice gives the same results bit for bit [1]         */
     int32_t tile_rows;    /* fused 2D tile rows: 4, 8, 16 or 32; 0 = 8 [0]          */
     int32_t tile_wide;    /* fused 2D tile width: 0 = 64 cells, 1 = 128 cells less
                              the halo (a colour cell per lane of a 64-lane wave) [0].
@@ -426,6 +429,7 @@ typedef struct fld_tuning {
     int32_t tile_rows_coarse; /* fused 2D tile rows below the finest level              */
     int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass (tile_rows:
                              its down pass)                                          */
+    int32_t march_levels; /* 2D depths whose passes march rows (fused = 1 or 3)      */
 } fld_tuning;
 /* Errors: INVALID_ARG (null), NO_WORKSPACE (not bound yet). */
 int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out);

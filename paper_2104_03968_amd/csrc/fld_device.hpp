@@ -30,6 +30,14 @@ constexpr int kTailThreads = 512;
 constexpr int kTailCPT = 4;
 constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 constexpr int kTailWaveCells = 256;                         // tail levels run by one wavefront
+constexpr int kMarchNT = 128;                               // row-marching 2D window (threads, positions)
+constexpr int kMarchFz = 64;                                // rows per row-marching block
+// interior columns of a row-marching window: the halo is 2 nu + 1 (down) or 2 nu (up)
+__host__ __device__ constexpr int march_fx(int nu, bool down) { return kMarchNT - 2 * (2 * nu + (down ? 1 : 0)); }
+__host__ __device__ inline int32_t march_tiles(const int32_t n[3], int nu, bool down) {
+    const int fx = march_fx(nu, down);
+    return ((n[0] + fx - 1) / fx) * ((n[1] + kMarchFz - 1) / kMarchFz);
+}
 
 // Tile counts of one level for the two tilings (host and device agree on these).
 __host__ __device__ inline int32_t cell_tiles(const int32_t n[3]) {
@@ -305,6 +313,10 @@ void launch_down2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl,
                   int wide, int fy, int threads, int nblk, hipStream_t s);
 void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int wide, int fy,
                 int threads, int nblk, hipStream_t s);
+// The row-marching form of the same passes (down: nu sweeps from zero or the stored
+// iterate, restricting; up: prolongation and nu sweeps), for levels with many tiles.
+void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
+                   int nblk, hipStream_t s);
 // Fused 3D sweeps (one red-black sweep per launch, colour c0 first), reading x (or xs
 // with from_xs) and writing the other; modes: 0 from the iterate, 1 from zero, 2 / 3 the
 // same plus restriction of the final residual, 4 from the iterate plus the prolonged

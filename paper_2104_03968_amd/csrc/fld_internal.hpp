@@ -46,6 +46,8 @@ struct DimLists {
     std::vector<HostList> coarsen;             // per depth, all levels with a coarser one
     std::vector<HostList> down2, up2;          // per depth, fused 2D tiles (same levels as smooth)
     std::vector<int> thr_dn, thr_up;           // per depth, workgroup size of those tiles (256 or 1024)
+    std::vector<HostList> mdn, mup;            // per depth, row-marching windows (same levels)
+    std::vector<char> march;                   // per depth: the passes march rows instead of tiles
     bool fused = false;
     std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
     std::vector<int> fz_r;                     // per depth, planes per block of the restricting sweep

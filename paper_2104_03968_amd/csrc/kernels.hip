@@ -1510,6 +1510,180 @@ k_up2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList 
     }
 }
 
+// Calls f(std::integral_constant<int, 0>{}) .. f(std::integral_constant<int, N - 1>{}) in order.
+template <int N, typename F>
+__device__ __forceinline__ void unroll(F&& f) {
+    if constexpr (N > 0) {
+        unroll<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row-marching fused 2D level kernels for levels with many tiles.  A block of
+// kMarchNT threads owns a window of as many x positions (FX interior columns and a
+// halo of H on each side, one position per thread) and fz rows, and marches along y
+// with all 2 nu half sweeps of the pass in flight at once: at step zt, half sweep k
+// (k = 1 .. 2 nu, in order) updates row zt - k.  Row zt - k + 1 was updated by half
+// sweep k - 1 earlier in the same step and row zt - k - 1 two steps before, so every
+// cell sees its y-neighbours exactly as a global red-black sweep leaves them; the
+// y-neighbours are the thread's own registers (a ring of rows per thread), the
+// x-neighbours come from an LDS row per half sweep written one step earlier.  One
+// barrier per step.  Half sweep k is computed on positions [k, W - k) of the window
+// and on rows [z0 - H + k, z1 + H - k), the same shrinking regions as the LDS tile
+// kernels, whose operand order every update and residual keeps: the two paths give
+// bitwise equal results.  The down pass (H = 2 nu + 1) starts from zero or the
+// stored iterate, writes the smoothed iterate to xs and averages the final residual
+// onto the coarse right-hand side (the residual of row r is formed one step after
+// its last update, and the coarse cell of a row pair is finished one step later);
+// the up pass (H = 2 nu) starts from xs plus the prolonged coarse correction and
+// writes x.  Unlike a tile, a window recomputes no rows: only the x halo and the
+// 2H halo rows of each block's march.
+// ---------------------------------------------------------------------------
+template <typename T, int NU, bool DOWN>
+__global__ void __launch_bounds__(kMarchNT)
+k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int fz, int load_x) {
+    constexpr int NT = kMarchNT;
+    constexpr int SS = 2 * NU;                       // half sweeps of the pass
+    constexpr int H = DOWN ? SS + 1 : SS;            // halo positions (rows) of the window
+    constexpr int FX = NT - 2 * H;
+    constexpr int PF = 2;                            // rows loaded ahead
+    constexpr int NB = SS + PF + 3;                  // register ring: rows zt + PF .. zt - SS - 2
+    constexpr int NW = SS + 3;                       // LDS ring of lower x-face rows
+    static_assert(FX > 0 && FX % 2 == 0, "the window's interior pairs up for the restriction");
+    // rows as loaded (three slots: the next step's is written before its barrier) and
+    // after half sweep k = 1 .. SS (two slots: written after the barrier)
+    __shared__ T x0r[3][NT];
+    __shared__ T xkr[SS][2][NT];
+    __shared__ T w0r[NW][NT];
+    __shared__ T res[DOWN ? 2 : 1][NT];
+    const int lx = threadIdx.x;
+    const XcdOrder order(jl.total);
+    for (int kk = order.first(); order.more(kk); kk += order.per) {
+        const int tt = order.tile(kk);
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[job_level(jl, jb)];
+        if (!S[d.sidx].active) continue;                              // uniform per tile
+        const int lt = tt - job_start(jl, jb);
+        const int nx = d.n[0], ny = d.n[1];
+        const int tx_n = (nx + FX - 1) / FX;
+        const int gx0 = (lt % tx_n) * FX - H;
+        const int z0 = (lt / tx_n) * fz, z1 = min(z0 + fz, ny);
+        const int zs = z0 - H, ze = z1 + SS + 2;
+        const int gx = gx0 + lx;
+        const bool inx = gx >= 0 && gx < nx;
+        const int gxc = min(max(gx, 0), nx - 1);
+        const gptr<T> xin = as_global(DOWN ? Arr<T>::x(d) : Arr<T>::xs(d));
+        const gptr<T> xout = as_global(DOWN ? Arr<T>::xs(d) : Arr<T>::x(d));
+        const gptr<T> bg = as_global(Arr<T>::b(d));
+        const gptr<T> w0g = as_global(Arr<T>::w(d, 0));
+        const gptr<T> w1g = as_global(Arr<T>::w(d, 1));
+        const LevelDesc& cL = L[d.coarse];
+        const gptr<T> cxg = as_global(Arr<T>::x(cL));
+        const gptr<T> cbg = as_global(Arr<T>::b(cL));
+        const int cn0 = cL.n[0], cn1 = cL.n[1];
+        const bool loadx = DOWN ? load_x != 0 : true;
+        T X[NB], B[NB], W0[NB], W1[NB], CC[NB];
+        unroll<NB>([&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            X[q] = B[q] = W0[q] = W1[q] = CC[q] = T(0);
+        });
+        // loads of row gj at the clamped row and column (masked when committed).  They are
+        // issued on every step, whatever the row, and the iterate's (skipped when the pass
+        // starts from zero) last: the compiler's wait before a row's first use then counts
+        // the next row's loads as still in flight instead of waiting for them too.
+        auto load = [&](auto Sl, int gj) {
+            constexpr int q = decltype(Sl)::value;
+            const int jc = min(max(gj, 0), ny - 1);
+            const long idx = gxc + (long)nx * jc;
+            B[q] = bg[idx];
+            W0[q] = w0g[idx];
+            W1[q] = w1g[idx];
+            if constexpr (!DOWN) CC[q] = cxg[(gxc >> 1) + (long)cn0 * (jc >> 1)];
+            X[q] = loadx ? xin[idx] : T(0);
+        };
+        T acc = T(0);                                 // coarse cell of a row pair (owners)
+        const bool rown = DOWN && lx >= H && lx < NT - H && ((lx - H) & 1) == 0;
+        auto step = [&](auto Qc, int zt) {
+            constexpr int q = decltype(Qc)::value;   // register slot of row zt
+            // A: row zt enters the window (zero outside the level)
+            {
+                const bool in = inx && zt >= 0 && zt < ny;
+                T xv = X[q];
+                if (!DOWN) xv += CC[q];
+                X[q] = in ? xv : T(0);
+                B[q] = in ? B[q] : T(0);
+                W0[q] = in ? W0[q] : T(0);
+                W1[q] = in ? W1[q] : T(0);
+                x0r[(zt - zs) % 3][lx] = X[q];
+                w0r[(zt - zs) % NW][lx] = W0[q];
+            }
+            load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
+            __syncthreads();
+            const int bp = (zt - zs + 2) % 3;          // slot of x0r written in the previous step
+            const int bp2 = (zt - zs + 1) & 1;         // slot of xkr written in the previous step
+            const int bc2 = (zt - zs) & 1;             // slot of xkr of this step
+            // the half sweeps, in order
+            auto half = [&](auto Kc) {
+                constexpr int k = decltype(Kc)::value;
+                constexpr int qk = (q + NB - k) % NB, qd = (q + NB - k - 1) % NB, qu = (q + NB - k + 1) % NB;
+                constexpr int color = DOWN ? ((k - 1) & 1) : (k & 1);
+                const int r = zt - k;
+                const T* xp;                                   // row r after half sweep k - 1
+                if constexpr (k == 1) xp = x0r[bp];
+                else xp = xkr[k - 2][bp2];
+                if (r >= z0 - H + k && r < z1 + H - k && lx >= k && lx < NT - k && ((gx + r) & 1) == color) {
+                    const T wl = W0[qk], wr = w0r[(r - zs) % NW][lx + 1], wd = W1[qk], wu = W1[qu];
+                    const T s = B[qk] + wl * xp[lx - 1] + wr * xp[lx + 1] + wd * X[qd] + wu * X[qu];
+                    X[qk] = s / (T(1) + wl + wr + wd + wu);
+                }
+                xkr[k - 1][bc2][lx] = X[qk];
+            };
+            unroll<SS>([&](auto Kc) { half(std::integral_constant<int, decltype(Kc)::value + 1>{}); });
+            // row zt - SS is final
+            {
+                constexpr int qf = (q + NB - SS) % NB;
+                const int rf = zt - SS;
+                if (rf >= z0 && rf < z1 && lx >= H && lx < NT - H && inx) xout[gx + (long)nx * rf] = X[qf];
+            }
+            if constexpr (DOWN) {
+                // the coarse cells of the row pair whose residuals the previous step formed
+                const int rp = zt - SS - 2;
+                if (rp >= z0 && rp < z1 && rown) {
+                    if (((rp - z0) & 1) == 0) acc = T(0);
+                    acc += res[(zt - zs + 1) & 1][lx];
+                    acc += res[(zt - zs + 1) & 1][lx + 1];
+                    if ((rp - z0) & 1) {
+                        const int CI = gx >> 1, CJ = rp >> 1;
+                        if (CI < cn0 && CJ < cn1) cbg[CI + (long)cn0 * CJ] = acc * T(0.25);
+                    }
+                }
+                // the residual of row zt - SS - 1 (final, as are both of its y-neighbours)
+                constexpr int q3 = (q + NB - SS - 1) % NB, q2 = (q + NB - SS) % NB, q4 = (q + NB - SS - 2) % NB;
+                const int rr = zt - SS - 1;
+                T rv = T(0);
+                if (rr >= z0 && rr < z1 && lx >= H && lx < NT - H) {
+                    const T xc = X[q3];
+                    const T xl = xkr[SS - 1][bp2][lx - 1], xrr = xkr[SS - 1][bp2][lx + 1];
+                    rv = B[q3] - xc - W0[q3] * (xc - xl) - w0r[(rr - zs) % NW][lx + 1] * (xc - xrr) -
+                         W1[q3] * (xc - X[q4]) - W1[q2] * (xc - X[q2]);
+                }
+                res[(zt - zs) & 1][lx] = rv;
+            }
+        };
+        static_assert(PF == 2, "the prologue below loads two rows");
+        load(std::integral_constant<int, 0>{}, zs);
+        load(std::integral_constant<int, 1>{}, zs + 1);
+        // whole rounds of NB steps without a branch between them, then the last steps
+        int zb = zs;
+        for (; zb + NB <= ze; zb += NB) unroll<NB>([&](auto Qc) { step(Qc, zb + decltype(Qc)::value); });
+        unroll<NB - 1>([&](auto Qc) {
+            if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
+        });
+        __syncthreads();                                       // the rows are reused by the next tile
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Fused 3D sweeps.  One launch runs one whole red-black sweep (colour c0, then
 // 1-c0) over blocks of FX x FY interior columns and fz planes.  A block of
@@ -2914,6 +3088,22 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
         if (fp32) up2_t<float, NU, WIDE, FY>(L, S, jl, threads, g, s);
         else up2_t<double, NU, WIDE, FY>(L, S, jl, threads, g, s);
     }));
+}
+
+void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
+                   int nblk, hipStream_t s) {
+    if (jl.total <= 0) return;
+    // the same operands as the fused tile passes (k_down2 / k_up2)
+    if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) *
+                 (down ? 4.0 + (load_x ? 1.0 : 0.0) + 2.0 / 4.0 : 5.0 + 1.0 / 4.0)))
+        return;
+    const int g = blocks_for_xcd(jl.total, nblk);
+#define FLD_MARCH(T_, D_) hipLaunchKernelGGL((k_march2<T_, NU, D_>), dim3(g), dim3(kMarchNT), 0, s, L, S, jl, kMarchFz, load_x)
+    FLD_NU_DISPATCH(nu, {
+        if (down) { if (fp32) FLD_MARCH(float, true); else FLD_MARCH(double, true); }
+        else { if (fp32) FLD_MARCH(float, false); else FLD_MARCH(double, false); }
+    });
+#undef FLD_MARCH
 }
 
 template <int DIM, typename T, bool BC>

@@ -70,7 +70,7 @@ int validate_opts(const fld_opts& o) {
     if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 16 || o.nu2 > 16) return FLD_ERR_INVALID_ARG;
     if (o.krylov && o.nu1 != o.nu2) return FLD_ERR_INVALID_ARG;   // CG needs a symmetric V-cycle
     if (o.krylov != 0 && o.krylov != 1) return FLD_ERR_INVALID_ARG;
-    if (o.fused != 0 && o.fused != 1) return FLD_ERR_INVALID_ARG;
+    if (o.fused < 0 || o.fused > 3) return FLD_ERR_INVALID_ARG;
     if (o.autotune < 0 || o.autotune > 2) return FLD_ERR_INVALID_ARG;
     if (o.tile_rows != 0 && o.tile_rows != 4 && o.tile_rows != 8 && o.tile_rows != 16 && o.tile_rows != 32)
         return FLD_ERR_INVALID_ARG;
@@ -126,6 +126,10 @@ int tiles_one(const LevelDesc&) { return 1; }
 // many workgroups whatever cap the stencil kernels are tuned to.
 constexpr int kCellBlocks = 8192;
 inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
+
+// A fused 2D depth marches rows when its down pass has at least this many windows per
+// compute unit (fld_opts.fused = 1).
+constexpr int kMarchMinBlocks = 4;
 
 // Fused-tile prefixes of the down / up lists (2D) and the sweep lists (3D) for the
 // plan's launch shape.
@@ -357,9 +361,23 @@ static void build_lists(Plan& p) {
                   fused2_supported(p.opts.nu2) && fused2_supported(p.nuc1) && fused2_supported(p.nuc2);
         D.down2.resize(D.fused ? maxdepth : 0);
         D.up2.resize(D.fused ? maxdepth : 0);
+        D.mdn.resize(D.fused ? maxdepth : 0);
+        D.mup.resize(D.fused ? maxdepth : 0);
+        D.march.assign(D.fused ? maxdepth : 0, 0);
         for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
             D.down2[dpt].levels = D.smooth[dpt].levels;
             D.up2[dpt].levels = D.smooth[dpt].levels;
+            // row-marching windows: no rows recomputed, so they pay where a depth has many
+            // windows to keep every compute unit busy (fused = 3 forces them, 2 forbids them)
+            const int n1 = dpt == 0 ? p.opts.nu1 : p.nuc1, n2 = dpt == 0 ? p.opts.nu2 : p.nuc2;
+            HostList& md = D.mdn[dpt];
+            HostList& mu = D.mup[dpt];
+            md.levels = mu.levels = D.smooth[dpt].levels;
+            md.prefix.assign(1, 0);
+            mu.prefix.assign(1, 0);
+            for (int32_t li : md.levels) md.prefix.push_back(md.prefix.back() + march_tiles(p.levels[li].n, n1, true));
+            for (int32_t li : mu.levels) mu.prefix.push_back(mu.prefix.back() + march_tiles(p.levels[li].n, n2, false));
+            D.march[dpt] = p.opts.fused == 3 || (p.opts.fused == 1 && md.prefix.back() >= kMarchMinBlocks * p.ncu);
         }
         // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
         // even for its result to end in x
@@ -483,6 +501,8 @@ static void layout(Plan& p) {
         for (auto& l : D.coarsen) place_list(l);
         for (auto& l : D.down2) place_list(l);
         for (auto& l : D.up2) place_list(l);
+        for (auto& l : D.mdn) place_list(l);
+        for (auto& l : D.mup) place_list(l);
         for (auto& l : D.sw3) place_list(l);
         for (auto& l : D.sr3) place_list(l);
         for (auto& l : D.smooth) place_list(l);
@@ -589,6 +609,10 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             }
             continue;
         }
+        if (D.fused && D.march[d]) {
+            launch_march2(f32, p.dL, p.dS, D.mdn[d].dev, nu1, 1, d == d0 ? load0 : 0, p.nblk, s);
+            continue;
+        }
         if (D.fused) {
             launch_down2(f32, p.dL, p.dS, D.down2[d].dev, nu1, d == d0 ? load0 : 0, p.tile_wide,
                          d == 0 ? p.tile_rows : p.tile_rows_c, D.thr_dn[d], p.nblk, s);
@@ -609,6 +633,10 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
                 launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, D.fz_s[d], p.nblk,
                               s);
+            continue;
+        }
+        if (D.fused && D.march[d]) {
+            launch_march2(f32, p.dL, p.dS, D.mup[d].dev, nu2, 0, 0, p.nblk, s);
             continue;
         }
         if (D.fused) {
@@ -865,8 +893,8 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
         stage_list(p, D.pq3, img);
         stage_list(p, D.coarsest, img);
         stage_list(p, D.tail, img);
-        for (auto* v : {&D.coarsen, &D.down2, &D.up2, &D.sw3, &D.sr3, &D.smooth, &D.restrict_, &D.prolong,
-                        &D.tail_from, &D.coarsest_from})
+        for (auto* v : {&D.coarsen, &D.down2, &D.up2, &D.mdn, &D.mup, &D.sw3, &D.sr3, &D.smooth, &D.restrict_,
+                        &D.prolong, &D.tail_from, &D.coarsest_from})
             for (auto& l : *v) stage_list(p, l, img);
         if (!D.tail.empty() && prepare_tail(D.dim, p.mixed, D.tail_smem) != 0) {
             g_last_error = "hipFuncSetAttribute(max dynamic LDS) failed for the tail kernel";
@@ -1310,13 +1338,19 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                                  -1, p.opts.rtol, p.opts.max_cycles, cell_blocks(p), s);
                     break;
                 case FLD_KERNEL_DOWN:
-                    if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
+                    if (has_level && D.fused && D.march[level])
+                        launch_march2(p.mixed, p.dL, p.dS, D.mdn[level].dev, level == 0 ? p.opts.nu1 : p.nuc1, 1, 0,
+                                      p.nblk, s);
+                    else if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
                                                              level == 0 ? p.opts.nu1 : p.nuc1, 0,
                                                              p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
                                                              D.thr_dn[level], p.nblk, s);
                     break;
                 case FLD_KERNEL_UP:
-                    if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
+                    if (has_level && D.fused && D.march[level])
+                        launch_march2(p.mixed, p.dL, p.dS, D.mup[level].dev, level == 0 ? p.opts.nu2 : p.nuc2, 0, 0,
+                                      p.nblk, s);
+                    else if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
                                                          level == 0 ? p.opts.nu2 : p.nuc2,
                                                          p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
                                                          D.thr_up[level], p.nblk, s);
@@ -1696,6 +1730,10 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     out->fused3_levels = l3;
     out->tile_rows_coarse = p.tile_rows_c;
     out->tile_rows_up = p.tile_rows_u;
+    int m2 = 0;
+    for (const auto& D : p.dl)
+        for (size_t d = 0; d < D.march.size(); ++d) m2 += D.march[d] ? 1 : 0;
+    out->march_levels = m2;
     return FLD_OK;
 }
 

@@ -89,6 +89,7 @@ def test_plan_create_validates_options(kw, code):
     (dict(tile_wide=1, tile_rows=32, fused=0), True), (dict(tile_depth=16), True),
     (dict(tile_depth=64), True), (dict(tile_depth=24), False), (dict(autotune=1, tile_depth=32), False),
     (dict(fused3_levels=2), True), (dict(fused3_levels=-1), False), (dict(autotune=1, fused3_levels=1), False),
+    (dict(fused=2), True), (dict(fused=3), True), (dict(fused=4), False), (dict(fused=-1), False),
     (dict(tile_rows_coarse=4), True), (dict(tile_rows_coarse=12), False),
     (dict(autotune=1, tile_rows_coarse=8), False), (dict(tile_wide=1, tile_rows_coarse=32), False),
     (dict(tile_rows_up=16), True), (dict(tile_rows_up=6), False), (dict(autotune=1, tile_rows_up=8), False),

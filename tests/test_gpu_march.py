@@ -1,0 +1,69 @@
+"""The row-marching fused 2D level kernels (k_march2) against the LDS-tile ones: the
+same operand order on every cell update and residual, so a step through either gives
+bitwise equal results, at every sweep count, in both precisions and under CG, plain
+V-cycles and the full-multigrid start; and the default rule picks the march only on
+depths with many windows."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as O                     # noqa: E402
+import workloads as W                  # noqa: E402
+import paper_2104_03968_amd as fld     # noqa: E402
+from tests.gpu_common import run_step, rel_l2   # noqa: E402
+
+# widths across and off the window widths (118 / 120 interior columns at nu = 2), odd
+# coarsest levels, a grid narrower than one window, one taller than one march block
+SHAPES = [(256, 256), (130, 372), (96, 64), (200, 120), (48, 40), (320, 236)]
+
+
+def _grids(seed):
+    return [W.random_grid(s, seed + 7 * i, dt=3e-3 * (1 + i % 3)) for i, s in enumerate(SHAPES)]
+
+
+def _pair(grids, **kw):
+    xa, sa, ra = run_step(grids, fused=3, **kw)
+    xb, sb, rb = run_step(grids, fused=2, **kw)
+    assert ra == 0 and rb == 0, (sa, sb)
+    for i in range(len(grids)):
+        assert sa[i]["cycles"] == sb[i]["cycles"], (i, sa[i], sb[i])
+        assert np.array_equal(xa[i], xb[i]), (i, np.abs(xa[i] - xb[i]).max())
+    return xa, sa
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_march_equals_tiles_bitwise(nu, precision):
+    grids = _grids(640000 + 10 * nu)
+    _pair(grids, precision=precision, nu1=nu, nu2=nu, nu_coarse=nu)
+
+
+@pytest.mark.parametrize("krylov,fmg", [(0, 0), (0, 1), (1, 0)])
+def test_march_equals_tiles_other_iterations(krylov, fmg):
+    grids = _grids(641000)
+    _pair(grids, precision=0, krylov=krylov, fmg=fmg)
+
+
+def test_march_meets_the_oracle():
+    grids = _grids(642000)[:3]
+    rtol = min(1e-10 / O.q_b(g.E) for g in grids)
+    xs, st = _pair(grids, precision=0, rtol=rtol)
+    for g, x in zip(grids, xs):
+        x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h)
+        assert rel_l2(x, x_or) <= 1e-10 * 1.01
+
+
+def test_default_rule_marches_only_where_windows_are_many():
+    big = fld.Plan([(512, 512)] * 40, h=[(1 / 512, 1 / 512)] * 40)
+    one = fld.Plan([(1024, 1024)], h=[(1 / 1024, 1 / 1024)])
+    forced = fld.Plan([(64, 64)], h=[(1 / 64, 1 / 64)], fused=3)
+    tiles = fld.Plan([(512, 512)] * 40, h=[(1 / 512, 1 / 512)] * 40, fused=2)
+    assert big.tuning()["march_levels"] >= 1
+    assert one.tuning()["march_levels"] == 0
+    assert forced.tuning()["march_levels"] >= 1
+    assert tiles.tuning()["march_levels"] == 0
+    for p in (big, one, forced, tiles):
+        p.close()
