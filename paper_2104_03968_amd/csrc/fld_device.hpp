@@ -30,10 +30,12 @@ constexpr int kTailThreads = 512;
 constexpr int kTailCPT = 4;
 constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 constexpr int kTailWaveCells = 256;                         // tail levels run by one wavefront
-constexpr int kMarchNT = 128;                               // row-marching 2D window (threads, positions)
-constexpr int kMarchFz = 64;                                // rows per row-marching block
-// interior columns of a row-marching window: the halo is 2 nu + 1 (down) or 2 nu (up)
-__host__ __device__ constexpr int march_fx(int nu, bool down) { return kMarchNT - 2 * (2 * nu + (down ? 1 : 0)); }
+constexpr int kMarchNP = 128;                               // row-marching 2D window: positions (two a lane)
+constexpr int kMarchFz = 64;                                // rows per row-marching window
+// halo of a row-marching window (even, so that a lane's two columns pair up for the
+// restriction): 2 nu + 2 on the down pass, 2 nu on the up pass; and its interior columns
+__host__ __device__ constexpr int march_halo(int nu, bool down) { return 2 * nu + (down ? 2 : 0); }
+__host__ __device__ constexpr int march_fx(int nu, bool down) { return kMarchNP - 2 * march_halo(nu, down); }
 __host__ __device__ inline int32_t march_tiles(const int32_t n[3], int nu, bool down) {
     const int fx = march_fx(nu, down);
     return ((n[0] + fx - 1) / fx) * ((n[1] + kMarchFz - 1) / kMarchFz);

@@ -1519,60 +1519,78 @@ __device__ __forceinline__ void unroll(F&& f) {
     }
 }
 
+// Value of v on lane l - 1 (LEFT) or l + 1 of the wavefront, 0 on lane 0 / 63: DPP
+// whole-wavefront shifts (every lane must be active).
+__device__ __forceinline__ uint32_t lane_shift(uint32_t v, bool left) {
+    return left ? __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xF, 0xF, true)     // wave_shr:1
+                : __builtin_amdgcn_update_dpp(0u, v, 0x130, 0xF, 0xF, true);    // wave_shl:1
+}
+template <bool LEFT>
+__device__ __forceinline__ float lane_nb(float v) {
+    return __builtin_bit_cast(float, lane_shift(__builtin_bit_cast(uint32_t, v), LEFT));
+}
+template <bool LEFT>
+__device__ __forceinline__ double lane_nb(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = lane_shift((uint32_t)u, LEFT), hi = lane_shift((uint32_t)(u >> 32), LEFT);
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
-// Row-marching fused 2D level kernels for levels with many tiles.  A block of
-// kMarchNT threads owns a window of as many x positions (FX interior columns and a
-// halo of H on each side, one position per thread) and fz rows, and marches along y
-// with all 2 nu half sweeps of the pass in flight at once: at step zt, half sweep k
-// (k = 1 .. 2 nu, in order) updates row zt - k.  Row zt - k + 1 was updated by half
-// sweep k - 1 earlier in the same step and row zt - k - 1 two steps before, so every
-// cell sees its y-neighbours exactly as a global red-black sweep leaves them; the
-// y-neighbours are the thread's own registers (a ring of rows per thread), the
-// x-neighbours come from an LDS row per half sweep written one step earlier.  One
-// barrier per step.  Half sweep k is computed on positions [k, W - k) of the window
-// and on rows [z0 - H + k, z1 + H - k), the same shrinking regions as the LDS tile
-// kernels, whose operand order every update and residual keeps: the two paths give
-// bitwise equal results.  The down pass (H = 2 nu + 1) starts from zero or the
-// stored iterate, writes the smoothed iterate to xs and averages the final residual
-// onto the coarse right-hand side (the residual of row r is formed one step after
-// its last update, and the coarse cell of a row pair is finished one step later);
-// the up pass (H = 2 nu) starts from xs plus the prolonged coarse correction and
-// writes x.  Unlike a tile, a window recomputes no rows: only the x halo and the
-// 2H halo rows of each block's march.
+// Row-marching fused 2D level kernels for levels with many windows.  One wavefront
+// owns a window of kMarchNP x positions (FX interior columns and an even halo of H
+// on each side), two adjacent columns a lane, and fz rows, and marches along y with
+// all 2 nu half sweeps of the pass in flight at once: at step zt, half sweep k
+// (k = 1 .. 2 nu, in order) updates row zt - k.  Row zt - k + 1 went through half
+// sweep k - 1 earlier in the same step and row zt - k - 1 through half sweep k one
+// step earlier, so every cell sees its neighbours exactly as a global red-black
+// sweep leaves them.  In a step every half sweep updates the same one of a lane's two
+// columns (the colour flips with both k and the row), the even one on every other
+// step, so no lane idles: the y-neighbours are the lane's own registers (a ring of
+// rows), the x-neighbours its other column and, across the pair boundary, the
+// neighbouring lane's, taken by a DPP lane shift.  No LDS and no barrier.  Each cell
+// update and residual keeps the operand order of the LDS tile kernels (k_down2 /
+// k_up2), which gives bitwise equal results.  Rows and positions near the window's
+// edge take wrong neighbours (zero rows before the march, the shifted-in zero at the
+// wavefront's ends); that error moves inward one position or row per half sweep and
+// stays in the halo.  Cells outside the level hold x = b = 0 and zero faces, and
+// the level's boundary faces are zero, so they stay zero.  The down pass (halo 2 nu
+// + 2) starts from zero or the stored iterate, writes the smoothed iterate to xs and
+// averages the final residual of each row pair onto the coarse right-hand side (the
+// residual of row r one step after its last update; a lane's two columns are the
+// two fine columns of one coarse cell); the up pass (halo 2 nu) starts from xs plus
+// the prolonged coarse correction and writes x.  A window recomputes no rows, only
+// the x halo and its march's halo rows.
 // ---------------------------------------------------------------------------
-template <typename T, int NU, bool DOWN>
-__global__ void __launch_bounds__(kMarchNT)
-k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int fz, int load_x) {
-    constexpr int NT = kMarchNT;
+template <typename T, int NU, bool DOWN, bool LOADX>
+__global__ void __launch_bounds__(64)
+k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int fz) {
+    constexpr int NP = kMarchNP;
     constexpr int SS = 2 * NU;                       // half sweeps of the pass
-    constexpr int H = DOWN ? SS + 1 : SS;            // halo positions (rows) of the window
-    constexpr int FX = NT - 2 * H;
+    constexpr int H = march_halo(NU, DOWN);
+    constexpr int FX = march_fx(NU, DOWN);
     constexpr int PF = 2;                            // rows loaded ahead
-    constexpr int NB = SS + PF + 3;                  // register ring: rows zt + PF .. zt - SS - 2
-    constexpr int NW = SS + 3;                       // LDS ring of lower x-face rows
-    static_assert(FX > 0 && FX % 2 == 0, "the window's interior pairs up for the restriction");
-    // rows as loaded (three slots: the next step's is written before its barrier) and
-    // after half sweep k = 1 .. SS (two slots: written after the barrier)
-    __shared__ T x0r[3][NT];
-    __shared__ T xkr[SS][2][NT];
-    __shared__ T w0r[NW][NT];
-    __shared__ T res[DOWN ? 2 : 1][NT];
-    const int lx = threadIdx.x;
+    constexpr int NB = SS + PF + 4;                  // register ring: rows zt + PF .. zt - SS - 2 (and one spare)
+    static_assert(H % 2 == 0 && FX % 2 == 0 && NB % 2 == 0, "pairs of columns, steps of known parity");
+    using V2 = T __attribute__((ext_vector_type(2)));
+    const int l = threadIdx.x;
     const XcdOrder order(jl.total);
     for (int kk = order.first(); order.more(kk); kk += order.per) {
         const int tt = order.tile(kk);
         const int jb = find_job(jl.prefix, jl.njobs, tt);
         const LevelDesc& d = L[job_level(jl, jb)];
-        if (!S[d.sidx].active) continue;                              // uniform per tile
+        if (!S[d.sidx].active) continue;                              // uniform per window
         const int lt = tt - job_start(jl, jb);
-        const int nx = d.n[0], ny = d.n[1];
+        const int nx = d.n[0], ny = d.n[1];                           // even: the level has a coarse one
         const int tx_n = (nx + FX - 1) / FX;
-        const int gx0 = (lt % tx_n) * FX - H;
+        const int gx0 = (lt % tx_n) * FX - H;                         // even
         const int z0 = (lt / tx_n) * fz, z1 = min(z0 + fz, ny);
-        const int zs = z0 - H, ze = z1 + SS + 2;
-        const int gx = gx0 + lx;
-        const bool inx = gx >= 0 && gx < nx;
-        const int gxc = min(max(gx, 0), nx - 1);
+        const int zs = z0 - H;                                        // even: step zt has zt's parity
+        const int ze = z1 + SS + (DOWN ? 1 : 0);
+        const int ge = gx0 + 2 * l;                                   // the lane's even column
+        const bool inx = ge >= 0 && ge < nx;                          // both columns in the level, or neither
+        const int pc = min(max(ge, 0), nx - 2);
+        const bool own = inx && l >= H / 2 && l < (NP - H) / 2;       // an interior pair
         const gptr<T> xin = as_global(DOWN ? Arr<T>::x(d) : Arr<T>::xs(d));
         const gptr<T> xout = as_global(DOWN ? Arr<T>::xs(d) : Arr<T>::x(d));
         const gptr<T> bg = as_global(Arr<T>::b(d));
@@ -1582,93 +1600,107 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const gptr<T> cxg = as_global(Arr<T>::x(cL));
         const gptr<T> cbg = as_global(Arr<T>::b(cL));
         const int cn0 = cL.n[0], cn1 = cL.n[1];
-        const bool loadx = DOWN ? load_x != 0 : true;
-        T X[NB], B[NB], W0[NB], W1[NB], CC[NB];
+        T Xe[NB], Xo[NB], Be[NB], Bo[NB], W0e[NB], W0o[NB], W1e[NB], W1o[NB], C[NB];
         unroll<NB>([&](auto Qc) {
             constexpr int q = decltype(Qc)::value;
-            X[q] = B[q] = W0[q] = W1[q] = CC[q] = T(0);
+            Xe[q] = Xo[q] = Be[q] = Bo[q] = W0e[q] = W0o[q] = W1e[q] = W1o[q] = C[q] = T(0);
         });
-        // loads of row gj at the clamped row and column (masked when committed).  They are
-        // issued on every step, whatever the row, and the iterate's (skipped when the pass
-        // starts from zero) last: the compiler's wait before a row's first use then counts
-        // the next row's loads as still in flight instead of waiting for them too.
+        // loads of row gj (clamped) at the lane's two columns (clamped), masked when
+        // committed; issued on every step whatever the row, so that the compiler's wait
+        // before a row's first use leaves the next row's loads in flight
         auto load = [&](auto Sl, int gj) {
             constexpr int q = decltype(Sl)::value;
             const int jc = min(max(gj, 0), ny - 1);
-            const long idx = gxc + (long)nx * jc;
-            B[q] = bg[idx];
-            W0[q] = w0g[idx];
-            W1[q] = w1g[idx];
-            if constexpr (!DOWN) CC[q] = cxg[(gxc >> 1) + (long)cn0 * (jc >> 1)];
-            X[q] = loadx ? xin[idx] : T(0);
+            const long idx = pc + (long)nx * jc;
+            const V2 b2 = *(const gptr<V2>)(bg + idx);
+            const V2 u2 = *(const gptr<V2>)(w0g + idx);
+            const V2 v2 = *(const gptr<V2>)(w1g + idx);
+            Be[q] = b2.x;
+            Bo[q] = b2.y;
+            W0e[q] = u2.x;
+            W0o[q] = u2.y;
+            W1e[q] = v2.x;
+            W1o[q] = v2.y;
+            if constexpr (!DOWN) C[q] = cxg[(pc >> 1) + (long)cn0 * (jc >> 1)];
+            if constexpr (LOADX) {
+                const V2 x2 = *(const gptr<V2>)(xin + idx);
+                Xe[q] = x2.x;
+                Xo[q] = x2.y;
+            } else {
+                Xe[q] = Xo[q] = T(0);
+            }
         };
-        T acc = T(0);                                 // coarse cell of a row pair (owners)
-        const bool rown = DOWN && lx >= H && lx < NT - H && ((lx - H) & 1) == 0;
+        T acc = T(0);                                 // the lane's coarse cell of a row pair
         auto step = [&](auto Qc, int zt) {
-            constexpr int q = decltype(Qc)::value;   // register slot of row zt
-            // A: row zt enters the window (zero outside the level)
+            constexpr int q = decltype(Qc)::value;   // register slot of row zt; zt = q (mod 2)
+            // the column that updates: down passes take colour 0 first, so cell (i, r) of
+            // half sweep k updates when i + r + k is odd, i.e. i + zt is odd; up passes
+            // take colour 1 first (i + zt even)
+            constexpr bool AE = DOWN ? (q & 1) != 0 : (q & 1) == 0;
             {
+                // row zt enters the window (zero outside the level)
                 const bool in = inx && zt >= 0 && zt < ny;
-                T xv = X[q];
-                if (!DOWN) xv += CC[q];
-                X[q] = in ? xv : T(0);
-                B[q] = in ? B[q] : T(0);
-                W0[q] = in ? W0[q] : T(0);
-                W1[q] = in ? W1[q] : T(0);
-                x0r[(zt - zs) % 3][lx] = X[q];
-                w0r[(zt - zs) % NW][lx] = W0[q];
+                T xe = Xe[q], xo = Xo[q];
+                if constexpr (!DOWN) {
+                    xe += C[q];
+                    xo += C[q];
+                }
+                Xe[q] = in ? xe : T(0);
+                Xo[q] = in ? xo : T(0);
+                Be[q] = in ? Be[q] : T(0);
+                Bo[q] = in ? Bo[q] : T(0);
+                W0e[q] = in ? W0e[q] : T(0);
+                W0o[q] = in ? W0o[q] : T(0);
+                W1e[q] = in ? W1e[q] : T(0);
+                W1o[q] = in ? W1o[q] : T(0);
             }
             load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
-            __syncthreads();
-            const int bp = (zt - zs + 2) % 3;          // slot of x0r written in the previous step
-            const int bp2 = (zt - zs + 1) & 1;         // slot of xkr written in the previous step
-            const int bc2 = (zt - zs) & 1;             // slot of xkr of this step
-            // the half sweeps, in order
-            auto half = [&](auto Kc) {
-                constexpr int k = decltype(Kc)::value;
+            unroll<SS>([&](auto Kc) {
+                constexpr int k = decltype(Kc)::value + 1;
                 constexpr int qk = (q + NB - k) % NB, qd = (q + NB - k - 1) % NB, qu = (q + NB - k + 1) % NB;
-                constexpr int color = DOWN ? ((k - 1) & 1) : (k & 1);
-                const int r = zt - k;
-                const T* xp;                                   // row r after half sweep k - 1
-                if constexpr (k == 1) xp = x0r[bp];
-                else xp = xkr[k - 2][bp2];
-                if (r >= z0 - H + k && r < z1 + H - k && lx >= k && lx < NT - k && ((gx + r) & 1) == color) {
-                    const T wl = W0[qk], wr = w0r[(r - zs) % NW][lx + 1], wd = W1[qk], wu = W1[qu];
-                    const T s = B[qk] + wl * xp[lx - 1] + wr * xp[lx + 1] + wd * X[qd] + wu * X[qu];
-                    X[qk] = s / (T(1) + wl + wr + wd + wu);
+                if constexpr (AE) {
+                    const T xl = lane_nb<true>(Xo[qk]);
+                    const T wl = W0e[qk], wr = W0o[qk], wd = W1e[qk], wu = W1e[qu];
+                    const T s = Be[qk] + wl * xl + wr * Xo[qk] + wd * Xe[qd] + wu * Xe[qu];
+                    Xe[qk] = s / (T(1) + wl + wr + wd + wu);
+                } else {
+                    const T xr = lane_nb<false>(Xe[qk]);
+                    const T wl = W0o[qk], wr = lane_nb<false>(W0e[qk]), wd = W1o[qk], wu = W1o[qu];
+                    const T s = Bo[qk] + wl * Xe[qk] + wr * xr + wd * Xo[qd] + wu * Xo[qu];
+                    Xo[qk] = s / (T(1) + wl + wr + wd + wu);
                 }
-                xkr[k - 1][bc2][lx] = X[qk];
-            };
-            unroll<SS>([&](auto Kc) { half(std::integral_constant<int, decltype(Kc)::value + 1>{}); });
+            });
             // row zt - SS is final
             {
                 constexpr int qf = (q + NB - SS) % NB;
                 const int rf = zt - SS;
-                if (rf >= z0 && rf < z1 && lx >= H && lx < NT - H && inx) xout[gx + (long)nx * rf] = X[qf];
+                if (own && rf >= z0 && rf < z1) {
+                    V2 o2;
+                    o2.x = Xe[qf];
+                    o2.y = Xo[qf];
+                    *(gptr<V2>)(xout + ge + (long)nx * rf) = o2;
+                }
             }
             if constexpr (DOWN) {
-                // the coarse cells of the row pair whose residuals the previous step formed
-                const int rp = zt - SS - 2;
-                if (rp >= z0 && rp < z1 && rown) {
-                    if (((rp - z0) & 1) == 0) acc = T(0);
-                    acc += res[(zt - zs + 1) & 1][lx];
-                    acc += res[(zt - zs + 1) & 1][lx + 1];
-                    if ((rp - z0) & 1) {
-                        const int CI = gx >> 1, CJ = rp >> 1;
+                // the residual of row zt - SS - 1 (final, as are its neighbours) at both
+                // columns, added into the coarse cell in the tile kernels' order
+                constexpr int q3 = (q + NB - SS - 1) % NB, q2 = (q + NB - SS) % NB, q4 = (q + NB - SS - 2) % NB;
+                const T xe = Xe[q3], xo = Xo[q3];
+                const T xl = lane_nb<true>(xo), xr = lane_nb<false>(xe), wr = lane_nb<false>(W0e[q3]);
+                const T re = Be[q3] - xe - W0e[q3] * (xe - xl) - W0o[q3] * (xe - xo) - W1e[q3] * (xe - Xe[q4]) -
+                             W1e[q2] * (xe - Xe[q2]);
+                const T ro = Bo[q3] - xo - W0o[q3] * (xo - xe) - wr * (xo - xr) - W1o[q3] * (xo - Xo[q4]) -
+                             W1o[q2] * (xo - Xo[q2]);
+                const int rr = zt - SS - 1;
+                if (own && rr >= z0 && rr < z1) {
+                    if (((rr - z0) & 1) == 0) acc = T(0);
+                    acc += re;
+                    acc += ro;
+                    if ((rr - z0) & 1) {
+                        const int CI = ge >> 1, CJ = rr >> 1;
                         if (CI < cn0 && CJ < cn1) cbg[CI + (long)cn0 * CJ] = acc * T(0.25);
                     }
                 }
-                // the residual of row zt - SS - 1 (final, as are both of its y-neighbours)
-                constexpr int q3 = (q + NB - SS - 1) % NB, q2 = (q + NB - SS) % NB, q4 = (q + NB - SS - 2) % NB;
-                const int rr = zt - SS - 1;
-                T rv = T(0);
-                if (rr >= z0 && rr < z1 && lx >= H && lx < NT - H) {
-                    const T xc = X[q3];
-                    const T xl = xkr[SS - 1][bp2][lx - 1], xrr = xkr[SS - 1][bp2][lx + 1];
-                    rv = B[q3] - xc - W0[q3] * (xc - xl) - w0r[(rr - zs) % NW][lx + 1] * (xc - xrr) -
-                         W1[q3] * (xc - X[q4]) - W1[q2] * (xc - X[q2]);
-                }
-                res[(zt - zs) & 1][lx] = rv;
             }
         };
         static_assert(PF == 2, "the prologue below loads two rows");
@@ -1680,7 +1712,6 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         unroll<NB - 1>([&](auto Qc) {
             if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
         });
-        __syncthreads();                                       // the rows are reused by the next tile
     }
 }
 
@@ -3097,11 +3128,15 @@ void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
     if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) *
                  (down ? 4.0 + (load_x ? 1.0 : 0.0) + 2.0 / 4.0 : 5.0 + 1.0 / 4.0)))
         return;
-    const int g = blocks_for_xcd(jl.total, nblk);
-#define FLD_MARCH(T_, D_) hipLaunchKernelGGL((k_march2<T_, NU, D_>), dim3(g), dim3(kMarchNT), 0, s, L, S, jl, kMarchFz, load_x)
+    // one block per window: a window's march is long, and a block that owns several runs
+    // them back to back while other compute units may idle
+    (void)nblk;
+    const int g = blocks_for_xcd(jl.total, jl.total);
+#define FLD_MARCH(T_, D_, X_) hipLaunchKernelGGL((k_march2<T_, NU, D_, X_>), dim3(g), dim3(64), 0, s, L, S, jl, kMarchFz)
     FLD_NU_DISPATCH(nu, {
-        if (down) { if (fp32) FLD_MARCH(float, true); else FLD_MARCH(double, true); }
-        else { if (fp32) FLD_MARCH(float, false); else FLD_MARCH(double, false); }
+        if (down && load_x) { if (fp32) FLD_MARCH(float, true, true); else FLD_MARCH(double, true, true); }
+        else if (down) { if (fp32) FLD_MARCH(float, true, false); else FLD_MARCH(double, true, false); }
+        else { if (fp32) FLD_MARCH(float, false, true); else FLD_MARCH(double, false, true); }
     });
 #undef FLD_MARCH
 }
