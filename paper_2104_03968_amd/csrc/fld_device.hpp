@@ -94,6 +94,12 @@ __host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], bool restr, 
 // interior columns with one halo position around them, fz planes per block.
 constexpr int kPqPX = 66;
 constexpr int kPqPY = 15;
+// row-march CG direction update (2D level 0): windows of kMarchNP - 4 interior columns,
+// about kPq2Waves of them resident per compute unit
+constexpr int kPq2Waves = 16;
+__host__ __device__ inline int32_t pq2_tiles(const int32_t n[3], int fz) {
+    return ((n[0] + kMarchNP - 5) / (kMarchNP - 4)) * ((n[1] + fz - 1) / fz);
+}
 __host__ __device__ inline int32_t pq3_tiles(const int32_t n[3], int fz) {
     return ((n[0] + kPqPX - 3) / (kPqPX - 2)) * ((n[1] + kPqPY - 3) / (kPqPY - 2)) * ((n[2] + fz - 1) / fz);
 }
@@ -350,6 +356,7 @@ void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, Job
 // The same on the z-march tiles of a pq3 list (3D grids without Dirichlet or periodic faces):
 // each tile stores its partial of p . q; a launch_finalize over the same list finishes.
 void launch_cg_pq3(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fz, int nblk, hipStream_t s);
+void launch_cg_pq2m(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fz, hipStream_t s);
 // X += the level-0 V-cycle iterate (FP32 when mixed, else FP64).
 void launch_correct(int dim, bool mixed, const LevelDesc* L, const GridState* S, JobList jl, int nblk,
                     hipStream_t s);

@@ -62,7 +62,8 @@ struct DimLists {
     size_t tail_smem = 0;                      // LDS bytes of the largest tail
     bool fin_fused = false;                    // finish reductions in the last block (small grids)
     bool fold = false;                         // CG scalars formed in the consuming kernels (mid-sized grids)
-    HostList pq3;                              // level 0, z-march CG tiles (3D, zero-flux operators)
+    HostList pq3;                              // level 0, marching CG tiles (zero-flux operators): z-march
+                                               // (3D) or row march (2D, even rows)
     int fz_pq = 16;                            // planes per z-march CG tile
     int maxdepth = 0;
 };

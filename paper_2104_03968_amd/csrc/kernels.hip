@@ -2639,6 +2639,134 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
     }
 }
 
+// The same direction update and product on 2D grids without Dirichlet or periodic
+// faces as a row march: one wavefront owns a window of kMarchNP columns (two a lane:
+// kMarchNP - 4 interior columns and a halo of two on each side, so that a lane's
+// columns start at an even index and load as one vector) and walks fz rows, forming
+// p = z + beta p_old once per cell; a cell's x-neighbours' p and its right face come
+// from the lane's other column or, across the pair boundary, from the neighbouring
+// lane by a DPP shift, its y-neighbours from the lane's own registers, so every row of
+// z, p_old and the faces is read once.  q follows k_cg_pq's operand order (a boundary
+// face's stored weight is 0 and the cell past it holds p = 0).  One partial of p . q
+// per window, summed in a fixed order (each lane's rows in turn, even column first,
+// then a butterfly over the wavefront); a separate finalize sums the partials.
+template <bool MIXED>
+__global__ void __launch_bounds__(64)
+k_cg_pq2m(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fz) {
+    constexpr int NP = kMarchNP, HX = 2, FX = NP - 2 * HX;
+    constexpr int PF = 2, NB = PF + 3;                   // rows zt + 2 .. zt - 2
+    using V2 = double __attribute__((ext_vector_type(2)));
+    using ZT = std::conditional_t<MIXED, float, double>;
+    using Z2 = ZT __attribute__((ext_vector_type(2)));
+    const int l = threadIdx.x;
+    const XcdOrder order(jl.total);
+    for (int kk = order.first(); order.more(kk); kk += order.per) {
+        const int tt = order.tile(kk);
+        const int jb = find_job(jl.prefix, jl.njobs, tt);
+        const LevelDesc& d = L[job_level(jl, jb)];
+        GridState& g = S[d.sidx];
+        if (!g.active) continue;                                      // uniform per window
+        const int lt = tt - job_start(jl, jb);
+        const bool restart = g.iter == 0;                             // p = z (the old direction is not read)
+        const double beta = g.beta;
+        const int par = g.iter & 1;
+        const gptr<double> Pn = as_global(d.P[par]);
+        const gptr<double> Po = as_global(d.P[par ^ 1]);
+        const gptr<double> Qg = as_global(d.Q);
+        const gptr<ZT> zg = as_global(MIXED ? (ZT*)d.x32 : (ZT*)d.x);
+        const gptr<double> w0g = as_global(d.w[0]), w1g = as_global(d.w[1]);
+        const int nx = d.n[0], ny = d.n[1];
+        const int tx_n = (nx + FX - 1) / FX;
+        const int gx0 = (lt % tx_n) * FX - HX;
+        const int z0 = (lt / tx_n) * fz, z1 = min(z0 + fz, ny);
+        const int zs = z0 - 1, ze = z1 + 1;
+        const int ge = gx0 + 2 * l;
+        const bool inx = ge >= 0 && ge < nx;                          // nx even: both columns or neither
+        const int pc = min(max(ge, 0), nx - 2);
+        const bool own = inx && l >= HX / 2 && l < (NP - HX) / 2;
+        ZT Ze[NB], Zo[NB];
+        double Oe[NB], Oo[NB], Pe[NB], Pq[NB], W0e[NB], W0o[NB], W1e[NB], W1o[NB];
+        unroll<NB>([&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            Ze[q] = Zo[q] = ZT(0);
+            Oe[q] = Oo[q] = Pe[q] = Pq[q] = W0e[q] = W0o[q] = W1e[q] = W1o[q] = 0.0;
+        });
+        auto load = [&](auto Sl, int gj) {
+            constexpr int q = decltype(Sl)::value;
+            const long idx = pc + (long)nx * min(max(gj, 0), ny - 1);
+            const Z2 z2 = *(const gptr<Z2>)(zg + idx);
+            const V2 u2 = *(const gptr<V2>)(w0g + idx);
+            const V2 v2 = *(const gptr<V2>)(w1g + idx);
+            Ze[q] = z2.x;
+            Zo[q] = z2.y;
+            W0e[q] = u2.x;
+            W0o[q] = u2.y;
+            W1e[q] = v2.x;
+            W1o[q] = v2.y;
+            if (!restart) {
+                const V2 o2 = *(const gptr<V2>)(Po + idx);
+                Oe[q] = o2.x;
+                Oo[q] = o2.y;
+            }
+        };
+        double acc = 0.0;
+        auto step = [&](auto Qc, int zt) {
+            constexpr int q = decltype(Qc)::value, q1 = (q + NB - 1) % NB, q2 = (q + NB - 2) % NB;
+            {
+                // row zt enters: its p (zero outside the level)
+                const bool in = inx && zt >= 0 && zt < ny;
+                const double pe = restart ? (double)Ze[q] : (double)Ze[q] + beta * Oe[q];
+                const double po = restart ? (double)Zo[q] : (double)Zo[q] + beta * Oo[q];
+                Pe[q] = in ? pe : 0.0;
+                Pq[q] = in ? po : 0.0;
+                W0e[q] = in ? W0e[q] : 0.0;
+                W0o[q] = in ? W0o[q] : 0.0;
+                W1e[q] = in ? W1e[q] : 0.0;
+                W1o[q] = in ? W1o[q] : 0.0;
+            }
+            load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
+            // q of row zt - 1
+            const double pe = Pe[q1], po = Pq[q1];
+            const double pl = lane_nb<true>(po), pr = lane_nb<false>(pe), wr = lane_nb<false>(W0e[q1]);
+            double qe = pe;
+            qe += W0e[q1] * (pe - pl);
+            qe += W0o[q1] * (pe - po);
+            qe += W1e[q1] * (pe - Pe[q2]);
+            qe += W1e[q] * (pe - Pe[q]);
+            double qo = po;
+            qo += W0o[q1] * (po - pe);
+            qo += wr * (po - pr);
+            qo += W1o[q1] * (po - Pq[q2]);
+            qo += W1o[q] * (po - Pq[q]);
+            const int r = zt - 1;
+            if (own && r >= z0 && r < z1) {
+                const long idx = ge + (long)nx * r;
+                V2 p2, q2v;
+                p2.x = pe;
+                p2.y = po;
+                q2v.x = qe;
+                q2v.y = qo;
+                *(gptr<V2>)(Pn + idx) = p2;
+                *(gptr<V2>)(Qg + idx) = q2v;
+                acc += pe * qe;
+                acc += po * qo;
+            }
+        };
+        static_assert(PF == 2, "the prologue below loads two rows");
+        load(std::integral_constant<int, 0>{}, zs);
+        load(std::integral_constant<int, 1>{}, zs + 1);
+        int zb = zs;
+        for (; zb + NB <= ze; zb += NB) unroll<NB>([&](auto Qc) { step(Qc, zb + decltype(Qc)::value); });
+        unroll<NB - 1>([&](auto Qc) {
+            if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
+        });
+        // fixed-order butterfly: every lane ends with the same sum (a + b = b + a exactly)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (l == 0) d.part[lt] = acc;
+    }
+}
+
 template <int DIM, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl, int fin, double rtol,
@@ -3222,6 +3350,15 @@ void launch_cg_pq3(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int
     const int g = blocks_for_xcd(jl.total, nblk);
     if (mixed) hipLaunchKernelGGL((k_cg_pq3<true>), dim3(g), dim3(1024), 0, s, L, S, jl, fz);
     else hipLaunchKernelGGL((k_cg_pq3<false>), dim3(g), dim3(1024), 0, s, L, S, jl, fz);
+}
+
+void launch_cg_pq2m(bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fz, hipStream_t s) {
+    if (jl.total <= 0) return;
+    // z, the old direction and the two face arrays read once; p and q written
+    if (acct_add(jl.cells * ((mixed ? 4.0 : 8.0) + 8.0 + 16.0 + 16.0))) return;
+    const int g = blocks_for_xcd(jl.total, jl.total);           // one wavefront per window
+    if (mixed) hipLaunchKernelGGL((k_cg_pq2m<true>), dim3(g), dim3(64), 0, s, L, S, jl, fz);
+    else hipLaunchKernelGGL((k_cg_pq2m<false>), dim3(g), dim3(64), 0, s, L, S, jl, fz);
 }
 
 void launch_cg_update(int dim, bool mixed, const LevelDesc* L, GridState* S, JobList jl, int fin, double rtol, int max_cycles,

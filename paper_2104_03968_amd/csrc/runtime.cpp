@@ -339,10 +339,27 @@ static void build_lists(Plan& p) {
         int64_t all_tiles = 0;
         for (size_t j = 0; j + 1 < D.l0_cell.prefix.size(); ++j) all_tiles += D.l0_cell.prefix[j + 1] - D.l0_cell.prefix[j];
         D.fold = !D.fin_fused && max_tiles <= kFoldMaxTiles && all_tiles <= kCellBlocks;
-        // 3D grids with zero-flux operators (no Dirichlet couplings, no wrapped neighbours)
-        // run the CG direction update as a z-march; its plane depth balances the blocks
-        // over the compute units (rounds of one block per unit, fz + 2 steps each)
+        // grids with zero-flux operators (no Dirichlet couplings, no wrapped neighbours) run
+        // the CG direction update as a march when its reductions finish in a k_finalize
+        // launch: 3D as a z-march, its plane depth balancing the blocks over the compute
+        // units (rounds of one block per unit, fz + 2 steps each)
         D.pq3.prefix.assign(1, 0);
+        bool even_rows = true;                       // 2D: rows of an even cell count load as pairs
+        for (int32_t li : D.l0_cell.levels) even_rows = even_rows && p.levels[li].n[0] % 2 == 0;
+        if (D.dim == 2 && even_rows && !p.nb_bc() && !D.fin_fused && !D.fold && !D.l0_cell.empty()) {
+            // 2D: a row march, one wavefront per window; rounds of about kPq2Waves windows
+            // per compute unit, fz + 2 steps each
+            int64_t best = -1;
+            for (int fz : {16, 32, 64, 128}) {
+                int64_t tiles = 0;
+                for (int32_t li : D.l0_cell.levels) tiles += pq2_tiles(p.levels[li].n, fz);
+                const int64_t per = (int64_t)p.ncu * kPq2Waves;
+                const int64_t cost = ((tiles + per - 1) / per) * (fz + 2);
+                if (best < 0 || cost < best) { best = cost; D.fz_pq = fz; }
+            }
+            D.pq3.levels = D.l0_cell.levels;
+            for (int32_t li : D.pq3.levels) D.pq3.prefix.push_back(D.pq3.prefix.back() + pq2_tiles(p.levels[li].n, D.fz_pq));
+        }
         if (D.dim == 3 && !p.nb_bc() && !D.fin_fused && !D.fold && !D.l0_cell.empty()) {
             int64_t best = -1;
             for (int fz : {8, 16, 32, 64}) {
@@ -724,7 +741,8 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
             if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
             if (!D.pq3.empty()) {
-                launch_cg_pq3(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, cell_blocks(p), s);
+                if (dim == 3) launch_cg_pq3(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, cell_blocks(p), s);
+                else launch_cg_pq2m(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, s);
                 launch_finalize(p.dL, p.dS, D.pq3.dev, FIN_PQ, rt, mc, s);
             } else {
                 launch_cg_pq(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_PQ : (D.fold ? kFinFold : -1), rt, mc,
@@ -1734,6 +1752,9 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     for (const auto& D : p.dl)
         for (size_t d = 0; d < D.march.size(); ++d) m2 += D.march[d] ? 1 : 0;
     out->march_levels = m2;
+    out->pq_rows = 0;
+    for (const auto& D : p.dl)
+        if (!D.pq3.empty()) out->pq_rows = D.fz_pq;
     return FLD_OK;
 }
 

@@ -1,4 +1,4 @@
-"""The row-marching fused 2D level kernels (k_march2) against the LDS-tile ones: the
+"""The row-marching 2D kernels.  The fused level kernels (k_march2) against the LDS-tile ones: the
 same operand order on every cell update and residual, so a step through either gives
 bitwise equal results, at every sweep count, in both precisions and under CG, plain
 V-cycles and the full-multigrid start; and the default rule picks the march only on
@@ -67,3 +67,44 @@ def test_default_rule_marches_only_where_windows_are_many():
     assert tiles.tuning()["march_levels"] == 0
     for p in (big, one, forced, tiles):
         p.close()
+
+
+# The row-march CG direction update (k_cg_pq2m) runs on 2D plans whose reductions finish
+# in a k_finalize launch (too many level-0 tiles to fold), zero-flux faces and even row
+# lengths.  Its p . q partials are per window, so its sums round differently from the
+# cell-tile kernel's: parity is against the oracle (1e-10 relative L2, the step target)
+# and against each grid solved alone (cell-tile kernel), not bitwise.
+def _big_batch(seed, odd=False):
+    shapes = [(512, 512)] * 33 + [(384, 640), (256, 1024)]      # 8944 level-0 tiles: no folding
+    if odd:
+        shapes[5] = (512, 511)
+    return [W.random_grid(s, seed + i, dt=2e-3 * (1 + i % 4)) for i, s in enumerate(shapes)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pq_march_meets_the_oracle(precision):
+    grids = _big_batch(650000)
+    plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids], precision=precision)
+    assert plan.tuning()["pq_rows"] > 0
+    plan.close()
+    pick = (0, 17, 33, 34)
+    rtol = min(1e-10 / O.q_b(grids[i].E) for i in pick)
+    xs, st, rc = run_step(grids, precision=precision, rtol=rtol)
+    assert rc == 0, [s for s in st if s["status"] != 0][:2]
+    for i in pick:
+        x_or, _ = O.diffusion_step(grids[i].E, grids[i].kappa_rho, grids[i].dt, grids[i].h)
+        assert rel_l2(xs[i], x_or) <= 1e-10, (i, rel_l2(xs[i], x_or))
+        (x1,), _, rc1 = run_step([grids[i]], precision=precision, rtol=rtol)
+        assert rc1 == 0 and rel_l2(xs[i], x1) <= 2e-10
+
+
+def test_pq_march_skips_odd_rows():
+    grids = _big_batch(651000, odd=True)
+    plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids])
+    assert plan.tuning()["pq_rows"] == 0
+    plan.close()
+    rtol = 1e-10 / O.q_b(grids[5].E)
+    xs, st, rc = run_step(grids, rtol=rtol)
+    assert rc == 0
+    x_or, _ = O.diffusion_step(grids[5].E, grids[5].kappa_rho, grids[5].dt, grids[5].h)
+    assert rel_l2(xs[5], x_or) <= 1e-10
