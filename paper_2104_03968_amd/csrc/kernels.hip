@@ -1858,7 +1858,9 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 t.w0[s0][ly][lx] = W0[q];
                 t.w1[s0][ly][lx] = W1[q];
             }
-            if (zt + PF < ze) load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
+            // issued on every step (the plane is clamped): a conditional load makes the
+            // compiler's wait before a plane's first use cover the next plane's loads too
+            load(std::integral_constant<int, (q + PF) % NB>{}, zt + PF);
             __syncthreads();
             // C: colour c0 on plane zt - 1
             const int p1 = zt - 1;
@@ -1941,17 +1943,15 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 }
             }
         };
-        static_assert(PF == 2 && NB == 6, "the prologue and the unrolled march below assume these");
+        static_assert(PF == 2, "the prologue below loads two planes");
         load(std::integral_constant<int, 0>{}, zs);
         load(std::integral_constant<int, 1>{}, zs + 1);
-        for (int zb = zs; zb < ze; zb += NB) {
-            step(std::integral_constant<int, 0>{}, zb);
-            if (zb + 1 < ze) step(std::integral_constant<int, 1>{}, zb + 1);
-            if (zb + 2 < ze) step(std::integral_constant<int, 2>{}, zb + 2);
-            if (zb + 3 < ze) step(std::integral_constant<int, 3>{}, zb + 3);
-            if (zb + 4 < ze) step(std::integral_constant<int, 4>{}, zb + 4);
-            if (zb + 5 < ze) step(std::integral_constant<int, 5>{}, zb + 5);
-        }
+        // whole rounds of NB steps without a branch between them, then the last steps
+        int zb = zs;
+        for (; zb + NB <= ze; zb += NB) unroll<NB>([&](auto Qc) { step(Qc, zb + decltype(Qc)::value); });
+        unroll<NB - 1>([&](auto Qc) {
+            if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
+        });
         __syncthreads();                                       // the slots are reused by the next tile
     }
 }
@@ -2583,10 +2583,10 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
             constexpr int q = decltype(Sl)::value;
             const long idx = cxy + min(max(gk, 0), n2 - 1) * sz;
             Z[q] = zv[idx];
-            if (!restart) PO[q] = Po[idx];
             W0[q] = w0g[idx];
             W1[q] = w1g[idx];
             W2[q] = w2g[idx];
+            if (!restart) PO[q] = Po[idx];        // last: the conditional load's wait stays exact
         };
         double acc = 0.0;
         auto step = [&](auto Sc, int zt) {
@@ -2605,7 +2605,7 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
                     sw1[s0][ly][lx] = W1[q];
                 }
             }
-            if (zt + 2 < ze) load(std::integral_constant<int, (q + 2) % NB>{}, zt + 2);
+            load(std::integral_constant<int, (q + 2) % NB>{}, zt + 2);   // on every step (clamped plane)
             __syncthreads();
             const int p1 = zt - 1;
             if (p1 >= z0 && p1 < z1 && inner && in_xy) {
@@ -2626,13 +2626,11 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         };
         load(std::integral_constant<int, 0>{}, zs);
         load(std::integral_constant<int, 1>{}, zs + 1);
-        for (int zb = zs; zb < ze; zb += NB) {
-            step(std::integral_constant<int, 0>{}, zb);
-            if (zb + 1 < ze) step(std::integral_constant<int, 1>{}, zb + 1);
-            if (zb + 2 < ze) step(std::integral_constant<int, 2>{}, zb + 2);
-            if (zb + 3 < ze) step(std::integral_constant<int, 3>{}, zb + 3);
-            if (zb + 4 < ze) step(std::integral_constant<int, 4>{}, zb + 4);
-        }
+        int zb = zs;
+        for (; zb + NB <= ze; zb += NB) unroll<NB>([&](auto Qc) { step(Qc, zb + decltype(Qc)::value); });
+        unroll<NB - 1>([&](auto Qc) {
+            if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
+        });
         double unused = 0.0;
         block_sum2<1024>(acc, unused, sh);                 // its barriers also free the slots
         if (threadIdx.x == 0) d.part[lt] = acc;
