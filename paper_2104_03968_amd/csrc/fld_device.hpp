@@ -323,8 +323,10 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
                 int threads, int nblk, hipStream_t s);
 // The row-marching form of the same passes (down: nu sweeps from zero or the stored
 // iterate, restricting; up: prolongation and nu sweeps), for levels with many tiles.
+// rz (FP64 up pass of level 0 under CG, where b is the residual): each window also
+// leaves its partial of b . x (r . z) in the level's partials, for a k_finalize
 void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
-                   int nblk, hipStream_t s);
+                   int nblk, hipStream_t s, int rz = 0);
 // Fused 3D sweeps (one red-black sweep per launch, colour c0 first), reading x (or xs
 // with from_xs) and writing the other; modes: 0 from the iterate, 1 from zero, 2 / 3 the
 // same plus restriction of the final residual, 4 from the iterate plus the prolonged

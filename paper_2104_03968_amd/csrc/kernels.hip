@@ -1559,12 +1559,14 @@ __device__ __forceinline__ double lane_nb(double v) {
 // averages the final residual of each row pair onto the coarse right-hand side (the
 // residual of row r one step after its last update; a lane's two columns are the
 // two fine columns of one coarse cell); the up pass (halo 2 nu) starts from xs plus
-// the prolonged coarse correction and writes x.  A window recomputes no rows, only
-// the x halo and its march's halo rows.
+// the prolonged coarse correction and writes x; on level 0 under CG (FP64, b = r) it
+// can also sum b . x over the window's interior (each lane's rows in turn, even
+// column first, then a butterfly) into one partial of r . z.  A window recomputes no
+// rows, only the x halo and its march's halo rows.
 // ---------------------------------------------------------------------------
 template <typename T, int NU, bool DOWN, bool LOADX>
 __global__ void __launch_bounds__(64)
-k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int fz) {
+k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int fz, int rz) {
     constexpr int NP = kMarchNP;
     constexpr int SS = 2 * NU;                       // half sweeps of the pass
     constexpr int H = march_halo(NU, DOWN);
@@ -1631,6 +1633,7 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
             }
         };
         T acc = T(0);                                 // the lane's coarse cell of a row pair
+        double rzacc = 0.0;                           // up pass, rz: the lane's b . x
         auto step = [&](auto Qc, int zt) {
             constexpr int q = decltype(Qc)::value;   // register slot of row zt; zt = q (mod 2)
             // the column that updates: down passes take colour 0 first, so cell (i, r) of
@@ -1679,6 +1682,12 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                     o2.x = Xe[qf];
                     o2.y = Xo[qf];
                     *(gptr<V2>)(xout + ge + (long)nx * rf) = o2;
+                    if constexpr (!DOWN && std::is_same_v<T, double>) {
+                        if (rz) {
+                            rzacc += Be[qf] * Xe[qf];
+                            rzacc += Bo[qf] * Xo[qf];
+                        }
+                    }
                 }
             }
             if constexpr (DOWN) {
@@ -1712,6 +1721,14 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         unroll<NB - 1>([&](auto Qc) {
             if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
         });
+        if constexpr (!DOWN && std::is_same_v<T, double>) {
+            if (rz) {
+                // fixed-order butterfly: every lane ends with the same sum
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) rzacc += __shfl_xor(rzacc, off, 64);
+                if (l == 0) d.part[lt] = rzacc;
+            }
+        }
     }
 }
 
@@ -3248,7 +3265,7 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
 }
 
 void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
-                   int nblk, hipStream_t s) {
+                   int nblk, hipStream_t s, int rz) {
     if (jl.total <= 0) return;
     // the same operands as the fused tile passes (k_down2 / k_up2)
     if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) *
@@ -3258,7 +3275,7 @@ void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
     // them back to back while other compute units may idle
     (void)nblk;
     const int g = blocks_for_xcd(jl.total, jl.total);
-#define FLD_MARCH(T_, D_, X_) hipLaunchKernelGGL((k_march2<T_, NU, D_, X_>), dim3(g), dim3(64), 0, s, L, S, jl, kMarchFz)
+#define FLD_MARCH(T_, D_, X_) hipLaunchKernelGGL((k_march2<T_, NU, D_, X_>), dim3(g), dim3(64), 0, s, L, S, jl, kMarchFz, rz)
     FLD_NU_DISPATCH(nu, {
         if (down && load_x) { if (fp32) FLD_MARCH(float, true, true); else FLD_MARCH(double, true, true); }
         else if (down) { if (fp32) FLD_MARCH(float, true, false); else FLD_MARCH(double, true, false); }

@@ -605,7 +605,7 @@ static void layout(Plan& p) {
 // stage) over the grids with a level there, with the given tail / coarsest lists;
 // load0: the level at d0 starts from its stored iterate instead of zero.
 static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int load0, const JobList& tail,
-                            const JobList& coarsest) {
+                            const JobList& coarsest, bool rz0 = false) {
     const bool f32 = p.mixed;
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;   // level-0 V-cycle starts from the iterate
     const int dim = D.dim;
@@ -653,7 +653,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             continue;
         }
         if (D.fused && D.march[d]) {
-            launch_march2(f32, p.dL, p.dS, D.mup[d].dev, nu2, 0, 0, p.nblk, s);
+            launch_march2(f32, p.dL, p.dS, D.mup[d].dev, nu2, 0, 0, p.nblk, s, rz0 && d == 0 ? 1 : 0);
             continue;
         }
         if (D.fused) {
@@ -676,9 +676,18 @@ static bool level0_reads_iterate(const Plan& p, const DimLists& D) {
     return !D.fused;
 }
 
-static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s) {
+static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s, bool rz0 = false) {
     const int plain64 = (!p.krylov && !p.mixed) ? 1 : 0;
-    enqueue_mg_from(p, D, s, 0, plain64, D.tail.dev, D.coarsest.dev);
+    enqueue_mg_from(p, D, s, 0, plain64, D.tail.dev, D.coarsest.dev, rz0);
+}
+
+// Whether the level-0 up pass of the CG preconditioner also forms the r . z partials
+// (one per window, summed by a k_finalize over the march list): FP64 (b is r), a row
+// march on level 0 of every grid (a grid without a coarse level has no up pass), and
+// reductions that finish in a k_finalize launch anyway.
+static bool rz_in_march(const Plan& p, const DimLists& D) {
+    return p.krylov && !p.mixed && !D.fin_fused && !D.fold && D.fused && !D.march.empty() && D.march[0] &&
+           D.mup[0].levels.size() == D.l0_cell.levels.size();
 }
 
 // Full-multigrid cycle on the V-cycle's level-0 arrays (Sec. 3.4 starts each solve
@@ -729,7 +738,8 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
     for (auto& D : p.dl) {
         if (D.l0_cell.empty()) continue;
         const int dim = D.dim;
-        enqueue_mg(p, D, s);
+        const bool rzm = rz_in_march(p, D);
+        enqueue_mg(p, D, s, rzm);
         const JobList& l0 = D.l0_cell.dev;
         if (p.krylov) {
             const double rt = p.opts.rtol;
@@ -738,8 +748,12 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             // the r.z and p.q reductions finish in the last tile's block (few tiles), in the
             // next kernel's blocks (D.fold), or in a k_finalize launch
             const bool fin_launch = !ff && !D.fold;
-            launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
-            if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
+            if (rzm) {
+                launch_finalize(p.dL, p.dS, D.mup[0].dev, FIN_RZ, rt, mc, s);
+            } else {
+                launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
+                if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
+            }
             if (!D.pq3.empty()) {
                 if (dim == 3) launch_cg_pq3(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, cell_blocks(p), s);
                 else launch_cg_pq2m(p.mixed, p.dL, p.dS, D.pq3.dev, D.fz_pq, s);

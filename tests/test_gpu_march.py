@@ -99,6 +99,8 @@ def test_pq_march_meets_the_oracle(precision):
 
 
 def test_pq_march_skips_odd_rows():
+    """An odd row length keeps the cell-tile CG kernels; that grid has no coarse level
+    (no up pass), so r . z is not formed in the march either."""
     grids = _big_batch(651000, odd=True)
     plan = fld.Plan([g.E.shape for g in grids], h=[g.h for g in grids])
     assert plan.tuning()["pq_rows"] == 0
