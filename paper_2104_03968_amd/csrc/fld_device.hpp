@@ -332,8 +332,10 @@ void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
 // same plus restriction of the final residual, 4 from the iterate plus the prolonged
 // coarse correction.
 bool fused3_supported(bool fp32);
+// rz (the last up sweep of level 0 under FP64 CG, a plain SW_LOAD sweep, where b is the
+// residual): each window also leaves its partial of b . x (r . z) in the level's partials
 void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
-                   int from_xs, int fz, int nblk, hipStream_t s);
+                   int from_xs, int fz, int nblk, hipStream_t s, int rz = 0);
 // bc: the plan has Dirichlet or periodic faces.
 void launch_tail(int dim, bool fp32, int bc, const LevelDesc* L, const GridState* S, JobList jl, size_t smem,
                  int nu1, int nu2, int plain64, hipStream_t s);

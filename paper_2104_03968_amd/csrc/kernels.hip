@@ -1790,7 +1790,7 @@ struct Sweep3Lds {
 template <typename T, int MODE>
 __global__ void __launch_bounds__(1024)
 k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobList jl, int c0, int from_xs,
-         int fz) {
+         int fz, int rz) {
     using M = Sweep3Mode<MODE>;
     constexpr int H = M::H, HC = M::HC, HX = M::HX, FX = M::FX, FY = M::FY, R = M::R;
     constexpr int PX = M::PX, PY = M::PY;
@@ -1799,6 +1799,10 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
     constexpr int PF = 2, NB = PF + 4;
     static_assert(HX == H, "every window position is read by a neighbour");
     __shared__ Sweep3Lds<T, R, PX, PY, M::RESTR> t;
+    // the last up sweep of level 0 under FP64 CG (rz): each thread's b . x, summed in a
+    // fixed order into one partial of r . z per window
+    constexpr bool RZ = MODE == SW_LOAD && std::is_same_v<T, double>;
+    __shared__ double shrz[RZ ? PX * PY : 1];
     const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
     // rings outside the interior: o >= H is interior; o >= H - HC takes the first colour,
     // o >= H - HC + 1 the second
@@ -1853,6 +1857,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
             if (M::PROL) CC[q] = cx[ccol + (long)cn0 * cn1 * (kc >> 1)];
         };
         T racc = T(0);
+        double rzacc = 0.0;
         // coarse cell of the restriction owners: thread e < (FX/2)(FY/2)
         const int rci = threadIdx.x % (FX / 2), rcj = threadIdx.x / (FX / 2);
         const bool rown = M::RESTR && threadIdx.x < (FX / 2) * (FY / 2) && (gx0 + H) / 2 + rci < cn0 &&
@@ -1921,7 +1926,12 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 if (M::RESTR) t.x[s2][ly][lx] = X[q2];
             }
             // plane zt - 2 is final on the interior
-            if (p2 >= z0 && p2 < z1 && in_r && in_xy) xout[cxy + p2 * sz] = X[q2];
+            if (p2 >= z0 && p2 < z1 && in_r && in_xy) {
+                xout[cxy + p2 * sz] = X[q2];
+                if constexpr (RZ) {
+                    if (rz) rzacc += B[q2] * X[q2];
+                }
+            }
             if (M::RESTR) {
                 // residual of the final iterate on plane zt - 3 (its in-plane neighbours and the
                 // plane below from the slots, the plane above from the registers)
@@ -1970,6 +1980,24 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
             if (zb + decltype(Qc)::value < ze) step(Qc, zb + decltype(Qc)::value);
         });
         __syncthreads();                                       // the slots are reused by the next tile
+        if constexpr (RZ) {
+            if (rz) {
+                // thread order: lane l of wave 0 sums threads 16 l .. 16 l + 15, then the wave
+                constexpr int NTH = PX * PY, PER = (NTH + 63) / 64;
+                shrz[threadIdx.x] = rzacc;
+                __syncthreads();
+                if (threadIdx.x < 64) {
+                    double v = 0.0;
+                    for (int i = 0; i < PER; ++i) {
+                        const int th = threadIdx.x * PER + i;
+                        if (th < NTH) v += shrz[th];
+                    }
+                    v = wave_sum(v);
+                    if (threadIdx.x == 0) d.part[lt] = v;
+                }
+                __syncthreads();                               // shrz is reused by the next tile
+            }
+        }
     }
 }
 
@@ -3155,7 +3183,7 @@ bool fused3_supported(bool fp32) {
 }
 
 void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int mode, int c0,
-                   int from_xs, int fz, int nblk, hipStream_t s) {
+                   int from_xs, int fz, int nblk, hipStream_t s, int rz) {
     if (jl.total <= 0) return;
     {   // b and three face arrays read, the iterate read (not from zero) and written; the
         // restricting sweep writes the coarse b and x, the prolonging one reads coarse x
@@ -3171,9 +3199,9 @@ void launch_sweep3(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
 #define FLD_SWEEP3(M)                                                                                   \
     do {                                                                                               \
         if (fp32) hipLaunchKernelGGL((k_sweep3<float, M>), dim3(g), dim3(Sweep3Mode<M>::PX * Sweep3Mode<M>::PY), \
-                                     0, s, L, S, jl, c0, from_xs, fz);                                 \
+                                     0, s, L, S, jl, c0, from_xs, fz, rz);                             \
         else hipLaunchKernelGGL((k_sweep3<double, M>), dim3(g), dim3(Sweep3Mode<M>::PX * Sweep3Mode<M>::PY), \
-                                0, s, L, S, jl, c0, from_xs, fz);                                      \
+                                0, s, L, S, jl, c0, from_xs, fz, rz);                                  \
     } while (0)
     switch (mode) {
         case SW_LOAD: FLD_SWEEP3(SW_LOAD); break;

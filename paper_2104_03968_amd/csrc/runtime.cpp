@@ -647,9 +647,11 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
     for (int d = D.maxdepth - 1; d >= d0; --d) {
         const int nu1 = d == 0 ? p.opts.nu1 : p.nuc1, nu2 = d == 0 ? p.opts.nu2 : p.nuc2;
         if (d < L3) {
-            for (int k = nu1 + 1; k <= nu1 + nu2; ++k)
-                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, k == nu1 + 1 ? 4 : 0, 1, k % 2 == 0, D.fz_s[d], p.nblk,
-                              s);
+            for (int k = nu1 + 1; k <= nu1 + nu2; ++k) {
+                const int mode = k == nu1 + 1 ? 4 : 0;
+                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, mode, 1, k % 2 == 0, D.fz_s[d], p.nblk, s,
+                              rz0 && d == 0 && k == nu1 + nu2 && mode == 0 ? 1 : 0);
+            }
             continue;
         }
         if (D.fused && D.march[d]) {
@@ -682,13 +684,18 @@ static void enqueue_mg(Plan& p, DimLists& D, hipStream_t s, bool rz0 = false) {
 }
 
 // Whether the level-0 up pass of the CG preconditioner also forms the r . z partials
-// (one per window, summed by a k_finalize over the march list): FP64 (b is r), a row
-// march on level 0 of every grid (a grid without a coarse level has no up pass), and
-// reductions that finish in a k_finalize launch anyway.
+// (one per window, summed by a k_finalize over the pass's list): FP64 (b is r), reductions
+// that finish in a k_finalize launch anyway, and every grid's level 0 in the pass (a grid
+// without a coarse level has none): in 2D a row march, in 3D a fused last sweep (a plain
+// one: nu2 >= 2).
 static bool rz_in_march(const Plan& p, const DimLists& D) {
-    return p.krylov && !p.mixed && !D.fin_fused && !D.fold && D.fused && !D.march.empty() && D.march[0] &&
-           D.mup[0].levels.size() == D.l0_cell.levels.size();
+    if (!p.krylov || p.mixed || D.fin_fused || D.fold) return false;
+    if (D.dim == 3)
+        return D.fused3 && p.sweep3 && D.levels3 >= 1 && p.opts.nu2 >= 2 &&
+               D.sw3[0].levels.size() == D.l0_cell.levels.size();
+    return D.fused && !D.march.empty() && D.march[0] && D.mup[0].levels.size() == D.l0_cell.levels.size();
 }
+static const JobList& rz_list(const DimLists& D) { return D.dim == 3 ? D.sw3[0].dev : D.mup[0].dev; }
 
 // Full-multigrid cycle on the V-cycle's level-0 arrays (Sec. 3.4 starts each solve
 // with one): the right-hand side averaged down to every grid's deepest wide level,
@@ -749,7 +756,7 @@ static void enqueue_cycle(Plan& p, hipStream_t s) {
             // next kernel's blocks (D.fold), or in a k_finalize launch
             const bool fin_launch = !ff && !D.fold;
             if (rzm) {
-                launch_finalize(p.dL, p.dS, D.mup[0].dev, FIN_RZ, rt, mc, s);
+                launch_finalize(p.dL, p.dS, rz_list(D), FIN_RZ, rt, mc, s);
             } else {
                 launch_cg_rz(dim, p.mixed, p.dL, p.dS, l0, ff ? FIN_RZ : -1, rt, mc, cell_blocks(p), s);
                 if (fin_launch) launch_finalize(p.dL, p.dS, l0, FIN_RZ, rt, mc, s);
