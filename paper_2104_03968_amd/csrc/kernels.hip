@@ -1784,7 +1784,7 @@ struct Sweep3Lds {
     T x[R][PY][PX];
     T w0[R][PY][PX];
     T w1[R][PY][PX];
-    T res[RESTR ? PY : 1][PX];
+    T res[RESTR ? 2 : 1][RESTR ? PY : 1][PX];   // residual planes of two steps
 };
 
 template <typename T, int MODE>
@@ -1820,7 +1820,9 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         const int tx = lt % tx_n, rest = lt / tx_n;
         const int gx0 = tx * FX - H, gy0 = (rest % ty_n) * FY - H;
         const int z0 = (rest / ty_n) * fz, z1 = min(z0 + fz, n2);
-        const int zs = z0 - HX, ze = z1 + HX;          // planes stored, and steps: [zs, ze)
+        // planes stored, and steps: [zs, ze); a restricting sweep takes one step more, in
+        // which the owners add the last residual plane
+        const int zs = z0 - HX, ze = z1 + HX + (M::RESTR ? 1 : 0);
         const int gx = gx0 + lx, gy = gy0 + ly;
         const bool in_xy = gx >= 0 && gx < n0 && gy >= 0 && gy < n1;
         const long sy = n0, sz = (long)n0 * n1;
@@ -1933,11 +1935,29 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                 }
             }
             if (M::RESTR) {
+                // the owners add the residual plane formed one step earlier (this step's
+                // barrier ordered its stores before these loads)
+                const int pp = zt - 4;
+                if (pp >= z0 && pp < z1 && rown) {
+                    const int ax = H + 2 * rci, ay = H + 2 * rcj, sr = (pp - zs) & 1;
+                    if (((pp - z0) & 1) == 0) racc = T(0);
+                    racc += t.res[sr][ay][ax];
+                    racc += t.res[sr][ay][ax + 1];
+                    racc += t.res[sr][ay + 1][ax];
+                    racc += t.res[sr][ay + 1][ax + 1];
+                    if ((pp - z0) & 1) {
+                        // the coarse level's sweeps start from zero (per-colour kernels read it)
+                        const long cidx = (gx0 + H) / 2 + rci + (long)cn0 * ((gy0 + H) / 2 + rcj +
+                                                                          (long)cn1 * (pp >> 1));
+                        cb[cidx] = racc * T(0.125);
+                        cx[cidx] = T(0);
+                    }
+                }
                 // residual of the final iterate on plane zt - 3 (its in-plane neighbours and the
-                // plane below from the slots, the plane above from the registers)
+                // plane below from the slots, the plane above from the registers), into the
+                // residual plane of this step's parity
                 const int p3 = zt - 3;
-                const bool rp = p3 >= z0 && p3 < z1;                // uniform
-                if (rp) {
+                if (p3 >= z0 && p3 < z1) {                             // uniform
                     T r = T(0);
                     if (in_r && in_xy) {
                         const int s3 = (p3 - zs) % R, s4 = (p3 - 1 - zs) % R;
@@ -1950,23 +1970,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
                         r -= W2[q3] * (xc - t.x[s4][ly][lx]);
                         r -= W2[q2] * (xc - X[q2]);
                     }
-                    t.res[M::RESTR ? ly : 0][lx] = r;
-                    __syncthreads();
-                    if (rown) {
-                        const int ax = H + 2 * rci, ay = H + 2 * rcj;
-                        if (((p3 - z0) & 1) == 0) racc = T(0);
-                        racc += t.res[ay][ax];
-                        racc += t.res[ay][ax + 1];
-                        racc += t.res[ay + 1][ax];
-                        racc += t.res[ay + 1][ax + 1];
-                        if ((p3 - z0) & 1) {
-                            // the coarse level's sweeps start from zero (per-colour kernels read it)
-                            const long cidx = (gx0 + H) / 2 + rci + (long)cn0 * ((gy0 + H) / 2 + rcj +
-                                                                              (long)cn1 * (p3 >> 1));
-                            cb[cidx] = racc * T(0.125);
-                            cx[cidx] = T(0);
-                        }
-                    }
+                    t.res[M::RESTR ? (p3 - zs) & 1 : 0][M::RESTR ? ly : 0][lx] = r;
                 }
             }
         };
