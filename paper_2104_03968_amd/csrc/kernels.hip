@@ -1612,7 +1612,7 @@ k_march2(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         // before a row's first use leaves the next row's loads in flight
         auto load = [&](auto Sl, int gj) {
             constexpr int q = decltype(Sl)::value;
-            const int jc = min(max(gj, 0), ny - 1);
+            const int jc = min(max(min(gj, ze - 1), 0), ny - 1);   // rows past the march: its last (cached)
             const long idx = pc + (long)nx * jc;
             const V2 b2 = *(const gptr<V2>)(bg + idx);
             const V2 u2 = *(const gptr<V2>)(w0g + idx);
@@ -1849,7 +1849,7 @@ k_sweep3(const LevelDesc* __restrict__ L, const GridState* __restrict__ S, JobLi
         // branch-free loads of plane gk at the clamped column (masked when stored)
         auto load = [&](auto Sl, int gk) {
             constexpr int q = decltype(Sl)::value;
-            const int kc = min(max(gk, 0), n2 - 1);
+            const int kc = min(max(min(gk, z1 + HX - 1), 0), n2 - 1);   // planes past the window: its last (cached)
             const long idx = cxy + kc * sz;
             if (M::LOADX) X[q] = xin[idx];
             B[q] = bg[idx];
@@ -2630,7 +2630,7 @@ k_cg_pq3(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl,
         double Z[NB], PO[NB], W0[NB], W1[NB], W2[NB], PV[NB];
         auto load = [&](auto Sl, int gk) {
             constexpr int q = decltype(Sl)::value;
-            const long idx = cxy + min(max(gk, 0), n2 - 1) * sz;
+            const long idx = cxy + min(max(min(gk, ze - 1), 0), n2 - 1) * sz;   // past the march: its last plane
             Z[q] = zv[idx];
             W0[q] = w0g[idx];
             W1[q] = w1g[idx];
@@ -2740,7 +2740,7 @@ k_cg_pq2m(const LevelDesc* __restrict__ L, GridState* __restrict__ S, JobList jl
         });
         auto load = [&](auto Sl, int gj) {
             constexpr int q = decltype(Sl)::value;
-            const long idx = pc + (long)nx * min(max(gj, 0), ny - 1);
+            const long idx = pc + (long)nx * min(max(min(gj, ze - 1), 0), ny - 1);   // past the march: its last row
             const Z2 z2 = *(const gptr<Z2>)(zg + idx);
             const V2 u2 = *(const gptr<V2>)(w0g + idx);
             const V2 v2 = *(const gptr<V2>)(w1g + idx);
