@@ -94,9 +94,11 @@ __host__ __device__ inline int32_t sweep3_tiles(const int32_t n[3], bool restr, 
 // interior columns with one halo position around them, fz planes per block.
 constexpr int kPqPX = 66;
 constexpr int kPqPY = 15;
-// row-march CG direction update (2D level 0): windows of kMarchNP - 4 interior columns,
-// about kPq2Waves of them resident per compute unit
-constexpr int kPq2Waves = 16;
+// row-march CG direction update (2D level 0): windows of kMarchNP - 4 interior columns
+// and kPq2Rows rows
+constexpr int kPq2Rows = 64;
+// plane depth of the level-0 3D sweep that also forms r . z
+constexpr int kRz3Fz = 32;
 __host__ __device__ inline int32_t pq2_tiles(const int32_t n[3], int fz) {
     return ((n[0] + kMarchNP - 5) / (kMarchNP - 4)) * ((n[1] + fz - 1) / fz);
 }

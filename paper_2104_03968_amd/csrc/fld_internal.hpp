@@ -64,6 +64,8 @@ struct DimLists {
     bool fold = false;                         // CG scalars formed in the consuming kernels (mid-sized grids)
     HostList pq3;                              // level 0, marching CG tiles (zero-flux operators): z-march
                                                // (3D) or row march (2D, even rows)
+    HostList rz3;                              // level 0, plain 3D sweep windows of kRz3Fz planes (the
+                                               // last up sweep when it also forms r . z)
     int fz_pq = 16;                            // planes per z-march CG tile
     int maxdepth = 0;
 };

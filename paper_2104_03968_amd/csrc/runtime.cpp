@@ -165,6 +165,12 @@ void finish_fused(const Plan& p, DimLists& D) {
     // to fill the chip: by default only the leading depths whose plain sweep has at least
     // one block per two compute units run fused, the coarser ones per colour (at 256^3 the
     // two finest, as the autotuner also picks)
+    // the last level-0 up sweep under FP64 CG also forms r . z; it marches a fixed plane
+    // depth, so a grid's partials (one per window) do not depend on the tuned one
+    D.rz3.levels = D.sw3.empty() ? std::vector<int32_t>{} : D.sw3[0].levels;
+    D.rz3.prefix.assign(1, 0);
+    for (int32_t li : D.rz3.levels)
+        D.rz3.prefix.push_back(D.rz3.prefix.back() + sweep3_tiles(p.levels[li].n, false, kRz3Fz));
     const int nd = (int)D.sw3.size();
     if (p.sweep3_levels > 0) {
         D.levels3 = std::min(p.sweep3_levels, nd);
@@ -347,16 +353,9 @@ static void build_lists(Plan& p) {
         bool even_rows = true;                       // 2D: rows of an even cell count load as pairs
         for (int32_t li : D.l0_cell.levels) even_rows = even_rows && p.levels[li].n[0] % 2 == 0;
         if (D.dim == 2 && even_rows && !p.nb_bc() && !D.fin_fused && !D.fold && !D.l0_cell.empty()) {
-            // 2D: a row march, one wavefront per window; rounds of about kPq2Waves windows
-            // per compute unit, fz + 2 steps each
-            int64_t best = -1;
-            for (int fz : {16, 32, 64, 128}) {
-                int64_t tiles = 0;
-                for (int32_t li : D.l0_cell.levels) tiles += pq2_tiles(p.levels[li].n, fz);
-                const int64_t per = (int64_t)p.ncu * kPq2Waves;
-                const int64_t cost = ((tiles + per - 1) / per) * (fz + 2);
-                if (best < 0 || cost < best) { best = cost; D.fz_pq = fz; }
-            }
+            // 2D: a row march, one wavefront per window of a fixed height, so that a grid's
+            // p . q partials do not depend on what else the plan holds
+            D.fz_pq = kPq2Rows;
             D.pq3.levels = D.l0_cell.levels;
             for (int32_t li : D.pq3.levels) D.pq3.prefix.push_back(D.pq3.prefix.back() + pq2_tiles(p.levels[li].n, D.fz_pq));
         }
@@ -513,6 +512,7 @@ static void layout(Plan& p) {
     for (auto& D : p.dl) {
         place_list(D.l0_cell);
         place_list(D.pq3);
+        place_list(D.rz3);
         place_list(D.coarsest);
         place_list(D.tail);
         for (auto& l : D.coarsen) place_list(l);
@@ -649,8 +649,9 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
         if (d < L3) {
             for (int k = nu1 + 1; k <= nu1 + nu2; ++k) {
                 const int mode = k == nu1 + 1 ? 4 : 0;
-                launch_sweep3(f32, p.dL, p.dS, D.sw3[d].dev, mode, 1, k % 2 == 0, D.fz_s[d], p.nblk, s,
-                              rz0 && d == 0 && k == nu1 + nu2 && mode == 0 ? 1 : 0);
+                const bool rz = rz0 && d == 0 && k == nu1 + nu2 && mode == 0;
+                launch_sweep3(f32, p.dL, p.dS, rz ? D.rz3.dev : D.sw3[d].dev, mode, 1, k % 2 == 0,
+                              rz ? kRz3Fz : D.fz_s[d], p.nblk, s, rz ? 1 : 0);
             }
             continue;
         }
@@ -695,7 +696,7 @@ static bool rz_in_march(const Plan& p, const DimLists& D) {
                D.sw3[0].levels.size() == D.l0_cell.levels.size();
     return D.fused && !D.march.empty() && D.march[0] && D.mup[0].levels.size() == D.l0_cell.levels.size();
 }
-static const JobList& rz_list(const DimLists& D) { return D.dim == 3 ? D.sw3[0].dev : D.mup[0].dev; }
+static const JobList& rz_list(const DimLists& D) { return D.dim == 3 ? D.rz3.dev : D.mup[0].dev; }
 
 // Full-multigrid cycle on the V-cycle's level-0 arrays (Sec. 3.4 starts each solve
 // with one): the right-hand side averaged down to every grid's deepest wide level,
@@ -930,6 +931,7 @@ int plan_bind(Plan& p, void* dev, size_t bytes, const GridState* init) {
     for (auto& D : p.dl) {
         stage_list(p, D.l0_cell, img);
         stage_list(p, D.pq3, img);
+        stage_list(p, D.rz3, img);
         stage_list(p, D.coarsest, img);
         stage_list(p, D.tail, img);
         for (auto* v : {&D.coarsen, &D.down2, &D.up2, &D.mdn, &D.mup, &D.sw3, &D.sr3, &D.smooth, &D.restrict_,
