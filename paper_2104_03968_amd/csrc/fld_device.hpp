@@ -31,7 +31,7 @@ constexpr int kTailCPT = 4;
 constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 constexpr int kTailWaveCells = 256;                         // tail levels run by one wavefront
 constexpr int kMarchNP = 128;                               // row-marching 2D window: positions (two a lane)
-constexpr int kMarchFz = 64;                                // rows per row-marching window
+constexpr int kMarchFz = 32;                                // rows per row-marching window
 // halo of a row-marching window (even, so that a lane's two columns pair up for the
 // restriction): 2 nu + 2 on the down pass, 2 nu on the up pass; and its interior columns
 __host__ __device__ constexpr int march_halo(int nu, bool down) { return 2 * nu + (down ? 2 : 0); }
@@ -96,7 +96,7 @@ constexpr int kPqPX = 66;
 constexpr int kPqPY = 15;
 // row-march CG direction update (2D level 0): windows of kMarchNP - 4 interior columns
 // and kPq2Rows rows
-constexpr int kPq2Rows = 64;
+constexpr int kPq2Rows = 32;
 // plane depth of the level-0 3D sweep that also forms r . z
 constexpr int kRz3Fz = 32;
 __host__ __device__ inline int32_t pq2_tiles(const int32_t n[3], int fz) {
