@@ -121,11 +121,13 @@ int tiles_smooth(const LevelDesc& d) { return smooth_tiles(d.n); }
 int tiles_one(const LevelDesc&) { return 1; }
 
 
-// Workgroup cap of the level-0 cell kernels (coefficients, residual, CG vectors,
-// output, moments): streaming passes with a reduction per tile, which gain from
-// many workgroups whatever cap the stencil kernels are tuned to.
+// The level-0 cell kernels (coefficients, residual, CG vectors, output, moments) are
+// streaming passes with a reduction per tile: they launch one workgroup per tile,
+// whatever cap the stencil kernels are tuned to.  kCellBlocks bounds the plans whose
+// CG scalars are formed inside the consuming kernels (every block then reads all of
+// its grid's partials).
 constexpr int kCellBlocks = 8192;
-inline int cell_blocks(const Plan& p) { return std::max(p.nblk, kCellBlocks); }
+inline int cell_blocks(const Plan&) { return 1 << 30; }
 
 // A fused 2D depth marches rows when its down pass has at least this many windows per
 // compute unit (fld_opts.fused = 1).
