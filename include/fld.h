@@ -430,6 +430,8 @@ typedef struct fld_tuning {
     int32_t tile_rows_up; /* fused 2D tile rows of the finest level's up pass (tile_rows:
                              its down pass)                                          */
     int32_t march_levels; /* 2D depths whose passes march rows (fused = 1 or 3)      */
+    int32_t march_rows;   /* rows per window of the finest marching depth (32, or 16
+                             where 32-row windows would be too few); 0: none         */
     int32_t pq_rows;      /* rows (2D) or planes (3D) per window of the marching CG
                              direction update of level 0; 0 when the cell-tile kernel
                              runs it (few tiles, or Dirichlet / periodic faces, or a 2D

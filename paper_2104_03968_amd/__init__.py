@@ -99,7 +99,7 @@ class fld_tuning(C.Structure):
                 ("source", C.c_int32), ("candidates", C.c_int32), ("vcycle_us", C.c_double),
                 ("tile_depth", C.c_int32), ("fused3", C.c_int32), ("fused3_levels", C.c_int32),
                 ("tile_rows_coarse", C.c_int32), ("tile_rows_up", C.c_int32), ("march_levels", C.c_int32),
-                ("pq_rows", C.c_int32)]
+                ("march_rows", C.c_int32), ("pq_rows", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

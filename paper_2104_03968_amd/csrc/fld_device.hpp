@@ -32,13 +32,14 @@ constexpr int kTailMaxCoarsest = kTailThreads * kTailCPT;    // 2048 cells
 constexpr int kTailWaveCells = 256;                         // tail levels run by one wavefront
 constexpr int kMarchNP = 128;                               // row-marching 2D window: positions (two a lane)
 constexpr int kMarchFz = 32;                                // rows per row-marching window
+constexpr int kMarchFzShort = 16;                           // rows where windows are few
 // halo of a row-marching window (even, so that a lane's two columns pair up for the
 // restriction): 2 nu + 2 on the down pass, 2 nu on the up pass; and its interior columns
 __host__ __device__ constexpr int march_halo(int nu, bool down) { return 2 * nu + (down ? 2 : 0); }
 __host__ __device__ constexpr int march_fx(int nu, bool down) { return kMarchNP - 2 * march_halo(nu, down); }
-__host__ __device__ inline int32_t march_tiles(const int32_t n[3], int nu, bool down) {
+__host__ __device__ inline int32_t march_tiles(const int32_t n[3], int nu, bool down, int fz) {
     const int fx = march_fx(nu, down);
-    return ((n[0] + fx - 1) / fx) * ((n[1] + kMarchFz - 1) / kMarchFz);
+    return ((n[0] + fx - 1) / fx) * ((n[1] + fz - 1) / fz);
 }
 
 // Tile counts of one level for the two tilings (host and device agree on these).
@@ -328,7 +329,7 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
 // rz (FP64 up pass of level 0 under CG, where b is the residual): each window also
 // leaves its partial of b . x (r . z) in the level's partials, for a k_finalize
 void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
-                   int nblk, hipStream_t s, int rz = 0);
+                   int fz, int nblk, hipStream_t s, int rz = 0);
 // Fused 3D sweeps (one red-black sweep per launch, colour c0 first), reading x (or xs
 // with from_xs) and writing the other; modes: 0 from the iterate, 1 from zero, 2 / 3 the
 // same plus restriction of the final residual, 4 from the iterate plus the prolonged

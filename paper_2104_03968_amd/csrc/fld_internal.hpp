@@ -48,6 +48,7 @@ struct DimLists {
     std::vector<int> thr_dn, thr_up;           // per depth, workgroup size of those tiles (256 or 1024)
     std::vector<HostList> mdn, mup;            // per depth, row-marching windows (same levels)
     std::vector<char> march;                   // per depth: the passes march rows instead of tiles
+    std::vector<int> mfz;                      // per depth, rows per marching window
     bool fused = false;
     std::vector<HostList> sw3, sr3;            // per depth, fused 3D sweep blocks (plain / restricting)
     std::vector<int> fz_r;                     // per depth, planes per block of the restricting sweep

@@ -3297,7 +3297,7 @@ void launch_up2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, i
 }
 
 void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl, int nu, int down, int load_x,
-                   int nblk, hipStream_t s, int rz) {
+                   int fz, int nblk, hipStream_t s, int rz) {
     if (jl.total <= 0) return;
     // the same operands as the fused tile passes (k_down2 / k_up2)
     if (acct_add(jl.cells * (fp32 ? 4.0 : 8.0) *
@@ -3307,7 +3307,7 @@ void launch_march2(bool fp32, const LevelDesc* L, const GridState* S, JobList jl
     // them back to back while other compute units may idle
     (void)nblk;
     const int g = blocks_for_xcd(jl.total, jl.total);
-#define FLD_MARCH(T_, D_, X_) hipLaunchKernelGGL((k_march2<T_, NU, D_, X_>), dim3(g), dim3(64), 0, s, L, S, jl, kMarchFz, rz)
+#define FLD_MARCH(T_, D_, X_) hipLaunchKernelGGL((k_march2<T_, NU, D_, X_>), dim3(g), dim3(64), 0, s, L, S, jl, fz, rz)
     FLD_NU_DISPATCH(nu, {
         if (down && load_x) { if (fp32) FLD_MARCH(float, true, true); else FLD_MARCH(double, true, true); }
         else if (down) { if (fp32) FLD_MARCH(float, true, false); else FLD_MARCH(double, true, false); }

@@ -382,6 +382,7 @@ static void build_lists(Plan& p) {
         D.mdn.resize(D.fused ? maxdepth : 0);
         D.mup.resize(D.fused ? maxdepth : 0);
         D.march.assign(D.fused ? maxdepth : 0, 0);
+        D.mfz.assign(D.fused ? maxdepth : 0, kMarchFz);
         for (int dpt = 0; dpt < (int)D.down2.size(); ++dpt) {
             D.down2[dpt].levels = D.smooth[dpt].levels;
             D.up2[dpt].levels = D.smooth[dpt].levels;
@@ -391,11 +392,27 @@ static void build_lists(Plan& p) {
             HostList& md = D.mdn[dpt];
             HostList& mu = D.mup[dpt];
             md.levels = mu.levels = D.smooth[dpt].levels;
+            // windows of kMarchFz rows where they are many; of kMarchFzShort rows where that
+            // doubles them to enough and the levels fill the windows (a single 1024^2 grid's
+            // finest level: 576 windows of 16 rows, 12.5 us for its up pass against 15.0 us
+            // with tiles; small levels in 128-column windows are mostly empty)
+            int64_t w32 = 0, w16 = 0, cells = 0;
+            for (int32_t li : md.levels) {
+                w32 += march_tiles(p.levels[li].n, n1, true, kMarchFz);
+                w16 += march_tiles(p.levels[li].n, n1, true, kMarchFzShort);
+                cells += (int64_t)p.levels[li].n[0] * p.levels[li].n[1];
+            }
+            const bool many = w32 >= kMarchMinBlocks * p.ncu;
+            const bool full = 4 * cells >= 3 * w16 * (int64_t)march_fx(n1, true) * kMarchFzShort;
+            const bool enough = w16 >= kMarchMinBlocks / 2 * p.ncu && full;
+            D.mfz[dpt] = (many || !enough) ? kMarchFz : kMarchFzShort;
+            D.march[dpt] = p.opts.fused == 3 || (p.opts.fused == 1 && (many || enough));
             md.prefix.assign(1, 0);
             mu.prefix.assign(1, 0);
-            for (int32_t li : md.levels) md.prefix.push_back(md.prefix.back() + march_tiles(p.levels[li].n, n1, true));
-            for (int32_t li : mu.levels) mu.prefix.push_back(mu.prefix.back() + march_tiles(p.levels[li].n, n2, false));
-            D.march[dpt] = p.opts.fused == 3 || (p.opts.fused == 1 && md.prefix.back() >= kMarchMinBlocks * p.ncu);
+            for (int32_t li : md.levels)
+                md.prefix.push_back(md.prefix.back() + march_tiles(p.levels[li].n, n1, true, D.mfz[dpt]));
+            for (int32_t li : mu.levels)
+                mu.prefix.push_back(mu.prefix.back() + march_tiles(p.levels[li].n, n2, false, D.mfz[dpt]));
         }
         // fused 3D sweeps alternate between x and xs, so the V-cycle's sweep count must be
         // even for its result to end in x
@@ -629,7 +646,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             continue;
         }
         if (D.fused && D.march[d]) {
-            launch_march2(f32, p.dL, p.dS, D.mdn[d].dev, nu1, 1, d == d0 ? load0 : 0, p.nblk, s);
+            launch_march2(f32, p.dL, p.dS, D.mdn[d].dev, nu1, 1, d == d0 ? load0 : 0, D.mfz[d], p.nblk, s);
             continue;
         }
         if (D.fused) {
@@ -658,7 +675,7 @@ static void enqueue_mg_from(Plan& p, DimLists& D, hipStream_t s, int d0, int loa
             continue;
         }
         if (D.fused && D.march[d]) {
-            launch_march2(f32, p.dL, p.dS, D.mup[d].dev, nu2, 0, 0, p.nblk, s, rz0 && d == 0 ? 1 : 0);
+            launch_march2(f32, p.dL, p.dS, D.mup[d].dev, nu2, 0, 0, D.mfz[d], p.nblk, s, rz0 && d == 0 ? 1 : 0);
             continue;
         }
         if (D.fused) {
@@ -696,7 +713,8 @@ static bool rz_in_march(const Plan& p, const DimLists& D) {
     if (D.dim == 3)
         return D.fused3 && p.sweep3 && D.levels3 >= 1 && p.opts.nu2 >= 2 &&
                D.sw3[0].levels.size() == D.l0_cell.levels.size();
-    return D.fused && !D.march.empty() && D.march[0] && D.mup[0].levels.size() == D.l0_cell.levels.size();
+    return D.fused && !D.march.empty() && D.march[0] && D.mfz[0] == kMarchFz &&
+           D.mup[0].levels.size() == D.l0_cell.levels.size();
 }
 static const JobList& rz_list(const DimLists& D) { return D.dim == 3 ? D.rz3.dev : D.mup[0].dev; }
 
@@ -1383,7 +1401,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                 case FLD_KERNEL_DOWN:
                     if (has_level && D.fused && D.march[level])
                         launch_march2(p.mixed, p.dL, p.dS, D.mdn[level].dev, level == 0 ? p.opts.nu1 : p.nuc1, 1, 0,
-                                      p.nblk, s);
+                                      D.mfz[level], p.nblk, s);
                     else if (has_level && D.fused) launch_down2(p.mixed, p.dL, p.dS, D.down2[level].dev,
                                                              level == 0 ? p.opts.nu1 : p.nuc1, 0,
                                                              p.tile_wide, level == 0 ? p.tile_rows : p.tile_rows_c,
@@ -1392,7 +1410,7 @@ static int profile_kernel(Plan& p, int kernel, int level, int reps, hipStream_t 
                 case FLD_KERNEL_UP:
                     if (has_level && D.fused && D.march[level])
                         launch_march2(p.mixed, p.dL, p.dS, D.mup[level].dev, level == 0 ? p.opts.nu2 : p.nuc2, 0, 0,
-                                      p.nblk, s);
+                                      D.mfz[level], p.nblk, s);
                     else if (has_level && D.fused) launch_up2(p.mixed, p.dL, p.dS, D.up2[level].dev,
                                                          level == 0 ? p.opts.nu2 : p.nuc2,
                                                          p.tile_wide, level == 0 ? p.tile_rows_u : p.tile_rows_c,
@@ -1777,6 +1795,13 @@ int32_t fld_plan_tuning(fld_plan_t plan, fld_tuning* out) {
     for (const auto& D : p.dl)
         for (size_t d = 0; d < D.march.size(); ++d) m2 += D.march[d] ? 1 : 0;
     out->march_levels = m2;
+    out->march_rows = 0;
+    for (const auto& D : p.dl)
+        for (size_t d = 0; d < D.march.size(); ++d)
+            if (D.march[d]) {
+                out->march_rows = D.mfz[d];
+                break;
+            }
     out->pq_rows = 0;
     for (const auto& D : p.dl)
         if (!D.pq3.empty()) out->pq_rows = D.fz_pq;

@@ -57,16 +57,35 @@ def test_march_meets_the_oracle():
 
 
 def test_default_rule_marches_only_where_windows_are_many():
+    """32-row windows where there are at least four per compute unit; 16-row ones where
+    those are at least two per unit and the levels fill them (one 1024^2 grid's finest
+    level); tiles otherwise (one 512^2 grid)."""
     big = fld.Plan([(512, 512)] * 40, h=[(1 / 512, 1 / 512)] * 40)
     one = fld.Plan([(1024, 1024)], h=[(1 / 1024, 1 / 1024)])
+    half = fld.Plan([(512, 512)], h=[(1 / 512, 1 / 512)])
     forced = fld.Plan([(64, 64)], h=[(1 / 64, 1 / 64)], fused=3)
     tiles = fld.Plan([(512, 512)] * 40, h=[(1 / 512, 1 / 512)] * 40, fused=2)
-    assert big.tuning()["march_levels"] >= 1
-    assert one.tuning()["march_levels"] == 0
+    assert big.tuning()["march_levels"] >= 1 and big.tuning()["march_rows"] == 32
+    assert one.tuning()["march_levels"] == 1 and one.tuning()["march_rows"] == 16
+    assert half.tuning()["march_levels"] == 0 and half.tuning()["march_rows"] == 0
     assert forced.tuning()["march_levels"] >= 1
     assert tiles.tuning()["march_levels"] == 0
-    for p in (big, one, forced, tiles):
+    for p in (big, one, half, forced, tiles):
         p.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_short_windows_equal_tiles_and_meet_the_oracle(precision):
+    """A single 1024^2 grid marches its finest level in 16-row windows (CG with the tile
+    kernels' reductions): bitwise equal to the LDS tiles, and at the oracle."""
+    g = W.random_grid((1024, 1024), 643000, dt=2e-3)
+    rtol = 1e-10 / O.q_b(g.E)
+    (xa,), (sa,), ra = run_step([g], precision=precision, rtol=rtol)
+    (xb,), (sb,), rb = run_step([g], precision=precision, rtol=rtol, fused=2)
+    assert ra == 0 and rb == 0 and sa["cycles"] == sb["cycles"]
+    assert np.array_equal(xa, xb)
+    x_or, _ = O.diffusion_step(g.E, g.kappa_rho, g.dt, g.h)
+    assert rel_l2(xa, x_or) <= 1e-10 * 1.01
 
 
 # The row-march CG direction update (k_cg_pq2m) runs on 2D plans whose reductions finish
