@@ -316,3 +316,32 @@ def test_continuous_faces_need_plain_vcycles():
     assert e.value.code == fld.FLD_ERR_INVALID_ARG
     h = fld.fld_plan_create([fld.make_grid((16, 16))], fld.fld_opts_default(bc=bc, krylov=0))
     fld.fld_plan_destroy(h)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets (a field
+    added on one side only would shift the rest silently)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    names = ["fld_grid", "fld_opts", "fld_stats", "fld_gas", "fld_level_view", "fld_moments_out", "fld_tuning",
+             "fld_server_opts", "fld_request", "fld_result", "fld_server_info"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fld.h"', 'int main(void) {']
+    for n in names:
+        lines.append(f'    printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in getattr(fld, n)._fields_:
+            lines.append(f'    printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ['    return 0;', '}']
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "sizes"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        n, f, v = line.split()
+        cls = getattr(fld, n)
+        want = C.sizeof(cls) if f == "size" else getattr(cls, f).offset
+        assert int(v) == want, (n, f, int(v), want)
