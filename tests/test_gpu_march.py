@@ -129,3 +129,19 @@ def test_pq_march_skips_odd_rows():
     assert rc == 0
     x_or, _ = O.diffusion_step(grids[5].E, grids[5].kappa_rho, grids[5].dt, grids[5].h)
     assert rel_l2(xs[5], x_or) <= 1e-10
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+def test_short_windows_other_sweep_counts_bitwise(nu):
+    """16-row windows with one and three sweeps per side (halos of 4 and 8 rows on the down
+    pass): bitwise equal to the LDS tiles in both precisions."""
+    g = W.random_grid((1024, 1024), 644000 + nu, dt=3e-3)
+    for precision in (0, 1):
+        kw = dict(precision=precision, nu1=nu, nu2=nu)
+        plan = fld.Plan([g.E.shape], h=[g.h], **kw)
+        assert plan.tuning()["march_rows"] == 16
+        plan.close()
+        (xa,), (sa,), ra = run_step([g], **kw)
+        (xb,), (sb,), rb = run_step([g], fused=2, **kw)
+        assert ra == 0 and rb == 0 and sa["cycles"] == sb["cycles"]
+        assert np.array_equal(xa, xb), (nu, precision)
